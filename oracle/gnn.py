@@ -1,0 +1,169 @@
+"""FP64 NumPy oracle of the preconditioner GNN -- TEST INFRASTRUCTURE ONLY.
+
+Follows the paper's architecture (Method, "Architecture"; technical-details
+appendix):
+  * graph/matrix duality: every stored A_ij (diagonal included, as a self-loop)
+    is a directed edge i->j with scalar feature A_ij; the right-hand side b is
+    the scalar node feature;
+  * encoders: node and edge MLPs lift the scalars to h-dimensional latents;
+  * n_mp message-passing layers:
+        v_{i,t+1}  = f_v(v_{i,t}, sum_j e_{ij,t} * v_{j,t})     (* elementwise)
+        e_{ij,t+1} = f_e(e_{ij,t}, v_{i,t+1}, v_{j,t+1})        for every
+    directed edge, i.e. both (i,j) and (j,i) are updated;
+  * decoder: d_ij = f_dec(e_ij), a scalar per directed edge;
+  * lower-triangular assembly: L_ij = (d_ij + d_ji)/2 for i > j.
+
+Readings where the paper is silent (each listed in the design notes):
+  * every MLP is Lin-ReLU-Lin ("l layers" = 2 Linear layers), width h;
+  * the sum over j runs over every stored entry of row i (self-loop included),
+    without degree normalisation;
+  * normalisation: s = mean(diag A), edge input A_ij/s, node input b_i/rms(b);
+    the network's factor is scaled back by sqrt(s): L = sqrt(s) * L_hat;
+  * the diagonal, where the pair average is d_ii itself, is made positive with
+    L_ii = max(softplus(d_ii), 1e-6) so that L L^T is SPD by construction.
+
+Pins (tests/test_oracle_gnn.py): all-zero weights give a closed form; a
+2-node graph computed by hand; permutation equivariance; 5-hop locality;
+the reverse-mode derivative against central finite differences, the
+dot-product (adjoint) test and an independent torch-autograd float64 model.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+SOFTPLUS_FLOOR = 1e-6
+
+
+def _relu(x):
+    return np.maximum(x, 0.0)
+
+
+def _softplus(x):
+    return np.where(x > 20.0, x, np.log1p(np.exp(np.minimum(x, 20.0))))
+
+
+def _sigmoid(x):
+    return 1.0 / (1.0 + np.exp(-x))
+
+
+def _mlp_fwd(P, name, x):
+    pre = x @ P[f"{name}.W0"] + P[f"{name}.b0"]
+    hid = _relu(pre)
+    out = hid @ P[f"{name}.W1"] + P[f"{name}.b1"]
+    return out, (x, pre, hid)
+
+
+def _mlp_bwd(P, name, cache, gout, G):
+    x, pre, hid = cache
+    G[f"{name}.W1"] += hid.T @ gout
+    G[f"{name}.b1"] += gout.sum(axis=0)
+    ghid = gout @ P[f"{name}.W1"].T
+    gpre = ghid * (pre > 0.0)
+    G[f"{name}.W0"] += x.T @ gpre
+    G[f"{name}.b0"] += gpre.sum(axis=0)
+    return gpre @ P[f"{name}.W0"].T
+
+
+def normalisation(A, b):
+    """(s, rms): s = mean of diag(A), rms = sqrt(mean(b^2)) (1 if b = 0)."""
+    row = A.row_of_entry()
+    s = float(np.mean(A.val[A.colind == row]))
+    rms = float(np.sqrt(np.mean(np.asarray(b, np.float64) ** 2)))
+    return s, (rms if rms > 0.0 else 1.0)
+
+
+def reverse_map(A):
+    """rev[k] = position of (j,i) for entry k = (i,j): search for key j*n+i in
+    the row-major sorted key list of the CSR entries."""
+    row = A.row_of_entry().astype(np.int64)
+    col = A.colind.astype(np.int64)
+    key = row * A.n + col
+    q = np.searchsorted(key, col * A.n + row)
+    assert np.all(q < A.nnz) and np.all(key[np.minimum(q, A.nnz - 1)] == col * A.n + row), \
+        "pattern is not structurally symmetric"
+    return q
+
+
+def forward(A, b, P, h, n_mp, rev=None, keep=False):
+    """L values on the lower pattern (i >= j) in CSR order, float64.
+
+    Returns (lval, cache) where cache (if keep) holds what backward needs.
+    """
+    row = A.row_of_entry().astype(np.int64)
+    col = A.colind.astype(np.int64)
+    n = A.n
+    if rev is None:
+        rev = reverse_map(A)
+    s, rms = normalisation(A, b)
+    ahat = (A.val / s)[:, None]
+    bhat = (np.asarray(b, np.float64) / rms)[:, None]
+    caches = {}
+    V, caches["node_enc"] = _mlp_fwd(P, "node_enc", bhat)
+    E, caches["edge_enc"] = _mlp_fwd(P, "edge_enc", ahat)
+    Vs, Es = [V], [E]
+    for t in range(n_mp):
+        m = np.zeros((n, h))
+        np.add.at(m, row, E * V[col])
+        V, caches[f"mp{t}.node"] = _mlp_fwd(P, f"mp{t}.node", np.concatenate([V, m], axis=1))
+        E, caches[f"mp{t}.edge"] = _mlp_fwd(P, f"mp{t}.edge",
+                                            np.concatenate([E, V[row], V[col]], axis=1))
+        Vs.append(V)
+        Es.append(E)
+    d, caches["dec"] = _mlp_fwd(P, "dec", E)
+    d = d[:, 0]
+    lower = col <= row
+    diag = col == row
+    lhat = np.where(diag, np.maximum(_softplus(d), SOFTPLUS_FLOOR), 0.5 * (d + d[rev]))
+    lval = np.sqrt(s) * lhat[lower]
+    cache = None
+    if keep:
+        cache = dict(row=row, col=col, rev=rev, s=s, rms=rms, d=d, lower=lower, diag=diag,
+                     Vs=Vs, Es=Es, mlp=caches, n=n, h=h, n_mp=n_mp)
+    return lval, cache
+
+
+def backward(P, cache, glval):
+    """Gradients of sum(glval * lval) w.r.t. every parameter (float64 dict)."""
+    G = {k: np.zeros_like(v) for k, v in P.items()}
+    row, col, rev = cache["row"], cache["col"], cache["rev"]
+    n, h, n_mp = cache["n"], cache["h"], cache["n_mp"]
+    d, lower, diag = cache["d"], cache["lower"], cache["diag"]
+    nnz = d.shape[0]
+    glhat = np.zeros(nnz)
+    glhat[np.nonzero(lower)[0]] = np.sqrt(cache["s"]) * np.asarray(glval, np.float64)
+    gd = np.zeros(nnz)
+    # diagonal: max(softplus(d), floor)
+    sp = _softplus(d)
+    gd += np.where(diag & (sp > SOFTPLUS_FLOOR), glhat * _sigmoid(d), 0.0)
+    # strictly lower: (d_k + d_rev(k)) / 2
+    off = lower & ~diag
+    gd += np.where(off, 0.5 * glhat, 0.0)
+    np.add.at(gd, rev[off], 0.5 * glhat[off])
+    gE = _mlp_bwd(P, "dec", cache["mlp"]["dec"], gd[:, None], G)
+    Vs, Es = cache["Vs"], cache["Es"]
+    gV = np.zeros((n, h))
+    for t in range(n_mp - 1, -1, -1):
+        gX = _mlp_bwd(P, f"mp{t}.edge", cache["mlp"][f"mp{t}.edge"], gE, G)
+        gE = gX[:, :h].copy()
+        gV = gV.copy()
+        np.add.at(gV, row, gX[:, h:2 * h])
+        np.add.at(gV, col, gX[:, 2 * h:])
+        gY = _mlp_bwd(P, f"mp{t}.node", cache["mlp"][f"mp{t}.node"], gV, G)
+        gVt = gY[:, :h].copy()
+        gm = gY[:, h:]
+        Vt, Et = Vs[t], Es[t]
+        # m_i = sum_{k in row i} E_k * V_{col k}
+        gE += gm[row] * Vt[col]
+        np.add.at(gVt, col, gm[row] * Et)
+        gV = gVt
+    _mlp_bwd(P, "node_enc", cache["mlp"]["node_enc"], gV, G)
+    _mlp_bwd(P, "edge_enc", cache["mlp"]["edge_enc"], gE, G)
+    return G
+
+
+def training_loss(A, b, x, lval, pat_lrowptr, pat_lcol, llt_loss):
+    """Per-system normalised data loss ||L L^T x - b||^2 / rms(b)^2 and its
+    gradient w.r.t. L (llt_loss: the C oracle's raw loss/gradient routine)."""
+    _, rms = normalisation(A, b)
+    loss, g = llt_loss(lval, x, b)
+    return loss / rms ** 2, g / rms ** 2

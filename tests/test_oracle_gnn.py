@@ -1,0 +1,189 @@
+"""Pins for the FP64 GNN oracle (forward and hand-written reverse mode).
+
+Forward: a hand-computed 2-node example (tests/golden/gnn_two_node.json),
+the all-zero-weight closed form, permutation equivariance of the symmetric
+assembly, and n_mp-hop locality.  Backward: central finite differences and an
+independent torch float64 autograd model written with different primitives.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import pdegen as g
+from oracle import gnn
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def test_two_node_hand_example():
+    fx = json.load(open(os.path.join(GOLD, "gnn_two_node.json")))
+    A = g.csr_from_dense(np.array(fx["A"]))
+    P = {k: np.array(v, dtype=float) for k, v in fx["params"].items()}
+    for k, v in P.items():
+        if k.endswith(("b0", "b1")):
+            P[k] = v.reshape(-1)
+    lval, _ = gnn.forward(A, np.array(fx["b"]), P, fx["h"], fx["n_mp"])
+    np.testing.assert_allclose(lval, fx["expected_lval"], rtol=1e-15)
+
+
+def test_zero_weights_closed_form():
+    """All weights zero: every MLP returns its last bias, so d = dec.b1 on
+    every edge; L_ij = sqrt(s) dec.b1 (i>j), L_ii = sqrt(s) max(softplus(dec.b1), 1e-6)."""
+    A, b = g.heat_system_3d(5, 1e-3, k_seed=3, u0_seed=4)
+    P = g.init_gnn_params(8, 3, seed=1, zero=True)
+    c = float(P["dec.b1"][0])
+    lval, _ = gnn.forward(A, b, P, 8, 3)
+    pat = O.Pattern(A)
+    s = np.mean(O.diag(A))
+    row = np.repeat(np.arange(A.n), np.diff(pat.lrowptr))
+    diag = pat.lcol == row
+    np.testing.assert_allclose(lval[~diag], np.sqrt(s) * c, rtol=1e-15)
+    np.testing.assert_allclose(lval[diag], np.sqrt(s) * np.log1p(np.exp(c)), rtol=1e-15)
+
+
+def _sym_dense(A, lval):
+    pat = O.Pattern(A)
+    row = np.repeat(np.arange(A.n), np.diff(pat.lrowptr))
+    S = np.zeros((A.n, A.n))
+    S[row, pat.lcol] = lval
+    S[pat.lcol, row] = lval
+    return S
+
+
+def test_permutation_equivariance():
+    A = g.fem_p1_delaunay(10, 2, 3)[0]
+    b = np.random.default_rng(0).standard_normal(A.n)
+    P = g.init_gnn_params(6, 3, seed=2)
+    lval, _ = gnn.forward(A, b, P, 6, 3)
+    perm = np.random.default_rng(1).permutation(A.n)
+    Ap = g.permute_csr(A, perm)
+    lp, _ = gnn.forward(Ap, b[perm], P, 6, 3)
+    S = _sym_dense(A, lval)
+    Sp = _sym_dense(Ap, lp)
+    np.testing.assert_allclose(Sp, S[np.ix_(perm, perm)], rtol=1e-12, atol=1e-12)
+
+
+def test_locality_n_mp_hops():
+    """L_ij depends on b only within n_mp hops of {i, j}: flipping the sign of a
+    far b_k (rms(b) unchanged) leaves those entries bit-identical."""
+    m, n_mp = 12, 3
+    A = g.poisson_grid(m, 2)
+    b = np.random.default_rng(3).standard_normal(A.n)
+    P = g.init_gnn_params(8, n_mp, seed=4)
+    l0, _ = gnn.forward(A, b, P, 8, n_mp)
+    b2 = b.copy()
+    b2[0] = -b2[0]  # corner node (0, 0)
+    l1, _ = gnn.forward(A, b2, P, 8, n_mp)
+    pat = O.Pattern(A)
+    row = np.repeat(np.arange(A.n), np.diff(pat.lrowptr))
+    col = pat.lcol
+
+    def dist(i):
+        return i % m + i // m  # graph distance to the corner on the grid
+    far = np.minimum(dist(row), dist(col)) > n_mp
+    assert far.sum() > 0 and (~far).sum() > 0
+    assert np.array_equal(l0[far], l1[far])
+    assert np.any(l0[~far] != l1[~far])
+
+
+def _masks(A, b, P, h, n_mp):
+    _, c = gnn.forward(A, b, P, h, n_mp, keep=True)
+    return [c["mlp"][k][1] > 0 for k in sorted(c["mlp"])]
+
+
+def _fd_check(A, b, P, h, n_mp, seed):
+    """Central differences in a region where every ReLU keeps its side (the
+    map is smooth there); eps is halved until the activation pattern at
+    theta +- eps v equals the one at theta."""
+    rng = np.random.default_rng(seed)
+    lval, cache = gnn.forward(A, b, P, h, n_mp, keep=True)
+    gl = rng.standard_normal(lval.shape[0])
+    G = gnn.backward(P, cache, gl)
+    m0 = _masks(A, b, P, h, n_mp)
+    for _ in range(3):
+        V = {k: rng.standard_normal(v.shape) for k, v in P.items()}
+        eps = 1e-6
+        while True:
+            Pp = {k: P[k] + eps * V[k] for k in P}
+            Pm = {k: P[k] - eps * V[k] for k in P}
+            same = all(np.array_equal(a, c) for a, c in zip(m0, _masks(A, b, Pp, h, n_mp))) and \
+                all(np.array_equal(a, c) for a, c in zip(m0, _masks(A, b, Pm, h, n_mp)))
+            if same or eps < 1e-10:
+                break
+            eps /= 4
+        fp = gl @ gnn.forward(A, b, Pp, h, n_mp)[0]
+        fm = gl @ gnn.forward(A, b, Pm, h, n_mp)[0]
+        fd = (fp - fm) / (2 * eps)
+        an = sum(np.sum(G[k] * V[k]) for k in P)
+        assert abs(fd - an) <= 1e-6 * max(1.0, abs(fd)), (fd, an, eps)
+
+
+def test_backward_finite_differences():
+    A = g.poisson_grid(5, 2)
+    b = np.random.default_rng(5).standard_normal(A.n)
+    _fd_check(A, b, g.init_gnn_params(4, 2, seed=6), 4, 2, 7)
+    F = g.fem_p1_delaunay(7, 1, 2)[0]
+    bf = np.random.default_rng(8).standard_normal(F.n)
+    _fd_check(F, bf, g.init_gnn_params(3, 3, seed=9), 3, 3, 10)
+
+
+def _torch_model(A, b, P, h, n_mp):
+    """Independent float64 model with torch primitives (index_add_, cat, softplus)."""
+    row = torch.as_tensor(A.row_of_entry(), dtype=torch.long)
+    col = torch.as_tensor(A.colind, dtype=torch.long)
+    val = torch.as_tensor(A.val)
+    bt = torch.as_tensor(b)
+    s = val[row == col].mean()
+    rms = torch.sqrt((bt * bt).mean())
+    T = {k: torch.tensor(v, dtype=torch.float64, requires_grad=True) for k, v in P.items()}
+
+    def mlp(name, x):
+        return torch.relu(x @ T[name + ".W0"] + T[name + ".b0"]) @ T[name + ".W1"] + T[name + ".b1"]
+    V = mlp("node_enc", (bt / rms)[:, None])
+    E = mlp("edge_enc", (val / s)[:, None])
+    for t in range(n_mp):
+        m = torch.zeros(A.n, h, dtype=torch.float64).index_add_(0, row, E * V[col])
+        V = mlp(f"mp{t}.node", torch.cat([V, m], 1))
+        E = mlp(f"mp{t}.edge", torch.cat([E, V[row], V[col]], 1))
+    d = mlp("dec", E)[:, 0]
+    # pair average via a dense symmetric scatter
+    Dm = torch.zeros(A.n, A.n, dtype=torch.float64).index_put((row, col), d)
+    Sym = 0.5 * (Dm + Dm.T)
+    diag = torch.clamp(torch.nn.functional.softplus(torch.diagonal(Dm)), min=1e-6)
+    Lfull = torch.tril(Sym, -1) + torch.diag(diag)
+    lower = col <= row
+    return torch.sqrt(s) * Lfull[row[lower], col[lower]], T
+
+
+def test_backward_matches_torch_autograd():
+    A = g.fem_p1_delaunay(8, 3, 4)[0]
+    b = np.random.default_rng(11).standard_normal(A.n)
+    h, n_mp = 5, 3
+    P = g.init_gnn_params(h, n_mp, seed=12, gain=1.5)
+    lval, cache = gnn.forward(A, b, P, h, n_mp, keep=True)
+    lt, T = _torch_model(A, b, P, h, n_mp)
+    np.testing.assert_allclose(lval, lt.detach().numpy(), rtol=1e-12, atol=1e-13)
+    gl = np.random.default_rng(13).standard_normal(lval.shape[0])
+    (lt * torch.as_tensor(gl)).sum().backward()
+    G = gnn.backward(P, cache, gl)
+    for k in P:
+        np.testing.assert_allclose(G[k], T[k].grad.numpy(), rtol=1e-10, atol=1e-11, err_msg=k)
+
+
+def test_training_loss_normalisation():
+    """Per-system loss = ||L L^T x - b||^2 / rms(b)^2 (scale-free in b)."""
+    A = g.poisson_grid(6, 2)
+    pat = O.Pattern(A)
+    b = np.random.default_rng(1).standard_normal(A.n)
+    x = np.linalg.solve(A.to_dense(), b)
+    lval = O.ic0(pat, A)[0]
+    l1, g1 = gnn.training_loss(A, b, x, lval, pat.lrowptr, pat.lcol,
+                               lambda lv, xx, bb: O.llt_loss(pat, lv, xx, bb))
+    l2, g2 = gnn.training_loss(A, 10 * b, 10 * x, lval, pat.lrowptr, pat.lcol,
+                               lambda lv, xx, bb: O.llt_loss(pat, lv, xx, bb))
+    assert np.isclose(l1, l2, rtol=1e-12)
+    np.testing.assert_allclose(g1, g2, rtol=1e-10, atol=1e-12 * np.max(np.abs(g1)))
