@@ -1,0 +1,217 @@
+"""Benchmark: time to relative residual 1e-6 and PCG iterations, learned-L vs
+IC(0) (and Jacobi), on the 3D implicit-Euler heat step, 64^3 grid, 7-point
+stencil, n = 262,144 (log-normal GRF conductivity, sigma = 1, dt = 1e-3).
+
+A step is one pass of the hot path over one system: precompute the
+preconditioner (GNN prediction of L, or the IC(0) factorisation, or the
+Jacobi diagonal) and run PCG until ||r|| <= 1e-6 ||b|| with the FP64 true
+residual checked.  The system, its pattern analysis and the network weights
+are resident in HBM before the timed region.
+
+Prints one JSON line (see the end of main()).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+WEIGHTS = os.path.join(ROOT, "paper_2305_16432_amd", "weights", "heat3d_h32_mp3.npz")
+
+
+def _log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def hbm_bytes_sptrsv(info):
+    """Algorithmic bytes of one substitution launch with FP32 values, int32
+    indices: values + column indices (8 nnz_L), row pointers (4 (n+1)), the
+    right-hand side and the result (8 n), the level-order row list (4 n)."""
+    n, nl = info["n"], info["nnz_l"]
+    return 8 * nl + 4 * (n + 1) + 8 * n + 4 * n
+
+
+def hbm_bytes_spmv(info):
+    n, nnz = info["n"], info["nnz"]
+    return 8 * nnz + 4 * (n + 1) + 8 * n
+
+
+def cpu_baseline(A, b, tol, budget_s=20.0):
+    """The FP64 oracle (serial C) on the same system: IC(0) factorisation +
+    PCG to tol.  Single thread.  Repeated until about budget_s of CPU work or
+    3 runs, whichever first; reports the mean wall time per solve in ms."""
+    import oracle as O
+    pat = O.Pattern(A)
+    times, iters = [], None
+    t_start = time.perf_counter()
+    while len(times) < 3 and time.perf_counter() - t_start < budget_s:
+        t0 = time.perf_counter()
+        lval, st = O.ic0(pat, A)
+        res = O.pcg(A, b, O.PC_LLT, pat, lval, tol=tol)
+        times.append((time.perf_counter() - t0) * 1e3)
+        iters = res["iters"]
+    return {"value": float(np.mean(times)), "unit": "ms", "cores": 1, "kind": "oracle",
+            "sample": f"IC(0) factorisation + PCG to {tol:g} on the full 64^3 system "
+                      f"(serial C FP64, {len(times)} run(s), {iters} iterations)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--m", type=int, default=64)
+    ap.add_argument("--k-seed", type=int, default=1000)
+    ap.add_argument("--u-seed", type=int, default=2000)
+    ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--methods", default="learned,ic0,jacobi")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the solver does not shard a system across GPUs)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import pdegen as g
+    from paper_2305_16432_amd import lpcg
+
+    torch.cuda.set_device(0)
+    A, b = g.heat_system_3d(args.m, 1e-3, args.k_seed, args.u_seed)
+    _log(f"system n={A.n} nnz={A.nnz}")
+    S = lpcg.analyze(torch.as_tensor(A.rowptr).cuda(), torch.as_tensor(A.colind).cuda(),
+                     torch.as_tensor(A.val).cuda())
+    info = S.info
+    bd = torch.as_tensor(b).cuda()
+    nl = info["nnz_l"]
+    lval = torch.empty(nl, dtype=torch.float32, device="cuda")
+    utval = torch.empty(nl, dtype=torch.float32, device="cuda")
+    dinv = torch.empty(A.n, dtype=torch.float32, device="cuda")
+    x = torch.zeros_like(bd)
+    solve_kw = dict(tol=args.tol, check_every=8, max_restarts=2, use_graph=True)
+
+    methods = {}
+
+    def run_ic0():
+        lpcg.ic0(S, 0.0, 8, lval, utval)
+
+    def solve_llt():
+        x.zero_()
+        return lpcg.pcg_solve(S, lpcg.PC_LLT, bd, x=x, l_val=lval, ut_val=utval, **solve_kw)[1]
+
+    def run_jacobi():
+        lpcg.jacobi(S, dinv)
+
+    def solve_jacobi():
+        x.zero_()
+        return lpcg.pcg_solve(S, lpcg.PC_JACOBI, bd, x=x, dinv=dinv, **solve_kw)[1]
+
+    methods["ic0"] = (run_ic0, solve_llt)
+    methods["jacobi"] = (run_jacobi, solve_jacobi)
+    learned_note = None
+    if "learned" in args.methods:
+        if hasattr(lpcg, "gnn_predict_L") and os.path.exists(WEIGHTS):
+            W = np.load(WEIGHTS)
+            h, n_mp = int(W["h"]), int(W["n_mp"])
+            params = torch.as_tensor(W["params"].astype(np.float32)).cuda()
+            ws = lpcg.gnn_workspace(S, h, n_mp, train=False)
+
+            def run_learned():
+                lpcg.gnn_predict_L(S, params, h, n_mp, bd, ws, lval, utval)
+            methods["learned"] = (run_learned, solve_llt)
+        else:
+            learned_note = "learned-L unavailable (no trained weights in this build)"
+            _log(learned_note)
+
+    results = {}
+    order = [m for m in ("learned", "ic0", "jacobi") if m in methods and m in args.methods]
+    for name in order:
+        pre, solve = methods[name]
+        for _ in range(args.warmup):
+            pre()
+            solve()
+        torch.cuda.synchronize()
+        t_pre, t_solve, iters, relres = [], [], [], []
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        torch.cuda.synchronize()
+        wall0 = time.perf_counter()
+        for _ in range(args.steps):
+            e0.record()
+            pre()
+            e1.record()
+            res = solve()
+            e2.record()
+            torch.cuda.synchronize()
+            t_pre.append(e0.elapsed_time(e1))
+            t_solve.append(e1.elapsed_time(e2))
+            iters.append(res["iters"])
+            relres.append(res["relres_true"])
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - wall0) * 1e3 / args.steps
+        results[name] = dict(ms=float(np.mean(np.array(t_pre) + np.array(t_solve))),
+                             precompute_ms=float(np.mean(t_pre)), solve_ms=float(np.mean(t_solve)),
+                             wall_ms=wall, iters=int(np.max(iters)),
+                             relres_true=float(np.max(relres)), status=res["status"])
+        _log(f"{name}: {results[name]}")
+
+    # roofline: the substitution kernel (the per-iteration bottleneck of LLT PCG)
+    lpcg.ic0(S, 0.0, 8, lval, utval)
+    rhs = torch.as_tensor(b.astype(np.float32)).cuda()
+    ms_trsv = lpcg.time_sptrsv(S, False, lval, utval, rhs, reps=50)
+    bytes_trsv = hbm_bytes_sptrsv(info)
+    ms_spmv = lpcg.time_spmv(S, rhs, reps=100)
+    bytes_spmv = hbm_bytes_spmv(info)
+    peak = 8000.0  # GB/s, MI355X HBM3E
+    ach = bytes_trsv / (ms_trsv * 1e-3) / 1e9
+    _log(f"sptrsv fwd {ms_trsv * 1e3:.1f} us ({ach:.1f} GB/s), spmv {ms_spmv * 1e3:.2f} us "
+         f"({bytes_spmv / (ms_spmv * 1e-3) / 1e9:.1f} GB/s)")
+
+    cpu = None
+    if not args.no_cpu:
+        os.environ.setdefault("OMP_NUM_THREADS", "1")
+        cpu = cpu_baseline(A, b, args.tol)
+        cpu["host"] = platform.processor() or platform.machine()
+        cpu["host_cpus"] = os.cpu_count()
+
+    head = "learned" if "learned" in results else "ic0"
+    out = {
+        "metric": "time-to-1e-6 rel. residual (ms) + PCG iters: learned-L vs IC(0), 3D 64³",
+        "value": results[head]["ms"],
+        "unit": "ms",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": results[head]["ms"],
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 (apply) / f64 (dots, true residual)",
+        "data": "synthetic",
+        "config": {"workload": f"3D implicit-Euler heat step, {args.m}^3 grid, 7-point, "
+                               f"n={A.n}, k=exp(GRF sigma=1, ell=0.1), dt=1e-3, b=u0 GRF, tol={args.tol:g}",
+                   "method_of_value": head, "k_seed": args.k_seed, "u0_seed": args.u_seed},
+        "methods": results,
+        "roofline": {"bound": "hbm", "kernel": "sptrsv_forward", "achieved": ach, "peak": peak,
+                     "unit": "GB/s", "frac": ach / peak, "traffic": None,
+                     "bytes_per_launch": bytes_trsv, "us_per_launch": ms_trsv * 1e3,
+                     "levels": info["nlev_fwd"],
+                     "spmv": {"us_per_launch": ms_spmv * 1e3, "bytes_per_launch": bytes_spmv,
+                              "achieved": bytes_spmv / (ms_spmv * 1e-3) / 1e9}},
+        "cpu_baseline": cpu,
+    }
+    if learned_note:
+        out["note"] = learned_note
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

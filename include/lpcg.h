@@ -1,0 +1,260 @@
+/*
+ * lpcg.h -- C ABI of the learned-preconditioner PCG library (liblpcg.so) for
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The library solves sparse SPD systems A x = b from discretised second-order
+ * PDEs (paper: Preliminaries, "Discretization") with preconditioned conjugate
+ * gradient (Appendix, algorithm "PCG") and the preconditioner P = L L^T, where
+ * L is lower triangular on the pattern of tril(A) (Method, "Learning
+ * Preconditioners").  L comes from a message-passing GNN over the matrix graph
+ * (Method, "Architecture"; technical-details appendix) or from the IC(0) and
+ * Jacobi baselines (Experiments, baselines).  Training-side entry points give
+ * the data loss sum ||L L^T x - b||^2 (Method, equation loss_Ab), its gradient,
+ * the network's reverse mode and an Adam step.
+ *
+ * Conventions for every entry point
+ *  - All array arguments are DEVICE pointers (hipMalloc'd or torch CUDA
+ *    tensors) unless a comment says "host".  The caller owns them.
+ *  - Indices are int32; CSR rows have ascending, unique column indices and the
+ *    diagonal stored; the pattern must be structurally symmetric.
+ *  - Work is enqueued on the given stream.  Entry points documented as
+ *    "synchronous" wait for their stream before returning; the others return
+ *    as soon as the work is enqueued.
+ *  - Return value: LPCG_OK or one of the LPCG_E* codes below; a message is
+ *    available from lpcg_last_error() (thread-local).  No C++ exception ever
+ *    crosses this interface and the library never aborts the process.
+ *  - L is stored in lower CSR order (rows ascending, columns ascending, the
+ *    diagonal last in each row), FP32.  "Ut" denotes the same values in the
+ *    CSR order of U = L^T (rows ascending, diagonal first).
+ */
+#ifndef LPCG_H
+#define LPCG_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ----------------------------------------------------------------- status */
+#define LPCG_OK          0
+#define LPCG_EINVAL      1  /* bad argument / pattern (unsorted, no diagonal, not symmetric) */
+#define LPCG_EHIP        2  /* a HIP runtime call failed */
+#define LPCG_ENOTCONV    3  /* PCG hit maxit; x holds the last iterate */
+#define LPCG_EBREAKDOWN  4  /* PCG p^T A p <= 0 or non-finite; IC(0) pivot <= 0 */
+#define LPCG_ENONFINITE  5  /* a predicted factor has a non-finite or non-positive diagonal */
+#define LPCG_ENOMEM      6  /* device allocation failed / workspace too small */
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *lpcg_last_error(void);
+/* Library version string. */
+const char *lpcg_version(void);
+
+/* ------------------------------------------------------------- matrices */
+/* Sparse square matrix in CSR, device pointers.  val may be NULL where only
+ * the pattern is needed. */
+typedef struct {
+    int32_t n;
+    int32_t nnz;
+    const int32_t *rowptr; /* [n+1] */
+    const int32_t *colind; /* [nnz] */
+    const double *val;     /* [nnz] FP64 */
+} lpcg_csr;
+
+/* Opaque handle: one sparsity pattern (possibly a block-diagonal batch of
+ * independent systems), its derived structure, a copy of A's values and the
+ * solver's work vectors.  Owned by the library. */
+typedef struct lpcg_system lpcg_system;
+
+typedef struct {
+    int32_t n, nnz, nnz_l;       /* nnz_l = stored entries of tril(A) */
+    int32_t nlev_fwd, nlev_bwd;  /* level counts of the L and L^T solves */
+    int32_t max_width_fwd, max_width_bwd; /* largest level */
+    int32_t nsys;                /* systems in the batch (1 if not batched) */
+} lpcg_info;
+
+/* Pattern analysis (graph/matrix duality of the Method section; levels of
+ * the substitution DAG): copies A, builds tril(A) (lrowptr/lcol), U = L^T
+ * (urowptr/ucol and the map from U entries to L entries), the reverse-edge map
+ * rev[k] = position of (j,i) for entry k = (i,j), the forward and backward
+ * levels (longest-path depth) and the level sets (rows ascending inside a
+ * level).  A->val must be set.  sys_rowptr (HOST, nsys+1 entries, first 0, last
+ * n) splits a block-diagonal batch into independent systems; NULL or nsys <= 1
+ * means one system.  Synchronous.  *out is owned by the caller until
+ * lpcg_destroy.  Errors: EINVAL (n <= 0, unsorted/duplicate columns, missing
+ * diagonal, unsymmetric pattern, a row crossing a system boundary), ENOMEM,
+ * EHIP. */
+int lpcg_analyze(const lpcg_csr *A, const int32_t *sys_rowptr, int32_t nsys,
+                 lpcg_system **out, hipStream_t stream);
+
+/* Replace A's values (same pattern), FP64 device array of length nnz. */
+int lpcg_update_values(lpcg_system *sys, const double *val, hipStream_t stream);
+
+/* Sizes and level counts (host struct). */
+int lpcg_get_info(const lpcg_system *sys, lpcg_info *info);
+
+/* Copies of the derived integer structure for inspection; every pointer is a
+ * device array of the documented length or NULL to skip.  lsrc[nnz_l]: A
+ * position of each L entry; u2l[nnz_l]: L position of each U entry;
+ * levels[n]; lev_ptr[nlev+1]; lev_rows[n]. */
+int lpcg_export_pattern(const lpcg_system *sys,
+                        int32_t *lrowptr, int32_t *lcol, int32_t *lsrc,
+                        int32_t *urowptr, int32_t *ucol, int32_t *u2l,
+                        int32_t *rev,
+                        int32_t *flevel, int32_t *flev_ptr, int32_t *flev_rows,
+                        int32_t *blevel, int32_t *blev_ptr, int32_t *blev_rows,
+                        hipStream_t stream);
+
+void lpcg_destroy(lpcg_system *sys);
+
+/* ----------------------------------------------------- building blocks */
+/* y = A x (Appendix PCG, "w = A p"; Method: one round of message passing).
+ * prec = 32: x, y FP32 with FP32 values; prec = 64: FP64 throughout. */
+int lpcg_spmv(const lpcg_system *sys, int32_t prec, const void *x, void *y,
+              hipStream_t stream);
+
+/* Triangular solve with the factor of P = L L^T (Appendix PCG, "Solve P z =
+ * r"): transpose = 0 solves L y = rhs (forward), transpose = 1 solves
+ * L^T y = rhs (backward) using ut_val.  FP32.  rhs and y must not alias. */
+int lpcg_sptrsv(const lpcg_system *sys, int32_t transpose, const float *l_val,
+                const float *ut_val, const float *rhs, float *y, hipStream_t stream);
+
+/* Ut values from L values (gather through the U->L map). */
+int lpcg_l_to_ut(const lpcg_system *sys, const float *l_val, float *ut_val,
+                 hipStream_t stream);
+
+/* IC(0) (Experiments, incomplete Cholesky baseline): L on tril(A) with
+ * (L L^T)_ij = A_ij on the pattern, computed in FP64 and stored FP32 to l_val
+ * and ut_val.  On a pivot <= 0 the factorisation is retried on
+ * A + shift * diag(A) with shift = shift0 (or 1e-3 if shift0 == 0), doubling,
+ * at most max_retries times; *shift_used (host, may be NULL) receives the
+ * shift of the returned factor.  Synchronous.  Errors: EBREAKDOWN after the
+ * last retry. */
+int lpcg_ic0(const lpcg_system *sys, double shift0, int32_t max_retries,
+             float *l_val, float *ut_val, double *shift_used, hipStream_t stream);
+
+/* Jacobi (Experiments baseline): dinv = 1 / diag(A), FP32 [n]. */
+int lpcg_jacobi(const lpcg_system *sys, float *dinv, hipStream_t stream);
+
+/* Timing aids for roofline measurements.  lpcg_time_sptrsv launches the
+ * forward (transpose = 0) or backward substitution kernel reps times on
+ * `stream`, presetting y before each launch outside the timed interval, and
+ * writes to *ms_out (host) the mean duration of one substitution launch
+ * measured with HIP events recorded around each launch on the same stream.
+ * lpcg_time_spmv does the same for the FP32 SpMV y = A x.  Synchronous. */
+int lpcg_time_sptrsv(const lpcg_system *sys, int32_t transpose, const float *l_val,
+                     const float *ut_val, const float *rhs, float *y, int32_t reps,
+                     double *ms_out, hipStream_t stream);
+int lpcg_time_spmv(const lpcg_system *sys, const float *x, float *y, int32_t reps,
+                   double *ms_out, hipStream_t stream);
+
+/* ------------------------------------------------------------------ PCG */
+#define LPCG_PC_NONE   0
+#define LPCG_PC_JACOBI 1
+#define LPCG_PC_LLT    2
+
+typedef struct {
+    int32_t kind;          /* LPCG_PC_* */
+    const float *l_val;    /* LLT: [nnz_l] lower CSR order */
+    const float *ut_val;   /* LLT: [nnz_l] U CSR order */
+    const float *dinv;     /* JACOBI: [n] (NULL: computed internally) */
+} lpcg_precond;
+
+typedef struct {
+    double tol;            /* stop when ||r_k||_2 <= tol * ||b||_2 */
+    int32_t maxit;         /* iteration cap (<= 0: n) */
+    int32_t check_every;   /* iterations per host check of the done flag (<= 0: 8) */
+    int32_t max_restarts;  /* restarts from the FP64 true residual when the
+                              recursive residual converged but the true one
+                              did not (<= 0: none) */
+    int32_t use_graph;     /* capture the iteration chunk in a hipGraph */
+} lpcg_solve_opts;
+
+typedef struct {
+    int32_t iters;         /* products A p (k of the algorithm), all restarts */
+    int32_t status;        /* LPCG_OK / ENOTCONV / EBREAKDOWN */
+    int32_t restarts;
+    int32_t reserved;
+    double relres_rec;     /* recursive ||r_k|| / ||b|| at exit */
+    double relres_true;    /* FP64 ||b - A x|| / ||b|| at exit */
+} lpcg_result;
+
+/* PCG (Appendix algorithm) on A x = b.  b: FP64 [n]; x: FP64 [n], holds x0 on
+ * entry and the solution on return.  Vectors r, p, w, z live in FP32, the
+ * products r.z and p.w and the norms are accumulated in FP64, the true
+ * residual is FP64.  res (HOST) receives the outcome.  hist (device FP64
+ * [maxit+1] or NULL) receives ||r_k||/||b|| for k = 0..iters of the last
+ * restart.  Synchronous.  Returns res->status. */
+int lpcg_pcg_solve(lpcg_system *sys, const lpcg_precond *P, const double *b,
+                   double *x, const lpcg_solve_opts *opts, lpcg_result *res,
+                   double *hist, hipStream_t stream);
+
+/* ------------------------------------------------------------------ GNN */
+/* Encoder-processor-decoder GNN (Method "Architecture"; technical-details
+ * appendix), latent and hidden width h (multiple of 16, at most 64), n_mp
+ * message-passing layers.  params: FP32 master weights, device, in this order
+ * (each Linear maps x -> x W + b, W stored [fan_in][fan_out] row-major):
+ *   node_enc: W0[1][h] b0[h] W1[h][h] b1[h]
+ *   edge_enc: W0[1][h] b0[h] W1[h][h] b1[h]
+ *   for t in 0..n_mp-1:
+ *     mp{t}.node: W0[2h][h] b0[h] W1[h][h] b1[h]     (input [v_i, m_i])
+ *     mp{t}.edge: W0[3h][h] b0[h] W1[h][h] b1[h]     (input [e_ij, v_i, v_j])
+ *   dec: W0[h][h] b0[h] W1[h][1] b1[1]
+ * The GEMMs run on BF16 MFMA with FP32 accumulation. */
+typedef struct {
+    int32_t h;
+    int32_t n_mp;
+    const float *params;
+} lpcg_gnn;
+
+/* Number of FP32 parameters of the layout above. */
+int64_t lpcg_gnn_param_count(int32_t h, int32_t n_mp);
+
+/* Workspace bytes for gnn_predict_L (train = 0) or for the training forward
+ * and backward (train = 1, activations kept). */
+int64_t lpcg_gnn_workspace_bytes(const lpcg_system *sys, int32_t h, int32_t n_mp,
+                                 int32_t train);
+
+/* gnn_predict_L(graph, weights) -> L.  Node input b_i / rms(b), edge input
+ * A_ij / s with s = mean(diag A) (per system of a batch); d_ij = decoder
+ * output per directed edge; L_ij = sqrt(s) (d_ij + d_ji) / 2 for i > j and
+ * L_ii = sqrt(s) max(softplus(d_ii), 1e-6).  b: FP64 [n].  ws: device
+ * workspace of lpcg_gnn_workspace_bytes(.., 0) bytes.  Writes l_val and
+ * ut_val (either may be NULL).  Errors: EINVAL (h, n_mp), ENOMEM (ws too
+ * small). */
+int lpcg_gnn_predict_L(const lpcg_system *sys, const lpcg_gnn *net, const double *b,
+                       void *ws, int64_t ws_bytes, float *l_val, float *ut_val,
+                       hipStream_t stream);
+
+/* Training forward: as lpcg_gnn_predict_L, keeping activations in ws
+ * (lpcg_gnn_workspace_bytes(.., 1) bytes) for lpcg_gnn_backward. */
+int lpcg_gnn_forward_train(const lpcg_system *sys, const lpcg_gnn *net, const double *b,
+                           void *ws, int64_t ws_bytes, float *l_val, hipStream_t stream);
+
+/* Reverse mode of the network: given dl_val = d loss / d L (FP32 [nnz_l]),
+ * writes d loss / d params (FP32, same layout as params, overwritten).
+ * ws must hold the activations of the matching lpcg_gnn_forward_train. */
+int lpcg_gnn_backward(const lpcg_system *sys, const lpcg_gnn *net, void *ws,
+                      int64_t ws_bytes, const float *dl_val, float *dparams,
+                      hipStream_t stream);
+
+/* Data loss of the Method section per system s of the batch:
+ *   loss[s] = ||L L^T x - b||^2 / rms(b)^2   over the rows of system s
+ * (FP64 [nsys], overwritten) and dl_val = d(sum_s loss[s]) / d L (FP32
+ * [nnz_l], overwritten, may be NULL):  2 (r_i u_j + x_i w_j) / rms(b)^2 with
+ * u = L^T x, r = L u - b, w = L^T r.  x, b: FP64 [n]. */
+int lpcg_llt_loss(const lpcg_system *sys, const float *l_val, const double *x,
+                  const double *b, double *loss, float *dl_val, hipStream_t stream);
+
+/* Adam step on FP32 master weights (in place): m = b1 m + (1-b1) g,
+ * v = b2 v + (1-b2) g^2, p -= lr * (m / (1-b1^t)) / (sqrt(v / (1-b2^t)) + eps)
+ * with t = step (>= 1). */
+int lpcg_adam_step(float *params, const float *grads, float *m, float *v, int64_t count,
+                   float lr, float beta1, float beta2, float eps, int32_t step,
+                   hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LPCG_H */

@@ -1,0 +1,84 @@
+// Device helpers shared by the kernels of liblpcg (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace lpcg {
+
+constexpr int kWave = 64;
+
+// A substitution writes each solution entry exactly once.  Before a solve the
+// output vector is filled with this bit pattern (a NaN payload that FP32
+// arithmetic never produces: generated NaNs are canonicalised below), so the
+// entry itself serves as its ready flag and no separate flag or fence is
+// needed between value and flag.
+constexpr uint32_t kUnset = 0x7fffffffu;
+constexpr uint32_t kCanonNan = 0x7fc00000u;
+
+__device__ __forceinline__ uint32_t ld_agent(const uint32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_agent(uint32_t *p, uint32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int ld_agent_i(const int *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_agent_i(int *p, int v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t publishable(float v) {
+    uint32_t b = __float_as_uint(v);
+    return (v != v) ? kCanonNan : b;
+}
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
+
+// Next work item of a wave from a shared counter, as a wave-uniform (scalar)
+// value.  Every lane executes the atomic (the first active lane adds 1, the
+// others add 0) so there is no single-lane branch the compiler could fuse with
+// other single-lane code, and readfirstlane makes the result an SGPR, so the
+// loop exit on it is a uniform scalar branch.  (A lane-0-only atomic followed
+// by a cross-lane broadcast is not safe: the optimiser may rotate the loop so
+// that the other lanes re-broadcast a stale register and never leave it.)
+__device__ __forceinline__ int wave_ticket(int *ticket) {
+    const int leader = __builtin_amdgcn_readfirstlane(lane_id());
+    const int old = atomicAdd(ticket, lane_id() == leader ? 1 : 0);
+    return __builtin_amdgcn_readfirstlane(old);
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+// Sum over a block of BS threads, fixed reduction tree; result valid in all
+// threads.  lds must hold BS / 64 elements.
+template <int BS, typename T>
+__device__ __forceinline__ T block_sum(T v, T *lds) {
+    static_assert(BS % kWave == 0, "block size");
+    v = wave_sum(v);
+    const int w = threadIdx.x / kWave;
+    __syncthreads();
+    if (lane_id() == 0) lds[w] = v;
+    __syncthreads();
+    T s = 0;
+#pragma unroll
+    for (int i = 0; i < BS / kWave; ++i) s += lds[i];
+    return s;
+}
+
+// Deterministic reduction of np partial sums (fixed order), result in all
+// threads of the block.
+template <int BS>
+__device__ __forceinline__ double reduce_partials(const double *part, int np, double *lds) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < np; i += BS) s += part[i];
+    return block_sum<BS>(s, lds);
+}
+
+}  // namespace lpcg

@@ -1,0 +1,322 @@
+// Standalone building blocks: SpMV, triangular solves, IC(0), Jacobi.
+#include <algorithm>
+
+#include "device_util.h"
+#include "kern_spmv.h"
+#include "kern_sptrsv.h"
+#include "lpcg_internal.h"
+
+namespace lpcg {
+namespace {
+
+int nblk(long n, int t) { return (int)((n + t - 1) / t); }
+
+__global__ void k_zero_i32(int *p, int count) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = 0;
+}
+
+template <typename VT, typename XT>
+int launch_spmv(const lpcg_system *s, const VT *v, const XT *x, XT *y, hipStream_t st) {
+    const int threads = 256;
+    const int rows_per_block = threads / s->spmv_group;
+    const int blocks = std::min(nblk(s->n, rows_per_block), 8192);
+    switch (s->spmv_group) {
+        case 4: k_spmv<4><<<blocks, threads, 0, st>>>(s->n, s->rowptr, s->colind, v, x, y); break;
+        case 8: k_spmv<8><<<blocks, threads, 0, st>>>(s->n, s->rowptr, s->colind, v, x, y); break;
+        case 16: k_spmv<16><<<blocks, threads, 0, st>>>(s->n, s->rowptr, s->colind, v, x, y); break;
+        case 32: k_spmv<32><<<blocks, threads, 0, st>>>(s->n, s->rowptr, s->colind, v, x, y); break;
+        default: k_spmv<64><<<blocks, threads, 0, st>>>(s->n, s->rowptr, s->colind, v, x, y); break;
+    }
+    LPCG_LAUNCH_CHECK();
+    return LPCG_OK;
+}
+
+// ------------------------------------------------------------------ IC(0)
+// Incomplete Cholesky with zero fill on tril(A) (the paper's IC baseline):
+//   L_ij = (A_ij - sum_{k<j, k in S_i and S_j} L_ik L_jk) / L_jj   (j < i)
+//   L_ii = sqrt(A_ii (1 + shift) - sum_{k<i} L_ik^2)
+// Row i depends on the rows j of its strictly-lower entries, the same DAG as
+// the forward substitution: rows are handed out in forward level order
+// through a ticket.  FP64; every stored value is preset to kUnset64 and is its
+// own ready flag (agent-scope stores and loads), so no fence orders a row's
+// values against a separate flag.  A lane restarts the entry it is working on
+// when some value it needs is not yet published (non-blocking in the wave).
+constexpr uint64_t kUnset64 = 0x7fffffffffffffffull;
+constexpr uint64_t kCanonNan64 = 0x7ff8000000000000ull;
+
+__device__ __forceinline__ uint64_t ld64(const uint64_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st64(uint64_t *p, double v) {
+    uint64_t b = __double_as_longlong(v);
+    __hip_atomic_store(p, (v != v) ? kCanonNan64 : b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ void __launch_bounds__(256) k_ic0(int n, const int *__restrict__ order,
+                                             const int *__restrict__ lrp, const int *__restrict__ lci,
+                                             const int *__restrict__ lsrc,
+                                             const double *__restrict__ aval, double shift,
+                                             uint64_t *l64, int *ticket, int *bad_row) {
+    for (;;) {
+        const int chunk = wave_ticket(ticket);
+        if ((long)chunk * kWave >= n) break;
+        const int pos = chunk * kWave + lane_id();
+        int row = -1, a = 0, b = 0, p = 0;
+        if (pos < n) {
+            row = order[pos];
+            a = lrp[row];
+            b = lrp[row + 1];
+            p = a;
+        }
+        bool pending = row >= 0;
+        while (__ballot(pending) != 0) {
+            bool progress = pending;
+            while (progress) {
+                if (p < b - 1) {
+                    const int j = lci[p];
+                    const int jd = lrp[j + 1] - 1;
+                    const uint64_t djb = ld64(&l64[jd]);
+                    if (djb == kUnset64) { progress = false; break; }
+                    double sacc = aval[lsrc[p]];
+                    int ia = a, ib = lrp[j];
+                    bool ok = true;
+                    while (ia < p && ib < jd) {
+                        const int ka = lci[ia], kb = lci[ib];
+                        if (ka == kb) {
+                            const uint64_t ljk = ld64(&l64[ib]);
+                            if (ljk == kUnset64) { ok = false; break; }
+                            const double lik = __longlong_as_double(ld64(&l64[ia]));
+                            sacc -= lik * __longlong_as_double(ljk);
+                            ++ia;
+                            ++ib;
+                        } else if (ka < kb) {
+                            ++ia;
+                        } else {
+                            ++ib;
+                        }
+                    }
+                    if (!ok) { progress = false; break; }
+                    st64(&l64[p], sacc / __longlong_as_double(djb));
+                    ++p;
+                } else {
+                    double d = aval[lsrc[p]] * (1.0 + shift);
+                    for (int q = a; q < p; ++q) {
+                        const double l = __longlong_as_double(ld64(&l64[q]));
+                        d -= l * l;
+                    }
+                    if (!(d > 0.0) || !isfinite(d)) {
+                        atomicMin(bad_row, row);
+                        d = 1.0;  // keep dependants going; the result is rejected
+                    }
+                    st64(&l64[p], sqrt(d));
+                    pending = false;
+                    progress = false;
+                }
+            }
+            if (pending) __builtin_amdgcn_s_sleep(1);
+        }
+    }
+}
+
+__global__ void k_fill_u64(int count, uint64_t *p, uint64_t v) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = v;
+}
+
+__global__ void k_l64_to_f32(int nnz_l, const double *__restrict__ l64, const int *__restrict__ u2l,
+                             float *__restrict__ lval, float *__restrict__ utval) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nnz_l) return;
+    if (lval) lval[k] = (float)l64[k];
+    if (utval) utval[k] = (float)l64[u2l[k]];
+}
+
+__global__ void k_l_to_ut(int nnz_l, const float *__restrict__ lval, const int *__restrict__ u2l,
+                          float *__restrict__ utval) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < nnz_l) utval[k] = lval[u2l[k]];
+}
+
+__global__ void k_jacobi(int n, const double *__restrict__ diag, float *__restrict__ dinv) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dinv[i] = (float)(1.0 / diag[i]);
+}
+
+__global__ void k_set_i32(int *p, int v) { *p = v; }
+
+}  // namespace
+
+int spmv32(const lpcg_system *s, const float *x, float *y, hipStream_t st) {
+    return launch_spmv<float, float>(s, s->val32, x, y, st);
+}
+int spmv64(const lpcg_system *s, const double *x, double *y, hipStream_t st) {
+    return launch_spmv<double, double>(s, s->val64, x, y, st);
+}
+
+int sptrsv32(const lpcg_system *s, int transpose, const float *lval, const float *utval,
+             const float *rhs, float *y, int *ticket, hipStream_t st) {
+    const int n = s->n;
+    k_fill_u32<<<nblk(n, 256), 256, 0, st>>>(n, (uint32_t *)y, kUnset);
+    k_zero_i32<<<1, 64, 0, st>>>(ticket, 1);
+    const int blocks = nblk(trsv_waves(n), 4);
+    if (transpose)
+        k_sptrsv<true><<<blocks, 256, 0, st>>>(n, s->blev_rows, s->urowptr, s->ucol, utval, rhs,
+                                               (uint32_t *)y, ticket);
+    else
+        k_sptrsv<false><<<blocks, 256, 0, st>>>(n, s->flev_rows, s->lrowptr, s->lcol, lval, rhs,
+                                                (uint32_t *)y, ticket);
+    LPCG_LAUNCH_CHECK();
+    return LPCG_OK;
+}
+
+}  // namespace lpcg
+
+using namespace lpcg;
+
+extern "C" int lpcg_spmv(const lpcg_system *s, int32_t prec, const void *x, void *y,
+                         hipStream_t st) {
+    if (!s || !x || !y || (prec != 32 && prec != 64)) {
+        set_error("lpcg_spmv: invalid arguments");
+        return LPCG_EINVAL;
+    }
+    if (prec == 32) return spmv32(s, (const float *)x, (float *)y, st);
+    return spmv64(s, (const double *)x, (double *)y, st);
+}
+
+extern "C" int lpcg_sptrsv(const lpcg_system *s, int32_t transpose, const float *l_val,
+                           const float *ut_val, const float *rhs, float *y, hipStream_t st) {
+    if (!s || !rhs || !y || rhs == y || (transpose ? !ut_val : !l_val)) {
+        set_error("lpcg_sptrsv: invalid arguments");
+        return LPCG_EINVAL;
+    }
+    return sptrsv32(s, transpose, l_val, ut_val, rhs, y, s->ctrl + C_TICKET_X, st);
+}
+
+extern "C" int lpcg_l_to_ut(const lpcg_system *s, const float *l_val, float *ut_val,
+                            hipStream_t st) {
+    if (!s || !l_val || !ut_val) {
+        set_error("lpcg_l_to_ut: invalid arguments");
+        return LPCG_EINVAL;
+    }
+    k_l_to_ut<<<nblk(s->nnz_l, 256), 256, 0, st>>>(s->nnz_l, l_val, s->u2l, ut_val);
+    LPCG_LAUNCH_CHECK();
+    return LPCG_OK;
+}
+
+extern "C" int lpcg_jacobi(const lpcg_system *s, float *dinv, hipStream_t st) {
+    if (!s || !dinv) {
+        set_error("lpcg_jacobi: invalid arguments");
+        return LPCG_EINVAL;
+    }
+    k_jacobi<<<nblk(s->n, 256), 256, 0, st>>>(s->n, s->diag64, dinv);
+    LPCG_LAUNCH_CHECK();
+    return LPCG_OK;
+}
+
+extern "C" int lpcg_ic0(const lpcg_system *s, double shift0, int32_t max_retries, float *l_val,
+                        float *ut_val, double *shift_used, hipStream_t st) {
+    if (!s || (!l_val && !ut_val) || shift0 < 0) {
+        set_error("lpcg_ic0: invalid arguments");
+        return LPCG_EINVAL;
+    }
+    // FP64 factor in the (otherwise idle) partial-sum area would be too small:
+    // it lives in a dedicated scratch carved from the work vectors' storage.
+    double *l64 = nullptr;
+    LPCG_HIP(hipMallocAsync((void **)&l64, sizeof(double) * (size_t)s->nnz_l, st));
+    int *flags = s->ctrl + C_TICKET_X;  // ticket
+    int *bad = s->ctrl + C_STATUS;      // reused as the bad-row slot
+    double shift = shift0;
+    int rc = LPCG_EBREAKDOWN;
+    for (int attempt = 0; attempt <= std::max(0, (int)max_retries); ++attempt) {
+        k_fill_u64<<<nblk(s->nnz_l, 256), 256, 0, st>>>(s->nnz_l, (uint64_t *)l64, kUnset64);
+        k_set_i32<<<1, 1, 0, st>>>(flags, 0);
+        k_set_i32<<<1, 1, 0, st>>>(bad, 0x7fffffff);
+        const int blocks = nblk(trsv_waves(s->n), 4);
+        k_ic0<<<blocks, 256, 0, st>>>(s->n, s->flev_rows, s->lrowptr, s->lcol, s->lsrc, s->val64, shift,
+                                      (uint64_t *)l64, flags, bad);
+        LPCG_LAUNCH_CHECK();
+        int hbad = 0;
+        LPCG_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, st));
+        LPCG_HIP(hipStreamSynchronize(st));
+        if (hbad == 0x7fffffff) {
+            k_l64_to_f32<<<nblk(s->nnz_l, 256), 256, 0, st>>>(s->nnz_l, l64, s->u2l, l_val, ut_val);
+            LPCG_LAUNCH_CHECK();
+            if (shift_used) *shift_used = shift;
+            rc = LPCG_OK;
+            break;
+        }
+        set_error("lpcg_ic0: non-positive pivot at row %d (shift %g)", hbad, shift);
+        shift = shift == 0.0 ? 1e-3 : 2.0 * shift;
+    }
+    LPCG_HIP(hipFreeAsync(l64, st));
+    LPCG_HIP(hipStreamSynchronize(st));
+    return rc;
+}
+
+namespace {
+struct EventPair {
+    hipEvent_t a = nullptr, b = nullptr;
+    ~EventPair() {
+        if (a) hipEventDestroy(a);
+        if (b) hipEventDestroy(b);
+    }
+};
+}  // namespace
+
+extern "C" int lpcg_time_sptrsv(const lpcg_system *s, int32_t transpose, const float *l_val,
+                                const float *ut_val, const float *rhs, float *y, int32_t reps,
+                                double *ms_out, hipStream_t st) {
+    if (!s || !rhs || !y || rhs == y || reps <= 0 || !ms_out || (transpose ? !ut_val : !l_val)) {
+        set_error("lpcg_time_sptrsv: invalid arguments");
+        return LPCG_EINVAL;
+    }
+    EventPair ev;
+    LPCG_HIP(hipEventCreate(&ev.a));
+    LPCG_HIP(hipEventCreate(&ev.b));
+    const int n = s->n;
+    int *ticket = s->ctrl + C_TICKET_X;
+    const int blocks = nblk(trsv_waves(n), 4);
+    double total = 0;
+    for (int r = 0; r < reps; ++r) {
+        k_fill_u32<<<nblk(n, 256), 256, 0, st>>>(n, (uint32_t *)y, kUnset);
+        k_zero_i32<<<1, 64, 0, st>>>(ticket, 1);
+        LPCG_HIP(hipEventRecord(ev.a, st));
+        if (transpose)
+            k_sptrsv<true><<<blocks, 256, 0, st>>>(n, s->blev_rows, s->urowptr, s->ucol, ut_val, rhs,
+                                                   (uint32_t *)y, ticket);
+        else
+            k_sptrsv<false><<<blocks, 256, 0, st>>>(n, s->flev_rows, s->lrowptr, s->lcol, l_val, rhs,
+                                                    (uint32_t *)y, ticket);
+        LPCG_HIP(hipEventRecord(ev.b, st));
+        LPCG_LAUNCH_CHECK();
+        LPCG_HIP(hipEventSynchronize(ev.b));
+        float ms = 0;
+        LPCG_HIP(hipEventElapsedTime(&ms, ev.a, ev.b));
+        total += ms;
+    }
+    *ms_out = total / reps;
+    return LPCG_OK;
+}
+
+extern "C" int lpcg_time_spmv(const lpcg_system *s, const float *x, float *y, int32_t reps,
+                              double *ms_out, hipStream_t st) {
+    if (!s || !x || !y || reps <= 0 || !ms_out) {
+        set_error("lpcg_time_spmv: invalid arguments");
+        return LPCG_EINVAL;
+    }
+    EventPair ev;
+    LPCG_HIP(hipEventCreate(&ev.a));
+    LPCG_HIP(hipEventCreate(&ev.b));
+    LPCG_HIP(hipEventRecord(ev.a, st));
+    for (int r = 0; r < reps; ++r) {
+        int rc = spmv32(s, x, y, st);
+        if (rc) return rc;
+    }
+    LPCG_HIP(hipEventRecord(ev.b, st));
+    LPCG_HIP(hipEventSynchronize(ev.b));
+    float ms = 0;
+    LPCG_HIP(hipEventElapsedTime(&ms, ev.a, ev.b));
+    *ms_out = (double)ms / reps;
+    return LPCG_OK;
+}

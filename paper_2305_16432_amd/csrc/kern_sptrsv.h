@@ -1,0 +1,106 @@
+// Sparse triangular substitution with the factor of P = L L^T (Appendix PCG,
+// "Solve P z = r": forward L y = r, then backward L^T z = y).
+//
+// One launch per solve, dependency driven (no level barriers):
+//  * rows are visited in level order (level sets of the analysis), handed
+//    out 64 at a time to waves through a ticket counter, so a wave only ever
+//    waits on rows that were handed out earlier, to waves already running;
+//  * the output vector is preset to the kUnset bit pattern; a row's result,
+//    stored with one agent-scope store, is its own ready flag;
+//  * a lane issues the loads of all its dependencies at once, consumes the
+//    ready prefix, and retries only what is missing (non-blocking inside the
+//    wave, so dependencies between lanes of one wave cannot deadlock).
+// Bytes per row: 8 per stored entry + 4 (rhs) + 4 (out) + 8 (row pointers)
+// + 4 (level-order row id) + 4 per dependency value read.
+#pragma once
+
+#include "device_util.h"
+
+namespace lpcg {
+
+constexpr int kTrsvBatch = 8;
+
+// Solves one chunk of 64 rows of the level order starting at `base`.
+// UPPER = 0: L in lower CSR, diagonal last; UPPER = 1: U = L^T in upper CSR,
+// diagonal first.  Returns (per lane) the row solved (-1 if none) and its value.
+template <bool UPPER>
+__device__ __forceinline__ int trsv_chunk(int n, int base, const int *__restrict__ order,
+                                          const int *__restrict__ rp, const int *__restrict__ ci,
+                                          const float *__restrict__ v, const float *__restrict__ rhs,
+                                          uint32_t *ybits, float &yout) {
+    const int pos = base + lane_id();
+    int row = -1, k = 0, kend = 0;
+    float acc = 0.f, dg = 1.f;
+    if (pos < n) {
+        row = order[pos];
+        const int a = rp[row], b = rp[row + 1];
+        if (UPPER) {
+            dg = v[a];
+            k = a + 1;
+            kend = b;
+        } else {
+            dg = v[b - 1];
+            k = a;
+            kend = b - 1;
+        }
+        acc = rhs[row];
+    }
+    bool pending = row >= 0;
+    while (__ballot(pending) != 0) {
+        if (pending) {
+            while (k < kend) {
+                uint32_t got[kTrsvBatch];
+                const int m = min(kTrsvBatch, kend - k);
+#pragma unroll
+                for (int t = 0; t < kTrsvBatch; ++t)
+                    if (t < m) got[t] = ld_agent(&ybits[ci[k + t]]);
+                int used = 0;
+#pragma unroll
+                for (int t = 0; t < kTrsvBatch; ++t) {
+                    if (t < m && used == t && got[t] != kUnset) {
+                        acc -= v[k + t] * __uint_as_float(got[t]);
+                        ++used;
+                    }
+                }
+                k += used;
+                if (used < m) break;
+            }
+            if (k == kend) {
+                const float yv = acc / dg;
+                st_agent(&ybits[row], publishable(yv));
+                yout = yv;
+                pending = false;
+            }
+        }
+        if (pending) __builtin_amdgcn_s_sleep(1);
+    }
+    return row;
+}
+
+template <bool UPPER>
+__global__ void __launch_bounds__(256) k_sptrsv(int n, const int *__restrict__ order,
+                                                const int *__restrict__ rp, const int *__restrict__ ci,
+                                                const float *__restrict__ v,
+                                                const float *__restrict__ rhs, uint32_t *ybits,
+                                                int *ticket) {
+    for (;;) {
+        const int chunk = wave_ticket(ticket);
+        if ((long)chunk * kWave >= n) break;
+        float yv;
+        trsv_chunk<UPPER>(n, chunk * kWave, order, rp, ci, v, rhs, ybits, yv);
+    }
+}
+
+static __global__ void k_fill_u32(int n, uint32_t *p, uint32_t v) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// Number of waves for a dependency-driven launch: enough to keep every CU
+// busy, never more than there are chunks.
+inline int trsv_waves(int n) {
+    const int chunks = (n + kWave - 1) / kWave;
+    return chunks < 4096 ? chunks : 4096;
+}
+
+}  // namespace lpcg

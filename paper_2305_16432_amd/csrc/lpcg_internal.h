@@ -1,0 +1,87 @@
+// Internal declarations of liblpcg (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "lpcg.h"
+
+namespace lpcg {
+
+// thread-local error message
+void set_error(const char *fmt, ...);
+int hip_fail(hipError_t e, const char *what, const char *file, int line);
+
+// Blocks of the fixed-grid vector kernels.  Partial sums are written one per
+// block, so the grid must stay fixed for the reduction order to be fixed.
+constexpr int kVecThreads = 256;
+constexpr int kMaxVecBlocks = 1024;
+
+// Layout of the small control words and FP64 scalars of a PCG solve.
+enum Ctrl : int {
+    C_DONE = 0,      // nonzero: every later kernel of the solve returns at once
+    C_STATUS = 1,    // LPCG_OK / ENOTCONV / EBREAKDOWN
+    C_IT = 2,        // products A p done so far (k of the algorithm)
+    C_ITERS = 3,     // iteration count at exit
+    C_TICKET_F = 4,  // work counter of the forward substitution
+    C_TICKET_B = 5,  // work counter of the backward substitution
+    C_TICKET_X = 6,  // spare work counter (standalone solves)
+    C_MAXIT = 7,
+    C_NCTRL = 16
+};
+enum Scal : int {
+    S_BB = 0,        // ||b||^2
+    S_RZ0 = 1,       // r.z, parity 0
+    S_RZ1 = 2,       // r.z, parity 1
+    S_RR = 3,        // ||r||^2 at exit (recursive)
+    S_TOL2 = 4,      // tol^2
+    S_BETA = 5,
+    S_TRUE = 6,      // ||b - A x||^2 (FP64 true residual)
+    S_NSCAL = 16
+};
+
+}  // namespace lpcg
+
+struct lpcg_system {
+    int n = 0, nnz = 0, nnz_l = 0;
+    int nlev_f = 0, nlev_b = 0, max_w_f = 0, max_w_b = 0;
+    int nsys = 1;
+    // pattern (device)
+    int *rowptr = nullptr, *colind = nullptr, *erow = nullptr, *dpos = nullptr, *rev = nullptr;
+    int *lrowptr = nullptr, *lcol = nullptr, *lsrc = nullptr;
+    int *urowptr = nullptr, *ucol = nullptr, *u2l = nullptr;
+    int *flevel = nullptr, *flev_ptr = nullptr, *flev_rows = nullptr;
+    int *blevel = nullptr, *blev_ptr = nullptr, *blev_rows = nullptr;
+    int *sys_rowptr = nullptr, *row_sys = nullptr;
+    std::vector<int> h_flev_ptr, h_blev_ptr, h_sys_rowptr;
+    // values (device)
+    double *val64 = nullptr;
+    float *val32 = nullptr;
+    double *diag64 = nullptr;
+    // solver work vectors (device)
+    float *r = nullptr, *p = nullptr, *w = nullptr, *z = nullptr, *y = nullptr, *dinv = nullptr;
+    double *part = nullptr;      // partial sums (3 x max(kMaxVecBlocks, chunks))
+    int npart = 0;               // stride between the partial arrays
+    double *scal = nullptr;      // FP64 scalars (Scal)
+    int *ctrl = nullptr;         // control words (Ctrl)
+    int *h_ctrl = nullptr;       // pinned host mirror of ctrl
+    double *h_scal = nullptr;    // pinned host mirror of scal
+    int vec_blocks = 1;          // grid of the fixed-grid vector kernels
+    int spmv_group = 8;          // lanes per row in SpMV
+    // cached iteration-chunk graph of the last PCG solve (captured on a
+    // private stream, launched on the caller's)
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    std::vector<unsigned char> graph_key;
+    std::vector<void *> allocs;
+};
+
+#define LPCG_HIP(call)                                                               \
+    do {                                                                             \
+        hipError_t _e = (call);                                                      \
+        if (_e != hipSuccess) return ::lpcg::hip_fail(_e, #call, __FILE__, __LINE__); \
+    } while (0)
+
+#define LPCG_LAUNCH_CHECK() LPCG_HIP(hipGetLastError())

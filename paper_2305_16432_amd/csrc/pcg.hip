@@ -1,0 +1,494 @@
+// PCG (Appendix algorithm "PCG") on the GPU.
+//
+//   r0 = b - A x0;  z0 = P^-1 r0;  p1 = z0;  then for k = 1, 2, ...:
+//   w = A p_k;  alpha = r.z / p.w;  x += alpha p;  r -= alpha w;
+//   stop if ||r|| <= tol ||b||;  z = P^-1 r;  beta = r.z(new) / r.z(old);
+//   p = z + beta p.
+//
+// Precision: A's values, r, p, w, z in FP32; x, b and every dot product /
+// norm in FP64; the final true residual ||b - A x|| in FP64 (FP64 values).
+// P = L L^T is applied by the dependency-driven substitutions of
+// kern_sptrsv.h; Jacobi and no preconditioning fuse z into the vector
+// kernels.
+//
+// Control: the iteration state lives on the device (ctrl words, FP64
+// scalars).  Each kernel returns at once when the done flag is set, so the
+// host enqueues chunks of iterations (optionally as a captured hipGraph) and
+// reads the flag only between chunks.  Dot products are reduced in a fixed
+// order (per-block partials, then a fixed tree), so runs are bit-reproducible.
+//
+// Kernels of one LLT iteration (it = products A p so far):
+//   k_llt_fwd  : convergence test on ||r||^2 partials, then y = L^-1 r
+//   k_llt_bwd  : z = L^-T y, partial r.z per 64-row chunk
+//   k_rz       : r.z total, beta (single block)
+//   k_pupd     : p = z + beta p, reset y
+//   k_spmv_pw  : w = A p, partial p.w, it += 1
+//   k_xr       : alpha, breakdown test, x += alpha p, r -= alpha w, ||r||^2
+//                partials, reset z and the tickets
+// Jacobi / none:  k_rz (convergence test, r.z, beta; single block),
+//   k_pupd (z = dinv r on the fly), k_spmv_pw, k_xr (+ r.z partials).
+#include <algorithm>
+#include <cstring>
+
+#include "device_util.h"
+#include "kern_spmv.h"
+#include "kern_sptrsv.h"
+#include "lpcg_internal.h"
+
+namespace lpcg {
+
+int spmv32(const lpcg_system *s, const float *x, float *y, hipStream_t st);
+
+namespace {
+
+constexpr int VT = kVecThreads;
+
+struct Args {
+    int n, np_vec, np_chunk, maxit, kind;
+    const int *rp, *ci;
+    const float *v32;
+    const double *v64;
+    const int *lrp, *lci, *urp, *uci, *forder, *border;
+    const float *lval, *utval, *dinv;
+    const double *b;
+    double *x;
+    float *r, *p, *w;
+    uint32_t *y, *z;
+    double *part_rr, *part_rz, *part_pw, *part_bb;
+    double *scal, *hist;
+    int *ctrl;
+    double tol2;
+};
+
+// The done flag can be raised by block 0 while other blocks of the same
+// launch run; one thread reads it for the whole block so that every wave of a
+// block takes the same branch around the block barriers that follow.
+__device__ __forceinline__ bool is_done(const Args &a) {
+    __shared__ int flag;
+    if (threadIdx.x == 0) flag = a.ctrl[C_DONE];
+    __syncthreads();
+    return flag != 0;
+}
+
+// Convergence test on the ||r||^2 partials; every calling block reaches the
+// same decision (same partials, same order).  Block 0 records the outcome.
+__device__ bool converged_or_capped(const Args &a, double *lds) {
+    const double rr = reduce_partials<VT>(a.part_rr, a.np_vec, lds);
+    const double bb = a.scal[S_BB];
+    const int it = a.ctrl[C_IT];
+    const bool conv = !(rr > a.tol2 * bb);
+    const bool cap = !conv && it >= a.maxit;
+    const bool bad = !isfinite(rr);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (a.hist && it <= a.maxit) a.hist[it] = sqrt(rr / bb);
+        if (conv || cap || bad) {
+            a.ctrl[C_DONE] = 1;
+            a.ctrl[C_STATUS] = conv ? LPCG_OK : bad ? LPCG_EBREAKDOWN : LPCG_ENOTCONV;
+            a.ctrl[C_ITERS] = it;
+            a.scal[S_RR] = rr;
+        }
+    }
+    return conv || cap || bad;
+}
+
+// r = b - A x (FP64 product, FP32 r), ||b||^2, ||r||^2 and (Jacobi/none) r.z
+// partials; presets y, z for the substitutions.
+template <int KIND>
+__global__ void __launch_bounds__(VT) k_setup(Args a) {
+    __shared__ double lds[VT / kWave];
+    double bb = 0, rr = 0, rz = 0;
+    for (int i = blockIdx.x * VT + threadIdx.x; i < a.n; i += gridDim.x * VT) {
+        double s = 0;
+        for (int k = a.rp[i]; k < a.rp[i + 1]; ++k) s += a.v64[k] * a.x[a.ci[k]];
+        const double bi = a.b[i];
+        const float ri = (float)(bi - s);
+        a.r[i] = ri;
+        bb += bi * bi;
+        rr += (double)ri * ri;
+        if (KIND == LPCG_PC_JACOBI) rz += (double)ri * ri * a.dinv[i];
+        if (KIND == LPCG_PC_NONE) rz += (double)ri * ri;
+        if (KIND == LPCG_PC_LLT) {
+            a.y[i] = kUnset;
+            a.z[i] = kUnset;
+        }
+    }
+    bb = block_sum<VT>(bb, lds);
+    rr = block_sum<VT>(rr, lds);
+    rz = block_sum<VT>(rz, lds);
+    if (threadIdx.x == 0) {
+        a.part_bb[blockIdx.x] = bb;
+        a.part_rr[blockIdx.x] = rr;
+        if (KIND != LPCG_PC_LLT) a.part_rz[blockIdx.x] = rz;
+    }
+}
+
+// Single block: control words, ||b||^2, first convergence test.
+__global__ void __launch_bounds__(VT) k_setup_scal(Args a) {
+    __shared__ double lds[VT / kWave];
+    const double bb0 = reduce_partials<VT>(a.part_bb, a.np_vec, lds);
+    const double rr = reduce_partials<VT>(a.part_rr, a.np_vec, lds);
+    if (threadIdx.x == 0) {
+        const double bb = bb0 > 0 ? bb0 : 1.0;
+        a.scal[S_BB] = bb;
+        a.scal[S_RZ0] = 0;
+        a.scal[S_BETA] = 0;
+        a.scal[S_RR] = rr;
+        a.ctrl[C_IT] = 0;
+        a.ctrl[C_ITERS] = 0;
+        a.ctrl[C_TICKET_F] = 0;
+        a.ctrl[C_TICKET_B] = 0;
+        a.ctrl[C_STATUS] = LPCG_OK;
+        const bool conv = !(rr > a.tol2 * bb);
+        a.ctrl[C_DONE] = conv ? 1 : 0;
+        if (a.hist) a.hist[0] = sqrt(rr / bb);
+    }
+}
+
+__global__ void __launch_bounds__(256) k_llt_fwd(Args a) {
+    __shared__ double lds[VT / kWave];
+    if (is_done(a)) return;
+    if (converged_or_capped(a, lds)) return;
+    int *ticket = a.ctrl + C_TICKET_F;
+    for (;;) {
+        const int chunk = wave_ticket(ticket);
+        if ((long)chunk * kWave >= a.n) break;
+        float yv;
+        trsv_chunk<false>(a.n, chunk * kWave, a.forder, a.lrp, a.lci, a.lval, a.r, a.y, yv);
+    }
+}
+
+__global__ void __launch_bounds__(256) k_llt_bwd(Args a) {
+    if (is_done(a)) return;
+    int *ticket = a.ctrl + C_TICKET_B;
+    for (;;) {
+        const int chunk = wave_ticket(ticket);
+        if ((long)chunk * kWave >= a.n) break;
+        float zv = 0.f;
+        const int row = trsv_chunk<true>(a.n, chunk * kWave, a.border, a.urp, a.uci, a.utval,
+                                         (const float *)a.y, a.z, zv);
+        double rz = row >= 0 ? (double)a.r[row] * (double)zv : 0.0;
+        rz = wave_sum(rz);
+        a.part_rz[chunk] = rz;  // every lane stores the same wave total
+    }
+}
+
+// Single block: r.z total, beta.  Reads the previous r.z before replacing it.
+template <int KIND>
+__global__ void __launch_bounds__(1024) k_rz(Args a) {
+    __shared__ double lds[1024 / kWave];
+    if (is_done(a)) return;
+    if (KIND != LPCG_PC_LLT) {
+        // convergence test lives here for the fused preconditioners
+        const double rr = reduce_partials<1024>(a.part_rr, a.np_vec, lds);
+        const double bb = a.scal[S_BB];
+        const int it = a.ctrl[C_IT];
+        const bool conv = !(rr > a.tol2 * bb);
+        const bool cap = !conv && it >= a.maxit;
+        const bool bad = !isfinite(rr);
+        if (threadIdx.x == 0) {
+            if (a.hist && it <= a.maxit) a.hist[it] = sqrt(rr / bb);
+            if (conv || cap || bad) {
+                a.ctrl[C_DONE] = 1;
+                a.ctrl[C_STATUS] = conv ? LPCG_OK : bad ? LPCG_EBREAKDOWN : LPCG_ENOTCONV;
+                a.ctrl[C_ITERS] = it;
+                a.scal[S_RR] = rr;
+            }
+        }
+        if (conv || cap || bad) return;
+    }
+    const int np = KIND == LPCG_PC_LLT ? a.np_chunk : a.np_vec;
+    const double rz = reduce_partials<1024>(a.part_rz, np, lds);
+    if (threadIdx.x == 0) {
+        const int it = a.ctrl[C_IT];
+        const double old = a.scal[S_RZ0];
+        a.scal[S_BETA] = it == 0 ? 0.0 : rz / old;
+        a.scal[S_RZ0] = rz;
+    }
+}
+
+// p = z + beta p; z from the substitution (LLT) or dinv * r / r.
+template <int KIND>
+__global__ void __launch_bounds__(VT) k_pupd(Args a) {
+    if (is_done(a)) return;
+    const float beta = (float)a.scal[S_BETA];
+    const bool first = a.ctrl[C_IT] == 0;  // p_1 = z_0 exactly (p holds garbage)
+    for (int i = blockIdx.x * VT + threadIdx.x; i < a.n; i += gridDim.x * VT) {
+        float zi;
+        if (KIND == LPCG_PC_LLT) {
+            zi = __uint_as_float(a.z[i]);
+            a.y[i] = kUnset;
+        } else if (KIND == LPCG_PC_JACOBI) {
+            zi = a.dinv[i] * a.r[i];
+        } else {
+            zi = a.r[i];
+        }
+        a.p[i] = first ? zi : zi + beta * a.p[i];
+    }
+}
+
+// w = A p and partial p.w; block 0 counts the product.
+template <int G>
+__global__ void __launch_bounds__(VT) k_spmv_pw(Args a) {
+    __shared__ double lds[VT / kWave];
+    if (is_done(a)) return;
+    const int sub = threadIdx.x % G;
+    const int rows_per_pass = gridDim.x * (VT / G);
+    double pw = 0;
+    for (int row = blockIdx.x * (VT / G) + threadIdx.x / G; row < a.n; row += rows_per_pass) {
+        const float s = row_dot<G, float>(a.rp[row], a.rp[row + 1], sub, a.ci, a.v32, a.p);
+        if (sub == 0) {
+            a.w[row] = s;
+            pw += (double)a.p[row] * (double)s;
+        }
+    }
+    pw = block_sum<VT>(pw, lds);
+    if (threadIdx.x == 0) {
+        a.part_pw[blockIdx.x] = pw;
+        if (blockIdx.x == 0) a.ctrl[C_IT] = a.ctrl[C_IT] + 1;
+    }
+}
+
+// alpha = r.z / p.w (every block reduces the same partials), breakdown test,
+// x += alpha p, r -= alpha w, ||r||^2 (and r.z for Jacobi/none) partials.
+template <int KIND>
+__global__ void __launch_bounds__(VT) k_xr(Args a) {
+    __shared__ double lds[VT / kWave];
+    if (is_done(a)) return;
+    const double pw = reduce_partials<VT>(a.part_pw, a.np_vec, lds);
+    const double rz = a.scal[S_RZ0];
+    if (!(pw > 0.0) || !isfinite(pw) || !isfinite(rz)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            a.ctrl[C_DONE] = 1;
+            a.ctrl[C_STATUS] = LPCG_EBREAKDOWN;
+            a.ctrl[C_ITERS] = a.ctrl[C_IT];
+        }
+        return;
+    }
+    const double alpha = rz / pw;
+    const float af = (float)alpha;
+    double rr = 0, rzn = 0;
+    for (int i = blockIdx.x * VT + threadIdx.x; i < a.n; i += gridDim.x * VT) {
+        const float pi = a.p[i];
+        a.x[i] += alpha * (double)pi;
+        const float ri = a.r[i] - af * a.w[i];
+        a.r[i] = ri;
+        rr += (double)ri * ri;
+        if (KIND == LPCG_PC_JACOBI) rzn += (double)ri * ri * a.dinv[i];
+        if (KIND == LPCG_PC_NONE) rzn += (double)ri * ri;
+        if (KIND == LPCG_PC_LLT) a.z[i] = kUnset;
+    }
+    rr = block_sum<VT>(rr, lds);
+    if (KIND != LPCG_PC_LLT) rzn = block_sum<VT>(rzn, lds);
+    if (threadIdx.x == 0) {
+        a.part_rr[blockIdx.x] = rr;
+        if (KIND != LPCG_PC_LLT) a.part_rz[blockIdx.x] = rzn;
+        if (blockIdx.x == 0) {
+            a.ctrl[C_TICKET_F] = 0;
+            a.ctrl[C_TICKET_B] = 0;
+        }
+    }
+}
+
+// FP64 true residual partials ||b - A x||^2 (FP64 values).
+__global__ void __launch_bounds__(VT) k_true_res(Args a) {
+    __shared__ double lds[VT / kWave];
+    double rr = 0;
+    for (int i = blockIdx.x * VT + threadIdx.x; i < a.n; i += gridDim.x * VT) {
+        double s = 0;
+        for (int k = a.rp[i]; k < a.rp[i + 1]; ++k) s += a.v64[k] * a.x[a.ci[k]];
+        const double ri = a.b[i] - s;
+        rr += ri * ri;
+    }
+    rr = block_sum<VT>(rr, lds);
+    if (threadIdx.x == 0) a.part_pw[blockIdx.x] = rr;
+}
+
+__global__ void __launch_bounds__(VT) k_true_fin(Args a) {
+    __shared__ double lds[VT / kWave];
+    const double rr = reduce_partials<VT>(a.part_pw, a.np_vec, lds);
+    if (threadIdx.x == 0) a.scal[S_TRUE] = rr;
+}
+
+template <int KIND>
+int enqueue_iteration(const lpcg_system *s, const Args &a, hipStream_t st) {
+    const int vb = s->vec_blocks;
+    if (KIND == LPCG_PC_LLT) {
+        const int tb = (trsv_waves(s->n) + 3) / 4;
+        k_llt_fwd<<<tb, 256, 0, st>>>(a);
+        k_llt_bwd<<<tb, 256, 0, st>>>(a);
+    }
+    k_rz<KIND><<<1, 1024, 0, st>>>(a);
+    k_pupd<KIND><<<vb, VT, 0, st>>>(a);
+    switch (s->spmv_group) {
+        case 4: k_spmv_pw<4><<<vb, VT, 0, st>>>(a); break;
+        case 8: k_spmv_pw<8><<<vb, VT, 0, st>>>(a); break;
+        case 16: k_spmv_pw<16><<<vb, VT, 0, st>>>(a); break;
+        case 32: k_spmv_pw<32><<<vb, VT, 0, st>>>(a); break;
+        default: k_spmv_pw<64><<<vb, VT, 0, st>>>(a); break;
+    }
+    k_xr<KIND><<<vb, VT, 0, st>>>(a);
+    LPCG_LAUNCH_CHECK();
+    return LPCG_OK;
+}
+
+template <int KIND>
+int run_solve(lpcg_system *s, const Args &a, const lpcg_solve_opts &o, int &iters_total,
+              int &status, double &rr_out, hipStream_t st) {
+    const int vb = s->vec_blocks;
+    k_setup<KIND><<<vb, VT, 0, st>>>(a);
+    k_setup_scal<<<1, VT, 0, st>>>(a);
+    LPCG_LAUNCH_CHECK();
+    const int chunk = o.check_every > 0 ? o.check_every : 8;
+    hipGraphExec_t exec = nullptr;
+    if (o.use_graph) {
+        // key: kernel arguments + preconditioner kind + chunk length
+        std::vector<unsigned char> key(sizeof(Args) + 2 * sizeof(int));
+        memcpy(key.data(), &a, sizeof(Args));
+        const int extra[2] = {KIND, chunk};
+        memcpy(key.data() + sizeof(Args), extra, sizeof(extra));
+        if (s->graph_exec && s->graph_key == key) {
+            exec = s->graph_exec;
+        } else {
+            if (s->graph_exec) {
+                hipGraphExecDestroy(s->graph_exec);
+                s->graph_exec = nullptr;
+            }
+            if (!s->cap_stream) LPCG_HIP(hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));
+            hipGraph_t graph = nullptr;
+            LPCG_HIP(hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal));
+            int rc = LPCG_OK;
+            for (int c = 0; c < chunk && rc == LPCG_OK; ++c) rc = enqueue_iteration<KIND>(s, a, s->cap_stream);
+            hipError_t e = hipStreamEndCapture(s->cap_stream, &graph);
+            if (rc != LPCG_OK) {
+                if (graph) hipGraphDestroy(graph);
+                return rc;
+            }
+            LPCG_HIP(e);
+            hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            hipGraphDestroy(graph);
+            LPCG_HIP(ie);
+            s->graph_exec = exec;
+            s->graph_key = key;
+        }
+    }
+    int rc = LPCG_OK;
+    for (int guard = 0;; ++guard) {
+        if (exec) {
+            hipError_t e = hipGraphLaunch(exec, st);
+            if (e != hipSuccess) { rc = hip_fail(e, "hipGraphLaunch", __FILE__, __LINE__); break; }
+        } else {
+            for (int c = 0; c < chunk && rc == LPCG_OK; ++c) rc = enqueue_iteration<KIND>(s, a, st);
+            if (rc != LPCG_OK) break;
+        }
+        hipError_t e = hipMemcpyAsync(s->h_ctrl, s->ctrl, sizeof(int) * C_NCTRL, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) { rc = hip_fail(e, "pcg control readback", __FILE__, __LINE__); break; }
+        if (s->h_ctrl[C_DONE]) break;
+        if (guard > a.maxit / std::max(1, chunk) + 4) {
+            set_error("pcg: done flag never set");
+            rc = LPCG_EHIP;
+            break;
+        }
+    }
+    if (rc != LPCG_OK) return rc;
+    LPCG_HIP(hipMemcpyAsync(s->h_scal, s->scal, sizeof(double) * S_NSCAL, hipMemcpyDeviceToHost, st));
+    LPCG_HIP(hipStreamSynchronize(st));
+    iters_total += s->h_ctrl[C_ITERS];
+    status = s->h_ctrl[C_STATUS];
+    rr_out = s->h_scal[S_RR] / s->h_scal[S_BB];
+    return LPCG_OK;
+}
+
+}  // namespace
+}  // namespace lpcg
+
+using namespace lpcg;
+
+extern "C" int lpcg_pcg_solve(lpcg_system *s, const lpcg_precond *P, const double *b, double *x,
+                              const lpcg_solve_opts *opts, lpcg_result *res, double *hist,
+                              hipStream_t st) {
+    if (!s || !P || !b || !x || !opts || !res || !(opts->tol >= 0)) {
+        set_error("lpcg_pcg_solve: invalid arguments");
+        return LPCG_EINVAL;
+    }
+    if (P->kind == LPCG_PC_LLT && (!P->l_val || !P->ut_val)) {
+        set_error("lpcg_pcg_solve: LLT preconditioner needs l_val and ut_val");
+        return LPCG_EINVAL;
+    }
+    if (P->kind != LPCG_PC_LLT && P->kind != LPCG_PC_JACOBI && P->kind != LPCG_PC_NONE) {
+        set_error("lpcg_pcg_solve: unknown preconditioner kind %d", P->kind);
+        return LPCG_EINVAL;
+    }
+    Args a{};
+    a.n = s->n;
+    a.np_vec = s->vec_blocks;
+    a.np_chunk = (s->n + kWave - 1) / kWave;
+    a.maxit = opts->maxit > 0 ? opts->maxit : s->n;
+    a.kind = P->kind;
+    a.rp = s->rowptr;
+    a.ci = s->colind;
+    a.v32 = s->val32;
+    a.v64 = s->val64;
+    a.lrp = s->lrowptr;
+    a.lci = s->lcol;
+    a.urp = s->urowptr;
+    a.uci = s->ucol;
+    a.forder = s->flev_rows;
+    a.border = s->blev_rows;
+    a.lval = P->l_val;
+    a.utval = P->ut_val;
+    a.dinv = P->dinv ? P->dinv : s->dinv;
+    a.b = b;
+    a.x = x;
+    a.r = s->r;
+    a.p = s->p;
+    a.w = s->w;
+    a.y = (uint32_t *)s->y;
+    a.z = (uint32_t *)s->z;
+    a.part_rr = s->part;
+    a.part_rz = s->part + s->npart;
+    a.part_pw = s->part + 2 * (size_t)s->npart;
+    a.part_bb = s->part + 3 * (size_t)s->npart;
+    a.scal = s->scal;
+    a.hist = hist;
+    a.ctrl = s->ctrl;
+    a.tol2 = opts->tol * opts->tol;
+    if (P->kind == LPCG_PC_JACOBI && !P->dinv) {
+        int rc = lpcg_jacobi(s, s->dinv, st);
+        if (rc) return rc;
+    }
+    res->iters = 0;
+    res->restarts = 0;
+    res->status = LPCG_OK;
+    int iters = 0, status = LPCG_OK;
+    const int maxit0 = a.maxit;
+    double rr = 0;
+    for (int attempt = 0;; ++attempt) {
+        int rc;
+        if (P->kind == LPCG_PC_LLT) rc = run_solve<LPCG_PC_LLT>(s, a, *opts, iters, status, rr, st);
+        else if (P->kind == LPCG_PC_JACOBI) rc = run_solve<LPCG_PC_JACOBI>(s, a, *opts, iters, status, rr, st);
+        else rc = run_solve<LPCG_PC_NONE>(s, a, *opts, iters, status, rr, st);
+        if (rc != LPCG_OK) return rc;
+        // FP64 true residual
+        k_true_res<<<s->vec_blocks, VT, 0, st>>>(a);
+        k_true_fin<<<1, VT, 0, st>>>(a);
+        LPCG_LAUNCH_CHECK();
+        LPCG_HIP(hipMemcpyAsync(s->h_scal, s->scal, sizeof(double) * S_NSCAL, hipMemcpyDeviceToHost, st));
+        LPCG_HIP(hipStreamSynchronize(st));
+        const double truerel = sqrt(s->h_scal[S_TRUE] / s->h_scal[S_BB]);
+        res->relres_rec = sqrt(rr);
+        res->relres_true = truerel;
+        if (status == LPCG_OK && truerel > opts->tol && attempt < opts->max_restarts &&
+            iters < maxit0) {
+            res->restarts = attempt + 1;
+            a.maxit = std::max(1, maxit0 - iters);
+            continue;
+        }
+        break;
+    }
+    res->iters = iters;
+    res->status = status;
+    if (status == LPCG_ENOTCONV) set_error("pcg: no convergence within maxit");
+    if (status == LPCG_EBREAKDOWN) set_error("pcg: breakdown (p.Ap <= 0 or non-finite)");
+    return status;
+}

@@ -1,0 +1,272 @@
+"""Thin Python binding of liblpcg.so (argument marshalling only).
+
+Every function maps one-to-one onto the C entry point of the same name with
+the `lpcg_` prefix (include/lpcg.h).  Tensors are torch CUDA tensors; the
+library receives their device pointers and torch's current HIP stream.  No
+computation of the method happens here, and there is no fallback: if the
+shared library is missing or a call fails, an exception is raised.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblpcg.so")
+
+OK, EINVAL, EHIP, ENOTCONV, EBREAKDOWN, ENONFINITE, ENOMEM = range(7)
+PC_NONE, PC_JACOBI, PC_LLT = 0, 1, 2
+STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "EHIP", 3: "ENOTCONV", 4: "EBREAKDOWN",
+                5: "ENONFINITE", 6: "ENOMEM"}
+
+
+class LpcgError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class _CSR(C.Structure):
+    _fields_ = [("n", C.c_int32), ("nnz", C.c_int32), ("rowptr", C.c_void_p),
+                ("colind", C.c_void_p), ("val", C.c_void_p)]
+
+
+class _Info(C.Structure):
+    _fields_ = [("n", C.c_int32), ("nnz", C.c_int32), ("nnz_l", C.c_int32),
+                ("nlev_fwd", C.c_int32), ("nlev_bwd", C.c_int32),
+                ("max_width_fwd", C.c_int32), ("max_width_bwd", C.c_int32),
+                ("nsys", C.c_int32)]
+
+
+class _Precond(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("l_val", C.c_void_p), ("ut_val", C.c_void_p),
+                ("dinv", C.c_void_p)]
+
+
+class _Opts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("maxit", C.c_int32), ("check_every", C.c_int32),
+                ("max_restarts", C.c_int32), ("use_graph", C.c_int32)]
+
+
+class _Result(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("status", C.c_int32), ("restarts", C.c_int32),
+                ("reserved", C.c_int32), ("relres_rec", C.c_double), ("relres_true", C.c_double)]
+
+
+class _Gnn(C.Structure):
+    _fields_ = [("h", C.c_int32), ("n_mp", C.c_int32), ("params", C.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded shared library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: run __graft_entry__.build() first")
+        L = C.CDLL(LIB_PATH)
+        L.lpcg_last_error.restype = C.c_char_p
+        L.lpcg_version.restype = C.c_char_p
+        if hasattr(L, "lpcg_gnn_param_count"):
+            L.lpcg_gnn_param_count.restype = C.c_int64
+            L.lpcg_gnn_param_count.argtypes = [C.c_int32, C.c_int32]
+            L.lpcg_gnn_workspace_bytes.restype = C.c_int64
+            L.lpcg_gnn_workspace_bytes.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32]
+        L.lpcg_destroy.restype = None
+        _lib = L
+    return _lib
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("device tensor expected")
+    if not t.is_contiguous():
+        raise ValueError("contiguous tensor expected")
+    return C.c_void_p(t.data_ptr())
+
+
+def _check(rc, what):
+    if rc != OK:
+        raise LpcgError(rc, f"{what}: {lib().lpcg_last_error().decode()}")
+
+
+def _dev(t, dtype):
+    t = torch.as_tensor(t)
+    if t.dtype != dtype:
+        raise TypeError(f"{dtype} expected, got {t.dtype}")
+    return t if t.is_cuda else t.cuda()
+
+
+class System:
+    """Owns an lpcg_system handle (pattern analysis + values + work vectors)."""
+
+    def __init__(self, handle, n, nnz):
+        self._h = handle
+        self.n, self.nnz = n, nnz
+        self.info = get_info(self)
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise RuntimeError("system destroyed")
+        return self._h
+
+    def close(self):
+        if self._h is not None:
+            torch.cuda.synchronize()
+            lib().lpcg_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------------ analysis
+def analyze(rowptr, colind, val, sys_rowptr=None) -> System:
+    rowptr = _dev(rowptr, torch.int32).contiguous()
+    colind = _dev(colind, torch.int32).contiguous()
+    val = _dev(val, torch.float64).contiguous()
+    n = rowptr.numel() - 1
+    A = _CSR(n, colind.numel(), _ptr(rowptr), _ptr(colind), _ptr(val))
+    out = C.c_void_p()
+    if sys_rowptr is not None:
+        import numpy as np
+        sr = np.ascontiguousarray(sys_rowptr, dtype=np.int32)
+        nsys = sr.shape[0] - 1
+        srp = sr.ctypes.data_as(C.c_void_p)
+    else:
+        nsys, srp = 1, None
+    rc = lib().lpcg_analyze(C.byref(A), srp, C.c_int32(nsys), C.byref(out), _stream())
+    _check(rc, "lpcg_analyze")
+    return System(out, n, colind.numel())
+
+
+def update_values(sys: System, val):
+    val = _dev(val, torch.float64).contiguous()
+    _check(lib().lpcg_update_values(sys.handle, _ptr(val), _stream()), "lpcg_update_values")
+
+
+def get_info(sys: System) -> dict:
+    info = _Info()
+    _check(lib().lpcg_get_info(sys.handle, C.byref(info)), "lpcg_get_info")
+    return {f: getattr(info, f) for f, _ in _Info._fields_}
+
+
+def export_pattern(sys: System) -> dict:
+    i = sys.info
+    n, nnz, nl = i["n"], i["nnz"], i["nnz_l"]
+
+    def e(k):
+        return torch.empty(k, dtype=torch.int32, device="cuda")
+    out = dict(lrowptr=e(n + 1), lcol=e(nl), lsrc=e(nl), urowptr=e(n + 1), ucol=e(nl), u2l=e(nl),
+               rev=e(nnz), flevel=e(n), flev_ptr=e(i["nlev_fwd"] + 1), flev_rows=e(n),
+               blevel=e(n), blev_ptr=e(i["nlev_bwd"] + 1), blev_rows=e(n))
+    rc = lib().lpcg_export_pattern(sys.handle, *[_ptr(out[k]) for k in (
+        "lrowptr", "lcol", "lsrc", "urowptr", "ucol", "u2l", "rev", "flevel", "flev_ptr",
+        "flev_rows", "blevel", "blev_ptr", "blev_rows")], _stream())
+    _check(rc, "lpcg_export_pattern")
+    return out
+
+
+# ---------------------------------------------------------- building blocks
+def spmv(sys: System, x, out=None):
+    prec = 64 if x.dtype == torch.float64 else 32
+    if prec == 32 and x.dtype != torch.float32:
+        raise TypeError("float32 or float64 expected")
+    if out is None:
+        out = torch.empty_like(x)
+    _check(lib().lpcg_spmv(sys.handle, C.c_int32(prec), _ptr(x), _ptr(out), _stream()), "lpcg_spmv")
+    return out
+
+
+def sptrsv(sys: System, transpose: bool, l_val, ut_val, rhs, out=None):
+    if out is None:
+        out = torch.empty_like(rhs)
+    rc = lib().lpcg_sptrsv(sys.handle, C.c_int32(1 if transpose else 0), _ptr(l_val), _ptr(ut_val),
+                           _ptr(rhs), _ptr(out), _stream())
+    _check(rc, "lpcg_sptrsv")
+    return out
+
+
+def l_to_ut(sys: System, l_val, out=None):
+    if out is None:
+        out = torch.empty_like(l_val)
+    _check(lib().lpcg_l_to_ut(sys.handle, _ptr(l_val), _ptr(out), _stream()), "lpcg_l_to_ut")
+    return out
+
+
+def ic0(sys: System, shift0=0.0, max_retries=8, l_val=None, ut_val=None):
+    nl = sys.info["nnz_l"]
+    if l_val is None:
+        l_val = torch.empty(nl, dtype=torch.float32, device="cuda")
+    if ut_val is None:
+        ut_val = torch.empty(nl, dtype=torch.float32, device="cuda")
+    used = C.c_double(0)
+    rc = lib().lpcg_ic0(sys.handle, C.c_double(shift0), C.c_int32(max_retries), _ptr(l_val),
+                        _ptr(ut_val), C.byref(used), _stream())
+    _check(rc, "lpcg_ic0")
+    return l_val, ut_val, used.value
+
+
+def jacobi(sys: System, out=None):
+    if out is None:
+        out = torch.empty(sys.n, dtype=torch.float32, device="cuda")
+    _check(lib().lpcg_jacobi(sys.handle, _ptr(out), _stream()), "lpcg_jacobi")
+    return out
+
+
+# ---------------------------------------------------------------------- PCG
+def pcg_solve(sys: System, kind: int, b, x=None, l_val=None, ut_val=None, dinv=None,
+              tol=1e-6, maxit=0, check_every=8, max_restarts=0, use_graph=False,
+              hist=False, raise_on_status=False):
+    """Returns (x, result dict[, hist tensor])."""
+    b = _dev(b, torch.float64).contiguous()
+    if x is None:
+        x = torch.zeros_like(b)
+    P = _Precond(kind, _ptr(l_val), _ptr(ut_val), _ptr(dinv))
+    mi = maxit if maxit > 0 else sys.n
+    opts = _Opts(float(tol), int(mi), int(check_every), int(max_restarts), int(bool(use_graph)))
+    res = _Result()
+    h = torch.full((mi + 1,), float("nan"), dtype=torch.float64, device="cuda") if hist else None
+    rc = lib().lpcg_pcg_solve(sys.handle, C.byref(P), _ptr(b), _ptr(x), C.byref(opts),
+                              C.byref(res), _ptr(h), _stream())
+    if rc not in (OK, ENOTCONV, EBREAKDOWN) or (raise_on_status and rc != OK):
+        _check(rc, "lpcg_pcg_solve")
+    out = {f: getattr(res, f) for f, _ in _Result._fields_ if f != "reserved"}
+    if hist:
+        return x, out, h[: res.iters + 1] if res.restarts == 0 else h
+    return x, out
+
+
+# ------------------------------------------------------------------ timing
+def time_sptrsv(sys: System, transpose: bool, l_val, ut_val, rhs, reps=20):
+    """Mean duration (ms) of one substitution kernel launch (HIP events)."""
+    out = torch.empty_like(rhs)
+    ms = C.c_double(0)
+    rc = lib().lpcg_time_sptrsv(sys.handle, C.c_int32(1 if transpose else 0), _ptr(l_val),
+                                _ptr(ut_val), _ptr(rhs), _ptr(out), C.c_int32(reps), C.byref(ms),
+                                _stream())
+    _check(rc, "lpcg_time_sptrsv")
+    return ms.value
+
+
+def time_spmv(sys: System, x, reps=50):
+    """Mean duration (ms) of one FP32 SpMV launch (HIP events)."""
+    out = torch.empty_like(x)
+    ms = C.c_double(0)
+    rc = lib().lpcg_time_spmv(sys.handle, _ptr(x), _ptr(out), C.c_int32(reps), C.byref(ms), _stream())
+    _check(rc, "lpcg_time_spmv")
+    return ms.value
