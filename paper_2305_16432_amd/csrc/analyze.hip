@@ -360,7 +360,7 @@ int analyze_impl(const lpcg_csr *A, const int32_t *h_sys, int32_t nsys, lpcg_sys
     ALLOC(s->dinv, n);
     s->vec_blocks = std::max(1, std::min(kMaxVecBlocks, nblk(n, kVecThreads * 4)));
     const int chunks = nblk(n, kWave);
-    s->npart = std::max(kMaxVecBlocks, chunks);
+    s->npart = std::max(std::max(kMaxVecBlocks, kMaxSpmvBlocks), chunks);
     ALLOC(s->part, 4 * (size_t)s->npart);
     ALLOC(s->scal, S_NSCAL);
     ALLOC(s->ctrl, C_NCTRL);
@@ -369,6 +369,7 @@ int analyze_impl(const lpcg_csr *A, const int32_t *h_sys, int32_t nsys, lpcg_sys
     // SpMV lanes per row from the mean row length
     const double mean = (double)nnz / n;
     s->spmv_group = mean <= 4 ? 4 : mean <= 8 ? 8 : mean <= 16 ? 16 : mean <= 32 ? 32 : 64;
+    s->spmv_blocks = std::max(1, std::min(kMaxSpmvBlocks, nblk(n, kVecThreads / s->spmv_group)));
     k_values<<<nblk(std::max(n, nnz), 256), 256, 0, st>>>(nnz, n, A->val, s->dpos, s->val64, s->val32,
                                                            s->diag64);
     LPCG_LAUNCH_CHECK();

@@ -43,6 +43,7 @@ int launch_spmv(const lpcg_system *s, const VT *v, const XT *x, XT *y, hipStream
 // values against a separate flag.  A lane restarts the entry it is working on
 // when some value it needs is not yet published (non-blocking in the wave).
 constexpr uint64_t kUnset64 = 0x7fffffffffffffffull;
+constexpr int kIcRegDeps = 8;
 constexpr uint64_t kCanonNan64 = 0x7ff8000000000000ull;
 
 __device__ __forceinline__ uint64_t ld64(const uint64_t *p) {
@@ -69,9 +70,27 @@ __global__ void __launch_bounds__(256) k_ic0(int n, const int *__restrict__ orde
             b = lrp[row + 1];
             p = a;
         }
+        // Diagonal positions of the rows this row depends on (<= 8 of them
+        // are polled together, one memory round trip per round, before the
+        // entries are computed in order).
+        const int nd = b - a - 1;
+        const bool poll_first = nd > 0 && nd <= kIcRegDeps;
+        int jdiag[kIcRegDeps];
+#pragma unroll
+        for (int t = 0; t < kIcRegDeps; ++t) jdiag[t] = (poll_first && t < nd) ? lrp[lci[a + t] + 1] - 1 : 0;
+        bool diags_ready = !poll_first;
         bool pending = row >= 0;
         while (__ballot(pending) != 0) {
-            bool progress = pending;
+            if (pending && !diags_ready) {
+                uint64_t got[kIcRegDeps];
+#pragma unroll
+                for (int t = 0; t < kIcRegDeps; ++t) got[t] = t < nd ? ld64(&l64[jdiag[t]]) : 0ull;
+                bool ready = true;
+#pragma unroll
+                for (int t = 0; t < kIcRegDeps; ++t) ready = ready && (got[t] != kUnset64);
+                diags_ready = ready;
+            }
+            bool progress = pending && diags_ready;
             while (progress) {
                 if (p < b - 1) {
                     const int j = lci[p];

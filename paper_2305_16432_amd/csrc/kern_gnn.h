@@ -1,0 +1,133 @@
+// Building blocks of the GNN kernels: BF16 MFMA tiles (gfx950
+// v_mfma_f32_32x32x16_bf16) over 32 rows (nodes or directed edges) per wave.
+//
+// Orientation.  Every Linear layer y = x W is computed transposed,
+// D = W^T X^T, so that the rows (nodes/edges) are the 32 columns of the MFMA
+// tile:
+//   * B operand (X^T, K x 32): lane l holds row l%32 and 8 consecutive input
+//     features 8*(l/32) + 0..7 of K-step s (16 features per step) -- exactly a
+//     16-byte slice of the row in a row-major [rows x K] BF16 array;
+//   * A operand (W^T, 32 x K per output tile mt): lane l holds output
+//     feature mt*32 + l%32 and the same 8 input features;
+//   * accumulator D (32 x 32 per output tile): value i of lane l is output
+//     feature mt*32 + 8*(i/4) + 4*(l/32) + (i%4) of row l%32.
+// A layer whose input is the previous layer's accumulator (the hidden layer
+// of an MLP) takes its B operand straight from those registers; the K index
+// then runs over features in accumulator order, which is absorbed by reading
+// the weight rows in the same permuted order ("phi" order) when the A operand
+// is staged.  No transpose through LDS is needed between the two Linear
+// layers of an MLP.
+//
+// Weights are staged once per workgroup into LDS as BF16, already in operand
+// order (lane-contiguous 16-byte slices), from the FP32 master parameters.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "device_util.h"
+
+namespace lpcg {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kMaxMp = 8;
+
+// Offsets (in floats) of one MLP's tensors inside the flat parameter vector.
+struct MlpOff {
+    int W0, b0, W1, b1;
+};
+struct GnnOff {
+    MlpOff node_enc, edge_enc, node[kMaxMp], edge[kMaxMp], dec;
+    int total;
+};
+
+// Feature index of accumulator value i of lane l in output tile mt.
+__device__ __forceinline__ int acc_feat(int mt, int i, int lane) {
+    return mt * 32 + 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);
+}
+// Input feature of B-operand slot j at K-step s for lane l.
+//   natural order (input read from memory): s*16 + 8*(l/32) + j
+//   phi order (input = previous accumulators): acc_feat(s/2, (s%2)*8 + j, l)
+__device__ __forceinline__ int k_nat(int s, int j, int lane) { return s * 16 + 8 * (lane >> 5) + j; }
+__device__ __forceinline__ int k_phi(int s, int j, int lane) {
+    return acc_feat(s >> 1, ((s & 1) << 3) + j, lane);
+}
+
+// Stage W^T operands of a [K x M] FP32 row-major matrix W (row stride ldw,
+// first row k0) into LDS: slot ((mt*S + s)*64 + lane)*8 + j holds
+// W[k0 + korder(s, j, lane)][mt*32 + lane%32], S = K/16 steps, M/32 tiles.
+template <bool PHI>
+__device__ __forceinline__ void stage_weights(__bf16 *lds, const float *__restrict__ W, int ldw, int K,
+                                              int M) {
+    const int S = K / 16, MT = M / 32;
+    const int total = MT * S * 64 * 8;
+    for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+        const int j = idx & 7;
+        const int lane = (idx >> 3) & 63;
+        const int ms = idx >> 9;
+        const int s = ms % S, mt = ms / S;
+        const int k = PHI ? k_phi(s, j, lane) : k_nat(s, j, lane);
+        lds[idx] = (__bf16)W[(size_t)k * ldw + mt * 32 + (lane & 31)];
+    }
+}
+
+__device__ __forceinline__ bf16x8 lds_op(const __bf16 *lds, int S, int mt, int s, int lane) {
+    return *reinterpret_cast<const bf16x8 *>(lds + (((mt * S + s) << 6) + lane) * 8);
+}
+
+__device__ __forceinline__ f32x16 mfma(bf16x8 a, bf16x8 b, f32x16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ f32x16 zero16() {
+    f32x16 z;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) z[i] = 0.f;
+    return z;
+}
+
+// B operand for K-step s from accumulator tiles (phi order).
+template <int MT>
+__device__ __forceinline__ bf16x8 acc_operand(const f32x16 (&acc)[MT], int s) {
+    bf16x8 b;
+    const f32x16 &t = acc[s >> 1];
+    const int base = (s & 1) << 3;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) b[j] = (__bf16)t[base + j];
+    return b;
+}
+
+// 16-byte row slice load/store helpers (BF16 row-major arrays).
+__device__ __forceinline__ bf16x8 load8(const __bf16 *p) { return *reinterpret_cast<const bf16x8 *>(p); }
+
+// Store the accumulator tiles of one row (this lane's features) as BF16.
+template <int MT>
+__device__ __forceinline__ void store_acc_bf16(__bf16 *row, const f32x16 (&acc)[MT], int lane) {
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            bf16x4 v;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) v[r] = (__bf16)acc[mt][4 * q + r];
+            *reinterpret_cast<bf16x4 *>(row + acc_feat(mt, 4 * q, lane)) = v;
+        }
+}
+
+// Add bias (FP32 params) to accumulator tiles.
+template <int MT>
+__device__ __forceinline__ void add_bias(f32x16 (&acc)[MT], const float *__restrict__ b, int lane,
+                                         bool relu) {
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            float v = acc[mt][i] + b[acc_feat(mt, i, lane)];
+            acc[mt][i] = relu ? fmaxf(v, 0.f) : v;
+        }
+}
+
+}  // namespace lpcg

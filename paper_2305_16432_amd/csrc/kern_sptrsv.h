@@ -19,10 +19,18 @@
 namespace lpcg {
 
 constexpr int kTrsvBatch = 8;
+constexpr int kTrsvRegDeps = 8;  // rows with at most this many dependencies keep them in registers
 
 // Solves one chunk of 64 rows of the level order starting at `base`.
 // UPPER = 0: L in lower CSR, diagonal last; UPPER = 1: U = L^T in upper CSR,
 // diagonal first.  Returns (per lane) the row solved (-1 if none) and its value.
+//
+// A row with at most kTrsvRegDeps dependencies loads its column indices and
+// values into registers once, then each round re-reads all its dependency
+// values with independent loads (one memory round trip per round) and, once
+// none is unset, accumulates them in column order (fixed order: results are
+// bit-reproducible).  Longer rows consume the ready prefix of their entries in
+// batches of kTrsvBatch.
 template <bool UPPER>
 __device__ __forceinline__ int trsv_chunk(int n, int base, const int *__restrict__ order,
                                           const int *__restrict__ rp, const int *__restrict__ ci,
@@ -45,25 +53,53 @@ __device__ __forceinline__ int trsv_chunk(int n, int base, const int *__restrict
         }
         acc = rhs[row];
     }
+    const int nd = kend - k;
+    const bool in_regs = nd <= kTrsvRegDeps;
+    int cj[kTrsvRegDeps];
+    float vj[kTrsvRegDeps];
+#pragma unroll
+    for (int t = 0; t < kTrsvRegDeps; ++t) {
+        cj[t] = 0;
+        vj[t] = 0.f;
+        if (in_regs && t < nd) {
+            cj[t] = ci[k + t];
+            vj[t] = v[k + t];
+        }
+    }
     bool pending = row >= 0;
     while (__ballot(pending) != 0) {
         if (pending) {
-            while (k < kend) {
-                uint32_t got[kTrsvBatch];
-                const int m = min(kTrsvBatch, kend - k);
+            if (in_regs) {
+                uint32_t got[kTrsvRegDeps];
 #pragma unroll
-                for (int t = 0; t < kTrsvBatch; ++t)
-                    if (t < m) got[t] = ld_agent(&ybits[ci[k + t]]);
-                int used = 0;
+                for (int t = 0; t < kTrsvRegDeps; ++t) got[t] = t < nd ? ld_agent(&ybits[cj[t]]) : 0u;
+                bool ready = true;
 #pragma unroll
-                for (int t = 0; t < kTrsvBatch; ++t) {
-                    if (t < m && used == t && got[t] != kUnset) {
-                        acc -= v[k + t] * __uint_as_float(got[t]);
-                        ++used;
-                    }
+                for (int t = 0; t < kTrsvRegDeps; ++t) ready = ready && (got[t] != kUnset);
+                if (ready) {
+#pragma unroll
+                    for (int t = 0; t < kTrsvRegDeps; ++t)
+                        if (t < nd) acc -= vj[t] * __uint_as_float(got[t]);
+                    k = kend;
                 }
-                k += used;
-                if (used < m) break;
+            } else {
+                while (k < kend) {
+                    uint32_t got[kTrsvBatch];
+                    const int m = min(kTrsvBatch, kend - k);
+#pragma unroll
+                    for (int t = 0; t < kTrsvBatch; ++t)
+                        if (t < m) got[t] = ld_agent(&ybits[ci[k + t]]);
+                    int used = 0;
+#pragma unroll
+                    for (int t = 0; t < kTrsvBatch; ++t) {
+                        if (t < m && used == t && got[t] != kUnset) {
+                            acc -= v[k + t] * __uint_as_float(got[t]);
+                            ++used;
+                        }
+                    }
+                    k += used;
+                    if (used < m) break;
+                }
             }
             if (k == kend) {
                 const float yv = acc / dg;

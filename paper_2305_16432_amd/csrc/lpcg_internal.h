@@ -18,6 +18,7 @@ int hip_fail(hipError_t e, const char *what, const char *file, int line);
 // block, so the grid must stay fixed for the reduction order to be fixed.
 constexpr int kVecThreads = 256;
 constexpr int kMaxVecBlocks = 1024;
+constexpr int kMaxSpmvBlocks = 2048;
 
 // Layout of the small control words and FP64 scalars of a PCG solve.
 enum Ctrl : int {
@@ -69,6 +70,7 @@ struct lpcg_system {
     int *h_ctrl = nullptr;       // pinned host mirror of ctrl
     double *h_scal = nullptr;    // pinned host mirror of scal
     int vec_blocks = 1;          // grid of the fixed-grid vector kernels
+    int spmv_blocks = 1;         // grid of the fused SpMV + p.w kernel
     int spmv_group = 8;          // lanes per row in SpMV
     // cached iteration-chunk graph of the last PCG solve (captured on a
     // private stream, launched on the caller's)

@@ -44,7 +44,7 @@ namespace {
 constexpr int VT = kVecThreads;
 
 struct Args {
-    int n, np_vec, np_chunk, maxit, kind;
+    int n, np_vec, np_spmv, np_chunk, maxit, kind;
     const int *rp, *ci;
     const float *v32;
     const double *v64;
@@ -254,7 +254,7 @@ template <int KIND>
 __global__ void __launch_bounds__(VT) k_xr(Args a) {
     __shared__ double lds[VT / kWave];
     if (is_done(a)) return;
-    const double pw = reduce_partials<VT>(a.part_pw, a.np_vec, lds);
+    const double pw = reduce_partials<VT>(a.part_pw, a.np_spmv, lds);
     const double rz = a.scal[S_RZ0];
     if (!(pw > 0.0) || !isfinite(pw) || !isfinite(rz)) {
         if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -312,6 +312,7 @@ __global__ void __launch_bounds__(VT) k_true_fin(Args a) {
 template <int KIND>
 int enqueue_iteration(const lpcg_system *s, const Args &a, hipStream_t st) {
     const int vb = s->vec_blocks;
+    const int sb = s->spmv_blocks;
     if (KIND == LPCG_PC_LLT) {
         const int tb = (trsv_waves(s->n) + 3) / 4;
         k_llt_fwd<<<tb, 256, 0, st>>>(a);
@@ -320,11 +321,11 @@ int enqueue_iteration(const lpcg_system *s, const Args &a, hipStream_t st) {
     k_rz<KIND><<<1, 1024, 0, st>>>(a);
     k_pupd<KIND><<<vb, VT, 0, st>>>(a);
     switch (s->spmv_group) {
-        case 4: k_spmv_pw<4><<<vb, VT, 0, st>>>(a); break;
-        case 8: k_spmv_pw<8><<<vb, VT, 0, st>>>(a); break;
-        case 16: k_spmv_pw<16><<<vb, VT, 0, st>>>(a); break;
-        case 32: k_spmv_pw<32><<<vb, VT, 0, st>>>(a); break;
-        default: k_spmv_pw<64><<<vb, VT, 0, st>>>(a); break;
+        case 4: k_spmv_pw<4><<<sb, VT, 0, st>>>(a); break;
+        case 8: k_spmv_pw<8><<<sb, VT, 0, st>>>(a); break;
+        case 16: k_spmv_pw<16><<<sb, VT, 0, st>>>(a); break;
+        case 32: k_spmv_pw<32><<<sb, VT, 0, st>>>(a); break;
+        default: k_spmv_pw<64><<<sb, VT, 0, st>>>(a); break;
     }
     k_xr<KIND><<<vb, VT, 0, st>>>(a);
     LPCG_LAUNCH_CHECK();
@@ -422,6 +423,7 @@ extern "C" int lpcg_pcg_solve(lpcg_system *s, const lpcg_precond *P, const doubl
     Args a{};
     a.n = s->n;
     a.np_vec = s->vec_blocks;
+    a.np_spmv = s->spmv_blocks;
     a.np_chunk = (s->n + kWave - 1) / kWave;
     a.maxit = opts->maxit > 0 ? opts->maxit : s->n;
     a.kind = P->kind;

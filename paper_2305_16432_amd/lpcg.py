@@ -270,3 +270,75 @@ def time_spmv(sys: System, x, reps=50):
     rc = lib().lpcg_time_spmv(sys.handle, _ptr(x), _ptr(out), C.c_int32(reps), C.byref(ms), _stream())
     _check(rc, "lpcg_time_spmv")
     return ms.value
+
+
+# ---------------------------------------------------------------------- GNN
+def param_layout(h: int, n_mp: int):
+    """(name, shape) of every tensor of the flat FP32 parameter vector, in the
+    order of include/lpcg.h (node_enc, edge_enc, mp{t}.node, mp{t}.edge, dec;
+    each MLP: W0, b0, W1, b1 with W stored [fan_in][fan_out])."""
+    out = []
+
+    def mlp(prefix, fin, fout):
+        out.extend([(f"{prefix}.W0", (fin, h)), (f"{prefix}.b0", (h,)),
+                    (f"{prefix}.W1", (h, fout)), (f"{prefix}.b1", (fout,))])
+    mlp("node_enc", 1, h)
+    mlp("edge_enc", 1, h)
+    for t in range(n_mp):
+        mlp(f"mp{t}.node", 2 * h, h)
+        mlp(f"mp{t}.edge", 3 * h, h)
+    mlp("dec", h, 1)
+    return out
+
+
+def param_count(h: int, n_mp: int) -> int:
+    return int(lib().lpcg_gnn_param_count(h, n_mp))
+
+
+def pack_params(P: dict, h: int, n_mp: int) -> torch.Tensor:
+    """Flatten a dict of named arrays into the library's FP32 layout (host)."""
+    import numpy as np
+    parts = []
+    for name, shape in param_layout(h, n_mp):
+        a = np.asarray(P[name], dtype=np.float32)
+        if a.shape != shape:
+            raise ValueError(f"{name}: shape {a.shape}, expected {shape}")
+        parts.append(a.reshape(-1))
+    flat = np.concatenate(parts)
+    assert flat.shape[0] == param_count(h, n_mp)
+    return torch.as_tensor(flat)
+
+
+def unpack_params(flat, h: int, n_mp: int) -> dict:
+    import numpy as np
+    flat = np.asarray(flat.detach().cpu() if torch.is_tensor(flat) else flat)
+    out, p = {}, 0
+    for name, shape in param_layout(h, n_mp):
+        k = int(np.prod(shape))
+        out[name] = flat[p:p + k].reshape(shape)
+        p += k
+    return out
+
+
+def gnn_workspace(sys: System, h: int, n_mp: int, train: bool = False) -> torch.Tensor:
+    nbytes = int(lib().lpcg_gnn_workspace_bytes(sys.handle, h, n_mp, 1 if train else 0))
+    if nbytes < 0:
+        raise ValueError("invalid GNN dimensions")
+    return torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+
+
+def _net(params, h, n_mp):
+    if params.dtype != torch.float32:
+        raise TypeError("params must be float32")
+    return _Gnn(h, n_mp, _ptr(params))
+
+
+def gnn_predict_L(sys: System, params, h: int, n_mp: int, b, ws, l_val=None, ut_val=None):
+    nl = sys.info["nnz_l"]
+    if l_val is None:
+        l_val = torch.empty(nl, dtype=torch.float32, device="cuda")
+    net = _net(params, h, n_mp)
+    rc = lib().lpcg_gnn_predict_L(sys.handle, C.byref(net), _ptr(b), _ptr(ws), C.c_int64(ws.numel()),
+                                  _ptr(l_val), _ptr(ut_val), _stream())
+    _check(rc, "lpcg_gnn_predict_L")
+    return l_val, ut_val
