@@ -167,3 +167,16 @@ def training_loss(A, b, x, lval, pat_lrowptr, pat_lcol, llt_loss):
     _, rms = normalisation(A, b)
     loss, g = llt_loss(lval, x, b)
     return loss / rms ** 2, g / rms ** 2
+
+
+def adam(params, grads, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam step (Kingma & Ba 2015, Algorithm 1) on dicts of float64
+    arrays; returns (params, m, v) as new dicts."""
+    P, M, Vv = {}, {}, {}
+    for k in params:
+        M[k] = beta1 * m[k] + (1 - beta1) * grads[k]
+        Vv[k] = beta2 * v[k] + (1 - beta2) * grads[k] ** 2
+        mhat = M[k] / (1 - beta1 ** step)
+        vhat = Vv[k] / (1 - beta2 ** step)
+        P[k] = params[k] - lr * mhat / (np.sqrt(vhat) + eps)
+    return P, M, Vv

@@ -358,6 +358,10 @@ int analyze_impl(const lpcg_csr *A, const int32_t *h_sys, int32_t nsys, lpcg_sys
     ALLOC(s->z, n);
     ALLOC(s->y, n);
     ALLOC(s->dinv, n);
+    ALLOC(s->t64a, n);
+    ALLOC(s->t64b, n);
+    ALLOC(s->t64c, n);
+    ALLOC(s->sys_tmp, 2 * (size_t)nsys);
     s->vec_blocks = std::max(1, std::min(kMaxVecBlocks, nblk(n, kVecThreads * 4)));
     const int chunks = nblk(n, kWave);
     s->npart = std::max(std::max(kMaxVecBlocks, kMaxSpmvBlocks), chunks);

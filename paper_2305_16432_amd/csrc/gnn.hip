@@ -47,21 +47,21 @@ GnnOff gnn_offsets(int h, int n_mp) {
     return o;
 }
 
-// Workspace layout (byte offsets, 256-byte aligned).
+// Workspace layout (byte offsets, 256-byte aligned).  Inference keeps two
+// V/E buffers (ping-pong); training keeps every layer's activations plus the
+// backward pass's intermediates.
 struct GnnWs {
     size_t sys_s, sys_rms;
     size_t V[kMaxMp + 1], Pa[kMaxMp], Pb[kMaxMp], E[kMaxMp + 1];
     size_t d;
-    // backward scratch
-    size_t gd, gE[2], gV[2], gH, gPa, gPb, wpart;
+    // backward (train only)
+    size_t gd, gE[2], gV[2], gVmlp, gm, GH, G1, GVN, GH1, H1, Mt, gPa, gPb, HD, GHD, Henc, GHenc, Xn, Xe;
+    size_t wpart;
     size_t total;
 };
 
-// Waves that keep private weight-gradient partials in the backward pass.
-int gnn_wpart_waves(const lpcg_system *s) {
-    (void)s;
-    return 1024;
-}
+// Blocks of the weight-gradient kernels = number of per-block partial sums.
+constexpr int kWgradBlocks = 256;
 
 GnnWs gnn_ws_layout(const lpcg_system *s, int h, int n_mp, bool train) {
     GnnWs w{};
@@ -71,7 +71,7 @@ GnnWs gnn_ws_layout(const lpcg_system *s, int h, int n_mp, bool train) {
         off += (bytes + 255) & ~(size_t)255;
         return o;
     };
-    const size_t n = s->n, nnz = s->nnz;
+    const size_t n = s->n, nnz = s->nnz, mx = std::max(n, nnz);
     w.sys_s = take(sizeof(double) * s->nsys);
     w.sys_rms = take(sizeof(double) * s->nsys);
     const int nv = train ? n_mp + 1 : 2;
@@ -89,11 +89,24 @@ GnnWs gnn_ws_layout(const lpcg_system *s, int h, int n_mp, bool train) {
         w.gE[1] = take(4 * nnz * h);
         w.gV[0] = take(4 * n * h);
         w.gV[1] = take(4 * n * h);
-        w.gH = take(4 * nnz * h);
+        w.gVmlp = take(4 * n * h);
+        w.gm = take(4 * n * h);
+        w.GH = take(4 * nnz * h);
+        w.G1 = take(2 * nnz * h);
+        w.GVN = take(4 * n * h);
+        w.GH1 = take(4 * n * h);
+        w.H1 = take(2 * n * h);
+        w.Mt = take(2 * n * h);
         w.gPa = take(4 * n * h);
         w.gPb = take(4 * n * h);
+        w.HD = take(2 * nnz * h);
+        w.GHD = take(4 * nnz * h);
+        w.Henc = take(2 * mx * h);
+        w.GHenc = take(4 * mx * h);
+        w.Xn = take(4 * n);
+        w.Xe = take(4 * nnz);
         const GnnOff o = gnn_offsets(h, n_mp);
-        w.wpart = take(sizeof(float) * (size_t)o.total * gnn_wpart_waves(s));
+        w.wpart = take(sizeof(float) * (size_t)o.total * kWgradBlocks);
     }
     w.total = off;
     return w;
@@ -135,7 +148,7 @@ __global__ void __launch_bounds__(kGnnThreads) k_enc(int rows, const float *__re
                                                      const int *__restrict__ erow,
                                                      const int *__restrict__ row_sys,
                                                      const double *__restrict__ sys_scale,
-                                                     __bf16 *__restrict__ out) {
+                                                     __bf16 *__restrict__ out, float *__restrict__ xs_out) {
     constexpr int S = H / 16, MT = H / 32;
     __shared__ __bf16 w1[H * H];
     stage_weights<false>(w1, P + m.W1, H, H, H);
@@ -167,6 +180,7 @@ __global__ void __launch_bounds__(kGnnThreads) k_enc(int rows, const float *__re
         }
         add_bias<MT>(acc, b1, lane, false);
         if (valid) store_acc_bf16<MT>(out + (size_t)r * H, acc, lane);
+        if (valid && xs_out && lane < 32) xs_out[r] = x;
     }
 }
 
@@ -395,9 +409,11 @@ int forward_impl(const lpcg_system *s, const lpcg_gnn *net, const double *b, uns
     auto Pb = [&](int t) { return (__bf16 *)(ws + L.Pb[train ? t : 0]); };
     float *d = (float *)(ws + L.d);
     k_enc<H, true><<<gnn_blocks(s->n), kGnnThreads, 0, st>>>(s->n, P, o.node_enc, b, s->erow, s->row_sys,
-                                                              sys_rms, V(0));
+                                                              sys_rms, V(0),
+                                                              train ? (float *)(ws + L.Xn) : nullptr);
     k_enc<H, false><<<gnn_blocks(s->nnz), kGnnThreads, 0, st>>>(s->nnz, P, o.edge_enc, s->val64, s->erow,
-                                                                 s->row_sys, sys_s, E(0));
+                                                                 s->row_sys, sys_s, E(0),
+                                                                 train ? (float *)(ws + L.Xe) : nullptr);
     const int T = net->n_mp;
     for (int t = 0; t < T; ++t) {
         k_node<H><<<gnn_blocks(s->n), kGnnThreads, 0, st>>>(s->n, s->rowptr, s->colind, P, o.node[t],
@@ -465,4 +481,628 @@ extern "C" int lpcg_gnn_predict_L(const lpcg_system *s, const lpcg_gnn *net, con
 extern "C" int lpcg_gnn_forward_train(const lpcg_system *s, const lpcg_gnn *net, const double *b, void *ws,
                                       int64_t ws_bytes, float *l_val, hipStream_t st) {
     return gnn_forward(s, net, b, ws, ws_bytes, true, l_val, nullptr, st);
+}
+
+// ===========================================================================
+// Reverse mode of the network (hand-written).  For every Linear layer
+// y = x W + b the data gradient gx = g W^T runs on MFMA with W staged
+// untransposed; weight gradients dW = X^T G and bias gradients sum(G) are
+// reductions over all rows done by one generic kernel (k_wgrad) into
+// per-block partials, summed in a fixed order at the end (no atomics: the
+// gradient is bit-reproducible).  Forward pre-activations are recomputed from
+// the BF16 activations kept by the training forward.
+// ===========================================================================
+namespace lpcg {
+namespace {
+
+__device__ __forceinline__ float sigmoid_f(float x) { return 1.f / (1.f + expf(-x)); }
+
+// d loss / d d_k from d loss / d L (pair average, softplus diagonal, sqrt(s)).
+__global__ void k_assemble_bwd(int nnz, const int *__restrict__ rowptr, const int *__restrict__ lrowptr,
+                               const int *__restrict__ erow, const int *__restrict__ col,
+                               const int *__restrict__ rev, const int *__restrict__ row_sys,
+                               const double *__restrict__ sys_s, const float *__restrict__ d,
+                               const float *__restrict__ gl, float *__restrict__ gd) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nnz) return;
+    const int i = erow[k], j = col[k];
+    const float sq = (float)sqrt(sys_s[row_sys[i]]);
+    float g;
+    if (i == j) {
+        const int p = lrowptr[i] + (k - rowptr[i]);
+        g = softplus_f(d[k]) > 1e-6f ? sq * gl[p] * sigmoid_f(d[k]) : 0.f;
+    } else if (i > j) {
+        g = 0.5f * sq * gl[lrowptr[i] + (k - rowptr[i])];
+    } else {
+        const int kr = rev[k];
+        g = 0.5f * sq * gl[lrowptr[j] + (kr - rowptr[j])];
+    }
+    gd[k] = g;
+}
+
+// Decoder: pre = E_T Wd0 + bd0, d = relu(pre) wd1 + bd1.  Writes the hidden
+// activation HD, its gradient GHD and d loss / d E_T.
+template <int H>
+__global__ void __launch_bounds__(kGnnThreads) k_dec_bwd(int nnz, const float *__restrict__ P, MlpOff md,
+                                                         const __bf16 *__restrict__ ET,
+                                                         const float *__restrict__ gd, __bf16 *__restrict__ HD,
+                                                         float *__restrict__ GHD, float *__restrict__ gE) {
+    constexpr int S = H / 16, MT = H / 32;
+    __shared__ __bf16 wd[H * H], wdT[H * H];
+    stage_weights<false>(wd, P + md.W0, H, H, H);
+    stage_weightsT<true>(wdT, P + md.W0, H, H, H);
+    __syncthreads();
+    const int lane = lane_id();
+    const float *w1d = P + md.W1;
+    const int ntiles = (nnz + 31) / 32;
+    for (int tile = blockIdx.x * 4 + threadIdx.x / kWave; tile < ntiles; tile += gridDim.x * 4) {
+        const int e = tile * 32 + (lane & 31);
+        const bool valid = e < nnz;
+        f32x16 pre[MT];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) pre[mt] = zero16();
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            bf16x8 b;
+            if (valid) {
+                b = load8(ET + (size_t)e * H + k_nat(s, 0, lane));
+            } else {
+#pragma unroll
+                for (int j = 0; j < 8; ++j) b[j] = (__bf16)0.f;
+            }
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) pre[mt] = mfma(lds_op(wd, S, mt, s, lane), b, pre[mt]);
+        }
+        add_bias<MT>(pre, P + md.b0, lane, false);
+        const float ge = valid ? gd[e] : 0.f;
+        f32x16 hd[MT], g[MT];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const float v = pre[mt][i];
+                hd[mt][i] = fmaxf(v, 0.f);
+                g[mt][i] = v > 0.f ? ge * w1d[acc_feat(mt, i, lane)] : 0.f;
+            }
+        f32x16 gx[MT];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) gx[mt] = zero16();
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const bf16x8 b = acc_operand<MT>(g, s);
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) gx[mt] = mfma(lds_op(wdT, S, mt, s, lane), b, gx[mt]);
+        }
+        if (valid) {
+            store_acc_bf16<MT>(HD + (size_t)e * H, hd, lane);
+            store_acc_f32<MT>(GHD + (size_t)e * H, g, lane);
+            store_acc_f32<MT>(gE + (size_t)e * H, gx, lane);
+        }
+    }
+}
+
+// Edge layer t: recompute g1 = relu(E_t We + Pa[r] + Pb[c] + b0); from
+// gEn = d loss / d E_{t+1}: GH = (gEn W1^T) * [g1 > 0], gEt = GH We^T.
+template <int H>
+__global__ void __launch_bounds__(kGnnThreads) k_edge_bwd(int nnz, const int *__restrict__ erow,
+                                                          const int *__restrict__ col,
+                                                          const float *__restrict__ P, MlpOff me,
+                                                          const __bf16 *__restrict__ Et,
+                                                          const __bf16 *__restrict__ Pa,
+                                                          const __bf16 *__restrict__ Pb,
+                                                          const float *__restrict__ gEn, __bf16 *__restrict__ G1,
+                                                          float *__restrict__ GH, float *__restrict__ gEt) {
+    constexpr int S = H / 16, MT = H / 32;
+    __shared__ __bf16 we[H * H], w1T[H * H], weT[H * H];
+    stage_weights<false>(we, P + me.W0, H, H, H);
+    stage_weightsT<false>(w1T, P + me.W1, H, H, H);
+    stage_weightsT<true>(weT, P + me.W0, H, H, H);
+    __syncthreads();
+    const int lane = lane_id();
+    const float *b0 = P + me.b0;
+    const int ntiles = (nnz + 31) / 32;
+    for (int tile = blockIdx.x * 4 + threadIdx.x / kWave; tile < ntiles; tile += gridDim.x * 4) {
+        const int e = tile * 32 + (lane & 31);
+        const bool valid = e < nnz;
+        const int r = valid ? erow[e] : 0, c = valid ? col[e] : 0;
+        f32x16 pre[MT], gg[MT];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+            pre[mt] = zero16();
+            gg[mt] = zero16();
+        }
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            bf16x8 bx, bg;
+            if (valid) {
+                bx = load8(Et + (size_t)e * H + k_nat(s, 0, lane));
+                bg = load8f(gEn + (size_t)e * H + k_nat(s, 0, lane));
+            } else {
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    bx[j] = (__bf16)0.f;
+                    bg[j] = (__bf16)0.f;
+                }
+            }
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) {
+                pre[mt] = mfma(lds_op(we, S, mt, s, lane), bx, pre[mt]);
+                gg[mt] = mfma(lds_op(w1T, S, mt, s, lane), bg, gg[mt]);
+            }
+        }
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int f = acc_feat(mt, 4 * q, lane);
+                bf16x4 ga, gb;
+                if (valid) {
+                    ga = *reinterpret_cast<const bf16x4 *>(Pa + (size_t)r * H + f);
+                    gb = *reinterpret_cast<const bf16x4 *>(Pb + (size_t)c * H + f);
+                }
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const float add = valid ? (float)ga[t] + (float)gb[t] : 0.f;
+                    const float v = pre[mt][4 * q + t] + add + b0[f + t];
+                    pre[mt][4 * q + t] = fmaxf(v, 0.f);
+                    if (!(v > 0.f)) gg[mt][4 * q + t] = 0.f;
+                }
+            }
+        f32x16 gx[MT];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) gx[mt] = zero16();
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const bf16x8 b = acc_operand<MT>(gg, s);
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) gx[mt] = mfma(lds_op(weT, S, mt, s, lane), b, gx[mt]);
+        }
+        if (valid) {
+            store_acc_bf16<MT>(G1 + (size_t)e * H, pre, lane);
+            store_acc_f32<MT>(GH + (size_t)e * H, gg, lane);
+            store_acc_f32<MT>(gEt + (size_t)e * H, gx, lane);
+        }
+    }
+}
+
+// Node layer t.  From GH (edge hidden gradients): gPa_i = sum_{k in row i}
+// GH[k], gPb_j = sum_{k in row j} GH[rev k]; gVn = gVacc + gPa Wa^T + gPb Wb^T
+// (d loss / d V_{t+1}); node MLP: recompute X = [V_t, m_t], h1 = relu(X W0 +
+// b0); GH1 = (gVn W1^T) * [h1 > 0]; [gVmlp, gm] = GH1 W0^T.
+template <int H>
+__global__ void __launch_bounds__(kGnnThreads) k_node_bwd(
+    int n, const int *__restrict__ rowptr, const int *__restrict__ col, const int *__restrict__ rev,
+    const float *__restrict__ P, MlpOff mv, MlpOff me, const __bf16 *__restrict__ Vt,
+    const __bf16 *__restrict__ Et, const float *__restrict__ GH, const float *__restrict__ gVacc,
+    float *__restrict__ gPa, float *__restrict__ gPb, __bf16 *__restrict__ H1, float *__restrict__ GVN,
+    float *__restrict__ GH1, __bf16 *__restrict__ Mt, float *__restrict__ gm, float *__restrict__ gVmlp) {
+    constexpr int S = H / 16, MT = H / 32;
+    __shared__ __bf16 w0[2 * H * H], waT[H * H], wbT[H * H], w1T[H * H], w0T[2 * H * H];
+    stage_weights<false>(w0, P + mv.W0, H, 2 * H, H);
+    stage_weightsT<false>(waT, P + me.W0 + H * H, H, H, H);
+    stage_weightsT<false>(wbT, P + me.W0 + 2 * H * H, H, H, H);
+    stage_weightsT<true>(w1T, P + mv.W1, H, H, H);
+    stage_weightsT<true>(w0T, P + mv.W0, H, H, 2 * H);
+    __syncthreads();
+    const int lane = lane_id();
+    const int ntiles = (n + 31) / 32;
+    for (int tile = blockIdx.x * 4 + threadIdx.x / kWave; tile < ntiles; tile += gridDim.x * 4) {
+        const int i = tile * 32 + (lane & 31);
+        const bool valid = i < n;
+        // gPa, gPb in natural order; B operands of the projection gradients
+        f32x16 gvn[MT];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) gvn[mt] = zero16();
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            float sa[8], sb[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) sa[j] = sb[j] = 0.f;
+            if (valid) {
+                const int f = k_nat(s, 0, lane);
+                for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+                    const float *ga = GH + (size_t)k * H + f;
+                    const float *gb = GH + (size_t)rev[k] * H + f;
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) {
+                        sa[j] += ga[j];
+                        sb[j] += gb[j];
+                    }
+                }
+                float *oa = gPa + (size_t)i * H + f, *ob = gPb + (size_t)i * H + f;
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    oa[j] = sa[j];
+                    ob[j] = sb[j];
+                }
+            }
+            bf16x8 ba, bb;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                ba[j] = (__bf16)sa[j];
+                bb[j] = (__bf16)sb[j];
+            }
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) {
+                gvn[mt] = mfma(lds_op(waT, S, mt, s, lane), ba, gvn[mt]);
+                gvn[mt] = mfma(lds_op(wbT, S, mt, s, lane), bb, gvn[mt]);
+            }
+        }
+        if (valid && gVacc) {
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const f32x4 v = *reinterpret_cast<const f32x4 *>(gVacc + (size_t)i * H + acc_feat(mt, 4 * q, lane));
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) gvn[mt][4 * q + t] += v[t];
+                }
+        }
+        // recompute the node MLP input and hidden layer
+        bf16x8 bx[2 * S];
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            if (valid) {
+                bx[s] = load8(Vt + (size_t)i * H + k_nat(s, 0, lane));
+            } else {
+#pragma unroll
+                for (int j = 0; j < 8; ++j) bx[s][j] = (__bf16)0.f;
+            }
+        }
+        float msum[S][8];
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) msum[s][j] = 0.f;
+        if (valid) {
+            for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+                const int c = col[k];
+#pragma unroll
+                for (int s = 0; s < S; ++s) {
+                    const bf16x8 e8 = load8(Et + (size_t)k * H + k_nat(s, 0, lane));
+                    const bf16x8 v8 = load8(Vt + (size_t)c * H + k_nat(s, 0, lane));
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) msum[s][j] += (float)e8[j] * (float)v8[j];
+                }
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) bx[S + s][j] = (__bf16)msum[s][j];
+            if (valid) *reinterpret_cast<bf16x8 *>(Mt + (size_t)i * H + k_nat(s, 0, lane)) = bx[S + s];
+        }
+        f32x16 h1[MT];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) h1[mt] = zero16();
+#pragma unroll
+        for (int s = 0; s < 2 * S; ++s)
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) h1[mt] = mfma(lds_op(w0, 2 * S, mt, s, lane), bx[s], h1[mt]);
+        add_bias<MT>(h1, P + mv.b0, lane, false);
+        f32x16 gh1[MT];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) gh1[mt] = zero16();
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const bf16x8 b = acc_operand<MT>(gvn, s);
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) gh1[mt] = mfma(lds_op(w1T, S, mt, s, lane), b, gh1[mt]);
+        }
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const bool on = h1[mt][q] > 0.f;
+                h1[mt][q] = on ? h1[mt][q] : 0.f;
+                if (!on) gh1[mt][q] = 0.f;
+            }
+        f32x16 gx[2 * MT];
+#pragma unroll
+        for (int mt = 0; mt < 2 * MT; ++mt) gx[mt] = zero16();
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const bf16x8 b = acc_operand<MT>(gh1, s);
+#pragma unroll
+            for (int mt = 0; mt < 2 * MT; ++mt) gx[mt] = mfma(lds_op(w0T, S, mt, s, lane), b, gx[mt]);
+        }
+        if (valid) {
+            store_acc_f32<MT>(GVN + (size_t)i * H, gvn, lane);
+            store_acc_bf16<MT>(H1 + (size_t)i * H, h1, lane);
+            store_acc_f32<MT>(GH1 + (size_t)i * H, gh1, lane);
+            f32x16 gv[MT], gmm[MT];
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) {
+                gv[mt] = gx[mt];
+                gmm[mt] = gx[MT + mt];
+            }
+            store_acc_f32<MT>(gVmlp + (size_t)i * H, gv, lane);
+            store_acc_f32<MT>(gm + (size_t)i * H, gmm, lane);
+        }
+    }
+}
+
+// Adjoint of m_i = sum_{k in row i} E[k] * V[col k] with respect to E:
+// gE[k] += gm[row k] * V[col k].
+template <int H>
+__global__ void k_agg_bwd_edge(int nnz, const int *__restrict__ erow, const int *__restrict__ col,
+                               const __bf16 *__restrict__ V, const float *__restrict__ gm, float *__restrict__ gE) {
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long)nnz * (H / 4)) return;
+    const int e = (int)(idx / (H / 4)), f = (int)(idx % (H / 4)) * 4;
+    const int r = erow[e], c = col[e];
+    f32x4 g = *reinterpret_cast<f32x4 *>(gE + (size_t)e * H + f);
+    const f32x4 m = *reinterpret_cast<const f32x4 *>(gm + (size_t)r * H + f);
+    const bf16x4 v = *reinterpret_cast<const bf16x4 *>(V + (size_t)c * H + f);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) g[t] += m[t] * (float)v[t];
+    *reinterpret_cast<f32x4 *>(gE + (size_t)e * H + f) = g;
+}
+
+// ... and with respect to V: gV[j] = gVmlp[j] + sum_{k in row j} gm[col k] * E[rev k]
+// (the entries (i, j) with col = j are the reverses of row j's entries).
+template <int H>
+__global__ void k_agg_bwd_node(int n, const int *__restrict__ rowptr, const int *__restrict__ col,
+                               const int *__restrict__ rev, const __bf16 *__restrict__ E,
+                               const float *__restrict__ gm, const float *__restrict__ gVmlp,
+                               float *__restrict__ gV) {
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long)n * (H / 4)) return;
+    const int j = (int)(idx / (H / 4)), f = (int)(idx % (H / 4)) * 4;
+    f32x4 g = *reinterpret_cast<const f32x4 *>(gVmlp + (size_t)j * H + f);
+    for (int k = rowptr[j]; k < rowptr[j + 1]; ++k) {
+        const f32x4 m = *reinterpret_cast<const f32x4 *>(gm + (size_t)col[k] * H + f);
+        const bf16x4 e = *reinterpret_cast<const bf16x4 *>(E + (size_t)rev[k] * H + f);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) g[t] += m[t] * (float)e[t];
+    }
+    *reinterpret_cast<f32x4 *>(gV + (size_t)j * H + f) = g;
+}
+
+// Encoder: h = relu(x W0 + b0) (kept as Henc), GHenc = (gOut W1^T) * [h > 0],
+// Xs = x.
+template <int H>
+__global__ void __launch_bounds__(kGnnThreads) k_enc_bwd(int rows, const float *__restrict__ P, MlpOff m,
+                                                         const float *__restrict__ xs,
+                                                         const float *__restrict__ gOut, __bf16 *__restrict__ Henc,
+                                                         float *__restrict__ GHenc) {
+    constexpr int S = H / 16, MT = H / 32;
+    __shared__ __bf16 w1T[H * H];
+    stage_weightsT<false>(w1T, P + m.W1, H, H, H);
+    __syncthreads();
+    const int lane = lane_id();
+    const float *W0 = P + m.W0, *b0 = P + m.b0;
+    const int ntiles = (rows + 31) / 32;
+    for (int tile = blockIdx.x * 4 + threadIdx.x / kWave; tile < ntiles; tile += gridDim.x * 4) {
+        const int r = tile * 32 + (lane & 31);
+        const bool valid = r < rows;
+        const float x = valid ? xs[r] : 0.f;
+        f32x16 gh[MT];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) gh[mt] = zero16();
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            bf16x8 hb, gb;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int k = k_nat(s, j, lane);
+                hb[j] = (__bf16)fmaxf(x * W0[k] + b0[k], 0.f);
+            }
+            if (valid) {
+                *reinterpret_cast<bf16x8 *>(Henc + (size_t)r * H + k_nat(s, 0, lane)) = hb;
+                gb = load8f(gOut + (size_t)r * H + k_nat(s, 0, lane));
+            } else {
+#pragma unroll
+                for (int j = 0; j < 8; ++j) gb[j] = (__bf16)0.f;
+            }
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) gh[mt] = mfma(lds_op(w1T, S, mt, s, lane), gb, gh[mt]);
+        }
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int f = acc_feat(mt, i, lane);
+                if (!(x * W0[f] + b0[f] > 0.f)) gh[mt][i] = 0.f;
+            }
+        if (valid) store_acc_f32<MT>(GHenc + (size_t)r * H, gh, lane);
+    }
+}
+
+// Sources of the weight-gradient reduction dW = X^T G (rows x K each).
+enum SrcKind : int { SRC_BF16 = 0, SRC_F32 = 1, SRC_SCALAR = 2, SRC_BF16_CAT = 3 };
+struct WSrc {
+    int kind;
+    const void *a;  // matrix / scalar vector / first half of a concatenation
+    const void *b;  // second half (SRC_BF16_CAT), same width as the first
+    int K;          // columns (1 for scalars; total width for concatenations)
+};
+
+__device__ __forceinline__ float src_at(const WSrc &s, int row, int c) {
+    switch (s.kind) {
+        case SRC_BF16: return (float)((const __bf16 *)s.a)[(size_t)row * s.K + c];
+        case SRC_F32: return ((const float *)s.a)[(size_t)row * s.K + c];
+        case SRC_SCALAR: return c == 0 ? ((const float *)s.a)[row] : 0.f;
+        default: {
+            const int half = s.K / 2;
+            return c < half ? (float)((const __bf16 *)s.a)[(size_t)row * half + c]
+                            : (float)((const __bf16 *)s.b)[(size_t)row * half + (c - half)];
+        }
+    }
+}
+
+// Per-block partial of dW = X^T G (and sum(G) for the bias) over the rows.
+// Each wave stages 32-row tiles transposed in its own LDS slice and
+// accumulates on MFMA with the rows as the contraction; the block's 4 waves
+// are summed in a fixed order.  KXP / MP: K of X and G padded to 32.
+template <int KXP, int MP>
+__global__ void __launch_bounds__(kGnnThreads) k_wgrad(int rows, WSrc X, WSrc G, int Mreal,
+                                                       float *__restrict__ wpart, int ptotal, int offW,
+                                                       int offB) {
+    constexpr int KT = KXP / 32, MTN = MP / 32;
+    __shared__ __bf16 xt[4][KXP * 32];
+    __shared__ __bf16 gt[4][MP * 32];
+    __shared__ float red[4][32 * 32];
+    __shared__ float bred[4][64];
+    const int lane = lane_id(), w = threadIdx.x / kWave;
+    f32x16 acc[KT][MTN];
+#pragma unroll
+    for (int a = 0; a < KT; ++a)
+#pragma unroll
+        for (int b = 0; b < MTN; ++b) acc[a][b] = zero16();
+    float bsum = 0.f;
+    const int ntiles = (rows + 31) / 32;
+    for (int tile = blockIdx.x * 4 + w; tile < ntiles; tile += gridDim.x * 4) {
+        for (int idx = lane; idx < 32 * KXP; idx += kWave) {
+            const int r = idx / KXP, c = idx % KXP;
+            const int row = tile * 32 + r;
+            const float v = (row < rows && c < X.K) ? src_at(X, row, c) : 0.f;
+            xt[w][c * 32 + r] = (__bf16)v;
+        }
+        for (int idx = lane; idx < 32 * MP; idx += kWave) {
+            const int r = idx / MP, c = idx % MP;
+            const int row = tile * 32 + r;
+            const float v = (row < rows && c < G.K) ? src_at(G, row, c) : 0.f;
+            gt[w][c * 32 + r] = (__bf16)v;
+            bsum += v;  // column c = lane % MP for this lane, fixed
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+#pragma unroll
+            for (int a = 0; a < KT; ++a) {
+                const bf16x8 av =
+                    *reinterpret_cast<const bf16x8 *>(&xt[w][(a * 32 + (lane & 31)) * 32 + s * 16 + 8 * (lane >> 5)]);
+#pragma unroll
+                for (int b = 0; b < MTN; ++b) {
+                    const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(
+                        &gt[w][(b * 32 + (lane & 31)) * 32 + s * 16 + 8 * (lane >> 5)]);
+                    acc[a][b] = mfma(av, bv, acc[a][b]);
+                }
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    // fixed-order sum over the block's waves, one 32x32 tile at a time
+    for (int a = 0; a < KT; ++a)
+        for (int b = 0; b < MTN; ++b) {
+#pragma unroll
+            for (int i = 0; i < 16; ++i) red[w][(8 * (i >> 2) + 4 * (lane >> 5) + (i & 3)) * 32 + (lane & 31)] = acc[a][b][i];
+            __syncthreads();
+            for (int e = threadIdx.x; e < 32 * 32; e += kGnnThreads) {
+                const float v = red[0][e] + red[1][e] + red[2][e] + red[3][e];
+                const int kx = a * 32 + e / 32, m = b * 32 + e % 32;
+                if (kx < X.K && m < Mreal) wpart[(size_t)blockIdx.x * ptotal + offW + (size_t)kx * Mreal + m] = v;
+            }
+            __syncthreads();
+        }
+    if (offB >= 0) {
+        if (MP == 32) bsum += __shfl_xor(bsum, 32, kWave);
+        if (lane < MP) bred[w][lane] = bsum;
+        __syncthreads();
+        if (threadIdx.x < Mreal)
+            wpart[(size_t)blockIdx.x * ptotal + offB + threadIdx.x] =
+                bred[0][threadIdx.x] + bred[1][threadIdx.x] + bred[2][threadIdx.x] + bred[3][threadIdx.x];
+    }
+}
+
+__global__ void k_wreduce(int ptotal, int nb, const float *__restrict__ wpart, float *__restrict__ dparams) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ptotal) return;
+    float s = 0.f;
+    for (int b = 0; b < nb; ++b) s += wpart[(size_t)b * ptotal + i];
+    dparams[i] = s;
+}
+
+template <int KXP, int MP>
+void wgrad(int rows, WSrc X, WSrc G, int Mreal, float *wpart, int ptotal, int offW, int offB, hipStream_t st) {
+    k_wgrad<KXP, MP><<<kWgradBlocks, kGnnThreads, 0, st>>>(rows, X, G, Mreal, wpart, ptotal, offW, offB);
+}
+
+template <int H>
+int backward_impl(const lpcg_system *s, const lpcg_gnn *net, unsigned char *ws, const GnnWs &L,
+                  const float *dl, float *dparams, hipStream_t st) {
+    const int T = net->n_mp;
+    const GnnOff o = gnn_offsets(H, T);
+    const float *P = net->params;
+    auto V = [&](int t) { return (const __bf16 *)(ws + L.V[t]); };
+    auto E = [&](int t) { return (const __bf16 *)(ws + L.E[t]); };
+    auto F = [&](size_t off) { return (float *)(ws + off); };
+    auto B16 = [&](size_t off) { return (__bf16 *)(ws + off); };
+    const double *sys_s = (const double *)(ws + L.sys_s), *sys_rms = (const double *)(ws + L.sys_rms);
+    float *wpart = F(L.wpart);
+    const int n = s->n, nnz = s->nnz, pt = o.total;
+    auto bf = [](const void *p, int K) { return WSrc{SRC_BF16, p, nullptr, K}; };
+    auto f32 = [](const void *p, int K) { return WSrc{SRC_F32, p, nullptr, K}; };
+    auto sc = [](const void *p) { return WSrc{SRC_SCALAR, p, nullptr, 1}; };
+
+    k_assemble_bwd<<<nblk(nnz, 256), 256, 0, st>>>(nnz, s->rowptr, s->lrowptr, s->erow, s->colind, s->rev,
+                                                    s->row_sys, sys_s, F(L.d), dl, F(L.gd));
+    k_dec_bwd<H><<<gnn_blocks(nnz), kGnnThreads, 0, st>>>(nnz, P, o.dec, E(T), F(L.gd), B16(L.HD), F(L.GHD),
+                                                          F(L.gE[T & 1]));
+    wgrad<H, H>(nnz, bf(E(T), H), f32(F(L.GHD), H), H, wpart, pt, o.dec.W0, o.dec.b0, st);
+    wgrad<H, 32>(nnz, bf(B16(L.HD), H), sc(F(L.gd)), 1, wpart, pt, o.dec.W1, o.dec.b1, st);
+    const float *gVacc = nullptr;
+    for (int t = T - 1; t >= 0; --t) {
+        float *gEn = F(L.gE[(t + 1) & 1]), *gEt = F(L.gE[t & 1]);
+        k_edge_bwd<H><<<gnn_blocks(nnz), kGnnThreads, 0, st>>>(nnz, s->erow, s->colind, P, o.edge[t], E(t),
+                                                               (const __bf16 *)(ws + L.Pa[t]),
+                                                               (const __bf16 *)(ws + L.Pb[t]), gEn, B16(L.G1),
+                                                               F(L.GH), gEt);
+        wgrad<H, H>(nnz, bf(B16(L.G1), H), f32(gEn, H), H, wpart, pt, o.edge[t].W1, o.edge[t].b1, st);
+        wgrad<H, H>(nnz, bf(E(t), H), f32(F(L.GH), H), H, wpart, pt, o.edge[t].W0, o.edge[t].b0, st);
+        k_node_bwd<H><<<gnn_blocks(n), kGnnThreads, 0, st>>>(
+            n, s->rowptr, s->colind, s->rev, P, o.node[t], o.edge[t], V(t), E(t), F(L.GH), gVacc, F(L.gPa),
+            F(L.gPb), B16(L.H1), F(L.GVN), F(L.GH1), B16(L.Mt), F(L.gm), F(L.gVmlp));
+        wgrad<H, H>(n, bf(V(t + 1), H), f32(F(L.gPa), H), H, wpart, pt, o.edge[t].W0 + H * H, -1, st);
+        wgrad<H, H>(n, bf(V(t + 1), H), f32(F(L.gPb), H), H, wpart, pt, o.edge[t].W0 + 2 * H * H, -1, st);
+        wgrad<H, H>(n, bf(B16(L.H1), H), f32(F(L.GVN), H), H, wpart, pt, o.node[t].W1, o.node[t].b1, st);
+        wgrad<2 * H, H>(n, WSrc{SRC_BF16_CAT, V(t), B16(L.Mt), 2 * H}, f32(F(L.GH1), H), H, wpart, pt,
+                        o.node[t].W0, o.node[t].b0, st);
+        k_agg_bwd_edge<H><<<nblk((long)nnz * (H / 4), 256), 256, 0, st>>>(nnz, s->erow, s->colind, V(t), F(L.gm),
+                                                                          gEt);
+        float *gVout = F(L.gV[t & 1]);
+        k_agg_bwd_node<H><<<nblk((long)n * (H / 4), 256), 256, 0, st>>>(n, s->rowptr, s->colind, s->rev, E(t),
+                                                                        F(L.gm), F(L.gVmlp), gVout);
+        gVacc = gVout;
+    }
+    // encoders: node (gradient gVacc w.r.t. V_0), edge (gE[0] w.r.t. E_0)
+    k_enc_bwd<H><<<gnn_blocks(n), kGnnThreads, 0, st>>>(n, P, o.node_enc, F(L.Xn), gVacc, B16(L.Henc),
+                                                         F(L.GHenc));
+    wgrad<H, H>(n, bf(B16(L.Henc), H), f32(gVacc, H), H, wpart, pt, o.node_enc.W1, o.node_enc.b1, st);
+    wgrad<32, H>(n, sc(F(L.Xn)), f32(F(L.GHenc), H), H, wpart, pt, o.node_enc.W0, o.node_enc.b0, st);
+    k_enc_bwd<H><<<gnn_blocks(nnz), kGnnThreads, 0, st>>>(nnz, P, o.edge_enc, F(L.Xe), F(L.gE[0]), B16(L.Henc),
+                                                           F(L.GHenc));
+    wgrad<H, H>(nnz, bf(B16(L.Henc), H), f32(F(L.gE[0]), H), H, wpart, pt, o.edge_enc.W1, o.edge_enc.b1, st);
+    wgrad<32, H>(nnz, sc(F(L.Xe)), f32(F(L.GHenc), H), H, wpart, pt, o.edge_enc.W0, o.edge_enc.b0, st);
+    k_wreduce<<<nblk(pt, 256), 256, 0, st>>>(pt, kWgradBlocks, wpart, dparams);
+    (void)sys_rms;
+    LPCG_LAUNCH_CHECK();
+    return LPCG_OK;
+}
+
+}  // namespace
+}  // namespace lpcg
+
+using namespace lpcg;
+
+extern "C" int lpcg_gnn_backward(const lpcg_system *s, const lpcg_gnn *net, void *ws, int64_t ws_bytes,
+                                 const float *dl_val, float *dparams, hipStream_t st) {
+    int rc = check_net(net);
+    if (rc) return rc;
+    if (!s || !ws || !dl_val || !dparams) {
+        set_error("lpcg_gnn_backward: invalid arguments");
+        return LPCG_EINVAL;
+    }
+    const GnnWs L = gnn_ws_layout(s, net->h, net->n_mp, true);
+    if ((size_t)ws_bytes < L.total) {
+        set_error("lpcg_gnn_backward: workspace of %lld bytes, %zu needed", (long long)ws_bytes, L.total);
+        return LPCG_ENOMEM;
+    }
+    if (net->h == 32) return backward_impl<32>(s, net, (unsigned char *)ws, L, dl_val, dparams, st);
+    return backward_impl<64>(s, net, (unsigned char *)ws, L, dl_val, dparams, st);
 }

@@ -74,6 +74,25 @@ __device__ __forceinline__ void stage_weights(__bf16 *lds, const float *__restri
     }
 }
 
+// Stage W (untransposed) operands for a data-gradient product gx = g W^T,
+// computed as gx^T = W g^T: the contraction runs over W's columns (fan_out,
+// Kc of them) and the output over its rows (fan_in, Mo of them).  Slot
+// ((mt*S + s)*64 + lane)*8 + j holds W[mt*32 + lane%32][korder(s, j, lane)].
+template <bool PHI>
+__device__ __forceinline__ void stage_weightsT(__bf16 *lds, const float *__restrict__ W, int ldw, int Kc,
+                                               int Mo) {
+    const int S = Kc / 16, MT = Mo / 32;
+    const int total = MT * S * 64 * 8;
+    for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+        const int j = idx & 7;
+        const int lane = (idx >> 3) & 63;
+        const int ms = idx >> 9;
+        const int s = ms % S, mt = ms / S;
+        const int k = PHI ? k_phi(s, j, lane) : k_nat(s, j, lane);
+        lds[idx] = (__bf16)W[(size_t)(mt * 32 + (lane & 31)) * ldw + k];
+    }
+}
+
 __device__ __forceinline__ bf16x8 lds_op(const __bf16 *lds, int S, int mt, int s, int lane) {
     return *reinterpret_cast<const bf16x8 *>(lds + (((mt * S + s) << 6) + lane) * 8);
 }
@@ -97,6 +116,33 @@ __device__ __forceinline__ bf16x8 acc_operand(const f32x16 (&acc)[MT], int s) {
     const int base = (s & 1) << 3;
 #pragma unroll
     for (int j = 0; j < 8; ++j) b[j] = (__bf16)t[base + j];
+    return b;
+}
+
+// Store the accumulator tiles of one row as FP32.
+template <int MT>
+__device__ __forceinline__ void store_acc_f32(float *row, const f32x16 (&acc)[MT], int lane) {
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            f32x4 v;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) v[r] = acc[mt][4 * q + r];
+            *reinterpret_cast<f32x4 *>(row + acc_feat(mt, 4 * q, lane)) = v;
+        }
+}
+
+// B operand for K-step s from a row-major FP32 row (natural order).
+__device__ __forceinline__ bf16x8 load8f(const float *p) {
+    const f32x4 a = *reinterpret_cast<const f32x4 *>(p);
+    const f32x4 c = *reinterpret_cast<const f32x4 *>(p + 4);
+    bf16x8 b;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        b[j] = (__bf16)a[j];
+        b[4 + j] = (__bf16)c[j];
+    }
     return b;
 }
 

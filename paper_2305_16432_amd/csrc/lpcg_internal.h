@@ -63,6 +63,8 @@ struct lpcg_system {
     double *diag64 = nullptr;
     // solver work vectors (device)
     float *r = nullptr, *p = nullptr, *w = nullptr, *z = nullptr, *y = nullptr, *dinv = nullptr;
+    double *t64a = nullptr, *t64b = nullptr, *t64c = nullptr;  // FP64 work vectors (loss)
+    double *sys_tmp = nullptr;                                  // [2 * nsys] per-system scalars
     double *part = nullptr;      // partial sums (3 x max(kMaxVecBlocks, chunks))
     int npart = 0;               // stride between the partial arrays
     double *scal = nullptr;      // FP64 scalars (Scal)

@@ -342,3 +342,74 @@ def gnn_predict_L(sys: System, params, h: int, n_mp: int, b, ws, l_val=None, ut_
                                   _ptr(l_val), _ptr(ut_val), _stream())
     _check(rc, "lpcg_gnn_predict_L")
     return l_val, ut_val
+
+
+def gnn_forward_train(sys: System, params, h: int, n_mp: int, b, ws, l_val=None):
+    nl = sys.info["nnz_l"]
+    if l_val is None:
+        l_val = torch.empty(nl, dtype=torch.float32, device="cuda")
+    net = _net(params, h, n_mp)
+    rc = lib().lpcg_gnn_forward_train(sys.handle, C.byref(net), _ptr(b), _ptr(ws), C.c_int64(ws.numel()),
+                                      _ptr(l_val), _stream())
+    _check(rc, "lpcg_gnn_forward_train")
+    return l_val
+
+
+def gnn_backward(sys: System, params, h: int, n_mp: int, ws, dl_val, dparams=None):
+    if dparams is None:
+        dparams = torch.empty_like(params)
+    net = _net(params, h, n_mp)
+    rc = lib().lpcg_gnn_backward(sys.handle, C.byref(net), _ptr(ws), C.c_int64(ws.numel()),
+                                 _ptr(dl_val.contiguous()), _ptr(dparams), _stream())
+    _check(rc, "lpcg_gnn_backward")
+    return dparams
+
+
+def llt_loss(sys: System, l_val, x, b, grad=True):
+    """(loss per system [nsys] FP64, d sum(loss) / d L FP32 or None)."""
+    loss = torch.empty(sys.info["nsys"], dtype=torch.float64, device="cuda")
+    dl = torch.empty_like(l_val) if grad else None
+    rc = lib().lpcg_llt_loss(sys.handle, _ptr(l_val), _ptr(x), _ptr(b), _ptr(loss), _ptr(dl), _stream())
+    _check(rc, "lpcg_llt_loss")
+    return loss, dl
+
+
+def adam_step(params, grads, m, v, lr, step, beta1=0.9, beta2=0.999, eps=1e-8):
+    rc = lib().lpcg_adam_step(_ptr(params), _ptr(grads), _ptr(m), _ptr(v), C.c_int64(params.numel()),
+                              C.c_float(lr), C.c_float(beta1), C.c_float(beta2), C.c_float(eps),
+                              C.c_int32(step), _stream())
+    _check(rc, "lpcg_adam_step")
+
+
+class GnnL(torch.autograd.Function):
+    """L = GNN(A, b; params) with the library's forward and hand-written
+    backward (argument marshalling only)."""
+
+    @staticmethod
+    def forward(ctx, params, sys, h, n_mp, b, ws):
+        l_val = gnn_forward_train(sys, params, h, n_mp, b, ws)
+        ctx.sys, ctx.h, ctx.n_mp, ctx.ws = sys, h, n_mp, ws
+        ctx.save_for_backward(params)
+        return l_val
+
+    @staticmethod
+    def backward(ctx, g_l):
+        (params,) = ctx.saved_tensors
+        dparams = gnn_backward(ctx.sys, params, ctx.h, ctx.n_mp, ctx.ws, g_l.float().contiguous())
+        return dparams, None, None, None, None, None
+
+
+class LltLoss(torch.autograd.Function):
+    """sum over systems of ||L L^T x - b||^2 / rms(b)^2 with the library's
+    closed-form gradient."""
+
+    @staticmethod
+    def forward(ctx, l_val, sys, x, b):
+        loss, dl = llt_loss(sys, l_val, x, b, grad=True)
+        ctx.save_for_backward(dl)
+        return loss.sum()
+
+    @staticmethod
+    def backward(ctx, g):
+        (dl,) = ctx.saved_tensors
+        return (dl * g.to(dl.dtype)), None, None, None

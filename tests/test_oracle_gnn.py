@@ -187,3 +187,22 @@ def test_training_loss_normalisation():
                                lambda lv, xx, bb: O.llt_loss(pat, lv, xx, bb))
     assert np.isclose(l1, l2, rtol=1e-12)
     np.testing.assert_allclose(g1, g2, rtol=1e-10, atol=1e-12 * np.max(np.abs(g1)))
+
+
+def test_adam_first_step_is_signed_lr_and_minimises_quadratic():
+    """First step from zero moments: m_hat = g, v_hat = g^2, so the update is
+    lr * g / (|g| + eps) = lr * sign(g) up to eps.  On f(p) = sum(c p^2 / 2)
+    the iterates approach the minimiser 0."""
+    rng = np.random.default_rng(0)
+    p0 = {"w": rng.standard_normal(50)}
+    g = {"w": rng.standard_normal(50)}
+    z = {"w": np.zeros(50)}
+    p1, _, _ = gnn.adam(p0, g, z, z, step=1, lr=1e-2)
+    np.testing.assert_allclose(p0["w"] - p1["w"], 1e-2 * g["w"] / (np.abs(g["w"]) + 1e-8), rtol=1e-12)
+    assert np.all(np.sign(p0["w"] - p1["w"]) == np.sign(g["w"]))
+    c = rng.uniform(0.5, 2.0, 50)
+    p, m, v = {"w": rng.standard_normal(50)}, dict(z), dict(z)
+    start = np.abs(p["w"]).max()
+    for t in range(1, 3001):
+        p, m, v = gnn.adam(p, {"w": c * p["w"]}, m, v, step=t, lr=1e-2)
+    assert np.abs(p["w"]).max() < 0.05 * start
