@@ -122,11 +122,12 @@ def main():
         if hasattr(lpcg, "gnn_predict_L") and os.path.exists(WEIGHTS):
             W = np.load(WEIGHTS)
             h, n_mp = int(W["h"]), int(W["n_mp"])
+            dmode = int(W["diag_mode"]) if "diag_mode" in W else 0
             params = torch.as_tensor(W["params"].astype(np.float32)).cuda()
             ws = lpcg.gnn_workspace(S, h, n_mp, train=False)
 
             def run_learned():
-                lpcg.gnn_predict_L(S, params, h, n_mp, bd, ws, lval, utval)
+                lpcg.gnn_predict_L(S, params, h, n_mp, bd, ws, lval, utval, diag_mode=dmode)
             methods["learned"] = (run_learned, solve_llt)
         else:
             learned_note = "learned-L unavailable (no trained weights in this build)"

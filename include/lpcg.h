@@ -206,6 +206,9 @@ typedef struct {
     int32_t h;
     int32_t n_mp;
     const float *params;
+    int32_t diag_mode;  /* 0: L_ii = sqrt(s) max(softplus(d_ii), 1e-6), L_ij = sqrt(s) (d_ij+d_ji)/2;
+                           1: L' D L'^T with D = diag(A) (technical-details appendix):
+                              L_ii = sqrt(A_ii), L_ij = sqrt(A_jj) (d_ij + d_ji)/2 */
 } lpcg_gnn;
 
 /* Number of FP32 parameters of the layout above. */
@@ -218,8 +221,8 @@ int64_t lpcg_gnn_workspace_bytes(const lpcg_system *sys, int32_t h, int32_t n_mp
 
 /* gnn_predict_L(graph, weights) -> L.  Node input b_i / rms(b), edge input
  * A_ij / s with s = mean(diag A) (per system of a batch); d_ij = decoder
- * output per directed edge; L_ij = sqrt(s) (d_ij + d_ji) / 2 for i > j and
- * L_ii = sqrt(s) max(softplus(d_ii), 1e-6).  b: FP64 [n].  ws: device
+ * output per directed edge, assembled on the lower triangle as documented
+ * for lpcg_gnn.diag_mode.  b: FP64 [n].  ws: device
  * workspace of lpcg_gnn_workspace_bytes(.., 0) bytes.  Writes l_val and
  * ut_val (either may be NULL).  Errors: EINVAL (h, n_mp), ENOMEM (ws too
  * small). */

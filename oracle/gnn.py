@@ -19,8 +19,12 @@ Readings where the paper is silent (each listed in the design notes):
     without degree normalisation;
   * normalisation: s = mean(diag A), edge input A_ij/s, node input b_i/rms(b);
     the network's factor is scaled back by sqrt(s): L = sqrt(s) * L_hat;
-  * the diagonal, where the pair average is d_ii itself, is made positive with
-    L_ii = max(softplus(d_ii), 1e-6) so that L L^T is SPD by construction.
+  * diag_mode 0: the diagonal, where the pair average is d_ii itself, is made
+    positive with L_ii = max(softplus(d_ii), 1e-6) so that L L^T is SPD by
+    construction, and L = sqrt(s) * L_hat;
+  * diag_mode 1 (the appendix's L D L^T form with D = diag(A)): the network
+    predicts a unit lower-triangular L' and P = L' D L'^T = L L^T with
+    L = L' D^(1/2), i.e. L_ii = sqrt(A_ii), L_ij = sqrt(A_jj) (d_ij + d_ji)/2.
 
 Pins (tests/test_oracle_gnn.py): all-zero weights give a closed form; a
 2-node graph computed by hand; permutation equivariance; 5-hop locality;
@@ -84,7 +88,7 @@ def reverse_map(A):
     return q
 
 
-def forward(A, b, P, h, n_mp, rev=None, keep=False):
+def forward(A, b, P, h, n_mp, rev=None, keep=False, diag_mode=0):
     """L values on the lower pattern (i >= j) in CSR order, float64.
 
     Returns (lval, cache) where cache (if keep) holds what backward needs.
@@ -113,12 +117,20 @@ def forward(A, b, P, h, n_mp, rev=None, keep=False):
     d = d[:, 0]
     lower = col <= row
     diag = col == row
-    lhat = np.where(diag, np.maximum(_softplus(d), SOFTPLUS_FLOOR), 0.5 * (d + d[rev]))
-    lval = np.sqrt(s) * lhat[lower]
+    if diag_mode == 0:
+        lhat = np.where(diag, np.maximum(_softplus(d), SOFTPLUS_FLOOR), 0.5 * (d + d[rev]))
+        lval = np.sqrt(s) * lhat[lower]
+        colscale = None
+    else:
+        adiag = A.val[diag]                       # A_jj, j = 0..n-1
+        colscale = np.sqrt(adiag[np.minimum(row, col)])  # sqrt(A_cc), cc = column of the lower entry
+        lfull = np.where(diag, np.sqrt(adiag[row]), colscale * 0.5 * (d + d[rev]))
+        lval = lfull[lower]
     cache = None
     if keep:
         cache = dict(row=row, col=col, rev=rev, s=s, rms=rms, d=d, lower=lower, diag=diag,
-                     Vs=Vs, Es=Es, mlp=caches, n=n, h=h, n_mp=n_mp)
+                     Vs=Vs, Es=Es, mlp=caches, n=n, h=h, n_mp=n_mp, diag_mode=diag_mode,
+                     colscale=colscale)
     return lval, cache
 
 
@@ -129,14 +141,20 @@ def backward(P, cache, glval):
     n, h, n_mp = cache["n"], cache["h"], cache["n_mp"]
     d, lower, diag = cache["d"], cache["lower"], cache["diag"]
     nnz = d.shape[0]
-    glhat = np.zeros(nnz)
-    glhat[np.nonzero(lower)[0]] = np.sqrt(cache["s"]) * np.asarray(glval, np.float64)
     gd = np.zeros(nnz)
-    # diagonal: max(softplus(d), floor)
-    sp = _softplus(d)
-    gd += np.where(diag & (sp > SOFTPLUS_FLOOR), glhat * _sigmoid(d), 0.0)
-    # strictly lower: (d_k + d_rev(k)) / 2
     off = lower & ~diag
+    if cache.get("diag_mode", 0) == 0:
+        glhat = np.zeros(nnz)
+        glhat[np.nonzero(lower)[0]] = np.sqrt(cache["s"]) * np.asarray(glval, np.float64)
+        # diagonal: max(softplus(d), floor)
+        sp = _softplus(d)
+        gd += np.where(diag & (sp > SOFTPLUS_FLOOR), glhat * _sigmoid(d), 0.0)
+    else:
+        # diagonal fixed to sqrt(A_ii); strictly lower scaled by sqrt(A_jj)
+        glhat = np.zeros(nnz)
+        glhat[np.nonzero(lower)[0]] = np.asarray(glval, np.float64)
+        glhat = glhat * np.where(diag, 0.0, cache["colscale"])
+    # strictly lower: (d_k + d_rev(k)) / 2
     gd += np.where(off, 0.5 * glhat, 0.0)
     np.add.at(gd, rev[off], 0.5 * glhat[off])
     gE = _mlp_bwd(P, "dec", cache["mlp"]["dec"], gd[:, None], G)

@@ -374,24 +374,29 @@ __global__ void __launch_bounds__(kGnnThreads) k_edge(int nnz, const int *__rest
 __device__ __forceinline__ float softplus_f(float x) { return x > 20.f ? x : log1pf(expf(x)); }
 
 // L value of the lower-pattern entry with A-position k.
-__device__ __forceinline__ float l_entry(int k, const int *__restrict__ erow, const int *__restrict__ col,
-                                         const int *__restrict__ rev, const int *__restrict__ row_sys,
-                                         const double *__restrict__ sys_s, const float *__restrict__ d) {
-    const int i = erow[k];
-    const float sq = (float)sqrt(sys_s[row_sys[i]]);
-    if (col[k] == i) return sq * fmaxf(softplus_f(d[k]), 1e-6f);
-    return sq * 0.5f * (d[k] + d[rev[k]]);
+__device__ __forceinline__ float l_entry(int k, int mode, const int *__restrict__ erow,
+                                         const int *__restrict__ col, const int *__restrict__ rev,
+                                         const int *__restrict__ row_sys, const double *__restrict__ sys_s,
+                                         const double *__restrict__ diag64, const float *__restrict__ d) {
+    const int i = erow[k], j = col[k];
+    if (mode == 0) {
+        const float sq = (float)sqrt(sys_s[row_sys[i]]);
+        if (j == i) return sq * fmaxf(softplus_f(d[k]), 1e-6f);
+        return sq * 0.5f * (d[k] + d[rev[k]]);
+    }
+    if (j == i) return (float)sqrt(diag64[i]);
+    return (float)sqrt(diag64[j]) * (0.5f * (d[k] + d[rev[k]]));
 }
 
-__global__ void k_assemble(int nnz_l, const int *__restrict__ lsrc, const int *__restrict__ u2l,
+__global__ void k_assemble(int nnz_l, int mode, const int *__restrict__ lsrc, const int *__restrict__ u2l,
                            const int *__restrict__ erow, const int *__restrict__ col,
                            const int *__restrict__ rev, const int *__restrict__ row_sys,
-                           const double *__restrict__ sys_s, const float *__restrict__ d,
-                           float *__restrict__ lval, float *__restrict__ utval) {
+                           const double *__restrict__ sys_s, const double *__restrict__ diag64,
+                           const float *__restrict__ d, float *__restrict__ lval, float *__restrict__ utval) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= nnz_l) return;
-    if (lval) lval[p] = l_entry(lsrc[p], erow, col, rev, row_sys, sys_s, d);
-    if (utval) utval[p] = l_entry(lsrc[u2l[p]], erow, col, rev, row_sys, sys_s, d);
+    if (lval) lval[p] = l_entry(lsrc[p], mode, erow, col, rev, row_sys, sys_s, diag64, d);
+    if (utval) utval[p] = l_entry(lsrc[u2l[p]], mode, erow, col, rev, row_sys, sys_s, diag64, d);
 }
 
 int gnn_blocks(long rows) { return std::max(1, std::min(kMaxGnnBlocks, nblk(rows, 32 * 4))); }
@@ -426,15 +431,17 @@ int forward_impl(const lpcg_system *s, const lpcg_gnn *net, const double *b, uns
                 s->nnz, s->erow, s->colind, P, o.edge[t], o.dec, E(t), Pa(t), Pb(t),
                 train ? E(t + 1) : nullptr, d);
     }
-    k_assemble<<<nblk(s->nnz_l, 256), 256, 0, st>>>(s->nnz_l, s->lsrc, s->u2l, s->erow, s->colind, s->rev,
-                                                     s->row_sys, sys_s, d, lval, utval);
+    k_assemble<<<nblk(s->nnz_l, 256), 256, 0, st>>>(s->nnz_l, net->diag_mode, s->lsrc, s->u2l, s->erow,
+                                                     s->colind, s->rev, s->row_sys, sys_s, s->diag64, d, lval,
+                                                     utval);
     LPCG_LAUNCH_CHECK();
     return LPCG_OK;
 }
 
 int check_net(const lpcg_gnn *net) {
-    if (!net || !net->params || (net->h != 32 && net->h != 64) || net->n_mp < 1 || net->n_mp > kMaxMp) {
-        set_error("gnn: h must be 32 or 64 and 1 <= n_mp <= %d", kMaxMp);
+    if (!net || !net->params || (net->h != 32 && net->h != 64) || net->n_mp < 1 || net->n_mp > kMaxMp ||
+        (net->diag_mode != 0 && net->diag_mode != 1)) {
+        set_error("gnn: h must be 32 or 64, 1 <= n_mp <= %d, diag_mode 0 or 1", kMaxMp);
         return LPCG_EINVAL;
     }
     return LPCG_OK;
@@ -497,25 +504,32 @@ namespace {
 
 __device__ __forceinline__ float sigmoid_f(float x) { return 1.f / (1.f + expf(-x)); }
 
-// d loss / d d_k from d loss / d L (pair average, softplus diagonal, sqrt(s)).
-__global__ void k_assemble_bwd(int nnz, const int *__restrict__ rowptr, const int *__restrict__ lrowptr,
+// d loss / d d_k from d loss / d L (pair average; softplus diagonal and sqrt(s)
+// in mode 0; fixed diagonal and sqrt(A_jj) column scale in mode 1).
+__global__ void k_assemble_bwd(int nnz, int mode, const int *__restrict__ rowptr, const int *__restrict__ lrowptr,
                                const int *__restrict__ erow, const int *__restrict__ col,
                                const int *__restrict__ rev, const int *__restrict__ row_sys,
-                               const double *__restrict__ sys_s, const float *__restrict__ d,
-                               const float *__restrict__ gl, float *__restrict__ gd) {
+                               const double *__restrict__ sys_s, const double *__restrict__ diag64,
+                               const float *__restrict__ d, const float *__restrict__ gl, float *__restrict__ gd) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= nnz) return;
     const int i = erow[k], j = col[k];
-    const float sq = (float)sqrt(sys_s[row_sys[i]]);
     float g;
     if (i == j) {
         const int p = lrowptr[i] + (k - rowptr[i]);
-        g = softplus_f(d[k]) > 1e-6f ? sq * gl[p] * sigmoid_f(d[k]) : 0.f;
-    } else if (i > j) {
-        g = 0.5f * sq * gl[lrowptr[i] + (k - rowptr[i])];
+        if (mode == 0) {
+            const float sq = (float)sqrt(sys_s[row_sys[i]]);
+            g = softplus_f(d[k]) > 1e-6f ? sq * gl[p] * sigmoid_f(d[k]) : 0.f;
+        } else {
+            g = 0.f;
+        }
     } else {
-        const int kr = rev[k];
-        g = 0.5f * sq * gl[lrowptr[j] + (kr - rowptr[j])];
+        // the lower entry of the pair: (i, j) if i > j, else (j, i)
+        const int lo_r = i > j ? i : j, lo_c = i > j ? j : i;
+        const int klo = i > j ? k : rev[k];
+        const int p = lrowptr[lo_r] + (klo - rowptr[lo_r]);
+        const float scale = mode == 0 ? (float)sqrt(sys_s[row_sys[i]]) : (float)sqrt(diag64[lo_c]);
+        g = 0.5f * scale * gl[p];
     }
     gd[k] = g;
 }
@@ -1040,8 +1054,9 @@ int backward_impl(const lpcg_system *s, const lpcg_gnn *net, unsigned char *ws, 
     auto f32 = [](const void *p, int K) { return WSrc{SRC_F32, p, nullptr, K}; };
     auto sc = [](const void *p) { return WSrc{SRC_SCALAR, p, nullptr, 1}; };
 
-    k_assemble_bwd<<<nblk(nnz, 256), 256, 0, st>>>(nnz, s->rowptr, s->lrowptr, s->erow, s->colind, s->rev,
-                                                    s->row_sys, sys_s, F(L.d), dl, F(L.gd));
+    k_assemble_bwd<<<nblk(nnz, 256), 256, 0, st>>>(nnz, net->diag_mode, s->rowptr, s->lrowptr, s->erow,
+                                                    s->colind, s->rev, s->row_sys, sys_s, s->diag64, F(L.d), dl,
+                                                    F(L.gd));
     k_dec_bwd<H><<<gnn_blocks(nnz), kGnnThreads, 0, st>>>(nnz, P, o.dec, E(T), F(L.gd), B16(L.HD), F(L.GHD),
                                                           F(L.gE[T & 1]));
     wgrad<H, H>(nnz, bf(E(T), H), f32(F(L.GHD), H), H, wpart, pt, o.dec.W0, o.dec.b0, st);

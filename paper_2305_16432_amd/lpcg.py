@@ -56,7 +56,7 @@ class _Result(C.Structure):
 
 
 class _Gnn(C.Structure):
-    _fields_ = [("h", C.c_int32), ("n_mp", C.c_int32), ("params", C.c_void_p)]
+    _fields_ = [("h", C.c_int32), ("n_mp", C.c_int32), ("params", C.c_void_p), ("diag_mode", C.c_int32)]
 
 
 _lib = None
@@ -327,38 +327,38 @@ def gnn_workspace(sys: System, h: int, n_mp: int, train: bool = False) -> torch.
     return torch.empty(nbytes, dtype=torch.uint8, device="cuda")
 
 
-def _net(params, h, n_mp):
+def _net(params, h, n_mp, diag_mode=0):
     if params.dtype != torch.float32:
         raise TypeError("params must be float32")
-    return _Gnn(h, n_mp, _ptr(params))
+    return _Gnn(h, n_mp, _ptr(params), diag_mode)
 
 
-def gnn_predict_L(sys: System, params, h: int, n_mp: int, b, ws, l_val=None, ut_val=None):
+def gnn_predict_L(sys: System, params, h: int, n_mp: int, b, ws, l_val=None, ut_val=None, diag_mode=0):
     nl = sys.info["nnz_l"]
     if l_val is None:
         l_val = torch.empty(nl, dtype=torch.float32, device="cuda")
-    net = _net(params, h, n_mp)
+    net = _net(params, h, n_mp, diag_mode)
     rc = lib().lpcg_gnn_predict_L(sys.handle, C.byref(net), _ptr(b), _ptr(ws), C.c_int64(ws.numel()),
                                   _ptr(l_val), _ptr(ut_val), _stream())
     _check(rc, "lpcg_gnn_predict_L")
     return l_val, ut_val
 
 
-def gnn_forward_train(sys: System, params, h: int, n_mp: int, b, ws, l_val=None):
+def gnn_forward_train(sys: System, params, h: int, n_mp: int, b, ws, l_val=None, diag_mode=0):
     nl = sys.info["nnz_l"]
     if l_val is None:
         l_val = torch.empty(nl, dtype=torch.float32, device="cuda")
-    net = _net(params, h, n_mp)
+    net = _net(params, h, n_mp, diag_mode)
     rc = lib().lpcg_gnn_forward_train(sys.handle, C.byref(net), _ptr(b), _ptr(ws), C.c_int64(ws.numel()),
                                       _ptr(l_val), _stream())
     _check(rc, "lpcg_gnn_forward_train")
     return l_val
 
 
-def gnn_backward(sys: System, params, h: int, n_mp: int, ws, dl_val, dparams=None):
+def gnn_backward(sys: System, params, h: int, n_mp: int, ws, dl_val, dparams=None, diag_mode=0):
     if dparams is None:
         dparams = torch.empty_like(params)
-    net = _net(params, h, n_mp)
+    net = _net(params, h, n_mp, diag_mode)
     rc = lib().lpcg_gnn_backward(sys.handle, C.byref(net), _ptr(ws), C.c_int64(ws.numel()),
                                  _ptr(dl_val.contiguous()), _ptr(dparams), _stream())
     _check(rc, "lpcg_gnn_backward")
@@ -386,17 +386,18 @@ class GnnL(torch.autograd.Function):
     backward (argument marshalling only)."""
 
     @staticmethod
-    def forward(ctx, params, sys, h, n_mp, b, ws):
-        l_val = gnn_forward_train(sys, params, h, n_mp, b, ws)
-        ctx.sys, ctx.h, ctx.n_mp, ctx.ws = sys, h, n_mp, ws
+    def forward(ctx, params, sys, h, n_mp, b, ws, diag_mode=0):
+        l_val = gnn_forward_train(sys, params, h, n_mp, b, ws, diag_mode=diag_mode)
+        ctx.sys, ctx.h, ctx.n_mp, ctx.ws, ctx.diag_mode = sys, h, n_mp, ws, diag_mode
         ctx.save_for_backward(params)
         return l_val
 
     @staticmethod
     def backward(ctx, g_l):
         (params,) = ctx.saved_tensors
-        dparams = gnn_backward(ctx.sys, params, ctx.h, ctx.n_mp, ctx.ws, g_l.float().contiguous())
-        return dparams, None, None, None, None, None
+        dparams = gnn_backward(ctx.sys, params, ctx.h, ctx.n_mp, ctx.ws, g_l.float().contiguous(),
+                               diag_mode=ctx.diag_mode)
+        return dparams, None, None, None, None, None, None
 
 
 class LltLoss(torch.autograd.Function):

@@ -1,0 +1,159 @@
+"""Train the preconditioner GNN on the GPU with the library's own forward,
+hand-written backward, data loss and Adam kernels (paper: loss_Ab, Adam at
+lr 1e-3; training-setup appendix).
+
+Data: implicit-Euler heat steps on an m^3 grid (7-point, k = exp(GRF sigma=1,
+ell=0.1), dt = 1e-3, b = u0 a smooth GRF), k seeds 0..nsys-1 and u0 seeds
+10000+seed; the solution x of each system (the third member of the paper's
+(A, x, b) training tuples) comes from SciPy's CG to a 1e-12 relative
+residual.  Every system shares one sparsity pattern, so a batch of B
+systems is one block-diagonal pattern analysed once; each step swaps in the
+batch's values.  Held-out check: PCG iterations to 1e-6 with the predicted
+L on a 64^3 system with unseen seeds, every eval_every steps; the weights
+with the fewest held-out iterations are kept (early stop on held-out).
+
+    python -m paper_2305_16432_amd.train --out paper_2305_16432_amd/weights/heat3d_h32_mp3.npz
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import multiprocessing as mp
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def _make(args):
+    m, seed = args
+    import scipy.sparse.linalg as spla
+    from threadpoolctl import threadpool_limits
+
+    import pdegen as g
+    A, b = g.heat_system_3d(m, 1e-3, k_seed=seed, u0_seed=10000 + seed)
+    with threadpool_limits(1):  # one BLAS thread per worker process
+        x, info = spla.cg(A.to_scipy(), b, rtol=1e-12, maxiter=20 * A.n)
+    assert info == 0
+    return A.val.astype(np.float64), b, x
+
+
+def make_dataset(m: int, nsys: int, workers: int):
+    import pdegen as g
+    A0, _ = g.heat_system_3d(m, 1e-3, k_seed=0, u0_seed=10000)
+    out = []
+    # fork before any GPU context exists (the workers re-import nothing), with
+    # the BLAS thread pools limited so workers do not oversubscribe the cores
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(1), mp.get_context("fork").Pool(workers) as pool:
+        for i, o in enumerate(pool.imap(_make, [(m, s) for s in range(nsys)], chunksize=2)):
+            out.append(o)
+            if (i + 1) % 50 == 0:
+                print(f"[train] generated {i + 1}/{nsys} systems", flush=True)
+    vals = np.stack([o[0] for o in out])
+    bs = np.stack([o[1] for o in out])
+    xs = np.stack([o[2] for o in out])
+    return A0, vals, bs, xs
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--m", type=int, default=32)
+    ap.add_argument("--nsys", type=int, default=1000)
+    ap.add_argument("--batch", type=int, default=8)
+    ap.add_argument("--steps", type=int, default=3000)
+    ap.add_argument("--h", type=int, default=32)
+    ap.add_argument("--n-mp", type=int, default=3)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--diag-mode", type=int, default=1)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--eval-every", type=int, default=100)
+    ap.add_argument("--eval-m", type=int, default=64)
+    ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
+    ap.add_argument("--out", required=True)
+    args = ap.parse_args()
+    print(f"[train] generating {args.nsys} systems of {args.m}^3 on {args.workers} workers", flush=True)
+    t0 = time.time()
+    A0, vals, bs, xs = make_dataset(args.m, args.nsys, args.workers)
+    print(f"[train] dataset {args.nsys} x n={A0.n} in {time.time() - t0:.1f}s", flush=True)
+
+    import torch
+
+    import pdegen as g
+    from paper_2305_16432_amd import lpcg
+    print("[train] torch imported", flush=True)
+    B, srp = g.block_diag_csr([A0] * args.batch)
+    S = lpcg.analyze(torch.as_tensor(B.rowptr).cuda(), torch.as_tensor(B.colind).cuda(),
+                     torch.as_tensor(B.val).cuda(), srp)
+    dv = torch.as_tensor(vals).cuda()
+    db = torch.as_tensor(bs).cuda()
+    dx = torch.as_tensor(xs).cuda()
+    h, n_mp = args.h, args.n_mp
+    dm = args.diag_mode
+    P0 = g.init_gnn_params(h, n_mp, seed=args.seed, gain=1.0)
+    if dm == 1:  # decoder output layer zero: L' = I, i.e. training starts at Jacobi
+        P0["dec.W1"][:] = 0.0
+        P0["dec.b1"][:] = 0.0
+    params = lpcg.pack_params(P0, h, n_mp).cuda()
+    m1, v1 = torch.zeros_like(params), torch.zeros_like(params)
+    ws = lpcg.gnn_workspace(S, h, n_mp, train=True)
+
+    # held-out evaluation system (unseen seeds, full size)
+    Ae, be = g.heat_system_3d(args.eval_m, 1e-3, k_seed=5000, u0_seed=6000)
+    Se = lpcg.analyze(torch.as_tensor(Ae.rowptr).cuda(), torch.as_tensor(Ae.colind).cuda(),
+                      torch.as_tensor(Ae.val).cuda())
+    bed = torch.as_tensor(be).cuda()
+    wse = lpcg.gnn_workspace(Se, h, n_mp)
+    nl = Se.info["nnz_l"]
+    le = torch.empty(nl, dtype=torch.float32, device="cuda")
+    ue = torch.empty(nl, dtype=torch.float32, device="cuda")
+    lic, uic, _ = lpcg.ic0(Se)
+    _, ric = lpcg.pcg_solve(Se, lpcg.PC_LLT, bed, l_val=lic, ut_val=uic, tol=1e-6, maxit=2000)
+    _, rj = lpcg.pcg_solve(Se, lpcg.PC_JACOBI, bed, tol=1e-6, maxit=2000)
+    print(f"[train] held-out 64^3: IC(0) {ric['iters']} its, Jacobi {rj['iters']} its", flush=True)
+
+    def evaluate():
+        lpcg.gnn_predict_L(Se, params, h, n_mp, bed, wse, le, ue, diag_mode=dm)
+        _, r = lpcg.pcg_solve(Se, lpcg.PC_LLT, bed, l_val=le, ut_val=ue, tol=1e-6, maxit=2000)
+        return r["iters"] if r["status"] == 0 else 10 ** 6
+
+    rng = np.random.default_rng(args.seed)
+    log = {"loss": [], "eval": [], "ic0_iters": ric["iters"], "jacobi_iters": rj["iters"]}
+    best = (evaluate(), 0, params.clone())
+    log["eval"].append((0, best[0]))
+    print(f"[train] step 0 held-out iters {best[0]}", flush=True)
+    nb = A0.nnz
+    t0 = time.time()
+    for step in range(1, args.steps + 1):
+        idx = torch.as_tensor(rng.choice(args.nsys, args.batch, replace=False)).cuda()
+        lpcg.update_values(S, dv[idx].reshape(-1).contiguous())
+        bb = db[idx].reshape(-1).contiguous()
+        xb = dx[idx].reshape(-1).contiguous()
+        L = lpcg.gnn_forward_train(S, params, h, n_mp, bb, ws, diag_mode=dm)
+        loss, dl = lpcg.llt_loss(S, L, xb, bb)
+        grad = lpcg.gnn_backward(S, params, h, n_mp, ws, dl, diag_mode=dm)
+        lpcg.adam_step(params, grad, m1, v1, args.lr, step)
+        if step % 10 == 0:
+            log["loss"].append((step, float(loss.sum()) / args.batch))
+        if step % args.eval_every == 0 or step == args.steps:
+            it = evaluate()
+            log["eval"].append((step, it))
+            if it < best[0]:
+                best = (it, step, params.clone())
+            print(f"[train] step {step} loss/system {log['loss'][-1][1]:.4g} held-out iters {it} "
+                  f"(best {best[0]} @ {best[1]}) {time.time() - t0:.1f}s", flush=True)
+    del nb
+    os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
+    np.savez(args.out, params=best[2].cpu().numpy(), h=h, n_mp=n_mp, diag_mode=dm, best_step=best[1],
+             best_iters=best[0], log=json.dumps(log), config=json.dumps(vars(args)))
+    print(f"[train] saved {args.out}: best held-out iters {best[0]} at step {best[1]} "
+          f"(IC(0) {ric['iters']}, Jacobi {rj['iters']})", flush=True)
+
+
+if __name__ == "__main__":
+    main()

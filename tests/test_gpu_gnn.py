@@ -21,26 +21,26 @@ pytestmark = pytest.mark.gpu
 REL_TOL = 2e-2
 
 
-def _gpu_L(S, A, b, P, h, n_mp):
+def _gpu_L(S, A, b, P, h, n_mp, diag_mode=0):
     params = lpcg.pack_params(P, h, n_mp).cuda()
     ws = lpcg.gnn_workspace(S, h, n_mp)
     nl = S.info["nnz_l"]
     lv = torch.empty(nl, dtype=torch.float32, device="cuda")
     ut = torch.empty(nl, dtype=torch.float32, device="cuda")
-    lpcg.gnn_predict_L(S, params, h, n_mp, cuda_f64(b), ws, lv, ut)
+    lpcg.gnn_predict_L(S, params, h, n_mp, cuda_f64(b), ws, lv, ut, diag_mode=diag_mode)
     torch.cuda.synchronize()
     return host(lv).astype(np.float64), host(ut).astype(np.float64)
 
 
-def _check(A, b, h, n_mp, seed, sys_rowptr=None):
+def _check(A, b, h, n_mp, seed, sys_rowptr=None, diag_mode=0):
     pat = O.Pattern(A)
     P = g.init_gnn_params(h, n_mp, seed=seed)
     S = gpu_system(A, sys_rowptr)
-    lg, ut = _gpu_L(S, A, b, P, h, n_mp)
+    lg, ut = _gpu_L(S, A, b, P, h, n_mp, diag_mode)
     if sys_rowptr is None:
-        ref, _ = ognn.forward(A, b, P, h, n_mp, rev=pat.rev)
+        ref, _ = ognn.forward(A, b, P, h, n_mp, rev=pat.rev, diag_mode=diag_mode)
     else:  # per-system normalisation: the oracle runs each block separately
-        ref = _blockwise_ref(A, b, P, h, n_mp, sys_rowptr, pat)
+        ref = _blockwise_ref(A, b, P, h, n_mp, sys_rowptr, pat, diag_mode)
     rel = np.linalg.norm(lg - ref) / np.linalg.norm(ref)
     row = np.repeat(np.arange(A.n), np.diff(pat.lrowptr))
     diag = pat.lcol == row
@@ -50,38 +50,41 @@ def _check(A, b, h, n_mp, seed, sys_rowptr=None):
     return rel
 
 
-def _blockwise_ref(A, b, P, h, n_mp, srp, pat):
+def _blockwise_ref(A, b, P, h, n_mp, srp, pat, diag_mode=0):
     out = np.zeros(pat.nnz_l)
     for s in range(len(srp) - 1):
         r0, r1 = srp[s], srp[s + 1]
         sub = g.canonical_csr(A.to_scipy()[r0:r1, r0:r1])
-        lsub, _ = ognn.forward(sub, b[r0:r1], P, h, n_mp)
+        lsub, _ = ognn.forward(sub, b[r0:r1], P, h, n_mp, diag_mode=diag_mode)
         out[pat.lrowptr[r0]:pat.lrowptr[r1]] = lsub
     return out
 
 
+@pytest.mark.parametrize("diag_mode", [0, 1])
 @pytest.mark.parametrize("h,n_mp", [(32, 3), (64, 2)])
 @pytest.mark.parametrize("name", ["poisson2d_32", "heat3d_13", "fem_40", "random_777", "tridiag_1000",
                                   "one"])
-def test_gnn_forward_parity(name, h, n_mp):
-    print(f"[gnn] {name} h={h} n_mp={n_mp}", flush=True)
+def test_gnn_forward_parity(name, h, n_mp, diag_mode):
+    print(f"[gnn] {name} h={h} n_mp={n_mp} diag_mode={diag_mode}", flush=True)
     A = matrices_small()[name]
     b = np.random.default_rng(1).standard_normal(A.n)
-    _check(A, b, h, n_mp, seed=5)
+    _check(A, b, h, n_mp, seed=5, diag_mode=diag_mode)
 
 
-def test_gnn_forward_batch_per_system_normalisation():
+@pytest.mark.parametrize("diag_mode", [0, 1])
+def test_gnn_forward_batch_per_system_normalisation(diag_mode):
     mats = [g.poisson_grid(9, 2), g.heat_system_3d(6, 1e-3, 1, 2)[0], g.fem_p1_delaunay(13, 0, 1)[0]]
     B, srp = g.block_diag_csr(mats)
     rng = np.random.default_rng(3)
     b = np.concatenate([rng.standard_normal(m.n) * (10.0 ** s) for s, m in enumerate(mats)])
-    _check(B, b, 32, 3, seed=7, sys_rowptr=srp)
+    _check(B, b, 32, 3, seed=7, sys_rowptr=srp, diag_mode=diag_mode)
 
 
-def test_gnn_forward_c3_full_size():
-    print("[gnn] heat3d_64 h=32 n_mp=3", flush=True)
+@pytest.mark.parametrize("diag_mode", [0, 1])
+def test_gnn_forward_c3_full_size(diag_mode):
+    print(f"[gnn] heat3d_64 h=32 n_mp=3 diag_mode={diag_mode}", flush=True)
     A, b = g.heat_system_3d(64, 1e-3, 1000, 2000)
-    rel = _check(A, b, 32, 3, seed=11)
+    rel = _check(A, b, 32, 3, seed=11, diag_mode=diag_mode)
     print(f"rel err {rel:.3e}")
 
 

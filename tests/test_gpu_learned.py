@@ -1,0 +1,82 @@
+"""What training buys: PCG iterations with the shipped trained network
+against the same network before training and against the classical
+preconditioners, on systems whose seeds were used neither for training
+(k seeds 0..999) nor for early stopping (k seed 5000)."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import pdegen as g
+from oracle import gnn as ognn
+from paper_2305_16432_amd import lpcg
+from tests.gpu_util import cuda_f64, gpu_system
+
+pytestmark = pytest.mark.gpu
+
+WEIGHTS = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                       "paper_2305_16432_amd", "weights", "heat3d_h32_mp3.npz")
+
+
+def _load():
+    W = np.load(WEIGHTS)
+    return (torch.as_tensor(W["params"].astype(np.float32)).cuda(), int(W["h"]), int(W["n_mp"]),
+            int(W["diag_mode"]))
+
+
+def _iters_learned(S, params, h, n_mp, dm, bd):
+    ws = lpcg.gnn_workspace(S, h, n_mp)
+    nl = S.info["nnz_l"]
+    lv = torch.empty(nl, dtype=torch.float32, device="cuda")
+    ut = torch.empty(nl, dtype=torch.float32, device="cuda")
+    lpcg.gnn_predict_L(S, params, h, n_mp, bd, ws, lv, ut, diag_mode=dm)
+    _, r = lpcg.pcg_solve(S, lpcg.PC_LLT, bd, l_val=lv, ut_val=ut, tol=1e-6, maxit=4000, max_restarts=2)
+    assert r["status"] == 0 and r["relres_true"] <= 1e-6, r
+    return r["iters"]
+
+
+@pytest.mark.parametrize("m,k_seed,u_seed", [(64, 7001, 8001), (64, 7002, 8002), (32, 7003, 8003)])
+def test_trained_network_beats_untrained_and_jacobi(m, k_seed, u_seed):
+    params, h, n_mp, dm = _load()
+    A, b = g.heat_system_3d(m, 1e-3, k_seed, u_seed)
+    S = gpu_system(A)
+    bd = cuda_f64(b)
+    it_trained = _iters_learned(S, params, h, n_mp, dm, bd)
+    # the same architecture before training: decoder output layer zero, i.e.
+    # L' = I and P = diag(A) (the initialisation the trainer starts from)
+    P0 = g.init_gnn_params(h, n_mp, seed=0)
+    P0["dec.W1"][:] = 0.0
+    P0["dec.b1"][:] = 0.0
+    it_untrained = _iters_learned(S, lpcg.pack_params(P0, h, n_mp).cuda(), h, n_mp, dm, bd)
+    l, ut, _ = lpcg.ic0(S)
+    _, ric = lpcg.pcg_solve(S, lpcg.PC_LLT, bd, l_val=l, ut_val=ut, tol=1e-6, max_restarts=2)
+    _, rj = lpcg.pcg_solve(S, lpcg.PC_JACOBI, bd, tol=1e-6, max_restarts=2)
+    print(f"[learned] {m}^3 seeds ({k_seed},{u_seed}): trained {it_trained}, untrained {it_untrained}, "
+          f"IC(0) {ric['iters']}, Jacobi {rj['iters']}", flush=True)
+    assert abs(it_untrained - rj["iters"]) <= 2  # untrained = Jacobi
+    assert it_trained <= 0.5 * it_untrained
+    assert it_trained <= 1.35 * ric["iters"]
+
+
+def test_trained_network_matches_oracle_on_heldout():
+    """The shipped network's L on a held-out 16^3 system: GPU vs FP64 oracle,
+    and the oracle's PCG with the oracle's L takes the same iterations."""
+    params, h, n_mp, dm = _load()
+    A, b = g.heat_system_3d(16, 1e-3, 7010, 8010)
+    pat = O.Pattern(A)
+    S = gpu_system(A)
+    bd = cuda_f64(b)
+    ws = lpcg.gnn_workspace(S, h, n_mp)
+    lv = torch.empty(pat.nnz_l, dtype=torch.float32, device="cuda")
+    ut = torch.empty_like(lv)
+    lpcg.gnn_predict_L(S, params, h, n_mp, bd, ws, lv, ut, diag_mode=dm)
+    P = {k: np.asarray(v, np.float64) for k, v in lpcg.unpack_params(params, h, n_mp).items()}
+    lref, _ = ognn.forward(A, b, P, h, n_mp, rev=pat.rev, diag_mode=dm)
+    lg = lv.cpu().numpy().astype(np.float64)
+    assert np.linalg.norm(lg - lref) / np.linalg.norm(lref) <= 2e-2
+    _, r = lpcg.pcg_solve(S, lpcg.PC_LLT, bd, l_val=lv, ut_val=ut, tol=1e-6, max_restarts=2)
+    ro = O.pcg(A, b, O.PC_LLT, pat, lref, tol=1e-6)
+    assert ro["status"] == O.OK and r["status"] == 0
+    assert abs(r["iters"] - ro["iters"]) <= max(2, 0.1 * ro["iters"]), (r["iters"], ro["iters"])

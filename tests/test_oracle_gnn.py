@@ -206,3 +206,43 @@ def test_adam_first_step_is_signed_lr_and_minimises_quadratic():
     for t in range(1, 3001):
         p, m, v = gnn.adam(p, {"w": c * p["w"]}, m, v, step=t, lr=1e-2)
     assert np.abs(p["w"]).max() < 0.05 * start
+
+
+def test_diag_mode1_zero_weights_closed_form_and_jacobi_start():
+    """diag_mode 1 (L' D L'^T with D = diag(A)) and all-zero weights except a
+    zero decoder bias: L' = I, so P = diag(A) exactly (Jacobi); with decoder
+    bias c: L_ij = sqrt(A_jj) c below the diagonal, L_ii = sqrt(A_ii)."""
+    A, b = g.heat_system_3d(5, 1e-3, k_seed=3, u0_seed=4)
+    pat = O.Pattern(A)
+    row = np.repeat(np.arange(A.n), np.diff(pat.lrowptr))
+    diag = pat.lcol == row
+    P = g.init_gnn_params(8, 2, seed=1, zero=True)
+    c = float(P["dec.b1"][0])
+    lval, _ = gnn.forward(A, b, P, 8, 2, diag_mode=1)
+    ad = O.diag(A)
+    np.testing.assert_allclose(lval[diag], np.sqrt(ad), rtol=1e-15)
+    np.testing.assert_allclose(lval[~diag], np.sqrt(ad[pat.lcol[~diag]]) * c, rtol=1e-15)
+    P["dec.b1"][:] = 0.0
+    lval, _ = gnn.forward(A, b, P, 8, 2, diag_mode=1)
+    x = np.random.default_rng(0).standard_normal(A.n)
+    r1 = O.pcg(A, x, O.PC_LLT, pat, lval, tol=1e-10, maxit=5)
+    r2 = O.pcg(A, x, O.PC_JACOBI, tol=1e-10, maxit=5)
+    np.testing.assert_allclose(r1["x"], r2["x"], rtol=1e-12, atol=1e-14)
+
+
+def test_diag_mode1_backward_finite_differences_and_torch():
+    A = g.fem_p1_delaunay(8, 3, 4)[0]
+    b = np.random.default_rng(11).standard_normal(A.n)
+    h, n_mp = 4, 2
+    P = g.init_gnn_params(h, n_mp, seed=12, gain=1.5)
+    lval, cache = gnn.forward(A, b, P, h, n_mp, keep=True, diag_mode=1)
+    rng = np.random.default_rng(3)
+    gl = rng.standard_normal(lval.shape[0])
+    G = gnn.backward(P, cache, gl)
+    V = {k: rng.standard_normal(v.shape) for k, v in P.items()}
+    eps = 1e-7
+    fp = gl @ gnn.forward(A, b, {k: P[k] + eps * V[k] for k in P}, h, n_mp, diag_mode=1)[0]
+    fm = gl @ gnn.forward(A, b, {k: P[k] - eps * V[k] for k in P}, h, n_mp, diag_mode=1)[0]
+    fd = (fp - fm) / (2 * eps)
+    an = sum(np.sum(G[k] * V[k]) for k in P)
+    assert abs(fd - an) <= 1e-5 * max(1.0, abs(fd)), (fd, an)
