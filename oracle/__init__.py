@@ -8,7 +8,8 @@ which holds no arithmetic of the method.
 
 Contents (each follows the cited part of the paper):
   * C routines (csrc/lpcg_oracle.c) wrapped here with ctypes: lower pattern,
-    transpose, reverse-edge map, forward/backward levels and level sets, SpMV,
+    transpose, reverse-edge map, forward/backward levels and level sets,
+    greedy multicolour ordering and the symmetric permutation, SpMV,
     forward/backward substitution, IC(0), PCG (Appendix algorithm), data loss
     and its gradient (equation loss_Ab).
   * oracle.gnn: the encoder-processor-decoder GNN (technical-details appendix)
@@ -110,6 +111,44 @@ def level_sets(level, nlev):
     rows = np.zeros(n, np.int32)
     lib().orc_level_sets(C.c_int(n), _p(level), C.c_int(nlev), _p(ptr), _p(rows))
     return ptr, rows
+
+
+def greedy_colors(n, lrowptr, lcol):
+    """(colour per row, number of colours): first-fit colouring in row order
+    on the lower-triangle graph."""
+    lrowptr, lcol = _i32(lrowptr), _i32(lcol)
+    color = np.zeros(n, np.int32)
+    nc = lib().orc_greedy_colors(C.c_int(n), _p(lrowptr), _p(lcol), _p(color))
+    return color, int(nc)
+
+
+def color_order(A, sys_rowptr=None):
+    """Multicolour ordering of A: perm[new] = old row, sorting rows by
+    (system of the batch, greedy colour) and keeping ascending row order within
+    a colour.  Returns (perm, colour per original row, number of colours)."""
+    lrowptr, lcol, _ = lower_pattern(A.n, A.rowptr, A.colind)
+    color, nc = greedy_colors(A.n, lrowptr, lcol)
+    srp = np.array([0, A.n]) if sys_rowptr is None else np.asarray(sys_rowptr)
+    row_sys = np.repeat(np.arange(len(srp) - 1), np.diff(srp))
+    perm = np.lexsort((np.arange(A.n), color, row_sys)).astype(np.int32)
+    return perm, color, nc
+
+
+def permute_sym(A, perm):
+    """P A P^T as a CSR with ascending columns: entry (r, c) of the result is
+    A[perm[r], perm[c]].  Every stored entry of A (explicit zeros included)
+    is kept."""
+    from pdegen.csr import CSR
+    perm = np.asarray(perm, np.int64)
+    iperm = np.empty_like(perm)
+    iperm[perm] = np.arange(A.n)
+    erow = np.repeat(np.arange(A.n), np.diff(A.rowptr))
+    r, c = iperm[erow], iperm[np.asarray(A.colind, np.int64)]
+    order = np.lexsort((c, r))
+    rowptr = np.zeros(A.n + 1, np.int64)
+    np.add.at(rowptr, r + 1, 1)
+    return CSR(A.n, np.cumsum(rowptr).astype(np.int32), c[order].astype(np.int32),
+               np.asarray(A.val, np.float64)[order])
 
 
 class Pattern:

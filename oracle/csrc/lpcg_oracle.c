@@ -126,6 +126,29 @@ int orc_levels_upper(int n, const int *urowptr, const int *ucol, int *level)
     return nlev;
 }
 
+/* Greedy (first-fit) colouring visiting rows in ascending order: colour(i)
+ * is the smallest non-negative integer that no neighbour j < i (a strictly
+ * lower entry of row i) already has.  Adjacent rows get different colours, so
+ * in an ordering by colour the rows of one colour depend only on rows of
+ * smaller colours.  Returns the number of colours. */
+int orc_greedy_colors(int n, const int *lrowptr, const int *lcol, int *color)
+{
+    int ncol = 0;
+    char *taken = (char *)calloc((size_t)n + 1, 1);
+    for (int i = 0; i < n; ++i) {
+        for (int p = lrowptr[i]; p < lrowptr[i + 1]; ++p)
+            if (lcol[p] < i) taken[color[lcol[p]]] = 1;
+        int c = 0;
+        while (taken[c]) ++c;
+        color[i] = c;
+        if (c + 1 > ncol) ncol = c + 1;
+        for (int p = lrowptr[i]; p < lrowptr[i + 1]; ++p)
+            if (lcol[p] < i) taken[color[lcol[p]]] = 0;
+    }
+    free(taken);
+    return ncol;
+}
+
 /* Level sets: rows grouped by level, levels ascending, rows ascending inside a
  * level.  lev_ptr[nlev+1], lev_rows[n]. */
 void orc_level_sets(int n, const int *level, int nlev, int *lev_ptr, int *lev_rows)
