@@ -72,7 +72,29 @@ typedef struct {
     int32_t nlev_fwd, nlev_bwd;  /* level counts of the L and L^T solves */
     int32_t max_width_fwd, max_width_bwd; /* largest level */
     int32_t nsys;                /* systems in the batch (1 if not batched) */
+    int32_t ordering;            /* LPCG_ORDER_* the system was analysed with */
+    int32_t ncolors;             /* colours of LPCG_ORDER_COLOR (0 otherwise) */
 } lpcg_info;
+
+/* Row orderings.  NATURAL keeps A's numbering (the factor lives on tril(A)).
+ * COLOR renumbers the rows before everything else: first-fit colouring in
+ * row order on the lower-triangle graph (colour(i) = smallest colour no
+ * neighbour j < i has), then rows sorted by (system of the batch, colour),
+ * ascending inside a colour.  The library then works on P A P^T: the factor
+ * lives on tril(P A P^T) and each triangular solve has at most as many
+ * levels as there are colours (2, red-black, on grid graphs).  This is a
+ * solver-side choice outside the paper; it changes the preconditioner that a
+ * given factor pattern can express, not the system solved.
+ *
+ * Numbering contract for a COLOR system: vectors indexed by rows of the
+ * problem (b, x, the x/y of lpcg_spmv, the rhs/y of lpcg_sptrsv, x and b of
+ * lpcg_llt_loss) are in the caller's ORIGINAL numbering and are permuted
+ * inside the library; preconditioner data (l_val, ut_val, dinv, every array
+ * of lpcg_export_pattern) is in the INTERNAL numbering; lpcg_export_perm
+ * gives perm[internal row] = original row.  The timing aids work in the
+ * internal numbering. */
+#define LPCG_ORDER_NATURAL 0
+#define LPCG_ORDER_COLOR   1
 
 /* Pattern analysis (graph/matrix duality of the Method section; levels of
  * the substitution DAG): copies A, builds tril(A) (lrowptr/lcol), U = L^T
@@ -81,14 +103,20 @@ typedef struct {
  * levels (longest-path depth) and the level sets (rows ascending inside a
  * level).  A->val must be set.  sys_rowptr (HOST, nsys+1 entries, first 0, last
  * n) splits a block-diagonal batch into independent systems; NULL or nsys <= 1
- * means one system.  Synchronous.  *out is owned by the caller until
- * lpcg_destroy.  Errors: EINVAL (n <= 0, unsorted/duplicate columns, missing
- * diagonal, unsymmetric pattern, a row crossing a system boundary), ENOMEM,
- * EHIP. */
+ * means one system.  ordering: LPCG_ORDER_NATURAL or LPCG_ORDER_COLOR (rows
+ * of one system stay inside that system's row range).  Synchronous.  *out is
+ * owned by the caller until lpcg_destroy.  Errors: EINVAL (n <= 0,
+ * unsorted/duplicate columns, missing diagonal, unsymmetric pattern, a row
+ * crossing a system boundary, unknown ordering), ENOMEM, EHIP. */
 int lpcg_analyze(const lpcg_csr *A, const int32_t *sys_rowptr, int32_t nsys,
-                 lpcg_system **out, hipStream_t stream);
+                 int32_t ordering, lpcg_system **out, hipStream_t stream);
 
-/* Replace A's values (same pattern), FP64 device array of length nnz. */
+/* perm[internal row] = original row, device int32 [n] (the identity for the
+ * natural ordering). */
+int lpcg_export_perm(const lpcg_system *sys, int32_t *perm, hipStream_t stream);
+
+/* Replace A's values (same pattern), FP64 device array of length nnz, in the
+ * caller's CSR entry order. */
 int lpcg_update_values(lpcg_system *sys, const double *val, hipStream_t stream);
 
 /* Sizes and level counts (host struct). */

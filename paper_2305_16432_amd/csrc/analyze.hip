@@ -11,6 +11,14 @@
 //   4. forward / backward levels, level(i) = 1 + max level of the rows i
 //      depends on (0 if none), computed by a dependency-driven kernel;
 //   5. level sets: rows sorted by (level, row) with a stable radix sort.
+// Optional multicolour ordering (LPCG_ORDER_COLOR): first-fit colours in row
+// order on the lower-triangle graph (a dependency-driven kernel over the
+// forward levels of the natural ordering), rows stably sorted by (system,
+// colour), and the analysis above repeated on P A P^T.  Rows of one colour
+// are mutually independent, so the triangular solves of the reordered system
+// have at most as many levels as there are colours (2 on a grid graph:
+// red-black).  This reordering is a solver-side choice, not part of the
+// method; the preconditioner it gives differs from the natural-order one.
 #include <hipcub/hipcub.hpp>
 
 #include <cstdarg>
@@ -152,9 +160,117 @@ __global__ void k_levels(int n, const int *__restrict__ rp, const int *__restric
     }
 }
 
+// First-fit colour of every row (rows handed out in forward level order,
+// so a row only waits on rows handed out earlier): colour(i) = smallest
+// c >= 0 that no strictly-lower neighbour j of row i has.  color[] is preset
+// to -1; a published colour is its own ready flag.
+__global__ void k_colors(int n, const int *__restrict__ order, const int *__restrict__ lrp,
+                         const int *__restrict__ lci, int *color, int *ticket) {
+    const int lane = lane_id();
+    for (;;) {
+        const int chunk = wave_ticket(ticket);
+        if ((long)chunk * kWave >= n) break;
+        const int pos = chunk * kWave + lane;
+        int row = -1, k0 = 0, k = 0, kend = 0;
+        if (pos < n) {
+            row = order[pos];
+            k0 = k = lrp[row];
+            kend = lrp[row + 1] - 1;  // diagonal last
+        }
+        bool pending = row >= 0;
+        while (__ballot(pending) != 0) {
+            if (pending) {
+                while (k < kend && ld_agent_i(&color[lci[k]]) >= 0) ++k;
+                if (k == kend) {
+                    // every neighbour's colour is final: take the smallest free one
+                    uint64_t taken = 0;
+                    bool big = false;
+                    for (int q = k0; q < kend; ++q) {
+                        const int c = ld_agent_i(&color[lci[q]]);
+                        if (c < 64) taken |= 1ull << c;
+                        else big = true;
+                    }
+                    int c = taken == ~0ull ? 64 : __builtin_ctzll(~taken);
+                    if (big || c == 64) {  // rare: colours beyond 63 among the neighbours
+                        for (bool hit = true; hit;) {
+                            hit = false;
+                            for (int q = k0; q < kend && !hit; ++q) hit = ld_agent_i(&color[lci[q]]) == c;
+                            if (hit) ++c;
+                        }
+                    }
+                    st_agent_i(&color[row], c);
+                    pending = false;
+                }
+            }
+            if (pending) __builtin_amdgcn_s_sleep(1);
+        }
+    }
+}
+
+__global__ void k_color_keys(int n, const int *__restrict__ row_sys, const int *__restrict__ color,
+                             int ncolors, int *__restrict__ keys, int *__restrict__ iota) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    keys[i] = row_sys[i] * ncolors + color[i];
+    iota[i] = i;
+}
+
+__global__ void k_perm_rows(int n, const int *__restrict__ perm, const int *__restrict__ rowptr,
+                            int *__restrict__ iperm, int *__restrict__ len) {
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const int o = perm[r];
+    iperm[o] = r;
+    len[r] = rowptr[o + 1] - rowptr[o];
+}
+
+// Row r of P A P^T: the entries of original row perm[r], columns renumbered
+// through iperm and sorted ascending (insertion sort; rows are short).
+// psrc[k'] = original position of internal entry k'.
+__global__ void k_perm_fill(int n, const int *__restrict__ perm, const int *__restrict__ iperm,
+                            const int *__restrict__ rowptr, const int *__restrict__ col,
+                            const int *__restrict__ nrp, int *__restrict__ ncol, int *__restrict__ psrc) {
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const int o = perm[r], a = rowptr[o], len = rowptr[o + 1] - a, base = nrp[r];
+    for (int t = 0; t < len; ++t) {
+        const int c = iperm[col[a + t]], src = a + t;
+        int q = t;
+        while (q > 0 && ncol[base + q - 1] > c) {
+            ncol[base + q] = ncol[base + q - 1];
+            psrc[base + q] = psrc[base + q - 1];
+            --q;
+        }
+        ncol[base + q] = c;
+        psrc[base + q] = src;
+    }
+}
+
+__global__ void k_gather_vals(int nnz, const int *__restrict__ psrc, const double *__restrict__ v,
+                              double *__restrict__ out) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < nnz) out[k] = v[psrc[k]];
+}
+
+template <typename T>
+__global__ void k_vec_gather(int n, const int *__restrict__ perm, const T *__restrict__ src, T *__restrict__ dst) {
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < n) dst[r] = src[perm[r]];
+}
+
+template <typename T>
+__global__ void k_vec_scatter(int n, const int *__restrict__ perm, const T *__restrict__ src, T *__restrict__ dst) {
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < n) dst[perm[r]] = src[r];
+}
+
 __global__ void k_iota_fill(int n, int *iota, int *lev_f, int *lev_b) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) { iota[i] = i; lev_f[i] = -1; lev_b[i] = -1; }
+    if (i < n) {
+        iota[i] = i;
+        if (lev_f) lev_f[i] = -1;
+        if (lev_b) lev_b[i] = -1;
+    }
 }
 
 // lev_ptr from keys sorted ascending: levels are contiguous 0..nlev-1 (every
@@ -172,16 +288,18 @@ __global__ void k_row_sys(int nsys, const int *__restrict__ sys_rowptr, int *__r
     for (int i = sys_rowptr[s] + threadIdx.x; i < sys_rowptr[s + 1]; i += blockDim.x) row_sys[i] = s;
 }
 
-__global__ void k_values(int nnz, int n, const double *__restrict__ v64, const int *__restrict__ dpos,
-                         double *__restrict__ val64, float *__restrict__ val32,
-                         double *__restrict__ diag64) {
+// Values in internal order (psrc: gather from the caller's entry order, or
+// null for the natural ordering); diagonal copy for Jacobi and the GNN.
+__global__ void k_values(int nnz, int n, const double *__restrict__ v64, const int *__restrict__ psrc,
+                         const int *__restrict__ dpos, double *__restrict__ val64,
+                         float *__restrict__ val32, double *__restrict__ diag64) {
     int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k < nnz) {
-        double v = v64[k];
+        double v = v64[psrc ? psrc[k] : k];
         val64[k] = v;
         val32[k] = (float)v;
     }
-    if (k < n) diag64[k] = v64[dpos[k]];
+    if (k < n) diag64[k] = v64[psrc ? psrc[dpos[k]] : dpos[k]];
 }
 
 int nblk(long n, int t) { return (int)((n + t - 1) / t); }
@@ -374,12 +492,99 @@ int analyze_impl(const lpcg_csr *A, const int32_t *h_sys, int32_t nsys, lpcg_sys
     const double mean = (double)nnz / n;
     s->spmv_group = mean <= 4 ? 4 : mean <= 8 ? 8 : mean <= 16 ? 16 : mean <= 32 ? 32 : 64;
     s->spmv_blocks = std::max(1, std::min(kMaxSpmvBlocks, nblk(n, kVecThreads / s->spmv_group)));
-    k_values<<<nblk(std::max(n, nnz), 256), 256, 0, st>>>(nnz, n, A->val, s->dpos, s->val64, s->val32,
-                                                           s->diag64);
+    k_values<<<nblk(std::max(n, nnz), 256), 256, 0, st>>>(nnz, n, A->val, nullptr, s->dpos, s->val64,
+                                                           s->val32, s->diag64);
     LPCG_LAUNCH_CHECK();
     LPCG_HIP(hipStreamSynchronize(st));
 #undef ALLOC
     return LPCG_OK;
+}
+
+// Multicolour analysis: natural analysis of A (validation, lower pattern,
+// forward levels) in a scratch system, colours, the permutation, P A P^T,
+// then the full analysis of P A P^T into s.
+int analyze_color(const lpcg_csr *A, const int32_t *h_sys, int32_t nsys, lpcg_system *s, hipStream_t st) {
+    const int n = A->n, nnz = A->nnz;
+    lpcg_system *s0 = new (std::nothrow) lpcg_system();
+    if (!s0) return LPCG_ENOMEM;
+    std::vector<void *> tmp;
+    auto cleanup = [&](int rc) {
+        hipStreamSynchronize(st);
+        for (void *p : tmp) hipFree(p);
+        lpcg_destroy(s0);
+        return rc;
+    };
+    auto talloc = [&](void **p, size_t bytes) -> int {
+        hipError_t e = hipMalloc(p, bytes ? bytes : 4);
+        if (e != hipSuccess) {
+            set_error("hipMalloc of %zu bytes failed: %s", bytes, hipGetErrorString(e));
+            return LPCG_ENOMEM;
+        }
+        tmp.push_back(*p);
+        return LPCG_OK;
+    };
+    int rc = analyze_impl(A, h_sys, nsys, s0, st);
+    if (rc) return cleanup(rc);
+    int *color = nullptr, *ticket = nullptr, *keys = nullptr, *skeys = nullptr, *iota = nullptr, *d_max = nullptr;
+    int *perm = nullptr, *iperm = nullptr, *len = nullptr, *nrp = nullptr, *ncol = nullptr, *psrc = nullptr;
+    double *nval = nullptr;
+    if ((rc = talloc((void **)&color, sizeof(int) * n)) || (rc = talloc((void **)&ticket, sizeof(int))) ||
+        (rc = talloc((void **)&keys, sizeof(int) * n)) || (rc = talloc((void **)&skeys, sizeof(int) * n)) ||
+        (rc = talloc((void **)&iota, sizeof(int) * n)) || (rc = talloc((void **)&d_max, sizeof(int))) ||
+        (rc = talloc((void **)&len, sizeof(int) * (n + 1))) || (rc = talloc((void **)&nrp, sizeof(int) * (n + 1))) ||
+        (rc = talloc((void **)&ncol, sizeof(int) * (size_t)nnz)) ||
+        (rc = talloc((void **)&nval, sizeof(double) * (size_t)nnz)))
+        return cleanup(rc);
+    if (hipMemsetAsync(color, 0xff, sizeof(int) * n, st) != hipSuccess ||
+        hipMemsetAsync(ticket, 0, sizeof(int), st) != hipSuccess)
+        return cleanup(hip_fail(hipGetLastError(), "hipMemsetAsync", __FILE__, __LINE__));
+    const int waves = std::min(nblk(n, kWave), 8192);
+    k_colors<<<nblk(waves, 4), 256, 0, st>>>(n, s0->flev_rows, s0->lrowptr, s0->lcol, color, ticket);
+    if (hipGetLastError() != hipSuccess) return cleanup(hip_fail(hipErrorLaunchFailure, "k_colors", __FILE__, __LINE__));
+    size_t tb = 0;
+    void *cub = nullptr;
+    hipcub::DeviceReduce::Max(nullptr, tb, color, d_max, n, st);
+    if ((rc = talloc(&cub, tb))) return cleanup(rc);
+    hipcub::DeviceReduce::Max(cub, tb, color, d_max, n, st);
+    int hmax = 0;
+    hipMemcpyAsync(&hmax, d_max, sizeof(int), hipMemcpyDeviceToHost, st);
+    if (hipStreamSynchronize(st) != hipSuccess)
+        return cleanup(hip_fail(hipGetLastError(), "colouring", __FILE__, __LINE__));
+    const int ncolors = hmax + 1;
+    if ((long)nsys * ncolors >= (1L << 30)) {
+        set_error("lpcg_analyze: %d systems x %d colours overflow the sort key", nsys, ncolors);
+        return cleanup(LPCG_EINVAL);
+    }
+    int bits = 1;
+    while ((1L << bits) < (long)nsys * ncolors) ++bits;
+    k_color_keys<<<nblk(n, 256), 256, 0, st>>>(n, s0->row_sys, color, ncolors, keys, iota);
+    // perm: rows sorted by (system, colour), stable (ascending rows within a key)
+    if ((rc = dalloc(s, &s->perm, n)) || (rc = dalloc(s, &s->iperm, n))) return cleanup(rc);
+    perm = s->perm;
+    iperm = s->iperm;
+    tb = 0;
+    hipcub::DeviceRadixSort::SortPairs(nullptr, tb, keys, skeys, iota, perm, n, 0, bits, st);
+    void *cub2 = nullptr;
+    if ((rc = talloc(&cub2, tb))) return cleanup(rc);
+    hipcub::DeviceRadixSort::SortPairs(cub2, tb, keys, skeys, iota, perm, n, 0, bits, st);
+    hipMemsetAsync(len + n, 0, sizeof(int), st);
+    k_perm_rows<<<nblk(n, 256), 256, 0, st>>>(n, perm, s0->rowptr, iperm, len);
+    tb = 0;
+    hipcub::DeviceScan::ExclusiveSum(nullptr, tb, len, nrp, n + 1, st);
+    void *cub3 = nullptr;
+    if ((rc = talloc(&cub3, tb))) return cleanup(rc);
+    hipcub::DeviceScan::ExclusiveSum(cub3, tb, len, nrp, n + 1, st);
+    if ((rc = dalloc(s, &s->psrc, nnz))) return cleanup(rc);
+    psrc = s->psrc;
+    k_perm_fill<<<nblk(n, 256), 256, 0, st>>>(n, perm, iperm, s0->rowptr, s0->colind, nrp, ncol, psrc);
+    k_gather_vals<<<nblk(nnz, 256), 256, 0, st>>>(nnz, psrc, A->val, nval);
+    if (hipGetLastError() != hipSuccess) return cleanup(hip_fail(hipErrorLaunchFailure, "permute", __FILE__, __LINE__));
+    lpcg_csr B{n, nnz, nrp, ncol, nval};
+    if ((rc = analyze_impl(&B, h_sys, nsys, s, st))) return cleanup(rc);
+    if ((rc = dalloc(s, &s->bperm, n)) || (rc = dalloc(s, &s->xperm, n))) return cleanup(rc);
+    s->ordering = LPCG_ORDER_COLOR;
+    s->ncolors = ncolors;
+    return cleanup(LPCG_OK);
 }
 
 }  // namespace
@@ -390,7 +595,33 @@ using namespace lpcg;
 extern "C" const char *lpcg_last_error(void) { return g_err; }
 extern "C" const char *lpcg_version(void) { return "lpcg 0.1 (gfx950)"; }
 
-extern "C" int lpcg_analyze(const lpcg_csr *A, const int32_t *sys_rowptr, int32_t nsys,
+namespace lpcg {
+template <typename T>
+static int permute_vec(const lpcg_system *s, const T *src, T *dst, bool to_int, hipStream_t st) {
+    if (!s->perm) {
+        if (src != dst) LPCG_HIP(hipMemcpyAsync(dst, src, sizeof(T) * s->n, hipMemcpyDeviceToDevice, st));
+        return LPCG_OK;
+    }
+    if (to_int) k_vec_gather<T><<<nblk(s->n, 256), 256, 0, st>>>(s->n, s->perm, src, dst);
+    else k_vec_scatter<T><<<nblk(s->n, 256), 256, 0, st>>>(s->n, s->perm, src, dst);
+    LPCG_LAUNCH_CHECK();
+    return LPCG_OK;
+}
+int to_internal_f64(const lpcg_system *s, const double *src, double *dst, hipStream_t st) {
+    return permute_vec(s, src, dst, true, st);
+}
+int from_internal_f64(const lpcg_system *s, const double *src, double *dst, hipStream_t st) {
+    return permute_vec(s, src, dst, false, st);
+}
+int to_internal_f32(const lpcg_system *s, const float *src, float *dst, hipStream_t st) {
+    return permute_vec(s, src, dst, true, st);
+}
+int from_internal_f32(const lpcg_system *s, const float *src, float *dst, hipStream_t st) {
+    return permute_vec(s, src, dst, false, st);
+}
+}  // namespace lpcg
+
+extern "C" int lpcg_analyze(const lpcg_csr *A, const int32_t *sys_rowptr, int32_t nsys, int32_t ordering,
                             lpcg_system **out, hipStream_t stream) {
     set_error("");
     if (!A || !out || A->n <= 0 || A->nnz < A->n || !A->rowptr || !A->colind || !A->val) {
@@ -413,9 +644,14 @@ extern "C" int lpcg_analyze(const lpcg_csr *A, const int32_t *sys_rowptr, int32_
     } else {
         nsys = 1;
     }
+    if (ordering != LPCG_ORDER_NATURAL && ordering != LPCG_ORDER_COLOR) {
+        set_error("lpcg_analyze: unknown ordering %d", ordering);
+        return LPCG_EINVAL;
+    }
     lpcg_system *s = new (std::nothrow) lpcg_system();
     if (!s) return LPCG_ENOMEM;
-    int rc = analyze_impl(A, h_sys, nsys, s, stream);
+    int rc = ordering == LPCG_ORDER_COLOR ? analyze_color(A, h_sys, nsys, s, stream)
+                                          : analyze_impl(A, h_sys, nsys, s, stream);
     if (rc != LPCG_OK) {
         hipStreamSynchronize(stream);
         lpcg_destroy(s);
@@ -430,7 +666,7 @@ extern "C" int lpcg_update_values(lpcg_system *s, const double *val, hipStream_t
         set_error("lpcg_update_values: invalid arguments");
         return LPCG_EINVAL;
     }
-    k_values<<<nblk(std::max(s->n, s->nnz), 256), 256, 0, stream>>>(s->nnz, s->n, val, s->dpos,
+    k_values<<<nblk(std::max(s->n, s->nnz), 256), 256, 0, stream>>>(s->nnz, s->n, val, s->psrc, s->dpos,
                                                                        s->val64, s->val32, s->diag64);
     LPCG_LAUNCH_CHECK();
     return LPCG_OK;
@@ -449,6 +685,8 @@ extern "C" int lpcg_get_info(const lpcg_system *s, lpcg_info *info) {
     info->max_width_fwd = s->max_w_f;
     info->max_width_bwd = s->max_w_b;
     info->nsys = s->nsys;
+    info->ordering = s->ordering;
+    info->ncolors = s->ncolors;
     return LPCG_OK;
 }
 
@@ -480,6 +718,20 @@ extern "C" int lpcg_export_pattern(const lpcg_system *s, int32_t *lrowptr, int32
     rc |= cp(blev_ptr, s->blev_ptr, s->nlev_b + 1);
     rc |= cp(blev_rows, s->blev_rows, s->n);
     return rc ? LPCG_EHIP : LPCG_OK;
+}
+
+extern "C" int lpcg_export_perm(const lpcg_system *s, int32_t *perm, hipStream_t st) {
+    if (!s || !perm) {
+        set_error("lpcg_export_perm: invalid arguments");
+        return LPCG_EINVAL;
+    }
+    if (s->perm) {
+        LPCG_HIP(hipMemcpyAsync(perm, s->perm, sizeof(int) * s->n, hipMemcpyDeviceToDevice, st));
+    } else {
+        k_iota_fill<<<nblk(s->n, 256), 256, 0, st>>>(s->n, perm, nullptr, nullptr);
+        LPCG_LAUNCH_CHECK();
+    }
+    return LPCG_OK;
 }
 
 extern "C" void lpcg_destroy(lpcg_system *s) {

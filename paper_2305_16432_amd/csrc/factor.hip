@@ -199,8 +199,20 @@ extern "C" int lpcg_spmv(const lpcg_system *s, int32_t prec, const void *x, void
         set_error("lpcg_spmv: invalid arguments");
         return LPCG_EINVAL;
     }
-    if (prec == 32) return spmv32(s, (const float *)x, (float *)y, st);
-    return spmv64(s, (const double *)x, (double *)y, st);
+    if (!s->perm) {
+        if (prec == 32) return spmv32(s, (const float *)x, (float *)y, st);
+        return spmv64(s, (const double *)x, (double *)y, st);
+    }
+    // reordered system: x and y are in the caller's numbering
+    int rc;
+    if (prec == 32) {
+        float *xi = (float *)s->t64a, *yi = (float *)s->t64b;
+        if ((rc = to_internal_f32(s, (const float *)x, xi, st)) || (rc = spmv32(s, xi, yi, st))) return rc;
+        return from_internal_f32(s, yi, (float *)y, st);
+    }
+    if ((rc = to_internal_f64(s, (const double *)x, s->t64a, st)) || (rc = spmv64(s, s->t64a, s->t64b, st)))
+        return rc;
+    return from_internal_f64(s, s->t64b, (double *)y, st);
 }
 
 extern "C" int lpcg_sptrsv(const lpcg_system *s, int32_t transpose, const float *l_val,
@@ -209,7 +221,13 @@ extern "C" int lpcg_sptrsv(const lpcg_system *s, int32_t transpose, const float 
         set_error("lpcg_sptrsv: invalid arguments");
         return LPCG_EINVAL;
     }
-    return sptrsv32(s, transpose, l_val, ut_val, rhs, y, s->ctrl + C_TICKET_X, st);
+    if (!s->perm) return sptrsv32(s, transpose, l_val, ut_val, rhs, y, s->ctrl + C_TICKET_X, st);
+    float *ri = (float *)s->t64a, *yi = (float *)s->t64b;
+    int rc;
+    if ((rc = to_internal_f32(s, rhs, ri, st)) ||
+        (rc = sptrsv32(s, transpose, l_val, ut_val, ri, yi, s->ctrl + C_TICKET_X, st)))
+        return rc;
+    return from_internal_f32(s, yi, y, st);
 }
 
 extern "C" int lpcg_l_to_ut(const lpcg_system *s, const float *l_val, float *ut_val,

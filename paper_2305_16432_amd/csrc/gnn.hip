@@ -5,7 +5,7 @@
 //
 // Kernels (H = latent width, 32 or 64; one wave = 32 rows, BF16 MFMA with
 // FP32 accumulation, see kern_gnn.h):
-//   k_gnn_norm   per system: s = mean(diag A), rms(b)
+//   k_gnn_norm_* per system: s = mean(diag A), rms(b) (two-stage sums)
 //   k_enc<NODE>  node encoder on b_i/rms, edge encoder on A_ij/s
 //   k_node       aggregation m_i = sum_{k in row i} E[k] * V[col k] (fused),
 //                node MLP on [V_i, m_i], and the projections V W_a, V W_b of
@@ -51,7 +51,7 @@ GnnOff gnn_offsets(int h, int n_mp) {
 // V/E buffers (ping-pong); training keeps every layer's activations plus the
 // backward pass's intermediates.
 struct GnnWs {
-    size_t sys_s, sys_rms;
+    size_t sys_s, sys_rms, norm_part;
     size_t V[kMaxMp + 1], Pa[kMaxMp], Pb[kMaxMp], E[kMaxMp + 1];
     size_t d;
     // backward (train only)
@@ -62,6 +62,15 @@ struct GnnWs {
 
 // Blocks of the weight-gradient kernels = number of per-block partial sums.
 constexpr int kWgradBlocks = 256;
+
+// Row segments per system for the two-stage normalisation sums: enough for
+// the largest system of the batch.
+constexpr int kNormRows = 4096;
+int norm_segments(const lpcg_system *s) {
+    int mx = 1;
+    for (int i = 0; i < s->nsys; ++i) mx = std::max(mx, s->h_sys_rowptr[i + 1] - s->h_sys_rowptr[i]);
+    return (mx + kNormRows - 1) / kNormRows;
+}
 
 GnnWs gnn_ws_layout(const lpcg_system *s, int h, int n_mp, bool train) {
     GnnWs w{};
@@ -74,6 +83,7 @@ GnnWs gnn_ws_layout(const lpcg_system *s, int h, int n_mp, bool train) {
     const size_t n = s->n, nnz = s->nnz, mx = std::max(n, nnz);
     w.sys_s = take(sizeof(double) * s->nsys);
     w.sys_rms = take(sizeof(double) * s->nsys);
+    w.norm_part = take(2 * sizeof(double) * (size_t)s->nsys * norm_segments(s));
     const int nv = train ? n_mp + 1 : 2;
     const int np = train ? n_mp : 1;
     for (int i = 0; i < nv; ++i) w.V[i] = take(2 * n * h);
@@ -119,13 +129,15 @@ constexpr int kMaxGnnBlocks = 1024;
 
 int nblk(long n, int t) { return (int)((n + t - 1) / t); }
 
-__global__ void k_gnn_norm(int nsys, const int *__restrict__ sys_rowptr, const int *__restrict__ dpos,
-                           const double *__restrict__ val, const double *__restrict__ b,
-                           double *__restrict__ sys_s, double *__restrict__ sys_rms) {
+// Normalisation sums, stage 1: block (x, y) sums diag(A) and b^2 over
+// segment x (kNormRows rows) of system y; empty segments write zeros.
+__global__ void k_gnn_norm_part(int nseg, const int *__restrict__ sys_rowptr, const int *__restrict__ dpos,
+                                const double *__restrict__ val, const double *__restrict__ b,
+                                double *__restrict__ part) {
     __shared__ double lds[kGnnThreads / kWave];
-    const int sy = blockIdx.x;
-    if (sy >= nsys) return;
-    const int r0 = sys_rowptr[sy], r1 = sys_rowptr[sy + 1];
+    const int sy = blockIdx.y, sg = blockIdx.x;
+    const int r0 = sys_rowptr[sy] + sg * kNormRows;
+    const int r1 = min(sys_rowptr[sy + 1], r0 + kNormRows);
     double sd = 0, sb = 0;
     for (int i = r0 + threadIdx.x; i < r1; i += kGnnThreads) {
         sd += val[dpos[i]];
@@ -134,11 +146,27 @@ __global__ void k_gnn_norm(int nsys, const int *__restrict__ sys_rowptr, const i
     sd = block_sum<kGnnThreads>(sd, lds);
     sb = block_sum<kGnnThreads>(sb, lds);
     if (threadIdx.x == 0) {
-        const double cnt = (double)(r1 - r0);
-        sys_s[sy] = sd / cnt;
-        const double rms = sqrt(sb / cnt);
-        sys_rms[sy] = rms > 0 ? rms : 1.0;
+        part[2 * ((size_t)sy * nseg + sg)] = sd;
+        part[2 * ((size_t)sy * nseg + sg) + 1] = sb;
     }
+}
+
+// Stage 2: per system, s = mean(diag A) and rms(b) (1 if b = 0), summing the
+// segments in order (deterministic).
+__global__ void k_gnn_norm_fin(int nsys, int nseg, const int *__restrict__ sys_rowptr,
+                               const double *__restrict__ part, double *__restrict__ sys_s,
+                               double *__restrict__ sys_rms) {
+    const int sy = blockIdx.x * blockDim.x + threadIdx.x;
+    if (sy >= nsys) return;
+    double sd = 0, sb = 0;
+    for (int g = 0; g < nseg; ++g) {
+        sd += part[2 * ((size_t)sy * nseg + g)];
+        sb += part[2 * ((size_t)sy * nseg + g) + 1];
+    }
+    const double cnt = (double)(sys_rowptr[sy + 1] - sys_rowptr[sy]);
+    sys_s[sy] = sd / cnt;
+    const double rms = sqrt(sb / cnt);
+    sys_rms[sy] = rms > 0 ? rms : 1.0;
 }
 
 // Encoder: out[row] = relu(x W0 + b0) W1 + b1 with scalar input x.
@@ -407,7 +435,13 @@ int forward_impl(const lpcg_system *s, const lpcg_gnn *net, const double *b, uns
     const GnnOff o = gnn_offsets(H, net->n_mp);
     const float *P = net->params;
     double *sys_s = (double *)(ws + L.sys_s), *sys_rms = (double *)(ws + L.sys_rms);
-    k_gnn_norm<<<s->nsys, kGnnThreads, 0, st>>>(s->nsys, s->sys_rowptr, s->dpos, s->val64, b, sys_s, sys_rms);
+    {
+        const int nseg = norm_segments(s);
+        double *part = (double *)(ws + L.norm_part);
+        k_gnn_norm_part<<<dim3(nseg, s->nsys), kGnnThreads, 0, st>>>(nseg, s->sys_rowptr, s->dpos, s->val64, b,
+                                                                     part);
+        k_gnn_norm_fin<<<nblk(s->nsys, 64), 64, 0, st>>>(s->nsys, nseg, s->sys_rowptr, part, sys_s, sys_rms);
+    }
     auto V = [&](int t) { return (__bf16 *)(ws + L.V[train ? t : (t & 1)]); };
     auto E = [&](int t) { return (__bf16 *)(ws + L.E[train ? t : (t & 1)]); };
     auto Pa = [&](int t) { return (__bf16 *)(ws + L.Pa[train ? t : 0]); };
@@ -457,10 +491,18 @@ int gnn_forward(const lpcg_system *s, const lpcg_gnn *net, const double *b, void
         set_error("gnn forward: invalid arguments");
         return LPCG_EINVAL;
     }
+    if (s->nsys > 65535) {
+        set_error("gnn forward: at most 65535 systems per batch");
+        return LPCG_EINVAL;
+    }
     const GnnWs L = gnn_ws_layout(s, net->h, net->n_mp, train);
     if ((size_t)ws_bytes < L.total) {
         set_error("gnn forward: workspace of %lld bytes, %zu needed", (long long)ws_bytes, L.total);
         return LPCG_ENOMEM;
+    }
+    if (s->perm) {  // node inputs in the system's internal order
+        if ((rc = to_internal_f64(s, b, s->bperm, st))) return rc;
+        b = s->bperm;
     }
     if (net->h == 32) return forward_impl<32>(s, net, b, (unsigned char *)ws, L, train, lval, utval, st);
     return forward_impl<64>(s, net, b, (unsigned char *)ws, L, train, lval, utval, st);

@@ -96,6 +96,12 @@ extern "C" int lpcg_llt_loss(const lpcg_system *s, const float *l_val, const dou
     }
     const int n = s->n;
     double *u = s->t64a, *r = s->t64b, *w = s->t64c, *rms2 = s->sys_tmp;
+    if (s->perm) {  // x and b arrive in the caller's numbering
+        int rc;
+        if ((rc = to_internal_f64(s, x, s->xperm, st)) || (rc = to_internal_f64(s, b, s->bperm, st))) return rc;
+        x = s->xperm;
+        b = s->bperm;
+    }
     k_ltmul<<<nblk(n, 256), 256, 0, st>>>(n, s->urowptr, s->ucol, s->u2l, l_val, x, u);
     k_lmul_res<<<nblk(n, 256), 256, 0, st>>>(n, s->lrowptr, s->lcol, l_val, u, b, r);
     k_sys_loss<<<s->nsys, 256, 0, st>>>(s->nsys, s->sys_rowptr, b, r, rms2, loss);

@@ -56,6 +56,13 @@ struct lpcg_system {
     int *flevel = nullptr, *flev_ptr = nullptr, *flev_rows = nullptr;
     int *blevel = nullptr, *blev_ptr = nullptr, *blev_rows = nullptr;
     int *sys_rowptr = nullptr, *row_sys = nullptr;
+    // row ordering (LPCG_ORDER_*): the system holds P A P^T with
+    // perm[new] = original row, iperm[original] = new row and psrc[k'] = the
+    // position in the caller's CSR of internal entry k'.  All three are null
+    // for the natural ordering.
+    int ordering = 0, ncolors = 0;
+    int *perm = nullptr, *iperm = nullptr, *psrc = nullptr;
+    double *bperm = nullptr, *xperm = nullptr;  // caller vectors in internal order
     std::vector<int> h_flev_ptr, h_blev_ptr, h_sys_rowptr;
     // values (device)
     double *val64 = nullptr;
@@ -89,3 +96,14 @@ struct lpcg_system {
     } while (0)
 
 #define LPCG_LAUNCH_CHECK() LPCG_HIP(hipGetLastError())
+
+namespace lpcg {
+// Permutation of caller vectors (original numbering) to and from the
+// system's internal order: to_internal: dst[r] = src[perm[r]];
+// from_internal: dst[perm[r]] = src[r].  No-ops (plain copies are not made)
+// when the system has the natural ordering; callers test s->perm first.
+int to_internal_f64(const lpcg_system *s, const double *src, double *dst, hipStream_t st);
+int from_internal_f64(const lpcg_system *s, const double *src, double *dst, hipStream_t st);
+int to_internal_f32(const lpcg_system *s, const float *src, float *dst, hipStream_t st);
+int from_internal_f32(const lpcg_system *s, const float *src, float *dst, hipStream_t st);
+}  // namespace lpcg

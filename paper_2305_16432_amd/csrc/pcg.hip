@@ -440,8 +440,13 @@ extern "C" int lpcg_pcg_solve(lpcg_system *s, const lpcg_precond *P, const doubl
     a.lval = P->l_val;
     a.utval = P->ut_val;
     a.dinv = P->dinv ? P->dinv : s->dinv;
-    a.b = b;
-    a.x = x;
+    // a reordered system solves (P A P^T)(P x) = P b in its internal order
+    if (s->perm) {
+        int rc;
+        if ((rc = to_internal_f64(s, b, s->bperm, st)) || (rc = to_internal_f64(s, x, s->xperm, st))) return rc;
+    }
+    a.b = s->perm ? s->bperm : b;
+    a.x = s->perm ? s->xperm : x;
     a.r = s->r;
     a.p = s->p;
     a.w = s->w;
@@ -490,6 +495,11 @@ extern "C" int lpcg_pcg_solve(lpcg_system *s, const lpcg_precond *P, const doubl
     }
     res->iters = iters;
     res->status = status;
+    if (s->perm) {
+        int rc = from_internal_f64(s, s->xperm, x, st);
+        if (rc) return rc;
+        LPCG_HIP(hipStreamSynchronize(st));
+    }
     if (status == LPCG_ENOTCONV) set_error("pcg: no convergence within maxit");
     if (status == LPCG_EBREAKDOWN) set_error("pcg: breakdown (p.Ap <= 0 or non-finite)");
     return status;

@@ -37,7 +37,7 @@ class _Info(C.Structure):
     _fields_ = [("n", C.c_int32), ("nnz", C.c_int32), ("nnz_l", C.c_int32),
                 ("nlev_fwd", C.c_int32), ("nlev_bwd", C.c_int32),
                 ("max_width_fwd", C.c_int32), ("max_width_bwd", C.c_int32),
-                ("nsys", C.c_int32)]
+                ("nsys", C.c_int32), ("ordering", C.c_int32), ("ncolors", C.c_int32)]
 
 
 class _Precond(C.Structure):
@@ -135,7 +135,10 @@ class System:
 
 
 # ------------------------------------------------------------------ analysis
-def analyze(rowptr, colind, val, sys_rowptr=None) -> System:
+ORDER_NATURAL, ORDER_COLOR = 0, 1
+
+
+def analyze(rowptr, colind, val, sys_rowptr=None, ordering: int = ORDER_NATURAL) -> System:
     rowptr = _dev(rowptr, torch.int32).contiguous()
     colind = _dev(colind, torch.int32).contiguous()
     val = _dev(val, torch.float64).contiguous()
@@ -149,7 +152,7 @@ def analyze(rowptr, colind, val, sys_rowptr=None) -> System:
         srp = sr.ctypes.data_as(C.c_void_p)
     else:
         nsys, srp = 1, None
-    rc = lib().lpcg_analyze(C.byref(A), srp, C.c_int32(nsys), C.byref(out), _stream())
+    rc = lib().lpcg_analyze(C.byref(A), srp, C.c_int32(nsys), C.c_int32(ordering), C.byref(out), _stream())
     _check(rc, "lpcg_analyze")
     return System(out, n, colind.numel())
 
@@ -178,6 +181,13 @@ def export_pattern(sys: System) -> dict:
         "lrowptr", "lcol", "lsrc", "urowptr", "ucol", "u2l", "rev", "flevel", "flev_ptr",
         "flev_rows", "blevel", "blev_ptr", "blev_rows")], _stream())
     _check(rc, "lpcg_export_pattern")
+    return out
+
+
+def export_perm(sys: System):
+    """perm[internal row] = original row (identity for the natural ordering)."""
+    out = torch.empty(sys.info["n"], dtype=torch.int32, device="cuda")
+    _check(lib().lpcg_export_perm(sys.handle, _ptr(out), _stream()), "lpcg_export_perm")
     return out
 
 

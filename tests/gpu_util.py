@@ -26,8 +26,8 @@ def host(t):
     return t.detach().cpu().numpy()
 
 
-def gpu_system(A, sys_rowptr=None):
-    return lpcg.analyze(cuda_i32(A.rowptr), cuda_i32(A.colind), cuda_f64(A.val), sys_rowptr)
+def gpu_system(A, sys_rowptr=None, ordering=0):
+    return lpcg.analyze(cuda_i32(A.rowptr), cuda_i32(A.colind), cuda_f64(A.val), sys_rowptr, ordering)
 
 
 def matrices_small():
