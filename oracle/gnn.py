@@ -22,9 +22,14 @@ Readings where the paper is silent (each listed in the design notes):
   * diag_mode 0: the diagonal, where the pair average is d_ii itself, is made
     positive with L_ii = max(softplus(d_ii), 1e-6) so that L L^T is SPD by
     construction, and L = sqrt(s) * L_hat;
-  * diag_mode 1 (the appendix's L D L^T form with D = diag(A)): the network
-    predicts a unit lower-triangular L' and P = L' D L'^T = L L^T with
-    L = L' D^(1/2), i.e. L_ii = sqrt(A_ii), L_ij = sqrt(A_jj) (d_ij + d_ji)/2.
+  * diag_mode 1 (the appendix's L D L^T form with D = diag(A), reading L'
+    as unit lower-triangular): P = L' D L'^T = L L^T with L = L' D^(1/2),
+    i.e. L_ii = sqrt(A_ii), L_ij = sqrt(A_jj) (d_ij + d_ji)/2;
+  * diag_mode 2 (the same form, reading L' as a general lower-triangular
+    factor, which is what makes the appendix's equivalence with L L^T hold):
+    L'_ii = max(softplus(d_ii + ln(e - 1)), 1e-6) > 0 (equal to 1 at
+    d_ii = 0), so L_ii = sqrt(A_ii) L'_ii and L_ij = sqrt(A_jj) (d_ij + d_ji)/2.
+    Zero decoder output gives L' = I, i.e. P = diag(A), in modes 1 and 2.
 
 Pins (tests/test_oracle_gnn.py): all-zero weights give a closed form; a
 2-node graph computed by hand; permutation equivariance; 5-hop locality;
@@ -36,6 +41,7 @@ from __future__ import annotations
 import numpy as np
 
 SOFTPLUS_FLOOR = 1e-6
+DIAG_SHIFT = float(np.log(np.e - 1.0))  # softplus(DIAG_SHIFT) = 1
 
 
 def _relu(x):
@@ -124,7 +130,11 @@ def forward(A, b, P, h, n_mp, rev=None, keep=False, diag_mode=0):
     else:
         adiag = A.val[diag]                       # A_jj, j = 0..n-1
         colscale = np.sqrt(adiag[np.minimum(row, col)])  # sqrt(A_cc), cc = column of the lower entry
-        lfull = np.where(diag, np.sqrt(adiag[row]), colscale * 0.5 * (d + d[rev]))
+        if diag_mode == 1:
+            ldiag = np.sqrt(adiag[row])
+        else:
+            ldiag = colscale * np.maximum(_softplus(d + DIAG_SHIFT), SOFTPLUS_FLOOR)
+        lfull = np.where(diag, ldiag, colscale * 0.5 * (d + d[rev]))
         lval = lfull[lower]
     cache = None
     if keep:
@@ -150,9 +160,14 @@ def backward(P, cache, glval):
         sp = _softplus(d)
         gd += np.where(diag & (sp > SOFTPLUS_FLOOR), glhat * _sigmoid(d), 0.0)
     else:
-        # diagonal fixed to sqrt(A_ii); strictly lower scaled by sqrt(A_jj)
+        # strictly lower scaled by sqrt(A_jj); diagonal fixed to sqrt(A_ii)
+        # (mode 1) or sqrt(A_ii) max(softplus(d_ii + shift), floor) (mode 2)
         glhat = np.zeros(nnz)
         glhat[np.nonzero(lower)[0]] = np.asarray(glval, np.float64)
+        if cache["diag_mode"] == 2:
+            ds = d + DIAG_SHIFT
+            gd += np.where(diag & (_softplus(ds) > SOFTPLUS_FLOOR),
+                           glhat * cache["colscale"] * _sigmoid(ds), 0.0)
         glhat = glhat * np.where(diag, 0.0, cache["colscale"])
     # strictly lower: (d_k + d_rev(k)) / 2
     gd += np.where(off, 0.5 * glhat, 0.0)

@@ -131,8 +131,9 @@ def test_backward_finite_differences():
     _fd_check(F, bf, g.init_gnn_params(3, 3, seed=9), 3, 3, 10)
 
 
-def _torch_model(A, b, P, h, n_mp):
-    """Independent float64 model with torch primitives (index_add_, cat, softplus)."""
+def _torch_model(A, b, P, h, n_mp, diag_mode=0):
+    """Independent float64 model with torch primitives (index_add_, cat,
+    softplus); modes 1/2 build L = L' D^(1/2) as a dense matrix product."""
     row = torch.as_tensor(A.row_of_entry(), dtype=torch.long)
     col = torch.as_tensor(A.colind, dtype=torch.long)
     val = torch.as_tensor(A.val)
@@ -153,19 +154,29 @@ def _torch_model(A, b, P, h, n_mp):
     # pair average via a dense symmetric scatter
     Dm = torch.zeros(A.n, A.n, dtype=torch.float64).index_put((row, col), d)
     Sym = 0.5 * (Dm + Dm.T)
-    diag = torch.clamp(torch.nn.functional.softplus(torch.diagonal(Dm)), min=1e-6)
-    Lfull = torch.tril(Sym, -1) + torch.diag(diag)
     lower = col <= row
-    return torch.sqrt(s) * Lfull[row[lower], col[lower]], T
+    if diag_mode == 0:
+        diag = torch.clamp(torch.nn.functional.softplus(torch.diagonal(Dm)), min=1e-6)
+        Lfull = torch.tril(Sym, -1) + torch.diag(diag)
+        return torch.sqrt(s) * Lfull[row[lower], col[lower]], T
+    if diag_mode == 1:
+        dprime = torch.ones(A.n, dtype=torch.float64)
+    else:
+        dprime = torch.clamp(torch.nn.functional.softplus(torch.diagonal(Dm) + np.log(np.e - 1)), min=1e-6)
+    Lp = torch.tril(Sym, -1) + torch.diag(dprime)
+    Ad = torch.as_tensor(A.to_dense()).diagonal()
+    Lfull = Lp @ torch.diag(torch.sqrt(Ad))
+    return Lfull[row[lower], col[lower]], T
 
 
-def test_backward_matches_torch_autograd():
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_backward_matches_torch_autograd(mode):
     A = g.fem_p1_delaunay(8, 3, 4)[0]
     b = np.random.default_rng(11).standard_normal(A.n)
     h, n_mp = 5, 3
     P = g.init_gnn_params(h, n_mp, seed=12, gain=1.5)
-    lval, cache = gnn.forward(A, b, P, h, n_mp, keep=True)
-    lt, T = _torch_model(A, b, P, h, n_mp)
+    lval, cache = gnn.forward(A, b, P, h, n_mp, keep=True, diag_mode=mode)
+    lt, T = _torch_model(A, b, P, h, n_mp, diag_mode=mode)
     np.testing.assert_allclose(lval, lt.detach().numpy(), rtol=1e-12, atol=1e-13)
     gl = np.random.default_rng(13).standard_normal(lval.shape[0])
     (lt * torch.as_tensor(gl)).sum().backward()
@@ -208,41 +219,46 @@ def test_adam_first_step_is_signed_lr_and_minimises_quadratic():
     assert np.abs(p["w"]).max() < 0.05 * start
 
 
-def test_diag_mode1_zero_weights_closed_form_and_jacobi_start():
-    """diag_mode 1 (L' D L'^T with D = diag(A)) and all-zero weights except a
+@pytest.mark.parametrize("mode", [1, 2])
+def test_diag_mode1_zero_weights_closed_form_and_jacobi_start(mode):
+    """diag_mode 1/2 (L' D L'^T with D = diag(A)) and all-zero weights except a
     zero decoder bias: L' = I, so P = diag(A) exactly (Jacobi); with decoder
-    bias c: L_ij = sqrt(A_jj) c below the diagonal, L_ii = sqrt(A_ii)."""
+    bias c: L_ij = sqrt(A_jj) c below the diagonal, L_ii = sqrt(A_ii) (mode 1)
+    or sqrt(A_ii) log(1 + (e - 1) e^c) (mode 2: softplus(c + ln(e - 1)))."""
     A, b = g.heat_system_3d(5, 1e-3, k_seed=3, u0_seed=4)
     pat = O.Pattern(A)
     row = np.repeat(np.arange(A.n), np.diff(pat.lrowptr))
     diag = pat.lcol == row
     P = g.init_gnn_params(8, 2, seed=1, zero=True)
     c = float(P["dec.b1"][0])
-    lval, _ = gnn.forward(A, b, P, 8, 2, diag_mode=1)
+    lval, _ = gnn.forward(A, b, P, 8, 2, diag_mode=mode)
     ad = O.diag(A)
-    np.testing.assert_allclose(lval[diag], np.sqrt(ad), rtol=1e-15)
+    dscale = 1.0 if mode == 1 else np.log1p((np.e - 1.0) * np.exp(c))
+    np.testing.assert_allclose(lval[diag], np.sqrt(ad) * dscale, rtol=1e-14)
     np.testing.assert_allclose(lval[~diag], np.sqrt(ad[pat.lcol[~diag]]) * c, rtol=1e-15)
     P["dec.b1"][:] = 0.0
-    lval, _ = gnn.forward(A, b, P, 8, 2, diag_mode=1)
+    lval, _ = gnn.forward(A, b, P, 8, 2, diag_mode=mode)
+    np.testing.assert_allclose(lval[diag], np.sqrt(ad), rtol=1e-15)
     x = np.random.default_rng(0).standard_normal(A.n)
     r1 = O.pcg(A, x, O.PC_LLT, pat, lval, tol=1e-10, maxit=5)
     r2 = O.pcg(A, x, O.PC_JACOBI, tol=1e-10, maxit=5)
     np.testing.assert_allclose(r1["x"], r2["x"], rtol=1e-12, atol=1e-14)
 
 
-def test_diag_mode1_backward_finite_differences_and_torch():
+@pytest.mark.parametrize("mode", [1, 2])
+def test_diag_mode1_backward_finite_differences_and_torch(mode):
     A = g.fem_p1_delaunay(8, 3, 4)[0]
     b = np.random.default_rng(11).standard_normal(A.n)
     h, n_mp = 4, 2
     P = g.init_gnn_params(h, n_mp, seed=12, gain=1.5)
-    lval, cache = gnn.forward(A, b, P, h, n_mp, keep=True, diag_mode=1)
+    lval, cache = gnn.forward(A, b, P, h, n_mp, keep=True, diag_mode=mode)
     rng = np.random.default_rng(3)
     gl = rng.standard_normal(lval.shape[0])
     G = gnn.backward(P, cache, gl)
     V = {k: rng.standard_normal(v.shape) for k, v in P.items()}
     eps = 1e-7
-    fp = gl @ gnn.forward(A, b, {k: P[k] + eps * V[k] for k in P}, h, n_mp, diag_mode=1)[0]
-    fm = gl @ gnn.forward(A, b, {k: P[k] - eps * V[k] for k in P}, h, n_mp, diag_mode=1)[0]
+    fp = gl @ gnn.forward(A, b, {k: P[k] + eps * V[k] for k in P}, h, n_mp, diag_mode=mode)[0]
+    fm = gl @ gnn.forward(A, b, {k: P[k] - eps * V[k] for k in P}, h, n_mp, diag_mode=mode)[0]
     fd = (fp - fm) / (2 * eps)
     an = sum(np.sum(G[k] * V[k]) for k in P)
     assert abs(fd - an) <= 1e-5 * max(1.0, abs(fd)), (fd, an)
