@@ -8,6 +8,12 @@ Jacobi diagonal) and run PCG until ||r|| <= 1e-6 ||b|| with the FP64 true
 residual checked.  The system, its pattern analysis and the network weights
 are resident in HBM before the timed region.
 
+Both row orderings of the library are measured: the natural one (the factor
+on tril(A), as in the paper) and the multicolour one (red-black on this
+grid; the factor on tril(P A P^T)), each with its own trained network.  The
+headline value is learned-L in the ordering where it is fastest; every
+method/ordering pair is in "methods".
+
 Prints one JSON line (see the end of main()).
 """
 from __future__ import annotations
@@ -24,7 +30,9 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-WEIGHTS = os.path.join(ROOT, "paper_2305_16432_amd", "weights", "heat3d_h32_mp3.npz")
+WEIGHTS = {"natural": os.path.join(ROOT, "paper_2305_16432_amd", "weights", "heat3d_h32_mp3.npz"),
+           "color": os.path.join(ROOT, "paper_2305_16432_amd", "weights", "heat3d_h32_mp3_color.npz")}
+PEAK_HBM = 8000.0  # GB/s, MI355X HBM3E
 
 
 def _log(msg):
@@ -40,6 +48,7 @@ def hbm_bytes_sptrsv(info):
 
 
 def hbm_bytes_spmv(info):
+    """FP32 values + int32 columns (8 nnz), row pointers, x and y (8 n)."""
     n, nnz = info["n"], info["nnz"]
     return 8 * nnz + 4 * (n + 1) + 8 * n
 
@@ -59,7 +68,7 @@ def cpu_baseline(A, b, tol, budget_s=20.0):
         times.append((time.perf_counter() - t0) * 1e3)
         iters = res["iters"]
     return {"value": float(np.mean(times)), "unit": "ms", "cores": 1, "kind": "oracle",
-            "sample": f"IC(0) factorisation + PCG to {tol:g} on the full 64^3 system "
+            "sample": f"IC(0) factorisation + PCG to {tol:g} on the full 64^3 system, natural order "
                       f"(serial C FP64, {len(times)} run(s), {iters} iterations)"}
 
 
@@ -73,10 +82,11 @@ def main():
     ap.add_argument("--u-seed", type=int, default=2000)
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--orderings", default="natural,color")
     ap.add_argument("--methods", default="learned,ic0,jacobi")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py: runs on one GPU; --gpus {args.gpus} is not supported "
               "(the solver does not shard a system across GPUs)", file=sys.stderr)
         sys.exit(2)
 
@@ -88,93 +98,91 @@ def main():
     torch.cuda.set_device(0)
     A, b = g.heat_system_3d(args.m, 1e-3, args.k_seed, args.u_seed)
     _log(f"system n={A.n} nnz={A.nnz}")
-    S = lpcg.analyze(torch.as_tensor(A.rowptr).cuda(), torch.as_tensor(A.colind).cuda(),
-                     torch.as_tensor(A.val).cuda())
-    info = S.info
     bd = torch.as_tensor(b).cuda()
-    nl = info["nnz_l"]
-    lval = torch.empty(nl, dtype=torch.float32, device="cuda")
-    utval = torch.empty(nl, dtype=torch.float32, device="cuda")
-    dinv = torch.empty(A.n, dtype=torch.float32, device="cuda")
     x = torch.zeros_like(bd)
     solve_kw = dict(tol=args.tol, check_every=8, max_restarts=2, use_graph=True)
+    results, kernels = {}, {}
+    for ordering in args.orderings.split(","):
+        code = lpcg.ORDER_COLOR if ordering == "color" else lpcg.ORDER_NATURAL
+        S = lpcg.analyze(torch.as_tensor(A.rowptr).cuda(), torch.as_tensor(A.colind).cuda(),
+                         torch.as_tensor(A.val).cuda(), None, code)
+        info = S.info
+        _log(f"{ordering}: {info['nlev_fwd']} forward levels, {info['ncolors']} colours")
+        nl = info["nnz_l"]
+        lval = torch.empty(nl, dtype=torch.float32, device="cuda")
+        utval = torch.empty(nl, dtype=torch.float32, device="cuda")
+        dinv = torch.empty(A.n, dtype=torch.float32, device="cuda")
 
-    methods = {}
+        def run_ic0():
+            lpcg.ic0(S, 0.0, 8, lval, utval)
 
-    def run_ic0():
-        lpcg.ic0(S, 0.0, 8, lval, utval)
+        def solve_llt():
+            x.zero_()
+            return lpcg.pcg_solve(S, lpcg.PC_LLT, bd, x=x, l_val=lval, ut_val=utval, **solve_kw)[1]
 
-    def solve_llt():
-        x.zero_()
-        return lpcg.pcg_solve(S, lpcg.PC_LLT, bd, x=x, l_val=lval, ut_val=utval, **solve_kw)[1]
+        def run_jacobi():
+            lpcg.jacobi(S, dinv)
 
-    def run_jacobi():
-        lpcg.jacobi(S, dinv)
+        def solve_jacobi():
+            x.zero_()
+            return lpcg.pcg_solve(S, lpcg.PC_JACOBI, bd, x=x, dinv=dinv, **solve_kw)[1]
 
-    def solve_jacobi():
-        x.zero_()
-        return lpcg.pcg_solve(S, lpcg.PC_JACOBI, bd, x=x, dinv=dinv, **solve_kw)[1]
-
-    methods["ic0"] = (run_ic0, solve_llt)
-    methods["jacobi"] = (run_jacobi, solve_jacobi)
-    learned_note = None
-    if "learned" in args.methods:
-        if hasattr(lpcg, "gnn_predict_L") and os.path.exists(WEIGHTS):
-            W = np.load(WEIGHTS)
-            h, n_mp = int(W["h"]), int(W["n_mp"])
-            dmode = int(W["diag_mode"]) if "diag_mode" in W else 0
+        methods = {"ic0": (run_ic0, solve_llt)}
+        if ordering == "natural":
+            methods["jacobi"] = (run_jacobi, solve_jacobi)  # the same preconditioner in any order
+        if os.path.exists(WEIGHTS[ordering]):
+            W = np.load(WEIGHTS[ordering])
+            assert int(W["ordering"]) == code, "network trained for another ordering"
+            h, n_mp, dmode = int(W["h"]), int(W["n_mp"]), int(W["diag_mode"])
             params = torch.as_tensor(W["params"].astype(np.float32)).cuda()
             ws = lpcg.gnn_workspace(S, h, n_mp, train=False)
 
-            def run_learned():
+            def run_learned(params=params, h=h, n_mp=n_mp, dmode=dmode, ws=ws):
                 lpcg.gnn_predict_L(S, params, h, n_mp, bd, ws, lval, utval, diag_mode=dmode)
             methods["learned"] = (run_learned, solve_llt)
-        else:
-            learned_note = "learned-L unavailable (no trained weights in this build)"
-            _log(learned_note)
-
-    results = {}
-    order = [m for m in ("learned", "ic0", "jacobi") if m in methods and m in args.methods]
-    for name in order:
-        pre, solve = methods[name]
-        for _ in range(args.warmup):
-            pre()
-            solve()
-        torch.cuda.synchronize()
-        t_pre, t_solve, iters, relres = [], [], [], []
-        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
-        torch.cuda.synchronize()
-        wall0 = time.perf_counter()
-        for _ in range(args.steps):
-            e0.record()
-            pre()
-            e1.record()
-            res = solve()
-            e2.record()
+        for name in [m for m in ("learned", "ic0", "jacobi") if m in methods and m in args.methods]:
+            pre, solve = methods[name]
+            for _ in range(args.warmup):
+                pre()
+                solve()
             torch.cuda.synchronize()
-            t_pre.append(e0.elapsed_time(e1))
-            t_solve.append(e1.elapsed_time(e2))
-            iters.append(res["iters"])
-            relres.append(res["relres_true"])
-        torch.cuda.synchronize()
-        wall = (time.perf_counter() - wall0) * 1e3 / args.steps
-        results[name] = dict(ms=float(np.mean(np.array(t_pre) + np.array(t_solve))),
-                             precompute_ms=float(np.mean(t_pre)), solve_ms=float(np.mean(t_solve)),
-                             wall_ms=wall, iters=int(np.max(iters)),
-                             relres_true=float(np.max(relres)), status=res["status"])
-        _log(f"{name}: {results[name]}")
-
-    # roofline: the substitution kernel (the per-iteration bottleneck of LLT PCG)
-    lpcg.ic0(S, 0.0, 8, lval, utval)
-    rhs = torch.as_tensor(b.astype(np.float32)).cuda()
-    ms_trsv = lpcg.time_sptrsv(S, False, lval, utval, rhs, reps=50)
-    bytes_trsv = hbm_bytes_sptrsv(info)
-    ms_spmv = lpcg.time_spmv(S, rhs, reps=100)
-    bytes_spmv = hbm_bytes_spmv(info)
-    peak = 8000.0  # GB/s, MI355X HBM3E
-    ach = bytes_trsv / (ms_trsv * 1e-3) / 1e9
-    _log(f"sptrsv fwd {ms_trsv * 1e3:.1f} us ({ach:.1f} GB/s), spmv {ms_spmv * 1e3:.2f} us "
-         f"({bytes_spmv / (ms_spmv * 1e-3) / 1e9:.1f} GB/s)")
+            t_pre, t_solve, iters, relres = [], [], [], []
+            e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+            wall0 = time.perf_counter()
+            for _ in range(args.steps):
+                e0.record()
+                pre()
+                e1.record()
+                res = solve()
+                e2.record()
+                torch.cuda.synchronize()
+                t_pre.append(e0.elapsed_time(e1))
+                t_solve.append(e1.elapsed_time(e2))
+                iters.append(res["iters"])
+                relres.append(res["relres_true"])
+            torch.cuda.synchronize()
+            wall = (time.perf_counter() - wall0) * 1e3 / args.steps
+            key = name if ordering == "natural" else f"{name}_{ordering}"
+            results[key] = dict(ms=float(np.mean(np.array(t_pre) + np.array(t_solve))),
+                                precompute_ms=float(np.mean(t_pre)), solve_ms=float(np.mean(t_solve)),
+                                wall_ms=wall, iters=int(np.max(iters)), relres_true=float(np.max(relres)),
+                                status=res["status"], ordering=ordering,
+                                us_per_iter=float(np.mean(t_solve)) * 1e3 / max(1, int(np.max(iters))))
+            _log(f"{key}: {results[key]}")
+        # kernel timings in this ordering (HIP events around each launch on its stream)
+        lpcg.ic0(S, 0.0, 8, lval, utval)
+        rhs = torch.as_tensor(b.astype(np.float32)).cuda()
+        ms_f = lpcg.time_sptrsv(S, False, lval, utval, rhs, reps=50)
+        ms_b = lpcg.time_sptrsv(S, True, lval, utval, rhs, reps=50)
+        ms_spmv = lpcg.time_spmv(S, rhs, reps=100)
+        bt, bs = hbm_bytes_sptrsv(info), hbm_bytes_spmv(info)
+        kernels[ordering] = dict(
+            levels=info["nlev_fwd"],
+            sptrsv_fwd=dict(us=ms_f * 1e3, bytes=bt, gbs=bt / (ms_f * 1e-3) / 1e9),
+            sptrsv_bwd=dict(us=ms_b * 1e3, bytes=bt, gbs=bt / (ms_b * 1e-3) / 1e9),
+            spmv=dict(us=ms_spmv * 1e3, bytes=bs, gbs=bs / (ms_spmv * 1e-3) / 1e9))
+        _log(f"{ordering} kernels: {kernels[ordering]}")
+        del S
 
     cpu = None
     if not args.no_cpu:
@@ -183,7 +191,12 @@ def main():
         cpu["host"] = platform.processor() or platform.machine()
         cpu["host_cpus"] = os.cpu_count()
 
-    head = "learned" if "learned" in results else "ic0"
+    learned = [k for k in results if k.startswith("learned")]
+    head = min(learned, key=lambda k: results[k]["ms"]) if learned else \
+        min((k for k in results if k.startswith("ic0")), key=lambda k: results[k]["ms"])
+    head_order = results[head]["ordering"]
+    kf = kernels[head_order]["sptrsv_fwd"]
+    ic0_same = "ic0" if head_order == "natural" else f"ic0_{head_order}"
     out = {
         "metric": "time-to-1e-6 rel. residual (ms) + PCG iters: learned-L vs IC(0), 3D 64³",
         "value": results[head]["ms"],
@@ -197,20 +210,20 @@ def main():
         "vs_baseline": None,
         "dtype": "f32 (apply) / f64 (dots, true residual)",
         "data": "synthetic",
-        "config": {"workload": f"3D implicit-Euler heat step, {args.m}^3 grid, 7-point, "
-                               f"n={A.n}, k=exp(GRF sigma=1, ell=0.1), dt=1e-3, b=u0 GRF, tol={args.tol:g}",
-                   "method_of_value": head, "k_seed": args.k_seed, "u0_seed": args.u_seed},
+        "config": {"workload": f"3D implicit-Euler heat step, {args.m}^3 grid, 7-point, n={A.n}, "
+                               f"k=exp(GRF sigma=1, ell=0.1), dt=1e-3, b=u0 GRF, tol={args.tol:g}",
+                   "method_of_value": head, "ordering_of_value": head_order,
+                   "iters_of_value": results[head]["iters"],
+                   "ic0_same_ordering_ms": results.get(ic0_same, {}).get("ms"),
+                   "ic0_same_ordering_iters": results.get(ic0_same, {}).get("iters"),
+                   "k_seed": args.k_seed, "u0_seed": args.u_seed},
         "methods": results,
-        "roofline": {"bound": "hbm", "kernel": "sptrsv_forward", "achieved": ach, "peak": peak,
-                     "unit": "GB/s", "frac": ach / peak, "traffic": None,
-                     "bytes_per_launch": bytes_trsv, "us_per_launch": ms_trsv * 1e3,
-                     "levels": info["nlev_fwd"],
-                     "spmv": {"us_per_launch": ms_spmv * 1e3, "bytes_per_launch": bytes_spmv,
-                              "achieved": bytes_spmv / (ms_spmv * 1e-3) / 1e9}},
+        "roofline": {"bound": "hbm", "kernel": f"sptrsv_forward ({head_order} order)",
+                     "achieved": kf["gbs"], "peak": PEAK_HBM, "unit": "GB/s", "frac": kf["gbs"] / PEAK_HBM,
+                     "traffic": None, "bytes_per_launch": kf["bytes"], "us_per_launch": kf["us"],
+                     "levels": kernels[head_order]["levels"], "kernels": kernels},
         "cpu_baseline": cpu,
     }
-    if learned_note:
-        out["note"] = learned_note
     print(json.dumps(out), flush=True)
 
 

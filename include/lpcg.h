@@ -177,6 +177,37 @@ int lpcg_time_sptrsv(const lpcg_system *sys, int32_t transpose, const float *l_v
 int lpcg_time_spmv(const lpcg_system *sys, const float *x, float *y, int32_t reps,
                    double *ms_out, hipStream_t stream);
 
+/* ------------------------------------------------------------ tuning */
+/* Configuration of one substitution direction.  mode 0: dependency driven
+ * (one launch; rows handed to `waves` waves in level order, each row polls
+ * its dependencies' ready flags, sleeping `backoff` rounds between polls);
+ * mode 1: level synchronous (one launch per level, a few lanes per row, no
+ * polling).  A new system uses mode 1 when the direction has at most 16
+ * levels, mode 0 with 4096 waves and backoff 1 otherwise. */
+typedef struct {
+    int32_t direction;     /* 0: forward (L y = r), 1: backward (L^T z = y) */
+    int32_t mode;          /* 0 dependency driven, 1 level synchronous */
+    int32_t waves;         /* mode 0: waves launched (0 = default) */
+    int32_t backoff;       /* mode 0: sleep rounds between polls (0..64) */
+    double us;             /* lpcg_autotune: mean duration of one solve */
+} lpcg_trsv_cfg;
+
+/* Autotuner: times every candidate configuration of both substitution
+ * directions on this system with the given factor (reps timed runs after
+ * one warm-up, HIP events on `stream`), keeps the fastest per direction for
+ * every later call on the system, and writes up to table_len measured
+ * candidates to table (HOST, may be NULL) and their number to *n_table
+ * (HOST, may be NULL).  Uses the system's work vectors: not concurrent with
+ * a solve on the same system.  Synchronous. */
+int lpcg_autotune(lpcg_system *sys, const float *l_val, const float *ut_val, int32_t reps,
+                  lpcg_trsv_cfg *table, int32_t table_len, int32_t *n_table, hipStream_t stream);
+
+/* Read / force the configuration of one direction (HOST struct; `us` is
+ * ignored).  Errors: EINVAL for an unknown direction, mode or a backoff
+ * outside 0..64. */
+int lpcg_get_trsv_cfg(const lpcg_system *sys, int32_t direction, lpcg_trsv_cfg *out);
+int lpcg_set_trsv_cfg(lpcg_system *sys, const lpcg_trsv_cfg *cfg);
+
 /* ------------------------------------------------------------------ PCG */
 #define LPCG_PC_NONE   0
 #define LPCG_PC_JACOBI 1
@@ -235,8 +266,12 @@ typedef struct {
     int32_t n_mp;
     const float *params;
     int32_t diag_mode;  /* 0: L_ii = sqrt(s) max(softplus(d_ii), 1e-6), L_ij = sqrt(s) (d_ij+d_ji)/2;
-                           1: L' D L'^T with D = diag(A) (technical-details appendix):
-                              L_ii = sqrt(A_ii), L_ij = sqrt(A_jj) (d_ij + d_ji)/2 */
+                           1: L' D L'^T with D = diag(A) (technical-details appendix),
+                              L' unit lower triangular:
+                              L_ii = sqrt(A_ii), L_ij = sqrt(A_jj) (d_ij + d_ji)/2;
+                           2: the same form with a learned positive diagonal of L':
+                              L_ii = sqrt(A_ii) max(softplus(d_ii + ln(e-1)), 1e-6),
+                              L_ij = sqrt(A_jj) (d_ij + d_ji)/2 */
 } lpcg_gnn;
 
 /* Number of FP32 parameters of the layout above. */

@@ -482,12 +482,20 @@ int analyze_impl(const lpcg_csr *A, const int32_t *h_sys, int32_t nsys, lpcg_sys
     ALLOC(s->sys_tmp, 2 * (size_t)nsys);
     s->vec_blocks = std::max(1, std::min(kMaxVecBlocks, nblk(n, kVecThreads * 4)));
     const int chunks = nblk(n, kWave);
-    s->npart = std::max(std::max(kMaxVecBlocks, kMaxSpmvBlocks), chunks);
+    // per-block partials: vector kernels, SpMV, one per 64-row chunk of the
+    // dependency-driven substitution, or one per block of the level launches
+    s->npart = std::max(std::max(kMaxVecBlocks, kMaxSpmvBlocks), chunks + std::max(s->nlev_f, s->nlev_b));
     ALLOC(s->part, 4 * (size_t)s->npart);
     ALLOC(s->scal, S_NSCAL);
     ALLOC(s->ctrl, C_NCTRL);
     LPCG_HIP(hipHostMalloc((void **)&s->h_ctrl, sizeof(int) * C_NCTRL, hipHostMallocDefault));
     LPCG_HIP(hipHostMalloc((void **)&s->h_scal, sizeof(double) * S_NSCAL, hipHostMallocDefault));
+    // substitution defaults: level-synchronous launches when there are few
+    // levels (multicolour orderings), dependency driven otherwise
+    const double lmean = (double)s->nnz_l / n;
+    s->trsv_g = lmean <= 4 ? 4 : lmean <= 8 ? 8 : 16;
+    s->trsv[0].mode = s->nlev_f <= kLevelModeMaxLevels ? 1 : 0;
+    s->trsv[1].mode = s->nlev_b <= kLevelModeMaxLevels ? 1 : 0;
     // SpMV lanes per row from the mean row length
     const double mean = (double)nnz / n;
     s->spmv_group = mean <= 4 ? 4 : mean <= 8 ? 8 : mean <= 16 ? 16 : mean <= 32 ? 32 : 64;

@@ -173,20 +173,61 @@ int spmv64(const lpcg_system *s, const double *x, double *y, hipStream_t st) {
     return launch_spmv<double, double>(s, s->val64, x, y, st);
 }
 
-int sptrsv32(const lpcg_system *s, int transpose, const float *lval, const float *utval,
-             const float *rhs, float *y, int *ticket, hipStream_t st) {
+// Enqueue the kernels of one substitution with configuration c: the
+// dependency-driven kernel expects y preset to kUnset and the ticket zeroed
+// (trsv_presets); the level-synchronous launches need nothing.
+int trsv_kernels(const lpcg_system *s, int transpose, const TrsvCfg &c, const float *lval,
+                 const float *utval, const float *rhs, float *y, int *ticket, hipStream_t st) {
     const int n = s->n;
-    k_fill_u32<<<nblk(n, 256), 256, 0, st>>>(n, (uint32_t *)y, kUnset);
-    k_zero_i32<<<1, 64, 0, st>>>(ticket, 1);
-    const int blocks = nblk(trsv_waves(n), 4);
-    if (transpose)
-        k_sptrsv<true><<<blocks, 256, 0, st>>>(n, s->blev_rows, s->urowptr, s->ucol, utval, rhs,
-                                               (uint32_t *)y, ticket);
-    else
-        k_sptrsv<false><<<blocks, 256, 0, st>>>(n, s->flev_rows, s->lrowptr, s->lcol, lval, rhs,
-                                                (uint32_t *)y, ticket);
+    const bool up = transpose != 0;
+    const int *order = up ? s->blev_rows : s->flev_rows;
+    const int *rp = up ? s->urowptr : s->lrowptr;
+    const int *ci = up ? s->ucol : s->lcol;
+    const float *v = up ? utval : lval;
+    if (c.mode == 0) {
+        const int blocks = nblk(trsv_waves(n, c.waves), 4);
+        if (up)
+            k_sptrsv<true><<<blocks, 256, 0, st>>>(n, order, rp, ci, v, rhs, (uint32_t *)y, ticket, c.backoff);
+        else
+            k_sptrsv<false><<<blocks, 256, 0, st>>>(n, order, rp, ci, v, rhs, (uint32_t *)y, ticket, c.backoff);
+        LPCG_LAUNCH_CHECK();
+        return LPCG_OK;
+    }
+    const std::vector<int> &lp = up ? s->h_blev_ptr : s->h_flev_ptr;
+    for (size_t l = 0; l + 1 < lp.size(); ++l) {
+        const int rows = lp[l + 1] - lp[l];
+        const int nb = level_blocks(rows, s->trsv_g);
+        const int *ord = order + lp[l];
+#define LPCG_LVL(UP, G) k_trsv_level<UP, G><<<nb, 256, 0, st>>>(rows, ord, rp, ci, v, rhs, y)
+        if (up) {
+            if (s->trsv_g == 4) LPCG_LVL(true, 4);
+            else if (s->trsv_g == 8) LPCG_LVL(true, 8);
+            else LPCG_LVL(true, 16);
+        } else {
+            if (s->trsv_g == 4) LPCG_LVL(false, 4);
+            else if (s->trsv_g == 8) LPCG_LVL(false, 8);
+            else LPCG_LVL(false, 16);
+        }
+#undef LPCG_LVL
+    }
     LPCG_LAUNCH_CHECK();
     return LPCG_OK;
+}
+
+int trsv_presets(const lpcg_system *s, const TrsvCfg &c, float *y, int *ticket, hipStream_t st) {
+    if (c.mode != 0) return LPCG_OK;
+    k_fill_u32<<<nblk(s->n, 256), 256, 0, st>>>(s->n, (uint32_t *)y, kUnset);
+    k_zero_i32<<<1, 64, 0, st>>>(ticket, 1);
+    LPCG_LAUNCH_CHECK();
+    return LPCG_OK;
+}
+
+int sptrsv32(const lpcg_system *s, int transpose, const float *lval, const float *utval,
+             const float *rhs, float *y, int *ticket, hipStream_t st) {
+    const TrsvCfg &c = s->trsv[transpose ? 1 : 0];
+    int rc = trsv_presets(s, c, y, ticket, st);
+    if (rc) return rc;
+    return trsv_kernels(s, transpose, c, lval, utval, rhs, y, ticket, st);
 }
 
 }  // namespace lpcg
@@ -311,22 +352,16 @@ extern "C" int lpcg_time_sptrsv(const lpcg_system *s, int32_t transpose, const f
     EventPair ev;
     LPCG_HIP(hipEventCreate(&ev.a));
     LPCG_HIP(hipEventCreate(&ev.b));
-    const int n = s->n;
     int *ticket = s->ctrl + C_TICKET_X;
-    const int blocks = nblk(trsv_waves(n), 4);
+    const TrsvCfg &c = s->trsv[transpose ? 1 : 0];
     double total = 0;
     for (int r = 0; r < reps; ++r) {
-        k_fill_u32<<<nblk(n, 256), 256, 0, st>>>(n, (uint32_t *)y, kUnset);
-        k_zero_i32<<<1, 64, 0, st>>>(ticket, 1);
+        int rc = trsv_presets(s, c, y, ticket, st);
+        if (rc) return rc;
         LPCG_HIP(hipEventRecord(ev.a, st));
-        if (transpose)
-            k_sptrsv<true><<<blocks, 256, 0, st>>>(n, s->blev_rows, s->urowptr, s->ucol, ut_val, rhs,
-                                                   (uint32_t *)y, ticket);
-        else
-            k_sptrsv<false><<<blocks, 256, 0, st>>>(n, s->flev_rows, s->lrowptr, s->lcol, l_val, rhs,
-                                                    (uint32_t *)y, ticket);
+        rc = trsv_kernels(s, transpose, c, l_val, ut_val, rhs, y, ticket, st);
+        if (rc) return rc;
         LPCG_HIP(hipEventRecord(ev.b, st));
-        LPCG_LAUNCH_CHECK();
         LPCG_HIP(hipEventSynchronize(ev.b));
         float ms = 0;
         LPCG_HIP(hipEventElapsedTime(&ms, ev.a, ev.b));
@@ -355,5 +390,102 @@ extern "C" int lpcg_time_spmv(const lpcg_system *s, const float *x, float *y, in
     float ms = 0;
     LPCG_HIP(hipEventElapsedTime(&ms, ev.a, ev.b));
     *ms_out = (double)ms / reps;
+    return LPCG_OK;
+}
+
+extern "C" int lpcg_get_trsv_cfg(const lpcg_system *s, int32_t direction, lpcg_trsv_cfg *out) {
+    if (!s || !out || direction < 0 || direction > 1) {
+        set_error("lpcg_get_trsv_cfg: invalid arguments");
+        return LPCG_EINVAL;
+    }
+    const TrsvCfg &c = s->trsv[direction];
+    out->direction = direction;
+    out->mode = c.mode;
+    out->waves = c.mode == 0 ? trsv_waves(s->n, c.waves) : 0;
+    out->backoff = c.backoff;
+    out->us = 0;
+    return LPCG_OK;
+}
+
+extern "C" int lpcg_set_trsv_cfg(lpcg_system *s, const lpcg_trsv_cfg *cfg) {
+    if (!s || !cfg || cfg->direction < 0 || cfg->direction > 1 || cfg->mode < 0 || cfg->mode > 1 ||
+        cfg->waves < 0 || cfg->backoff < 0 || cfg->backoff > 64) {
+        set_error("lpcg_set_trsv_cfg: invalid configuration");
+        return LPCG_EINVAL;
+    }
+    TrsvCfg &c = s->trsv[cfg->direction];
+    c.mode = cfg->mode;
+    c.waves = cfg->waves;
+    c.backoff = cfg->backoff;
+    if (s->graph_exec) {  // the cached PCG graph launches the old kernels
+        hipGraphExecDestroy(s->graph_exec);
+        s->graph_exec = nullptr;
+        s->graph_key.clear();
+    }
+    return LPCG_OK;
+}
+
+extern "C" int lpcg_autotune(lpcg_system *s, const float *l_val, const float *ut_val, int32_t reps,
+                             lpcg_trsv_cfg *table, int32_t table_len, int32_t *n_table, hipStream_t st) {
+    if (!s || !l_val || !ut_val || reps <= 0 || (table_len > 0 && !table)) {
+        set_error("lpcg_autotune: invalid arguments");
+        return LPCG_EINVAL;
+    }
+    EventPair ev;
+    LPCG_HIP(hipEventCreate(&ev.a));
+    LPCG_HIP(hipEventCreate(&ev.b));
+    // right-hand side of ones in p, result in w (PCG work vectors)
+    k_fill_u32<<<nblk(s->n, 256), 256, 0, st>>>(s->n, (uint32_t *)s->p, 0x3f800000u);
+    LPCG_LAUNCH_CHECK();
+    int *ticket = s->ctrl + C_TICKET_X;
+    int count = 0;
+    for (int dir = 0; dir < 2; ++dir) {
+        const int nlev = dir ? s->nlev_b : s->nlev_f;
+        std::vector<TrsvCfg> cands;
+        if (nlev <= kLevelModeTuneLevels) cands.push_back(TrsvCfg{1, 0, 1});
+        for (int w : {256, 512, 1024, 2048, 4096})
+            for (int bo : {1, 4, 16}) {
+                if (w > trsv_waves(s->n, 1 << 30) && w != 256) continue;  // more waves than chunks
+                cands.push_back(TrsvCfg{0, w, bo});
+            }
+        double best = 1e30;
+        TrsvCfg best_c = s->trsv[dir];
+        for (const TrsvCfg &c : cands) {
+            double tot = 0;
+            for (int r = 0; r <= reps; ++r) {  // first run warms up
+                int rc = trsv_presets(s, c, s->w, ticket, st);
+                if (rc) return rc;
+                LPCG_HIP(hipEventRecord(ev.a, st));
+                rc = trsv_kernels(s, dir, c, l_val, ut_val, s->p, s->w, ticket, st);
+                if (rc) return rc;
+                LPCG_HIP(hipEventRecord(ev.b, st));
+                LPCG_HIP(hipEventSynchronize(ev.b));
+                float ms = 0;
+                LPCG_HIP(hipEventElapsedTime(&ms, ev.a, ev.b));
+                if (r > 0) tot += ms;
+            }
+            const double us = 1e3 * tot / reps;
+            if (count < table_len) {
+                lpcg_trsv_cfg &e = table[count];
+                e.direction = dir;
+                e.mode = c.mode;
+                e.waves = c.mode == 0 ? trsv_waves(s->n, c.waves) : 0;
+                e.backoff = c.backoff;
+                e.us = us;
+            }
+            ++count;
+            if (us < best) {
+                best = us;
+                best_c = c;
+            }
+        }
+        s->trsv[dir] = best_c;
+    }
+    if (n_table) *n_table = count;
+    if (s->graph_exec) {
+        hipGraphExecDestroy(s->graph_exec);
+        s->graph_exec = nullptr;
+        s->graph_key.clear();
+    }
     return LPCG_OK;
 }

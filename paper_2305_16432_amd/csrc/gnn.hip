@@ -399,6 +399,9 @@ __global__ void __launch_bounds__(kGnnThreads) k_edge(int nnz, const int *__rest
     }
 }
 
+// softplus(kDiagShift) = 1: the learned diagonal of L' starts at 1 (mode 2).
+constexpr float kDiagShift = 0.54132485461291810f;  // ln(e - 1)
+
 __device__ __forceinline__ float softplus_f(float x) { return x > 20.f ? x : log1pf(expf(x)); }
 
 // L value of the lower-pattern entry with A-position k.
@@ -412,7 +415,10 @@ __device__ __forceinline__ float l_entry(int k, int mode, const int *__restrict_
         if (j == i) return sq * fmaxf(softplus_f(d[k]), 1e-6f);
         return sq * 0.5f * (d[k] + d[rev[k]]);
     }
-    if (j == i) return (float)sqrt(diag64[i]);
+    if (j == i) {
+        const float sa = (float)sqrt(diag64[i]);
+        return mode == 1 ? sa : sa * fmaxf(softplus_f(d[k] + kDiagShift), 1e-6f);
+    }
     return (float)sqrt(diag64[j]) * (0.5f * (d[k] + d[rev[k]]));
 }
 
@@ -474,8 +480,8 @@ int forward_impl(const lpcg_system *s, const lpcg_gnn *net, const double *b, uns
 
 int check_net(const lpcg_gnn *net) {
     if (!net || !net->params || (net->h != 32 && net->h != 64) || net->n_mp < 1 || net->n_mp > kMaxMp ||
-        (net->diag_mode != 0 && net->diag_mode != 1)) {
-        set_error("gnn: h must be 32 or 64, 1 <= n_mp <= %d, diag_mode 0 or 1", kMaxMp);
+        net->diag_mode < 0 || net->diag_mode > 2) {
+        set_error("gnn: h must be 32 or 64, 1 <= n_mp <= %d, diag_mode 0, 1 or 2", kMaxMp);
         return LPCG_EINVAL;
     }
     return LPCG_OK;
@@ -547,7 +553,8 @@ namespace {
 __device__ __forceinline__ float sigmoid_f(float x) { return 1.f / (1.f + expf(-x)); }
 
 // d loss / d d_k from d loss / d L (pair average; softplus diagonal and sqrt(s)
-// in mode 0; fixed diagonal and sqrt(A_jj) column scale in mode 1).
+// in mode 0; sqrt(A_jj) column scale with a fixed diagonal in mode 1 or the
+// shifted-softplus diagonal in mode 2).
 __global__ void k_assemble_bwd(int nnz, int mode, const int *__restrict__ rowptr, const int *__restrict__ lrowptr,
                                const int *__restrict__ erow, const int *__restrict__ col,
                                const int *__restrict__ rev, const int *__restrict__ row_sys,
@@ -562,6 +569,9 @@ __global__ void k_assemble_bwd(int nnz, int mode, const int *__restrict__ rowptr
         if (mode == 0) {
             const float sq = (float)sqrt(sys_s[row_sys[i]]);
             g = softplus_f(d[k]) > 1e-6f ? sq * gl[p] * sigmoid_f(d[k]) : 0.f;
+        } else if (mode == 2) {
+            const float ds = d[k] + kDiagShift;
+            g = softplus_f(ds) > 1e-6f ? (float)sqrt(diag64[i]) * gl[p] * sigmoid_f(ds) : 0.f;
         } else {
             g = 0.f;
         }

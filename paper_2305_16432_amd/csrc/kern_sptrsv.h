@@ -35,7 +35,7 @@ template <bool UPPER>
 __device__ __forceinline__ int trsv_chunk(int n, int base, const int *__restrict__ order,
                                           const int *__restrict__ rp, const int *__restrict__ ci,
                                           const float *__restrict__ v, const float *__restrict__ rhs,
-                                          uint32_t *ybits, float &yout) {
+                                          uint32_t *ybits, float &yout, int backoff) {
     const int pos = base + lane_id();
     int row = -1, k = 0, kend = 0;
     float acc = 0.f, dg = 1.f;
@@ -108,7 +108,10 @@ __device__ __forceinline__ int trsv_chunk(int n, int base, const int *__restrict
                 pending = false;
             }
         }
-        if (pending) __builtin_amdgcn_s_sleep(1);
+        // back off between polling rounds (fewer polls in flight shorten
+        // the latency of the stores being waited for)
+        if (pending)
+            for (int t = 0; t < backoff; ++t) __builtin_amdgcn_s_sleep(1);
     }
     return row;
 }
@@ -118,13 +121,56 @@ __global__ void __launch_bounds__(256) k_sptrsv(int n, const int *__restrict__ o
                                                 const int *__restrict__ rp, const int *__restrict__ ci,
                                                 const float *__restrict__ v,
                                                 const float *__restrict__ rhs, uint32_t *ybits,
-                                                int *ticket) {
+                                                int *ticket, int backoff) {
     for (;;) {
         const int chunk = wave_ticket(ticket);
         if ((long)chunk * kWave >= n) break;
         float yv;
-        trsv_chunk<UPPER>(n, chunk * kWave, order, rp, ci, v, rhs, ybits, yv);
+        trsv_chunk<UPPER>(n, chunk * kWave, order, rp, ci, v, rhs, ybits, yv, backoff);
     }
+}
+
+// ---------------------------------------------------------------------------
+// Level-synchronous substitution: one launch per level (launch order is the
+// only synchronisation, so loads and stores are plain).  G lanes share a row;
+// the rows of a level are order[0 .. rows).  Returns the row's solution in
+// lane sub == 0 of its group.  Accumulation: G strided partial sums combined
+// by a shuffle tree (fixed order, bit-reproducible for a given G).
+template <bool UPPER, int G>
+__device__ __forceinline__ float trsv_level_row(int row, int sub, const int *__restrict__ rp,
+                                                const int *__restrict__ ci, const float *__restrict__ v,
+                                                const float *__restrict__ rhs, const float *__restrict__ y) {
+    const int a = rp[row], b = rp[row + 1];
+    const int k0 = UPPER ? a + 1 : a, k1 = UPPER ? b : b - 1;
+    float acc = 0.f;
+    for (int k = k0 + sub; k < k1; k += G) acc += v[k] * y[ci[k]];
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, G);
+    return (rhs[row] - acc) / v[UPPER ? a : b - 1];
+}
+
+template <bool UPPER, int G>
+__global__ void __launch_bounds__(256) k_trsv_level(int rows, const int *__restrict__ order,
+                                                    const int *__restrict__ rp, const int *__restrict__ ci,
+                                                    const float *__restrict__ v, const float *__restrict__ rhs,
+                                                    float *__restrict__ y) {
+    const int sub = threadIdx.x % G;
+    constexpr int per = 256 / G;
+    for (int idx = blockIdx.x * per + threadIdx.x / G; idx < rows; idx += gridDim.x * per) {
+        const int row = order[idx];
+        const float yv = trsv_level_row<UPPER, G>(row, sub, rp, ci, v, rhs, y);
+        if (sub == 0) y[row] = yv;
+    }
+}
+
+// Blocks of one level launch: enough for the level's rows, at most one per
+// 64 rows (so the per-block partial sums of a whole solve number at most
+// chunks + levels).
+inline int level_blocks(int rows, int G) {
+    const int per = 256 / G;
+    const int want = (rows + per - 1) / per;
+    const int cap = (rows + 63) / 64;
+    return want < cap ? want : cap;
 }
 
 static __global__ void k_fill_u32(int n, uint32_t *p, uint32_t v) {
@@ -132,11 +178,12 @@ static __global__ void k_fill_u32(int n, uint32_t *p, uint32_t v) {
     if (i < n) p[i] = v;
 }
 
-// Number of waves for a dependency-driven launch: enough to keep every CU
-// busy, never more than there are chunks.
-inline int trsv_waves(int n) {
+// Number of waves for a dependency-driven launch: the requested count (0:
+// 4096), never more than there are chunks.
+inline int trsv_waves(int n, int want = 0) {
     const int chunks = (n + kWave - 1) / kWave;
-    return chunks < 4096 ? chunks : 4096;
+    const int w = want > 0 ? want : 4096;
+    return chunks < w ? chunks : w;
 }
 
 }  // namespace lpcg

@@ -19,6 +19,10 @@ int hip_fail(hipError_t e, const char *what, const char *file, int line);
 constexpr int kVecThreads = 256;
 constexpr int kMaxVecBlocks = 1024;
 constexpr int kMaxSpmvBlocks = 2048;
+// Default substitution mode: level-synchronous up to this many levels.
+constexpr int kLevelModeMaxLevels = 16;
+// The autotuner tries level-synchronous launches up to this many levels.
+constexpr int kLevelModeTuneLevels = 1024;
 
 // Layout of the small control words and FP64 scalars of a PCG solve.
 enum Ctrl : int {
@@ -41,6 +45,13 @@ enum Scal : int {
     S_BETA = 5,
     S_TRUE = 6,      // ||b - A x||^2 (FP64 true residual)
     S_NSCAL = 16
+};
+
+// Configuration of one substitution direction: mode 0 = dependency driven
+// (one launch; `waves` waves, `backoff` sleep rounds between polls), mode 1 =
+// level synchronous (one launch per level, `g` lanes per row).
+struct TrsvCfg {
+    int mode = 0, waves = 0, backoff = 1;
 };
 
 }  // namespace lpcg
@@ -81,6 +92,8 @@ struct lpcg_system {
     int vec_blocks = 1;          // grid of the fixed-grid vector kernels
     int spmv_blocks = 1;         // grid of the fused SpMV + p.w kernel
     int spmv_group = 8;          // lanes per row in SpMV
+    lpcg::TrsvCfg trsv[2];       // forward (L) and backward (L^T) substitution
+    int trsv_g = 8;              // lanes per row of the level-synchronous kernel
     // cached iteration-chunk graph of the last PCG solve (captured on a
     // private stream, launched on the caller's)
     hipStream_t cap_stream = nullptr;

@@ -44,7 +44,8 @@ namespace {
 constexpr int VT = kVecThreads;
 
 struct Args {
-    int n, np_vec, np_spmv, np_chunk, maxit, kind;
+    int n, np_vec, np_spmv, np_chunk, np_rz, maxit, kind;
+    int backoff_f, backoff_b;
     const int *rp, *ci;
     const float *v32;
     const double *v64;
@@ -153,7 +154,7 @@ __global__ void __launch_bounds__(256) k_llt_fwd(Args a) {
         const int chunk = wave_ticket(ticket);
         if ((long)chunk * kWave >= a.n) break;
         float yv;
-        trsv_chunk<false>(a.n, chunk * kWave, a.forder, a.lrp, a.lci, a.lval, a.r, a.y, yv);
+        trsv_chunk<false>(a.n, chunk * kWave, a.forder, a.lrp, a.lci, a.lval, a.r, a.y, yv, a.backoff_f);
     }
 }
 
@@ -165,11 +166,51 @@ __global__ void __launch_bounds__(256) k_llt_bwd(Args a) {
         if ((long)chunk * kWave >= a.n) break;
         float zv = 0.f;
         const int row = trsv_chunk<true>(a.n, chunk * kWave, a.border, a.urp, a.uci, a.utval,
-                                         (const float *)a.y, a.z, zv);
+                                         (const float *)a.y, a.z, zv, a.backoff_b);
         double rz = row >= 0 ? (double)a.r[row] * (double)zv : 0.0;
         rz = wave_sum(rz);
         a.part_rz[chunk] = rz;  // every lane stores the same wave total
     }
+}
+
+// Level-synchronous forms of the two substitutions: one launch per level
+// (rows a.forder/a.border[lev0 .. lev0 + rows)).  The first forward launch
+// also takes the convergence test; every backward launch writes one r.z
+// partial per block at part_rz[part0 + block].
+template <int G>
+__global__ void __launch_bounds__(256) k_llt_fwd_level(Args a, int lev0, int rows, int first) {
+    __shared__ double lds[VT / kWave];
+    if (is_done(a)) return;
+    if (first && converged_or_capped(a, lds)) return;
+    const int sub = threadIdx.x % G;
+    constexpr int per = 256 / G;
+    float *y = (float *)a.y;
+    for (int idx = blockIdx.x * per + threadIdx.x / G; idx < rows; idx += gridDim.x * per) {
+        const int row = a.forder[lev0 + idx];
+        const float yv = trsv_level_row<false, G>(row, sub, a.lrp, a.lci, a.lval, a.r, y);
+        if (sub == 0) y[row] = yv;
+    }
+}
+
+template <int G>
+__global__ void __launch_bounds__(256) k_llt_bwd_level(Args a, int lev0, int rows, int part0) {
+    __shared__ double lds[VT / kWave];
+    if (is_done(a)) return;
+    const int sub = threadIdx.x % G;
+    constexpr int per = 256 / G;
+    const float *y = (const float *)a.y;
+    float *z = (float *)a.z;
+    double rz = 0;
+    for (int idx = blockIdx.x * per + threadIdx.x / G; idx < rows; idx += gridDim.x * per) {
+        const int row = a.border[lev0 + idx];
+        const float zv = trsv_level_row<true, G>(row, sub, a.urp, a.uci, a.utval, y, z);
+        if (sub == 0) {
+            z[row] = zv;
+            rz += (double)a.r[row] * (double)zv;
+        }
+    }
+    rz = block_sum<VT>(rz, lds);
+    if (threadIdx.x == 0) a.part_rz[part0 + blockIdx.x] = rz;
 }
 
 // Single block: r.z total, beta.  Reads the previous r.z before replacing it.
@@ -196,7 +237,7 @@ __global__ void __launch_bounds__(1024) k_rz(Args a) {
         }
         if (conv || cap || bad) return;
     }
-    const int np = KIND == LPCG_PC_LLT ? a.np_chunk : a.np_vec;
+    const int np = KIND == LPCG_PC_LLT ? a.np_rz : a.np_vec;
     const double rz = reduce_partials<1024>(a.part_rz, np, lds);
     if (threadIdx.x == 0) {
         const int it = a.ctrl[C_IT];
@@ -314,9 +355,31 @@ int enqueue_iteration(const lpcg_system *s, const Args &a, hipStream_t st) {
     const int vb = s->vec_blocks;
     const int sb = s->spmv_blocks;
     if (KIND == LPCG_PC_LLT) {
-        const int tb = (trsv_waves(s->n) + 3) / 4;
-        k_llt_fwd<<<tb, 256, 0, st>>>(a);
-        k_llt_bwd<<<tb, 256, 0, st>>>(a);
+        const int G = s->trsv_g;
+        if (s->trsv[0].mode == 0) {
+            k_llt_fwd<<<(trsv_waves(s->n, s->trsv[0].waves) + 3) / 4, 256, 0, st>>>(a);
+        } else {
+            const std::vector<int> &lp = s->h_flev_ptr;
+            for (size_t l = 0; l + 1 < lp.size(); ++l) {
+                const int rows = lp[l + 1] - lp[l], nb = level_blocks(rows, G), first = l == 0;
+                if (G == 4) k_llt_fwd_level<4><<<nb, 256, 0, st>>>(a, lp[l], rows, first);
+                else if (G == 8) k_llt_fwd_level<8><<<nb, 256, 0, st>>>(a, lp[l], rows, first);
+                else k_llt_fwd_level<16><<<nb, 256, 0, st>>>(a, lp[l], rows, first);
+            }
+        }
+        if (s->trsv[1].mode == 0) {
+            k_llt_bwd<<<(trsv_waves(s->n, s->trsv[1].waves) + 3) / 4, 256, 0, st>>>(a);
+        } else {
+            const std::vector<int> &lp = s->h_blev_ptr;
+            int part0 = 0;
+            for (size_t l = 0; l + 1 < lp.size(); ++l) {
+                const int rows = lp[l + 1] - lp[l], nb = level_blocks(rows, G);
+                if (G == 4) k_llt_bwd_level<4><<<nb, 256, 0, st>>>(a, lp[l], rows, part0);
+                else if (G == 8) k_llt_bwd_level<8><<<nb, 256, 0, st>>>(a, lp[l], rows, part0);
+                else k_llt_bwd_level<16><<<nb, 256, 0, st>>>(a, lp[l], rows, part0);
+                part0 += nb;
+            }
+        }
     }
     k_rz<KIND><<<1, 1024, 0, st>>>(a);
     k_pupd<KIND><<<vb, VT, 0, st>>>(a);
@@ -343,9 +406,10 @@ int run_solve(lpcg_system *s, const Args &a, const lpcg_solve_opts &o, int &iter
     hipGraphExec_t exec = nullptr;
     if (o.use_graph) {
         // key: kernel arguments + preconditioner kind + chunk length
-        std::vector<unsigned char> key(sizeof(Args) + 2 * sizeof(int));
+        std::vector<unsigned char> key(sizeof(Args) + 9 * sizeof(int));
         memcpy(key.data(), &a, sizeof(Args));
-        const int extra[2] = {KIND, chunk};
+        const int extra[9] = {KIND, chunk, s->trsv[0].mode, s->trsv[0].waves, s->trsv[0].backoff,
+                              s->trsv[1].mode, s->trsv[1].waves, s->trsv[1].backoff, s->trsv_g};
         memcpy(key.data() + sizeof(Args), extra, sizeof(extra));
         if (s->graph_exec && s->graph_key == key) {
             exec = s->graph_exec;
@@ -425,6 +489,15 @@ extern "C" int lpcg_pcg_solve(lpcg_system *s, const lpcg_precond *P, const doubl
     a.np_vec = s->vec_blocks;
     a.np_spmv = s->spmv_blocks;
     a.np_chunk = (s->n + kWave - 1) / kWave;
+    a.backoff_f = s->trsv[0].backoff;
+    a.backoff_b = s->trsv[1].backoff;
+    if (s->trsv[1].mode == 0) {
+        a.np_rz = a.np_chunk;
+    } else {
+        a.np_rz = 0;
+        for (size_t l = 0; l + 1 < s->h_blev_ptr.size(); ++l)
+            a.np_rz += level_blocks(s->h_blev_ptr[l + 1] - s->h_blev_ptr[l], s->trsv_g);
+    }
     a.maxit = opts->maxit > 0 ? opts->maxit : s->n;
     a.kind = P->kind;
     a.rp = s->rowptr;

@@ -55,6 +55,11 @@ class _Result(C.Structure):
                 ("reserved", C.c_int32), ("relres_rec", C.c_double), ("relres_true", C.c_double)]
 
 
+class _TrsvCfg(C.Structure):
+    _fields_ = [("direction", C.c_int32), ("mode", C.c_int32), ("waves", C.c_int32),
+                ("backoff", C.c_int32), ("us", C.c_double)]
+
+
 class _Gnn(C.Structure):
     _fields_ = [("h", C.c_int32), ("n_mp", C.c_int32), ("params", C.c_void_p), ("diag_mode", C.c_int32)]
 
@@ -189,6 +194,29 @@ def export_perm(sys: System):
     out = torch.empty(sys.info["n"], dtype=torch.int32, device="cuda")
     _check(lib().lpcg_export_perm(sys.handle, _ptr(out), _stream()), "lpcg_export_perm")
     return out
+
+
+# ------------------------------------------------------------------ tuning
+def autotune(sys: System, l_val, ut_val, reps: int = 5) -> list:
+    """Time every substitution configuration, keep the fastest per
+    direction; returns the measured table as a list of dicts."""
+    table = (_TrsvCfg * 64)()
+    n = C.c_int32(0)
+    rc = lib().lpcg_autotune(sys.handle, _ptr(l_val), _ptr(ut_val), C.c_int32(reps), table, C.c_int32(64),
+                             C.byref(n), _stream())
+    _check(rc, "lpcg_autotune")
+    return [{f: getattr(table[i], f) for f, _ in _TrsvCfg._fields_} for i in range(min(n.value, 64))]
+
+
+def get_trsv_cfg(sys: System, direction: int) -> dict:
+    c = _TrsvCfg()
+    _check(lib().lpcg_get_trsv_cfg(sys.handle, C.c_int32(direction), C.byref(c)), "lpcg_get_trsv_cfg")
+    return {f: getattr(c, f) for f, _ in _TrsvCfg._fields_ if f != "us"}
+
+
+def set_trsv_cfg(sys: System, direction: int, mode: int, waves: int = 0, backoff: int = 1):
+    c = _TrsvCfg(direction, mode, waves, backoff, 0.0)
+    _check(lib().lpcg_set_trsv_cfg(sys.handle, C.byref(c)), "lpcg_set_trsv_cfg")
 
 
 # ---------------------------------------------------------- building blocks

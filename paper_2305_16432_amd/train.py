@@ -3,12 +3,14 @@ hand-written backward, data loss and Adam kernels (paper: loss_Ab, Adam at
 lr 1e-3; training-setup appendix).
 
 Data: implicit-Euler heat steps on an m^3 grid (7-point, k = exp(GRF sigma=1,
-ell=0.1), dt = 1e-3, b = u0 a smooth GRF), k seeds 0..nsys-1 and u0 seeds
+ell=0.1), dt = 1e-3, b = u0 a smooth GRF; --rhs white/mix use white-noise
+right-hand sides for all/every other system), k seeds 0..nsys-1 and u0 seeds
 10000+seed; the solution x of each system (the third member of the paper's
 (A, x, b) training tuples) comes from SciPy's CG to a 1e-12 relative
 residual.  Every system shares one sparsity pattern, so a batch of B
 systems is one block-diagonal pattern analysed once; each step swaps in the
-batch's values.  Held-out check: PCG iterations to 1e-6 with the predicted
+batch's values.  --ordering color trains for the multicolour row ordering
+(the factor then lives on tril(P A P^T)).  Held-out check: PCG iterations to 1e-6 with the predicted
 L on a 64^3 system with unseen seeds, every eval_every steps; the weights
 with the fewest held-out iterations are kept (early stop on held-out).
 
@@ -31,19 +33,21 @@ if ROOT not in sys.path:
 
 
 def _make(args):
-    m, seed = args
+    m, seed, rhs = args
     import scipy.sparse.linalg as spla
     from threadpoolctl import threadpool_limits
 
     import pdegen as g
-    A, b = g.heat_system_3d(m, 1e-3, k_seed=seed, u0_seed=10000 + seed)
+    if rhs == "mix":  # alternate smooth and white right-hand sides
+        rhs = "grf" if seed % 2 == 0 else "white"
+    A, b = g.heat_system_3d(m, 1e-3, k_seed=seed, u0_seed=10000 + seed, rhs=rhs)
     with threadpool_limits(1):  # one BLAS thread per worker process
         x, info = spla.cg(A.to_scipy(), b, rtol=1e-12, maxiter=20 * A.n)
     assert info == 0
     return A.val.astype(np.float64), b, x
 
 
-def make_dataset(m: int, nsys: int, workers: int):
+def make_dataset(m: int, nsys: int, workers: int, rhs: str = "grf"):
     import pdegen as g
     A0, _ = g.heat_system_3d(m, 1e-3, k_seed=0, u0_seed=10000)
     out = []
@@ -51,7 +55,7 @@ def make_dataset(m: int, nsys: int, workers: int):
     # the BLAS thread pools limited so workers do not oversubscribe the cores
     from threadpoolctl import threadpool_limits
     with threadpool_limits(1), mp.get_context("fork").Pool(workers) as pool:
-        for i, o in enumerate(pool.imap(_make, [(m, s) for s in range(nsys)], chunksize=2)):
+        for i, o in enumerate(pool.imap(_make, [(m, s, rhs) for s in range(nsys)], chunksize=2)):
             out.append(o)
             if (i + 1) % 50 == 0:
                 print(f"[train] generated {i + 1}/{nsys} systems", flush=True)
@@ -71,6 +75,9 @@ def main():
     ap.add_argument("--n-mp", type=int, default=3)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--diag-mode", type=int, default=1)
+    ap.add_argument("--ordering", choices=["natural", "color"], default="natural")
+    ap.add_argument("--rhs", choices=["grf", "white", "mix"], default="grf",
+                    help="training right-hand sides: smooth GRF states, white noise, or both")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--eval-every", type=int, default=100)
     ap.add_argument("--eval-m", type=int, default=64)
@@ -79,7 +86,7 @@ def main():
     args = ap.parse_args()
     print(f"[train] generating {args.nsys} systems of {args.m}^3 on {args.workers} workers", flush=True)
     t0 = time.time()
-    A0, vals, bs, xs = make_dataset(args.m, args.nsys, args.workers)
+    A0, vals, bs, xs = make_dataset(args.m, args.nsys, args.workers, args.rhs)
     print(f"[train] dataset {args.nsys} x n={A0.n} in {time.time() - t0:.1f}s", flush=True)
 
     import torch
@@ -87,16 +94,17 @@ def main():
     import pdegen as g
     from paper_2305_16432_amd import lpcg
     print("[train] torch imported", flush=True)
+    order = lpcg.ORDER_COLOR if args.ordering == "color" else lpcg.ORDER_NATURAL
     B, srp = g.block_diag_csr([A0] * args.batch)
     S = lpcg.analyze(torch.as_tensor(B.rowptr).cuda(), torch.as_tensor(B.colind).cuda(),
-                     torch.as_tensor(B.val).cuda(), srp)
+                     torch.as_tensor(B.val).cuda(), srp, order)
     dv = torch.as_tensor(vals).cuda()
     db = torch.as_tensor(bs).cuda()
     dx = torch.as_tensor(xs).cuda()
     h, n_mp = args.h, args.n_mp
     dm = args.diag_mode
     P0 = g.init_gnn_params(h, n_mp, seed=args.seed, gain=1.0)
-    if dm == 1:  # decoder output layer zero: L' = I, i.e. training starts at Jacobi
+    if dm in (1, 2):  # decoder output layer zero: L' = I, i.e. training starts at Jacobi
         P0["dec.W1"][:] = 0.0
         P0["dec.b1"][:] = 0.0
     params = lpcg.pack_params(P0, h, n_mp).cuda()
@@ -106,7 +114,7 @@ def main():
     # held-out evaluation system (unseen seeds, full size)
     Ae, be = g.heat_system_3d(args.eval_m, 1e-3, k_seed=5000, u0_seed=6000)
     Se = lpcg.analyze(torch.as_tensor(Ae.rowptr).cuda(), torch.as_tensor(Ae.colind).cuda(),
-                      torch.as_tensor(Ae.val).cuda())
+                      torch.as_tensor(Ae.val).cuda(), None, order)
     bed = torch.as_tensor(be).cuda()
     wse = lpcg.gnn_workspace(Se, h, n_mp)
     nl = Se.info["nnz_l"]
@@ -115,7 +123,7 @@ def main():
     lic, uic, _ = lpcg.ic0(Se)
     _, ric = lpcg.pcg_solve(Se, lpcg.PC_LLT, bed, l_val=lic, ut_val=uic, tol=1e-6, maxit=2000)
     _, rj = lpcg.pcg_solve(Se, lpcg.PC_JACOBI, bed, tol=1e-6, maxit=2000)
-    print(f"[train] held-out 64^3: IC(0) {ric['iters']} its, Jacobi {rj['iters']} its", flush=True)
+    print(f"[train] held-out 64^3 ({args.ordering} order, {Se.info['nlev_fwd']} levels): IC(0) {ric['iters']} its, Jacobi {rj['iters']} its", flush=True)
 
     def evaluate():
         lpcg.gnn_predict_L(Se, params, h, n_mp, bed, wse, le, ue, diag_mode=dm)
@@ -149,7 +157,8 @@ def main():
                   f"(best {best[0]} @ {best[1]}) {time.time() - t0:.1f}s", flush=True)
     del nb
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
-    np.savez(args.out, params=best[2].cpu().numpy(), h=h, n_mp=n_mp, diag_mode=dm, best_step=best[1],
+    np.savez(args.out, params=best[2].cpu().numpy(), h=h, n_mp=n_mp, diag_mode=dm, ordering=order,
+             best_step=best[1],
              best_iters=best[0], log=json.dumps(log), config=json.dumps(vars(args)))
     print(f"[train] saved {args.out}: best held-out iters {best[0]} at step {best[1]} "
           f"(IC(0) {ric['iters']}, Jacobi {rj['iters']})", flush=True)

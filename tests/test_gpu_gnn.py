@@ -60,7 +60,7 @@ def _blockwise_ref(A, b, P, h, n_mp, srp, pat, diag_mode=0):
     return out
 
 
-@pytest.mark.parametrize("diag_mode", [0, 1])
+@pytest.mark.parametrize("diag_mode", [0, 1, 2])
 @pytest.mark.parametrize("h,n_mp", [(32, 3), (64, 2)])
 @pytest.mark.parametrize("name", ["poisson2d_32", "heat3d_13", "fem_40", "random_777", "tridiag_1000",
                                   "one"])
@@ -71,7 +71,7 @@ def test_gnn_forward_parity(name, h, n_mp, diag_mode):
     _check(A, b, h, n_mp, seed=5, diag_mode=diag_mode)
 
 
-@pytest.mark.parametrize("diag_mode", [0, 1])
+@pytest.mark.parametrize("diag_mode", [0, 1, 2])
 def test_gnn_forward_batch_per_system_normalisation(diag_mode):
     mats = [g.poisson_grid(9, 2), g.heat_system_3d(6, 1e-3, 1, 2)[0], g.fem_p1_delaunay(13, 0, 1)[0]]
     B, srp = g.block_diag_csr(mats)
@@ -80,7 +80,7 @@ def test_gnn_forward_batch_per_system_normalisation(diag_mode):
     _check(B, b, 32, 3, seed=7, sys_rowptr=srp, diag_mode=diag_mode)
 
 
-@pytest.mark.parametrize("diag_mode", [0, 1])
+@pytest.mark.parametrize("diag_mode", [0, 1, 2])
 def test_gnn_forward_c3_full_size(diag_mode):
     print(f"[gnn] heat3d_64 h=32 n_mp=3 diag_mode={diag_mode}", flush=True)
     A, b = g.heat_system_3d(64, 1e-3, 1000, 2000)

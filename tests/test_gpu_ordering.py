@@ -142,7 +142,7 @@ def test_color_pcg_c3_full_size():
     assert abs(res["iters"] - ro["iters"]) <= max(2, 0.1 * ro["iters"])
 
 
-@pytest.mark.parametrize("diag_mode", [0, 1])
+@pytest.mark.parametrize("diag_mode", [0, 1, 2])
 def test_color_gnn_and_loss(diag_mode):
     A = matrices_small()["fem_40"]
     b = np.random.default_rng(5).standard_normal(A.n)

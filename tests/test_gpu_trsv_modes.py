@@ -1,0 +1,114 @@
+"""Both substitution modes (dependency driven with several wave counts and
+back-offs; level synchronous) in both row orderings, against the oracle, and
+the autotuner that chooses between them.
+
+Bars: componentwise backward error |rhs - T y| <= 4 k u32 |T| |y| for the
+solves (Higham's substitution bound in FP32, c = 4 covering FMA and the
+division); PCG iterations within max(2, 10%) of the FP64 oracle's and the
+FP64 true residual <= tol."""
+import numpy as np
+import pytest
+
+import oracle as O
+import pdegen as g
+from paper_2305_16432_amd import lpcg
+from tests.gpu_util import U32, cuda_f32, cuda_f64, gpu_system, host, matrices_small
+
+pytestmark = pytest.mark.gpu
+
+CFGS = [(0, 256, 4), (0, 4096, 1), (0, 1024, 16), (1, 0, 1)]
+
+
+def _lower(pat, seed):
+    rng = np.random.default_rng(seed)
+    lv = rng.uniform(-0.3, 0.3, pat.nnz_l)
+    row = np.repeat(np.arange(len(pat.lrowptr) - 1), np.diff(pat.lrowptr))
+    d = pat.lcol == row
+    lv[d] = rng.uniform(1.0, 2.0, d.sum())
+    return lv.astype(np.float32).astype(np.float64)
+
+
+@pytest.mark.parametrize("cfg", CFGS)
+@pytest.mark.parametrize("ordering", [0, 1])
+@pytest.mark.parametrize("name", ["tridiag_1000", "heat3d_13", "fem_40", "random_777", "one"])
+def test_sptrsv_modes(name, ordering, cfg):
+    mode, waves, backoff = cfg
+    print(f"[trsv] {name} ordering {ordering} cfg {cfg}", flush=True)
+    A = matrices_small()[name]
+    if ordering:
+        perm, _, _ = O.color_order(A)
+        Ai = O.permute_sym(A, perm)
+    else:
+        perm, Ai = np.arange(A.n), A
+    pat = O.Pattern(Ai)
+    S = gpu_system(A, None, ordering)
+    for d in (0, 1):
+        lpcg.set_trsv_cfg(S, d, mode, waves, backoff)
+        assert lpcg.get_trsv_cfg(S, d)["mode"] == mode
+    lval = _lower(pat, 3)
+    utv = lval[pat.usrc]
+    rhs = np.random.default_rng(4).standard_normal(A.n).astype(np.float32).astype(np.float64)
+    L = g.CSR(A.n, pat.lrowptr, pat.lcol, lval).to_scipy()
+    k = max(1, np.diff(pat.lrowptr).max())
+    # vectors in the caller's numbering; the factor acts on the internal order
+    y = host(lpcg.sptrsv(S, False, cuda_f32(lval), cuda_f32(utv), cuda_f32(rhs))).astype(np.float64)[perm]
+    z = host(lpcg.sptrsv(S, True, cuda_f32(lval), cuda_f32(utv), cuda_f32(rhs))).astype(np.float64)[perm]
+    r = rhs[perm]
+    assert np.all(np.abs(r - L @ y) <= 4 * k * U32 * (abs(L) @ np.abs(y)) + 1e-30)
+    assert np.all(np.abs(r - L.T @ z) <= 4 * k * U32 * (abs(L.T) @ np.abs(z)) + 1e-30)
+    np.testing.assert_allclose(y, O.trsv_lower(pat, lval, r), rtol=1e-3, atol=1e-5 * np.abs(y).max())
+    np.testing.assert_allclose(z, O.trsv_upper(pat, lval, r), rtol=1e-3, atol=1e-5 * np.abs(z).max())
+
+
+@pytest.mark.parametrize("cfg", CFGS)
+@pytest.mark.parametrize("ordering", [0, 1])
+@pytest.mark.parametrize("name", ["heat3d_13", "fem_40"])
+def test_pcg_ic0_modes(name, ordering, cfg):
+    A = matrices_small()[name]
+    b = np.random.default_rng(2).standard_normal(A.n)
+    if ordering:
+        perm, _, _ = O.color_order(A)
+        Ai = O.permute_sym(A, perm)
+    else:
+        perm, Ai = np.arange(A.n), A
+    pat = O.Pattern(Ai)
+    S = gpu_system(A, None, ordering)
+    for d in (0, 1):
+        lpcg.set_trsv_cfg(S, d, *cfg)
+    l, ut, _ = lpcg.ic0(S)
+    for use_graph in (False, True):
+        x, res = lpcg.pcg_solve(S, lpcg.PC_LLT, cuda_f64(b), l_val=l, ut_val=ut, tol=1e-6, max_restarts=2,
+                                use_graph=use_graph)
+        lref, _ = O.ic0(pat, Ai)
+        ro = O.pcg(Ai, b[perm], O.PC_LLT, pat, lref, tol=1e-6)
+        assert res["status"] == 0 and O.true_relres(A, b, host(x)) <= 1e-6
+        assert abs(res["iters"] - ro["iters"]) <= max(2, 0.1 * ro["iters"]), (res["iters"], ro["iters"])
+
+
+@pytest.mark.parametrize("ordering", [0, 1])
+def test_autotune_c3_full_size(ordering):
+    print(f"[autotune] heat3d_64 ordering {ordering}", flush=True)
+    A, b = g.heat_system_3d(64, 1e-3, 1000, 2000)
+    S = gpu_system(A, None, ordering)
+    l, ut, _ = lpcg.ic0(S)
+    table = lpcg.autotune(S, l, ut, reps=3)
+    assert len(table) >= 2
+    for d in (0, 1):
+        rows = [t for t in table if t["direction"] == d]
+        best = min(rows, key=lambda t: t["us"])
+        got = lpcg.get_trsv_cfg(S, d)
+        assert got["mode"] == best["mode"] and got["backoff"] == best["backoff"]
+        if best["mode"] == 0:
+            assert got["waves"] == best["waves"]
+        for t in sorted(rows, key=lambda t: t["us"])[:6]:
+            print(f"  dir {d} mode {t['mode']} waves {t['waves']} backoff {t['backoff']}: {t['us']:.1f} us")
+    x, res = lpcg.pcg_solve(S, lpcg.PC_LLT, cuda_f64(b), l_val=l, ut_val=ut, tol=1e-6, max_restarts=2)
+    assert res["status"] == 0 and O.true_relres(A, b, host(x)) <= 1e-6
+
+
+def test_trsv_cfg_rejects_bad_values():
+    S = gpu_system(g.poisson_grid(5, 2))
+    for bad in [(2, 0, 0, 1), (0, 3, 0, 1), (0, 0, 0, 65)]:
+        with pytest.raises(lpcg.LpcgError) as e:
+            lpcg.set_trsv_cfg(S, *bad)
+        assert e.value.code == lpcg.EINVAL

@@ -6,14 +6,17 @@ import numpy as np
 
 import pdegen as g
 
-WEIGHTS = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
-                       "paper_2305_16432_amd", "weights", "heat3d_h32_mp3.npz")
+import pytest
+
+WDIR = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2305_16432_amd",
+                    "weights")
 
 
-def test_weights_file_layout():
-    W = np.load(WEIGHTS)  # allow_pickle stays False
+@pytest.mark.parametrize("fname,ordering", [("heat3d_h32_mp3.npz", 0), ("heat3d_h32_mp3_color.npz", 1)])
+def test_weights_file_layout(fname, ordering):
+    W = np.load(os.path.join(WDIR, fname))  # allow_pickle stays False
     h, n_mp, dm = int(W["h"]), int(W["n_mp"]), int(W["diag_mode"])
-    assert (h, n_mp, dm) == (32, 3, 1)
+    assert (h, n_mp, dm, int(W["ordering"])) == (32, 3, 1, ordering)
     n = sum(int(np.prod(s)) for _, s in g.gnn_param_shapes(h, n_mp))
     assert W["params"].shape == (n,) and np.all(np.isfinite(W["params"]))
     log = json.loads(str(W["log"]))
