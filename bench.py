@@ -127,6 +127,13 @@ def main():
             x.zero_()
             return lpcg.pcg_solve(S, lpcg.PC_JACOBI, bd, x=x, dinv=dinv, **solve_kw)[1]
 
+        # per-pattern tuning of the substitution kernels (like the analysis,
+        # done once per sparsity pattern, outside the timed region)
+        lpcg.ic0(S, 0.0, 8, lval, utval)
+        tune = lpcg.autotune(S, lval, utval, reps=3)
+        cfg = [lpcg.get_trsv_cfg(S, d) for d in (0, 1)]
+        _log(f"{ordering}: substitution configuration {cfg} ({len(tune)} candidates timed)")
+
         methods = {"ic0": (run_ic0, solve_llt)}
         if ordering == "natural":
             methods["jacobi"] = (run_jacobi, solve_jacobi)  # the same preconditioner in any order
@@ -177,7 +184,7 @@ def main():
         ms_spmv = lpcg.time_spmv(S, rhs, reps=100)
         bt, bs = hbm_bytes_sptrsv(info), hbm_bytes_spmv(info)
         kernels[ordering] = dict(
-            levels=info["nlev_fwd"],
+            levels=info["nlev_fwd"], trsv_cfg=cfg,
             sptrsv_fwd=dict(us=ms_f * 1e3, bytes=bt, gbs=bt / (ms_f * 1e-3) / 1e9),
             sptrsv_bwd=dict(us=ms_b * 1e3, bytes=bt, gbs=bt / (ms_b * 1e-3) / 1e9),
             spmv=dict(us=ms_spmv * 1e3, bytes=bs, gbs=bs / (ms_spmv * 1e-3) / 1e9))

@@ -304,6 +304,11 @@ __global__ void k_values(int nnz, int n, const double *__restrict__ v64, const i
 
 int nblk(long n, int t) { return (int)((n + t - 1) / t); }
 
+__global__ void k_fill_part(long n, uint64_t *p) {
+    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = kPartUnset;
+}
+
 template <typename T>
 int dalloc(lpcg_system *s, T **p, size_t count) {
     void *q = nullptr;
@@ -472,6 +477,7 @@ int analyze_impl(const lpcg_csr *A, const int32_t *h_sys, int32_t nsys, lpcg_sys
     ALLOC(s->diag64, n);
     ALLOC(s->r, n);
     ALLOC(s->p, n);
+    ALLOC(s->p2, n);
     ALLOC(s->w, n);
     ALLOC(s->z, n);
     ALLOC(s->y, n);
@@ -480,12 +486,14 @@ int analyze_impl(const lpcg_csr *A, const int32_t *h_sys, int32_t nsys, lpcg_sys
     ALLOC(s->t64b, n);
     ALLOC(s->t64c, n);
     ALLOC(s->sys_tmp, 2 * (size_t)nsys);
-    s->vec_blocks = std::max(1, std::min(kMaxVecBlocks, nblk(n, kVecThreads * 4)));
+    s->vec_blocks = std::max(1, std::min(kMaxVecBlocks, nblk(n, kVecThreads)));
     const int chunks = nblk(n, kWave);
     // per-block partials: vector kernels, SpMV, one per 64-row chunk of the
     // dependency-driven substitution, or one per block of the level launches
     s->npart = std::max(std::max(kMaxVecBlocks, kMaxSpmvBlocks), chunks + std::max(s->nlev_f, s->nlev_b));
     ALLOC(s->part, 4 * (size_t)s->npart);
+    ALLOC(s->sync_part, 4 * (size_t)s->npart);
+    k_fill_part<<<nblk(4L * s->npart, 256), 256, 0, st>>>(4L * s->npart, (uint64_t *)s->sync_part);
     ALLOC(s->scal, S_NSCAL);
     ALLOC(s->ctrl, C_NCTRL);
     LPCG_HIP(hipHostMalloc((void **)&s->h_ctrl, sizeof(int) * C_NCTRL, hipHostMallocDefault));

@@ -34,6 +34,23 @@ __device__ __forceinline__ uint32_t publishable(float v) {
     return (v != v) ? kCanonNan : b;
 }
 
+// FP64 partial sums handed from every block to the block that finishes last
+// follow the same rule: the slot is preset to kPartUnset, the value is stored
+// with one agent-scope atomic store and is its own ready flag.
+constexpr uint64_t kPartUnset = 0x7ff4000000000badull;  // signalling-NaN payload, never computed
+constexpr uint64_t kCanonNan64 = 0x7ff8000000000000ull;
+
+__device__ __forceinline__ uint64_t ld_agent_u64(const uint64_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_agent_u64(uint64_t *p, uint64_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void publish_partial(double *part, int i, double v) {
+    const uint64_t b = (v != v) ? kCanonNan64 : (uint64_t)__double_as_longlong(v);
+    st_agent_u64(reinterpret_cast<uint64_t *>(part) + i, b);
+}
+
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
 
 // Next work item of a wave from a shared counter, as a wave-uniform (scalar)
@@ -70,6 +87,48 @@ __device__ __forceinline__ T block_sum(T v, T *lds) {
 #pragma unroll
     for (int i = 0; i < BS / kWave; ++i) s += lds[i];
     return s;
+}
+
+// Sum of np published partials in a fixed order (result in all threads);
+// waits for each slot to be published and rearms it with kPartUnset.  Each
+// thread issues the loads of up to kPubBatch of its slots at once and
+// re-polls only the ones still unset, so the wait costs about one memory
+// round trip rather than one per slot.
+constexpr int kPubBatch = 16;
+template <int BS>
+__device__ __forceinline__ double reduce_published(double *part, int np, double *lds) {
+    uint64_t *q = reinterpret_cast<uint64_t *>(part);
+    double s = 0.0;
+    for (int base = 0; base < np; base += BS * kPubBatch) {
+        uint64_t v[kPubBatch];
+#pragma unroll
+        for (int t = 0; t < kPubBatch; ++t) {
+            const int i = base + t * BS + (int)threadIdx.x;
+            v[t] = i < np ? ld_agent_u64(q + i) : 0ull;
+        }
+        for (;;) {
+            bool pending = false;
+#pragma unroll
+            for (int t = 0; t < kPubBatch; ++t) {
+                const int i = base + t * BS + (int)threadIdx.x;
+                if (i < np && v[t] == kPartUnset) {
+                    v[t] = ld_agent_u64(q + i);
+                    pending = pending || v[t] == kPartUnset;
+                }
+            }
+            if (!pending) break;
+            __builtin_amdgcn_s_sleep(1);
+        }
+#pragma unroll
+        for (int t = 0; t < kPubBatch; ++t) {
+            const int i = base + t * BS + (int)threadIdx.x;
+            if (i < np) {
+                s += __longlong_as_double((long long)v[t]);
+                st_agent_u64(q + i, kPartUnset);
+            }
+        }
+    }
+    return block_sum<BS>(s, lds);
 }
 
 // Deterministic reduction of np partial sums (fixed order), result in all

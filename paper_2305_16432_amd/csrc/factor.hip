@@ -443,9 +443,9 @@ extern "C" int lpcg_autotune(lpcg_system *s, const float *l_val, const float *ut
         const int nlev = dir ? s->nlev_b : s->nlev_f;
         std::vector<TrsvCfg> cands;
         if (nlev <= kLevelModeTuneLevels) cands.push_back(TrsvCfg{1, 0, 1});
-        for (int w : {256, 512, 1024, 2048, 4096})
-            for (int bo : {1, 4, 16}) {
-                if (w > trsv_waves(s->n, 1 << 30) && w != 256) continue;  // more waves than chunks
+        for (int w : {64, 128, 256, 512, 1024, 2048, 4096})
+            for (int bo : {1, 4, 16, 64}) {
+                if (w > trsv_waves(s->n, 1 << 30) && w != 64) continue;  // more waves than chunks
                 cands.push_back(TrsvCfg{0, w, bo});
             }
         double best = 1e30;

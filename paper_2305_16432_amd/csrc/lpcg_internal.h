@@ -44,6 +44,7 @@ enum Scal : int {
     S_TOL2 = 4,      // tol^2
     S_BETA = 5,
     S_TRUE = 6,      // ||b - A x||^2 (FP64 true residual)
+    S_ALPHA = 7,     // alpha of the current iteration
     S_NSCAL = 16
 };
 
@@ -81,10 +82,13 @@ struct lpcg_system {
     double *diag64 = nullptr;
     // solver work vectors (device)
     float *r = nullptr, *p = nullptr, *w = nullptr, *z = nullptr, *y = nullptr, *dinv = nullptr;
+    float *p2 = nullptr;  // second search-direction buffer (p alternates by iteration parity)
     double *t64a = nullptr, *t64b = nullptr, *t64c = nullptr;  // FP64 work vectors (loss)
     double *sys_tmp = nullptr;                                  // [2 * nsys] per-system scalars
     double *part = nullptr;      // partial sums (3 x max(kMaxVecBlocks, chunks))
     int npart = 0;               // stride between the partial arrays
+    double *sync_part = nullptr; // 4 x npart published partials (slots preset to kPartUnset):
+                                 // backward r.z, SpMV p.w, update ||r||^2 and r.z
     double *scal = nullptr;      // FP64 scalars (Scal)
     int *ctrl = nullptr;         // control words (Ctrl)
     int *h_ctrl = nullptr;       // pinned host mirror of ctrl

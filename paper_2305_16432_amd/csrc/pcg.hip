@@ -1,32 +1,35 @@
 // PCG (Appendix algorithm "PCG") on the GPU.
 //
-//   r0 = b - A x0;  z0 = P^-1 r0;  p1 = z0;  then for k = 1, 2, ...:
-//   w = A p_k;  alpha = r.z / p.w;  x += alpha p;  r -= alpha w;
-//   stop if ||r|| <= tol ||b||;  z = P^-1 r;  beta = r.z(new) / r.z(old);
-//   p = z + beta p.
+//   r0 = b - A x0;  z0 = P^-1 r0;  then for k = 1, 2, ...:
+//   p_k = z_{k-1} + beta p_{k-1} (p_1 = z_0);  w = A p_k;  alpha = r.z / p.w;
+//   x += alpha p;  r -= alpha w;  stop if ||r|| <= tol ||b||;  z = P^-1 r;
+//   beta = r.z(new) / r.z(old).
 //
 // Precision: A's values, r, p, w, z in FP32; x, b and every dot product /
 // norm in FP64; the final true residual ||b - A x|| in FP64 (FP64 values).
-// P = L L^T is applied by the dependency-driven substitutions of
-// kern_sptrsv.h; Jacobi and no preconditioning fuse z into the vector
-// kernels.
 //
 // Control: the iteration state lives on the device (ctrl words, FP64
 // scalars).  Each kernel returns at once when the done flag is set, so the
 // host enqueues chunks of iterations (optionally as a captured hipGraph) and
-// reads the flag only between chunks.  Dot products are reduced in a fixed
-// order (per-block partials, then a fixed tree), so runs are bit-reproducible.
+// reads the flag only between chunks.  Every dot product is reduced in a
+// fixed order: every block publishes its partial (an agent-scope atomic store
+// into a slot preset to a sentinel, so the value is its own ready flag), and
+// the block of highest index waits for the slots, sums them in index order and
+// computes the scalar the next kernel needs: runs are bit-reproducible, no
+// launch is spent on a reduction, and neither an arrival counter (device-scope
+// atomics on one address serialise) nor a cache-flushing fence is needed.
 //
-// Kernels of one LLT iteration (it = products A p so far):
-//   k_llt_fwd  : convergence test on ||r||^2 partials, then y = L^-1 r
-//   k_llt_bwd  : z = L^-T y, partial r.z per 64-row chunk
-//   k_rz       : r.z total, beta (single block)
-//   k_pupd     : p = z + beta p, reset y
-//   k_spmv_pw  : w = A p, partial p.w, it += 1
-//   k_xr       : alpha, breakdown test, x += alpha p, r -= alpha w, ||r||^2
-//                partials, reset z and the tickets
-// Jacobi / none:  k_rz (convergence test, r.z, beta; single block),
-//   k_pupd (z = dinv r on the fly), k_spmv_pw, k_xr (+ r.z partials).
+// Kernels of one iteration (it = products A p so far):
+//   LLT:    fwd   y = L^-1 r                       (kern_sptrsv.h, either mode)
+//           bwd   z = L^-T y, r.z partials; reducer block: beta
+//   all:    spmv  p = z + beta p_prev (p double-buffered by the parity of
+//                 it), w = A p computed from z and p_prev on the fly, p.w
+//                 partials; reducer block: alpha, breakdown test, it += 1
+//           xr    x += alpha p, r -= alpha w, ||r||^2 (Jacobi/none: r.z)
+//                 partials, presets of the dependency-driven substitution;
+//                 reducer block: convergence test (Jacobi/none: beta)
+// Jacobi and none form z = dinv r / r on the fly, so an iteration is two
+// launches; LLT adds the substitutions.
 #include <algorithm>
 #include <cstring>
 
@@ -44,8 +47,8 @@ namespace {
 constexpr int VT = kVecThreads;
 
 struct Args {
-    int n, np_vec, np_spmv, np_chunk, np_rz, maxit, kind;
-    int backoff_f, backoff_b;
+    int n, np_vec, np_rz, maxit, kind;
+    int backoff_f, backoff_b, reset_y, reset_z;
     const int *rp, *ci;
     const float *v32;
     const double *v64;
@@ -53,17 +56,19 @@ struct Args {
     const float *lval, *utval, *dinv;
     const double *b;
     double *x;
-    float *r, *p, *w;
+    float *r, *p0, *p1, *w;
     uint32_t *y, *z;
-    double *part_rr, *part_rz, *part_pw, *part_bb;
+    double *part_rr, *part_rz, *part_pw, *part_bb;  // plain partials (setup, true residual)
+    double *sp_rz, *sp_pw, *sp_rr, *sp_rz2;          // published partials (reducer-block sums)
     double *scal, *hist;
     int *ctrl;
     double tol2;
 };
 
-// The done flag can be raised by block 0 while other blocks of the same
-// launch run; one thread reads it for the whole block so that every wave of a
-// block takes the same branch around the block barriers that follow.
+// The done flag is only raised by an earlier launch or by the reducer block
+// after every other block of the launch has published (and so has read the
+// flag), so every block of a launch sees the same value; one thread
+// reads it so that the block branches uniformly around its barriers.
 __device__ __forceinline__ bool is_done(const Args &a) {
     __shared__ int flag;
     if (threadIdx.x == 0) flag = a.ctrl[C_DONE];
@@ -71,29 +76,29 @@ __device__ __forceinline__ bool is_done(const Args &a) {
     return flag != 0;
 }
 
-// Convergence test on the ||r||^2 partials; every calling block reaches the
-// same decision (same partials, same order).  Block 0 records the outcome.
-__device__ bool converged_or_capped(const Args &a, double *lds) {
-    const double rr = reduce_partials<VT>(a.part_rr, a.np_vec, lds);
+// The block of highest index reduces: after publishing its own partial it
+// sums every published slot (reduce_published waits for each to become
+// visible).  Only that block waits, and it waits on blocks that never wait on
+// it, so the wait always ends; no counter or fence is needed.
+__device__ __forceinline__ bool is_reducer() { return blockIdx.x == gridDim.x - 1; }
+
+// Convergence bookkeeping after ||r||^2 (thread 0 of the deciding block).
+__device__ __forceinline__ void record_residual(const Args &a, double rr, int it) {
     const double bb = a.scal[S_BB];
-    const int it = a.ctrl[C_IT];
     const bool conv = !(rr > a.tol2 * bb);
     const bool cap = !conv && it >= a.maxit;
     const bool bad = !isfinite(rr);
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        if (a.hist && it <= a.maxit) a.hist[it] = sqrt(rr / bb);
-        if (conv || cap || bad) {
-            a.ctrl[C_DONE] = 1;
-            a.ctrl[C_STATUS] = conv ? LPCG_OK : bad ? LPCG_EBREAKDOWN : LPCG_ENOTCONV;
-            a.ctrl[C_ITERS] = it;
-            a.scal[S_RR] = rr;
-        }
+    if (a.hist && it <= a.maxit) a.hist[it] = sqrt(rr / bb);
+    a.scal[S_RR] = rr;
+    if (conv || cap || bad) {
+        a.ctrl[C_DONE] = 1;
+        a.ctrl[C_STATUS] = conv ? LPCG_OK : bad ? LPCG_EBREAKDOWN : LPCG_ENOTCONV;
+        a.ctrl[C_ITERS] = it;
     }
-    return conv || cap || bad;
 }
 
 // r = b - A x (FP64 product, FP32 r), ||b||^2, ||r||^2 and (Jacobi/none) r.z
-// partials; presets y, z for the substitutions.
+// partials; presets y, z for dependency-driven substitutions.
 template <int KIND>
 __global__ void __launch_bounds__(VT) k_setup(Args a) {
     __shared__ double lds[VT / kWave];
@@ -123,15 +128,18 @@ __global__ void __launch_bounds__(VT) k_setup(Args a) {
     }
 }
 
-// Single block: control words, ||b||^2, first convergence test.
+// Single block: control words, ||b||^2, first convergence test; for
+// Jacobi/none the first r.z and beta = 0.
+template <int KIND>
 __global__ void __launch_bounds__(VT) k_setup_scal(Args a) {
     __shared__ double lds[VT / kWave];
     const double bb0 = reduce_partials<VT>(a.part_bb, a.np_vec, lds);
     const double rr = reduce_partials<VT>(a.part_rr, a.np_vec, lds);
+    const double rz = KIND != LPCG_PC_LLT ? reduce_partials<VT>(a.part_rz, a.np_vec, lds) : 0.0;
     if (threadIdx.x == 0) {
         const double bb = bb0 > 0 ? bb0 : 1.0;
         a.scal[S_BB] = bb;
-        a.scal[S_RZ0] = 0;
+        a.scal[S_RZ0] = rz;
         a.scal[S_BETA] = 0;
         a.scal[S_RR] = rr;
         a.ctrl[C_IT] = 0;
@@ -145,10 +153,19 @@ __global__ void __launch_bounds__(VT) k_setup_scal(Args a) {
     }
 }
 
+// beta from the r.z partials (reducer block of the backward substitution).
+__device__ __forceinline__ void finish_rz(const Args &a, double *lds) {
+    const double rz = reduce_published<VT>(a.sp_rz, a.np_rz, lds);
+    if (threadIdx.x == 0) {
+        const int it = a.ctrl[C_IT];
+        const double old = a.scal[S_RZ0];
+        a.scal[S_BETA] = it == 0 ? 0.0 : rz / old;
+        a.scal[S_RZ0] = rz;
+    }
+}
+
 __global__ void __launch_bounds__(256) k_llt_fwd(Args a) {
-    __shared__ double lds[VT / kWave];
     if (is_done(a)) return;
-    if (converged_or_capped(a, lds)) return;
     int *ticket = a.ctrl + C_TICKET_F;
     for (;;) {
         const int chunk = wave_ticket(ticket);
@@ -159,6 +176,7 @@ __global__ void __launch_bounds__(256) k_llt_fwd(Args a) {
 }
 
 __global__ void __launch_bounds__(256) k_llt_bwd(Args a) {
+    __shared__ double lds[VT / kWave];
     if (is_done(a)) return;
     int *ticket = a.ctrl + C_TICKET_B;
     for (;;) {
@@ -169,19 +187,18 @@ __global__ void __launch_bounds__(256) k_llt_bwd(Args a) {
                                          (const float *)a.y, a.z, zv, a.backoff_b);
         double rz = row >= 0 ? (double)a.r[row] * (double)zv : 0.0;
         rz = wave_sum(rz);
-        a.part_rz[chunk] = rz;  // every lane stores the same wave total
+        if (lane_id() == 0) publish_partial(a.sp_rz, chunk, rz);
     }
+    if (is_reducer()) finish_rz(a, lds);
 }
 
 // Level-synchronous forms of the two substitutions: one launch per level
-// (rows a.forder/a.border[lev0 .. lev0 + rows)).  The first forward launch
-// also takes the convergence test; every backward launch writes one r.z
-// partial per block at part_rz[part0 + block].
+// (rows a.forder/a.border[lev0 .. lev0 + rows)).  Every backward launch
+// writes one r.z partial per block at part_rz[part0 + block]; the last
+// backward launch (last = 1) also finishes beta.
 template <int G>
-__global__ void __launch_bounds__(256) k_llt_fwd_level(Args a, int lev0, int rows, int first) {
-    __shared__ double lds[VT / kWave];
+__global__ void __launch_bounds__(256) k_llt_fwd_level(Args a, int lev0, int rows) {
     if (is_done(a)) return;
-    if (first && converged_or_capped(a, lds)) return;
     const int sub = threadIdx.x % G;
     constexpr int per = 256 / G;
     float *y = (float *)a.y;
@@ -193,7 +210,7 @@ __global__ void __launch_bounds__(256) k_llt_fwd_level(Args a, int lev0, int row
 }
 
 template <int G>
-__global__ void __launch_bounds__(256) k_llt_bwd_level(Args a, int lev0, int rows, int part0) {
+__global__ void __launch_bounds__(256) k_llt_bwd_level(Args a, int lev0, int rows, int part0, int last) {
     __shared__ double lds[VT / kWave];
     if (is_done(a)) return;
     const int sub = threadIdx.x % G;
@@ -210,120 +227,105 @@ __global__ void __launch_bounds__(256) k_llt_bwd_level(Args a, int lev0, int row
         }
     }
     rz = block_sum<VT>(rz, lds);
-    if (threadIdx.x == 0) a.part_rz[part0 + blockIdx.x] = rz;
+    if (threadIdx.x == 0) publish_partial(a.sp_rz, part0 + blockIdx.x, rz);
+    if (last && is_reducer()) finish_rz(a, lds);
 }
 
-// Single block: r.z total, beta.  Reads the previous r.z before replacing it.
+// Entry j of the new search direction p = z + beta p_prev (p = z in the first
+// iteration), with z formed on the fly for Jacobi / no preconditioning.
 template <int KIND>
-__global__ void __launch_bounds__(1024) k_rz(Args a) {
-    __shared__ double lds[1024 / kWave];
-    if (is_done(a)) return;
-    if (KIND != LPCG_PC_LLT) {
-        // convergence test lives here for the fused preconditioners
-        const double rr = reduce_partials<1024>(a.part_rr, a.np_vec, lds);
-        const double bb = a.scal[S_BB];
-        const int it = a.ctrl[C_IT];
-        const bool conv = !(rr > a.tol2 * bb);
-        const bool cap = !conv && it >= a.maxit;
-        const bool bad = !isfinite(rr);
-        if (threadIdx.x == 0) {
-            if (a.hist && it <= a.maxit) a.hist[it] = sqrt(rr / bb);
-            if (conv || cap || bad) {
-                a.ctrl[C_DONE] = 1;
-                a.ctrl[C_STATUS] = conv ? LPCG_OK : bad ? LPCG_EBREAKDOWN : LPCG_ENOTCONV;
-                a.ctrl[C_ITERS] = it;
-                a.scal[S_RR] = rr;
-            }
-        }
-        if (conv || cap || bad) return;
-    }
-    const int np = KIND == LPCG_PC_LLT ? a.np_rz : a.np_vec;
-    const double rz = reduce_partials<1024>(a.part_rz, np, lds);
-    if (threadIdx.x == 0) {
-        const int it = a.ctrl[C_IT];
-        const double old = a.scal[S_RZ0];
-        a.scal[S_BETA] = it == 0 ? 0.0 : rz / old;
-        a.scal[S_RZ0] = rz;
-    }
+__device__ __forceinline__ float pdir(const Args &a, int j, bool first, float beta, const float *__restrict__ pp) {
+    float zj;
+    if (KIND == LPCG_PC_LLT) zj = __uint_as_float(a.z[j]);
+    else if (KIND == LPCG_PC_JACOBI) zj = a.dinv[j] * a.r[j];
+    else zj = a.r[j];
+    return first ? zj : __fmaf_rn(beta, pp[j], zj);
 }
 
-// p = z + beta p; z from the substitution (LLT) or dinv * r / r.
-template <int KIND>
-__global__ void __launch_bounds__(VT) k_pupd(Args a) {
-    if (is_done(a)) return;
-    const float beta = (float)a.scal[S_BETA];
-    const bool first = a.ctrl[C_IT] == 0;  // p_1 = z_0 exactly (p holds garbage)
-    for (int i = blockIdx.x * VT + threadIdx.x; i < a.n; i += gridDim.x * VT) {
-        float zi;
-        if (KIND == LPCG_PC_LLT) {
-            zi = __uint_as_float(a.z[i]);
-            a.y[i] = kUnset;
-        } else if (KIND == LPCG_PC_JACOBI) {
-            zi = a.dinv[i] * a.r[i];
-        } else {
-            zi = a.r[i];
-        }
-        a.p[i] = first ? zi : zi + beta * a.p[i];
-    }
-}
-
-// w = A p and partial p.w; block 0 counts the product.
-template <int G>
+// p = z + beta p_prev, w = A p and p.w partials; the reducer block computes
+// alpha (breakdown when p.w <= 0 or non-finite) and counts the product.
+template <int G, int KIND>
 __global__ void __launch_bounds__(VT) k_spmv_pw(Args a) {
     __shared__ double lds[VT / kWave];
     if (is_done(a)) return;
+    const int it = a.ctrl[C_IT];
+    const bool first = it == 0;
+    const float beta = (float)a.scal[S_BETA];
+    float *pn = (it & 1) ? a.p1 : a.p0;
+    const float *pp = (it & 1) ? a.p0 : a.p1;
     const int sub = threadIdx.x % G;
     const int rows_per_pass = gridDim.x * (VT / G);
     double pw = 0;
     for (int row = blockIdx.x * (VT / G) + threadIdx.x / G; row < a.n; row += rows_per_pass) {
-        const float s = row_dot<G, float>(a.rp[row], a.rp[row + 1], sub, a.ci, a.v32, a.p);
+        float acc = 0.f;
+        for (int k = a.rp[row] + sub; k < a.rp[row + 1]; k += G)
+            acc += a.v32[k] * pdir<KIND>(a, a.ci[k], first, beta, pp);
+#pragma unroll
+        for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, G);
         if (sub == 0) {
-            a.w[row] = s;
-            pw += (double)a.p[row] * (double)s;
+            const float pi = pdir<KIND>(a, row, first, beta, pp);
+            pn[row] = pi;
+            a.w[row] = acc;
+            pw += (double)pi * (double)acc;
         }
     }
     pw = block_sum<VT>(pw, lds);
+    if (threadIdx.x == 0) publish_partial(a.sp_pw, blockIdx.x, pw);
+    if (!is_reducer()) return;
+    const double pwt = reduce_published<VT>(a.sp_pw, gridDim.x, lds);
     if (threadIdx.x == 0) {
-        a.part_pw[blockIdx.x] = pw;
-        if (blockIdx.x == 0) a.ctrl[C_IT] = a.ctrl[C_IT] + 1;
+        const double rz = a.scal[S_RZ0];
+        a.ctrl[C_IT] = it + 1;
+        if (!(pwt > 0.0) || !isfinite(pwt) || !isfinite(rz)) {
+            a.ctrl[C_DONE] = 1;
+            a.ctrl[C_STATUS] = LPCG_EBREAKDOWN;
+            a.ctrl[C_ITERS] = it + 1;
+        } else {
+            a.scal[S_ALPHA] = rz / pwt;
+        }
     }
 }
 
-// alpha = r.z / p.w (every block reduces the same partials), breakdown test,
-// x += alpha p, r -= alpha w, ||r||^2 (and r.z for Jacobi/none) partials.
+// x += alpha p, r -= alpha w, ||r||^2 (Jacobi/none: r.z) partials, presets
+// for the dependency-driven substitutions; the reducer block takes the
+// convergence test (Jacobi/none: and beta) and rearms the tickets.
 template <int KIND>
 __global__ void __launch_bounds__(VT) k_xr(Args a) {
     __shared__ double lds[VT / kWave];
     if (is_done(a)) return;
-    const double pw = reduce_partials<VT>(a.part_pw, a.np_spmv, lds);
-    const double rz = a.scal[S_RZ0];
-    if (!(pw > 0.0) || !isfinite(pw) || !isfinite(rz)) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
-            a.ctrl[C_DONE] = 1;
-            a.ctrl[C_STATUS] = LPCG_EBREAKDOWN;
-            a.ctrl[C_ITERS] = a.ctrl[C_IT];
-        }
-        return;
-    }
-    const double alpha = rz / pw;
+    const int it = a.ctrl[C_IT];
+    const float *p = ((it - 1) & 1) ? a.p1 : a.p0;
+    const double alpha = a.scal[S_ALPHA];
     const float af = (float)alpha;
     double rr = 0, rzn = 0;
     for (int i = blockIdx.x * VT + threadIdx.x; i < a.n; i += gridDim.x * VT) {
-        const float pi = a.p[i];
-        a.x[i] += alpha * (double)pi;
+        a.x[i] += alpha * (double)p[i];
         const float ri = a.r[i] - af * a.w[i];
         a.r[i] = ri;
         rr += (double)ri * ri;
         if (KIND == LPCG_PC_JACOBI) rzn += (double)ri * ri * a.dinv[i];
         if (KIND == LPCG_PC_NONE) rzn += (double)ri * ri;
-        if (KIND == LPCG_PC_LLT) a.z[i] = kUnset;
+        if (KIND == LPCG_PC_LLT) {
+            if (a.reset_y) a.y[i] = kUnset;
+            if (a.reset_z) a.z[i] = kUnset;
+        }
     }
     rr = block_sum<VT>(rr, lds);
     if (KIND != LPCG_PC_LLT) rzn = block_sum<VT>(rzn, lds);
     if (threadIdx.x == 0) {
-        a.part_rr[blockIdx.x] = rr;
-        if (KIND != LPCG_PC_LLT) a.part_rz[blockIdx.x] = rzn;
-        if (blockIdx.x == 0) {
+        publish_partial(a.sp_rr, blockIdx.x, rr);
+        if (KIND != LPCG_PC_LLT) publish_partial(a.sp_rz2, blockIdx.x, rzn);
+    }
+    if (!is_reducer()) return;
+    const double rrt = reduce_published<VT>(a.sp_rr, gridDim.x, lds);
+    const double rzt = KIND != LPCG_PC_LLT ? reduce_published<VT>(a.sp_rz2, gridDim.x, lds) : 0.0;
+    if (threadIdx.x == 0) {
+        record_residual(a, rrt, it);
+        if (KIND != LPCG_PC_LLT) {
+            const double old = a.scal[S_RZ0];
+            a.scal[S_BETA] = rzt / old;
+            a.scal[S_RZ0] = rzt;
+        } else {
             a.ctrl[C_TICKET_F] = 0;
             a.ctrl[C_TICKET_B] = 0;
         }
@@ -361,10 +363,10 @@ int enqueue_iteration(const lpcg_system *s, const Args &a, hipStream_t st) {
         } else {
             const std::vector<int> &lp = s->h_flev_ptr;
             for (size_t l = 0; l + 1 < lp.size(); ++l) {
-                const int rows = lp[l + 1] - lp[l], nb = level_blocks(rows, G), first = l == 0;
-                if (G == 4) k_llt_fwd_level<4><<<nb, 256, 0, st>>>(a, lp[l], rows, first);
-                else if (G == 8) k_llt_fwd_level<8><<<nb, 256, 0, st>>>(a, lp[l], rows, first);
-                else k_llt_fwd_level<16><<<nb, 256, 0, st>>>(a, lp[l], rows, first);
+                const int rows = lp[l + 1] - lp[l], nb = level_blocks(rows, G);
+                if (G == 4) k_llt_fwd_level<4><<<nb, 256, 0, st>>>(a, lp[l], rows);
+                else if (G == 8) k_llt_fwd_level<8><<<nb, 256, 0, st>>>(a, lp[l], rows);
+                else k_llt_fwd_level<16><<<nb, 256, 0, st>>>(a, lp[l], rows);
             }
         }
         if (s->trsv[1].mode == 0) {
@@ -374,21 +376,20 @@ int enqueue_iteration(const lpcg_system *s, const Args &a, hipStream_t st) {
             int part0 = 0;
             for (size_t l = 0; l + 1 < lp.size(); ++l) {
                 const int rows = lp[l + 1] - lp[l], nb = level_blocks(rows, G);
-                if (G == 4) k_llt_bwd_level<4><<<nb, 256, 0, st>>>(a, lp[l], rows, part0);
-                else if (G == 8) k_llt_bwd_level<8><<<nb, 256, 0, st>>>(a, lp[l], rows, part0);
-                else k_llt_bwd_level<16><<<nb, 256, 0, st>>>(a, lp[l], rows, part0);
+                const int last = l + 2 == lp.size();
+                if (G == 4) k_llt_bwd_level<4><<<nb, 256, 0, st>>>(a, lp[l], rows, part0, last);
+                else if (G == 8) k_llt_bwd_level<8><<<nb, 256, 0, st>>>(a, lp[l], rows, part0, last);
+                else k_llt_bwd_level<16><<<nb, 256, 0, st>>>(a, lp[l], rows, part0, last);
                 part0 += nb;
             }
         }
     }
-    k_rz<KIND><<<1, 1024, 0, st>>>(a);
-    k_pupd<KIND><<<vb, VT, 0, st>>>(a);
     switch (s->spmv_group) {
-        case 4: k_spmv_pw<4><<<sb, VT, 0, st>>>(a); break;
-        case 8: k_spmv_pw<8><<<sb, VT, 0, st>>>(a); break;
-        case 16: k_spmv_pw<16><<<sb, VT, 0, st>>>(a); break;
-        case 32: k_spmv_pw<32><<<sb, VT, 0, st>>>(a); break;
-        default: k_spmv_pw<64><<<sb, VT, 0, st>>>(a); break;
+        case 4: k_spmv_pw<4, KIND><<<sb, VT, 0, st>>>(a); break;
+        case 8: k_spmv_pw<8, KIND><<<sb, VT, 0, st>>>(a); break;
+        case 16: k_spmv_pw<16, KIND><<<sb, VT, 0, st>>>(a); break;
+        case 32: k_spmv_pw<32, KIND><<<sb, VT, 0, st>>>(a); break;
+        default: k_spmv_pw<64, KIND><<<sb, VT, 0, st>>>(a); break;
     }
     k_xr<KIND><<<vb, VT, 0, st>>>(a);
     LPCG_LAUNCH_CHECK();
@@ -400,7 +401,7 @@ int run_solve(lpcg_system *s, const Args &a, const lpcg_solve_opts &o, int &iter
               int &status, double &rr_out, hipStream_t st) {
     const int vb = s->vec_blocks;
     k_setup<KIND><<<vb, VT, 0, st>>>(a);
-    k_setup_scal<<<1, VT, 0, st>>>(a);
+    k_setup_scal<KIND><<<1, VT, 0, st>>>(a);
     LPCG_LAUNCH_CHECK();
     const int chunk = o.check_every > 0 ? o.check_every : 8;
     hipGraphExec_t exec = nullptr;
@@ -487,19 +488,19 @@ extern "C" int lpcg_pcg_solve(lpcg_system *s, const lpcg_precond *P, const doubl
     Args a{};
     a.n = s->n;
     a.np_vec = s->vec_blocks;
-    a.np_spmv = s->spmv_blocks;
-    a.np_chunk = (s->n + kWave - 1) / kWave;
+    a.maxit = opts->maxit > 0 ? opts->maxit : s->n;
+    a.kind = P->kind;
     a.backoff_f = s->trsv[0].backoff;
     a.backoff_b = s->trsv[1].backoff;
+    a.reset_y = s->trsv[0].mode == 0;
+    a.reset_z = s->trsv[1].mode == 0;
     if (s->trsv[1].mode == 0) {
-        a.np_rz = a.np_chunk;
+        a.np_rz = (s->n + kWave - 1) / kWave;
     } else {
         a.np_rz = 0;
         for (size_t l = 0; l + 1 < s->h_blev_ptr.size(); ++l)
             a.np_rz += level_blocks(s->h_blev_ptr[l + 1] - s->h_blev_ptr[l], s->trsv_g);
     }
-    a.maxit = opts->maxit > 0 ? opts->maxit : s->n;
-    a.kind = P->kind;
     a.rp = s->rowptr;
     a.ci = s->colind;
     a.v32 = s->val32;
@@ -521,7 +522,8 @@ extern "C" int lpcg_pcg_solve(lpcg_system *s, const lpcg_precond *P, const doubl
     a.b = s->perm ? s->bperm : b;
     a.x = s->perm ? s->xperm : x;
     a.r = s->r;
-    a.p = s->p;
+    a.p0 = s->p;
+    a.p1 = s->p2;
     a.w = s->w;
     a.y = (uint32_t *)s->y;
     a.z = (uint32_t *)s->z;
@@ -529,6 +531,10 @@ extern "C" int lpcg_pcg_solve(lpcg_system *s, const lpcg_precond *P, const doubl
     a.part_rz = s->part + s->npart;
     a.part_pw = s->part + 2 * (size_t)s->npart;
     a.part_bb = s->part + 3 * (size_t)s->npart;
+    a.sp_rz = s->sync_part;
+    a.sp_pw = s->sync_part + s->npart;
+    a.sp_rr = s->sync_part + 2 * (size_t)s->npart;
+    a.sp_rz2 = s->sync_part + 3 * (size_t)s->npart;
     a.scal = s->scal;
     a.hist = hist;
     a.ctrl = s->ctrl;
