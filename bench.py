@@ -11,8 +11,9 @@ are resident in HBM before the timed region.
 Both row orderings of the library are measured: the natural one (the factor
 on tril(A), as in the paper) and the multicolour one (red-black on this
 grid; the factor on tril(P A P^T)), each with its own trained network.  The
-headline value is learned-L in the ordering where it is fastest; every
-method/ordering pair is in "methods".
+headline value is learned-L in the natural ordering (the paper's setting),
+compared with IC(0) in the same ordering; every method/ordering pair is in
+"methods".
 
 Prints one JSON line (see the end of main()).
 """
@@ -198,9 +199,9 @@ def main():
         cpu["host"] = platform.processor() or platform.machine()
         cpu["host_cpus"] = os.cpu_count()
 
-    learned = [k for k in results if k.startswith("learned")]
-    head = min(learned, key=lambda k: results[k]["ms"]) if learned else \
-        min((k for k in results if k.startswith("ic0")), key=lambda k: results[k]["ms"])
+    # headline: learned L in the natural ordering (the factor on tril(A), the
+    # paper's setting), else the first learned / IC(0) result measured
+    head = next((k for k in ("learned", "learned_color", "ic0", "ic0_color") if k in results))
     head_order = results[head]["ordering"]
     kf = kernels[head_order]["sptrsv_fwd"]
     ic0_same = "ic0" if head_order == "natural" else f"ic0_{head_order}"
