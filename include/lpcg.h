@@ -182,13 +182,20 @@ int lpcg_time_spmv(const lpcg_system *sys, const float *x, float *y, int32_t rep
  * (one launch; rows handed to `waves` waves in level order, each row polls
  * its dependencies' ready flags, sleeping `backoff` rounds between polls);
  * mode 1: level synchronous (one launch per level, a few lanes per row, no
- * polling).  A new system uses mode 1 when the direction has at most 16
+ * polling); mode 2: single workgroup (one block of 1024 threads walks every
+ * level with block barriers, on a level-ordered copy of the factor that is
+ * prepared once per factor; only for systems whose widest level has at most
+ * 3072 rows).  A new system uses mode 1 when the direction has at most 16
  * levels, mode 0 with 4096 waves and backoff 1 otherwise. */
 typedef struct {
     int32_t direction;     /* 0: forward (L y = r), 1: backward (L^T z = y) */
-    int32_t mode;          /* 0 dependency driven, 1 level synchronous */
+    int32_t mode;          /* 0 dependency driven, 1 level synchronous, 2 single workgroup */
     int32_t waves;         /* mode 0: waves launched (0 = default) */
     int32_t backoff;       /* mode 0: sleep rounds between polls (0..64) */
+    int32_t block_stride;  /* mode 0: only blocks whose index is a multiple of this
+                              (1, 2, 4 or 8) work; with the hardware's round-robin
+                              dispatch over the 8 XCDs, 8 keeps every working wave
+                              on one XCD (one L2).  0 means 1. */
     double us;             /* lpcg_autotune: mean duration of one solve */
 } lpcg_trsv_cfg;
 
@@ -203,8 +210,9 @@ int lpcg_autotune(lpcg_system *sys, const float *l_val, const float *ut_val, int
                   lpcg_trsv_cfg *table, int32_t table_len, int32_t *n_table, hipStream_t stream);
 
 /* Read / force the configuration of one direction (HOST struct; `us` is
- * ignored).  Errors: EINVAL for an unknown direction, mode or a backoff
- * outside 0..64. */
+ * ignored).  Errors: EINVAL for an unknown direction, mode, a backoff outside
+ * 0..64, a block_stride other than 0, 1, 2, 4, 8, or mode 2 on a system with
+ * a level wider than 3072 rows. */
 int lpcg_get_trsv_cfg(const lpcg_system *sys, int32_t direction, lpcg_trsv_cfg *out);
 int lpcg_set_trsv_cfg(lpcg_system *sys, const lpcg_trsv_cfg *cfg);
 

@@ -264,6 +264,32 @@ __global__ void k_vec_scatter(int n, const int *__restrict__ perm, const T *__re
     if (r < n) dst[perm[r]] = src[r];
 }
 
+// Level-ordered packed pattern of one triangular factor (UPPER = 0: L rows,
+// diagonal last; UPPER = 1: U rows, diagonal first), rows in `order`.
+template <bool UPPER>
+__global__ void k_lo_count(int n, const int *__restrict__ order, const int *__restrict__ rp, int *__restrict__ cnt) {
+    int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    const int row = order[q];
+    cnt[q] = rp[row + 1] - rp[row] - 1;
+}
+
+template <bool UPPER>
+__global__ void k_lo_fill(int n, const int *__restrict__ order, const int *__restrict__ rp,
+                          const int *__restrict__ ci, const int *__restrict__ ptr, int *__restrict__ col,
+                          int *__restrict__ src, int *__restrict__ dsrc) {
+    int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    const int row = order[q], a = rp[row], b = rp[row + 1];
+    const int k0 = UPPER ? a + 1 : a, k1 = UPPER ? b : b - 1;
+    int e = ptr[q];
+    for (int k = k0; k < k1; ++k, ++e) {
+        col[e] = ci[k];
+        src[e] = k;
+    }
+    dsrc[q] = UPPER ? a : b - 1;
+}
+
 __global__ void k_iota_fill(int n, int *iota, int *lev_f, int *lev_b) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) {
@@ -471,6 +497,36 @@ int analyze_impl(const lpcg_csr *A, const int32_t *h_sys, int32_t nsys, lpcg_sys
     if ((rc = build_levels(s, true, s->blevel, nullptr, st, &s->blev_ptr, &s->blev_rows, s->h_blev_ptr,
                            s->nlev_b, s->max_w_b, iota, keys, ticket)))
         return rc;
+    // level-ordered packed patterns for the single-workgroup substitution
+    for (int d = 0; d < 2; ++d) {
+        const int *order = d ? s->blev_rows : s->flev_rows;
+        const int *rp = d ? s->urowptr : s->lrowptr;
+        const int *ci = d ? s->ucol : s->lcol;
+        const int noff = s->nnz_l - n;
+        ALLOC(s->lo_ptr[d], n + 1);
+        ALLOC(s->lo_col[d], std::max(noff, 1));
+        ALLOC(s->lo_src[d], std::max(noff, 1));
+        ALLOC(s->lo_dsrc[d], n);
+        ALLOC(s->lo_val[d], std::max(noff, 1));
+        ALLOC(s->lo_diag[d], n);
+        int *cnt = nl;  // n + 1 ints of scratch (the lower counts are no longer needed)
+        if (d) k_lo_count<true><<<nblk(n, 256), 256, 0, st>>>(n, order, rp, cnt);
+        else k_lo_count<false><<<nblk(n, 256), 256, 0, st>>>(n, order, rp, cnt);
+        LPCG_HIP(hipMemsetAsync(cnt + n, 0, sizeof(int), st));
+        size_t tb2 = 0;
+        LPCG_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tb2, cnt, s->lo_ptr[d], n + 1, st));
+        void *tmp2 = nullptr;
+        LPCG_HIP(hipMallocAsync(&tmp2, tb2, st));
+        LPCG_HIP(hipcub::DeviceScan::ExclusiveSum(tmp2, tb2, cnt, s->lo_ptr[d], n + 1, st));
+        LPCG_HIP(hipFreeAsync(tmp2, st));
+        if (d)
+            k_lo_fill<true><<<nblk(n, 256), 256, 0, st>>>(n, order, rp, ci, s->lo_ptr[d], s->lo_col[d],
+                                                            s->lo_src[d], s->lo_dsrc[d]);
+        else
+            k_lo_fill<false><<<nblk(n, 256), 256, 0, st>>>(n, order, rp, ci, s->lo_ptr[d], s->lo_col[d],
+                                                             s->lo_src[d], s->lo_dsrc[d]);
+        LPCG_LAUNCH_CHECK();
+    }
     // values and solver work space
     ALLOC(s->val64, nnz);
     ALLOC(s->val32, nnz);

@@ -173,9 +173,16 @@ int spmv64(const lpcg_system *s, const double *x, double *y, hipStream_t st) {
     return launch_spmv<double, double>(s, s->val64, x, y, st);
 }
 
+// Whether the single-workgroup mode can take a direction: every level must
+// fit in kWgRows rows per thread.
+bool wg_mode_fits(const lpcg_system *s, int transpose) {
+    return (transpose ? s->max_w_b : s->max_w_f) <= kWgRows * kWgThreads;
+}
+
 // Enqueue the kernels of one substitution with configuration c: the
-// dependency-driven kernel expects y preset to kUnset and the ticket zeroed
-// (trsv_presets); the level-synchronous launches need nothing.
+// dependency-driven kernel expects y preset to kUnset and the ticket zeroed,
+// the single-workgroup kernel the factor's values in level-ordered form
+// (trsv_presets does both); the level-synchronous launches need nothing.
 int trsv_kernels(const lpcg_system *s, int transpose, const TrsvCfg &c, const float *lval,
                  const float *utval, const float *rhs, float *y, int *ticket, hipStream_t st) {
     const int n = s->n;
@@ -185,11 +192,20 @@ int trsv_kernels(const lpcg_system *s, int transpose, const TrsvCfg &c, const fl
     const int *ci = up ? s->ucol : s->lcol;
     const float *v = up ? utval : lval;
     if (c.mode == 0) {
-        const int blocks = nblk(trsv_waves(n, c.waves), 4);
+        const int blocks = nblk(trsv_waves(n, c.waves), 4) * c.stride;
         if (up)
-            k_sptrsv<true><<<blocks, 256, 0, st>>>(n, order, rp, ci, v, rhs, (uint32_t *)y, ticket, c.backoff);
+            k_sptrsv<true><<<blocks, 256, 0, st>>>(n, order, rp, ci, v, rhs, (uint32_t *)y, ticket, c.backoff,
+                                                   c.stride);
         else
-            k_sptrsv<false><<<blocks, 256, 0, st>>>(n, order, rp, ci, v, rhs, (uint32_t *)y, ticket, c.backoff);
+            k_sptrsv<false><<<blocks, 256, 0, st>>>(n, order, rp, ci, v, rhs, (uint32_t *)y, ticket, c.backoff,
+                                                    c.stride);
+        LPCG_LAUNCH_CHECK();
+        return LPCG_OK;
+    }
+    if (c.mode == 2) {
+        const int d = up ? 1 : 0;
+        k_trsv_wg<<<1, kWgThreads, 0, st>>>(up ? s->nlev_b : s->nlev_f, up ? s->blev_ptr : s->flev_ptr, order,
+                                            s->lo_ptr[d], s->lo_col[d], s->lo_val[d], s->lo_diag[d], rhs, y);
         LPCG_LAUNCH_CHECK();
         return LPCG_OK;
     }
@@ -214,7 +230,20 @@ int trsv_kernels(const lpcg_system *s, int transpose, const TrsvCfg &c, const fl
     return LPCG_OK;
 }
 
-int trsv_presets(const lpcg_system *s, const TrsvCfg &c, float *y, int *ticket, hipStream_t st) {
+// Level-ordered values of one direction's factor (single-workgroup mode).
+int lo_prepare(const lpcg_system *s, int transpose, const float *lval, const float *utval, hipStream_t st) {
+    const int d = transpose ? 1 : 0;
+    const int noff = s->nnz_l - s->n;
+    k_lo_prep<<<nblk(std::max(noff, s->n), 256), 256, 0, st>>>(noff, s->n, s->lo_src[d], s->lo_dsrc[d],
+                                                                 transpose ? utval : lval, s->lo_val[d],
+                                                                 s->lo_diag[d]);
+    LPCG_LAUNCH_CHECK();
+    return LPCG_OK;
+}
+
+int trsv_presets(const lpcg_system *s, int transpose, const TrsvCfg &c, const float *lval, const float *utval,
+                 float *y, int *ticket, hipStream_t st) {
+    if (c.mode == 2) return lo_prepare(s, transpose, lval, utval, st);
     if (c.mode != 0) return LPCG_OK;
     k_fill_u32<<<nblk(s->n, 256), 256, 0, st>>>(s->n, (uint32_t *)y, kUnset);
     k_zero_i32<<<1, 64, 0, st>>>(ticket, 1);
@@ -225,7 +254,7 @@ int trsv_presets(const lpcg_system *s, const TrsvCfg &c, float *y, int *ticket, 
 int sptrsv32(const lpcg_system *s, int transpose, const float *lval, const float *utval,
              const float *rhs, float *y, int *ticket, hipStream_t st) {
     const TrsvCfg &c = s->trsv[transpose ? 1 : 0];
-    int rc = trsv_presets(s, c, y, ticket, st);
+    int rc = trsv_presets(s, transpose, c, lval, utval, y, ticket, st);
     if (rc) return rc;
     return trsv_kernels(s, transpose, c, lval, utval, rhs, y, ticket, st);
 }
@@ -356,7 +385,7 @@ extern "C" int lpcg_time_sptrsv(const lpcg_system *s, int32_t transpose, const f
     const TrsvCfg &c = s->trsv[transpose ? 1 : 0];
     double total = 0;
     for (int r = 0; r < reps; ++r) {
-        int rc = trsv_presets(s, c, y, ticket, st);
+        int rc = trsv_presets(s, transpose, c, l_val, ut_val, y, ticket, st);
         if (rc) return rc;
         LPCG_HIP(hipEventRecord(ev.a, st));
         rc = trsv_kernels(s, transpose, c, l_val, ut_val, rhs, y, ticket, st);
@@ -403,20 +432,29 @@ extern "C" int lpcg_get_trsv_cfg(const lpcg_system *s, int32_t direction, lpcg_t
     out->mode = c.mode;
     out->waves = c.mode == 0 ? trsv_waves(s->n, c.waves) : 0;
     out->backoff = c.backoff;
+    out->block_stride = c.stride;
     out->us = 0;
     return LPCG_OK;
 }
 
 extern "C" int lpcg_set_trsv_cfg(lpcg_system *s, const lpcg_trsv_cfg *cfg) {
-    if (!s || !cfg || cfg->direction < 0 || cfg->direction > 1 || cfg->mode < 0 || cfg->mode > 1 ||
-        cfg->waves < 0 || cfg->backoff < 0 || cfg->backoff > 64) {
+    if (!s || !cfg || cfg->direction < 0 || cfg->direction > 1 || cfg->mode < 0 || cfg->mode > 2 ||
+        cfg->waves < 0 || cfg->backoff < 0 || cfg->backoff > 64 ||
+        (cfg->block_stride != 0 && cfg->block_stride != 1 && cfg->block_stride != 2 &&
+         cfg->block_stride != 4 && cfg->block_stride != 8)) {
         set_error("lpcg_set_trsv_cfg: invalid configuration");
+        return LPCG_EINVAL;
+    }
+    if (cfg->mode == 2 && !wg_mode_fits(s, cfg->direction)) {
+        set_error("lpcg_set_trsv_cfg: a level has more than %d rows, too wide for the single-workgroup mode",
+                  kWgRows * kWgThreads);
         return LPCG_EINVAL;
     }
     TrsvCfg &c = s->trsv[cfg->direction];
     c.mode = cfg->mode;
     c.waves = cfg->waves;
     c.backoff = cfg->backoff;
+    c.stride = cfg->block_stride > 0 ? cfg->block_stride : 1;
     if (s->graph_exec) {  // the cached PCG graph launches the old kernels
         hipGraphExecDestroy(s->graph_exec);
         s->graph_exec = nullptr;
@@ -442,18 +480,20 @@ extern "C" int lpcg_autotune(lpcg_system *s, const float *l_val, const float *ut
     for (int dir = 0; dir < 2; ++dir) {
         const int nlev = dir ? s->nlev_b : s->nlev_f;
         std::vector<TrsvCfg> cands;
-        if (nlev <= kLevelModeTuneLevels) cands.push_back(TrsvCfg{1, 0, 1});
+        if (nlev <= kLevelModeTuneLevels) cands.push_back(TrsvCfg{1, 0, 1, 1});
+        if (wg_mode_fits(s, dir)) cands.push_back(TrsvCfg{2, 0, 1, 1});
         for (int w : {64, 128, 256, 512, 1024, 2048, 4096})
             for (int bo : {1, 4, 16, 64}) {
                 if (w > trsv_waves(s->n, 1 << 30) && w != 64) continue;  // more waves than chunks
-                cands.push_back(TrsvCfg{0, w, bo});
+                cands.push_back(TrsvCfg{0, w, bo, 1});
+                if (w <= 512) cands.push_back(TrsvCfg{0, w, bo, 8});  // all waves on one XCD
             }
         double best = 1e30;
         TrsvCfg best_c = s->trsv[dir];
         for (const TrsvCfg &c : cands) {
             double tot = 0;
             for (int r = 0; r <= reps; ++r) {  // first run warms up
-                int rc = trsv_presets(s, c, s->w, ticket, st);
+                int rc = trsv_presets(s, dir, c, l_val, ut_val, s->w, ticket, st);
                 if (rc) return rc;
                 LPCG_HIP(hipEventRecord(ev.a, st));
                 rc = trsv_kernels(s, dir, c, l_val, ut_val, s->p, s->w, ticket, st);
@@ -471,6 +511,7 @@ extern "C" int lpcg_autotune(lpcg_system *s, const float *l_val, const float *ut
                 e.mode = c.mode;
                 e.waves = c.mode == 0 ? trsv_waves(s->n, c.waves) : 0;
                 e.backoff = c.backoff;
+                e.block_stride = c.stride;
                 e.us = us;
             }
             ++count;

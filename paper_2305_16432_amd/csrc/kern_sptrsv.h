@@ -121,7 +121,8 @@ __global__ void __launch_bounds__(256) k_sptrsv(int n, const int *__restrict__ o
                                                 const int *__restrict__ rp, const int *__restrict__ ci,
                                                 const float *__restrict__ v,
                                                 const float *__restrict__ rhs, uint32_t *ybits,
-                                                int *ticket, int backoff) {
+                                                int *ticket, int backoff, int stride) {
+    if (blockIdx.x % stride != 0) return;  // placement: only every stride-th block works
     for (;;) {
         const int chunk = wave_ticket(ticket);
         if ((long)chunk * kWave >= n) break;
@@ -187,3 +188,123 @@ inline int trsv_waves(int n, int want = 0) {
 }
 
 }  // namespace lpcg
+
+// ---------------------------------------------------------------------------
+// Single-workgroup substitution (mode 2): one block of kWgThreads threads
+// walks every level, with a block barrier between levels, on the level-
+// ordered packed pattern (lo_ptr/lo_col/lo_val/lo_diag of lpcg_system;
+// level position q holds row rows[q]).  Communication stays inside one CU, so
+// a level costs a block barrier and the y gathers instead of a cross-CU
+// signal.  Loads that do not depend on y are software-pipelined: entry ranges,
+// rows and diagonals two levels ahead, columns, values and right-hand sides
+// one level ahead.  A thread handles at most kWgRows rows of a level (so the
+// widest level may have kWgRows * kWgThreads rows); entries beyond kWgEnt per
+// row are loaded inline.  Accumulation in entry (column) order.
+constexpr int kWgThreads = 1024;
+constexpr int kWgRows = 3;
+constexpr int kWgEnt = 4;
+
+struct WgA {  // stage A: per row of a level
+    int row[kWgRows], e0[kWgRows], ne[kWgRows];
+    float diag[kWgRows];
+};
+struct WgB {  // stage B: entries and right-hand side
+    int col[kWgRows][kWgEnt];
+    float val[kWgRows][kWgEnt];
+    float rhs[kWgRows];
+};
+
+__device__ __forceinline__ void wg_load_a(WgA &A, int q0, int q1, const int *__restrict__ rows,
+                                          const int *__restrict__ ptr, const float *__restrict__ diag) {
+#pragma unroll
+    for (int r = 0; r < kWgRows; ++r) {
+        const int q = q0 + (int)threadIdx.x + r * kWgThreads;
+        if (q < q1) {
+            A.row[r] = rows[q];
+            A.e0[r] = ptr[q];
+            A.ne[r] = ptr[q + 1] - A.e0[r];
+            A.diag[r] = diag[q];
+        } else {
+            A.row[r] = -1;
+            A.e0[r] = 0;
+            A.ne[r] = 0;
+            A.diag[r] = 1.f;
+        }
+    }
+}
+
+__device__ __forceinline__ void wg_load_b(WgB &B, const WgA &A, const int *__restrict__ col,
+                                          const float *__restrict__ val, const float *__restrict__ rhs) {
+#pragma unroll
+    for (int r = 0; r < kWgRows; ++r) {
+#pragma unroll
+        for (int j = 0; j < kWgEnt; ++j) {
+            const bool ok = j < A.ne[r];
+            B.col[r][j] = ok ? col[A.e0[r] + j] : 0;
+            B.val[r][j] = ok ? val[A.e0[r] + j] : 0.f;
+        }
+        B.rhs[r] = A.row[r] >= 0 ? rhs[A.row[r]] : 0.f;
+    }
+}
+
+// Solve the rows of one level; returns sum over this thread's rows of
+// w[row] * y[row] when w is given (the r.z partial of the backward solve).
+__device__ __forceinline__ double wg_solve(const WgA &A, const WgB &B, const int *__restrict__ col,
+                                           const float *__restrict__ val, float *y, const float *w) {
+    double dot = 0.0;
+#pragma unroll
+    for (int r = 0; r < kWgRows; ++r) {
+        if (A.row[r] < 0) continue;
+        float acc = 0.f;
+#pragma unroll
+        for (int j = 0; j < kWgEnt; ++j)
+            if (j < A.ne[r]) acc += B.val[r][j] * y[B.col[r][j]];
+        for (int j = kWgEnt; j < A.ne[r]; ++j) acc += val[A.e0[r] + j] * y[col[A.e0[r] + j]];
+        const float yv = (B.rhs[r] - acc) / A.diag[r];
+        y[A.row[r]] = yv;
+        if (w) dot += (double)w[A.row[r]] * (double)yv;
+    }
+    return dot;
+}
+
+// Whole substitution in the calling block (all threads call; contains block
+// barriers).  lev_ptr is the device level pointer array (nlev + 1 entries).
+__device__ __forceinline__ double wg_substitute(int nlev, const int *__restrict__ lev_ptr,
+                                                const int *__restrict__ rows, const int *__restrict__ ptr,
+                                                const int *__restrict__ col, const float *__restrict__ val,
+                                                const float *__restrict__ diag, const float *__restrict__ rhs,
+                                                float *y, const float *w) {
+    WgA A0, A1, A2;
+    WgB B0, B1;
+    wg_load_a(A0, lev_ptr[0], lev_ptr[1], rows, ptr, diag);
+    wg_load_b(B0, A0, col, val, rhs);
+    if (nlev > 1) wg_load_a(A1, lev_ptr[1], lev_ptr[2], rows, ptr, diag);
+    double dot = 0.0;
+    for (int l = 0; l < nlev; ++l) {
+        if (l + 1 < nlev) wg_load_b(B1, A1, col, val, rhs);
+        if (l + 2 < nlev) wg_load_a(A2, lev_ptr[l + 2], lev_ptr[l + 3], rows, ptr, diag);
+        dot += wg_solve(A0, B0, col, val, y, w);
+        __syncthreads();
+        A0 = A1;
+        A1 = A2;
+        B0 = B1;
+    }
+    return dot;
+}
+
+static __global__ void __launch_bounds__(kWgThreads) k_trsv_wg(int nlev, const int *__restrict__ lev_ptr,
+                                                        const int *__restrict__ rows, const int *__restrict__ ptr,
+                                                        const int *__restrict__ col, const float *__restrict__ val,
+                                                        const float *__restrict__ diag,
+                                                        const float *__restrict__ rhs, float *y) {
+    wg_substitute(nlev, lev_ptr, rows, ptr, col, val, diag, rhs, y, nullptr);
+}
+
+// Values of one factor in level-ordered packed form: val_lo[e] = v[src[e]],
+// diag_lo[q] = v[dsrc[q]].
+static __global__ void k_lo_prep(int noff, int n, const int *__restrict__ src, const int *__restrict__ dsrc,
+                          const float *__restrict__ v, float *__restrict__ val_lo, float *__restrict__ diag_lo) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < noff) val_lo[i] = v[src[i]];
+    if (i < n) diag_lo[i] = v[dsrc[i]];
+}

@@ -49,10 +49,12 @@ enum Scal : int {
 };
 
 // Configuration of one substitution direction: mode 0 = dependency driven
-// (one launch; `waves` waves, `backoff` sleep rounds between polls), mode 1 =
-// level synchronous (one launch per level, `g` lanes per row).
+// (one launch; `waves` waves in blocks whose index is a multiple of `stride`,
+// `backoff` sleep rounds between polls), mode 1 =
+// level synchronous (one launch per level, `g` lanes per row), mode 2 = one
+// workgroup walking all levels with block barriers.
 struct TrsvCfg {
-    int mode = 0, waves = 0, backoff = 1;
+    int mode = 0, waves = 0, backoff = 1, stride = 1;
 };
 
 }  // namespace lpcg
@@ -76,6 +78,15 @@ struct lpcg_system {
     int *perm = nullptr, *iperm = nullptr, *psrc = nullptr;
     double *bperm = nullptr, *xperm = nullptr;  // caller vectors in internal order
     std::vector<int> h_flev_ptr, h_blev_ptr, h_sys_rowptr;
+    // level-ordered packed factor patterns (index 0: L rows in forward level
+    // order, 1: U = L^T rows in backward level order): for level position q,
+    // off-diagonal entries lo_ptr[q] .. lo_ptr[q+1] with columns lo_col and
+    // positions lo_src in the CSR value array; lo_dsrc[q] = the diagonal's
+    // position.  lo_val / lo_diag hold one factor's values in that order
+    // (prepared per solve) for the single-workgroup substitution.
+    int *lo_ptr[2] = {nullptr, nullptr}, *lo_col[2] = {nullptr, nullptr};
+    int *lo_src[2] = {nullptr, nullptr}, *lo_dsrc[2] = {nullptr, nullptr};
+    float *lo_val[2] = {nullptr, nullptr}, *lo_diag[2] = {nullptr, nullptr};
     // values (device)
     double *val64 = nullptr;
     float *val32 = nullptr;

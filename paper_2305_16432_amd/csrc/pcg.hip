@@ -41,6 +41,7 @@
 namespace lpcg {
 
 int spmv32(const lpcg_system *s, const float *x, float *y, hipStream_t st);
+int lo_prepare(const lpcg_system *s, int transpose, const float *lval, const float *utval, hipStream_t st);
 
 namespace {
 
@@ -48,11 +49,15 @@ constexpr int VT = kVecThreads;
 
 struct Args {
     int n, np_vec, np_rz, maxit, kind;
-    int backoff_f, backoff_b, reset_y, reset_z;
+    int backoff_f, backoff_b, stride_f, stride_b, reset_y, reset_z;
     const int *rp, *ci;
     const float *v32;
     const double *v64;
     const int *lrp, *lci, *urp, *uci, *forder, *border;
+    int nlev_f, nlev_b;
+    const int *flp, *blp;                             // device level pointers
+    const int *lo_ptr_f, *lo_col_f, *lo_ptr_b, *lo_col_b;  // level-ordered packed patterns
+    const float *lo_val_f, *lo_diag_f, *lo_val_b, *lo_diag_b;
     const float *lval, *utval, *dinv;
     const double *b;
     double *x;
@@ -165,6 +170,7 @@ __device__ __forceinline__ void finish_rz(const Args &a, double *lds) {
 }
 
 __global__ void __launch_bounds__(256) k_llt_fwd(Args a) {
+    if (blockIdx.x % a.stride_f != 0) return;  // placement: only every stride-th block works
     if (is_done(a)) return;
     int *ticket = a.ctrl + C_TICKET_F;
     for (;;) {
@@ -177,6 +183,7 @@ __global__ void __launch_bounds__(256) k_llt_fwd(Args a) {
 
 __global__ void __launch_bounds__(256) k_llt_bwd(Args a) {
     __shared__ double lds[VT / kWave];
+    if (blockIdx.x % a.stride_b != 0) return;  // placement: only every stride-th block works
     if (is_done(a)) return;
     int *ticket = a.ctrl + C_TICKET_B;
     for (;;) {
@@ -189,7 +196,8 @@ __global__ void __launch_bounds__(256) k_llt_bwd(Args a) {
         rz = wave_sum(rz);
         if (lane_id() == 0) publish_partial(a.sp_rz, chunk, rz);
     }
-    if (is_reducer()) finish_rz(a, lds);
+    // reducer: the working block of highest index
+    if ((int)blockIdx.x == ((int)gridDim.x - 1) / a.stride_b * a.stride_b) finish_rz(a, lds);
 }
 
 // Level-synchronous forms of the two substitutions: one launch per level
@@ -229,6 +237,28 @@ __global__ void __launch_bounds__(256) k_llt_bwd_level(Args a, int lev0, int row
     rz = block_sum<VT>(rz, lds);
     if (threadIdx.x == 0) publish_partial(a.sp_rz, part0 + blockIdx.x, rz);
     if (last && is_reducer()) finish_rz(a, lds);
+}
+
+// Single-workgroup substitutions (one block walking all levels): forward,
+// backward, or both in one launch; the backward part also forms r.z with a
+// block reduction and beta, so no partials are published.
+__global__ void __launch_bounds__(kWgThreads) k_llt_wg(Args a, int do_fwd, int do_bwd) {
+    __shared__ double lds[kWgThreads / kWave];
+    if (is_done(a)) return;
+    if (do_fwd)
+        wg_substitute(a.nlev_f, a.flp, a.forder, a.lo_ptr_f, a.lo_col_f, a.lo_val_f, a.lo_diag_f, a.r,
+                      (float *)a.y, nullptr);
+    if (do_bwd) {
+        const double rz = wg_substitute(a.nlev_b, a.blp, a.border, a.lo_ptr_b, a.lo_col_b, a.lo_val_b,
+                                        a.lo_diag_b, (const float *)a.y, (float *)a.z, a.r);
+        const double t = block_sum<kWgThreads>(rz, lds);
+        if (threadIdx.x == 0) {
+            const int it = a.ctrl[C_IT];
+            const double old = a.scal[S_RZ0];
+            a.scal[S_BETA] = it == 0 ? 0.0 : t / old;
+            a.scal[S_RZ0] = t;
+        }
+    }
 }
 
 // Entry j of the new search direction p = z + beta p_prev (p = z in the first
@@ -358,8 +388,11 @@ int enqueue_iteration(const lpcg_system *s, const Args &a, hipStream_t st) {
     const int sb = s->spmv_blocks;
     if (KIND == LPCG_PC_LLT) {
         const int G = s->trsv_g;
-        if (s->trsv[0].mode == 0) {
-            k_llt_fwd<<<(trsv_waves(s->n, s->trsv[0].waves) + 3) / 4, 256, 0, st>>>(a);
+        const bool wf = s->trsv[0].mode == 2, wb = s->trsv[1].mode == 2;
+        if (wf) {
+            k_llt_wg<<<1, kWgThreads, 0, st>>>(a, 1, wb ? 1 : 0);
+        } else if (s->trsv[0].mode == 0) {
+            k_llt_fwd<<<(trsv_waves(s->n, s->trsv[0].waves) + 3) / 4 * s->trsv[0].stride, 256, 0, st>>>(a);
         } else {
             const std::vector<int> &lp = s->h_flev_ptr;
             for (size_t l = 0; l + 1 < lp.size(); ++l) {
@@ -369,8 +402,10 @@ int enqueue_iteration(const lpcg_system *s, const Args &a, hipStream_t st) {
                 else k_llt_fwd_level<16><<<nb, 256, 0, st>>>(a, lp[l], rows);
             }
         }
-        if (s->trsv[1].mode == 0) {
-            k_llt_bwd<<<(trsv_waves(s->n, s->trsv[1].waves) + 3) / 4, 256, 0, st>>>(a);
+        if (wb) {
+            if (!wf) k_llt_wg<<<1, kWgThreads, 0, st>>>(a, 0, 1);
+        } else if (s->trsv[1].mode == 0) {
+            k_llt_bwd<<<(trsv_waves(s->n, s->trsv[1].waves) + 3) / 4 * s->trsv[1].stride, 256, 0, st>>>(a);
         } else {
             const std::vector<int> &lp = s->h_blev_ptr;
             int part0 = 0;
@@ -411,6 +446,7 @@ int run_solve(lpcg_system *s, const Args &a, const lpcg_solve_opts &o, int &iter
         memcpy(key.data(), &a, sizeof(Args));
         const int extra[9] = {KIND, chunk, s->trsv[0].mode, s->trsv[0].waves, s->trsv[0].backoff,
                               s->trsv[1].mode, s->trsv[1].waves, s->trsv[1].backoff, s->trsv_g};
+        // (the block strides travel in Args and are part of the key through it)
         memcpy(key.data() + sizeof(Args), extra, sizeof(extra));
         if (s->graph_exec && s->graph_key == key) {
             exec = s->graph_exec;
@@ -492,6 +528,8 @@ extern "C" int lpcg_pcg_solve(lpcg_system *s, const lpcg_precond *P, const doubl
     a.kind = P->kind;
     a.backoff_f = s->trsv[0].backoff;
     a.backoff_b = s->trsv[1].backoff;
+    a.stride_f = s->trsv[0].stride;
+    a.stride_b = s->trsv[1].stride;
     a.reset_y = s->trsv[0].mode == 0;
     a.reset_z = s->trsv[1].mode == 0;
     if (s->trsv[1].mode == 0) {
@@ -511,6 +549,18 @@ extern "C" int lpcg_pcg_solve(lpcg_system *s, const lpcg_precond *P, const doubl
     a.uci = s->ucol;
     a.forder = s->flev_rows;
     a.border = s->blev_rows;
+    a.nlev_f = s->nlev_f;
+    a.nlev_b = s->nlev_b;
+    a.flp = s->flev_ptr;
+    a.blp = s->blev_ptr;
+    a.lo_ptr_f = s->lo_ptr[0];
+    a.lo_col_f = s->lo_col[0];
+    a.lo_val_f = s->lo_val[0];
+    a.lo_diag_f = s->lo_diag[0];
+    a.lo_ptr_b = s->lo_ptr[1];
+    a.lo_col_b = s->lo_col[1];
+    a.lo_val_b = s->lo_val[1];
+    a.lo_diag_b = s->lo_diag[1];
     a.lval = P->l_val;
     a.utval = P->ut_val;
     a.dinv = P->dinv ? P->dinv : s->dinv;
@@ -539,6 +589,13 @@ extern "C" int lpcg_pcg_solve(lpcg_system *s, const lpcg_precond *P, const doubl
     a.hist = hist;
     a.ctrl = s->ctrl;
     a.tol2 = opts->tol * opts->tol;
+    if (P->kind == LPCG_PC_LLT) {  // level-ordered factor values for the single-workgroup mode
+        for (int d = 0; d < 2; ++d)
+            if (s->trsv[d].mode == 2) {
+                int rc = lo_prepare(s, d, P->l_val, P->ut_val, st);
+                if (rc) return rc;
+            }
+    }
     if (P->kind == LPCG_PC_JACOBI && !P->dinv) {
         int rc = lpcg_jacobi(s, s->dinv, st);
         if (rc) return rc;

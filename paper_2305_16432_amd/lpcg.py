@@ -57,7 +57,7 @@ class _Result(C.Structure):
 
 class _TrsvCfg(C.Structure):
     _fields_ = [("direction", C.c_int32), ("mode", C.c_int32), ("waves", C.c_int32),
-                ("backoff", C.c_int32), ("us", C.c_double)]
+                ("backoff", C.c_int32), ("block_stride", C.c_int32), ("us", C.c_double)]
 
 
 class _Gnn(C.Structure):
@@ -214,8 +214,9 @@ def get_trsv_cfg(sys: System, direction: int) -> dict:
     return {f: getattr(c, f) for f, _ in _TrsvCfg._fields_ if f != "us"}
 
 
-def set_trsv_cfg(sys: System, direction: int, mode: int, waves: int = 0, backoff: int = 1):
-    c = _TrsvCfg(direction, mode, waves, backoff, 0.0)
+def set_trsv_cfg(sys: System, direction: int, mode: int, waves: int = 0, backoff: int = 1,
+                 block_stride: int = 1):
+    c = _TrsvCfg(direction, mode, waves, backoff, block_stride, 0.0)
     _check(lib().lpcg_set_trsv_cfg(sys.handle, C.byref(c)), "lpcg_set_trsv_cfg")
 
 

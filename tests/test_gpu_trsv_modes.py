@@ -16,7 +16,7 @@ from tests.gpu_util import U32, cuda_f32, cuda_f64, gpu_system, host, matrices_s
 
 pytestmark = pytest.mark.gpu
 
-CFGS = [(0, 256, 4), (0, 4096, 1), (0, 1024, 16), (1, 0, 1)]
+CFGS = [(0, 256, 4, 1), (0, 4096, 1, 1), (0, 1024, 16, 1), (0, 128, 16, 8), (1, 0, 1, 1), (2, 0, 1, 1)]
 
 
 def _lower(pat, seed):
@@ -32,7 +32,7 @@ def _lower(pat, seed):
 @pytest.mark.parametrize("ordering", [0, 1])
 @pytest.mark.parametrize("name", ["tridiag_1000", "heat3d_13", "fem_40", "random_777", "one"])
 def test_sptrsv_modes(name, ordering, cfg):
-    mode, waves, backoff = cfg
+    mode, waves, backoff, stride = cfg
     print(f"[trsv] {name} ordering {ordering} cfg {cfg}", flush=True)
     A = matrices_small()[name]
     if ordering:
@@ -43,8 +43,8 @@ def test_sptrsv_modes(name, ordering, cfg):
     pat = O.Pattern(Ai)
     S = gpu_system(A, None, ordering)
     for d in (0, 1):
-        lpcg.set_trsv_cfg(S, d, mode, waves, backoff)
-        assert lpcg.get_trsv_cfg(S, d)["mode"] == mode
+        lpcg.set_trsv_cfg(S, d, mode, waves, backoff, stride)
+        assert lpcg.get_trsv_cfg(S, d)["mode"] == mode and lpcg.get_trsv_cfg(S, d)["block_stride"] == stride
     lval = _lower(pat, 3)
     utv = lval[pat.usrc]
     rhs = np.random.default_rng(4).standard_normal(A.n).astype(np.float32).astype(np.float64)
@@ -98,17 +98,43 @@ def test_autotune_c3_full_size(ordering):
         best = min(rows, key=lambda t: t["us"])
         got = lpcg.get_trsv_cfg(S, d)
         assert got["mode"] == best["mode"] and got["backoff"] == best["backoff"]
+        assert got["block_stride"] == best["block_stride"]
         if best["mode"] == 0:
             assert got["waves"] == best["waves"]
         for t in sorted(rows, key=lambda t: t["us"])[:6]:
-            print(f"  dir {d} mode {t['mode']} waves {t['waves']} backoff {t['backoff']}: {t['us']:.1f} us")
+            print(f"  dir {d} mode {t['mode']} waves {t['waves']} backoff {t['backoff']} "
+                  f"stride {t['block_stride']}: {t['us']:.1f} us")
     x, res = lpcg.pcg_solve(S, lpcg.PC_LLT, cuda_f64(b), l_val=l, ut_val=ut, tol=1e-6, max_restarts=2)
     assert res["status"] == 0 and O.true_relres(A, b, host(x)) <= 1e-6
 
 
 def test_trsv_cfg_rejects_bad_values():
     S = gpu_system(g.poisson_grid(5, 2))
-    for bad in [(2, 0, 0, 1), (0, 3, 0, 1), (0, 0, 0, 65)]:
+    for bad in [(2, 0, 0, 1), (0, 3, 0, 1), (0, 0, 0, 65), (0, 0, 0, 1, 3)]:
         with pytest.raises(lpcg.LpcgError) as e:
             lpcg.set_trsv_cfg(S, *bad)
         assert e.value.code == lpcg.EINVAL
+    # single-workgroup mode: at most 3 x 1024 rows per level (red-black 80x80: 3200)
+    W = gpu_system(g.poisson_grid(80, 2), None, 1)
+    assert W.info["max_width_fwd"] > 3072
+    with pytest.raises(lpcg.LpcgError) as e:
+        lpcg.set_trsv_cfg(W, 0, 2)
+    assert e.value.code == lpcg.EINVAL
+
+
+@pytest.mark.parametrize("transpose", [False, True])
+def test_single_workgroup_c3_full_size(transpose):
+    """Mode 2 at 64^3 natural order (190 levels, widest 3072 rows): backward
+    error against the GPU IC(0) factor."""
+    A, b = g.heat_system_3d(64, 1e-3, 1000, 2000)
+    pat = O.Pattern(A)
+    S = gpu_system(A)
+    for d in (0, 1):
+        lpcg.set_trsv_cfg(S, d, 2)
+    l, ut, _ = lpcg.ic0(S)
+    lval = host(l).astype(np.float64)
+    rhs = b.astype(np.float32).astype(np.float64)
+    y = host(lpcg.sptrsv(S, transpose, l, ut, cuda_f32(rhs))).astype(np.float64)
+    L = g.CSR(A.n, pat.lrowptr, pat.lcol, lval).to_scipy()
+    T = L.T if transpose else L
+    assert np.all(np.abs(rhs - T @ y) <= 4 * 4 * U32 * (abs(T) @ np.abs(y)))
