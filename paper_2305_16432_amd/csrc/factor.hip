@@ -44,7 +44,6 @@ int launch_spmv(const lpcg_system *s, const VT *v, const XT *x, XT *y, hipStream
 // when some value it needs is not yet published (non-blocking in the wave).
 constexpr uint64_t kUnset64 = 0x7fffffffffffffffull;
 constexpr int kIcRegDeps = 8;
-constexpr uint64_t kCanonNan64 = 0x7ff8000000000000ull;
 
 __device__ __forceinline__ uint64_t ld64(const uint64_t *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -58,7 +57,7 @@ __global__ void __launch_bounds__(256) k_ic0(int n, const int *__restrict__ orde
                                              const int *__restrict__ lrp, const int *__restrict__ lci,
                                              const int *__restrict__ lsrc,
                                              const double *__restrict__ aval, double shift,
-                                             uint64_t *l64, int *ticket, int *bad_row) {
+                                             uint64_t *l64, int *ticket, int *bad_row, int backoff) {
     for (;;) {
         const int chunk = wave_ticket(ticket);
         if ((long)chunk * kWave >= n) break;
@@ -133,7 +132,8 @@ __global__ void __launch_bounds__(256) k_ic0(int n, const int *__restrict__ orde
                     progress = false;
                 }
             }
-            if (pending) __builtin_amdgcn_s_sleep(1);
+            if (pending)
+                for (int t = 0; t < backoff; ++t) __builtin_amdgcn_s_sleep(1);
         }
     }
 }
@@ -339,9 +339,12 @@ extern "C" int lpcg_ic0(const lpcg_system *s, double shift0, int32_t max_retries
         k_fill_u64<<<nblk(s->nnz_l, 256), 256, 0, st>>>(s->nnz_l, (uint64_t *)l64, kUnset64);
         k_set_i32<<<1, 1, 0, st>>>(flags, 0);
         k_set_i32<<<1, 1, 0, st>>>(bad, 0x7fffffff);
-        const int blocks = nblk(trsv_waves(s->n), 4);
+        // same DAG as the forward substitution: reuse its wave count and
+        // back-off when that direction runs dependency driven
+        const TrsvCfg &fc = s->trsv[0];
+        const int blocks = nblk(trsv_waves(s->n, fc.mode == 0 ? fc.waves : 0), 4);
         k_ic0<<<blocks, 256, 0, st>>>(s->n, s->flev_rows, s->lrowptr, s->lcol, s->lsrc, s->val64, shift,
-                                      (uint64_t *)l64, flags, bad);
+                                      (uint64_t *)l64, flags, bad, fc.mode == 0 ? fc.backoff : 1);
         LPCG_LAUNCH_CHECK();
         int hbad = 0;
         LPCG_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, st));
