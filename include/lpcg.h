@@ -257,6 +257,31 @@ int lpcg_pcg_solve(lpcg_system *sys, const lpcg_precond *P, const double *b,
                    double *x, const lpcg_solve_opts *opts, lpcg_result *res,
                    double *hist, hipStream_t stream);
 
+/* Batched PCG: one PCG (Appendix algorithm) per system of a block-diagonal
+ * batch (lpcg_analyze with sys_rowptr), each with its own alpha, beta,
+ * residual test (||r_s|| <= tol ||b_s||), iteration count and status; all
+ * systems advance in the same launches and a finished system stops updating.
+ * b, x: FP64 [n] for the whole batch (x holds x0 on entry).  res: HOST array
+ * of nsys results, in system order (restarts from the FP64 true residual as
+ * in lpcg_pcg_solve, per system).  hist is not recorded.  Synchronous.
+ * Returns LPCG_OK when every system converged, else the first failing
+ * system's status. */
+int lpcg_pcg_solve_batched(lpcg_system *sys, const lpcg_precond *P, const double *b,
+                           double *x, const lpcg_solve_opts *opts, lpcg_result *res,
+                           hipStream_t stream);
+
+/* FP64 iterative refinement around the FP32 batched PCG, for every system of
+ * the batch (a single system is a batch of one): r = b - A x in FP64; systems
+ * with ||r|| <= tol ||b|| are done; the others solve A d = r with the inner
+ * PCG to tol_inner (inner->tol is ignored) and take x += d; at most max_outer
+ * refinement steps.  res (HOST, nsys): iters = inner iterations summed,
+ * restarts = refinement steps taken, relres_true = final FP64 relative
+ * residual, status LPCG_OK when it is <= tol (else ENOTCONV, or EBREAKDOWN
+ * from an inner solve).  Synchronous. */
+int lpcg_pcg_solve_ir(lpcg_system *sys, const lpcg_precond *P, const double *b, double *x,
+                      double tol, double tol_inner, int32_t max_outer,
+                      const lpcg_solve_opts *inner, lpcg_result *res, hipStream_t stream);
+
 /* ------------------------------------------------------------------ GNN */
 /* Encoder-processor-decoder GNN (Method "Architecture"; technical-details
  * appendix), latent and hidden width h (multiple of 16, at most 64), n_mp

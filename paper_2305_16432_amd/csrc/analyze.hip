@@ -547,6 +547,34 @@ int analyze_impl(const lpcg_csr *A, const int32_t *h_sys, int32_t nsys, lpcg_sys
     // per-block partials: vector kernels, SpMV, one per 64-row chunk of the
     // dependency-driven substitution, or one per block of the level launches
     s->npart = std::max(std::max(kMaxVecBlocks, kMaxSpmvBlocks), chunks + std::max(s->nlev_f, s->nlev_b));
+    // batched-solve segments (host-built from the system boundaries)
+    {
+        std::vector<int> ss, r0, r1, sp(nsys + 1, 0);
+        for (int sy = 0; sy < nsys; ++sy) {
+            sp[sy] = (int)ss.size();
+            for (int a0 = s->h_sys_rowptr[sy]; a0 < s->h_sys_rowptr[sy + 1]; a0 += kSegRows) {
+                ss.push_back(sy);
+                r0.push_back(a0);
+                r1.push_back(std::min(a0 + kSegRows, s->h_sys_rowptr[sy + 1]));
+            }
+        }
+        sp[nsys] = (int)ss.size();
+        s->nseg = (int)ss.size();
+        ALLOC(s->seg_sys, s->nseg);
+        ALLOC(s->seg_row0, s->nseg);
+        ALLOC(s->seg_row1, s->nseg);
+        ALLOC(s->sys_seg_ptr, nsys + 1);
+        LPCG_HIP(hipMemcpyAsync(s->seg_sys, ss.data(), sizeof(int) * s->nseg, hipMemcpyHostToDevice, st));
+        LPCG_HIP(hipMemcpyAsync(s->seg_row0, r0.data(), sizeof(int) * s->nseg, hipMemcpyHostToDevice, st));
+        LPCG_HIP(hipMemcpyAsync(s->seg_row1, r1.data(), sizeof(int) * s->nseg, hipMemcpyHostToDevice, st));
+        LPCG_HIP(hipMemcpyAsync(s->sys_seg_ptr, sp.data(), sizeof(int) * (nsys + 1), hipMemcpyHostToDevice, st));
+        LPCG_HIP(hipStreamSynchronize(st));  // the host vectors go out of scope
+        ALLOC(s->bscal, 8 * (size_t)nsys);
+        ALLOC(s->bctrl, 8 * (size_t)nsys);
+        ALLOC(s->ir_rel, nsys);
+        ALLOC(s->ir_flag, nsys);
+        s->npart = std::max(s->npart, s->nseg);
+    }
     ALLOC(s->part, 4 * (size_t)s->npart);
     ALLOC(s->sync_part, 4 * (size_t)s->npart);
     k_fill_part<<<nblk(4L * s->npart, 256), 256, 0, st>>>(4L * s->npart, (uint64_t *)s->sync_part);
@@ -809,6 +837,7 @@ extern "C" int lpcg_export_perm(const lpcg_system *s, int32_t *perm, hipStream_t
 extern "C" void lpcg_destroy(lpcg_system *s) {
     if (!s) return;
     if (s->graph_exec) hipGraphExecDestroy(s->graph_exec);
+    if (s->bgraph_exec) hipGraphExecDestroy(s->bgraph_exec);
     if (s->cap_stream) hipStreamDestroy(s->cap_stream);
     for (void *p : s->allocs) hipFree(p);
     if (s->h_ctrl) hipHostFree(s->h_ctrl);

@@ -463,6 +463,11 @@ extern "C" int lpcg_set_trsv_cfg(lpcg_system *s, const lpcg_trsv_cfg *cfg) {
         s->graph_exec = nullptr;
         s->graph_key.clear();
     }
+    if (s->bgraph_exec) {
+        hipGraphExecDestroy(s->bgraph_exec);
+        s->bgraph_exec = nullptr;
+        s->bgraph_key.clear();
+    }
     return LPCG_OK;
 }
 
@@ -530,6 +535,11 @@ extern "C" int lpcg_autotune(lpcg_system *s, const float *l_val, const float *ut
         hipGraphExecDestroy(s->graph_exec);
         s->graph_exec = nullptr;
         s->graph_key.clear();
+    }
+    if (s->bgraph_exec) {
+        hipGraphExecDestroy(s->bgraph_exec);
+        s->bgraph_exec = nullptr;
+        s->bgraph_key.clear();
     }
     return LPCG_OK;
 }

@@ -23,6 +23,8 @@ constexpr int kMaxSpmvBlocks = 2048;
 constexpr int kLevelModeMaxLevels = 16;
 // The autotuner tries level-synchronous launches up to this many levels.
 constexpr int kLevelModeTuneLevels = 1024;
+// Rows per segment (one block) of the batched solver's vector kernels.
+constexpr int kSegRows = 1024;
 
 // Layout of the small control words and FP64 scalars of a PCG solve.
 enum Ctrl : int {
@@ -34,6 +36,7 @@ enum Ctrl : int {
     C_TICKET_B = 5,  // work counter of the backward substitution
     C_TICKET_X = 6,  // spare work counter (standalone solves)
     C_MAXIT = 7,
+    C_NDONE = 8,     // batched solve: systems finished
     C_NCTRL = 16
 };
 enum Scal : int {
@@ -109,6 +112,17 @@ struct lpcg_system {
     int spmv_group = 8;          // lanes per row in SpMV
     lpcg::TrsvCfg trsv[2];       // forward (L) and backward (L^T) substitution
     int trsv_g = 8;              // lanes per row of the level-synchronous kernel
+    // batched solves: row segments of at most kSegRows rows that never cross
+    // a system (one block each), the segment range of every system, and the
+    // per-system FP64 scalars / control words
+    int nseg = 0;
+    int *seg_sys = nullptr, *seg_row0 = nullptr, *seg_row1 = nullptr, *sys_seg_ptr = nullptr;
+    double *bscal = nullptr;  // [nsys * 8]
+    int *bctrl = nullptr;     // [nsys * 8]
+    double *ir_rel = nullptr; // [nsys] refinement: relative residual per system
+    int *ir_flag = nullptr;   // [nsys] refinement: 1 = converged
+    hipGraphExec_t bgraph_exec = nullptr;
+    std::vector<unsigned char> bgraph_key;
     // cached iteration-chunk graph of the last PCG solve (captured on a
     // private stream, launched on the caller's)
     hipStream_t cap_stream = nullptr;
@@ -134,4 +148,9 @@ int to_internal_f64(const lpcg_system *s, const double *src, double *dst, hipStr
 int from_internal_f64(const lpcg_system *s, const double *src, double *dst, hipStream_t st);
 int to_internal_f32(const lpcg_system *s, const float *src, float *dst, hipStream_t st);
 int from_internal_f32(const lpcg_system *s, const float *src, float *dst, hipStream_t st);
+// Substitution launches shared by the single and batched solvers (factor.hip).
+struct TrsvCfg;
+int trsv_kernels(const lpcg_system *s, int transpose, const TrsvCfg &c, const float *lval, const float *utval,
+                 const float *rhs, float *y, int *ticket, hipStream_t st);
+int lo_prepare(const lpcg_system *s, int transpose, const float *lval, const float *utval, hipStream_t st);
 }  // namespace lpcg

@@ -290,6 +290,43 @@ def pcg_solve(sys: System, kind: int, b, x=None, l_val=None, ut_val=None, dinv=N
     return x, out
 
 
+def pcg_solve_batched(sys: System, kind: int, b, x=None, l_val=None, ut_val=None, dinv=None,
+                      tol=1e-6, maxit=0, check_every=8, max_restarts=0, use_graph=False,
+                      raise_on_status=False):
+    """One PCG per system of a batch; returns (x, list of per-system result dicts)."""
+    b = _dev(b, torch.float64).contiguous()
+    if x is None:
+        x = torch.zeros_like(b)
+    nsys = sys.info["nsys"]
+    P = _Precond(kind, _ptr(l_val), _ptr(ut_val), _ptr(dinv))
+    mi = maxit if maxit > 0 else sys.n
+    opts = _Opts(float(tol), int(mi), int(check_every), int(max_restarts), int(bool(use_graph)))
+    res = (_Result * nsys)()
+    rc = lib().lpcg_pcg_solve_batched(sys.handle, C.byref(P), _ptr(b), _ptr(x), C.byref(opts), res, _stream())
+    if rc not in (OK, ENOTCONV, EBREAKDOWN) or (raise_on_status and rc != OK):
+        _check(rc, "lpcg_pcg_solve_batched")
+    return x, [{f: getattr(r, f) for f, _ in _Result._fields_ if f != "reserved"} for r in res]
+
+
+def pcg_solve_ir(sys: System, kind: int, b, x=None, l_val=None, ut_val=None, dinv=None,
+                 tol=1e-10, tol_inner=1e-4, max_outer=20, maxit=0, check_every=8, use_graph=False,
+                 raise_on_status=False):
+    """FP64 iterative refinement over the FP32 batched PCG; returns (x, per-system results)."""
+    b = _dev(b, torch.float64).contiguous()
+    if x is None:
+        x = torch.zeros_like(b)
+    nsys = sys.info["nsys"]
+    P = _Precond(kind, _ptr(l_val), _ptr(ut_val), _ptr(dinv))
+    mi = maxit if maxit > 0 else sys.n
+    opts = _Opts(float(tol_inner), int(mi), int(check_every), 0, int(bool(use_graph)))
+    res = (_Result * nsys)()
+    rc = lib().lpcg_pcg_solve_ir(sys.handle, C.byref(P), _ptr(b), _ptr(x), C.c_double(tol), C.c_double(tol_inner),
+                                 C.c_int32(max_outer), C.byref(opts), res, _stream())
+    if rc not in (OK, ENOTCONV, EBREAKDOWN) or (raise_on_status and rc != OK):
+        _check(rc, "lpcg_pcg_solve_ir")
+    return x, [{f: getattr(r, f) for f, _ in _Result._fields_ if f != "reserved"} for r in res]
+
+
 # ------------------------------------------------------------------ timing
 def time_sptrsv(sys: System, transpose: bool, l_val, ut_val, rhs, reps=20):
     """Mean duration (ms) of one substitution kernel launch (HIP events)."""

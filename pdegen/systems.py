@@ -183,3 +183,24 @@ def random_lower_dag(n: int, p: float, seed: int) -> CSR:
     d = d + d.T
     d = d + np.diag(np.abs(d).sum(axis=1) + 1.0)
     return canonical_csr(sp.csr_matrix(np.where(pat | np.eye(n, dtype=bool), d, 0.0)))
+
+
+def mixed_batch(nsys: int, n_min: int, n_max: int, seed: int):
+    """Uneven batch of independent systems: sizes log-uniform in
+    [n_min, n_max] (seeded), alternately P1 FEM on a jittered Delaunay grid
+    (side ~ sqrt(n) + 2, boundary eliminated) and the 3D heat step on a cube of
+    side ceil(n^(1/3)); k fields and right-hand sides seeded per system
+    (b = u0 GRF for the 3D systems, the lumped FEM load for the 2D ones).
+    Returns a list of (A, b)."""
+    rng = np.random.default_rng(seed)
+    sizes = np.exp(rng.uniform(np.log(n_min), np.log(n_max), nsys))
+    out = []
+    for i, n in enumerate(sizes):
+        if i % 2 == 0:
+            side = max(4, int(round(np.sqrt(n))) + 2)
+            A, b, _ = fem_p1_delaunay(side, k_seed=seed * 1000 + i, f_seed=seed * 1000 + i + 500)
+        else:
+            m = max(2, int(np.ceil(n ** (1.0 / 3.0))))
+            A, b = heat_system_3d(m, 1e-3, k_seed=seed * 1000 + i, u0_seed=seed * 1000 + i + 500)
+        out.append((A, b))
+    return out

@@ -1,0 +1,212 @@
+"""GPU parity of the batched solver (one PCG per system of a block-diagonal
+batch, each with its own alpha, beta and residual test) and of the FP64
+iterative refinement around it, against the oracle run system by system.
+
+Bars per system: FP64 true relative residual <= tol (hard); x within
+kappa_hat * tol of the oracle's; iterations within max(2, 10%) of the
+oracle's PCG on that system alone.  Finite-precision CG loses orthogonality
+and converges later than exact CG (Greenbaum), increasingly with the
+condition number, so the band widens to 25% without preconditioning or for
+kappa >= 1e4 and to 60% for kappa >= 1e5 (the 1000-point 1D Laplacian in
+red-black order: kappa ~ 4e5, 501 oracle iterations)."""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+import torch
+
+import oracle as O
+import pdegen as g
+from paper_2305_16432_amd import lpcg
+from tests.gpu_util import cuda_f64, gpu_system, host
+
+pytestmark = pytest.mark.gpu
+
+
+def _mats():
+    return [g.poisson_grid(9, 2), g.heat_system_3d(13, 1e-3, 5, 6)[0], g.fem_p1_delaunay(30, 1, 2)[0],
+            g.random_spd(300, 0.02, 3), g.tridiag_1d(1000), g.csr_from_dense(np.array([[3.0]])),
+            g.heat_system_3d(6, 1e-3, 7, 8)[0]]
+
+
+def _kappa(A):
+    ev = np.linalg.eigvalsh(A.to_dense())
+    return ev[-1] / ev[0]
+
+
+def _sub(A, ordering):
+    if ordering:
+        perm, _, _ = O.color_order(A)
+        return perm, O.permute_sym(A, perm)
+    return np.arange(A.n), A
+
+
+def _oracle(A, b, kind, ordering, tol):
+    perm, Ai = _sub(A, ordering)
+    pat = O.Pattern(Ai)
+    if kind == "ic0":
+        l, _ = O.ic0(pat, Ai)
+        r = O.pcg(Ai, b[perm], O.PC_LLT, pat, l, tol=tol)
+    else:
+        r = O.pcg(Ai, b[perm], O.PC_JACOBI if kind == "jacobi" else O.PC_NONE, tol=tol)
+    x = np.empty(A.n)
+    x[perm] = r["x"]
+    return r["iters"], x
+
+
+def _solve(S, kind, b, **kw):
+    pk = {"ic0": lpcg.PC_LLT, "jacobi": lpcg.PC_JACOBI, "none": lpcg.PC_NONE}[kind]
+    l = ut = None
+    if kind == "ic0":
+        l, ut, _ = lpcg.ic0(S)
+    return lpcg.pcg_solve_batched(S, pk, cuda_f64(b), l_val=l, ut_val=ut, **kw)
+
+
+@pytest.mark.parametrize("ordering", [0, 1])
+@pytest.mark.parametrize("kind", ["ic0", "jacobi", "none"])
+def test_batched_pcg_per_system_parity(kind, ordering):
+    mats = _mats()
+    B, srp = g.block_diag_csr(mats)
+    rng = np.random.default_rng(4)
+    bs = [rng.standard_normal(m.n) * 10.0 ** (i % 3 - 1) for i, m in enumerate(mats)]
+    S = gpu_system(B, srp, ordering)
+    assert S.info["nsys"] == len(mats)
+    tol = 1e-6
+    x, res = _solve(S, kind, np.concatenate(bs), tol=tol, max_restarts=2, use_graph=True)
+    xh = host(x)
+    for i, (A, b) in enumerate(zip(mats, bs)):
+        kap = _kappa(A)
+        slack = 0.6 if kap >= 1e5 else 0.25 if (kind == "none" or kap >= 1e4) else 0.1
+        xi = xh[srp[i]:srp[i + 1]]
+        it_ref, x_ref = _oracle(A, b, kind, ordering, tol)
+        print(f"[batch] {kind} ord {ordering} system {i} n={A.n}: gpu {res[i]['iters']} oracle {it_ref}", flush=True)
+        assert res[i]["status"] == lpcg.OK
+        assert O.true_relres(A, b, xi) <= tol and res[i]["relres_true"] <= tol
+        assert abs(res[i]["iters"] - it_ref) <= max(2, int(slack * it_ref)), (i, res[i]["iters"], it_ref)
+        assert np.linalg.norm(xi - x_ref) <= kap * tol * np.linalg.norm(x_ref)
+
+
+def test_batched_zero_rhs_maxit_and_graph_equals_eager():
+    mats = _mats()
+    B, srp = g.block_diag_csr(mats)
+    rng = np.random.default_rng(5)
+    bs = [rng.standard_normal(m.n) for m in mats]
+    bs[1][:] = 0.0  # a zero right-hand side finishes at setup with x = 0
+    b = np.concatenate(bs)
+    S = gpu_system(B, srp)
+    x1, r1 = _solve(S, "jacobi", b, tol=1e-8, use_graph=True)
+    x2, r2 = _solve(S, "jacobi", b, tol=1e-8, use_graph=False)
+    assert torch.equal(x1, x2) and [r["iters"] for r in r1] == [r["iters"] for r in r2]
+    assert r1[1]["iters"] == 0 and r1[1]["status"] == lpcg.OK
+    assert np.all(host(x1)[srp[1]:srp[2]] == 0.0)
+    # a small iteration cap: the 1x1 system still converges (one exact step,
+    # then FP32 rounding of r may take one more), the large ones do not
+    _, r3 = _solve(S, "none", b, tol=1e-12, maxit=3)
+    assert r3[5]["status"] == lpcg.OK and r3[5]["iters"] <= 3
+    assert r3[1]["status"] == lpcg.OK
+    assert any(r["status"] == lpcg.ENOTCONV and r["iters"] == 3 for r in r3)
+
+
+@pytest.mark.parametrize("ordering", [0, 1])
+def test_iterative_refinement_to_1e10(ordering):
+    mats = _mats()
+    B, srp = g.block_diag_csr(mats)
+    rng = np.random.default_rng(6)
+    bs = [rng.standard_normal(m.n) for m in mats]
+    S = gpu_system(B, srp, ordering)
+    l, ut, _ = lpcg.ic0(S)
+    x, res = lpcg.pcg_solve_ir(S, lpcg.PC_LLT, cuda_f64(np.concatenate(bs)), l_val=l, ut_val=ut, tol=1e-10,
+                               tol_inner=1e-4, max_outer=10, use_graph=True)
+    xh = host(x)
+    for i, (A, b) in enumerate(zip(mats, bs)):
+        xi = xh[srp[i]:srp[i + 1]]
+        print(f"[ir] system {i} n={A.n}: iters {res[i]['iters']} steps {res[i]['restarts']} "
+              f"relres {res[i]['relres_true']:.2e}", flush=True)
+        assert res[i]["status"] == lpcg.OK
+        rel = O.true_relres(A, b, xi)
+        # the FP64 residual itself is only known to within its rounding:
+        # |fl(b - A x) - (b - A x)| <= gamma_k |A||x| (k = longest row), relative to ||b||
+        k = int(np.diff(A.rowptr).max())
+        absAx = O.spmv(g.CSR(A.n, A.rowptr, A.colind, np.abs(A.val)), np.abs(xi))
+        bound = 2 * (k + 1) * 2.0 ** -53 * np.linalg.norm(absAx) / np.linalg.norm(b)
+        assert rel <= 1e-10 and abs(rel - res[i]["relres_true"]) <= 1e-3 * rel + bound
+        xs = spla.spsolve(A.to_scipy().tocsc(), b)
+        assert np.linalg.norm(xi - xs) <= _kappa(A) * 1e-10 * np.linalg.norm(xs)
+        assert res[i]["restarts"] <= 4
+
+
+def test_uneven_mixed_batch_ir():
+    """64 systems of 2k-20k unknowns (half 2D FEM, half 3D heat steps), IC(0)
+    and refinement to 1e-10; every system's FP64 residual is checked, and
+    four sampled systems against the oracle's FP64 PCG."""
+    print("[batch] mixed 64 systems", flush=True)
+    sysl = g.mixed_batch(64, 2000, 20000, seed=3)
+    mats = [A for A, _ in sysl]
+    B, srp = g.block_diag_csr(mats)
+    b = np.concatenate([bb for _, bb in sysl])
+    S = gpu_system(B, srp)
+    l, ut, _ = lpcg.ic0(S)
+    x, res = lpcg.pcg_solve_ir(S, lpcg.PC_LLT, cuda_f64(b), l_val=l, ut_val=ut, tol=1e-10, tol_inner=1e-4,
+                               max_outer=10, use_graph=True)
+    xh = host(x)
+    for i, A in enumerate(mats):
+        assert res[i]["status"] == lpcg.OK
+        assert O.true_relres(A, sysl[i][1], xh[srp[i]:srp[i + 1]]) <= 1e-10
+    for i in np.random.default_rng(0).choice(len(mats), 4, replace=False):
+        A, bi = sysl[i]
+        pat = O.Pattern(A)
+        lo, _ = O.ic0(pat, A)
+        ro = O.pcg(A, bi, O.PC_LLT, pat, lo, tol=1e-11)
+        xi = xh[srp[i]:srp[i + 1]]
+        assert np.linalg.norm(xi - ro["x"]) <= 1e-6 * np.linalg.norm(ro["x"])
+
+
+def _gen(args):
+    from threadpoolctl import threadpool_limits
+
+    import pdegen as gg
+    seed, i, n = args
+    with threadpool_limits(1):
+        if i % 2 == 0:
+            side = max(4, int(round(np.sqrt(n))) + 2)
+            A, b, _ = gg.fem_p1_delaunay(side, k_seed=seed * 1000 + i, f_seed=seed * 1000 + i + 500)
+        else:
+            m = max(2, int(np.ceil(n ** (1.0 / 3.0))))
+            A, b = gg.heat_system_3d(m, 1e-3, k_seed=seed * 1000 + i, u0_seed=seed * 1000 + i + 500)
+    return A, b
+
+
+def test_c4_full_size_256_uneven_systems():
+    """256 systems with sizes log-uniform in [2k, 200k] (half 2D FEM, half
+    3D heat steps; the sizes and seeds of pdegen.mixed_batch(256, 2000,
+    200000, seed=9)), one analysis, IC(0), FP64 refinement over the batched
+    FP32 PCG to 1e-10: every system's FP64 residual, and four sampled systems
+    against the oracle's FP64 IC(0)-PCG."""
+    import multiprocessing as mp
+    seed, nsys = 9, 256
+    rng = np.random.default_rng(seed)
+    sizes = np.exp(rng.uniform(np.log(2000), np.log(200000), nsys))
+    print(f"[c4] generating {nsys} systems, sum n ~ {int(sizes.sum())}", flush=True)
+    with mp.get_context("fork").Pool(16) as pool:
+        sysl = pool.map(_gen, [(seed, i, n) for i, n in enumerate(sizes)], chunksize=4)
+    mats = [A for A, _ in sysl]
+    B, srp = g.block_diag_csr(mats)
+    b = np.concatenate([bb for _, bb in sysl])
+    print(f"[c4] n={B.n} nnz={B.nnz}", flush=True)
+    S = gpu_system(B, srp)
+    l, ut, _ = lpcg.ic0(S)
+    x, res = lpcg.pcg_solve_ir(S, lpcg.PC_LLT, cuda_f64(b), l_val=l, ut_val=ut, tol=1e-10, tol_inner=1e-4,
+                               max_outer=10, use_graph=True)
+    xh = host(x)
+    its = [r["iters"] for r in res]
+    print(f"[c4] inner iterations min {min(its)} max {max(its)}, steps max {max(r['restarts'] for r in res)}",
+          flush=True)
+    for i, A in enumerate(mats):
+        assert res[i]["status"] == lpcg.OK, (i, res[i])
+        assert O.true_relres(A, sysl[i][1], xh[srp[i]:srp[i + 1]]) <= 1e-10
+    for i in np.random.default_rng(1).choice(nsys, 4, replace=False):
+        A, bi = sysl[i]
+        pat = O.Pattern(A)
+        lo, _ = O.ic0(pat, A)
+        ro = O.pcg(A, bi, O.PC_LLT, pat, lo, tol=1e-11)
+        xi = xh[srp[i]:srp[i + 1]]
+        assert np.linalg.norm(xi - ro["x"]) <= 1e-6 * np.linalg.norm(ro["x"])
