@@ -236,18 +236,36 @@ def pcg(A, b, kind=PC_LLT, pat=None, lval=None, tol=1e-6, maxit=None, x0=None,
         P.lrowptr, P.lcol, P.lval = _p(pat.lrowptr).value, _p(pat.lcol).value, _p(lv).value
         P.urowptr, P.ucol, P.uval = _p(pat.urowptr).value, _p(pat.ucol).value, _p(uv).value
     hist = np.zeros(maxit + 1)
+    coef = np.zeros(2 * (maxit + 1))
     pv = np.zeros((maxit, n)) if keep_p else None
     iters = C.c_int(0)
     relres = C.c_double(0)
     st = lib().orc_pcg(C.c_int(n), _p(_i32(A.rowptr)), _p(_i32(A.colind)), _p(_f64(A.val)),
                        _p(b), _p(x), C.byref(P), C.c_double(tol), C.c_int(maxit),
                        C.byref(iters), C.byref(relres), _p(hist),
-                       _p(pv) if keep_p else None)
-    out = dict(x=x, iters=iters.value, relres=relres.value, status=int(st),
-               hist=hist[:iters.value + 1].copy())
+                       _p(pv) if keep_p else None, _p(coef))
+    k = iters.value
+    out = dict(x=x, iters=k, relres=relres.value, status=int(st),
+               hist=hist[:k + 1].copy(), alpha=coef[2:2 * k + 2:2].copy(),
+               beta=coef[3:2 * k + 1:2].copy())
     if keep_p:
         out["P"] = pv[:iters.value].copy()
     return out
+
+
+def lanczos_extremes(alpha, beta):
+    """Extreme eigenvalues of the Lanczos tridiagonal of the preconditioned
+    operator built from PCG's coefficients (Golub & Van Loan, CG-Lanczos
+    connection): T_kk = 1/alpha_k + beta_{k-1}/alpha_{k-1},
+    T_k,k+1 = sqrt(beta_k)/alpha_k.  Returns (lambda_min, lambda_max)."""
+    from scipy.linalg import eigvalsh_tridiagonal
+    a = np.asarray(alpha, np.float64)
+    bt = np.asarray(beta, np.float64)[: len(a) - 1]
+    d = 1.0 / a
+    d[1:] += bt / a[:-1]
+    e = np.sqrt(bt) / a[:-1]
+    ev = eigvalsh_tridiagonal(d, e)
+    return float(ev[0]), float(ev[-1])
 
 
 def llt_loss(pat, lval, x, b, grad=True):

@@ -15,6 +15,11 @@
  *   - the data loss sum ||L L^T x - b||^2 (Method, equation loss_Ab) and its
  *     gradient with respect to the entries of L.
  *
+ * The PCG optionally records its coefficients (coef[2k] = alpha_k,
+ * coef[2k+1] = beta_k), from which the Lanczos tridiagonal of the
+ * preconditioned operator follows (the condition-number estimate of the
+ * appendix "Condition Number Comparison").
+ *
  * All arrays are host arrays.  Indices are int32, CSR rows sorted ascending.
  * Build: gcc -O2 -ffp-contract=off -shared -fPIC (no FMA contraction, so every
  * product and sum is rounded exactly as written).
@@ -297,7 +302,7 @@ enum { ORC_OK = 0, ORC_NOTCONV = 1, ORC_BREAKDOWN = 2 };
  * pvec (optional, n * (maxit+1)): the search directions p_1..p_k, for tests. */
 int orc_pcg(int n, const int *rowptr, const int *col, const double *val,
             const double *b, double *x, const orc_precond *P, double tol, int maxit,
-            int *iters, double *relres, double *hist, double *pvec)
+            int *iters, double *relres, double *hist, double *pvec, double *coef)
 {
     double *r = (double *)malloc(sizeof(double) * (size_t)n);
     double *z = (double *)malloc(sizeof(double) * (size_t)n);
@@ -330,6 +335,7 @@ int orc_pcg(int n, const int *rowptr, const int *col, const double *val,
         double pw = dot(n, p, w);
         if (!(pw > 0.0) || !isfinite(pw) || !isfinite(rz)) { status = ORC_BREAKDOWN; break; }
         double alpha = rz / pw;
+        if (coef) coef[2 * k] = alpha;                  /* alpha_k */
         for (int i = 0; i < n; ++i) x[i] = x[i] + alpha * p[i];
         for (int i = 0; i < n; ++i) r[i] = r[i] - alpha * w[i];
         rn = sqrt(dot(n, r, r));
@@ -339,6 +345,7 @@ int orc_pcg(int n, const int *rowptr, const int *col, const double *val,
         apply_prec(n, P, r, z, t);                      /* Solve P z_k = r_k */
         double rz_new = dot(n, r, z);
         double beta = rz_new / rz;                      /* beta_k */
+        if (coef) coef[2 * k + 1] = beta;
         for (int i = 0; i < n; ++i) p[i] = z[i] + beta * p[i];
         rz = rz_new;
     }
