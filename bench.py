@@ -34,6 +34,28 @@ sys.path.insert(0, ROOT)
 WEIGHTS = {"natural": os.path.join(ROOT, "paper_2305_16432_amd", "weights", "heat3d_h32_mp3.npz"),
            "color": os.path.join(ROOT, "paper_2305_16432_amd", "weights", "heat3d_h32_mp3_color.npz")}
 PEAK_HBM = 8000.0  # GB/s, MI355X HBM3E
+# HBM bytes of the roofline kernel measured with rocprofv3 --pmc FETCH_SIZE /
+# WRITE_SIZE (scaled by the same counters on a copy of known size); valid
+# only while the kernel source is the one that was profiled.
+TRAFFIC = os.path.join(ROOT, "profiles", "sptrsv_forward_heat3d_64_traffic.json")
+TRAFFIC_SRC = [os.path.join(ROOT, "paper_2305_16432_amd", "csrc", "kern_sptrsv.h")]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch from the committed counter summary, or None when
+    absent, for another kernel, or taken on a different kernel source."""
+    import hashlib
+    if not os.path.exists(TRAFFIC):
+        return None
+    with open(TRAFFIC) as f:
+        t = json.load(f)
+    h = hashlib.sha256()
+    for p in TRAFFIC_SRC:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    if t.get("kernel") != kernel or t.get("source_sha256") != h.hexdigest():
+        return None
+    return t.get("bytes_per_launch")
 
 
 def _log(msg):
@@ -85,6 +107,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--orderings", default="natural,color")
     ap.add_argument("--methods", default="learned,ic0,jacobi")
+    ap.add_argument("--calibrate-copy", type=int, default=0,
+                    help="MiB of a plain device copy to run first (counter calibration under rocprofv3 --pmc)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: runs on one GPU; --gpus {args.gpus} is not supported "
@@ -97,6 +121,13 @@ def main():
     from paper_2305_16432_amd import lpcg
 
     torch.cuda.set_device(0)
+    if args.calibrate_copy > 0:  # a copy of known size: reads and writes calibrate_copy MiB each
+        src = torch.ones(args.calibrate_copy * 2 ** 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        _log(f"calibration copy of {args.calibrate_copy} MiB done")
+        del src, dst
     A, b = g.heat_system_3d(args.m, 1e-3, args.k_seed, args.u_seed)
     _log(f"system n={A.n} nnz={A.nnz}")
     bd = torch.as_tensor(b).cuda()
@@ -117,16 +148,19 @@ def main():
         def run_ic0():
             lpcg.ic0(S, 0.0, 8, lval, utval)
 
+        maxit = A.n
+        coef = torch.zeros(2 * (maxit + 1), dtype=torch.float64, device="cuda")
+
         def solve_llt():
             x.zero_()
-            return lpcg.pcg_solve(S, lpcg.PC_LLT, bd, x=x, l_val=lval, ut_val=utval, **solve_kw)[1]
+            return lpcg.pcg_solve(S, lpcg.PC_LLT, bd, x=x, l_val=lval, ut_val=utval, coef=coef, **solve_kw)[1]
 
         def run_jacobi():
             lpcg.jacobi(S, dinv)
 
         def solve_jacobi():
             x.zero_()
-            return lpcg.pcg_solve(S, lpcg.PC_JACOBI, bd, x=x, dinv=dinv, **solve_kw)[1]
+            return lpcg.pcg_solve(S, lpcg.PC_JACOBI, bd, x=x, dinv=dinv, coef=coef, **solve_kw)[1]
 
         # per-pattern tuning of the substitution kernels (like the analysis,
         # done once per sparsity pattern, outside the timed region)
@@ -171,10 +205,14 @@ def main():
             torch.cuda.synchronize()
             wall = (time.perf_counter() - wall0) * 1e3 / args.steps
             key = name if ordering == "natural" else f"{name}_{ordering}"
+            # condition number of the preconditioned operator from the last
+            # solve's coefficients (Lanczos; host work outside the timed region)
+            lmin, lmax = lpcg.lanczos_extremes(coef, res["iters"]) if res["restarts"] == 0 else (None, None)
             results[key] = dict(ms=float(np.mean(np.array(t_pre) + np.array(t_solve))),
                                 precompute_ms=float(np.mean(t_pre)), solve_ms=float(np.mean(t_solve)),
                                 wall_ms=wall, iters=int(np.max(iters)), relres_true=float(np.max(relres)),
                                 status=res["status"], ordering=ordering,
+                                kappa_lanczos=(lmax / lmin) if lmin else None,
                                 us_per_iter=float(np.mean(t_solve)) * 1e3 / max(1, int(np.max(iters))))
             _log(f"{key}: {results[key]}")
         # kernel timings in this ordering (HIP events around each launch on its stream)
@@ -228,7 +266,7 @@ def main():
         "methods": results,
         "roofline": {"bound": "hbm", "kernel": f"sptrsv_forward ({head_order} order)",
                      "achieved": kf["gbs"], "peak": PEAK_HBM, "unit": "GB/s", "frac": kf["gbs"] / PEAK_HBM,
-                     "traffic": None, "bytes_per_launch": kf["bytes"], "us_per_launch": kf["us"],
+                     "traffic": measured_traffic(f"sptrsv_forward ({head_order} order)"), "bytes_per_launch": kf["bytes"], "us_per_launch": kf["us"],
                      "levels": kernels[head_order]["levels"], "kernels": kernels},
         "cpu_baseline": cpu,
     }

@@ -252,10 +252,19 @@ typedef struct {
  * products r.z and p.w and the norms are accumulated in FP64, the true
  * residual is FP64.  res (HOST) receives the outcome.  hist (device FP64
  * [maxit+1] or NULL) receives ||r_k||/||b|| for k = 0..iters of the last
- * restart.  Synchronous.  Returns res->status. */
+ * restart.  coef (device FP64 [2 (maxit+1)] or NULL) receives alpha_k at
+ * coef[2k] and beta_k at coef[2k+1] of the last restart (for
+ * lpcg_lanczos_extremes).  Synchronous.  Returns res->status. */
 int lpcg_pcg_solve(lpcg_system *sys, const lpcg_precond *P, const double *b,
                    double *x, const lpcg_solve_opts *opts, lpcg_result *res,
-                   double *hist, hipStream_t stream);
+                   double *hist, double *coef, hipStream_t stream);
+
+/* Condition-number estimate of the preconditioned operator (appendix
+ * "Condition Number Comparison"): extreme eigenvalues of the CG-Lanczos
+ * tridiagonal built from k iterations' coefficients (HOST coef as written by
+ * lpcg_pcg_solve: coef[2i] = alpha_i, coef[2i+1] = beta_i), by Sturm-count
+ * bisection.  kappa ~ lmax / lmin.  Errors: EINVAL (k < 1, alpha <= 0). */
+int lpcg_lanczos_extremes(const double *coef, int32_t k, double *lmin, double *lmax);
 
 /* Batched PCG: one PCG (Appendix algorithm) per system of a block-diagonal
  * batch (lpcg_analyze with sys_rowptr), each with its own alpha, beta,

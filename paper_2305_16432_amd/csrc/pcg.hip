@@ -31,6 +31,7 @@
 // Jacobi and none form z = dinv r / r on the fly, so an iteration is two
 // launches; LLT adds the substitutions.
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 
 #include "device_util.h"
@@ -65,7 +66,7 @@ struct Args {
     uint32_t *y, *z;
     double *part_rr, *part_rz, *part_pw, *part_bb;  // plain partials (setup, true residual)
     double *sp_rz, *sp_pw, *sp_rr, *sp_rz2;          // published partials (reducer-block sums)
-    double *scal, *hist;
+    double *scal, *hist, *coef;
     int *ctrl;
     double tol2;
 };
@@ -166,6 +167,7 @@ __device__ __forceinline__ void finish_rz(const Args &a, double *lds) {
         const double old = a.scal[S_RZ0];
         a.scal[S_BETA] = it == 0 ? 0.0 : rz / old;
         a.scal[S_RZ0] = rz;
+        if (a.coef && it >= 1 && it <= a.maxit) a.coef[2 * it + 1] = rz / old;
     }
 }
 
@@ -257,6 +259,7 @@ __global__ void __launch_bounds__(kWgThreads) k_llt_wg(Args a, int do_fwd, int d
             const double old = a.scal[S_RZ0];
             a.scal[S_BETA] = it == 0 ? 0.0 : t / old;
             a.scal[S_RZ0] = t;
+            if (a.coef && it >= 1 && it <= a.maxit) a.coef[2 * it + 1] = t / old;
         }
     }
 }
@@ -312,6 +315,7 @@ __global__ void __launch_bounds__(VT) k_spmv_pw(Args a) {
             a.ctrl[C_ITERS] = it + 1;
         } else {
             a.scal[S_ALPHA] = rz / pwt;
+            if (a.coef && it + 1 <= a.maxit) a.coef[2 * (it + 1)] = rz / pwt;
         }
     }
 }
@@ -355,6 +359,7 @@ __global__ void __launch_bounds__(VT) k_xr(Args a) {
             const double old = a.scal[S_RZ0];
             a.scal[S_BETA] = rzt / old;
             a.scal[S_RZ0] = rzt;
+            if (a.coef && it >= 1 && it <= a.maxit) a.coef[2 * it + 1] = rzt / old;
         } else {
             a.ctrl[C_TICKET_F] = 0;
             a.ctrl[C_TICKET_B] = 0;
@@ -507,7 +512,7 @@ int run_solve(lpcg_system *s, const Args &a, const lpcg_solve_opts &o, int &iter
 using namespace lpcg;
 
 extern "C" int lpcg_pcg_solve(lpcg_system *s, const lpcg_precond *P, const double *b, double *x,
-                              const lpcg_solve_opts *opts, lpcg_result *res, double *hist,
+                              const lpcg_solve_opts *opts, lpcg_result *res, double *hist, double *coef,
                               hipStream_t st) {
     if (!s || !P || !b || !x || !opts || !res || !(opts->tol >= 0)) {
         set_error("lpcg_pcg_solve: invalid arguments");
@@ -587,6 +592,7 @@ extern "C" int lpcg_pcg_solve(lpcg_system *s, const lpcg_precond *P, const doubl
     a.sp_rz2 = s->sync_part + 3 * (size_t)s->npart;
     a.scal = s->scal;
     a.hist = hist;
+    a.coef = coef;
     a.ctrl = s->ctrl;
     a.tol2 = opts->tol * opts->tol;
     if (P->kind == LPCG_PC_LLT) {  // level-ordered factor values for the single-workgroup mode
@@ -639,4 +645,59 @@ extern "C" int lpcg_pcg_solve(lpcg_system *s, const lpcg_precond *P, const doubl
     if (status == LPCG_ENOTCONV) set_error("pcg: no convergence within maxit");
     if (status == LPCG_EBREAKDOWN) set_error("pcg: breakdown (p.Ap <= 0 or non-finite)");
     return status;
+}
+
+// Extreme eigenvalues of the CG-Lanczos tridiagonal T_k of the preconditioned
+// operator (appendix "Condition Number Comparison"): T_ii = 1/alpha_i +
+// beta_{i-1}/alpha_{i-1}, T_i,i+1 = sqrt(beta_i)/alpha_i.  Each extreme is
+// found by bisection on the Sturm count (number of eigenvalues below x) inside
+// the Gershgorin interval.
+extern "C" int lpcg_lanczos_extremes(const double *coef, int32_t k, double *lmin, double *lmax) {
+    if (!coef || k < 1 || !lmin || !lmax) {
+        set_error("lpcg_lanczos_extremes: invalid arguments");
+        return LPCG_EINVAL;
+    }
+    std::vector<double> d(k), e2(k, 0.0), e(k, 0.0);
+    for (int i = 0; i < k; ++i) {
+        const double al = coef[2 * (i + 1)];
+        if (!(al > 0) || !std::isfinite(al)) {
+            set_error("lpcg_lanczos_extremes: alpha_%d = %g is not positive", i + 1, al);
+            return LPCG_EINVAL;
+        }
+        d[i] = 1.0 / al;
+        if (i > 0) d[i] += coef[2 * i + 1] / coef[2 * i];
+        if (i + 1 < k) {
+            const double be = coef[2 * (i + 1) + 1];
+            e[i] = std::sqrt(std::max(be, 0.0)) / al;
+            e2[i] = e[i] * e[i];
+        }
+    }
+    double lo = d[0], hi = d[0];
+    for (int i = 0; i < k; ++i) {
+        const double r = (i > 0 ? e[i - 1] : 0.0) + (i + 1 < k ? e[i] : 0.0);
+        lo = std::min(lo, d[i] - r);
+        hi = std::max(hi, d[i] + r);
+    }
+    auto below = [&](double x) {  // eigenvalues of T smaller than x
+        int c = 0;
+        double q = 1.0;
+        for (int i = 0; i < k; ++i) {
+            q = d[i] - x - (i > 0 ? e2[i - 1] / q : 0.0);
+            if (q == 0.0) q = -1e-300;
+            if (q < 0) ++c;
+        }
+        return c;
+    };
+    auto kth = [&](int idx) {  // idx-th smallest eigenvalue (0-based)
+        double a = lo, b = hi;
+        for (int it = 0; it < 200 && b - a > 1e-15 * std::max(std::fabs(a), std::fabs(b)); ++it) {
+            const double m = 0.5 * (a + b);
+            if (below(m) > idx) b = m;
+            else a = m;
+        }
+        return 0.5 * (a + b);
+    };
+    *lmin = kth(0);
+    *lmax = kth(k - 1);
+    return LPCG_OK;
 }

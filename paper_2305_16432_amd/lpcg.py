@@ -270,8 +270,9 @@ def jacobi(sys: System, out=None):
 # ---------------------------------------------------------------------- PCG
 def pcg_solve(sys: System, kind: int, b, x=None, l_val=None, ut_val=None, dinv=None,
               tol=1e-6, maxit=0, check_every=8, max_restarts=0, use_graph=False,
-              hist=False, raise_on_status=False):
-    """Returns (x, result dict[, hist tensor])."""
+              hist=False, raise_on_status=False, coef=None):
+    """Returns (x, result dict[, hist tensor]).  coef: optional device FP64
+    tensor of 2 (maxit + 1) entries that receives alpha_k / beta_k."""
     b = _dev(b, torch.float64).contiguous()
     if x is None:
         x = torch.zeros_like(b)
@@ -280,8 +281,10 @@ def pcg_solve(sys: System, kind: int, b, x=None, l_val=None, ut_val=None, dinv=N
     opts = _Opts(float(tol), int(mi), int(check_every), int(max_restarts), int(bool(use_graph)))
     res = _Result()
     h = torch.full((mi + 1,), float("nan"), dtype=torch.float64, device="cuda") if hist else None
+    if coef is not None and coef.numel() < 2 * (mi + 1):
+        raise ValueError("coef needs 2 (maxit + 1) entries")
     rc = lib().lpcg_pcg_solve(sys.handle, C.byref(P), _ptr(b), _ptr(x), C.byref(opts),
-                              C.byref(res), _ptr(h), _stream())
+                              C.byref(res), _ptr(h), _ptr(coef), _stream())
     if rc not in (OK, ENOTCONV, EBREAKDOWN) or (raise_on_status and rc != OK):
         _check(rc, "lpcg_pcg_solve")
     out = {f: getattr(res, f) for f, _ in _Result._fields_ if f != "reserved"}
@@ -325,6 +328,17 @@ def pcg_solve_ir(sys: System, kind: int, b, x=None, l_val=None, ut_val=None, din
     if rc not in (OK, ENOTCONV, EBREAKDOWN) or (raise_on_status and rc != OK):
         _check(rc, "lpcg_pcg_solve_ir")
     return x, [{f: getattr(r, f) for f, _ in _Result._fields_ if f != "reserved"} for r in res]
+
+
+def lanczos_extremes(coef, iters: int):
+    """(lambda_min, lambda_max) of the preconditioned operator estimated from
+    the PCG coefficients (host computation in the library)."""
+    import numpy as np
+    c = np.ascontiguousarray(coef.detach().cpu().numpy() if torch.is_tensor(coef) else coef, dtype=np.float64)
+    lo, hi = C.c_double(0), C.c_double(0)
+    _check(lib().lpcg_lanczos_extremes(c.ctypes.data_as(C.c_void_p), C.c_int32(iters), C.byref(lo), C.byref(hi)),
+           "lpcg_lanczos_extremes")
+    return lo.value, hi.value
 
 
 # ------------------------------------------------------------------ timing
