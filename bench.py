@@ -205,9 +205,13 @@ def main():
             torch.cuda.synchronize()
             wall = (time.perf_counter() - wall0) * 1e3 / args.steps
             key = name if ordering == "natural" else f"{name}_{ordering}"
-            # condition number of the preconditioned operator from the last
-            # solve's coefficients (Lanczos; host work outside the timed region)
-            lmin, lmax = lpcg.lanczos_extremes(coef, res["iters"]) if res["restarts"] == 0 else (None, None)
+            # condition number of the preconditioned operator (Lanczos, from the
+            # coefficients of one more solve without restarts; outside the
+            # timed region)
+            solve_kw["max_restarts"] = 0
+            r0 = solve()
+            solve_kw["max_restarts"] = 2
+            lmin, lmax = lpcg.lanczos_extremes(coef, r0["iters"]) if r0["iters"] > 0 else (None, None)
             results[key] = dict(ms=float(np.mean(np.array(t_pre) + np.array(t_solve))),
                                 precompute_ms=float(np.mean(t_pre)), solve_ms=float(np.mean(t_solve)),
                                 wall_ms=wall, iters=int(np.max(iters)), relres_true=float(np.max(relres)),
