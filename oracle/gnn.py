@@ -31,6 +31,10 @@ Readings where the paper is silent (each listed in the design notes):
     d_ii = 0), so L_ii = sqrt(A_ii) L'_ii and L_ij = sqrt(A_jj) (d_ij + d_ji)/2.
     Zero decoder output gives L' = I, i.e. P = diag(A), in modes 1 and 2.
 
+frobenius_loss: the loss_A ablation of the loss-function section, pinned by
+a dense computation, finite differences, zero at an exact Cholesky factor
+and a closed form for a diagonal L (tests/test_oracle_frobenius.py).
+
 Pins (tests/test_oracle_gnn.py): all-zero weights give a closed form; a
 2-node graph computed by hand; permutation equivariance; 5-hop locality;
 the reverse-mode derivative against central finite differences, the
@@ -200,6 +204,24 @@ def training_loss(A, b, x, lval, pat_lrowptr, pat_lcol, llt_loss):
     _, rms = normalisation(A, b)
     loss, g = llt_loss(lval, x, b)
     return loss / rms ** 2, g / rms ** 2
+
+
+def frobenius_loss(A, lval, lrowptr, lcol):
+    """The Frobenius loss of equation loss_A for one system,
+    ||L L^T - A||_F^2 over every entry (the fill of L L^T included), divided
+    by s^2 with s = mean(diag A) (scale-free reading), and its gradient with
+    respect to the stored entries of L: d/dL_ij = 4 ((L L^T - A) L)_ij.
+    Sparse products (scipy) on the explicit matrices."""
+    import scipy.sparse as sp
+    n = A.n
+    L = sp.csr_matrix((np.asarray(lval, np.float64), np.asarray(lcol), np.asarray(lrowptr)), shape=(n, n))
+    E = (L @ L.T - A.to_scipy()).tocsr()
+    s, _ = normalisation(A, np.ones(n))
+    loss = float(np.sum(E.data ** 2))
+    G = (E @ L).tocsr()
+    rows = np.repeat(np.arange(n), np.diff(lrowptr))
+    g = 4.0 * np.asarray(G[rows, np.asarray(lcol)]).ravel()
+    return loss / s ** 2, g / s ** 2
 
 
 def adam(params, grads, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
