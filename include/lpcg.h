@@ -355,6 +355,17 @@ int lpcg_gnn_backward(const lpcg_system *sys, const lpcg_gnn *net, void *ws,
 int lpcg_llt_loss(const lpcg_system *sys, const float *l_val, const double *x,
                   const double *b, double *loss, float *dl_val, hipStream_t stream);
 
+/* Frobenius loss of equation loss_A (the ablation of the loss-function
+ * section): per system ||L L^T - A||_F^2 / s^2 over every entry of
+ * L L^T - A (fill included), s = mean(diag A) of the system, into loss[nsys]
+ * (device FP64), and when dl_val is given the gradient
+ * 4 (L L^T - A) L / s^2 on L's entries (FP32 [nnz_l], L order).  The pattern
+ * of L L^T - A is built at the first call on a system (synchronous; it
+ * allocates); later calls only enqueue.  Errors: EINVAL when a row of
+ * L L^T - A has more than 256 entries, ENOMEM. */
+int lpcg_frob_loss(lpcg_system *sys, const float *l_val, double *loss, float *dl_val,
+                   hipStream_t stream);
+
 /* Adam step on FP32 master weights (in place): m = b1 m + (1-b1) g,
  * v = b2 v + (1-b2) g^2, p -= lr * (m / (1-b1^t)) / (sqrt(v / (1-b2^t)) + eps)
  * with t = step (>= 1). */

@@ -121,6 +121,10 @@ struct lpcg_system {
     int *bctrl = nullptr;     // [nsys * 8]
     double *ir_rel = nullptr; // [nsys] refinement: relative residual per system
     int *ir_flag = nullptr;   // [nsys] refinement: 1 = converged
+    // Frobenius loss: CSR pattern of E = L L^T - A (built at the first call)
+    int nnz_e = 0;
+    int *erp = nullptr, *ecol = nullptr;
+    double *eval = nullptr, *erowsq = nullptr;
     hipGraphExec_t bgraph_exec = nullptr;
     std::vector<unsigned char> bgraph_key;
     // cached iteration-chunk graph of the last PCG solve (captured on a

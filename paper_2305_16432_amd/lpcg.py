@@ -464,6 +464,14 @@ def llt_loss(sys: System, l_val, x, b, grad=True):
     return loss, dl
 
 
+def frob_loss(sys: System, l_val, grad=True):
+    """Per-system ||L L^T - A||_F^2 / s^2 (device FP64 [nsys]) and its gradient."""
+    loss = torch.empty(sys.info["nsys"], dtype=torch.float64, device="cuda")
+    dl = torch.empty_like(l_val) if grad else None
+    _check(lib().lpcg_frob_loss(sys.handle, _ptr(l_val), _ptr(loss), _ptr(dl), _stream()), "lpcg_frob_loss")
+    return loss, dl
+
+
 def adam_step(params, grads, m, v, lr, step, beta1=0.9, beta2=0.999, eps=1e-8):
     rc = lib().lpcg_adam_step(_ptr(params), _ptr(grads), _ptr(m), _ptr(v), C.c_int64(params.numel()),
                               C.c_float(lr), C.c_float(beta1), C.c_float(beta2), C.c_float(eps),

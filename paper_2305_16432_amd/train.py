@@ -76,6 +76,8 @@ def main():
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--diag-mode", type=int, default=1)
     ap.add_argument("--ordering", choices=["natural", "color"], default="natural")
+    ap.add_argument("--loss", choices=["data", "frobenius"], default="data",
+                    help="data: ||L L^T x - b||^2 (equation loss_Ab); frobenius: ||L L^T - A||_F^2 (loss_A ablation)")
     ap.add_argument("--rhs", choices=["grf", "white", "mix"], default="grf",
                     help="training right-hand sides: smooth GRF states, white noise, or both")
     ap.add_argument("--seed", type=int, default=0)
@@ -143,7 +145,10 @@ def main():
         bb = db[idx].reshape(-1).contiguous()
         xb = dx[idx].reshape(-1).contiguous()
         L = lpcg.gnn_forward_train(S, params, h, n_mp, bb, ws, diag_mode=dm)
-        loss, dl = lpcg.llt_loss(S, L, xb, bb)
+        if args.loss == "data":
+            loss, dl = lpcg.llt_loss(S, L, xb, bb)
+        else:
+            loss, dl = lpcg.frob_loss(S, L)
         grad = lpcg.gnn_backward(S, params, h, n_mp, ws, dl, diag_mode=dm)
         lpcg.adam_step(params, grad, m1, v1, args.lr, step)
         if step % 10 == 0:

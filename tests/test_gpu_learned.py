@@ -87,3 +87,21 @@ def test_trained_network_matches_oracle_on_heldout():
     ro = O.pcg(A, b, O.PC_LLT, pat, lref, tol=1e-6)
     assert ro["status"] == O.OK and r["status"] == 0
     assert abs(r["iters"] - ro["iters"]) <= max(2, 0.1 * ro["iters"]), (r["iters"], ro["iters"])
+
+
+@pytest.mark.parametrize("k_seed,u_seed", [(7001, 8001), (7002, 8002)])
+def test_data_loss_beats_frobenius_loss(k_seed, u_seed):
+    """The loss ablation of the paper: the same architecture trained with the
+    Frobenius loss ||L L^T - A||_F^2 (equation loss_A) instead of the data loss
+    (equation loss_Ab) needs more PCG iterations on held-out 64^3 systems."""
+    W = np.load(os.path.join(WDIR, "heat3d_h32_mp3_frobenius.npz"))
+    pf = torch.as_tensor(W["params"].astype(np.float32)).cuda()
+    pd_, h, n_mp, dm = _load(0)
+    assert (int(W["h"]), int(W["n_mp"]), int(W["diag_mode"])) == (h, n_mp, dm)
+    A, b = g.heat_system_3d(64, 1e-3, k_seed, u_seed)
+    S = gpu_system(A)
+    bd = cuda_f64(b)
+    it_data = _iters_learned(S, pd_, h, n_mp, dm, bd)
+    it_frob = _iters_learned(S, pf, h, n_mp, dm, bd)
+    print(f"[loss ablation] seeds ({k_seed},{u_seed}): data loss {it_data}, Frobenius loss {it_frob}", flush=True)
+    assert it_data < 0.8 * it_frob

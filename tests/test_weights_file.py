@@ -12,7 +12,8 @@ WDIR = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
                     "weights")
 
 
-@pytest.mark.parametrize("fname,ordering", [("heat3d_h32_mp3.npz", 0), ("heat3d_h32_mp3_color.npz", 1)])
+@pytest.mark.parametrize("fname,ordering", [("heat3d_h32_mp3.npz", 0), ("heat3d_h32_mp3_color.npz", 1),
+                                            ("heat3d_h32_mp3_frobenius.npz", 0)])
 def test_weights_file_layout(fname, ordering):
     W = np.load(os.path.join(WDIR, fname))  # allow_pickle stays False
     h, n_mp, dm = int(W["h"]), int(W["n_mp"]), int(W["diag_mode"])
