@@ -98,10 +98,14 @@ def reverse_map(A):
     return q
 
 
-def forward(A, b, P, h, n_mp, rev=None, keep=False, diag_mode=0):
+def forward(A, b, P, h, n_mp, rev=None, keep=False, diag_mode=0, x_head=False):
     """L values on the lower pattern (i >= j) in CSR order, float64.
 
     Returns (lval, cache) where cache (if keep) holds what backward needs.
+    With x_head the node decoder regresses the normalised solution from the
+    final node latents (appendix "Comparison with Starting Guess"): the cache
+    is always returned and holds xhat (normalised units, x s / rms(b)) and x0
+    (the starting guess in the system's units).
     """
     row = A.row_of_entry().astype(np.int64)
     col = A.colind.astype(np.int64)
@@ -125,6 +129,11 @@ def forward(A, b, P, h, n_mp, rev=None, keep=False, diag_mode=0):
         Es.append(E)
     d, caches["dec"] = _mlp_fwd(P, "dec", E)
     d = d[:, 0]
+    xhat = None
+    if x_head:
+        xo, caches["xdec"] = _mlp_fwd(P, "xdec", V)
+        xhat = xo[:, 0]
+        keep = True
     lower = col <= row
     diag = col == row
     if diag_mode == 0:
@@ -144,12 +153,13 @@ def forward(A, b, P, h, n_mp, rev=None, keep=False, diag_mode=0):
     if keep:
         cache = dict(row=row, col=col, rev=rev, s=s, rms=rms, d=d, lower=lower, diag=diag,
                      Vs=Vs, Es=Es, mlp=caches, n=n, h=h, n_mp=n_mp, diag_mode=diag_mode,
-                     colscale=colscale)
+                     colscale=colscale, xhat=xhat, x0=None if xhat is None else xhat * rms / s)
     return lval, cache
 
 
-def backward(P, cache, glval):
-    """Gradients of sum(glval * lval) w.r.t. every parameter (float64 dict)."""
+def backward(P, cache, glval, gxhat=None):
+    """Gradients of sum(glval * lval) (+ sum(gxhat * xhat) with the x_hat
+    head) w.r.t. every parameter (float64 dict)."""
     G = {k: np.zeros_like(v) for k, v in P.items()}
     row, col, rev = cache["row"], cache["col"], cache["rev"]
     n, h, n_mp = cache["n"], cache["h"], cache["n_mp"]
@@ -179,6 +189,8 @@ def backward(P, cache, glval):
     gE = _mlp_bwd(P, "dec", cache["mlp"]["dec"], gd[:, None], G)
     Vs, Es = cache["Vs"], cache["Es"]
     gV = np.zeros((n, h))
+    if gxhat is not None:  # the x_hat head reads the final node latents
+        gV = _mlp_bwd(P, "xdec", cache["mlp"]["xdec"], np.asarray(gxhat, np.float64)[:, None], G)
     for t in range(n_mp - 1, -1, -1):
         gX = _mlp_bwd(P, f"mp{t}.edge", cache["mlp"][f"mp{t}.edge"], gE, G)
         gE = gX[:, :h].copy()
@@ -204,6 +216,14 @@ def training_loss(A, b, x, lval, pat_lrowptr, pat_lcol, llt_loss):
     _, rms = normalisation(A, b)
     loss, g = llt_loss(lval, x, b)
     return loss / rms ** 2, g / rms ** 2
+
+
+def x0_loss(A, b, x, xhat):
+    """Regression loss of the x_hat head for one system: ||xhat - x s/rms(b)||^2
+    in the network's normalised units, and its gradient w.r.t. xhat."""
+    s, rms = normalisation(A, b)
+    d = np.asarray(xhat, np.float64) - np.asarray(x, np.float64) * s / rms
+    return float(d @ d), 2.0 * d
 
 
 def frobenius_loss(A, lval, lrowptr, lcol):

@@ -9,6 +9,8 @@ hidden width h, and n_mp message-passing layers with separate weights:
   mp{t}.node : Lin(2h, h) - ReLU - Lin(h, h)      input [v_i, m_i]
   mp{t}.edge : Lin(3h, h) - ReLU - Lin(h, h)      input [e_ij, v_i, v_j]
   dec      : Lin(h, h)  - ReLU - Lin(h, 1)
+  xdec     : Lin(h, h)  - ReLU - Lin(h, 1)       (optional x_hat_0 head on the
+                                                 final node latents)
 
 A Linear layer maps x -> x W + b with W stored [fan_in, fan_out] row-major.
 """
@@ -17,7 +19,7 @@ from __future__ import annotations
 import numpy as np
 
 
-def gnn_param_shapes(h: int, n_mp: int) -> list[tuple[str, tuple[int, ...]]]:
+def gnn_param_shapes(h: int, n_mp: int, x_head: bool = False) -> list[tuple[str, tuple[int, ...]]]:
     out: list[tuple[str, tuple[int, ...]]] = []
 
     def mlp(prefix, fin, fout):
@@ -30,16 +32,19 @@ def gnn_param_shapes(h: int, n_mp: int) -> list[tuple[str, tuple[int, ...]]]:
         mlp(f"mp{t}.node", 2 * h, h)
         mlp(f"mp{t}.edge", 3 * h, h)
     mlp("dec", h, 1)
+    if x_head:
+        mlp("xdec", h, 1)
     return out
 
 
 def init_gnn_params(h: int, n_mp: int, seed: int, gain: float = 1.0,
-                    zero: bool = False) -> dict[str, np.ndarray]:
+                    zero: bool = False, x_head: bool = False) -> dict[str, np.ndarray]:
     """Uniform(-gain/sqrt(fan_in), gain/sqrt(fan_in)) for weights and biases
     (float64).  zero=True gives all-zero weights and seeded biases."""
     rng = np.random.default_rng(seed)
     params = {}
-    for name, shape in gnn_param_shapes(h, n_mp):
+    shapes = gnn_param_shapes(h, n_mp, x_head)
+    for name, shape in shapes:
         fan_in = shape[0] if len(shape) == 2 else None
         if name.endswith(("W0", "W1")):
             bound = gain / np.sqrt(shape[0])
@@ -47,7 +52,7 @@ def init_gnn_params(h: int, n_mp: int, seed: int, gain: float = 1.0,
         else:
             # bias: fan-in of the matching weight
             wname = name[:-2] + "W" + name[-1]
-            fin = dict(gnn_param_shapes(h, n_mp))[wname][0]
+            fin = dict(shapes)[wname][0]
             bound = gain / np.sqrt(fin)
             params[name] = rng.uniform(-bound, bound, shape)
         del fan_in

@@ -131,7 +131,7 @@ def test_backward_finite_differences():
     _fd_check(F, bf, g.init_gnn_params(3, 3, seed=9), 3, 3, 10)
 
 
-def _torch_model(A, b, P, h, n_mp, diag_mode=0):
+def _torch_model(A, b, P, h, n_mp, diag_mode=0, x_head=False):
     """Independent float64 model with torch primitives (index_add_, cat,
     softplus); modes 1/2 build L = L' D^(1/2) as a dense matrix product."""
     row = torch.as_tensor(A.row_of_entry(), dtype=torch.long)
@@ -151,6 +151,8 @@ def _torch_model(A, b, P, h, n_mp, diag_mode=0):
         V = mlp(f"mp{t}.node", torch.cat([V, m], 1))
         E = mlp(f"mp{t}.edge", torch.cat([E, V[row], V[col]], 1))
     d = mlp("dec", E)[:, 0]
+    if x_head:
+        T["__xhat"] = mlp("xdec", V)[:, 0]
     # pair average via a dense symmetric scatter
     Dm = torch.zeros(A.n, A.n, dtype=torch.float64).index_put((row, col), d)
     Sym = 0.5 * (Dm + Dm.T)
@@ -262,3 +264,57 @@ def test_diag_mode1_backward_finite_differences_and_torch(mode):
     fd = (fp - fm) / (2 * eps)
     an = sum(np.sum(G[k] * V[k]) for k in P)
     assert abs(fd - an) <= 1e-5 * max(1.0, abs(fd)), (fd, an)
+
+
+def test_x_head_zero_weights_closed_form():
+    """All-zero weights: the node decoder outputs its bias, so x0 = b1 rms(b)/s
+    at every node (appendix "Comparison with Starting Guess")."""
+    A, b = g.heat_system_3d(5, 1e-3, k_seed=3, u0_seed=4)
+    P = g.init_gnn_params(8, 2, seed=1, zero=True, x_head=True)
+    _, cache = gnn.forward(A, b, P, 8, 2, x_head=True)
+    s = np.mean(O.diag(A))
+    rms = np.sqrt(np.mean(b ** 2))
+    np.testing.assert_allclose(cache["x0"], P["xdec.b1"][0] * rms / s, rtol=1e-15)
+
+
+def test_x_head_backward_torch_and_finite_differences():
+    A = g.fem_p1_delaunay(8, 3, 4)[0]
+    b = np.random.default_rng(11).standard_normal(A.n)
+    h, n_mp = 5, 2
+    P = g.init_gnn_params(h, n_mp, seed=12, gain=1.5, x_head=True)
+    lval, cache = gnn.forward(A, b, P, h, n_mp, keep=True, diag_mode=1, x_head=True)
+    rng = np.random.default_rng(13)
+    gl = rng.standard_normal(lval.shape[0])
+    gx = rng.standard_normal(A.n)
+    G = gnn.backward(P, cache, gl, gx)
+    # independent float64 torch model with autograd
+    lt, T = _torch_model(A, b, P, h, n_mp, diag_mode=1, x_head=True)
+    np.testing.assert_allclose(cache["xhat"], T["__xhat"].detach().numpy(), rtol=1e-12, atol=1e-13)
+    ((lt * torch.as_tensor(gl)).sum() + (T["__xhat"] * torch.as_tensor(gx)).sum()).backward()
+    for k in P:
+        np.testing.assert_allclose(G[k], T[k].grad.numpy(), rtol=1e-10, atol=1e-11, err_msg=k)
+    # central differences along a random direction
+    V = {k: rng.standard_normal(v.shape) for k, v in P.items()}
+    eps = 1e-7
+
+    def f(Q):
+        lv, c = gnn.forward(A, b, Q, h, n_mp, diag_mode=1, x_head=True)
+        return gl @ lv + gx @ c["xhat"]
+    fd = (f({k: P[k] + eps * V[k] for k in P}) - f({k: P[k] - eps * V[k] for k in P})) / (2 * eps)
+    an = sum(np.sum(G[k] * V[k]) for k in P)
+    assert abs(fd - an) <= 1e-5 * max(1.0, abs(fd)), (fd, an)
+
+
+def test_x0_loss_zero_at_solution_and_gradient():
+    A, b = g.heat_system_3d(4, 1e-3, 1, 2)
+    x = np.linalg.solve(A.to_dense(), b)
+    s = np.mean(O.diag(A))
+    rms = np.sqrt(np.mean(b ** 2))
+    loss, gr = gnn.x0_loss(A, b, x, x * s / rms)
+    assert loss == 0.0 and np.all(gr == 0.0)
+    xh = np.random.default_rng(0).standard_normal(A.n)
+    loss, gr = gnn.x0_loss(A, b, x, xh)
+    v = np.random.default_rng(1).standard_normal(A.n)
+    eps = 1e-6
+    fd = (gnn.x0_loss(A, b, x, xh + eps * v)[0] - gnn.x0_loss(A, b, x, xh - eps * v)[0]) / (2 * eps)
+    assert abs(fd - gr @ v) <= 1e-7 * max(1.0, abs(fd))
