@@ -302,6 +302,7 @@ int lpcg_pcg_solve_ir(lpcg_system *sys, const lpcg_precond *P, const double *b, 
  *     mp{t}.node: W0[2h][h] b0[h] W1[h][h] b1[h]     (input [v_i, m_i])
  *     mp{t}.edge: W0[3h][h] b0[h] W1[h][h] b1[h]     (input [e_ij, v_i, v_j])
  *   dec: W0[h][h] b0[h] W1[h][1] b1[1]
+ *   xdec: W0[h][h] b0[h] W1[h][1] b1[1]              (only when x_head = 1)
  * The GEMMs run on BF16 MFMA with FP32 accumulation. */
 typedef struct {
     int32_t h;
@@ -314,10 +315,13 @@ typedef struct {
                            2: the same form with a learned positive diagonal of L':
                               L_ii = sqrt(A_ii) max(softplus(d_ii + ln(e-1)), 1e-6),
                               L_ij = sqrt(A_jj) (d_ij + d_ji)/2 */
+    int32_t x_head;     /* 1: the network also carries the initial-guess head xdec (appendix
+                           comparing with a predicted starting guess x^0), an MLP on the
+                           final node latents; 0: no head */
 } lpcg_gnn;
 
-/* Number of FP32 parameters of the layout above. */
-int64_t lpcg_gnn_param_count(int32_t h, int32_t n_mp);
+/* Number of FP32 parameters of the layout above (-1 for invalid sizes). */
+int64_t lpcg_gnn_param_count(int32_t h, int32_t n_mp, int32_t x_head);
 
 /* Workspace bytes for gnn_predict_L (train = 0) or for the training forward
  * and backward (train = 1, activations kept). */
@@ -340,9 +344,34 @@ int lpcg_gnn_predict_L(const lpcg_system *sys, const lpcg_gnn *net, const double
 int lpcg_gnn_forward_train(const lpcg_system *sys, const lpcg_gnn *net, const double *b,
                            void *ws, int64_t ws_bytes, float *l_val, hipStream_t stream);
 
+/* Initial-guess head (appendix comparing with a predicted starting guess
+ * x^0): the node decoder xdec regresses, per node, the solution of the
+ * normalised system (A/s) x' = b/rms(b), that is x' = x s / rms(b), and
+ * x0 = x^ rms(b) / s per system of the batch.  Runs the network (as
+ * lpcg_gnn_predict_L, same workspace; l_val and ut_val may be NULL) and
+ * writes x0 (FP64 [n], device, original numbering) for use as the PCG
+ * starting point.  Errors: EINVAL (net->x_head = 0, x0 NULL), ENOMEM. */
+int lpcg_gnn_predict_x0(const lpcg_system *sys, const lpcg_gnn *net, const double *b,
+                        void *ws, int64_t ws_bytes, float *l_val, float *ut_val, double *x0,
+                        hipStream_t stream);
+
+/* Loss of the initial-guess head, per system of the batch:
+ *   loss[s] = sum_i (x^_i - x_i s / rms(b))^2   over the rows of system s
+ * (FP64 [nsys], device, overwritten), from the head output of the last
+ * forward (lpcg_gnn_forward_train, lpcg_gnn_predict_L or _x0) run on ws; x
+ * (FP64 [n], original numbering) is the target solution.  When weight != 0
+ * the gradient weight * d(sum_s loss[s]) / d x^ is stored in ws for the next
+ * lpcg_gnn_backward (lpcg_gnn_forward_train resets it to zero, so a backward
+ * without this call leaves xdec with zero gradient).  Errors: EINVAL
+ * (net->x_head = 0), ENOMEM (ws too small). */
+int lpcg_x0_loss(const lpcg_system *sys, const lpcg_gnn *net, void *ws, int64_t ws_bytes,
+                 const double *x, double weight, double *loss, hipStream_t stream);
+
 /* Reverse mode of the network: given dl_val = d loss / d L (FP32 [nnz_l]),
  * writes d loss / d params (FP32, same layout as params, overwritten).
- * ws must hold the activations of the matching lpcg_gnn_forward_train. */
+ * With x_head = 1 the head's loss gradient left in ws by lpcg_x0_loss is
+ * included.  ws must hold the activations of the matching
+ * lpcg_gnn_forward_train. */
 int lpcg_gnn_backward(const lpcg_system *sys, const lpcg_gnn *net, void *ws,
                       int64_t ws_bytes, const float *dl_val, float *dparams,
                       hipStream_t stream);

@@ -14,6 +14,8 @@
 //   k_edge<LAST> edge MLP per directed edge; the last layer also runs the
 //                decoder and writes the scalar d per edge
 //   k_assemble   pair average, softplus diagonal, sqrt(s) scaling
+//   k_xdec       optional node decoder on the final node latents: the
+//                initial-guess head x^_i (in the frame of A/s and b/rms(b))
 #include <algorithm>
 #include <cstring>
 
@@ -23,7 +25,7 @@
 
 namespace lpcg {
 
-GnnOff gnn_offsets(int h, int n_mp) {
+GnnOff gnn_offsets(int h, int n_mp, bool x_head) {
     GnnOff o{};
     int p = 0;
     auto mlp = [&](MlpOff &m, int fin, int fout) {
@@ -43,17 +45,19 @@ GnnOff gnn_offsets(int h, int n_mp) {
         mlp(o.edge[t], 3 * h, h);
     }
     mlp(o.dec, h, 1);
+    if (x_head) mlp(o.xdec, h, 1);
     o.total = p;
     return o;
 }
 
 // Workspace layout (byte offsets, 256-byte aligned).  Inference keeps two
 // V/E buffers (ping-pong); training keeps every layer's activations plus the
-// backward pass's intermediates.
+// backward pass's intermediates.  The normalisation scalars and the head's
+// buffers come first, at offsets common to both layouts.
 struct GnnWs {
     size_t sys_s, sys_rms, norm_part;
     size_t V[kMaxMp + 1], Pa[kMaxMp], Pb[kMaxMp], E[kMaxMp + 1];
-    size_t d;
+    size_t d, xhat, gxhat;
     // backward (train only)
     size_t gd, gE[2], gV[2], gVmlp, gm, GH, G1, GVN, GH1, H1, Mt, gPa, gPb, HD, GHD, Henc, GHenc, Xn, Xe;
     size_t wpart;
@@ -84,6 +88,10 @@ GnnWs gnn_ws_layout(const lpcg_system *s, int h, int n_mp, bool train) {
     w.sys_s = take(sizeof(double) * s->nsys);
     w.sys_rms = take(sizeof(double) * s->nsys);
     w.norm_part = take(2 * sizeof(double) * (size_t)s->nsys * norm_segments(s));
+    // the head's output and loss gradient sit before every buffer whose size
+    // depends on `train`, at the same offset in both layouts
+    w.xhat = take(4 * n);
+    w.gxhat = take(4 * n);
     const int nv = train ? n_mp + 1 : 2;
     const int np = train ? n_mp : 1;
     for (int i = 0; i < nv; ++i) w.V[i] = take(2 * n * h);
@@ -115,7 +123,7 @@ GnnWs gnn_ws_layout(const lpcg_system *s, int h, int n_mp, bool train) {
         w.GHenc = take(4 * mx * h);
         w.Xn = take(4 * n);
         w.Xe = take(4 * nnz);
-        const GnnOff o = gnn_offsets(h, n_mp);
+        const GnnOff o = gnn_offsets(h, n_mp, true);  // room for the head's weights
         w.wpart = take(sizeof(float) * (size_t)o.total * kWgradBlocks);
     }
     w.total = off;
@@ -433,12 +441,58 @@ __global__ void k_assemble(int nnz_l, int mode, const int *__restrict__ lsrc, co
     if (utval) utval[p] = l_entry(lsrc[u2l[p]], mode, erow, col, rev, row_sys, sys_s, diag64, d);
 }
 
+// Initial-guess head: x^_i = relu(V_i W0 + b0) w1 + b1 on the final node
+// latents V = V_T.
+template <int H>
+__global__ void __launch_bounds__(kGnnThreads) k_xdec(int n, const float *__restrict__ P, MlpOff m,
+                                                      const __bf16 *__restrict__ VT, float *__restrict__ xhat) {
+    constexpr int S = H / 16, MT = H / 32;
+    __shared__ __bf16 w0[H * H];
+    stage_weights<false>(w0, P + m.W0, H, H, H);
+    __syncthreads();
+    const int lane = lane_id();
+    const float *w1 = P + m.W1;
+    const int ntiles = (n + 31) / 32;
+    for (int tile = blockIdx.x * 4 + threadIdx.x / kWave; tile < ntiles; tile += gridDim.x * 4) {
+        const int i = tile * 32 + (lane & 31);
+        const bool valid = i < n;
+        f32x16 hid[MT];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) hid[mt] = zero16();
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            bf16x8 b;
+            if (valid) {
+                b = load8(VT + (size_t)i * H + k_nat(s, 0, lane));
+            } else {
+#pragma unroll
+                for (int j = 0; j < 8; ++j) b[j] = (__bf16)0.f;
+            }
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) hid[mt] = mfma(lds_op(w0, S, mt, s, lane), b, hid[mt]);
+        }
+        add_bias<MT>(hid, P + m.b0, lane, true);
+        float part = 0.f;
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int q = 0; q < 16; ++q) part += hid[mt][q] * w1[acc_feat(mt, q, lane)];
+        part += __shfl_xor(part, 32, kWave);
+        if (valid && lane < 32) xhat[i] = part + P[m.b1];
+    }
+}
+
+__global__ void k_zero_f32(int n, float *__restrict__ p) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.f;
+}
+
 int gnn_blocks(long rows) { return std::max(1, std::min(kMaxGnnBlocks, nblk(rows, 32 * 4))); }
 
 template <int H>
 int forward_impl(const lpcg_system *s, const lpcg_gnn *net, const double *b, unsigned char *ws,
                  const GnnWs &L, bool train, float *lval, float *utval, hipStream_t st) {
-    const GnnOff o = gnn_offsets(H, net->n_mp);
+    const GnnOff o = gnn_offsets(H, net->n_mp, net->x_head != 0);
     const float *P = net->params;
     double *sys_s = (double *)(ws + L.sys_s), *sys_rms = (double *)(ws + L.sys_rms);
     {
@@ -474,14 +528,20 @@ int forward_impl(const lpcg_system *s, const lpcg_gnn *net, const double *b, uns
     k_assemble<<<nblk(s->nnz_l, 256), 256, 0, st>>>(s->nnz_l, net->diag_mode, s->lsrc, s->u2l, s->erow,
                                                      s->colind, s->rev, s->row_sys, sys_s, s->diag64, d, lval,
                                                      utval);
+    if (net->x_head) {
+        k_xdec<H><<<gnn_blocks(s->n), kGnnThreads, 0, st>>>(s->n, P, o.xdec, V(T), (float *)(ws + L.xhat));
+        // the head's loss gradient starts at zero: a backward without an
+        // initial-guess loss leaves the head's weights with zero gradient
+        if (train) k_zero_f32<<<nblk(s->n, 256), 256, 0, st>>>(s->n, (float *)(ws + L.gxhat));
+    }
     LPCG_LAUNCH_CHECK();
     return LPCG_OK;
 }
 
 int check_net(const lpcg_gnn *net) {
     if (!net || !net->params || (net->h != 32 && net->h != 64) || net->n_mp < 1 || net->n_mp > kMaxMp ||
-        net->diag_mode < 0 || net->diag_mode > 2) {
-        set_error("gnn: h must be 32 or 64, 1 <= n_mp <= %d, diag_mode 0, 1 or 2", kMaxMp);
+        net->diag_mode < 0 || net->diag_mode > 2 || net->x_head < 0 || net->x_head > 1) {
+        set_error("gnn: h must be 32 or 64, 1 <= n_mp <= %d, diag_mode 0, 1 or 2, x_head 0 or 1", kMaxMp);
         return LPCG_EINVAL;
     }
     return LPCG_OK;
@@ -518,9 +578,9 @@ int gnn_forward(const lpcg_system *s, const lpcg_gnn *net, const double *b, void
 
 using namespace lpcg;
 
-extern "C" int64_t lpcg_gnn_param_count(int32_t h, int32_t n_mp) {
-    if (h <= 0 || n_mp < 1 || n_mp > kMaxMp) return -1;
-    return gnn_offsets(h, n_mp).total;
+extern "C" int64_t lpcg_gnn_param_count(int32_t h, int32_t n_mp, int32_t x_head) {
+    if (h <= 0 || n_mp < 1 || n_mp > kMaxMp || x_head < 0 || x_head > 1) return -1;
+    return gnn_offsets(h, n_mp, x_head != 0).total;
 }
 
 extern "C" int64_t lpcg_gnn_workspace_bytes(const lpcg_system *s, int32_t h, int32_t n_mp, int32_t train) {
@@ -536,6 +596,112 @@ extern "C" int lpcg_gnn_predict_L(const lpcg_system *s, const lpcg_gnn *net, con
 extern "C" int lpcg_gnn_forward_train(const lpcg_system *s, const lpcg_gnn *net, const double *b, void *ws,
                                       int64_t ws_bytes, float *l_val, hipStream_t st) {
     return gnn_forward(s, net, b, ws, ws_bytes, true, l_val, nullptr, st);
+}
+
+// --------------------------------------------------------------------------
+// Initial-guess head (appendix comparing with a predicted starting guess):
+// the node decoder regresses the solution of the normalised system
+// (A/s) x' = b/rms(b), i.e. x' = x s / rms(b); x0 = x^ rms(b) / s.
+namespace lpcg {
+namespace {
+
+__global__ void k_x0_scale(int n, const int *__restrict__ row_sys, const double *__restrict__ sys_s,
+                           const double *__restrict__ sys_rms, const float *__restrict__ xhat,
+                           double *__restrict__ x0) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int y = row_sys[i];
+    x0[i] = (double)xhat[i] * sys_rms[y] / sys_s[y];
+}
+
+// Stage 1 of the head's loss: block (x, y) handles segment x (kNormRows
+// rows) of system y: d_i = x^_i - x_i s / rms, gradient w 2 d_i, partial sum
+// of d_i^2.
+__global__ void k_x0_loss_part(int nseg, const int *__restrict__ sys_rowptr, const double *__restrict__ sys_s,
+                               const double *__restrict__ sys_rms, const float *__restrict__ xhat,
+                               const double *__restrict__ x, double w, float *__restrict__ gxhat,
+                               double *__restrict__ part) {
+    __shared__ double lds[kGnnThreads / kWave];
+    const int sy = blockIdx.y, sg = blockIdx.x;
+    const int r0 = sys_rowptr[sy] + sg * kNormRows;
+    const int r1 = min(sys_rowptr[sy + 1], r0 + kNormRows);
+    const double scale = sys_s[sy] / sys_rms[sy];
+    double acc = 0;
+    for (int i = r0 + threadIdx.x; i < r1; i += kGnnThreads) {
+        const double d = (double)xhat[i] - x[i] * scale;
+        acc += d * d;
+        if (gxhat) gxhat[i] = (float)(2.0 * w * d);
+    }
+    acc = block_sum<kGnnThreads>(acc, lds);
+    if (threadIdx.x == 0) part[(size_t)sy * nseg + sg] = acc;
+}
+
+__global__ void k_x0_loss_fin(int nsys, int nseg, const double *__restrict__ part, double *__restrict__ loss) {
+    const int sy = blockIdx.x * blockDim.x + threadIdx.x;
+    if (sy >= nsys) return;
+    double acc = 0;
+    for (int g = 0; g < nseg; ++g) acc += part[(size_t)sy * nseg + g];
+    loss[sy] = acc;
+}
+
+int check_head(const lpcg_system *s, const lpcg_gnn *net, const void *ws, int64_t ws_bytes, const char *who) {
+    int rc = check_net(net);
+    if (rc) return rc;
+    if (!s || !ws || !net->x_head) {
+        set_error("%s: invalid arguments (the network needs x_head = 1)", who);
+        return LPCG_EINVAL;
+    }
+    const GnnWs L = gnn_ws_layout(s, net->h, net->n_mp, false);
+    if ((size_t)ws_bytes < L.total) {
+        set_error("%s: workspace of %lld bytes, %zu needed", who, (long long)ws_bytes, L.total);
+        return LPCG_ENOMEM;
+    }
+    return LPCG_OK;
+}
+
+}  // namespace
+}  // namespace lpcg
+
+extern "C" int lpcg_gnn_predict_x0(const lpcg_system *s, const lpcg_gnn *net, const double *b, void *ws,
+                                   int64_t ws_bytes, float *l_val, float *ut_val, double *x0, hipStream_t st) {
+    int rc = check_head(s, net, ws, ws_bytes, "lpcg_gnn_predict_x0");
+    if (rc) return rc;
+    if (!x0) {
+        set_error("lpcg_gnn_predict_x0: x0 is NULL");
+        return LPCG_EINVAL;
+    }
+    if ((rc = gnn_forward(s, net, b, ws, ws_bytes, false, l_val, ut_val, st))) return rc;
+    const GnnWs L = gnn_ws_layout(s, net->h, net->n_mp, false);
+    const unsigned char *w = (const unsigned char *)ws;
+    double *dst = s->perm ? s->xperm : x0;
+    k_x0_scale<<<nblk(s->n, 256), 256, 0, st>>>(s->n, s->row_sys, (const double *)(w + L.sys_s),
+                                                (const double *)(w + L.sys_rms), (const float *)(w + L.xhat), dst);
+    LPCG_LAUNCH_CHECK();
+    return s->perm ? from_internal_f64(s, s->xperm, x0, st) : LPCG_OK;
+}
+
+extern "C" int lpcg_x0_loss(const lpcg_system *s, const lpcg_gnn *net, void *ws, int64_t ws_bytes,
+                            const double *x, double weight, double *loss, hipStream_t st) {
+    int rc = check_head(s, net, ws, ws_bytes, "lpcg_x0_loss");
+    if (rc) return rc;
+    if (!x || !loss) {
+        set_error("lpcg_x0_loss: invalid arguments");
+        return LPCG_EINVAL;
+    }
+    if (s->perm) {
+        if ((rc = to_internal_f64(s, x, s->xperm, st))) return rc;
+        x = s->xperm;
+    }
+    const GnnWs L = gnn_ws_layout(s, net->h, net->n_mp, false);
+    unsigned char *w = (unsigned char *)ws;
+    const int nseg = norm_segments(s);
+    double *part = (double *)(w + L.norm_part);
+    k_x0_loss_part<<<dim3(nseg, s->nsys), kGnnThreads, 0, st>>>(
+        nseg, s->sys_rowptr, (const double *)(w + L.sys_s), (const double *)(w + L.sys_rms),
+        (const float *)(w + L.xhat), x, weight, weight != 0.0 ? (float *)(w + L.gxhat) : nullptr, part);
+    k_x0_loss_fin<<<nblk(s->nsys, 64), 64, 0, st>>>(s->nsys, nseg, part, loss);
+    LPCG_LAUNCH_CHECK();
+    return LPCG_OK;
 }
 
 // ===========================================================================
@@ -586,8 +752,9 @@ __global__ void k_assemble_bwd(int nnz, int mode, const int *__restrict__ rowptr
     gd[k] = g;
 }
 
-// Decoder: pre = E_T Wd0 + bd0, d = relu(pre) wd1 + bd1.  Writes the hidden
-// activation HD, its gradient GHD and d loss / d E_T.
+// Decoder MLP h -> h -> 1 on `nnz` rows of ET (the edge decoder on E_T, or
+// the initial-guess head on V_T): pre = ET Wd0 + bd0, d = relu(pre) wd1 + bd1.
+// Writes the hidden activation HD, its gradient GHD and d loss / d ET.
 template <int H>
 __global__ void __launch_bounds__(kGnnThreads) k_dec_bwd(int nnz, const float *__restrict__ P, MlpOff md,
                                                          const __bf16 *__restrict__ ET,
@@ -1093,7 +1260,7 @@ template <int H>
 int backward_impl(const lpcg_system *s, const lpcg_gnn *net, unsigned char *ws, const GnnWs &L,
                   const float *dl, float *dparams, hipStream_t st) {
     const int T = net->n_mp;
-    const GnnOff o = gnn_offsets(H, T);
+    const GnnOff o = gnn_offsets(H, T, net->x_head != 0);
     const float *P = net->params;
     auto V = [&](int t) { return (const __bf16 *)(ws + L.V[t]); };
     auto E = [&](int t) { return (const __bf16 *)(ws + L.E[t]); };
@@ -1114,6 +1281,17 @@ int backward_impl(const lpcg_system *s, const lpcg_gnn *net, unsigned char *ws, 
     wgrad<H, H>(nnz, bf(E(T), H), f32(F(L.GHD), H), H, wpart, pt, o.dec.W0, o.dec.b0, st);
     wgrad<H, 32>(nnz, bf(B16(L.HD), H), sc(F(L.gd)), 1, wpart, pt, o.dec.W1, o.dec.b1, st);
     const float *gVacc = nullptr;
+    if (net->x_head) {
+        // initial-guess head: same MLP shape as the edge decoder, on the node
+        // latents V_T; its input gradient seeds d loss / d V_T (HD and GHD are
+        // free again once the edge decoder's weight gradients are enqueued)
+        float *gVT = F(L.gV[T & 1]);
+        k_dec_bwd<H><<<gnn_blocks(n), kGnnThreads, 0, st>>>(n, P, o.xdec, V(T), F(L.gxhat), B16(L.HD),
+                                                             F(L.GHD), gVT);
+        wgrad<H, H>(n, bf(V(T), H), f32(F(L.GHD), H), H, wpart, pt, o.xdec.W0, o.xdec.b0, st);
+        wgrad<H, 32>(n, bf(B16(L.HD), H), sc(F(L.gxhat)), 1, wpart, pt, o.xdec.W1, o.xdec.b1, st);
+        gVacc = gVT;
+    }
     for (int t = T - 1; t >= 0; --t) {
         float *gEn = F(L.gE[(t + 1) & 1]), *gEt = F(L.gE[t & 1]);
         k_edge_bwd<H><<<gnn_blocks(nnz), kGnnThreads, 0, st>>>(nnz, s->erow, s->colind, P, o.edge[t], E(t),

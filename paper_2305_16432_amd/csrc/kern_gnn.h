@@ -41,6 +41,7 @@ struct MlpOff {
 };
 struct GnnOff {
     MlpOff node_enc, edge_enc, node[kMaxMp], edge[kMaxMp], dec;
+    MlpOff xdec;  // node decoder of the initial-guess head (when present)
     int total;
 };
 

@@ -61,7 +61,8 @@ class _TrsvCfg(C.Structure):
 
 
 class _Gnn(C.Structure):
-    _fields_ = [("h", C.c_int32), ("n_mp", C.c_int32), ("params", C.c_void_p), ("diag_mode", C.c_int32)]
+    _fields_ = [("h", C.c_int32), ("n_mp", C.c_int32), ("params", C.c_void_p), ("diag_mode", C.c_int32),
+                ("x_head", C.c_int32)]
 
 
 _lib = None
@@ -78,7 +79,7 @@ def lib():
         L.lpcg_version.restype = C.c_char_p
         if hasattr(L, "lpcg_gnn_param_count"):
             L.lpcg_gnn_param_count.restype = C.c_int64
-            L.lpcg_gnn_param_count.argtypes = [C.c_int32, C.c_int32]
+            L.lpcg_gnn_param_count.argtypes = [C.c_int32, C.c_int32, C.c_int32]
             L.lpcg_gnn_workspace_bytes.restype = C.c_int64
             L.lpcg_gnn_workspace_bytes.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32]
         L.lpcg_destroy.restype = None
@@ -363,10 +364,11 @@ def time_spmv(sys: System, x, reps=50):
 
 
 # ---------------------------------------------------------------------- GNN
-def param_layout(h: int, n_mp: int):
+def param_layout(h: int, n_mp: int, x_head: bool = False):
     """(name, shape) of every tensor of the flat FP32 parameter vector, in the
-    order of include/lpcg.h (node_enc, edge_enc, mp{t}.node, mp{t}.edge, dec;
-    each MLP: W0, b0, W1, b1 with W stored [fan_in][fan_out])."""
+    order of include/lpcg.h (node_enc, edge_enc, mp{t}.node, mp{t}.edge, dec,
+    and xdec with the initial-guess head; each MLP: W0, b0, W1, b1 with W
+    stored [fan_in][fan_out])."""
     out = []
 
     def mlp(prefix, fin, fout):
@@ -378,24 +380,37 @@ def param_layout(h: int, n_mp: int):
         mlp(f"mp{t}.node", 2 * h, h)
         mlp(f"mp{t}.edge", 3 * h, h)
     mlp("dec", h, 1)
+    if x_head:
+        mlp("xdec", h, 1)
     return out
 
 
-def param_count(h: int, n_mp: int) -> int:
-    return int(lib().lpcg_gnn_param_count(h, n_mp))
+def param_count(h: int, n_mp: int, x_head: bool = False) -> int:
+    return int(lib().lpcg_gnn_param_count(h, n_mp, 1 if x_head else 0))
+
+
+def has_x_head(nparams: int, h: int, n_mp: int) -> bool:
+    """Whether a flat parameter vector of nparams entries carries the head."""
+    if nparams == param_count(h, n_mp, False):
+        return False
+    if nparams == param_count(h, n_mp, True):
+        return True
+    raise ValueError(f"{nparams} parameters match neither layout of h={h}, n_mp={n_mp}")
 
 
 def pack_params(P: dict, h: int, n_mp: int) -> torch.Tensor:
-    """Flatten a dict of named arrays into the library's FP32 layout (host)."""
+    """Flatten a dict of named arrays into the library's FP32 layout (host);
+    the head is packed when P holds xdec.*."""
     import numpy as np
     parts = []
-    for name, shape in param_layout(h, n_mp):
+    x_head = "xdec.W0" in P
+    for name, shape in param_layout(h, n_mp, x_head):
         a = np.asarray(P[name], dtype=np.float32)
         if a.shape != shape:
             raise ValueError(f"{name}: shape {a.shape}, expected {shape}")
         parts.append(a.reshape(-1))
     flat = np.concatenate(parts)
-    assert flat.shape[0] == param_count(h, n_mp)
+    assert flat.shape[0] == param_count(h, n_mp, x_head)
     return torch.as_tensor(flat)
 
 
@@ -403,7 +418,7 @@ def unpack_params(flat, h: int, n_mp: int) -> dict:
     import numpy as np
     flat = np.asarray(flat.detach().cpu() if torch.is_tensor(flat) else flat)
     out, p = {}, 0
-    for name, shape in param_layout(h, n_mp):
+    for name, shape in param_layout(h, n_mp, has_x_head(flat.shape[0], h, n_mp)):
         k = int(np.prod(shape))
         out[name] = flat[p:p + k].reshape(shape)
         p += k
@@ -420,7 +435,7 @@ def gnn_workspace(sys: System, h: int, n_mp: int, train: bool = False) -> torch.
 def _net(params, h, n_mp, diag_mode=0):
     if params.dtype != torch.float32:
         raise TypeError("params must be float32")
-    return _Gnn(h, n_mp, _ptr(params), diag_mode)
+    return _Gnn(h, n_mp, _ptr(params), diag_mode, 1 if has_x_head(params.numel(), h, n_mp) else 0)
 
 
 def gnn_predict_L(sys: System, params, h: int, n_mp: int, b, ws, l_val=None, ut_val=None, diag_mode=0):
@@ -443,6 +458,33 @@ def gnn_forward_train(sys: System, params, h: int, n_mp: int, b, ws, l_val=None,
                                       _ptr(l_val), _stream())
     _check(rc, "lpcg_gnn_forward_train")
     return l_val
+
+
+def gnn_predict_x0(sys: System, params, h: int, n_mp: int, b, ws, l_val=None, ut_val=None, x0=None,
+                   diag_mode=0):
+    """L (and U = L^T when ut_val is given) plus the head's starting guess x0
+    (FP64 [n], original numbering); params must carry the head."""
+    if l_val is None:
+        l_val = torch.empty(sys.info["nnz_l"], dtype=torch.float32, device="cuda")
+    if x0 is None:
+        x0 = torch.empty(sys.n, dtype=torch.float64, device="cuda")
+    net = _net(params, h, n_mp, diag_mode)
+    rc = lib().lpcg_gnn_predict_x0(sys.handle, C.byref(net), _ptr(b), _ptr(ws), C.c_int64(ws.numel()),
+                                   _ptr(l_val), _ptr(ut_val), _ptr(x0), _stream())
+    _check(rc, "lpcg_gnn_predict_x0")
+    return l_val, ut_val, x0
+
+
+def x0_loss(sys: System, params, h: int, n_mp: int, ws, x, weight=1.0, diag_mode=0):
+    """Per-system loss of the head against the solution x (device FP64
+    [nsys]); with weight != 0 its scaled gradient is left in ws for
+    gnn_backward."""
+    loss = torch.empty(sys.info["nsys"], dtype=torch.float64, device="cuda")
+    net = _net(params, h, n_mp, diag_mode)
+    rc = lib().lpcg_x0_loss(sys.handle, C.byref(net), _ptr(ws), C.c_int64(ws.numel()), _ptr(x),
+                            C.c_double(weight), _ptr(loss), _stream())
+    _check(rc, "lpcg_x0_loss")
+    return loss
 
 
 def gnn_backward(sys: System, params, h: int, n_mp: int, ws, dl_val, dparams=None, diag_mode=0):

@@ -12,7 +12,14 @@ systems is one block-diagonal pattern analysed once; each step swaps in the
 batch's values.  --ordering color trains for the multicolour row ordering
 (the factor then lives on tril(P A P^T)).  Held-out check: PCG iterations to 1e-6 with the predicted
 L on a 64^3 system with unseen seeds, every eval_every steps; the weights
-with the fewest held-out iterations are kept (early stop on held-out).
+with the fewest held-out iterations are kept (early stop on held-out;
+--head-only keeps the last weights, since L does not change).
+
+--x-head adds the initial-guess head (appendix comparing with a predicted
+starting guess x^0): a node decoder regressing x s / rms(b), trained with
+the weighted loss sum_i (x^_i - x_i s / rms(b))^2 next to the data loss (or
+alone with --head-only, which updates only the head so L stays that of the
+--init network); the held-out PCG then starts from the predicted x0.
 
     python -m paper_2305_16432_amd.train --out paper_2305_16432_amd/weights/heat3d_h32_mp3.npz
 """
@@ -80,12 +87,27 @@ def main():
                     help="data: ||L L^T x - b||^2 (equation loss_Ab); frobenius: ||L L^T - A||_F^2 (loss_A ablation)")
     ap.add_argument("--rhs", choices=["grf", "white", "mix"], default="grf",
                     help="training right-hand sides: smooth GRF states, white noise, or both")
+    ap.add_argument("--x-head", action="store_true",
+                    help="add the initial-guess head (node decoder regressing x); held-out PCG starts from its x0")
+    ap.add_argument("--x-weight", type=float, default=1.0, help="weight of the head's loss")
+    ap.add_argument("--head-only", action="store_true",
+                    help="update only the head's weights (L stays that of the initial network)")
+    ap.add_argument("--init", default=None, help="start from a saved network (.npz); its h, n_mp, "
+                                                 "diag mode and ordering override the options")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--eval-every", type=int, default=100)
     ap.add_argument("--eval-m", type=int, default=64)
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--out", required=True)
     args = ap.parse_args()
+    init = None
+    if args.init:
+        z = np.load(args.init, allow_pickle=False)
+        init = z["params"]
+        args.h, args.n_mp, args.diag_mode = int(z["h"]), int(z["n_mp"]), int(z["diag_mode"])
+        args.ordering = "color" if int(z["ordering"]) == 1 else "natural"
+    if args.head_only and not args.x_head:
+        ap.error("--head-only needs --x-head")
     print(f"[train] generating {args.nsys} systems of {args.m}^3 on {args.workers} workers", flush=True)
     t0 = time.time()
     A0, vals, bs, xs = make_dataset(args.m, args.nsys, args.workers, args.rhs)
@@ -105,11 +127,21 @@ def main():
     dx = torch.as_tensor(xs).cuda()
     h, n_mp = args.h, args.n_mp
     dm = args.diag_mode
-    P0 = g.init_gnn_params(h, n_mp, seed=args.seed, gain=1.0)
+    xh = args.x_head
+    P0 = g.init_gnn_params(h, n_mp, seed=args.seed, gain=1.0, x_head=xh)
     if dm in (1, 2):  # decoder output layer zero: L' = I, i.e. training starts at Jacobi
         P0["dec.W1"][:] = 0.0
         P0["dec.b1"][:] = 0.0
+    if xh:  # head output zero: the first evaluation starts PCG from x0 = 0
+        P0["xdec.W1"][:] = 0.0
+        P0["xdec.b1"][:] = 0.0
+    if init is not None:
+        P0.update({k: v for k, v in lpcg.unpack_params(init, h, n_mp).items() if xh or not k.startswith("xdec.")})
     params = lpcg.pack_params(P0, h, n_mp).cuda()
+    grad_mask = None
+    if args.head_only:
+        grad_mask = torch.zeros_like(params)
+        grad_mask[lpcg.param_count(h, n_mp, False):] = 1.0
     m1, v1 = torch.zeros_like(params), torch.zeros_like(params)
     ws = lpcg.gnn_workspace(S, h, n_mp, train=True)
 
@@ -127,9 +159,19 @@ def main():
     _, rj = lpcg.pcg_solve(Se, lpcg.PC_JACOBI, bed, tol=1e-6, maxit=2000)
     print(f"[train] held-out 64^3 ({args.ordering} order, {Se.info['nlev_fwd']} levels): IC(0) {ric['iters']} its, Jacobi {rj['iters']} its", flush=True)
 
-    def evaluate():
-        lpcg.gnn_predict_L(Se, params, h, n_mp, bed, wse, le, ue, diag_mode=dm)
-        _, r = lpcg.pcg_solve(Se, lpcg.PC_LLT, bed, l_val=le, ut_val=ue, tol=1e-6, maxit=2000)
+    def evaluate(with_x0=xh, report=None):
+        x0 = None
+        if xh:
+            _, _, x0 = lpcg.gnn_predict_x0(Se, params, h, n_mp, bed, wse, le, ue, diag_mode=dm)
+        else:
+            lpcg.gnn_predict_L(Se, params, h, n_mp, bed, wse, le, ue, diag_mode=dm)
+        _, r, hist = lpcg.pcg_solve(Se, lpcg.PC_LLT, bed, x=x0 if with_x0 else None, l_val=le, ut_val=ue,
+                                    tol=1e-6, maxit=2000, hist=True)
+        if report is not None:  # relative residual of the starting point, then at each tolerance
+            hh = hist.cpu().numpy()
+            report["start_relres"] = float(hh[0])
+            report["iters_to"] = {f"1e-{e}": int(np.argmax(hh <= 10.0 ** -e)) if np.any(hh <= 10.0 ** -e)
+                                  else None for e in range(1, 7)}
         return r["iters"] if r["status"] == 0 else 10 ** 6
 
     rng = np.random.default_rng(args.seed)
@@ -149,18 +191,33 @@ def main():
             loss, dl = lpcg.llt_loss(S, L, xb, bb)
         else:
             loss, dl = lpcg.frob_loss(S, L)
+        if xh:
+            lx = lpcg.x0_loss(S, params, h, n_mp, ws, xb, weight=args.x_weight, diag_mode=dm)
+            if args.head_only:
+                loss, dl = lx, torch.zeros_like(dl)
+            else:
+                loss = loss + args.x_weight * lx
         grad = lpcg.gnn_backward(S, params, h, n_mp, ws, dl, diag_mode=dm)
+        if grad_mask is not None:
+            grad.mul_(grad_mask)
         lpcg.adam_step(params, grad, m1, v1, args.lr, step)
         if step % 10 == 0:
             log["loss"].append((step, float(loss.sum()) / args.batch))
         if step % args.eval_every == 0 or step == args.steps:
             it = evaluate()
             log["eval"].append((step, it))
-            if it < best[0]:
+            if it < best[0] or (args.head_only and step == args.steps):  # head-only keeps the last weights
                 best = (it, step, params.clone())
             print(f"[train] step {step} loss/system {log['loss'][-1][1]:.4g} held-out iters {it} "
                   f"(best {best[0]} @ {best[1]}) {time.time() - t0:.1f}s", flush=True)
     del nb
+    if xh:
+        params.copy_(best[2])
+        log["from_x0"], log["from_zero"] = {}, {}
+        evaluate(True, log["from_x0"])
+        evaluate(False, log["from_zero"])
+        print(f"[train] best network from its x0: {log['from_x0']}", flush=True)
+        print(f"[train] best network from x = 0: {log['from_zero']}", flush=True)
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
     np.savez(args.out, params=best[2].cpu().numpy(), h=h, n_mp=n_mp, diag_mode=dm, ordering=order,
              best_step=best[1],
