@@ -11,7 +11,8 @@ Contents (each follows the cited part of the paper):
     transpose, reverse-edge map, forward/backward levels and level sets,
     greedy multicolour ordering and the symmetric permutation, SpMV,
     forward/backward substitution, IC(0), PCG (Appendix algorithm), data loss
-    and its gradient (equation loss_Ab).
+    and its gradient (equation loss_Ab); in Python: the symmetric
+    Gauss-Seidel factor and the Lanczos extremes of the PCG coefficients.
   * oracle.gnn: the encoder-processor-decoder GNN (technical-details appendix)
     forward and its hand-written reverse-mode derivative, NumPy float64.
 
@@ -210,6 +211,17 @@ def ic0(pat, A, shift=0.0):
 def diag(A):
     r = A.row_of_entry()
     return _f64(A.val)[A.colind == r]
+
+
+def sgs_factor(pat, A):
+    """Symmetric Gauss-Seidel as a factor P = L L^T (Experiments, baseline
+    methods: the triangles are taken from A itself; CG needs a symmetric
+    preconditioner, so the forward sweep is followed by the backward one):
+    P = (D + A_<) D^-1 (D + A_<)^T, i.e. L = (D + A_<) D^-1/2 on the pattern
+    of tril(A): L_ij = A_ij / sqrt(A_jj) (which gives sqrt(A_ii) on the
+    diagonal)."""
+    aval = _f64(A.val)[pat.lsrc]
+    return aval / np.sqrt(diag(A)[pat.lcol])
 
 
 def pcg(A, b, kind=PC_LLT, pat=None, lval=None, tol=1e-6, maxit=None, x0=None,
