@@ -106,7 +106,7 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--orderings", default="natural,color")
-    ap.add_argument("--methods", default="learned,ic0,jacobi")
+    ap.add_argument("--methods", default="learned,ic0,sgs,jacobi")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="MiB of a plain device copy to run first (counter calibration under rocprofv3 --pmc)")
     args = ap.parse_args()
@@ -158,6 +158,9 @@ def main():
         def run_jacobi():
             lpcg.jacobi(S, dinv)
 
+        def run_sgs():
+            lpcg.sgs(S, lval, utval)
+
         def solve_jacobi():
             x.zero_()
             return lpcg.pcg_solve(S, lpcg.PC_JACOBI, bd, x=x, dinv=dinv, coef=coef, **solve_kw)[1]
@@ -172,6 +175,7 @@ def main():
         methods = {"ic0": (run_ic0, solve_llt)}
         if ordering == "natural":
             methods["jacobi"] = (run_jacobi, solve_jacobi)  # the same preconditioner in any order
+            methods["sgs"] = (run_sgs, solve_llt)
         if os.path.exists(WEIGHTS[ordering]):
             W = np.load(WEIGHTS[ordering])
             assert int(W["ordering"]) == code, "network trained for another ordering"
@@ -182,7 +186,7 @@ def main():
             def run_learned(params=params, h=h, n_mp=n_mp, dmode=dmode, ws=ws):
                 lpcg.gnn_predict_L(S, params, h, n_mp, bd, ws, lval, utval, diag_mode=dmode)
             methods["learned"] = (run_learned, solve_llt)
-        for name in [m for m in ("learned", "ic0", "jacobi") if m in methods and m in args.methods]:
+        for name in [m for m in ("learned", "ic0", "sgs", "jacobi") if m in methods and m in args.methods]:
             pre, solve = methods[name]
             for _ in range(args.warmup):
                 pre()

@@ -152,6 +152,14 @@ int lpcg_sptrsv(const lpcg_system *sys, int32_t transpose, const float *l_val,
 int lpcg_l_to_ut(const lpcg_system *sys, const float *l_val, float *ut_val,
                  hipStream_t stream);
 
+/* Symmetric Gauss-Seidel (Experiments, baseline methods; the triangles
+ * come from A itself, taken in the symmetric form CG needs):
+ * P = (D + A_<) D^-1 (D + A_<)^T = L L^T with L_ij = A_ij / sqrt(A_jj) on
+ * tril(A) (sqrt(A_ii) on the diagonal), computed in FP64 and stored FP32 to
+ * l_val and/or ut_val (either may be NULL, not both).  Asynchronous on
+ * stream.  Errors: EINVAL. */
+int lpcg_sgs(const lpcg_system *sys, float *l_val, float *ut_val, hipStream_t stream);
+
 /* IC(0) (Experiments, incomplete Cholesky baseline): L on tril(A) with
  * (L L^T)_ij = A_ij on the pattern, computed in FP64 and stored FP32 to l_val
  * and ut_val.  On a pivot <= 0 the factorisation is retried on

@@ -151,6 +151,20 @@ __global__ void k_l64_to_f32(int nnz_l, const double *__restrict__ l64, const in
     if (utval) utval[k] = (float)l64[u2l[k]];
 }
 
+// Symmetric Gauss-Seidel factor on tril(A): L_ij = A_ij / sqrt(A_jj) (the
+// diagonal becomes sqrt(A_ii)), in FP64 and stored FP32.
+__global__ void k_sgs(int nnz_l, const int *__restrict__ lsrc, const int *__restrict__ lcol,
+                      const double *__restrict__ val64, const double *__restrict__ diag64,
+                      const int *__restrict__ u2l, float *__restrict__ lval, float *__restrict__ utval) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= nnz_l) return;
+    if (lval) lval[p] = (float)(val64[lsrc[p]] / sqrt(diag64[lcol[p]]));
+    if (utval) {
+        const int q = u2l[p];
+        utval[p] = (float)(val64[lsrc[q]] / sqrt(diag64[lcol[q]]));
+    }
+}
+
 __global__ void k_l_to_ut(int nnz_l, const float *__restrict__ lval, const int *__restrict__ u2l,
                           float *__restrict__ utval) {
     int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -362,6 +376,17 @@ extern "C" int lpcg_ic0(const lpcg_system *s, double shift0, int32_t max_retries
     LPCG_HIP(hipFreeAsync(l64, st));
     LPCG_HIP(hipStreamSynchronize(st));
     return rc;
+}
+
+extern "C" int lpcg_sgs(const lpcg_system *s, float *l_val, float *ut_val, hipStream_t st) {
+    if (!s || (!l_val && !ut_val)) {
+        set_error("lpcg_sgs: invalid arguments");
+        return LPCG_EINVAL;
+    }
+    k_sgs<<<nblk(s->nnz_l, 256), 256, 0, st>>>(s->nnz_l, s->lsrc, s->lcol, s->val64, s->diag64, s->u2l, l_val,
+                                                ut_val);
+    LPCG_LAUNCH_CHECK();
+    return LPCG_OK;
 }
 
 namespace {

@@ -248,6 +248,17 @@ def l_to_ut(sys: System, l_val, out=None):
     return out
 
 
+def sgs(sys: System, l_val=None, ut_val=None):
+    """Symmetric Gauss-Seidel factor L = (D + A_<) D^-1/2 (and U = L^T)."""
+    nl = sys.info["nnz_l"]
+    if l_val is None:
+        l_val = torch.empty(nl, dtype=torch.float32, device="cuda")
+    if ut_val is None:
+        ut_val = torch.empty(nl, dtype=torch.float32, device="cuda")
+    _check(lib().lpcg_sgs(sys.handle, _ptr(l_val), _ptr(ut_val), _stream()), "lpcg_sgs")
+    return l_val, ut_val
+
+
 def ic0(sys: System, shift0=0.0, max_retries=8, l_val=None, ut_val=None):
     nl = sys.info["nnz_l"]
     if l_val is None:

@@ -1,5 +1,5 @@
-"""GPU parity: PCG (Appendix algorithm) with IC(0), Jacobi and no
-preconditioner -- HIP library vs the FP64 oracle.
+"""GPU parity: PCG (Appendix algorithm) with IC(0), symmetric Gauss-Seidel,
+Jacobi and no preconditioner -- HIP library vs the FP64 oracle.
 
 Several results are correct (any x with FP64 true relative residual <= tol),
 so the comparisons are: the FP64 true residual (hard), x against the
@@ -44,9 +44,11 @@ def _kappa_bound(A):
 def _run(A, kind, tol, b, use_graph=False, pat=None):
     S = gpu_system(A)
     l = ut = None
-    pk = {"ic0": lpcg.PC_LLT, "jacobi": lpcg.PC_JACOBI, "none": lpcg.PC_NONE}[kind]
+    pk = {"ic0": lpcg.PC_LLT, "sgs": lpcg.PC_LLT, "jacobi": lpcg.PC_JACOBI, "none": lpcg.PC_NONE}[kind]
     if kind == "ic0":
         l, ut, _ = lpcg.ic0(S)
+    elif kind == "sgs":
+        l, ut = lpcg.sgs(S)
     x, res, hist = lpcg.pcg_solve(S, pk, cuda_f64(b), l_val=l, ut_val=ut, tol=tol, hist=True,
                                   use_graph=use_graph, max_restarts=3)
     return S, host(x), res, host(hist), l
@@ -57,10 +59,12 @@ def _oracle(A, kind, tol, b):
     if kind == "ic0":
         lval, _ = O.ic0(pat, A)
         return O.pcg(A, b, O.PC_LLT, pat, lval, tol=tol)
+    if kind == "sgs":
+        return O.pcg(A, b, O.PC_LLT, pat, O.sgs_factor(pat, A), tol=tol)
     return O.pcg(A, b, O.PC_JACOBI if kind == "jacobi" else O.PC_NONE, tol=tol)
 
 
-@pytest.mark.parametrize("kind", ["ic0", "jacobi", "none"])
+@pytest.mark.parametrize("kind", ["ic0", "sgs", "jacobi", "none"])
 @pytest.mark.parametrize("name", ["poisson2d_32", "heat3d_13", "fem_40", "random_777"])
 def test_pcg_small(name, kind):
     print(f"[pcg] {name} {kind}", flush=True)
@@ -92,7 +96,7 @@ def test_pcg_c0_ic0_vs_dense_cholesky():
     assert np.linalg.norm(x - xs) / np.linalg.norm(xs) <= _kappa_bound(A) * 1.5e-8
 
 
-@pytest.mark.parametrize("kind", ["ic0", "jacobi"])
+@pytest.mark.parametrize("kind", ["ic0", "sgs", "jacobi"])
 def test_pcg_c3_full_size(kind):
     """3D 64^3 heat step, tol 1e-6: FP64 true residual, iterations and sampled
     entries of x against the oracle."""
