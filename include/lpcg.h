@@ -197,13 +197,19 @@ int lpcg_time_spmv(const lpcg_system *sys, const float *x, float *y, int32_t rep
  * levels, mode 0 with 4096 waves and backoff 1 otherwise. */
 typedef struct {
     int32_t direction;     /* 0: forward (L y = r), 1: backward (L^T z = y) */
-    int32_t mode;          /* 0 dependency driven, 1 level synchronous, 2 single workgroup */
+    int32_t mode;          /* 0 dependency driven, 1 level synchronous, 2 single workgroup,
+                              3 blocked (one wave per block of block_rows consecutive rows;
+                              dependencies inside a block through LDS, on earlier blocks
+                              polled; rows with at most 7 dependencies) */
     int32_t waves;         /* mode 0: waves launched (0 = default) */
-    int32_t backoff;       /* mode 0: sleep rounds between polls (0..64) */
+    int32_t backoff;       /* modes 0 and 3: sleep rounds between polls (0..64) */
     int32_t block_stride;  /* mode 0: only blocks whose index is a multiple of this
                               (1, 2, 4 or 8) work; with the hardware's round-robin
                               dispatch over the 8 XCDs, 8 keeps every working wave
                               on one XCD (one L2).  0 means 1. */
+    int32_t block_rows;    /* mode 3: rows per block (64 .. 65536; 0 = 1024); the
+                              schedule is built on the host when the configuration is set
+                              (synchronous) */
     double us;             /* lpcg_autotune: mean duration of one solve */
 } lpcg_trsv_cfg;
 

@@ -839,6 +839,7 @@ extern "C" void lpcg_destroy(lpcg_system *s) {
     if (s->graph_exec) hipGraphExecDestroy(s->graph_exec);
     if (s->bgraph_exec) hipGraphExecDestroy(s->bgraph_exec);
     if (s->cap_stream) hipStreamDestroy(s->cap_stream);
+    for (int d = 0; d < 2; ++d) blk_free(s, d);
     for (void *p : s->allocs) hipFree(p);
     if (s->h_ctrl) hipHostFree(s->h_ctrl);
     if (s->h_scal) hipHostFree(s->h_scal);

@@ -193,6 +193,141 @@ bool wg_mode_fits(const lpcg_system *s, int transpose) {
     return (transpose ? s->max_w_b : s->max_w_f) <= kWgRows * kWgThreads;
 }
 
+// ---------------------------------------------------------------- mode 3
+constexpr size_t kBlkLdsMax = 144 * 1024;  // dynamic LDS of a blocked wave (160 KB per CU)
+
+void blk_free(lpcg_system *s, int d) {
+    for (int **p : {&s->blk_brow[d], &s->blk_bch[d], &s->blk_ch[d], &s->blk_rec[d], &s->blk_vsrc[d]}) {
+        if (*p) (void)hipFree(*p);
+        *p = nullptr;
+    }
+    s->blk_B[d] = 0;
+}
+
+template <typename T>
+static int upload(T **dst, const std::vector<T> &h) {
+    LPCG_HIP(hipMalloc((void **)dst, sizeof(T) * std::max<size_t>(1, h.size())));
+    LPCG_HIP(hipMemcpy(*dst, h.data(), sizeof(T) * h.size(), hipMemcpyHostToDevice));
+    return LPCG_OK;
+}
+
+// Schedule of direction d (0: L rows ascending, 1: U = L^T rows descending)
+// for blocks of B rows: per block, the rows ordered by their level inside the
+// block, cut into chunks of at most 64 rows of one level, and one record per
+// row (dependency codes in CSR order, row, and the positions of the values).
+int blk_prepare(lpcg_system *s, int d, int B) {
+    if (s->blk_B[d] == B && s->blk_rec[d]) return LPCG_OK;
+    if (B < 64 || B > (1 << 16)) {
+        set_error("blocked substitution: block size %d outside [64, 65536]", B);
+        return LPCG_EINVAL;
+    }
+    const int n = s->n, nl = s->nnz_l;
+    std::vector<int> rp(n + 1), ci(nl);
+    LPCG_HIP(hipDeviceSynchronize());
+    LPCG_HIP(hipMemcpy(rp.data(), d ? s->urowptr : s->lrowptr, sizeof(int) * (n + 1), hipMemcpyDeviceToHost));
+    LPCG_HIP(hipMemcpy(ci.data(), d ? s->ucol : s->lcol, sizeof(int) * nl, hipMemcpyDeviceToHost));
+    int maxdep = 0;
+    for (int r = 0; r < n; ++r) maxdep = std::max(maxdep, rp[r + 1] - rp[r] - 1);
+    const int W = maxdep <= 3 ? 3 : maxdep <= 7 ? 7 : 0;
+    if (!W) {
+        set_error("blocked substitution: a row has %d dependencies (at most 7)", maxdep);
+        return LPCG_EINVAL;
+    }
+    const int RW = 2 * W + 2, nb = (n + B - 1) / B;
+    std::vector<int> brow(2 * (size_t)nb), bch(1, 0), ch, rec((size_t)n * RW, 0), vsrc((size_t)n * (W + 1), -1);
+    std::vector<int> lev(n, 0), cnt, order;
+    int chmax = 0;
+    for (int b = 0; b < nb; ++b) {
+        const int r0 = d ? std::max(0, n - (b + 1) * B) : b * B;
+        const int r1 = d ? n - b * B : std::min(n, (b + 1) * B);
+        brow[2 * b] = r0;
+        brow[2 * b + 1] = r1 - r0;
+        int maxl = 0;
+        for (int i = 0; i < r1 - r0; ++i) {  // solve order inside the block
+            const int r = d ? r1 - 1 - i : r0 + i;
+            int l = 0;
+            for (int k = rp[r]; k < rp[r + 1]; ++k) {
+                const int c = ci[k];
+                if (c != r && c >= r0 && c < r1) l = std::max(l, lev[c] + 1);
+            }
+            lev[r] = l;
+            maxl = std::max(maxl, l);
+        }
+        cnt.assign(maxl + 2, 0);
+        for (int r = r0; r < r1; ++r) ++cnt[lev[r] + 1];
+        for (int l = 0; l <= maxl; ++l) cnt[l + 1] += cnt[l];
+        order.assign(r1 - r0, 0);
+        std::vector<int> fill(cnt.begin(), cnt.end() - 1);
+        for (int i = 0; i < r1 - r0; ++i) {
+            const int r = d ? r1 - 1 - i : r0 + i;
+            order[fill[lev[r]]++] = r;
+        }
+        const int cbase = (int)ch.size() / 2;
+        for (int l = 0; l <= maxl; ++l)
+            for (int p = cnt[l]; p < cnt[l + 1]; p += kWave) {
+                ch.push_back(p);
+                ch.push_back(std::min(kWave, cnt[l + 1] - p));
+            }
+        bch.push_back((int)ch.size() / 2);
+        chmax = std::max(chmax, (int)ch.size() / 2 - cbase);
+        for (int p = 0; p < r1 - r0; ++p) {
+            const int r = order[p];
+            int *w = &rec[(size_t)(r0 + p) * RW];
+            int *vs = &vsrc[(size_t)(r0 + p) * (W + 1)];
+            for (int t = 0; t < W; ++t) w[t] = -1;
+            w[W] = r - r0;
+            int t = 0;
+            for (int k = rp[r]; k < rp[r + 1]; ++k) {
+                const int c = ci[k];
+                if (c == r) {
+                    vs[W] = k;
+                    continue;
+                }
+                w[t] = (c >= r0 && c < r1) ? -2 - (c - r0) : c;
+                vs[t] = k;
+                ++t;
+            }
+        }
+    }
+    const size_t lds = W == 3 ? blk_lds_bytes<3>(B, chmax) : blk_lds_bytes<7>(B, chmax);
+    if (lds > kBlkLdsMax) {
+        set_error("blocked substitution: %zu bytes of LDS for block size %d (at most %zu)", lds, B, kBlkLdsMax);
+        return LPCG_EINVAL;
+    }
+    blk_free(s, d);
+    int rc;
+    if ((rc = upload(&s->blk_brow[d], brow)) || (rc = upload(&s->blk_bch[d], bch)) ||
+        (rc = upload(&s->blk_ch[d], ch)) || (rc = upload(&s->blk_rec[d], rec)) ||
+        (rc = upload(&s->blk_vsrc[d], vsrc))) {
+        blk_free(s, d);
+        return rc;
+    }
+    s->blk_B[d] = B;
+    s->blk_W[d] = W;
+    s->blk_nb[d] = nb;
+    s->blk_chmax[d] = chmax;
+    // allow the blocked kernels' dynamic LDS (set here, before any launch or
+    // graph capture that uses the schedule)
+    LPCG_HIP(hipFuncSetAttribute((const void *)k_sptrsv_blk<3>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)kBlkLdsMax));
+    LPCG_HIP(hipFuncSetAttribute((const void *)k_sptrsv_blk<7>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)kBlkLdsMax));
+    return LPCG_OK;
+}
+
+int blk_pack(const lpcg_system *s, int d, const float *lval, const float *utval, hipStream_t st) {
+    const float *v = d ? utval : lval;
+    if (s->blk_W[d] == 3) k_blk_pack<3><<<nblk(s->n, 256), 256, 0, st>>>(s->n, s->blk_vsrc[d], v, s->blk_rec[d]);
+    else k_blk_pack<7><<<nblk(s->n, 256), 256, 0, st>>>(s->n, s->blk_vsrc[d], v, s->blk_rec[d]);
+    LPCG_LAUNCH_CHECK();
+    return LPCG_OK;
+}
+
+static BlkSched blk_sched(const lpcg_system *s, int d) {
+    return BlkSched{s->blk_brow[d], s->blk_bch[d], reinterpret_cast<const int2 *>(s->blk_ch[d]), s->blk_rec[d],
+                    s->blk_nb[d], s->blk_B[d], s->blk_chmax[d]};
+}
+
 // Enqueue the kernels of one substitution with configuration c: the
 // dependency-driven kernel expects y preset to kUnset and the ticket zeroed,
 // the single-workgroup kernel the factor's values in level-ordered form
@@ -213,6 +348,22 @@ int trsv_kernels(const lpcg_system *s, int transpose, const TrsvCfg &c, const fl
         else
             k_sptrsv<false><<<blocks, 256, 0, st>>>(n, order, rp, ci, v, rhs, (uint32_t *)y, ticket, c.backoff,
                                                     c.stride);
+        LPCG_LAUNCH_CHECK();
+        return LPCG_OK;
+    }
+    if (c.mode == 3) {
+        const int d = up ? 1 : 0;
+        if (s->blk_B[d] != c.blk || !s->blk_rec[d]) {
+            set_error("blocked substitution: no schedule for block size %d", c.blk);
+            return LPCG_EINVAL;
+        }
+        const BlkSched S = blk_sched(s, d);
+        if (s->blk_W[d] == 3)
+            k_sptrsv_blk<3><<<S.nb, kWave, blk_lds_bytes<3>(S.bmax, S.chmax), st>>>(S, rhs, (uint32_t *)y, ticket,
+                                                                                 c.backoff);
+        else
+            k_sptrsv_blk<7><<<S.nb, kWave, blk_lds_bytes<7>(S.bmax, S.chmax), st>>>(S, rhs, (uint32_t *)y, ticket,
+                                                                                 c.backoff);
         LPCG_LAUNCH_CHECK();
         return LPCG_OK;
     }
@@ -258,7 +409,12 @@ int lo_prepare(const lpcg_system *s, int transpose, const float *lval, const flo
 int trsv_presets(const lpcg_system *s, int transpose, const TrsvCfg &c, const float *lval, const float *utval,
                  float *y, int *ticket, hipStream_t st) {
     if (c.mode == 2) return lo_prepare(s, transpose, lval, utval, st);
-    if (c.mode != 0) return LPCG_OK;
+    if (c.mode == 3) {
+        int rc = blk_prepare(const_cast<lpcg_system *>(s), transpose ? 1 : 0, c.blk);
+        if (rc || (rc = blk_pack(s, transpose ? 1 : 0, lval, utval, st))) return rc;
+    } else if (c.mode != 0) {
+        return LPCG_OK;
+    }
     k_fill_u32<<<nblk(s->n, 256), 256, 0, st>>>(s->n, (uint32_t *)y, kUnset);
     k_zero_i32<<<1, 64, 0, st>>>(ticket, 1);
     LPCG_LAUNCH_CHECK();
@@ -461,12 +617,13 @@ extern "C" int lpcg_get_trsv_cfg(const lpcg_system *s, int32_t direction, lpcg_t
     out->waves = c.mode == 0 ? trsv_waves(s->n, c.waves) : 0;
     out->backoff = c.backoff;
     out->block_stride = c.stride;
+    out->block_rows = c.mode == 3 ? c.blk : 0;
     out->us = 0;
     return LPCG_OK;
 }
 
 extern "C" int lpcg_set_trsv_cfg(lpcg_system *s, const lpcg_trsv_cfg *cfg) {
-    if (!s || !cfg || cfg->direction < 0 || cfg->direction > 1 || cfg->mode < 0 || cfg->mode > 2 ||
+    if (!s || !cfg || cfg->direction < 0 || cfg->direction > 1 || cfg->mode < 0 || cfg->mode > 3 ||
         cfg->waves < 0 || cfg->backoff < 0 || cfg->backoff > 64 ||
         (cfg->block_stride != 0 && cfg->block_stride != 1 && cfg->block_stride != 2 &&
          cfg->block_stride != 4 && cfg->block_stride != 8)) {
@@ -478,11 +635,16 @@ extern "C" int lpcg_set_trsv_cfg(lpcg_system *s, const lpcg_trsv_cfg *cfg) {
                   kWgRows * kWgThreads);
         return LPCG_EINVAL;
     }
+    if (cfg->mode == 3) {  // builds the schedule (synchronous)
+        const int rc = blk_prepare(s, cfg->direction, cfg->block_rows > 0 ? cfg->block_rows : 1024);
+        if (rc) return rc;
+    }
     TrsvCfg &c = s->trsv[cfg->direction];
     c.mode = cfg->mode;
     c.waves = cfg->waves;
     c.backoff = cfg->backoff;
     c.stride = cfg->block_stride > 0 ? cfg->block_stride : 1;
+    c.blk = cfg->mode == 3 ? (cfg->block_rows > 0 ? cfg->block_rows : 1024) : 0;
     if (s->graph_exec) {  // the cached PCG graph launches the old kernels
         hipGraphExecDestroy(s->graph_exec);
         s->graph_exec = nullptr;
@@ -515,6 +677,9 @@ extern "C" int lpcg_autotune(lpcg_system *s, const float *l_val, const float *ut
         std::vector<TrsvCfg> cands;
         if (nlev <= kLevelModeTuneLevels) cands.push_back(TrsvCfg{1, 0, 1, 1});
         if (wg_mode_fits(s, dir)) cands.push_back(TrsvCfg{2, 0, 1, 1});
+        for (int B : {512, 1024, 2048})  // blocked mode, where the rows and the LDS allow it
+            if (B < s->n && blk_prepare(s, dir, B) == LPCG_OK)
+                for (int bo : {0, 1}) cands.push_back(TrsvCfg{3, 0, bo, 1, B});
         for (int w : {64, 128, 256, 512, 1024, 2048, 4096})
             for (int bo : {1, 4, 16, 64}) {
                 if (w > trsv_waves(s->n, 1 << 30) && w != 64) continue;  // more waves than chunks
@@ -545,6 +710,7 @@ extern "C" int lpcg_autotune(lpcg_system *s, const float *l_val, const float *ut
                 e.waves = c.mode == 0 ? trsv_waves(s->n, c.waves) : 0;
                 e.backoff = c.backoff;
                 e.block_stride = c.stride;
+                e.block_rows = c.mode == 3 ? c.blk : 0;
                 e.us = us;
             }
             ++count;
@@ -552,6 +718,10 @@ extern "C" int lpcg_autotune(lpcg_system *s, const float *l_val, const float *ut
                 best = us;
                 best_c = c;
             }
+        }
+        if (best_c.mode == 3) {  // leave the winner's schedule in place
+            const int rc = blk_prepare(s, dir, best_c.blk);
+            if (rc) return rc;
         }
         s->trsv[dir] = best_c;
     }

@@ -308,3 +308,216 @@ static __global__ void k_lo_prep(int noff, int n, const int *__restrict__ src, c
     if (i < noff) val_lo[i] = v[src[i]];
     if (i < n) diag_lo[i] = v[dsrc[i]];
 }
+
+namespace lpcg {
+
+// ---------------------------------------------------------------------------
+// Blocked substitution (mode 3).  The rows are cut into blocks of B
+// consecutive rows, taken in solve order (ascending for L, descending for
+// L^T); one wave owns a block, blocks are handed out through a ticket in that
+// order.  A host-built schedule lists a block's rows by their level inside
+// the block (longest path over in-block dependencies), in chunks of at most
+// 64 rows of one level.  The wave copies its block's records and right-hand
+// side into LDS once, then walks the chunks: in-block dependencies are read
+// from LDS; dependencies on rows of earlier blocks are polled from global
+// memory (the value is its own ready flag, as in the dependency-driven mode),
+// their loads issued kBlkDist chunks ahead in a register ring.  Every load of
+// the ring is unconditional (slots without such a dependency read entry 0 and
+// ignore it) so that the waits for one chunk leave the later chunks' loads in
+// flight.  Accumulation follows the row's CSR order, as in the other modes.
+//
+// Record of a row (2W + 2 words, W = 3 or 7 dependencies at most): words
+// [0, W) dependency codes (>= 0: global row; -1: none; <= -2: in-block row
+// -2 - code, relative to the block's first row), word W the row relative to
+// the block's first row, words W+1 .. 2W the values, word 2W + 1 the
+// diagonal.  The values are packed per factor by k_blk_pack.
+constexpr int kBlkDist = 2;
+
+template <int W>
+struct BlkSlot {
+    int code[W];
+    int row;
+    float val[W];
+    float dg, rhs, rr;
+    uint32_t gv[W];
+    bool act;
+};
+
+template <int W>
+__device__ __forceinline__ void blk_read(BlkSlot<W> &q, const int *rec, const int2 *ch, int c, int nch) {
+    constexpr int RW = 2 * W + 2;
+    const int l = lane_id();
+    const int2 cc = ch[min(c, nch - 1)];
+    q.act = c < nch && l < cc.y;
+    const int p = cc.x + min(l, cc.y - 1);
+    const int4 *r4 = reinterpret_cast<const int4 *>(rec + p * RW);
+    int w[RW];
+#pragma unroll
+    for (int i = 0; i < RW / 4; ++i) {
+        const int4 t = r4[i];
+        w[4 * i] = t.x;
+        w[4 * i + 1] = t.y;
+        w[4 * i + 2] = t.z;
+        w[4 * i + 3] = t.w;
+    }
+#pragma unroll
+    for (int t = 0; t < W; ++t) {
+        q.code[t] = w[t];
+        q.val[t] = __int_as_float(w[W + 1 + t]);
+    }
+    q.row = w[W];
+    q.dg = __int_as_float(w[2 * W + 1]);
+}
+
+template <int W>
+__device__ __forceinline__ void blk_issue(BlkSlot<W> &q, const float *rsh, const uint32_t *ybits,
+                                          const float *rr, int r0) {
+    q.rhs = rsh[q.row];
+    q.rr = rr ? rr[r0 + q.row] : 0.f;
+#pragma unroll
+    for (int t = 0; t < W; ++t) q.gv[t] = ld_agent(&ybits[max(q.code[t], 0)]);
+}
+
+// Solve one chunk; returns the lane's solution value (0 for idle lanes).
+template <int W>
+__device__ __forceinline__ float blk_process(BlkSlot<W> &q, float *ysh, int r0, uint32_t *ybits, int backoff) {
+    bool ready = true;
+#pragma unroll
+    for (int t = 0; t < W; ++t) ready = ready && (!q.act || q.code[t] < 0 || q.gv[t] != kUnset);
+    while (__ballot(!ready) != 0) {
+        for (int s = 0; s < backoff; ++s) __builtin_amdgcn_s_sleep(1);
+        if (!ready) {
+            ready = true;
+#pragma unroll
+            for (int t = 0; t < W; ++t)
+                if (q.code[t] >= 0 && q.gv[t] == kUnset) {
+                    q.gv[t] = ld_agent(&ybits[q.code[t]]);
+                    ready = ready && q.gv[t] != kUnset;
+                }
+        }
+    }
+    float yl[W];
+#pragma unroll
+    for (int t = 0; t < W; ++t) yl[t] = ysh[q.code[t] <= -2 ? -2 - q.code[t] : 0];
+    float acc = q.rhs;
+#pragma unroll
+    for (int t = 0; t < W; ++t) {
+        const float dep = q.code[t] >= 0 ? __uint_as_float(q.gv[t]) : yl[t];
+        if (q.code[t] != -1) acc -= q.val[t] * dep;
+    }
+    const float y = acc / q.dg;
+    if (q.act) {
+        ysh[q.row] = y;
+        st_agent(&ybits[r0 + q.row], publishable(y));
+    }
+    // LDS ordering between the lanes of the wave (no global wait)
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    return q.act ? y : 0.f;
+}
+
+// Schedule of one direction (device arrays).
+struct BlkSched {
+    const int *brow;  // [2 nb]: first row and row count of block b
+    const int *bch;   // [nb + 1]: chunk range of block b
+    const int2 *ch;   // chunk table: first record (relative to the block) and rows
+    const int *rec;   // [n * (2W + 2)] records, block b's at its rows' positions
+    int nb, bmax, chmax;
+};
+
+// Dynamic LDS of the blocked kernels: records, right-hand side, solution and
+// chunk table of one block.
+template <int W>
+inline size_t blk_lds_bytes(int bmax, int chmax) {
+    return (size_t)bmax * (2 * W + 2 + 2) * 4 + (size_t)chmax * 8;
+}
+
+// Block b of a solve: stage, then walk the chunks.  rr (may be NULL): the
+// lane's sum of rr[row] * solution[row] is returned (fixed order: the lane's
+// chunks in schedule order).
+template <int W>
+__device__ double blk_solve(const BlkSched &S, int b, const float *rhs, uint32_t *ybits, const float *rr,
+                            int backoff) {
+    constexpr int RW = 2 * W + 2;
+    extern __shared__ int blk_dyn[];
+    int *rec = blk_dyn;
+    float *rsh = reinterpret_cast<float *>(rec + S.bmax * RW);
+    float *ysh = rsh + S.bmax;
+    int2 *ch = reinterpret_cast<int2 *>(ysh + S.bmax);
+    const int l = lane_id();
+    const int r0 = S.brow[2 * b], nr = S.brow[2 * b + 1];
+    const int c0 = S.bch[b], nch = S.bch[b + 1] - c0;
+    {  // staging: every load of a batch is issued before its stores
+        const int4 *src = reinterpret_cast<const int4 *>(S.rec + (size_t)r0 * RW);
+        int4 *dst = reinterpret_cast<int4 *>(rec);
+        const int n4 = nr * RW / 4;
+        for (int i = l; i < n4; i += kWave * 8) {
+            int4 v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = src[min(i + u * kWave, n4 - 1)];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (i + u * kWave < n4) dst[i + u * kWave] = v[u];
+        }
+        for (int i = l; i < nr; i += kWave * 8) {
+            float v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = rhs[r0 + min(i + u * kWave, nr - 1)];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (i + u * kWave < nr) rsh[i + u * kWave] = v[u];
+        }
+        for (int i = l; i < nch; i += kWave) ch[i] = S.ch[c0 + i];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    constexpr int R = kBlkDist + 2;
+    BlkSlot<W> q[R];
+#pragma unroll
+    for (int j = 0; j <= kBlkDist; ++j) blk_read<W>(q[j], rec, ch, j, nch);
+#pragma unroll
+    for (int j = 0; j < kBlkDist; ++j) blk_issue<W>(q[j], rsh, ybits, rr, r0);
+    double rz = 0.0;
+    for (int c = 0; c < nch; c += R) {
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            if (c + j < nch) {
+                blk_read<W>(q[(j + kBlkDist + 1) % R], rec, ch, c + j + kBlkDist + 1, nch);
+                blk_issue<W>(q[(j + kBlkDist) % R], rsh, ybits, rr, r0);
+                const float y = blk_process<W>(q[j], ysh, r0, ybits, backoff);
+                if (rr) rz += (double)q[j].rr * (double)y;
+            }
+        }
+    }
+    return rz;
+}
+
+template <int W>
+static __global__ void __launch_bounds__(kWave) k_sptrsv_blk(BlkSched S, const float *__restrict__ rhs,
+                                                            uint32_t *ybits, int *ticket, int backoff) {
+    for (;;) {
+        const int b = wave_ticket(ticket);
+        if (b >= S.nb) break;
+        blk_solve<W>(S, b, rhs, ybits, nullptr, backoff);
+    }
+}
+
+// Pack one factor's values into the records: vsrc[q * (W + 1) + t] is the
+// position of value t of record q in the factor's value array (-1: none),
+// entry W the diagonal's.
+template <int W>
+static __global__ void k_blk_pack(int n, const int *__restrict__ vsrc, const float *__restrict__ v,
+                                  int *__restrict__ rec) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    constexpr int RW = 2 * W + 2;
+#pragma unroll
+    for (int t = 0; t <= W; ++t) {
+        const int k = vsrc[(size_t)q * (W + 1) + t];
+        rec[(size_t)q * RW + W + 1 + t] = k >= 0 ? __float_as_int(v[k]) : 0;
+    }
+}
+
+}  // namespace lpcg

@@ -55,9 +55,11 @@ enum Scal : int {
 // (one launch; `waves` waves in blocks whose index is a multiple of `stride`,
 // `backoff` sleep rounds between polls), mode 1 =
 // level synchronous (one launch per level, `g` lanes per row), mode 2 = one
-// workgroup walking all levels with block barriers.
+// workgroup walking all levels with block barriers, mode 3 = blocked (one
+// wave per block of `blk` consecutive rows, in-block dependencies through
+// LDS, `backoff` sleep rounds between polls of the others).
 struct TrsvCfg {
-    int mode = 0, waves = 0, backoff = 1, stride = 1;
+    int mode = 0, waves = 0, backoff = 1, stride = 1, blk = 0;
 };
 
 }  // namespace lpcg
@@ -90,6 +92,13 @@ struct lpcg_system {
     int *lo_ptr[2] = {nullptr, nullptr}, *lo_col[2] = {nullptr, nullptr};
     int *lo_src[2] = {nullptr, nullptr}, *lo_dsrc[2] = {nullptr, nullptr};
     float *lo_val[2] = {nullptr, nullptr}, *lo_diag[2] = {nullptr, nullptr};
+    // blocked substitution (mode 3), per direction: the schedule built for
+    // block size blk_B[d] (0: none) with records of blk_W[d] dependencies
+    // (kern_sptrsv.h describes the arrays); blk_vsrc maps record values to
+    // positions in the factor's value array
+    int blk_B[2] = {0, 0}, blk_W[2] = {0, 0}, blk_nb[2] = {0, 0}, blk_chmax[2] = {0, 0};
+    int *blk_brow[2] = {nullptr, nullptr}, *blk_bch[2] = {nullptr, nullptr}, *blk_ch[2] = {nullptr, nullptr};
+    int *blk_rec[2] = {nullptr, nullptr}, *blk_vsrc[2] = {nullptr, nullptr};
     // values (device)
     double *val64 = nullptr;
     float *val32 = nullptr;
@@ -157,4 +166,9 @@ struct TrsvCfg;
 int trsv_kernels(const lpcg_system *s, int transpose, const TrsvCfg &c, const float *lval, const float *utval,
                  const float *rhs, float *y, int *ticket, hipStream_t st);
 int lo_prepare(const lpcg_system *s, int transpose, const float *lval, const float *utval, hipStream_t st);
+// Blocked mode: build (host, synchronous) the schedule of direction d for
+// block size B; pack one factor's values into its records; free it.
+int blk_prepare(lpcg_system *s, int d, int B);
+int blk_pack(const lpcg_system *s, int d, const float *lval, const float *utval, hipStream_t st);
+void blk_free(lpcg_system *s, int d);
 }  // namespace lpcg

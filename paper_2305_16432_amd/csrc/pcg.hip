@@ -59,6 +59,7 @@ struct Args {
     const int *flp, *blp;                             // device level pointers
     const int *lo_ptr_f, *lo_col_f, *lo_ptr_b, *lo_col_b;  // level-ordered packed patterns
     const float *lo_val_f, *lo_diag_f, *lo_val_b, *lo_diag_b;
+    BlkSched blk_f, blk_b;                            // blocked-mode schedules
     const float *lval, *utval, *dinv;
     const double *b;
     double *x;
@@ -159,9 +160,11 @@ __global__ void __launch_bounds__(VT) k_setup_scal(Args a) {
     }
 }
 
-// beta from the r.z partials (reducer block of the backward substitution).
+// beta from the r.z partials (reducer block of the backward substitution;
+// BS threads).
+template <int BS = VT>
 __device__ __forceinline__ void finish_rz(const Args &a, double *lds) {
-    const double rz = reduce_published<VT>(a.sp_rz, a.np_rz, lds);
+    const double rz = reduce_published<BS>(a.sp_rz, a.np_rz, lds);
     if (threadIdx.x == 0) {
         const int it = a.ctrl[C_IT];
         const double old = a.scal[S_RZ0];
@@ -200,6 +203,35 @@ __global__ void __launch_bounds__(256) k_llt_bwd(Args a) {
     }
     // reducer: the working block of highest index
     if ((int)blockIdx.x == ((int)gridDim.x - 1) / a.stride_b * a.stride_b) finish_rz(a, lds);
+}
+
+// Blocked forms (mode 3): one wave per block of rows; the backward one
+// publishes one r.z partial per block (in the block's fixed order) and its
+// last workgroup reduces them to beta.
+template <int W>
+__global__ void __launch_bounds__(kWave) k_llt_fwd_blk(Args a) {
+    if (is_done(a)) return;
+    int *ticket = a.ctrl + C_TICKET_F;
+    for (;;) {
+        const int b = wave_ticket(ticket);
+        if (b >= a.blk_f.nb) break;
+        blk_solve<W>(a.blk_f, b, a.r, a.y, nullptr, a.backoff_f);
+    }
+}
+
+template <int W>
+__global__ void __launch_bounds__(kWave) k_llt_bwd_blk(Args a) {
+    __shared__ double lds[1];
+    if (is_done(a)) return;
+    int *ticket = a.ctrl + C_TICKET_B;
+    for (;;) {
+        const int b = wave_ticket(ticket);
+        if (b >= a.blk_b.nb) break;
+        double rz = blk_solve<W>(a.blk_b, b, (const float *)a.y, a.z, a.r, a.backoff_b);
+        rz = wave_sum(rz);
+        if (lane_id() == 0) publish_partial(a.sp_rz, b, rz);
+    }
+    if (is_reducer()) finish_rz<kWave>(a, lds);
 }
 
 // Level-synchronous forms of the two substitutions: one launch per level
@@ -387,6 +419,17 @@ __global__ void __launch_bounds__(VT) k_true_fin(Args a) {
     if (threadIdx.x == 0) a.scal[S_TRUE] = rr;
 }
 
+// Dynamic LDS above the default limit for the blocked kernels of direction d
+// (set before any launch or capture).
+int blk_set_lds(const lpcg_system *s, int d) {
+    const int b = (int)(s->blk_W[d] == 3 ? blk_lds_bytes<3>(s->blk_B[d], s->blk_chmax[d])
+                                         : blk_lds_bytes<7>(s->blk_B[d], s->blk_chmax[d]));
+    const void *k = s->blk_W[d] == 3 ? (d ? (const void *)k_llt_bwd_blk<3> : (const void *)k_llt_fwd_blk<3>)
+                                     : (d ? (const void *)k_llt_bwd_blk<7> : (const void *)k_llt_fwd_blk<7>);
+    LPCG_HIP(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, b));
+    return LPCG_OK;
+}
+
 template <int KIND>
 int enqueue_iteration(const lpcg_system *s, const Args &a, hipStream_t st) {
     const int vb = s->vec_blocks;
@@ -396,6 +439,11 @@ int enqueue_iteration(const lpcg_system *s, const Args &a, hipStream_t st) {
         const bool wf = s->trsv[0].mode == 2, wb = s->trsv[1].mode == 2;
         if (wf) {
             k_llt_wg<<<1, kWgThreads, 0, st>>>(a, 1, wb ? 1 : 0);
+        } else if (s->trsv[0].mode == 3) {
+            if (s->blk_W[0] == 3)
+                k_llt_fwd_blk<3><<<a.blk_f.nb, kWave, blk_lds_bytes<3>(a.blk_f.bmax, a.blk_f.chmax), st>>>(a);
+            else
+                k_llt_fwd_blk<7><<<a.blk_f.nb, kWave, blk_lds_bytes<7>(a.blk_f.bmax, a.blk_f.chmax), st>>>(a);
         } else if (s->trsv[0].mode == 0) {
             k_llt_fwd<<<(trsv_waves(s->n, s->trsv[0].waves) + 3) / 4 * s->trsv[0].stride, 256, 0, st>>>(a);
         } else {
@@ -409,6 +457,11 @@ int enqueue_iteration(const lpcg_system *s, const Args &a, hipStream_t st) {
         }
         if (wb) {
             if (!wf) k_llt_wg<<<1, kWgThreads, 0, st>>>(a, 0, 1);
+        } else if (s->trsv[1].mode == 3) {
+            if (s->blk_W[1] == 3)
+                k_llt_bwd_blk<3><<<a.blk_b.nb, kWave, blk_lds_bytes<3>(a.blk_b.bmax, a.blk_b.chmax), st>>>(a);
+            else
+                k_llt_bwd_blk<7><<<a.blk_b.nb, kWave, blk_lds_bytes<7>(a.blk_b.bmax, a.blk_b.chmax), st>>>(a);
         } else if (s->trsv[1].mode == 0) {
             k_llt_bwd<<<(trsv_waves(s->n, s->trsv[1].waves) + 3) / 4 * s->trsv[1].stride, 256, 0, st>>>(a);
         } else {
@@ -447,10 +500,11 @@ int run_solve(lpcg_system *s, const Args &a, const lpcg_solve_opts &o, int &iter
     hipGraphExec_t exec = nullptr;
     if (o.use_graph) {
         // key: kernel arguments + preconditioner kind + chunk length
-        std::vector<unsigned char> key(sizeof(Args) + 9 * sizeof(int));
+        std::vector<unsigned char> key(sizeof(Args) + 11 * sizeof(int));
         memcpy(key.data(), &a, sizeof(Args));
-        const int extra[9] = {KIND, chunk, s->trsv[0].mode, s->trsv[0].waves, s->trsv[0].backoff,
-                              s->trsv[1].mode, s->trsv[1].waves, s->trsv[1].backoff, s->trsv_g};
+        const int extra[11] = {KIND, chunk, s->trsv[0].mode, s->trsv[0].waves, s->trsv[0].backoff,
+                               s->trsv[1].mode, s->trsv[1].waves, s->trsv[1].backoff, s->trsv_g,
+                               s->trsv[0].blk, s->trsv[1].blk};
         // (the block strides travel in Args and are part of the key through it)
         memcpy(key.data() + sizeof(Args), extra, sizeof(extra));
         if (s->graph_exec && s->graph_key == key) {
@@ -535,10 +589,12 @@ extern "C" int lpcg_pcg_solve(lpcg_system *s, const lpcg_precond *P, const doubl
     a.backoff_b = s->trsv[1].backoff;
     a.stride_f = s->trsv[0].stride;
     a.stride_b = s->trsv[1].stride;
-    a.reset_y = s->trsv[0].mode == 0;
-    a.reset_z = s->trsv[1].mode == 0;
+    a.reset_y = s->trsv[0].mode == 0 || s->trsv[0].mode == 3;
+    a.reset_z = s->trsv[1].mode == 0 || s->trsv[1].mode == 3;
     if (s->trsv[1].mode == 0) {
         a.np_rz = (s->n + kWave - 1) / kWave;
+    } else if (s->trsv[1].mode == 3) {
+        a.np_rz = s->blk_nb[1];
     } else {
         a.np_rz = 0;
         for (size_t l = 0; l + 1 < s->h_blev_ptr.size(); ++l)
@@ -595,12 +651,21 @@ extern "C" int lpcg_pcg_solve(lpcg_system *s, const lpcg_precond *P, const doubl
     a.coef = coef;
     a.ctrl = s->ctrl;
     a.tol2 = opts->tol * opts->tol;
-    if (P->kind == LPCG_PC_LLT) {  // level-ordered factor values for the single-workgroup mode
-        for (int d = 0; d < 2; ++d)
-            if (s->trsv[d].mode == 2) {
-                int rc = lo_prepare(s, d, P->l_val, P->ut_val, st);
-                if (rc) return rc;
+    if (P->kind == LPCG_PC_LLT) {  // the factor's values in the layouts of the single-workgroup and blocked modes
+        for (int d = 0; d < 2; ++d) {
+            int rc = LPCG_OK;
+            if (s->trsv[d].mode == 2) rc = lo_prepare(s, d, P->l_val, P->ut_val, st);
+            if (s->trsv[d].mode == 3) {
+                if ((rc = blk_prepare(s, d, s->trsv[d].blk)) || (rc = blk_pack(s, d, P->l_val, P->ut_val, st)))
+                    return rc;
+                rc = blk_set_lds(s, d);
             }
+            if (rc) return rc;
+        }
+        a.blk_f = BlkSched{s->blk_brow[0], s->blk_bch[0], reinterpret_cast<const int2 *>(s->blk_ch[0]),
+                           s->blk_rec[0], s->blk_nb[0], s->blk_B[0], s->blk_chmax[0]};
+        a.blk_b = BlkSched{s->blk_brow[1], s->blk_bch[1], reinterpret_cast<const int2 *>(s->blk_ch[1]),
+                           s->blk_rec[1], s->blk_nb[1], s->blk_B[1], s->blk_chmax[1]};
     }
     if (P->kind == LPCG_PC_JACOBI && !P->dinv) {
         int rc = lpcg_jacobi(s, s->dinv, st);

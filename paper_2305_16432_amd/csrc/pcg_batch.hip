@@ -351,10 +351,11 @@ int run_batch(lpcg_system *s, const BArgs &a, const lpcg_precond *P, const lpcg_
     const int chunk = o.check_every > 0 ? o.check_every : 8;
     hipGraphExec_t exec = nullptr;
     if (o.use_graph) {
-        std::vector<unsigned char> key(sizeof(BArgs) + 10 * sizeof(int) + 2 * sizeof(void *));
+        std::vector<unsigned char> key(sizeof(BArgs) + 12 * sizeof(int) + 2 * sizeof(void *));
         memcpy(key.data(), &a, sizeof(BArgs));
-        const int extra[10] = {KIND, chunk, s->trsv[0].mode, s->trsv[0].waves, s->trsv[0].backoff, s->trsv[0].stride,
-                               s->trsv[1].mode, s->trsv[1].waves, s->trsv[1].backoff, s->trsv[1].stride};
+        const int extra[12] = {KIND, chunk, s->trsv[0].mode, s->trsv[0].waves, s->trsv[0].backoff, s->trsv[0].stride,
+                               s->trsv[1].mode, s->trsv[1].waves, s->trsv[1].backoff, s->trsv[1].stride,
+                               s->trsv[0].blk, s->trsv[1].blk};
         memcpy(key.data() + sizeof(BArgs), extra, sizeof(extra));
         const void *vals[2] = {P->l_val, P->ut_val};
         memcpy(key.data() + sizeof(BArgs) + sizeof(extra), vals, sizeof(vals));
@@ -410,8 +411,8 @@ int batch_solve_internal(lpcg_system *s, const lpcg_precond *P, const double *b,
     a.n = s->n;
     a.nseg = s->nseg;
     a.maxit = o.maxit > 0 ? o.maxit : s->n;
-    a.reset_y = s->trsv[0].mode == 0;
-    a.reset_z = s->trsv[1].mode == 0;
+    a.reset_y = s->trsv[0].mode == 0 || s->trsv[0].mode == 3;
+    a.reset_z = s->trsv[1].mode == 0 || s->trsv[1].mode == 3;
     a.seg_sys = s->seg_sys;
     a.seg_row0 = s->seg_row0;
     a.seg_row1 = s->seg_row1;
@@ -486,11 +487,13 @@ int check_precond(const lpcg_precond *P, const char *who) {
 
 int prepare_precond(lpcg_system *s, const lpcg_precond *P, hipStream_t st) {
     if (P->kind == LPCG_PC_LLT)
-        for (int d = 0; d < 2; ++d)
-            if (s->trsv[d].mode == 2) {
-                int rc = lo_prepare(s, d, P->l_val, P->ut_val, st);
-                if (rc) return rc;
-            }
+        for (int d = 0; d < 2; ++d) {
+            int rc = LPCG_OK;
+            if (s->trsv[d].mode == 2) rc = lo_prepare(s, d, P->l_val, P->ut_val, st);
+            if (s->trsv[d].mode == 3 && !(rc = blk_prepare(s, d, s->trsv[d].blk)))
+                rc = blk_pack(s, d, P->l_val, P->ut_val, st);
+            if (rc) return rc;
+        }
     if (P->kind == LPCG_PC_JACOBI && !P->dinv) return lpcg_jacobi(s, s->dinv, st);
     return LPCG_OK;
 }

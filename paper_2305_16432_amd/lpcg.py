@@ -57,7 +57,8 @@ class _Result(C.Structure):
 
 class _TrsvCfg(C.Structure):
     _fields_ = [("direction", C.c_int32), ("mode", C.c_int32), ("waves", C.c_int32),
-                ("backoff", C.c_int32), ("block_stride", C.c_int32), ("us", C.c_double)]
+                ("backoff", C.c_int32), ("block_stride", C.c_int32), ("block_rows", C.c_int32),
+                ("us", C.c_double)]
 
 
 class _Gnn(C.Structure):
@@ -201,12 +202,13 @@ def export_perm(sys: System):
 def autotune(sys: System, l_val, ut_val, reps: int = 5) -> list:
     """Time every substitution configuration, keep the fastest per
     direction; returns the measured table as a list of dicts."""
-    table = (_TrsvCfg * 64)()
+    cap = 256
+    table = (_TrsvCfg * cap)()
     n = C.c_int32(0)
-    rc = lib().lpcg_autotune(sys.handle, _ptr(l_val), _ptr(ut_val), C.c_int32(reps), table, C.c_int32(64),
+    rc = lib().lpcg_autotune(sys.handle, _ptr(l_val), _ptr(ut_val), C.c_int32(reps), table, C.c_int32(cap),
                              C.byref(n), _stream())
     _check(rc, "lpcg_autotune")
-    return [{f: getattr(table[i], f) for f, _ in _TrsvCfg._fields_} for i in range(min(n.value, 64))]
+    return [{f: getattr(table[i], f) for f, _ in _TrsvCfg._fields_} for i in range(min(n.value, cap))]
 
 
 def get_trsv_cfg(sys: System, direction: int) -> dict:
@@ -216,8 +218,8 @@ def get_trsv_cfg(sys: System, direction: int) -> dict:
 
 
 def set_trsv_cfg(sys: System, direction: int, mode: int, waves: int = 0, backoff: int = 1,
-                 block_stride: int = 1):
-    c = _TrsvCfg(direction, mode, waves, backoff, block_stride, 0.0)
+                 block_stride: int = 1, block_rows: int = 0):
+    c = _TrsvCfg(direction, mode, waves, backoff, block_stride, block_rows, 0.0)
     _check(lib().lpcg_set_trsv_cfg(sys.handle, C.byref(c)), "lpcg_set_trsv_cfg")
 
 

@@ -1,6 +1,7 @@
-"""Both substitution modes (dependency driven with several wave counts and
-back-offs; level synchronous) in both row orderings, against the oracle, and
-the autotuner that chooses between them.
+"""Every substitution mode (dependency driven with several wave counts and
+back-offs; level synchronous; single workgroup; blocked with several block
+sizes) in both row orderings, against the oracle, and the autotuner that
+chooses between them.
 
 Bars: componentwise backward error |rhs - T y| <= 4 k u32 |T| |y| for the
 solves (Higham's substitution bound in FP32, c = 4 covering FMA and the
@@ -16,7 +17,31 @@ from tests.gpu_util import U32, cuda_f32, cuda_f64, gpu_system, host, matrices_s
 
 pytestmark = pytest.mark.gpu
 
-CFGS = [(0, 256, 4, 1), (0, 4096, 1, 1), (0, 1024, 16, 1), (0, 128, 16, 8), (1, 0, 1, 1), (2, 0, 1, 1)]
+# (mode, waves, backoff, block stride, block rows)
+CFGS = [(0, 256, 4, 1, 0), (0, 4096, 1, 1, 0), (0, 1024, 16, 1, 0), (0, 128, 16, 8, 0), (1, 0, 1, 1, 0),
+        (2, 0, 1, 1, 0), (3, 0, 0, 1, 64), (3, 0, 1, 1, 256), (3, 0, 0, 1, 1024)]
+
+
+def _blocked_fits(pat):
+    """The blocked mode takes rows with at most 7 dependencies."""
+    return max(np.diff(pat.lrowptr).max(), np.diff(pat.urowptr).max()) - 1 <= 7
+
+
+def _set_all(S, pat, cfg):
+    """Set cfg in both directions; False when the blocked mode (correctly)
+    refuses the pattern."""
+    mode, waves, backoff, stride, brows = cfg
+    if mode == 3 and not _blocked_fits(pat):
+        with pytest.raises(lpcg.LpcgError) as e:
+            lpcg.set_trsv_cfg(S, 0, mode, waves, backoff, stride, brows)
+        assert e.value.code == lpcg.EINVAL
+        return False
+    for d in (0, 1):
+        lpcg.set_trsv_cfg(S, d, mode, waves, backoff, stride, brows)
+        got = lpcg.get_trsv_cfg(S, d)
+        assert got["mode"] == mode and got["block_stride"] == stride
+        assert got["block_rows"] == (brows if mode == 3 else 0)
+    return True
 
 
 def _lower(pat, seed):
@@ -32,7 +57,6 @@ def _lower(pat, seed):
 @pytest.mark.parametrize("ordering", [0, 1])
 @pytest.mark.parametrize("name", ["tridiag_1000", "heat3d_13", "fem_40", "random_777", "one"])
 def test_sptrsv_modes(name, ordering, cfg):
-    mode, waves, backoff, stride = cfg
     print(f"[trsv] {name} ordering {ordering} cfg {cfg}", flush=True)
     A = matrices_small()[name]
     if ordering:
@@ -42,9 +66,8 @@ def test_sptrsv_modes(name, ordering, cfg):
         perm, Ai = np.arange(A.n), A
     pat = O.Pattern(Ai)
     S = gpu_system(A, None, ordering)
-    for d in (0, 1):
-        lpcg.set_trsv_cfg(S, d, mode, waves, backoff, stride)
-        assert lpcg.get_trsv_cfg(S, d)["mode"] == mode and lpcg.get_trsv_cfg(S, d)["block_stride"] == stride
+    if not _set_all(S, pat, cfg):
+        return
     lval = _lower(pat, 3)
     utv = lval[pat.usrc]
     rhs = np.random.default_rng(4).standard_normal(A.n).astype(np.float32).astype(np.float64)
@@ -73,8 +96,8 @@ def test_pcg_ic0_modes(name, ordering, cfg):
         perm, Ai = np.arange(A.n), A
     pat = O.Pattern(Ai)
     S = gpu_system(A, None, ordering)
-    for d in (0, 1):
-        lpcg.set_trsv_cfg(S, d, *cfg)
+    if not _set_all(S, pat, cfg):
+        return
     l, ut, _ = lpcg.ic0(S)
     for use_graph in (False, True):
         x, res = lpcg.pcg_solve(S, lpcg.PC_LLT, cuda_f64(b), l_val=l, ut_val=ut, tol=1e-6, max_restarts=2,
@@ -98,19 +121,20 @@ def test_autotune_c3_full_size(ordering):
         best = min(rows, key=lambda t: t["us"])
         got = lpcg.get_trsv_cfg(S, d)
         assert got["mode"] == best["mode"] and got["backoff"] == best["backoff"]
-        assert got["block_stride"] == best["block_stride"]
+        assert got["block_stride"] == best["block_stride"] and got["block_rows"] == best["block_rows"]
         if best["mode"] == 0:
             assert got["waves"] == best["waves"]
         for t in sorted(rows, key=lambda t: t["us"])[:6]:
             print(f"  dir {d} mode {t['mode']} waves {t['waves']} backoff {t['backoff']} "
-                  f"stride {t['block_stride']}: {t['us']:.1f} us")
+                  f"stride {t['block_stride']} rows {t['block_rows']}: {t['us']:.1f} us")
     x, res = lpcg.pcg_solve(S, lpcg.PC_LLT, cuda_f64(b), l_val=l, ut_val=ut, tol=1e-6, max_restarts=2)
     assert res["status"] == 0 and O.true_relres(A, b, host(x)) <= 1e-6
 
 
 def test_trsv_cfg_rejects_bad_values():
     S = gpu_system(g.poisson_grid(5, 2))
-    for bad in [(2, 0, 0, 1), (0, 3, 0, 1), (0, 0, 0, 65), (0, 0, 0, 1, 3)]:
+    for bad in [(2, 0, 0, 1), (0, 4, 0, 1), (0, 0, 0, 65), (0, 0, 0, 1, 3), (0, 3, 0, 1, 1, 32),
+                (0, 3, 0, 1, 1, 1 << 17)]:
         with pytest.raises(lpcg.LpcgError) as e:
             lpcg.set_trsv_cfg(S, *bad)
         assert e.value.code == lpcg.EINVAL
@@ -138,3 +162,46 @@ def test_single_workgroup_c3_full_size(transpose):
     L = g.CSR(A.n, pat.lrowptr, pat.lcol, lval).to_scipy()
     T = L.T if transpose else L
     assert np.all(np.abs(rhs - T @ y) <= 4 * 4 * U32 * (abs(T) @ np.abs(y)))
+
+
+@pytest.mark.parametrize("brows", [1024, 2048])
+@pytest.mark.parametrize("transpose", [False, True])
+def test_blocked_c3_full_size(transpose, brows):
+    """Mode 3 at 64^3 natural order: backward error against the GPU IC(0)
+    factor, and the same arithmetic as the dependency-driven mode (the row's
+    entries in CSR order), reported."""
+    print(f"[blocked] heat3d_64 transpose {transpose} rows {brows}", flush=True)
+    A, b = g.heat_system_3d(64, 1e-3, 1000, 2000)
+    pat = O.Pattern(A)
+    S = gpu_system(A)
+    l, ut, _ = lpcg.ic0(S)
+    rhs = b.astype(np.float32).astype(np.float64)
+    outs = {}
+    for mode, br in ((0, 0), (3, brows)):
+        for d in (0, 1):
+            lpcg.set_trsv_cfg(S, d, mode, 0, 1 if mode == 0 else 0, 1, br)
+        outs[mode] = host(lpcg.sptrsv(S, transpose, l, ut, cuda_f32(rhs))).astype(np.float64)
+    y = outs[3]
+    L = g.CSR(A.n, pat.lrowptr, pat.lcol, host(l).astype(np.float64)).to_scipy()
+    T = L.T if transpose else L
+    assert np.all(np.abs(rhs - T @ y) <= 4 * 4 * U32 * (abs(T) @ np.abs(y)))
+    print("bit-identical to the dependency-driven mode:", np.array_equal(outs[0], y),
+          "max rel diff", np.max(np.abs(outs[0] - y) / (np.abs(y) + 1e-30)))
+
+
+def test_blocked_pcg_c3_full_size():
+    """PCG at 64^3 with blocked substitutions in both directions (graph
+    captured): FP64 true residual and iterations equal to the dependency-
+    driven run."""
+    A, b = g.heat_system_3d(64, 1e-3, 1000, 2000)
+    S = gpu_system(A)
+    l, ut, _ = lpcg.ic0(S)
+    its = {}
+    for mode, br in ((0, 0), (3, 1024)):
+        for d in (0, 1):
+            lpcg.set_trsv_cfg(S, d, mode, 0, 1 if mode == 0 else 0, 1, br)
+        x, res = lpcg.pcg_solve(S, lpcg.PC_LLT, cuda_f64(b), l_val=l, ut_val=ut, tol=1e-6, max_restarts=2,
+                                use_graph=True)
+        assert res["status"] == 0 and O.true_relres(A, b, host(x)) <= 1e-6
+        its[mode] = res["iters"]
+    assert abs(its[3] - its[0]) <= 1, its
