@@ -509,9 +509,10 @@ extern "C" int lpcg_ic0(const lpcg_system *s, double shift0, int32_t max_retries
         k_fill_u64<<<nblk(s->nnz_l, 256), 256, 0, st>>>(s->nnz_l, (uint64_t *)l64, kUnset64);
         k_set_i32<<<1, 1, 0, st>>>(flags, 0);
         k_set_i32<<<1, 1, 0, st>>>(bad, 0x7fffffff);
-        // same DAG as the forward substitution: reuse its wave count and
-        // back-off when that direction runs dependency driven
-        const TrsvCfg &fc = s->trsv[0];
+        // same DAG as the forward substitution: reuse the wave count and
+        // back-off of its fastest dependency-driven configuration (tuned), or
+        // of the forward direction when that runs dependency driven
+        const TrsvCfg &fc = s->ic0_tuned ? s->ic0_cfg : s->trsv[0];
         const int blocks = nblk(trsv_waves(s->n, fc.mode == 0 ? fc.waves : 0), 4);
         k_ic0<<<blocks, 256, 0, st>>>(s->n, s->flev_rows, s->lrowptr, s->lcol, s->lsrc, s->val64, shift,
                                       (uint64_t *)l64, flags, bad, fc.mode == 0 ? fc.backoff : 1);
@@ -686,7 +687,7 @@ extern "C" int lpcg_autotune(lpcg_system *s, const float *l_val, const float *ut
                 cands.push_back(TrsvCfg{0, w, bo, 1});
                 if (w <= 512) cands.push_back(TrsvCfg{0, w, bo, 8});  // all waves on one XCD
             }
-        double best = 1e30;
+        double best = 1e30, best0 = 1e30;
         TrsvCfg best_c = s->trsv[dir];
         for (const TrsvCfg &c : cands) {
             double tot = 0;
@@ -717,6 +718,11 @@ extern "C" int lpcg_autotune(lpcg_system *s, const float *l_val, const float *ut
             if (us < best) {
                 best = us;
                 best_c = c;
+            }
+            if (dir == 0 && c.mode == 0 && c.stride == 1 && us < best0) {  // IC(0) walks the same DAG
+                best0 = us;
+                s->ic0_cfg = c;
+                s->ic0_tuned = true;
             }
         }
         if (best_c.mode == 3) {  // leave the winner's schedule in place

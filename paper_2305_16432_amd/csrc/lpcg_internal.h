@@ -120,6 +120,8 @@ struct lpcg_system {
     int spmv_blocks = 1;         // grid of the fused SpMV + p.w kernel
     int spmv_group = 8;          // lanes per row in SpMV
     lpcg::TrsvCfg trsv[2];       // forward (L) and backward (L^T) substitution
+    lpcg::TrsvCfg ic0_cfg;       // IC(0): the fastest dependency-driven forward configuration
+    bool ic0_tuned = false;
     int trsv_g = 8;              // lanes per row of the level-synchronous kernel
     // batched solves: row segments of at most kSegRows rows that never cross
     // a system (one block each), the segment range of every system, and the

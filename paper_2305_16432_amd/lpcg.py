@@ -448,7 +448,10 @@ def gnn_workspace(sys: System, h: int, n_mp: int, train: bool = False) -> torch.
 def _net(params, h, n_mp, diag_mode=0):
     if params.dtype != torch.float32:
         raise TypeError("params must be float32")
-    return _Gnn(h, n_mp, _ptr(params), diag_mode, 1 if has_x_head(params.numel(), h, n_mp) else 0)
+    # the head is present when the vector has the head's layout; the library
+    # validates the dimensions themselves
+    x_head = 1 if h > 0 and 1 <= n_mp and params.numel() == param_count(h, n_mp, True) else 0
+    return _Gnn(h, n_mp, _ptr(params), diag_mode, x_head)
 
 
 def gnn_predict_L(sys: System, params, h: int, n_mp: int, b, ws, l_val=None, ut_val=None, diag_mode=0):
