@@ -1,7 +1,10 @@
 // Sparse triangular substitution with the factor of P = L L^T (Appendix PCG,
-// "Solve P z = r": forward L y = r, then backward L^T z = y).
+// "Solve P z = r": forward L y = r, then backward L^T z = y).  Four modes,
+// chosen per direction by the autotuner: dependency driven (below), level
+// synchronous, single workgroup, and blocked (sections further down).  Every
+// mode accumulates a row's entries in CSR order.
 //
-// One launch per solve, dependency driven (no level barriers):
+// Dependency-driven mode, one launch per solve (no level barriers):
 //  * rows are visited in level order (level sets of the analysis), handed
 //    out 64 at a time to waves through a ticket counter, so a wave only ever
 //    waits on rows that were handed out earlier, to waves already running;
