@@ -206,7 +206,10 @@ typedef struct {
     int32_t block_stride;  /* mode 0: only blocks whose index is a multiple of this
                               (1, 2, 4 or 8) work; with the hardware's round-robin
                               dispatch over the 8 XCDs, 8 keeps every working wave
-                              on one XCD (one L2).  0 means 1. */
+                              on one XCD (one L2).  mode 3: 8 runs only the waves that
+                              the hardware reports on XCD 0 (its XCC_ID register), so
+                              all exchanges stay in one L2; other values: every wave.
+                              0 means 1. */
     int32_t block_rows;    /* mode 3: rows per block (64 .. 65536; 0 = 1024); the
                               schedule is built on the host when the configuration is set
                               (synchronous) */

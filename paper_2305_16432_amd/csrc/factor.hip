@@ -358,12 +358,13 @@ int trsv_kernels(const lpcg_system *s, int transpose, const TrsvCfg &c, const fl
             return LPCG_EINVAL;
         }
         const BlkSched S = blk_sched(s, d);
+        const int local = c.stride == 8, grid = S.nb * (local ? 8 : 1);
         if (s->blk_W[d] == 3)
-            k_sptrsv_blk<3><<<S.nb, kWave, blk_lds_bytes<3>(S.bmax, S.chmax), st>>>(S, rhs, (uint32_t *)y, ticket,
-                                                                                 c.backoff);
+            k_sptrsv_blk<3><<<grid, kWave, blk_lds_bytes<3>(S.bmax, S.chmax), st>>>(S, rhs, (uint32_t *)y, ticket,
+                                                                                 c.backoff, local);
         else
-            k_sptrsv_blk<7><<<S.nb, kWave, blk_lds_bytes<7>(S.bmax, S.chmax), st>>>(S, rhs, (uint32_t *)y, ticket,
-                                                                                 c.backoff);
+            k_sptrsv_blk<7><<<grid, kWave, blk_lds_bytes<7>(S.bmax, S.chmax), st>>>(S, rhs, (uint32_t *)y, ticket,
+                                                                                 c.backoff, local);
         LPCG_LAUNCH_CHECK();
         return LPCG_OK;
     }
@@ -680,7 +681,8 @@ extern "C" int lpcg_autotune(lpcg_system *s, const float *l_val, const float *ut
         if (wg_mode_fits(s, dir)) cands.push_back(TrsvCfg{2, 0, 1, 1});
         for (int B : {512, 1024, 2048})  // blocked mode, where the rows and the LDS allow it
             if (B < s->n && blk_prepare(s, dir, B) == LPCG_OK)
-                for (int bo : {0, 1}) cands.push_back(TrsvCfg{3, 0, bo, 1, B});
+                for (int bo : {0, 1})
+                    for (int xl : {1, 8}) cands.push_back(TrsvCfg{3, 0, bo, xl, B});  // 8: on XCD 0 only
         for (int w : {64, 128, 256, 512, 1024, 2048, 4096})
             for (int bo : {1, 4, 16, 64}) {
                 if (w > trsv_waves(s->n, 1 << 30) && w != 64) continue;  // more waves than chunks

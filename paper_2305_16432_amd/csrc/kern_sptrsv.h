@@ -497,9 +497,20 @@ __device__ double blk_solve(const BlkSched &S, int b, const float *rhs, uint32_t
     return rz;
 }
 
+// XCD-local variant: only the waves running on XCD 0 (hardware register
+// XCC_ID) take tickets, so every exchange between blocks stays in that XCD's
+// L2; the grid is launched 8 times larger.  Waves elsewhere hold no ticket, so
+// the ticket argument (a wave only waits on blocks held by running waves)
+// is unchanged.
+__device__ __forceinline__ bool blk_off_xcd(int local) {
+    return local && (__builtin_amdgcn_s_getreg((20) | (0 << 6) | (3 << 11)) & 7) != 0;
+}
+
 template <int W>
 static __global__ void __launch_bounds__(kWave) k_sptrsv_blk(BlkSched S, const float *__restrict__ rhs,
-                                                            uint32_t *ybits, int *ticket, int backoff) {
+                                                            uint32_t *ybits, int *ticket, int backoff,
+                                                            int local) {
+    if (blk_off_xcd(local)) return;
     for (;;) {
         const int b = wave_ticket(ticket);
         if (b >= S.nb) break;

@@ -205,11 +205,14 @@ __global__ void __launch_bounds__(256) k_llt_bwd(Args a) {
     if ((int)blockIdx.x == ((int)gridDim.x - 1) / a.stride_b * a.stride_b) finish_rz(a, lds);
 }
 
-// Blocked forms (mode 3): one wave per block of rows; the backward one
-// publishes one r.z partial per block (in the block's fixed order) and its
-// last workgroup reduces them to beta.
+// Blocked forms (mode 3): one wave per block of rows (block stride 8: the
+// XCD-local variant); the backward one publishes one r.z partial per block
+// (in the block's fixed order) and the wave that solved the last block
+// reduces them to beta (it waits only on blocks of lower tickets, held by
+// running waves).
 template <int W>
 __global__ void __launch_bounds__(kWave) k_llt_fwd_blk(Args a) {
+    if (blk_off_xcd(a.stride_f == 8)) return;
     if (is_done(a)) return;
     int *ticket = a.ctrl + C_TICKET_F;
     for (;;) {
@@ -222,16 +225,19 @@ __global__ void __launch_bounds__(kWave) k_llt_fwd_blk(Args a) {
 template <int W>
 __global__ void __launch_bounds__(kWave) k_llt_bwd_blk(Args a) {
     __shared__ double lds[1];
+    if (blk_off_xcd(a.stride_b == 8)) return;
     if (is_done(a)) return;
     int *ticket = a.ctrl + C_TICKET_B;
+    bool last = false;
     for (;;) {
         const int b = wave_ticket(ticket);
         if (b >= a.blk_b.nb) break;
         double rz = blk_solve<W>(a.blk_b, b, (const float *)a.y, a.z, a.r, a.backoff_b);
         rz = wave_sum(rz);
         if (lane_id() == 0) publish_partial(a.sp_rz, b, rz);
+        last = last || b == a.blk_b.nb - 1;
     }
-    if (is_reducer()) finish_rz<kWave>(a, lds);
+    if (last) finish_rz<kWave>(a, lds);
 }
 
 // Level-synchronous forms of the two substitutions: one launch per level
@@ -440,10 +446,11 @@ int enqueue_iteration(const lpcg_system *s, const Args &a, hipStream_t st) {
         if (wf) {
             k_llt_wg<<<1, kWgThreads, 0, st>>>(a, 1, wb ? 1 : 0);
         } else if (s->trsv[0].mode == 3) {
+            const int grid = a.blk_f.nb * (a.stride_f == 8 ? 8 : 1);
             if (s->blk_W[0] == 3)
-                k_llt_fwd_blk<3><<<a.blk_f.nb, kWave, blk_lds_bytes<3>(a.blk_f.bmax, a.blk_f.chmax), st>>>(a);
+                k_llt_fwd_blk<3><<<grid, kWave, blk_lds_bytes<3>(a.blk_f.bmax, a.blk_f.chmax), st>>>(a);
             else
-                k_llt_fwd_blk<7><<<a.blk_f.nb, kWave, blk_lds_bytes<7>(a.blk_f.bmax, a.blk_f.chmax), st>>>(a);
+                k_llt_fwd_blk<7><<<grid, kWave, blk_lds_bytes<7>(a.blk_f.bmax, a.blk_f.chmax), st>>>(a);
         } else if (s->trsv[0].mode == 0) {
             k_llt_fwd<<<(trsv_waves(s->n, s->trsv[0].waves) + 3) / 4 * s->trsv[0].stride, 256, 0, st>>>(a);
         } else {
@@ -458,10 +465,11 @@ int enqueue_iteration(const lpcg_system *s, const Args &a, hipStream_t st) {
         if (wb) {
             if (!wf) k_llt_wg<<<1, kWgThreads, 0, st>>>(a, 0, 1);
         } else if (s->trsv[1].mode == 3) {
+            const int grid = a.blk_b.nb * (a.stride_b == 8 ? 8 : 1);
             if (s->blk_W[1] == 3)
-                k_llt_bwd_blk<3><<<a.blk_b.nb, kWave, blk_lds_bytes<3>(a.blk_b.bmax, a.blk_b.chmax), st>>>(a);
+                k_llt_bwd_blk<3><<<grid, kWave, blk_lds_bytes<3>(a.blk_b.bmax, a.blk_b.chmax), st>>>(a);
             else
-                k_llt_bwd_blk<7><<<a.blk_b.nb, kWave, blk_lds_bytes<7>(a.blk_b.bmax, a.blk_b.chmax), st>>>(a);
+                k_llt_bwd_blk<7><<<grid, kWave, blk_lds_bytes<7>(a.blk_b.bmax, a.blk_b.chmax), st>>>(a);
         } else if (s->trsv[1].mode == 0) {
             k_llt_bwd<<<(trsv_waves(s->n, s->trsv[1].waves) + 3) / 4 * s->trsv[1].stride, 256, 0, st>>>(a);
         } else {

@@ -19,7 +19,7 @@ pytestmark = pytest.mark.gpu
 
 # (mode, waves, backoff, block stride, block rows)
 CFGS = [(0, 256, 4, 1, 0), (0, 4096, 1, 1, 0), (0, 1024, 16, 1, 0), (0, 128, 16, 8, 0), (1, 0, 1, 1, 0),
-        (2, 0, 1, 1, 0), (3, 0, 0, 1, 64), (3, 0, 1, 1, 256), (3, 0, 0, 1, 1024)]
+        (2, 0, 1, 1, 0), (3, 0, 0, 1, 64), (3, 0, 1, 1, 256), (3, 0, 0, 1, 1024), (3, 0, 0, 8, 128)]
 
 
 def _blocked_fits(pat):
@@ -191,17 +191,17 @@ def test_blocked_c3_full_size(transpose, brows):
 
 def test_blocked_pcg_c3_full_size():
     """PCG at 64^3 with blocked substitutions in both directions (graph
-    captured): FP64 true residual and iterations equal to the dependency-
-    driven run."""
+    captured), also in the XCD-local variant: FP64 true residual and
+    iterations equal to the dependency-driven run."""
     A, b = g.heat_system_3d(64, 1e-3, 1000, 2000)
     S = gpu_system(A)
     l, ut, _ = lpcg.ic0(S)
     its = {}
-    for mode, br in ((0, 0), (3, 1024)):
+    for mode, br, stride in ((0, 0, 1), (3, 1024, 1), (3, 2048, 8)):
         for d in (0, 1):
-            lpcg.set_trsv_cfg(S, d, mode, 0, 1 if mode == 0 else 0, 1, br)
+            lpcg.set_trsv_cfg(S, d, mode, 0, 1 if mode == 0 else 0, stride, br)
         x, res = lpcg.pcg_solve(S, lpcg.PC_LLT, cuda_f64(b), l_val=l, ut_val=ut, tol=1e-6, max_restarts=2,
                                 use_graph=True)
         assert res["status"] == 0 and O.true_relres(A, b, host(x)) <= 1e-6
-        its[mode] = res["iters"]
-    assert abs(its[3] - its[0]) <= 1, its
+        its[(mode, stride)] = res["iters"]
+    assert abs(its[(3, 1)] - its[(0, 1)]) <= 1 and abs(its[(3, 8)] - its[(0, 1)]) <= 1, its
