@@ -346,11 +346,12 @@ struct BlkSlot {
     bool act;
 };
 
+// Record of chunk c for this lane; cc = the chunk's table entry (read one
+// step earlier, so the record read does not wait on it).
 template <int W>
-__device__ __forceinline__ void blk_read(BlkSlot<W> &q, const int *rec, const int2 *ch, int c, int nch) {
+__device__ __forceinline__ void blk_read(BlkSlot<W> &q, const int *rec, int2 cc, int c, int nch) {
     constexpr int RW = 2 * W + 2;
     const int l = lane_id();
-    const int2 cc = ch[min(c, nch - 1)];
     q.act = c < nch && l < cc.y;
     const int p = cc.x + min(l, cc.y - 1);
     const int4 *r4 = reinterpret_cast<const int4 *>(rec + p * RW);
@@ -479,15 +480,17 @@ __device__ double blk_solve(const BlkSched &S, int b, const float *rhs, uint32_t
     constexpr int R = kBlkDist + 2;
     BlkSlot<W> q[R];
 #pragma unroll
-    for (int j = 0; j <= kBlkDist; ++j) blk_read<W>(q[j], rec, ch, j, nch);
+    for (int j = 0; j <= kBlkDist; ++j) blk_read<W>(q[j], rec, ch[min(j, nch - 1)], j, nch);
 #pragma unroll
     for (int j = 0; j < kBlkDist; ++j) blk_issue<W>(q[j], rsh, ybits, rr, r0);
+    int2 ccn = ch[min(kBlkDist + 1, nch - 1)];  // table entry of the next record to read
     double rz = 0.0;
     for (int c = 0; c < nch; c += R) {
 #pragma unroll
         for (int j = 0; j < R; ++j) {
             if (c + j < nch) {
-                blk_read<W>(q[(j + kBlkDist + 1) % R], rec, ch, c + j + kBlkDist + 1, nch);
+                blk_read<W>(q[(j + kBlkDist + 1) % R], rec, ccn, c + j + kBlkDist + 1, nch);
+                ccn = ch[min(c + j + kBlkDist + 2, nch - 1)];
                 blk_issue<W>(q[(j + kBlkDist) % R], rsh, ybits, rr, r0);
                 const float y = blk_process<W>(q[j], ysh, r0, ybits, backoff);
                 if (rr) rz += (double)q[j].rr * (double)y;

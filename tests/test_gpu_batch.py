@@ -85,6 +85,33 @@ def test_batched_pcg_per_system_parity(kind, ordering):
         assert np.linalg.norm(xi - x_ref) <= kap * tol * np.linalg.norm(x_ref)
 
 
+@pytest.mark.parametrize("brows,stride", [(256, 1), (1024, 1), (512, 8)])
+def test_batched_blocked_substitution(brows, stride):
+    """The batched solver with blocked substitutions (blocks may span several
+    systems; dependencies never cross systems): per-system parity with the
+    oracle and iterations within one of the dependency-driven run."""
+    mats = [m for i, m in enumerate(_mats()) if i != 3]  # rows of at most 7 dependencies
+    B, srp = g.block_diag_csr(mats)
+    rng = np.random.default_rng(5)
+    bs = [rng.standard_normal(m.n) for m in mats]
+    S = gpu_system(B, srp)
+    tol = 1e-6
+    _, res0 = _solve(S, "ic0", np.concatenate(bs), tol=tol, max_restarts=2, use_graph=True)
+    for d in (0, 1):
+        lpcg.set_trsv_cfg(S, d, 3, 0, 0, stride, brows)
+    x, res = _solve(S, "ic0", np.concatenate(bs), tol=tol, max_restarts=2, use_graph=True)
+    xh = host(x)
+    for i, (A, b) in enumerate(zip(mats, bs)):
+        xi = xh[srp[i]:srp[i + 1]]
+        it_ref, x_ref = _oracle(A, b, "ic0", 0, tol)
+        print(f"[batch blocked {brows}/{stride}] system {i} n={A.n}: gpu {res[i]['iters']} "
+              f"(dependency driven {res0[i]['iters']}) oracle {it_ref}", flush=True)
+        assert res[i]["status"] == lpcg.OK and O.true_relres(A, b, xi) <= tol
+        assert abs(res[i]["iters"] - res0[i]["iters"]) <= 1
+        assert abs(res[i]["iters"] - it_ref) <= max(2, int(0.1 * it_ref)), (i, res[i]["iters"], it_ref)
+        assert np.linalg.norm(xi - x_ref) <= _kappa(A) * tol * np.linalg.norm(x_ref)
+
+
 def test_batched_zero_rhs_maxit_and_graph_equals_eager():
     mats = _mats()
     B, srp = g.block_diag_csr(mats)
