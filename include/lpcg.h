@@ -216,6 +216,38 @@ typedef struct {
     double us;             /* lpcg_autotune: mean duration of one solve */
 } lpcg_trsv_cfg;
 
+/* Schedule of the blocked substitution (mode 3), computed on the host from
+ * a triangular CSR pattern, exactly as the library builds it for a system:
+ * for inspection and tests.  rowptr/col: HOST, n rows, the pattern of L
+ * (upper = 0: columns ascending, diagonal last, rows solved ascending) or of
+ * U = L^T (upper = 1: diagonal first, rows solved descending).  Rows are cut
+ * into blocks of block_rows consecutive rows in solve order; inside a block
+ * they are ordered by their level over in-block dependencies and cut into
+ * chunks of at most 64 rows of one level.  Call once with the five arrays
+ * NULL to get the sizes, then with caller-owned HOST arrays of
+ *   brow[2 nblocks]      first row, row count of each block
+ *   bch[nblocks + 1]     chunk range of each block
+ *   chunks[2 nchunks]    first record (relative to the block's first row)
+ *                        and row count of each chunk
+ *   rec[n (2 deps + 2)]  per row, at the block's own row positions: deps
+ *                        dependency codes in CSR order (>= 0 row of an
+ *                        earlier block, -1 none, <= -2 in-block row
+ *                        -2 - code relative to the block's first row), the
+ *                        row relative to the block's first row, then deps + 1
+ *                        value words (filled on the device per factor; 0 here)
+ *   vsrc[n (deps + 1)]   position in the CSR value array of each value and,
+ *                        last, of the diagonal (-1: none).
+ * deps is 3 or 7.  Errors: EINVAL (block_rows outside [64, 65536], a row with
+ * more than 7 dependencies, the LDS bound of the device kernel exceeded,
+ * arrays sized for another schedule). */
+typedef struct {
+    int32_t deps, nblocks, nchunks, max_chunks;
+    int32_t *brow, *bch, *chunks, *rec, *vsrc;
+} lpcg_blk_schedule;
+
+int lpcg_blocked_schedule(int32_t n, const int32_t *rowptr, const int32_t *col, int32_t upper,
+                          int32_t block_rows, lpcg_blk_schedule *out);
+
 /* Autotuner: times every candidate configuration of both substitution
  * directions on this system with the given factor (reps timed runs after
  * one warm-up, HIP events on `stream`), keeps the fastest per direction for

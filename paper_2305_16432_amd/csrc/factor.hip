@@ -215,17 +215,17 @@ static int upload(T **dst, const std::vector<T> &h) {
 // for blocks of B rows: per block, the rows ordered by their level inside the
 // block, cut into chunks of at most 64 rows of one level, and one record per
 // row (dependency codes in CSR order, row, and the positions of the values).
-int blk_prepare(lpcg_system *s, int d, int B) {
-    if (s->blk_B[d] == B && s->blk_rec[d]) return LPCG_OK;
-    if (B < 64 || B > (1 << 16)) {
-        set_error("blocked substitution: block size %d outside [64, 65536]", B);
+// Pure host code: rp/ci is the direction's CSR pattern (diagonal stored).
+struct BlkHost {
+    int W = 0, nb = 0, chmax = 0;
+    std::vector<int> brow, bch, ch, rec, vsrc;
+};
+
+static int blk_build(int n, const int *rp, const int *ci, int d, int B, BlkHost &o) {
+    if (n <= 0 || B < 64 || B > (1 << 16)) {
+        set_error("blocked substitution: block size %d outside [64, 65536] (n = %d)", B, n);
         return LPCG_EINVAL;
     }
-    const int n = s->n, nl = s->nnz_l;
-    std::vector<int> rp(n + 1), ci(nl);
-    LPCG_HIP(hipDeviceSynchronize());
-    LPCG_HIP(hipMemcpy(rp.data(), d ? s->urowptr : s->lrowptr, sizeof(int) * (n + 1), hipMemcpyDeviceToHost));
-    LPCG_HIP(hipMemcpy(ci.data(), d ? s->ucol : s->lcol, sizeof(int) * nl, hipMemcpyDeviceToHost));
     int maxdep = 0;
     for (int r = 0; r < n; ++r) maxdep = std::max(maxdep, rp[r + 1] - rp[r] - 1);
     const int W = maxdep <= 3 ? 3 : maxdep <= 7 ? 7 : 0;
@@ -234,14 +234,19 @@ int blk_prepare(lpcg_system *s, int d, int B) {
         return LPCG_EINVAL;
     }
     const int RW = 2 * W + 2, nb = (n + B - 1) / B;
-    std::vector<int> brow(2 * (size_t)nb), bch(1, 0), ch, rec((size_t)n * RW, 0), vsrc((size_t)n * (W + 1), -1);
+    o = BlkHost{};
+    o.W = W;
+    o.nb = nb;
+    o.brow.assign(2 * (size_t)nb, 0);
+    o.bch.assign(1, 0);
+    o.rec.assign((size_t)n * RW, 0);
+    o.vsrc.assign((size_t)n * (W + 1), -1);
     std::vector<int> lev(n, 0), cnt, order;
-    int chmax = 0;
     for (int b = 0; b < nb; ++b) {
         const int r0 = d ? std::max(0, n - (b + 1) * B) : b * B;
         const int r1 = d ? n - b * B : std::min(n, (b + 1) * B);
-        brow[2 * b] = r0;
-        brow[2 * b + 1] = r1 - r0;
+        o.brow[2 * b] = r0;
+        o.brow[2 * b + 1] = r1 - r0;
         int maxl = 0;
         for (int i = 0; i < r1 - r0; ++i) {  // solve order inside the block
             const int r = d ? r1 - 1 - i : r0 + i;
@@ -262,18 +267,18 @@ int blk_prepare(lpcg_system *s, int d, int B) {
             const int r = d ? r1 - 1 - i : r0 + i;
             order[fill[lev[r]]++] = r;
         }
-        const int cbase = (int)ch.size() / 2;
+        const int cbase = (int)o.ch.size() / 2;
         for (int l = 0; l <= maxl; ++l)
             for (int p = cnt[l]; p < cnt[l + 1]; p += kWave) {
-                ch.push_back(p);
-                ch.push_back(std::min(kWave, cnt[l + 1] - p));
+                o.ch.push_back(p);
+                o.ch.push_back(std::min(kWave, cnt[l + 1] - p));
             }
-        bch.push_back((int)ch.size() / 2);
-        chmax = std::max(chmax, (int)ch.size() / 2 - cbase);
+        o.bch.push_back((int)o.ch.size() / 2);
+        o.chmax = std::max(o.chmax, (int)o.ch.size() / 2 - cbase);
         for (int p = 0; p < r1 - r0; ++p) {
             const int r = order[p];
-            int *w = &rec[(size_t)(r0 + p) * RW];
-            int *vs = &vsrc[(size_t)(r0 + p) * (W + 1)];
+            int *w = &o.rec[(size_t)(r0 + p) * RW];
+            int *vs = &o.vsrc[(size_t)(r0 + p) * (W + 1)];
             for (int t = 0; t < W; ++t) w[t] = -1;
             w[W] = r - r0;
             int t = 0;
@@ -289,23 +294,35 @@ int blk_prepare(lpcg_system *s, int d, int B) {
             }
         }
     }
-    const size_t lds = W == 3 ? blk_lds_bytes<3>(B, chmax) : blk_lds_bytes<7>(B, chmax);
+    const size_t lds = W == 3 ? blk_lds_bytes<3>(B, o.chmax) : blk_lds_bytes<7>(B, o.chmax);
     if (lds > kBlkLdsMax) {
         set_error("blocked substitution: %zu bytes of LDS for block size %d (at most %zu)", lds, B, kBlkLdsMax);
         return LPCG_EINVAL;
     }
+    return LPCG_OK;
+}
+
+int blk_prepare(lpcg_system *s, int d, int B) {
+    if (s->blk_B[d] == B && s->blk_rec[d]) return LPCG_OK;
+    const int n = s->n, nl = s->nnz_l;
+    std::vector<int> rp(n + 1), ci(nl);
+    LPCG_HIP(hipDeviceSynchronize());
+    LPCG_HIP(hipMemcpy(rp.data(), d ? s->urowptr : s->lrowptr, sizeof(int) * (n + 1), hipMemcpyDeviceToHost));
+    LPCG_HIP(hipMemcpy(ci.data(), d ? s->ucol : s->lcol, sizeof(int) * nl, hipMemcpyDeviceToHost));
+    BlkHost o;
+    int rc = blk_build(n, rp.data(), ci.data(), d, B, o);
+    if (rc) return rc;
     blk_free(s, d);
-    int rc;
-    if ((rc = upload(&s->blk_brow[d], brow)) || (rc = upload(&s->blk_bch[d], bch)) ||
-        (rc = upload(&s->blk_ch[d], ch)) || (rc = upload(&s->blk_rec[d], rec)) ||
-        (rc = upload(&s->blk_vsrc[d], vsrc))) {
+    if ((rc = upload(&s->blk_brow[d], o.brow)) || (rc = upload(&s->blk_bch[d], o.bch)) ||
+        (rc = upload(&s->blk_ch[d], o.ch)) || (rc = upload(&s->blk_rec[d], o.rec)) ||
+        (rc = upload(&s->blk_vsrc[d], o.vsrc))) {
         blk_free(s, d);
         return rc;
     }
     s->blk_B[d] = B;
-    s->blk_W[d] = W;
-    s->blk_nb[d] = nb;
-    s->blk_chmax[d] = chmax;
+    s->blk_W[d] = o.W;
+    s->blk_nb[d] = o.nb;
+    s->blk_chmax[d] = o.chmax;
     // allow the blocked kernels' dynamic LDS (set here, before any launch or
     // graph capture that uses the schedule)
     LPCG_HIP(hipFuncSetAttribute((const void *)k_sptrsv_blk<3>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -605,6 +622,35 @@ extern "C" int lpcg_time_spmv(const lpcg_system *s, const float *x, float *y, in
     float ms = 0;
     LPCG_HIP(hipEventElapsedTime(&ms, ev.a, ev.b));
     *ms_out = (double)ms / reps;
+    return LPCG_OK;
+}
+
+extern "C" int lpcg_blocked_schedule(int32_t n, const int32_t *rowptr, const int32_t *col, int32_t upper,
+                                     int32_t block_rows, lpcg_blk_schedule *out) {
+    if (!out || !rowptr || !col || (upper != 0 && upper != 1)) {
+        set_error("lpcg_blocked_schedule: invalid arguments");
+        return LPCG_EINVAL;
+    }
+    BlkHost o;
+    const int rc = blk_build(n, rowptr, col, upper, block_rows, o);
+    if (rc) return rc;
+    const int nch = (int)o.ch.size() / 2;
+    const bool fill = out->brow && out->bch && out->chunks && out->rec && out->vsrc;
+    if (fill && (out->nblocks != o.nb || out->nchunks != nch || out->deps != o.W)) {
+        set_error("lpcg_blocked_schedule: output sized for another schedule");
+        return LPCG_EINVAL;
+    }
+    out->deps = o.W;
+    out->nblocks = o.nb;
+    out->nchunks = nch;
+    out->max_chunks = o.chmax;
+    if (fill) {
+        std::copy(o.brow.begin(), o.brow.end(), out->brow);
+        std::copy(o.bch.begin(), o.bch.end(), out->bch);
+        std::copy(o.ch.begin(), o.ch.end(), out->chunks);
+        std::copy(o.rec.begin(), o.rec.end(), out->rec);
+        std::copy(o.vsrc.begin(), o.vsrc.end(), out->vsrc);
+    }
     return LPCG_OK;
 }
 

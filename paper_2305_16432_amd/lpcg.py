@@ -61,6 +61,12 @@ class _TrsvCfg(C.Structure):
                 ("us", C.c_double)]
 
 
+class _BlkSchedule(C.Structure):
+    _fields_ = [("deps", C.c_int32), ("nblocks", C.c_int32), ("nchunks", C.c_int32), ("max_chunks", C.c_int32),
+                ("brow", C.c_void_p), ("bch", C.c_void_p), ("chunks", C.c_void_p), ("rec", C.c_void_p),
+                ("vsrc", C.c_void_p)]
+
+
 class _Gnn(C.Structure):
     _fields_ = [("h", C.c_int32), ("n_mp", C.c_int32), ("params", C.c_void_p), ("diag_mode", C.c_int32),
                 ("x_head", C.c_int32)]
@@ -221,6 +227,34 @@ def set_trsv_cfg(sys: System, direction: int, mode: int, waves: int = 0, backoff
                  block_stride: int = 1, block_rows: int = 0):
     c = _TrsvCfg(direction, mode, waves, backoff, block_stride, block_rows, 0.0)
     _check(lib().lpcg_set_trsv_cfg(sys.handle, C.byref(c)), "lpcg_set_trsv_cfg")
+
+
+def blocked_schedule(rowptr, col, upper: bool, block_rows: int) -> dict:
+    """Host schedule of the blocked substitution for a triangular CSR pattern
+    (lower: diagonal last; upper: diagonal first), as NumPy arrays."""
+    import numpy as np
+    rp = np.ascontiguousarray(rowptr, dtype=np.int32)
+    ci = np.ascontiguousarray(col, dtype=np.int32)
+    n = rp.shape[0] - 1
+    L = lib()
+    out = _BlkSchedule()
+    f = L.lpcg_blocked_schedule
+    args = (C.c_int32(n), rp.ctypes.data_as(C.c_void_p), ci.ctypes.data_as(C.c_void_p), C.c_int32(int(upper)),
+            C.c_int32(block_rows))
+    _check(f(*args, C.byref(out)), "lpcg_blocked_schedule")
+    w = out.deps
+    arrs = dict(brow=np.zeros(2 * out.nblocks, np.int32), bch=np.zeros(out.nblocks + 1, np.int32),
+                chunks=np.zeros(2 * out.nchunks, np.int32), rec=np.zeros(n * (2 * w + 2), np.int32),
+                vsrc=np.zeros(n * (w + 1), np.int32))
+    for k, a in arrs.items():
+        setattr(out, k, a.ctypes.data_as(C.c_void_p))
+    _check(f(*args, C.byref(out)), "lpcg_blocked_schedule")
+    arrs.update(deps=w, nblocks=out.nblocks, nchunks=out.nchunks, max_chunks=out.max_chunks)
+    arrs["brow"] = arrs["brow"].reshape(-1, 2)
+    arrs["chunks"] = arrs["chunks"].reshape(-1, 2)
+    arrs["rec"] = arrs["rec"].reshape(n, 2 * w + 2)
+    arrs["vsrc"] = arrs["vsrc"].reshape(n, w + 1)
+    return arrs
 
 
 # ---------------------------------------------------------- building blocks

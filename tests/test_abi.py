@@ -45,7 +45,7 @@ def test_binding_struct_layout_matches_header():
     from paper_2305_16432_amd import lpcg
     structs = {"lpcg_csr": lpcg._CSR, "lpcg_info": lpcg._Info, "lpcg_precond": lpcg._Precond,
                "lpcg_solve_opts": lpcg._Opts, "lpcg_result": lpcg._Result, "lpcg_gnn": lpcg._Gnn,
-               "lpcg_trsv_cfg": lpcg._TrsvCfg}
+               "lpcg_trsv_cfg": lpcg._TrsvCfg, "lpcg_blk_schedule": lpcg._BlkSchedule}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "lpcg.h"', "int main(void) {"]
     for cname, cls in structs.items():
         lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')

@@ -1,0 +1,95 @@
+"""The blocked substitution's schedule (host logic of the library, no GPU).
+
+A solve emulated in FP64 from the schedule alone -- blocks in order, chunks in
+order, each row from its record (dependency codes, the factor's values
+through vsrc, the diagonal) -- must reproduce the oracle's substitution bit
+for bit: both accumulate a row's entries in CSR order.  Structural checks:
+every row appears exactly once, chunks hold at most 64 rows of one block,
+an in-block dependency is produced in an earlier chunk of the same block, a
+global one in an earlier block."""
+import numpy as np
+import pytest
+
+import oracle as O
+import pdegen as g
+from paper_2305_16432_amd import lpcg
+from tests.gpu_util import matrices_small
+
+
+def _emulate(S, n, vals, rhs):
+    w = S["deps"]
+    y = np.full(n, np.nan)
+    block_of = np.full(n, -1)
+    chunk_of = np.full(n, -1)
+    seen = np.zeros(n, np.int64)
+    for b in range(S["nblocks"]):
+        r0, nr = S["brow"][b]
+        block_of[r0:r0 + nr] = b
+        for c in range(S["bch"][b], S["bch"][b + 1]):
+            p0, cnt = S["chunks"][c]
+            assert 1 <= cnt <= 64 and 0 <= p0 and p0 + cnt <= nr
+            for p in range(p0, p0 + cnt):
+                rec = S["rec"][r0 + p]
+                row = r0 + rec[w]
+                assert r0 <= row < r0 + nr
+                seen[row] += 1
+                acc = rhs[row]
+                for t in range(w):
+                    code = rec[t]
+                    if code == -1:
+                        assert S["vsrc"][r0 + p][t] == -1
+                        continue
+                    dep = code if code >= 0 else r0 + (-2 - code)
+                    if code >= 0:
+                        assert block_of[dep] != -1 and block_of[dep] < b, "global dependency not in an earlier block"
+                    else:
+                        assert chunk_of[dep] != -1 and chunk_of[dep] < c, "in-block dependency not in an earlier chunk"
+                    acc -= vals[S["vsrc"][r0 + p][t]] * y[dep]
+                y[row] = acc / vals[S["vsrc"][r0 + p][w]]
+                chunk_of[row] = c
+    assert np.all(seen == 1)
+    return y
+
+
+@pytest.mark.parametrize("brows", [64, 256, 1024])
+@pytest.mark.parametrize("name", ["one", "tridiag_1000", "poisson2d_32", "poisson3d_9", "heat3d_13", "fem_40"])
+def test_schedule_reproduces_substitution(name, brows):
+    A = matrices_small()[name]
+    pat = O.Pattern(A)
+    rng = np.random.default_rng(7)
+    lval = rng.uniform(-0.3, 0.3, pat.nnz_l)
+    row = np.repeat(np.arange(A.n), np.diff(pat.lrowptr))
+    lval[pat.lcol == row] = rng.uniform(1.0, 2.0, (pat.lcol == row).sum())
+    rhs = rng.standard_normal(A.n)
+    for upper in (False, True):
+        rp, ci = (pat.urowptr, pat.ucol) if upper else (pat.lrowptr, pat.lcol)
+        vals = pat.upper_values(lval) if upper else lval
+        S = lpcg.blocked_schedule(rp, ci, upper, brows)
+        assert S["deps"] == (3 if np.diff(rp).max() - 1 <= 3 else 7)
+        assert S["nblocks"] == -(-A.n // brows)
+        y = _emulate(S, A.n, vals, rhs)
+        ref = O.trsv_upper(pat, lval, rhs) if upper else O.trsv_lower(pat, lval, rhs)
+        np.testing.assert_array_equal(y, ref)
+
+
+def test_schedule_levels_of_a_plane_block():
+    """64^3-like structure at 16^3: a block of one plane (256 rows) has
+    16 + 16 - 1 in-block levels, one chunk each (at most 16 rows per level)."""
+    A = g.poisson_grid(16, 3)
+    pat = O.Pattern(A)
+    S = lpcg.blocked_schedule(pat.lrowptr, pat.lcol, False, 256)
+    assert S["nblocks"] == 16
+    assert all(S["bch"][b + 1] - S["bch"][b] == 31 for b in range(16))
+
+
+def test_schedule_rejects():
+    A = matrices_small()["random_777"]  # rows with more than 7 dependencies
+    pat = O.Pattern(A)
+    with pytest.raises(lpcg.LpcgError) as e:
+        lpcg.blocked_schedule(pat.lrowptr, pat.lcol, False, 256)
+    assert e.value.code == lpcg.EINVAL
+    B = matrices_small()["heat3d_13"]
+    pb = O.Pattern(B)
+    for bad in (32, 1 << 17):
+        with pytest.raises(lpcg.LpcgError):
+            lpcg.blocked_schedule(pb.lrowptr, pb.lcol, False, bad)
