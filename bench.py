@@ -95,6 +95,63 @@ def cpu_baseline(A, b, tol, budget_s=20.0):
                       f"(serial C FP64, {len(times)} run(s), {iters} iterations)"}
 
 
+def methods_learned(ordering, code, S):
+    """(params, h, n_mp, diag_mode, workspace) of the shipped network for an
+    ordering, or None."""
+    import torch
+    from paper_2305_16432_amd import lpcg
+    if not os.path.exists(WEIGHTS[ordering]):
+        return None
+    W = np.load(WEIGHTS[ordering])
+    if int(W["ordering"]) != code:
+        return None
+    h, n_mp, dmode = int(W["h"]), int(W["n_mp"]), int(W["diag_mode"])
+    params = torch.as_tensor(W["params"].astype(np.float32)).cuda()
+    return params, h, n_mp, dmode, lpcg.gnn_workspace(S, h, n_mp, train=False)
+
+
+def run_seeds(args, S, lval, utval, x, coef, solve_kw, net):
+    """Every test seed once (same pattern, new values): precompute + PCG time
+    and iterations of learned L, IC(0) and symmetric Gauss-Seidel, with their
+    means (outside the timed steps)."""
+    import torch
+    import pdegen as g
+    from paper_2305_16432_amd import lpcg
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    rows = []
+    for i in range(args.seeds):
+        ks, us = args.k_seed + i, args.u_seed + i
+        Ai, bi = g.heat_system_3d(args.m, 1e-3, ks, us)
+        lpcg.update_values(S, torch.as_tensor(Ai.val).cuda())
+        bdi = torch.as_tensor(bi).cuda()
+        row = {"k_seed": ks, "u0_seed": us}
+        pres = {"ic0": lambda: lpcg.ic0(S, 0.0, 8, lval, utval), "sgs": lambda: lpcg.sgs(S, lval, utval)}
+        if net is not None:
+            params, h, n_mp, dmode, ws = net
+            pres["learned"] = lambda: lpcg.gnn_predict_L(S, params, h, n_mp, bdi, ws, lval, utval, diag_mode=dmode)
+        for name, pre in pres.items():
+            e0.record()
+            pre()
+            e1.record()
+            x.zero_()
+            _, res = lpcg.pcg_solve(S, lpcg.PC_LLT, bdi, x=x, l_val=lval, ut_val=utval, coef=coef, **solve_kw)
+            e2.record()
+            torch.cuda.synchronize()
+            row[name] = dict(ms=e0.elapsed_time(e2), precompute_ms=e0.elapsed_time(e1), iters=res["iters"],
+                             relres_true=res["relres_true"], status=res["status"])
+        rows.append(row)
+        _log(f"seed {ks}/{us}: " + ", ".join(f"{k} {v['iters']} it {v['ms']:.2f} ms" for k, v in row.items()
+                                               if isinstance(v, dict)))
+    summary = {"per_seed": rows}
+    for name in ("learned", "ic0", "sgs"):
+        if all(name in r for r in rows):
+            summary[name] = dict(ms_mean=float(np.mean([r[name]["ms"] for r in rows])),
+                                 iters_mean=float(np.mean([r[name]["iters"] for r in rows])),
+                                 iters_max=int(np.max([r[name]["iters"] for r in rows])),
+                                 all_converged=all(r[name]["status"] == 0 for r in rows))
+    return summary
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -107,6 +164,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--orderings", default="natural,color")
     ap.add_argument("--methods", default="learned,ic0,sgs,jacobi")
+    ap.add_argument("--seeds", type=int, default=10,
+                    help="test seeds (k seed, u0 seed) + 0..seeds-1 run once per method after the timed steps")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="MiB of a plain device copy to run first (counter calibration under rocprofv3 --pmc)")
     args = ap.parse_args()
@@ -236,6 +295,8 @@ def main():
             sptrsv_bwd=dict(us=ms_b * 1e3, bytes=bt, gbs=bt / (ms_b * 1e-3) / 1e9),
             spmv=dict(us=ms_spmv * 1e3, bytes=bs, gbs=bs / (ms_spmv * 1e-3) / 1e9))
         _log(f"{ordering} kernels: {kernels[ordering]}")
+        if ordering == "natural" and args.seeds > 0:
+            per_seed = run_seeds(args, S, lval, utval, x, coef, solve_kw, methods_learned(ordering, code, S))
         del S
 
     cpu = None
@@ -277,6 +338,7 @@ def main():
                      "traffic": measured_traffic(f"sptrsv_forward ({head_order} order)"), "bytes_per_launch": kf["bytes"], "us_per_launch": kf["us"],
                      "levels": kernels[head_order]["levels"], "kernels": kernels},
         "cpu_baseline": cpu,
+        "seeds": per_seed if args.seeds > 0 and "natural" in args.orderings.split(",") else None,
     }
     print(json.dumps(out), flush=True)
 
