@@ -152,6 +152,16 @@ int lpcg_sptrsv(const lpcg_system *sys, int32_t transpose, const float *l_val,
 int lpcg_l_to_ut(const lpcg_system *sys, const float *l_val, float *ut_val,
                  hipStream_t stream);
 
+/* Validation of a factor before it is used as a preconditioner (the host
+ * policy around a learned factor: fall back to IC(0) or Jacobi when it
+ * fails): every diagonal entry of L must be a positive finite number and
+ * every other entry finite.  l_val: device FP32 [nnz_l], L order.  *bad_row
+ * (HOST, may be NULL): the first offending row in the internal numbering, or
+ * -1.  Synchronous.  Errors: ENONFINITE (a row fails), EINVAL.
+ * lpcg_gnn_predict_L itself is asynchronous and does not check. */
+int lpcg_check_factor(const lpcg_system *sys, const float *l_val, int32_t *bad_row,
+                      hipStream_t stream);
+
 /* Symmetric Gauss-Seidel (Experiments, baseline methods; the triangles
  * come from A itself, taken in the symmetric form CG needs):
  * P = (D + A_<) D^-1 (D + A_<)^T = L L^T with L_ij = A_ij / sqrt(A_jj) on

@@ -553,6 +553,39 @@ extern "C" int lpcg_ic0(const lpcg_system *s, double shift0, int32_t max_retries
     return rc;
 }
 
+// Factor validation: the first row whose diagonal is not a positive finite
+// number or that holds a non-finite entry (L rows store the diagonal last).
+__global__ void k_check_factor(int n, const int *__restrict__ lrowptr, const float *__restrict__ lval,
+                               int *__restrict__ bad) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int a = lrowptr[i], b = lrowptr[i + 1];
+    bool ok = lval[b - 1] > 0.f && isfinite(lval[b - 1]);
+    for (int k = a; k < b - 1; ++k) ok = ok && isfinite(lval[k]);
+    if (!ok) atomicMin(bad, i);
+}
+
+extern "C" int lpcg_check_factor(const lpcg_system *s, const float *l_val, int32_t *bad_row, hipStream_t st) {
+    if (!s || !l_val) {
+        set_error("lpcg_check_factor: invalid arguments");
+        return LPCG_EINVAL;
+    }
+    int *bad = s->ctrl + C_STATUS;  // scratch word (the solvers set it afresh)
+    k_set_i32<<<1, 1, 0, st>>>(bad, 0x7fffffff);
+    k_check_factor<<<nblk(s->n, 256), 256, 0, st>>>(s->n, s->lrowptr, l_val, bad);
+    LPCG_LAUNCH_CHECK();
+    int h = 0;
+    LPCG_HIP(hipMemcpyAsync(&h, bad, sizeof(int), hipMemcpyDeviceToHost, st));
+    LPCG_HIP(hipStreamSynchronize(st));
+    if (bad_row) *bad_row = h == 0x7fffffff ? -1 : h;
+    if (h != 0x7fffffff) {
+        set_error("lpcg_check_factor: row %d (internal numbering) has a non-positive or non-finite diagonal or a "
+                  "non-finite entry", h);
+        return LPCG_ENONFINITE;
+    }
+    return LPCG_OK;
+}
+
 extern "C" int lpcg_sgs(const lpcg_system *s, float *l_val, float *ut_val, hipStream_t st) {
     if (!s || (!l_val && !ut_val)) {
         set_error("lpcg_sgs: invalid arguments");

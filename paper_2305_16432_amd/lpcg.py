@@ -284,6 +284,15 @@ def l_to_ut(sys: System, l_val, out=None):
     return out
 
 
+def check_factor(sys: System, l_val):
+    """(ok, first bad row in the internal numbering or -1)."""
+    bad = C.c_int32(0)
+    rc = lib().lpcg_check_factor(sys.handle, _ptr(l_val), C.byref(bad), _stream())
+    if rc not in (OK, ENONFINITE):
+        _check(rc, "lpcg_check_factor")
+    return rc == OK, bad.value
+
+
 def sgs(sys: System, l_val=None, ut_val=None):
     """Symmetric Gauss-Seidel factor L = (D + A_<) D^-1/2 (and U = L^T)."""
     nl = sys.info["nnz_l"]
