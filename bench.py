@@ -95,6 +95,26 @@ def cpu_baseline(A, b, tol, budget_s=20.0):
                       f"(serial C FP64, {len(times)} run(s), {iters} iterations)"}
 
 
+PEAK_BF16_TFLOPS = 2500.0  # MI355X dense BF16 MFMA
+
+
+def gnn_model(n, nnz, nnz_l, h, n_mp):
+    """Algorithmic flops and HBM bytes of one network forward (factored first
+    edge layer; BF16 latents, FP32 decoder output and factor; weights and
+    index reads of the CSR row pointers neglected)."""
+    hh = 2 * h * h
+    flops = n * (2 * h + hh) + nnz * (2 * h + hh)                       # encoders
+    flops += n_mp * (nnz * 2 * h + n * (2 * hh + hh) + n * 2 * hh + nnz * 2 * hh)  # aggregation, node MLP,
+    flops += nnz * (hh + 2 * h)                                           # projections, edge MLP; decoder
+    lat = 2 * h                                                           # bytes per BF16 latent row
+    byts = n * (8 + lat) + nnz * (8 + 4 + lat)                            # encoders: b, A values, rows
+    for t in range(n_mp):
+        byts += n * lat + nnz * (lat + 4) + 3 * n * lat                   # node kernel: V, E, col; V', Pa, Pb
+        byts += nnz * (lat + 8) + 2 * n * lat + (4 * nnz if t == n_mp - 1 else nnz * lat)  # edge kernel
+    byts += nnz * 4 + nnz_l * 8                                           # assembly: d, L and U values
+    return float(flops), float(byts)
+
+
 def methods_learned(ordering, code, S):
     """(params, h, n_mp, diag_mode, workspace) of the shipped network for an
     ordering, or None."""
@@ -193,6 +213,7 @@ def main():
     x = torch.zeros_like(bd)
     solve_kw = dict(tol=args.tol, check_every=8, max_restarts=2, use_graph=True)
     results, kernels = {}, {}
+    gnn_dims = None
     for ordering in args.orderings.split(","):
         code = lpcg.ORDER_COLOR if ordering == "color" else lpcg.ORDER_NATURAL
         S = lpcg.analyze(torch.as_tensor(A.rowptr).cuda(), torch.as_tensor(A.colind).cuda(),
@@ -241,6 +262,9 @@ def main():
             h, n_mp, dmode = int(W["h"]), int(W["n_mp"]), int(W["diag_mode"])
             params = torch.as_tensor(W["params"].astype(np.float32)).cuda()
             ws = lpcg.gnn_workspace(S, h, n_mp, train=False)
+
+            if ordering == "natural":
+                gnn_dims = (A.n, A.nnz, info["nnz_l"], h, n_mp)
 
             def run_learned(params=params, h=h, n_mp=n_mp, dmode=dmode, ws=ws):
                 lpcg.gnn_predict_L(S, params, h, n_mp, bd, ws, lval, utval, diag_mode=dmode)
@@ -299,6 +323,15 @@ def main():
             per_seed = run_seeds(args, S, lval, utval, x, coef, solve_kw, methods_learned(ordering, code, S))
         del S
 
+    # the network forward (the learned method's precompute) against the
+    # BF16 MFMA and HBM peaks, from the flop and byte model above
+    gnn_info = None
+    if "learned" in results and gnn_dims is not None:
+        gf, gb = gnn_model(*gnn_dims)
+        t = results["learned"]["precompute_ms"] * 1e-3
+        gnn_info = dict(ms=t * 1e3, gflop=gf / 1e9, tflops=gf / t / 1e12, mfma_frac=gf / t / 1e12 / PEAK_BF16_TFLOPS,
+                        hbm_mb=gb / 1e6, gbs=gb / t / 1e9, hbm_frac=gb / t / 1e9 / PEAK_HBM,
+                        h=gnn_dims[3], n_mp=gnn_dims[4])
     cpu = None
     if not args.no_cpu:
         os.environ.setdefault("OMP_NUM_THREADS", "1")
@@ -339,6 +372,7 @@ def main():
                      "levels": kernels[head_order]["levels"], "kernels": kernels},
         "cpu_baseline": cpu,
         "seeds": per_seed if args.seeds > 0 and "natural" in args.orderings.split(",") else None,
+        "gnn": gnn_info,
     }
     print(json.dumps(out), flush=True)
 
