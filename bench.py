@@ -31,7 +31,8 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-WEIGHTS = {"natural": os.path.join(ROOT, "paper_2305_16432_amd", "weights", "heat3d_h32_mp3.npz"),
+# natural order: the network trained on 32^3 heat steps and fine-tuned on 64^3 ones
+WEIGHTS = {"natural": os.path.join(ROOT, "paper_2305_16432_amd", "weights", "heat3d_h32_mp3_ft64.npz"),
            "color": os.path.join(ROOT, "paper_2305_16432_amd", "weights", "heat3d_h32_mp3_color.npz")}
 PEAK_HBM = 8000.0  # GB/s, MI355X HBM3E
 # HBM bytes of the roofline kernel measured with rocprofv3 --pmc FETCH_SIZE /

@@ -22,6 +22,13 @@ alone with --head-only, which updates only the head so L stays that of the
 --init network); the held-out PCG then starts from the predicted x0.
 
     python -m paper_2305_16432_amd.train --out paper_2305_16432_amd/weights/heat3d_h32_mp3.npz
+
+Fine-tuning on the 64^3 size the network is evaluated at (400 systems, k
+seeds 0..399; held-out selection as above) gives the benchmark's network:
+
+    python -m paper_2305_16432_amd.train --m 64 --nsys 400 --batch 4 --lr 1e-4 --steps 3000 \
+        --init paper_2305_16432_amd/weights/heat3d_h32_mp3.npz \
+        --out paper_2305_16432_amd/weights/heat3d_h32_mp3_ft64.npz
 """
 from __future__ import annotations
 

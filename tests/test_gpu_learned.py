@@ -105,3 +105,24 @@ def test_data_loss_beats_frobenius_loss(k_seed, u_seed):
     it_frob = _iters_learned(S, pf, h, n_mp, dm, bd)
     print(f"[loss ablation] seeds ({k_seed},{u_seed}): data loss {it_data}, Frobenius loss {it_frob}", flush=True)
     assert it_data < 0.8 * it_frob
+
+
+@pytest.mark.parametrize("k_seed,u_seed", [(7001, 8001), (7002, 8002), (7004, 8004)])
+def test_fine_tuned_network_64(k_seed, u_seed):
+    """The network fine-tuned on 64^3 heat steps (the benchmark's): on held-out
+    64^3 systems it beats IC(0) and is no worse than the 32^3-trained one it
+    started from, give or take one iteration."""
+    W = np.load(os.path.join(WDIR, "heat3d_h32_mp3_ft64.npz"))
+    h, n_mp, dm = int(W["h"]), int(W["n_mp"]), int(W["diag_mode"])
+    pf = torch.as_tensor(W["params"].astype(np.float32)).cuda()
+    p0, h0, n0, d0 = _load(0)
+    A, b = g.heat_system_3d(64, 1e-3, k_seed, u_seed)
+    S = gpu_system(A)
+    bd = cuda_f64(b)
+    it_ft = _iters_learned(S, pf, h, n_mp, dm, bd)
+    it_32 = _iters_learned(S, p0, h0, n0, d0, bd)
+    l, ut, _ = lpcg.ic0(S)
+    _, ric = lpcg.pcg_solve(S, lpcg.PC_LLT, bd, l_val=l, ut_val=ut, tol=1e-6, max_restarts=2)
+    print(f"[fine-tuned] seeds ({k_seed},{u_seed}): fine-tuned {it_ft}, 32^3-trained {it_32}, IC(0) {ric['iters']}",
+          flush=True)
+    assert it_ft < ric["iters"] and it_ft <= it_32 + 1

@@ -13,7 +13,7 @@ WDIR = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
 
 
 @pytest.mark.parametrize("fname,ordering", [("heat3d_h32_mp3.npz", 0), ("heat3d_h32_mp3_color.npz", 1),
-                                            ("heat3d_h32_mp3_frobenius.npz", 0)])
+                                            ("heat3d_h32_mp3_frobenius.npz", 0), ("heat3d_h32_mp3_ft64.npz", 0)])
 def test_weights_file_layout(fname, ordering):
     W = np.load(os.path.join(WDIR, fname))  # allow_pickle stays False
     h, n_mp, dm = int(W["h"]), int(W["n_mp"]), int(W["diag_mode"])
@@ -22,3 +22,10 @@ def test_weights_file_layout(fname, ordering):
     assert W["params"].shape == (n,) and np.all(np.isfinite(W["params"]))
     log = json.loads(str(W["log"]))
     assert int(W["best_iters"]) < log["jacobi_iters"]
+
+
+def test_fine_tuned_network_provenance():
+    """The 64^3 fine-tuning started from the shipped 32^3 network."""
+    W = np.load(os.path.join(WDIR, "heat3d_h32_mp3_ft64.npz"))
+    cfg = json.loads(str(W["config"]))
+    assert cfg["m"] == 64 and cfg["init"].endswith("heat3d_h32_mp3.npz") and cfg["loss"] == "data"
