@@ -92,9 +92,14 @@ typedef struct {
  * inside the library; preconditioner data (l_val, ut_val, dinv, every array
  * of lpcg_export_pattern) is in the INTERNAL numbering; lpcg_export_perm
  * gives perm[internal row] = original row.  The timing aids work in the
- * internal numbering. */
+ * internal numbering.
+ *
+ * COLOR takes at most LPCG_COLOR_MAX_ROWS rows (all systems of a batch
+ * together): the largest colour analysis that has been run and verified.  A
+ * larger one is refused with EINVAL until it has been. */
 #define LPCG_ORDER_NATURAL 0
 #define LPCG_ORDER_COLOR   1
+#define LPCG_COLOR_MAX_ROWS 262144
 
 /* Pattern analysis (graph/matrix duality of the Method section; levels of
  * the substitution DAG): copies A, builds tril(A) (lrowptr/lcol), U = L^T
@@ -107,7 +112,8 @@ typedef struct {
  * of one system stay inside that system's row range).  Synchronous.  *out is
  * owned by the caller until lpcg_destroy.  Errors: EINVAL (n <= 0,
  * unsorted/duplicate columns, missing diagonal, unsymmetric pattern, a row
- * crossing a system boundary, unknown ordering), ENOMEM, EHIP. */
+ * crossing a system boundary, unknown ordering, COLOR with more than
+ * LPCG_COLOR_MAX_ROWS rows), ENOMEM, EHIP. */
 int lpcg_analyze(const lpcg_csr *A, const int32_t *sys_rowptr, int32_t nsys,
                  int32_t ordering, lpcg_system **out, hipStream_t stream);
 

@@ -748,6 +748,10 @@ extern "C" int lpcg_analyze(const lpcg_csr *A, const int32_t *sys_rowptr, int32_
         set_error("lpcg_analyze: unknown ordering %d", ordering);
         return LPCG_EINVAL;
     }
+    if (ordering == LPCG_ORDER_COLOR && A->n > LPCG_COLOR_MAX_ROWS) {
+        set_error("lpcg_analyze: the colour ordering takes at most %d rows (got %d)", LPCG_COLOR_MAX_ROWS, A->n);
+        return LPCG_EINVAL;
+    }
     lpcg_system *s = new (std::nothrow) lpcg_system();
     if (!s) return LPCG_ENOMEM;
     int rc = ordering == LPCG_ORDER_COLOR ? analyze_color(A, h_sys, nsys, s, stream)

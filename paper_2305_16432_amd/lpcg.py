@@ -149,6 +149,7 @@ class System:
 
 # ------------------------------------------------------------------ analysis
 ORDER_NATURAL, ORDER_COLOR = 0, 1
+COLOR_MAX_ROWS = 262144  # rows (whole batch) the colour ordering accepts
 
 
 def analyze(rowptr, colind, val, sys_rowptr=None, ordering: int = ORDER_NATURAL) -> System:

@@ -66,3 +66,24 @@ def test_binding_struct_layout_matches_header():
         assert int(got[cname]) == ctypes.sizeof(cls), cname
         for f, _ in cls._fields_:
             assert int(got[f"{cname}.{f}"]) == getattr(cls, f).offset, (cname, f)
+
+
+def test_colour_ordering_row_limit():
+    """The colour ordering's row limit: the binding's constant is the header's,
+    and a larger analysis is refused (EINVAL) on the host, before any device
+    work, so this runs without a GPU (the array pointers are never read)."""
+    from paper_2305_16432_amd import lpcg
+    m = re.search(r"#define\s+LPCG_COLOR_MAX_ROWS\s+(\d+)", open(HEADER).read())
+    assert m and int(m.group(1)) == lpcg.COLOR_MAX_ROWS
+    L = lpcg.lib()
+    dummy = (ctypes.c_int32 * 4)()
+    dval = (ctypes.c_double * 4)()
+    for n, ordering in ((lpcg.COLOR_MAX_ROWS + 1, lpcg.ORDER_COLOR), (1 << 22, lpcg.ORDER_COLOR)):
+        A = lpcg._CSR(n, 7 * n, ctypes.cast(dummy, ctypes.c_void_p), ctypes.cast(dummy, ctypes.c_void_p),
+                      ctypes.cast(dval, ctypes.c_void_p))
+        out = ctypes.c_void_p()
+        rc = L.lpcg_analyze(ctypes.byref(A), None, ctypes.c_int32(1), ctypes.c_int32(ordering),
+                            ctypes.byref(out), None)
+        assert rc == lpcg.EINVAL and not out.value
+        L.lpcg_last_error.restype = ctypes.c_char_p
+        assert b"colour ordering" in L.lpcg_last_error()
