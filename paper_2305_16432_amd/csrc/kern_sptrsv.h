@@ -373,32 +373,68 @@ __device__ __forceinline__ void blk_read(BlkSlot<W> &q, const int *rec, int2 cc,
     q.dg = __int_as_float(w[2 * W + 1]);
 }
 
-template <int W>
+template <int W, bool RZ>
 __device__ __forceinline__ void blk_issue(BlkSlot<W> &q, const float *rsh, const uint32_t *ybits,
-                                          const float *rr, int r0) {
+                                          const float *rrsh) {
     q.rhs = rsh[q.row];
-    q.rr = rr ? rr[r0 + q.row] : 0.f;
+    if constexpr (RZ) q.rr = rrsh[q.row];
 #pragma unroll
     for (int t = 0; t < W; ++t) q.gv[t] = ld_agent(&ybits[max(q.code[t], 0)]);
 }
 
 // Solve one chunk; returns the lane's solution value (0 for idle lanes).
-template <int W>
+// Values the prefetch found unset are polled again until published:
+// ROUND = false re-reads each missing value on its own (a load and its wait
+// per value); ROUND = true re-reads all of a lane's missing values in one
+// round of unconditional loads (entry 0 where nothing is missing) and waits
+// once per round, keeping the polled values apart from the ring slot.  Which
+// is faster depends on the direction (timed on the 64^3 grid: the round form
+// for the backward solve, the single form for the forward one).
+template <int W, bool ROUND>
 __device__ __forceinline__ float blk_process(BlkSlot<W> &q, float *ysh, int r0, uint32_t *ybits, int backoff) {
-    bool ready = true;
+    uint32_t gv[W];
+    if constexpr (ROUND) {
+        bool need[W];
+        bool any = false;
 #pragma unroll
-    for (int t = 0; t < W; ++t) ready = ready && (!q.act || q.code[t] < 0 || q.gv[t] != kUnset);
-    while (__ballot(!ready) != 0) {
-        for (int s = 0; s < backoff; ++s) __builtin_amdgcn_s_sleep(1);
-        if (!ready) {
-            ready = true;
-#pragma unroll
-            for (int t = 0; t < W; ++t)
-                if (q.code[t] >= 0 && q.gv[t] == kUnset) {
-                    q.gv[t] = ld_agent(&ybits[q.code[t]]);
-                    ready = ready && q.gv[t] != kUnset;
-                }
+        for (int t = 0; t < W; ++t) {
+            gv[t] = q.gv[t];
+            need[t] = q.act && q.code[t] >= 0 && gv[t] == kUnset;
+            any = any || need[t];
         }
+        while (__ballot(any) != 0) {
+            for (int s = 0; s < backoff; ++s) __builtin_amdgcn_s_sleep(1);
+            uint32_t rd[W];
+#pragma unroll
+            for (int t = 0; t < W; ++t) rd[t] = ld_agent(&ybits[need[t] ? q.code[t] : 0]);
+            any = false;
+#pragma unroll
+            for (int t = 0; t < W; ++t) {
+                if (need[t] && rd[t] != kUnset) {
+                    gv[t] = rd[t];
+                    need[t] = false;
+                }
+                any = any || need[t];
+            }
+        }
+    } else {
+        bool ready = true;
+#pragma unroll
+        for (int t = 0; t < W; ++t) ready = ready && (!q.act || q.code[t] < 0 || q.gv[t] != kUnset);
+        while (__ballot(!ready) != 0) {
+            for (int s = 0; s < backoff; ++s) __builtin_amdgcn_s_sleep(1);
+            if (!ready) {
+                ready = true;
+#pragma unroll
+                for (int t = 0; t < W; ++t)
+                    if (q.code[t] >= 0 && q.gv[t] == kUnset) {
+                        q.gv[t] = ld_agent(&ybits[q.code[t]]);
+                        ready = ready && q.gv[t] != kUnset;
+                    }
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < W; ++t) gv[t] = q.gv[t];
     }
     float yl[W];
 #pragma unroll
@@ -406,7 +442,7 @@ __device__ __forceinline__ float blk_process(BlkSlot<W> &q, float *ysh, int r0, 
     float acc = q.rhs;
 #pragma unroll
     for (int t = 0; t < W; ++t) {
-        const float dep = q.code[t] >= 0 ? __uint_as_float(q.gv[t]) : yl[t];
+        const float dep = q.code[t] >= 0 ? __uint_as_float(gv[t]) : yl[t];
         if (q.code[t] != -1) acc -= q.val[t] * dep;
     }
     const float y = acc / q.dg;
@@ -430,17 +466,17 @@ struct BlkSched {
     int nb, bmax, chmax;
 };
 
-// Dynamic LDS of the blocked kernels: records, right-hand side, solution and
-// chunk table of one block.
+// Dynamic LDS of the blocked kernels: records, right-hand side, solution,
+// chunk table and (fused PCG backward solve) the rr entries of one block.
 template <int W>
 inline size_t blk_lds_bytes(int bmax, int chmax) {
-    return (size_t)bmax * (2 * W + 2 + 2) * 4 + (size_t)chmax * 8;
+    return (size_t)bmax * (2 * W + 2 + 3) * 4 + (size_t)chmax * 8;
 }
 
-// Block b of a solve: stage, then walk the chunks.  rr (may be NULL): the
-// lane's sum of rr[row] * solution[row] is returned (fixed order: the lane's
-// chunks in schedule order).
-template <int W>
+// Block b of a solve: stage, then walk the chunks.  RZ: the lane's sum of
+// rr[row] * solution[row] is returned (fixed order: the lane's chunks in
+// schedule order); otherwise rr is not read and 0 is returned.
+template <int W, bool ROUND, bool RZ>
 __device__ double blk_solve(const BlkSched &S, int b, const float *rhs, uint32_t *ybits, const float *rr,
                             int backoff) {
     constexpr int RW = 2 * W + 2;
@@ -449,10 +485,14 @@ __device__ double blk_solve(const BlkSched &S, int b, const float *rhs, uint32_t
     float *rsh = reinterpret_cast<float *>(rec + S.bmax * RW);
     float *ysh = rsh + S.bmax;
     int2 *ch = reinterpret_cast<int2 *>(ysh + S.bmax);
+    float *rrsh = reinterpret_cast<float *>(ch + S.chmax);
     const int l = lane_id();
     const int r0 = S.brow[2 * b], nr = S.brow[2 * b + 1];
     const int c0 = S.bch[b], nch = S.bch[b + 1] - c0;
-    {  // staging: every load of a batch is issued before its stores
+    {  // staging: every load of a batch is issued before its stores.  Lanes
+       // past the end load the last element and store it back to the same
+       // place, so no branch guards a store (a guarded store would let the
+       // compiler sink its load into the branch and serialise the batch).
         const int4 *src = reinterpret_cast<const int4 *>(S.rec + (size_t)r0 * RW);
         int4 *dst = reinterpret_cast<int4 *>(rec);
         const int n4 = nr * RW / 4;
@@ -461,17 +501,23 @@ __device__ double blk_solve(const BlkSched &S, int b, const float *rhs, uint32_t
 #pragma unroll
             for (int u = 0; u < 8; ++u) v[u] = src[min(i + u * kWave, n4 - 1)];
 #pragma unroll
-            for (int u = 0; u < 8; ++u)
-                if (i + u * kWave < n4) dst[i + u * kWave] = v[u];
+            for (int u = 0; u < 8; ++u) dst[min(i + u * kWave, n4 - 1)] = v[u];
         }
         for (int i = l; i < nr; i += kWave * 8) {
             float v[8];
 #pragma unroll
             for (int u = 0; u < 8; ++u) v[u] = rhs[r0 + min(i + u * kWave, nr - 1)];
 #pragma unroll
-            for (int u = 0; u < 8; ++u)
-                if (i + u * kWave < nr) rsh[i + u * kWave] = v[u];
+            for (int u = 0; u < 8; ++u) rsh[min(i + u * kWave, nr - 1)] = v[u];
         }
+        if constexpr (RZ)
+            for (int i = l; i < nr; i += kWave * 8) {
+                float v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) v[u] = rr[r0 + min(i + u * kWave, nr - 1)];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) rrsh[min(i + u * kWave, nr - 1)] = v[u];
+            }
         for (int i = l; i < nch; i += kWave) ch[i] = S.ch[c0 + i];
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -482,7 +528,7 @@ __device__ double blk_solve(const BlkSched &S, int b, const float *rhs, uint32_t
 #pragma unroll
     for (int j = 0; j <= kBlkDist; ++j) blk_read<W>(q[j], rec, ch[min(j, nch - 1)], j, nch);
 #pragma unroll
-    for (int j = 0; j < kBlkDist; ++j) blk_issue<W>(q[j], rsh, ybits, rr, r0);
+    for (int j = 0; j < kBlkDist; ++j) blk_issue<W, RZ>(q[j], rsh, ybits, rrsh);
     int2 ccn = ch[min(kBlkDist + 1, nch - 1)];  // table entry of the next record to read
     double rz = 0.0;
     for (int c = 0; c < nch; c += R) {
@@ -491,9 +537,9 @@ __device__ double blk_solve(const BlkSched &S, int b, const float *rhs, uint32_t
             if (c + j < nch) {
                 blk_read<W>(q[(j + kBlkDist + 1) % R], rec, ccn, c + j + kBlkDist + 1, nch);
                 ccn = ch[min(c + j + kBlkDist + 2, nch - 1)];
-                blk_issue<W>(q[(j + kBlkDist) % R], rsh, ybits, rr, r0);
-                const float y = blk_process<W>(q[j], ysh, r0, ybits, backoff);
-                if (rr) rz += (double)q[j].rr * (double)y;
+                blk_issue<W, RZ>(q[(j + kBlkDist) % R], rsh, ybits, rrsh);
+                const float y = blk_process<W, ROUND>(q[j], ysh, r0, ybits, backoff);
+                if constexpr (RZ) rz += (double)q[j].rr * (double)y;
             }
         }
     }
@@ -509,7 +555,7 @@ __device__ __forceinline__ bool blk_off_xcd(int local) {
     return local && (__builtin_amdgcn_s_getreg((20) | (0 << 6) | (3 << 11)) & 7) != 0;
 }
 
-template <int W>
+template <int W, bool ROUND>
 static __global__ void __launch_bounds__(kWave) k_sptrsv_blk(BlkSched S, const float *__restrict__ rhs,
                                                             uint32_t *ybits, int *ticket, int backoff,
                                                             int local) {
@@ -517,7 +563,7 @@ static __global__ void __launch_bounds__(kWave) k_sptrsv_blk(BlkSched S, const f
     for (;;) {
         const int b = wave_ticket(ticket);
         if (b >= S.nb) break;
-        blk_solve<W>(S, b, rhs, ybits, nullptr, backoff);
+        blk_solve<W, ROUND, false>(S, b, rhs, ybits, nullptr, backoff);
     }
 }
 
