@@ -325,10 +325,10 @@ int blk_prepare(lpcg_system *s, int d, int B) {
     s->blk_chmax[d] = o.chmax;
     // allow the blocked kernels' dynamic LDS (set here, before any launch or
     // graph capture that uses the schedule)
-    const void *kers[] = {(const void *)k_sptrsv_blk<3, false>, (const void *)k_sptrsv_blk<7, false>,
-                          (const void *)k_sptrsv_blk<3, true>, (const void *)k_sptrsv_blk<7, true>};
-    for (const void *k : kers)
-        LPCG_HIP(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kBlkLdsMax));
+    LPCG_HIP(hipFuncSetAttribute((const void *)k_sptrsv_blk<3>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)kBlkLdsMax));
+    LPCG_HIP(hipFuncSetAttribute((const void *)k_sptrsv_blk<7>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)kBlkLdsMax));
     return LPCG_OK;
 }
 
@@ -376,16 +376,12 @@ int trsv_kernels(const lpcg_system *s, int transpose, const TrsvCfg &c, const fl
         }
         const BlkSched S = blk_sched(s, d);
         const int local = c.stride == 8, grid = S.nb * (local ? 8 : 1);
-        // backward solves poll missing values in rounds, forward ones singly
-        const size_t l3 = blk_lds_bytes<3>(S.bmax, S.chmax), l7 = blk_lds_bytes<7>(S.bmax, S.chmax);
-        if (s->blk_W[d] == 3 && up)
-            k_sptrsv_blk<3, true><<<grid, kWave, l3, st>>>(S, rhs, (uint32_t *)y, ticket, c.backoff, local);
-        else if (s->blk_W[d] == 3)
-            k_sptrsv_blk<3, false><<<grid, kWave, l3, st>>>(S, rhs, (uint32_t *)y, ticket, c.backoff, local);
-        else if (up)
-            k_sptrsv_blk<7, true><<<grid, kWave, l7, st>>>(S, rhs, (uint32_t *)y, ticket, c.backoff, local);
+        if (s->blk_W[d] == 3)
+            k_sptrsv_blk<3><<<grid, kWave, blk_lds_bytes<3>(S.bmax, S.chmax), st>>>(S, rhs, (uint32_t *)y, ticket,
+                                                                                 c.backoff, local);
         else
-            k_sptrsv_blk<7, false><<<grid, kWave, l7, st>>>(S, rhs, (uint32_t *)y, ticket, c.backoff, local);
+            k_sptrsv_blk<7><<<grid, kWave, blk_lds_bytes<7>(S.bmax, S.chmax), st>>>(S, rhs, (uint32_t *)y, ticket,
+                                                                                 c.backoff, local);
         LPCG_LAUNCH_CHECK();
         return LPCG_OK;
     }

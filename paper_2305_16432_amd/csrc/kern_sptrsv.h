@@ -383,58 +383,23 @@ __device__ __forceinline__ void blk_issue(BlkSlot<W> &q, const float *rsh, const
 }
 
 // Solve one chunk; returns the lane's solution value (0 for idle lanes).
-// Values the prefetch found unset are polled again until published:
-// ROUND = false re-reads each missing value on its own (a load and its wait
-// per value); ROUND = true re-reads all of a lane's missing values in one
-// round of unconditional loads (entry 0 where nothing is missing) and waits
-// once per round, keeping the polled values apart from the ring slot.  Which
-// is faster depends on the direction (timed on the 64^3 grid: the round form
-// for the backward solve, the single form for the forward one).
-template <int W, bool ROUND>
+// Values the prefetch found unset are re-read one by one until published.
+template <int W>
 __device__ __forceinline__ float blk_process(BlkSlot<W> &q, float *ysh, int r0, uint32_t *ybits, int backoff) {
-    uint32_t gv[W];
-    if constexpr (ROUND) {
-        bool need[W];
-        bool any = false;
+    bool ready = true;
 #pragma unroll
-        for (int t = 0; t < W; ++t) {
-            gv[t] = q.gv[t];
-            need[t] = q.act && q.code[t] >= 0 && gv[t] == kUnset;
-            any = any || need[t];
-        }
-        while (__ballot(any) != 0) {
-            for (int s = 0; s < backoff; ++s) __builtin_amdgcn_s_sleep(1);
-            uint32_t rd[W];
+    for (int t = 0; t < W; ++t) ready = ready && (!q.act || q.code[t] < 0 || q.gv[t] != kUnset);
+    while (__ballot(!ready) != 0) {
+        for (int s = 0; s < backoff; ++s) __builtin_amdgcn_s_sleep(1);
+        if (!ready) {
+            ready = true;
 #pragma unroll
-            for (int t = 0; t < W; ++t) rd[t] = ld_agent(&ybits[need[t] ? q.code[t] : 0]);
-            any = false;
-#pragma unroll
-            for (int t = 0; t < W; ++t) {
-                if (need[t] && rd[t] != kUnset) {
-                    gv[t] = rd[t];
-                    need[t] = false;
+            for (int t = 0; t < W; ++t)
+                if (q.code[t] >= 0 && q.gv[t] == kUnset) {
+                    q.gv[t] = ld_agent(&ybits[q.code[t]]);
+                    ready = ready && q.gv[t] != kUnset;
                 }
-                any = any || need[t];
-            }
         }
-    } else {
-        bool ready = true;
-#pragma unroll
-        for (int t = 0; t < W; ++t) ready = ready && (!q.act || q.code[t] < 0 || q.gv[t] != kUnset);
-        while (__ballot(!ready) != 0) {
-            for (int s = 0; s < backoff; ++s) __builtin_amdgcn_s_sleep(1);
-            if (!ready) {
-                ready = true;
-#pragma unroll
-                for (int t = 0; t < W; ++t)
-                    if (q.code[t] >= 0 && q.gv[t] == kUnset) {
-                        q.gv[t] = ld_agent(&ybits[q.code[t]]);
-                        ready = ready && q.gv[t] != kUnset;
-                    }
-            }
-        }
-#pragma unroll
-        for (int t = 0; t < W; ++t) gv[t] = q.gv[t];
     }
     float yl[W];
 #pragma unroll
@@ -442,7 +407,7 @@ __device__ __forceinline__ float blk_process(BlkSlot<W> &q, float *ysh, int r0, 
     float acc = q.rhs;
 #pragma unroll
     for (int t = 0; t < W; ++t) {
-        const float dep = q.code[t] >= 0 ? __uint_as_float(gv[t]) : yl[t];
+        const float dep = q.code[t] >= 0 ? __uint_as_float(q.gv[t]) : yl[t];
         if (q.code[t] != -1) acc -= q.val[t] * dep;
     }
     const float y = acc / q.dg;
@@ -476,7 +441,7 @@ inline size_t blk_lds_bytes(int bmax, int chmax) {
 // Block b of a solve: stage, then walk the chunks.  RZ: the lane's sum of
 // rr[row] * solution[row] is returned (fixed order: the lane's chunks in
 // schedule order); otherwise rr is not read and 0 is returned.
-template <int W, bool ROUND, bool RZ>
+template <int W, bool RZ>
 __device__ double blk_solve(const BlkSched &S, int b, const float *rhs, uint32_t *ybits, const float *rr,
                             int backoff) {
     constexpr int RW = 2 * W + 2;
@@ -538,7 +503,7 @@ __device__ double blk_solve(const BlkSched &S, int b, const float *rhs, uint32_t
                 blk_read<W>(q[(j + kBlkDist + 1) % R], rec, ccn, c + j + kBlkDist + 1, nch);
                 ccn = ch[min(c + j + kBlkDist + 2, nch - 1)];
                 blk_issue<W, RZ>(q[(j + kBlkDist) % R], rsh, ybits, rrsh);
-                const float y = blk_process<W, ROUND>(q[j], ysh, r0, ybits, backoff);
+                const float y = blk_process<W>(q[j], ysh, r0, ybits, backoff);
                 if constexpr (RZ) rz += (double)q[j].rr * (double)y;
             }
         }
@@ -555,7 +520,7 @@ __device__ __forceinline__ bool blk_off_xcd(int local) {
     return local && (__builtin_amdgcn_s_getreg((20) | (0 << 6) | (3 << 11)) & 7) != 0;
 }
 
-template <int W, bool ROUND>
+template <int W>
 static __global__ void __launch_bounds__(kWave) k_sptrsv_blk(BlkSched S, const float *__restrict__ rhs,
                                                             uint32_t *ybits, int *ticket, int backoff,
                                                             int local) {
@@ -563,7 +528,7 @@ static __global__ void __launch_bounds__(kWave) k_sptrsv_blk(BlkSched S, const f
     for (;;) {
         const int b = wave_ticket(ticket);
         if (b >= S.nb) break;
-        blk_solve<W, ROUND, false>(S, b, rhs, ybits, nullptr, backoff);
+        blk_solve<W, false>(S, b, rhs, ybits, nullptr, backoff);
     }
 }
 

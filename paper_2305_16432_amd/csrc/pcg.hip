@@ -218,7 +218,7 @@ __global__ void __launch_bounds__(kWave) k_llt_fwd_blk(Args a) {
     for (;;) {
         const int b = wave_ticket(ticket);
         if (b >= a.blk_f.nb) break;
-        blk_solve<W, false, false>(a.blk_f, b, a.r, a.y, nullptr, a.backoff_f);
+        blk_solve<W, false>(a.blk_f, b, a.r, a.y, nullptr, a.backoff_f);
     }
 }
 
@@ -232,7 +232,7 @@ __global__ void __launch_bounds__(kWave) k_llt_bwd_blk(Args a) {
     for (;;) {
         const int b = wave_ticket(ticket);
         if (b >= a.blk_b.nb) break;
-        double rz = blk_solve<W, true, true>(a.blk_b, b, (const float *)a.y, a.z, a.r, a.backoff_b);
+        double rz = blk_solve<W, true>(a.blk_b, b, (const float *)a.y, a.z, a.r, a.backoff_b);
         rz = wave_sum(rz);
         if (lane_id() == 0) publish_partial(a.sp_rz, b, rz);
         last = last || b == a.blk_b.nb - 1;
