@@ -384,11 +384,16 @@ __device__ __forceinline__ void blk_issue(BlkSlot<W> &q, const float *rsh, const
 
 // Solve one chunk; returns the lane's solution value (0 for idle lanes).
 // Values the prefetch found unset are re-read one by one until published.
+// Idle lanes hold the record of the chunk's last row (blk_read clamps them
+// to it), so they wait for the same values, compute the same result and
+// store the same bits to the same places.  The stores therefore need no
+// branch, and the compiler can count them among the memory operations in
+// flight, so its waits keep the prefetched chunks in flight.
 template <int W>
 __device__ __forceinline__ float blk_process(BlkSlot<W> &q, float *ysh, int r0, uint32_t *ybits, int backoff) {
     bool ready = true;
 #pragma unroll
-    for (int t = 0; t < W; ++t) ready = ready && (!q.act || q.code[t] < 0 || q.gv[t] != kUnset);
+    for (int t = 0; t < W; ++t) ready = ready && (q.code[t] < 0 || q.gv[t] != kUnset);
     while (__ballot(!ready) != 0) {
         for (int s = 0; s < backoff; ++s) __builtin_amdgcn_s_sleep(1);
         if (!ready) {
@@ -411,10 +416,8 @@ __device__ __forceinline__ float blk_process(BlkSlot<W> &q, float *ysh, int r0, 
         if (q.code[t] != -1) acc -= q.val[t] * dep;
     }
     const float y = acc / q.dg;
-    if (q.act) {
-        ysh[q.row] = y;
-        st_agent(&ybits[r0 + q.row], publishable(y));
-    }
+    ysh[q.row] = y;
+    st_agent(&ybits[r0 + q.row], publishable(y));
     // LDS ordering between the lanes of the wave (no global wait)
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
