@@ -104,6 +104,8 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--eval-every", type=int, default=100)
     ap.add_argument("--eval-m", type=int, default=64)
+    ap.add_argument("--eval-systems", type=int, default=1,
+                    help="held-out systems (k seeds 5000+i, u0 seeds 6000+i); selection uses their mean iterations")
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--out", required=True)
     args = ap.parse_args()
@@ -152,34 +154,48 @@ def main():
     m1, v1 = torch.zeros_like(params), torch.zeros_like(params)
     ws = lpcg.gnn_workspace(S, h, n_mp, train=True)
 
-    # held-out evaluation system (unseen seeds, full size)
-    Ae, be = g.heat_system_3d(args.eval_m, 1e-3, k_seed=5000, u0_seed=6000)
-    Se = lpcg.analyze(torch.as_tensor(Ae.rowptr).cuda(), torch.as_tensor(Ae.colind).cuda(),
-                      torch.as_tensor(Ae.val).cuda(), None, order)
-    bed = torch.as_tensor(be).cuda()
+    # held-out evaluation systems (unseen seeds, full size)
+    held = []
+    ric_its, rj_its = [], []
+    for i in range(max(1, args.eval_systems)):
+        Ae, be = g.heat_system_3d(args.eval_m, 1e-3, k_seed=5000 + i, u0_seed=6000 + i)
+        Se = lpcg.analyze(torch.as_tensor(Ae.rowptr).cuda(), torch.as_tensor(Ae.colind).cuda(),
+                          torch.as_tensor(Ae.val).cuda(), None, order)
+        bed = torch.as_tensor(be).cuda()
+        lic, uic, _ = lpcg.ic0(Se)
+        _, ric = lpcg.pcg_solve(Se, lpcg.PC_LLT, bed, l_val=lic, ut_val=uic, tol=1e-6, maxit=2000)
+        _, rj = lpcg.pcg_solve(Se, lpcg.PC_JACOBI, bed, tol=1e-6, maxit=2000)
+        ric_its.append(ric["iters"])
+        rj_its.append(rj["iters"])
+        held.append((Se, bed))
+    Se = held[0][0]
     wse = lpcg.gnn_workspace(Se, h, n_mp)
     nl = Se.info["nnz_l"]
     le = torch.empty(nl, dtype=torch.float32, device="cuda")
     ue = torch.empty(nl, dtype=torch.float32, device="cuda")
-    lic, uic, _ = lpcg.ic0(Se)
-    _, ric = lpcg.pcg_solve(Se, lpcg.PC_LLT, bed, l_val=lic, ut_val=uic, tol=1e-6, maxit=2000)
-    _, rj = lpcg.pcg_solve(Se, lpcg.PC_JACOBI, bed, tol=1e-6, maxit=2000)
-    print(f"[train] held-out 64^3 ({args.ordering} order, {Se.info['nlev_fwd']} levels): IC(0) {ric['iters']} its, Jacobi {rj['iters']} its", flush=True)
+    ric = {"iters": float(np.mean(ric_its))}
+    rj = {"iters": float(np.mean(rj_its))}
+    print(f"[train] held-out {len(held)} x {args.eval_m}^3 ({args.ordering} order, {Se.info['nlev_fwd']} levels): "
+          f"IC(0) {ric_its} its, Jacobi {rj_its} its", flush=True)
 
     def evaluate(with_x0=xh, report=None):
-        x0 = None
-        if xh:
-            _, _, x0 = lpcg.gnn_predict_x0(Se, params, h, n_mp, bed, wse, le, ue, diag_mode=dm)
-        else:
-            lpcg.gnn_predict_L(Se, params, h, n_mp, bed, wse, le, ue, diag_mode=dm)
-        _, r, hist = lpcg.pcg_solve(Se, lpcg.PC_LLT, bed, x=x0 if with_x0 else None, l_val=le, ut_val=ue,
-                                    tol=1e-6, maxit=2000, hist=True)
-        if report is not None:  # relative residual of the starting point, then at each tolerance
-            hh = hist.cpu().numpy()
-            report["start_relres"] = float(hh[0])
-            report["iters_to"] = {f"1e-{e}": int(np.argmax(hh <= 10.0 ** -e)) if np.any(hh <= 10.0 ** -e)
-                                  else None for e in range(1, 7)}
-        return r["iters"] if r["status"] == 0 else 10 ** 6
+        """Mean PCG iterations to 1e-6 over the held-out systems (10^6 if one fails)."""
+        its = []
+        for k, (Sk, bk) in enumerate(held):
+            x0 = None
+            if xh:
+                _, _, x0 = lpcg.gnn_predict_x0(Sk, params, h, n_mp, bk, wse, le, ue, diag_mode=dm)
+            else:
+                lpcg.gnn_predict_L(Sk, params, h, n_mp, bk, wse, le, ue, diag_mode=dm)
+            _, r, hist = lpcg.pcg_solve(Sk, lpcg.PC_LLT, bk, x=x0 if with_x0 else None, l_val=le, ut_val=ue,
+                                        tol=1e-6, maxit=2000, hist=True)
+            if report is not None and k == 0:  # first system: starting relative residual, then per tolerance
+                hh = hist.cpu().numpy()
+                report["start_relres"] = float(hh[0])
+                report["iters_to"] = {f"1e-{e}": int(np.argmax(hh <= 10.0 ** -e)) if np.any(hh <= 10.0 ** -e)
+                                      else None for e in range(1, 7)}
+            its.append(r["iters"] if r["status"] == 0 else 10 ** 6)
+        return float(np.mean(its)) if len(its) > 1 else its[0]
 
     rng = np.random.default_rng(args.seed)
     log = {"loss": [], "eval": [], "ic0_iters": ric["iters"], "jacobi_iters": rj["iters"]}
