@@ -214,9 +214,10 @@ int lpcg_time_spmv(const lpcg_system *sys, const float *x, float *y, int32_t rep
 typedef struct {
     int32_t direction;     /* 0: forward (L y = r), 1: backward (L^T z = y) */
     int32_t mode;          /* 0 dependency driven, 1 level synchronous, 2 single workgroup,
-                              3 blocked (one wave per block of block_rows consecutive rows;
-                              dependencies inside a block through LDS, on earlier blocks
-                              polled; rows with at most 7 dependencies) */
+                              3 blocked (one wave per block of block_rows rows, consecutive
+                              or banded (block_runs); dependencies inside a block through
+                              LDS, on earlier blocks polled; rows with at most 7
+                              dependencies) */
     int32_t waves;         /* mode 0: waves launched (0 = default) */
     int32_t backoff;       /* modes 0 and 3: sleep rounds between polls (0..64) */
     int32_t block_stride;  /* mode 0: only blocks whose index is a multiple of this
@@ -230,6 +231,14 @@ typedef struct {
                               schedule is built on the host when the configuration is set
                               (synchronous) */
     double us;             /* lpcg_autotune: mean duration of one solve */
+    int32_t block_runs;    /* mode 3: 1 (or 0): a block is block_rows consecutive rows.
+                              K > 1: banded, K runs of block_rows / K consecutive rows
+                              (a power of two), one stride D apart, D = the pattern's
+                              longest dependency offset (one plane of a natural-order
+                              grid); the rows must tile into such blocks (n a multiple of
+                              K D, D a multiple of the run) and every dependency on
+                              another block must point to an earlier block in solve
+                              order, else EINVAL */
 } lpcg_trsv_cfg;
 
 /* Schedule of the blocked substitution (mode 3), computed on the host from
@@ -237,32 +246,39 @@ typedef struct {
  * for inspection and tests.  rowptr/col: HOST, n rows, the pattern of L
  * (upper = 0: columns ascending, diagonal last, rows solved ascending) or of
  * U = L^T (upper = 1: diagonal first, rows solved descending).  Rows are cut
- * into blocks of block_rows consecutive rows in solve order; inside a block
- * they are ordered by their level over in-block dependencies and cut into
- * chunks of at most 64 rows of one level.  Call once with the five arrays
- * NULL to get the sizes, then with caller-owned HOST arrays of
- *   brow[2 nblocks]      first row, row count of each block
+ * into blocks of block_rows rows in solve order: consecutive rows
+ * (block_runs <= 1), or banded in block_runs runs as lpcg_trsv_cfg
+ * describes.  A block's positions 0 .. nr-1 map to its rows ascending
+ * (run_shift, run_stride below).  Inside a block the rows are ordered by
+ * their level over in-block dependencies and cut into chunks of at most 64
+ * rows of one level.  Call once with the five arrays NULL to get the sizes,
+ * then with caller-owned HOST arrays of
+ *   brow[2 nblocks]      first (smallest) row, row count of each block
  *   bch[nblocks + 1]     chunk range of each block
- *   chunks[2 nchunks]    first record (relative to the block's first row)
- *                        and row count of each chunk
- *   rec[n (2 deps + 2)]  per row, at the block's own row positions: deps
+ *   chunks[2 nchunks]    first record (schedule position in the block) and
+ *                        row count of each chunk
+ *   rec[n (2 deps + 2)]  record p of block b at row position map(b, p): deps
  *                        dependency codes in CSR order (>= 0 row of an
- *                        earlier block, -1 none, <= -2 in-block row
- *                        -2 - code relative to the block's first row), the
- *                        row relative to the block's first row, then deps + 1
- *                        value words (filled on the device per factor; 0 here)
+ *                        earlier block, -1 none, <= -2 in-block row at
+ *                        position -2 - code), the row's position, then
+ *                        deps + 1 value words (filled on the device per
+ *                        factor; 0 here)
  *   vsrc[n (deps + 1)]   position in the CSR value array of each value and,
  *                        last, of the diagonal (-1: none).
  * deps is 3 or 7.  Errors: EINVAL (block_rows outside [64, 65536], a row with
  * more than 7 dependencies, the LDS bound of the device kernel exceeded,
+ * banded blocks that do not tile the rows or are not in dependency order,
  * arrays sized for another schedule). */
 typedef struct {
     int32_t deps, nblocks, nchunks, max_chunks;
     int32_t *brow, *bch, *chunks, *rec, *vsrc;
+    int32_t run_shift, run_stride;  /* out: position x of block b is the row
+                                       brow[2b] + (x >> run_shift) * run_stride
+                                       + (x & ((1 << run_shift) - 1)) */
 } lpcg_blk_schedule;
 
 int lpcg_blocked_schedule(int32_t n, const int32_t *rowptr, const int32_t *col, int32_t upper,
-                          int32_t block_rows, lpcg_blk_schedule *out);
+                          int32_t block_rows, int32_t block_runs, lpcg_blk_schedule *out);
 
 /* Autotuner: times every candidate configuration of both substitution
  * directions on this system with the given factor (reps timed runs after

@@ -202,6 +202,9 @@ void blk_free(lpcg_system *s, int d) {
         *p = nullptr;
     }
     s->blk_B[d] = 0;
+    s->blk_K[d] = 1;
+    s->blk_lsh[d] = 30;
+    s->blk_D[d] = 0;
 }
 
 template <typename T>
@@ -217,11 +220,21 @@ static int upload(T **dst, const std::vector<T> &h) {
 // row (dependency codes in CSR order, row, and the positions of the values).
 // Pure host code: rp/ci is the direction's CSR pattern (diagonal stored).
 struct BlkHost {
-    int W = 0, nb = 0, chmax = 0;
+    int W = 0, nb = 0, chmax = 0, lsh = 30, D = 0;
     std::vector<int> brow, bch, ch, rec, vsrc;
 };
 
-static int blk_build(int n, const int *rp, const int *ci, int d, int B, BlkHost &o) {
+// Longest dependency offset of a triangular pattern (L: rows ascending,
+// diagonal last; U: diagonal first): the stride between the runs of a banded
+// block (one grid plane for a natural-order grid).
+static int blk_dep_offset(int n, const int *rp, const int *ci, int d) {
+    int D = 0;
+    for (int r = 0; r < n; ++r)
+        if (rp[r + 1] - rp[r] > 1) D = std::max(D, d ? ci[rp[r + 1] - 1] - r : r - ci[rp[r]]);
+    return D;
+}
+
+static int blk_build(int n, const int *rp, const int *ci, int d, int B, int K, BlkHost &o) {
     if (n <= 0 || B < 64 || B > (1 << 16)) {
         set_error("blocked substitution: block size %d outside [64, 65536] (n = %d)", B, n);
         return LPCG_EINVAL;
@@ -233,38 +246,86 @@ static int blk_build(int n, const int *rp, const int *ci, int d, int B, BlkHost 
         set_error("blocked substitution: a row has %d dependencies (at most 7)", maxdep);
         return LPCG_EINVAL;
     }
-    const int RW = 2 * W + 2, nb = (n + B - 1) / B;
+    // Banded blocks (K > 1): K runs of len = B / K consecutive rows, D rows
+    // apart (D = the longest dependency offset).  Group g holds the rows
+    // [g K D, (g + 1) K D), cut into D / len bands; block (g, q) is band q of
+    // every run of the group.  Blocks are numbered g-major in row order and
+    // ticketed in solve order (descending for U).
+    int len = B, D = 0, lsh = 30, Q = 1;
+    if (K > 1) {
+        D = blk_dep_offset(n, rp, ci, d);
+        len = B / K;
+        lsh = 0;
+        while ((1 << lsh) < len) ++lsh;
+        if (B % K || (1 << lsh) != len || D < len || D % len || (long)n % ((long)K * D)) {
+            set_error("blocked substitution: %d runs of %d rows do not tile %d rows with stride %d", K, len, n, D);
+            return LPCG_EINVAL;
+        }
+        Q = D / len;
+    } else if (K != 1) {
+        set_error("blocked substitution: %d runs per block", K);
+        return LPCG_EINVAL;
+    }
+    const long G = (long)K * D;
+    const int RW = 2 * W + 2, nb = K > 1 ? (int)(n / G) * Q : (n + B - 1) / B;
     o = BlkHost{};
     o.W = W;
     o.nb = nb;
+    o.lsh = lsh;
+    o.D = D;
     o.brow.assign(2 * (size_t)nb, 0);
     o.bch.assign(1, 0);
     o.rec.assign((size_t)n * RW, 0);
     o.vsrc.assign((size_t)n * (W + 1), -1);
     std::vector<int> lev(n, 0), cnt, order;
     for (int b = 0; b < nb; ++b) {
-        const int r0 = d ? std::max(0, n - (b + 1) * B) : b * B;
-        const int r1 = d ? n - b * B : std::min(n, (b + 1) * B);
+        int r0, nr, idx = 0;
+        if (K > 1) {
+            idx = d ? nb - 1 - b : b;
+            r0 = (int)((idx / Q) * G + (long)(idx % Q) * len);
+            nr = B;
+        } else {
+            r0 = d ? std::max(0, n - (b + 1) * B) : b * B;
+            nr = (d ? n - b * B : std::min(n, (b + 1) * B)) - r0;
+        }
         o.brow[2 * b] = r0;
-        o.brow[2 * b + 1] = r1 - r0;
+        o.brow[2 * b + 1] = nr;
+        auto row_of = [&](int x) { return r0 + (x >> lsh) * D + (x & ((1 << lsh) - 1)); };
+        // slot of row c in this block, or -1
+        auto slot_of = [&](int c) -> int {
+            if (K == 1) return c >= r0 && c < r0 + nr ? c - r0 : -1;
+            const long off = c - (long)(idx / Q) * G;
+            if (off < 0 || off >= G || (off % D) / len != idx % Q) return -1;
+            return (int)((off / D) * len + off % D - (long)(idx % Q) * len);
+        };
         int maxl = 0;
-        for (int i = 0; i < r1 - r0; ++i) {  // solve order inside the block
-            const int r = d ? r1 - 1 - i : r0 + i;
+        for (int i = 0; i < nr; ++i) {  // solve order inside the block
+            const int x = d ? nr - 1 - i : i, r = row_of(x);
             int l = 0;
             for (int k = rp[r]; k < rp[r + 1]; ++k) {
                 const int c = ci[k];
-                if (c != r && c >= r0 && c < r1) l = std::max(l, lev[c] + 1);
+                if (c == r) continue;
+                if (slot_of(c) >= 0) {
+                    l = std::max(l, lev[c] + 1);
+                } else if (K > 1) {  // another block: it must hold an earlier ticket
+                    const long oc = c % G;
+                    const int idc = (int)((c / G) * Q + (oc % D) / len);
+                    if (d ? idc <= idx : idc >= idx) {
+                        set_error("blocked substitution: banded blocks of %d runs are not in dependency order", K);
+                        return LPCG_EINVAL;
+                    }
+                }
             }
             lev[r] = l;
             maxl = std::max(maxl, l);
         }
         cnt.assign(maxl + 2, 0);
-        for (int r = r0; r < r1; ++r) ++cnt[lev[r] + 1];
+        for (int x = 0; x < nr; ++x) ++cnt[lev[row_of(x)] + 1];
         for (int l = 0; l <= maxl; ++l) cnt[l + 1] += cnt[l];
-        order.assign(r1 - r0, 0);
+        order.assign(nr, 0);
         std::vector<int> fill(cnt.begin(), cnt.end() - 1);
-        for (int i = 0; i < r1 - r0; ++i) {
-            const int r = d ? r1 - 1 - i : r0 + i;
+        for (int i = 0; i < nr; ++i) {
+            const int r = row_of(d ? nr - 1 - i : i);
             order[fill[lev[r]]++] = r;
         }
         const int cbase = (int)o.ch.size() / 2;
@@ -275,12 +336,12 @@ static int blk_build(int n, const int *rp, const int *ci, int d, int B, BlkHost 
             }
         o.bch.push_back((int)o.ch.size() / 2);
         o.chmax = std::max(o.chmax, (int)o.ch.size() / 2 - cbase);
-        for (int p = 0; p < r1 - r0; ++p) {
-            const int r = order[p];
-            int *w = &o.rec[(size_t)(r0 + p) * RW];
-            int *vs = &o.vsrc[(size_t)(r0 + p) * (W + 1)];
+        for (int p = 0; p < nr; ++p) {  // record p at the block's p-th row position
+            const int r = order[p], at = row_of(p);
+            int *w = &o.rec[(size_t)at * RW];
+            int *vs = &o.vsrc[(size_t)at * (W + 1)];
             for (int t = 0; t < W; ++t) w[t] = -1;
-            w[W] = r - r0;
+            w[W] = slot_of(r);
             int t = 0;
             for (int k = rp[r]; k < rp[r + 1]; ++k) {
                 const int c = ci[k];
@@ -288,7 +349,8 @@ static int blk_build(int n, const int *rp, const int *ci, int d, int B, BlkHost 
                     vs[W] = k;
                     continue;
                 }
-                w[t] = (c >= r0 && c < r1) ? -2 - (c - r0) : c;
+                const int sc = slot_of(c);
+                w[t] = sc >= 0 ? -2 - sc : c;
                 vs[t] = k;
                 ++t;
             }
@@ -302,15 +364,15 @@ static int blk_build(int n, const int *rp, const int *ci, int d, int B, BlkHost 
     return LPCG_OK;
 }
 
-int blk_prepare(lpcg_system *s, int d, int B) {
-    if (s->blk_B[d] == B && s->blk_rec[d]) return LPCG_OK;
+int blk_prepare(lpcg_system *s, int d, int B, int K) {
+    if (s->blk_B[d] == B && s->blk_K[d] == K && s->blk_rec[d]) return LPCG_OK;
     const int n = s->n, nl = s->nnz_l;
     std::vector<int> rp(n + 1), ci(nl);
     LPCG_HIP(hipDeviceSynchronize());
     LPCG_HIP(hipMemcpy(rp.data(), d ? s->urowptr : s->lrowptr, sizeof(int) * (n + 1), hipMemcpyDeviceToHost));
     LPCG_HIP(hipMemcpy(ci.data(), d ? s->ucol : s->lcol, sizeof(int) * nl, hipMemcpyDeviceToHost));
     BlkHost o;
-    int rc = blk_build(n, rp.data(), ci.data(), d, B, o);
+    int rc = blk_build(n, rp.data(), ci.data(), d, B, K, o);
     if (rc) return rc;
     blk_free(s, d);
     if ((rc = upload(&s->blk_brow[d], o.brow)) || (rc = upload(&s->blk_bch[d], o.bch)) ||
@@ -320,6 +382,9 @@ int blk_prepare(lpcg_system *s, int d, int B) {
         return rc;
     }
     s->blk_B[d] = B;
+    s->blk_K[d] = K;
+    s->blk_lsh[d] = o.lsh;
+    s->blk_D[d] = o.D;
     s->blk_W[d] = o.W;
     s->blk_nb[d] = o.nb;
     s->blk_chmax[d] = o.chmax;
@@ -342,7 +407,7 @@ int blk_pack(const lpcg_system *s, int d, const float *lval, const float *utval,
 
 static BlkSched blk_sched(const lpcg_system *s, int d) {
     return BlkSched{s->blk_brow[d], s->blk_bch[d], reinterpret_cast<const int2 *>(s->blk_ch[d]), s->blk_rec[d],
-                    s->blk_nb[d], s->blk_B[d], s->blk_chmax[d]};
+                    s->blk_nb[d], s->blk_B[d], s->blk_chmax[d], s->blk_lsh[d], s->blk_D[d]};
 }
 
 // Enqueue the kernels of one substitution with configuration c: the
@@ -370,8 +435,8 @@ int trsv_kernels(const lpcg_system *s, int transpose, const TrsvCfg &c, const fl
     }
     if (c.mode == 3) {
         const int d = up ? 1 : 0;
-        if (s->blk_B[d] != c.blk || !s->blk_rec[d]) {
-            set_error("blocked substitution: no schedule for block size %d", c.blk);
+        if (s->blk_B[d] != c.blk || s->blk_K[d] != c.runs || !s->blk_rec[d]) {
+            set_error("blocked substitution: no schedule for block size %d in %d runs", c.blk, c.runs);
             return LPCG_EINVAL;
         }
         const BlkSched S = blk_sched(s, d);
@@ -428,7 +493,7 @@ int trsv_presets(const lpcg_system *s, int transpose, const TrsvCfg &c, const fl
                  float *y, int *ticket, hipStream_t st) {
     if (c.mode == 2) return lo_prepare(s, transpose, lval, utval, st);
     if (c.mode == 3) {
-        int rc = blk_prepare(const_cast<lpcg_system *>(s), transpose ? 1 : 0, c.blk);
+        int rc = blk_prepare(const_cast<lpcg_system *>(s), transpose ? 1 : 0, c.blk, c.runs);
         if (rc || (rc = blk_pack(s, transpose ? 1 : 0, lval, utval, st))) return rc;
     } else if (c.mode != 0) {
         return LPCG_OK;
@@ -659,13 +724,13 @@ extern "C" int lpcg_time_spmv(const lpcg_system *s, const float *x, float *y, in
 }
 
 extern "C" int lpcg_blocked_schedule(int32_t n, const int32_t *rowptr, const int32_t *col, int32_t upper,
-                                     int32_t block_rows, lpcg_blk_schedule *out) {
+                                     int32_t block_rows, int32_t block_runs, lpcg_blk_schedule *out) {
     if (!out || !rowptr || !col || (upper != 0 && upper != 1)) {
         set_error("lpcg_blocked_schedule: invalid arguments");
         return LPCG_EINVAL;
     }
     BlkHost o;
-    const int rc = blk_build(n, rowptr, col, upper, block_rows, o);
+    const int rc = blk_build(n, rowptr, col, upper, block_rows, block_runs > 0 ? block_runs : 1, o);
     if (rc) return rc;
     const int nch = (int)o.ch.size() / 2;
     const bool fill = out->brow && out->bch && out->chunks && out->rec && out->vsrc;
@@ -677,6 +742,8 @@ extern "C" int lpcg_blocked_schedule(int32_t n, const int32_t *rowptr, const int
     out->nblocks = o.nb;
     out->nchunks = nch;
     out->max_chunks = o.chmax;
+    out->run_shift = o.lsh;
+    out->run_stride = o.D;
     if (fill) {
         std::copy(o.brow.begin(), o.brow.end(), out->brow);
         std::copy(o.bch.begin(), o.bch.end(), out->bch);
@@ -700,6 +767,7 @@ extern "C" int lpcg_get_trsv_cfg(const lpcg_system *s, int32_t direction, lpcg_t
     out->block_stride = c.stride;
     out->block_rows = c.mode == 3 ? c.blk : 0;
     out->us = 0;
+    out->block_runs = c.mode == 3 ? c.runs : 0;
     return LPCG_OK;
 }
 
@@ -717,7 +785,8 @@ extern "C" int lpcg_set_trsv_cfg(lpcg_system *s, const lpcg_trsv_cfg *cfg) {
         return LPCG_EINVAL;
     }
     if (cfg->mode == 3) {  // builds the schedule (synchronous)
-        const int rc = blk_prepare(s, cfg->direction, cfg->block_rows > 0 ? cfg->block_rows : 1024);
+        const int rc = blk_prepare(s, cfg->direction, cfg->block_rows > 0 ? cfg->block_rows : 1024,
+                                   cfg->block_runs > 0 ? cfg->block_runs : 1);
         if (rc) return rc;
     }
     TrsvCfg &c = s->trsv[cfg->direction];
@@ -726,6 +795,7 @@ extern "C" int lpcg_set_trsv_cfg(lpcg_system *s, const lpcg_trsv_cfg *cfg) {
     c.backoff = cfg->backoff;
     c.stride = cfg->block_stride > 0 ? cfg->block_stride : 1;
     c.blk = cfg->mode == 3 ? (cfg->block_rows > 0 ? cfg->block_rows : 1024) : 0;
+    c.runs = cfg->mode == 3 && cfg->block_runs > 0 ? cfg->block_runs : 1;
     if (s->graph_exec) {  // the cached PCG graph launches the old kernels
         hipGraphExecDestroy(s->graph_exec);
         s->graph_exec = nullptr;
@@ -761,7 +831,11 @@ extern "C" int lpcg_autotune(lpcg_system *s, const float *l_val, const float *ut
         for (int B : {512, 1024, 2048})  // blocked mode, where the rows and the LDS allow it
             if (B < s->n && blk_prepare(s, dir, B) == LPCG_OK)
                 for (int bo : {0, 1})
-                    for (int xl : {1, 8}) cands.push_back(TrsvCfg{3, 0, bo, xl, B});  // 8: on XCD 0 only
+                    for (int xl : {1, 8}) cands.push_back(TrsvCfg{3, 0, bo, xl, B, 1});  // 8: on XCD 0 only
+        for (int B : {1024, 2048})  // banded blocks, where the pattern tiles into them
+            for (int K : {2, 4, 8})
+                if (B < s->n && blk_prepare(s, dir, B, K) == LPCG_OK)
+                    for (int bo : {0, 1}) cands.push_back(TrsvCfg{3, 0, bo, 1, B, K});
         for (int w : {64, 128, 256, 512, 1024, 2048, 4096})
             for (int bo : {1, 4, 16, 64}) {
                 if (w > trsv_waves(s->n, 1 << 30) && w != 64) continue;  // more waves than chunks
@@ -794,6 +868,7 @@ extern "C" int lpcg_autotune(lpcg_system *s, const float *l_val, const float *ut
                 e.block_stride = c.stride;
                 e.block_rows = c.mode == 3 ? c.blk : 0;
                 e.us = us;
+                e.block_runs = c.mode == 3 ? c.runs : 0;
             }
             ++count;
             if (us < best) {
@@ -807,7 +882,7 @@ extern "C" int lpcg_autotune(lpcg_system *s, const float *l_val, const float *ut
             }
         }
         if (best_c.mode == 3) {  // leave the winner's schedule in place
-            const int rc = blk_prepare(s, dir, best_c.blk);
+            const int rc = blk_prepare(s, dir, best_c.blk, best_c.runs);
             if (rc) return rc;
         }
         s->trsv[dir] = best_c;

@@ -315,10 +315,13 @@ static __global__ void k_lo_prep(int noff, int n, const int *__restrict__ src, c
 namespace lpcg {
 
 // ---------------------------------------------------------------------------
-// Blocked substitution (mode 3).  The rows are cut into blocks of B
-// consecutive rows, taken in solve order (ascending for L, descending for
-// L^T); one wave owns a block, blocks are handed out through a ticket in that
-// order.  A host-built schedule lists a block's rows by their level inside
+// Blocked substitution (mode 3).  The rows are cut into blocks of B rows,
+// taken in solve order (ascending for L, descending for L^T); one wave owns a
+// block, blocks are handed out through a ticket in that order.  A block is
+// either B consecutive rows or, banded, K runs of B/K consecutive rows that
+// lie a fixed stride apart (the pattern's longest dependency, one grid plane
+// on a natural-order grid), so that several planes of a band share a wave and
+// their plane-to-plane dependencies stay in its LDS.  A host-built schedule lists a block's rows by their level inside
 // the block (longest path over in-block dependencies), in chunks of at most
 // 64 rows of one level.  The wave copies its block's records and right-hand
 // side into LDS once, then walks the chunks: in-block dependencies are read
@@ -331,10 +334,27 @@ namespace lpcg {
 //
 // Record of a row (2W + 2 words, W = 3 or 7 dependencies at most): words
 // [0, W) dependency codes (>= 0: global row; -1: none; <= -2: in-block row
-// -2 - code, relative to the block's first row), word W the row relative to
-// the block's first row, words W+1 .. 2W the values, word 2W + 1 the
-// diagonal.  The values are packed per factor by k_blk_pack.
+// of slot -2 - code), word W the row's slot in the block, words W+1 .. 2W
+// the values, word 2W + 1 the diagonal.  A slot x of block b is the row
+// blk_row(x): its rows ascending.  Record p of block b (schedule order) is
+// stored at global position blk_row(p), so the blocks' records tile [0, n).
+// The values are packed per factor by k_blk_pack.
 constexpr int kBlkDist = 2;
+
+// Schedule of one direction (device arrays).
+struct BlkSched {
+    const int *brow;  // [2 nb]: first (smallest) row and row count of block b
+    const int *bch;   // [nb + 1]: chunk range of block b
+    const int2 *ch;   // chunk table: first record (relative to the block) and rows
+    const int *rec;   // [n * (2W + 2)] records, block b's at its rows' positions
+    int nb, bmax, chmax;
+    int lsh, dstride;  // runs of 2^lsh rows, dstride apart (one run: lsh >= log2 B)
+};
+
+// Row of slot (or stored record) x of the block whose first row is r0.
+__device__ __forceinline__ int blk_row(const BlkSched &S, int r0, int x) {
+    return r0 + (x >> S.lsh) * S.dstride + (x & ((1 << S.lsh) - 1));
+}
 
 template <int W>
 struct BlkSlot {
@@ -390,7 +410,8 @@ __device__ __forceinline__ void blk_issue(BlkSlot<W> &q, const float *rsh, const
 // branch, and the compiler can count them among the memory operations in
 // flight, so its waits keep the prefetched chunks in flight.
 template <int W>
-__device__ __forceinline__ float blk_process(BlkSlot<W> &q, float *ysh, int r0, uint32_t *ybits, int backoff) {
+__device__ __forceinline__ float blk_process(BlkSlot<W> &q, float *ysh, const BlkSched &S, int r0,
+                                             uint32_t *ybits, int backoff) {
     bool ready = true;
 #pragma unroll
     for (int t = 0; t < W; ++t) ready = ready && (q.code[t] < 0 || q.gv[t] != kUnset);
@@ -417,22 +438,13 @@ __device__ __forceinline__ float blk_process(BlkSlot<W> &q, float *ysh, int r0, 
     }
     const float y = acc / q.dg;
     ysh[q.row] = y;
-    st_agent(&ybits[r0 + q.row], publishable(y));
+    st_agent(&ybits[blk_row(S, r0, q.row)], publishable(y));
     // LDS ordering between the lanes of the wave (no global wait)
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     return q.act ? y : 0.f;
 }
-
-// Schedule of one direction (device arrays).
-struct BlkSched {
-    const int *brow;  // [2 nb]: first row and row count of block b
-    const int *bch;   // [nb + 1]: chunk range of block b
-    const int2 *ch;   // chunk table: first record (relative to the block) and rows
-    const int *rec;   // [n * (2W + 2)] records, block b's at its rows' positions
-    int nb, bmax, chmax;
-};
 
 // Dynamic LDS of the blocked kernels: records, right-hand side, solution,
 // chunk table and (fused PCG backward solve) the rr entries of one block.
@@ -461,20 +473,24 @@ __device__ double blk_solve(const BlkSched &S, int b, const float *rhs, uint32_t
        // past the end load the last element and store it back to the same
        // place, so no branch guards a store (a guarded store would let the
        // compiler sink its load into the branch and serialise the batch).
-        const int4 *src = reinterpret_cast<const int4 *>(S.rec + (size_t)r0 * RW);
+        constexpr int Q4 = RW / 4;  // 16-byte pieces per record
+        const int4 *src = reinterpret_cast<const int4 *>(S.rec);
         int4 *dst = reinterpret_cast<int4 *>(rec);
-        const int n4 = nr * RW / 4;
+        const int n4 = nr * Q4;
         for (int i = l; i < n4; i += kWave * 8) {
             int4 v[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) v[u] = src[min(i + u * kWave, n4 - 1)];
+            for (int u = 0; u < 8; ++u) {
+                const int x = min(i + u * kWave, n4 - 1);
+                v[u] = src[(size_t)blk_row(S, r0, x / Q4) * Q4 + x % Q4];
+            }
 #pragma unroll
             for (int u = 0; u < 8; ++u) dst[min(i + u * kWave, n4 - 1)] = v[u];
         }
         for (int i = l; i < nr; i += kWave * 8) {
             float v[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) v[u] = rhs[r0 + min(i + u * kWave, nr - 1)];
+            for (int u = 0; u < 8; ++u) v[u] = rhs[blk_row(S, r0, min(i + u * kWave, nr - 1))];
 #pragma unroll
             for (int u = 0; u < 8; ++u) rsh[min(i + u * kWave, nr - 1)] = v[u];
         }
@@ -482,7 +498,7 @@ __device__ double blk_solve(const BlkSched &S, int b, const float *rhs, uint32_t
             for (int i = l; i < nr; i += kWave * 8) {
                 float v[8];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) v[u] = rr[r0 + min(i + u * kWave, nr - 1)];
+                for (int u = 0; u < 8; ++u) v[u] = rr[blk_row(S, r0, min(i + u * kWave, nr - 1))];
 #pragma unroll
                 for (int u = 0; u < 8; ++u) rrsh[min(i + u * kWave, nr - 1)] = v[u];
             }
@@ -506,7 +522,7 @@ __device__ double blk_solve(const BlkSched &S, int b, const float *rhs, uint32_t
                 blk_read<W>(q[(j + kBlkDist + 1) % R], rec, ccn, c + j + kBlkDist + 1, nch);
                 ccn = ch[min(c + j + kBlkDist + 2, nch - 1)];
                 blk_issue<W, RZ>(q[(j + kBlkDist) % R], rsh, ybits, rrsh);
-                const float y = blk_process<W>(q[j], ysh, r0, ybits, backoff);
+                const float y = blk_process<W>(q[j], ysh, S, r0, ybits, backoff);
                 if constexpr (RZ) rz += (double)q[j].rr * (double)y;
             }
         }

@@ -59,7 +59,7 @@ enum Scal : int {
 // wave per block of `blk` consecutive rows, in-block dependencies through
 // LDS, `backoff` sleep rounds between polls of the others).
 struct TrsvCfg {
-    int mode = 0, waves = 0, backoff = 1, stride = 1, blk = 0;
+    int mode = 0, waves = 0, backoff = 1, stride = 1, blk = 0, runs = 1;
 };
 
 }  // namespace lpcg
@@ -97,6 +97,8 @@ struct lpcg_system {
     // (kern_sptrsv.h describes the arrays); blk_vsrc maps record values to
     // positions in the factor's value array
     int blk_B[2] = {0, 0}, blk_W[2] = {0, 0}, blk_nb[2] = {0, 0}, blk_chmax[2] = {0, 0};
+    // banded blocks: blk_K[d] runs of 2^blk_lsh[d] rows, blk_D[d] apart (K = 1: consecutive rows)
+    int blk_K[2] = {1, 1}, blk_lsh[2] = {30, 30}, blk_D[2] = {0, 0};
     int *blk_brow[2] = {nullptr, nullptr}, *blk_bch[2] = {nullptr, nullptr}, *blk_ch[2] = {nullptr, nullptr};
     int *blk_rec[2] = {nullptr, nullptr}, *blk_vsrc[2] = {nullptr, nullptr};
     // values (device)
@@ -169,8 +171,9 @@ int trsv_kernels(const lpcg_system *s, int transpose, const TrsvCfg &c, const fl
                  const float *rhs, float *y, int *ticket, hipStream_t st);
 int lo_prepare(const lpcg_system *s, int transpose, const float *lval, const float *utval, hipStream_t st);
 // Blocked mode: build (host, synchronous) the schedule of direction d for
-// block size B; pack one factor's values into its records; free it.
-int blk_prepare(lpcg_system *s, int d, int B);
+// block size B in K runs (K = 1: consecutive rows); pack one factor's values
+// into its records; free it.
+int blk_prepare(lpcg_system *s, int d, int B, int K = 1);
 int blk_pack(const lpcg_system *s, int d, const float *lval, const float *utval, hipStream_t st);
 void blk_free(lpcg_system *s, int d);
 }  // namespace lpcg

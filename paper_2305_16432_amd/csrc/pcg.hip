@@ -508,11 +508,11 @@ int run_solve(lpcg_system *s, const Args &a, const lpcg_solve_opts &o, int &iter
     hipGraphExec_t exec = nullptr;
     if (o.use_graph) {
         // key: kernel arguments + preconditioner kind + chunk length
-        std::vector<unsigned char> key(sizeof(Args) + 11 * sizeof(int));
+        std::vector<unsigned char> key(sizeof(Args) + 13 * sizeof(int));
         memcpy(key.data(), &a, sizeof(Args));
-        const int extra[11] = {KIND, chunk, s->trsv[0].mode, s->trsv[0].waves, s->trsv[0].backoff,
+        const int extra[13] = {KIND, chunk, s->trsv[0].mode, s->trsv[0].waves, s->trsv[0].backoff,
                                s->trsv[1].mode, s->trsv[1].waves, s->trsv[1].backoff, s->trsv_g,
-                               s->trsv[0].blk, s->trsv[1].blk};
+                               s->trsv[0].blk, s->trsv[1].blk, s->trsv[0].runs, s->trsv[1].runs};
         // (the block strides travel in Args and are part of the key through it)
         memcpy(key.data() + sizeof(Args), extra, sizeof(extra));
         if (s->graph_exec && s->graph_key == key) {
@@ -664,16 +664,17 @@ extern "C" int lpcg_pcg_solve(lpcg_system *s, const lpcg_precond *P, const doubl
             int rc = LPCG_OK;
             if (s->trsv[d].mode == 2) rc = lo_prepare(s, d, P->l_val, P->ut_val, st);
             if (s->trsv[d].mode == 3) {
-                if ((rc = blk_prepare(s, d, s->trsv[d].blk)) || (rc = blk_pack(s, d, P->l_val, P->ut_val, st)))
+                if ((rc = blk_prepare(s, d, s->trsv[d].blk, s->trsv[d].runs)) ||
+                    (rc = blk_pack(s, d, P->l_val, P->ut_val, st)))
                     return rc;
                 rc = blk_set_lds(s, d);
             }
             if (rc) return rc;
         }
         a.blk_f = BlkSched{s->blk_brow[0], s->blk_bch[0], reinterpret_cast<const int2 *>(s->blk_ch[0]),
-                           s->blk_rec[0], s->blk_nb[0], s->blk_B[0], s->blk_chmax[0]};
+                           s->blk_rec[0], s->blk_nb[0], s->blk_B[0], s->blk_chmax[0], s->blk_lsh[0], s->blk_D[0]};
         a.blk_b = BlkSched{s->blk_brow[1], s->blk_bch[1], reinterpret_cast<const int2 *>(s->blk_ch[1]),
-                           s->blk_rec[1], s->blk_nb[1], s->blk_B[1], s->blk_chmax[1]};
+                           s->blk_rec[1], s->blk_nb[1], s->blk_B[1], s->blk_chmax[1], s->blk_lsh[1], s->blk_D[1]};
     }
     if (P->kind == LPCG_PC_JACOBI && !P->dinv) {
         int rc = lpcg_jacobi(s, s->dinv, st);

@@ -351,11 +351,11 @@ int run_batch(lpcg_system *s, const BArgs &a, const lpcg_precond *P, const lpcg_
     const int chunk = o.check_every > 0 ? o.check_every : 8;
     hipGraphExec_t exec = nullptr;
     if (o.use_graph) {
-        std::vector<unsigned char> key(sizeof(BArgs) + 12 * sizeof(int) + 2 * sizeof(void *));
+        std::vector<unsigned char> key(sizeof(BArgs) + 14 * sizeof(int) + 2 * sizeof(void *));
         memcpy(key.data(), &a, sizeof(BArgs));
-        const int extra[12] = {KIND, chunk, s->trsv[0].mode, s->trsv[0].waves, s->trsv[0].backoff, s->trsv[0].stride,
+        const int extra[14] = {KIND, chunk, s->trsv[0].mode, s->trsv[0].waves, s->trsv[0].backoff, s->trsv[0].stride,
                                s->trsv[1].mode, s->trsv[1].waves, s->trsv[1].backoff, s->trsv[1].stride,
-                               s->trsv[0].blk, s->trsv[1].blk};
+                               s->trsv[0].blk, s->trsv[1].blk, s->trsv[0].runs, s->trsv[1].runs};
         memcpy(key.data() + sizeof(BArgs), extra, sizeof(extra));
         const void *vals[2] = {P->l_val, P->ut_val};
         memcpy(key.data() + sizeof(BArgs) + sizeof(extra), vals, sizeof(vals));
@@ -490,7 +490,7 @@ int prepare_precond(lpcg_system *s, const lpcg_precond *P, hipStream_t st) {
         for (int d = 0; d < 2; ++d) {
             int rc = LPCG_OK;
             if (s->trsv[d].mode == 2) rc = lo_prepare(s, d, P->l_val, P->ut_val, st);
-            if (s->trsv[d].mode == 3 && !(rc = blk_prepare(s, d, s->trsv[d].blk)))
+            if (s->trsv[d].mode == 3 && !(rc = blk_prepare(s, d, s->trsv[d].blk, s->trsv[d].runs)))
                 rc = blk_pack(s, d, P->l_val, P->ut_val, st);
             if (rc) return rc;
         }

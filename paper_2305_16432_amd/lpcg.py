@@ -58,13 +58,13 @@ class _Result(C.Structure):
 class _TrsvCfg(C.Structure):
     _fields_ = [("direction", C.c_int32), ("mode", C.c_int32), ("waves", C.c_int32),
                 ("backoff", C.c_int32), ("block_stride", C.c_int32), ("block_rows", C.c_int32),
-                ("us", C.c_double)]
+                ("us", C.c_double), ("block_runs", C.c_int32)]
 
 
 class _BlkSchedule(C.Structure):
     _fields_ = [("deps", C.c_int32), ("nblocks", C.c_int32), ("nchunks", C.c_int32), ("max_chunks", C.c_int32),
                 ("brow", C.c_void_p), ("bch", C.c_void_p), ("chunks", C.c_void_p), ("rec", C.c_void_p),
-                ("vsrc", C.c_void_p)]
+                ("vsrc", C.c_void_p), ("run_shift", C.c_int32), ("run_stride", C.c_int32)]
 
 
 class _Gnn(C.Structure):
@@ -225,14 +225,15 @@ def get_trsv_cfg(sys: System, direction: int) -> dict:
 
 
 def set_trsv_cfg(sys: System, direction: int, mode: int, waves: int = 0, backoff: int = 1,
-                 block_stride: int = 1, block_rows: int = 0):
-    c = _TrsvCfg(direction, mode, waves, backoff, block_stride, block_rows, 0.0)
+                 block_stride: int = 1, block_rows: int = 0, block_runs: int = 1):
+    c = _TrsvCfg(direction, mode, waves, backoff, block_stride, block_rows, 0.0, block_runs)
     _check(lib().lpcg_set_trsv_cfg(sys.handle, C.byref(c)), "lpcg_set_trsv_cfg")
 
 
-def blocked_schedule(rowptr, col, upper: bool, block_rows: int) -> dict:
+def blocked_schedule(rowptr, col, upper: bool, block_rows: int, block_runs: int = 1) -> dict:
     """Host schedule of the blocked substitution for a triangular CSR pattern
-    (lower: diagonal last; upper: diagonal first), as NumPy arrays."""
+    (lower: diagonal last; upper: diagonal first), as NumPy arrays; position x
+    of block b is row brow[b, 0] + (x >> run_shift) * run_stride + (x & (2^run_shift - 1))."""
     import numpy as np
     rp = np.ascontiguousarray(rowptr, dtype=np.int32)
     ci = np.ascontiguousarray(col, dtype=np.int32)
@@ -241,7 +242,7 @@ def blocked_schedule(rowptr, col, upper: bool, block_rows: int) -> dict:
     out = _BlkSchedule()
     f = L.lpcg_blocked_schedule
     args = (C.c_int32(n), rp.ctypes.data_as(C.c_void_p), ci.ctypes.data_as(C.c_void_p), C.c_int32(int(upper)),
-            C.c_int32(block_rows))
+            C.c_int32(block_rows), C.c_int32(block_runs))
     _check(f(*args, C.byref(out)), "lpcg_blocked_schedule")
     w = out.deps
     arrs = dict(brow=np.zeros(2 * out.nblocks, np.int32), bch=np.zeros(out.nblocks + 1, np.int32),
@@ -250,7 +251,8 @@ def blocked_schedule(rowptr, col, upper: bool, block_rows: int) -> dict:
     for k, a in arrs.items():
         setattr(out, k, a.ctypes.data_as(C.c_void_p))
     _check(f(*args, C.byref(out)), "lpcg_blocked_schedule")
-    arrs.update(deps=w, nblocks=out.nblocks, nchunks=out.nchunks, max_chunks=out.max_chunks)
+    arrs.update(deps=w, nblocks=out.nblocks, nchunks=out.nchunks, max_chunks=out.max_chunks,
+                run_shift=out.run_shift, run_stride=out.run_stride)
     arrs["brow"] = arrs["brow"].reshape(-1, 2)
     arrs["chunks"] = arrs["chunks"].reshape(-1, 2)
     arrs["rec"] = arrs["rec"].reshape(n, 2 * w + 2)

@@ -6,7 +6,8 @@ through vsrc, the diagonal) -- must reproduce the oracle's substitution bit
 for bit: both accumulate a row's entries in CSR order.  Structural checks:
 every row appears exactly once, chunks hold at most 64 rows of one block,
 an in-block dependency is produced in an earlier chunk of the same block, a
-global one in an earlier block."""
+global one in an earlier block.  Banded blocks (several runs of rows one
+stride apart) are checked the same way, through the schedule's position map."""
 import numpy as np
 import pytest
 
@@ -18,34 +19,41 @@ from tests.gpu_util import matrices_small
 
 def _emulate(S, n, vals, rhs):
     w = S["deps"]
+    lsh, D = S["run_shift"], S["run_stride"]
     y = np.full(n, np.nan)
     block_of = np.full(n, -1)
     chunk_of = np.full(n, -1)
     seen = np.zeros(n, np.int64)
     for b in range(S["nblocks"]):
         r0, nr = S["brow"][b]
-        block_of[r0:r0 + nr] = b
+
+        def at(x):  # row of position x of this block
+            return r0 + (x >> lsh) * D + (x & ((1 << lsh) - 1))
+        rows = [at(x) for x in range(nr)]
+        assert all(block_of[r] == -1 for r in rows) and rows == sorted(rows)
+        block_of[rows] = b
         for c in range(S["bch"][b], S["bch"][b + 1]):
             p0, cnt = S["chunks"][c]
             assert 1 <= cnt <= 64 and 0 <= p0 and p0 + cnt <= nr
             for p in range(p0, p0 + cnt):
-                rec = S["rec"][r0 + p]
-                row = r0 + rec[w]
-                assert r0 <= row < r0 + nr
+                rec = S["rec"][at(p)]
+                vs = S["vsrc"][at(p)]
+                assert 0 <= rec[w] < nr
+                row = at(rec[w])
                 seen[row] += 1
                 acc = rhs[row]
                 for t in range(w):
                     code = rec[t]
                     if code == -1:
-                        assert S["vsrc"][r0 + p][t] == -1
+                        assert vs[t] == -1
                         continue
-                    dep = code if code >= 0 else r0 + (-2 - code)
+                    dep = code if code >= 0 else at(-2 - code)
                     if code >= 0:
                         assert block_of[dep] != -1 and block_of[dep] < b, "global dependency not in an earlier block"
                     else:
                         assert chunk_of[dep] != -1 and chunk_of[dep] < c, "in-block dependency not in an earlier chunk"
-                    acc -= vals[S["vsrc"][r0 + p][t]] * y[dep]
-                y[row] = acc / vals[S["vsrc"][r0 + p][w]]
+                    acc -= vals[vs[t]] * y[dep]
+                y[row] = acc / vals[vs[w]]
                 chunk_of[row] = c
     assert np.all(seen == 1)
     return y
@@ -93,3 +101,65 @@ def test_schedule_rejects():
     for bad in (32, 1 << 17):
         with pytest.raises(lpcg.LpcgError):
             lpcg.blocked_schedule(pb.lrowptr, pb.lcol, False, bad)
+
+
+def _factor(A, seed=7):
+    pat = O.Pattern(A)
+    rng = np.random.default_rng(seed)
+    lval = rng.uniform(-0.3, 0.3, pat.nnz_l)
+    row = np.repeat(np.arange(A.n), np.diff(pat.lrowptr))
+    lval[pat.lcol == row] = rng.uniform(1.0, 2.0, (pat.lcol == row).sum())
+    return pat, lval, rng.standard_normal(A.n)
+
+
+@pytest.mark.parametrize("m,brows,runs", [(8, 64, 2), (8, 128, 2), (8, 128, 4), (8, 256, 4),
+                                          (16, 256, 4), (16, 512, 4), (16, 512, 8), (16, 1024, 4)])
+def test_banded_schedule_reproduces_substitution(m, brows, runs):
+    """Banded blocks on an m^3 grid (runs one plane, m^2 rows, apart): both
+    directions reproduce the oracle bit for bit, and every block is a band of
+    `runs` consecutive planes."""
+    A = g.poisson_grid(m, 3)
+    pat, lval, rhs = _factor(A)
+    for upper in (False, True):
+        rp, ci = (pat.urowptr, pat.ucol) if upper else (pat.lrowptr, pat.lcol)
+        vals = pat.upper_values(lval) if upper else lval
+        S = lpcg.blocked_schedule(rp, ci, upper, brows, runs)
+        assert S["run_stride"] == m * m and (1 << S["run_shift"]) == brows // runs
+        assert S["nblocks"] == A.n // brows
+        y = _emulate(S, A.n, vals, rhs)
+        ref = O.trsv_upper(pat, lval, rhs) if upper else O.trsv_lower(pat, lval, rhs)
+        np.testing.assert_array_equal(y, ref)
+
+
+def test_banded_schedule_level_count():
+    """A block of 4 planes x 4 y-rows x 16 x-rows of the 16^3 grid: its
+    in-block levels are x + y + z, 15 + 3 + 3 + 1 = 22, each one chunk."""
+    A = g.poisson_grid(16, 3)
+    pat = O.Pattern(A)
+    S = lpcg.blocked_schedule(pat.lrowptr, pat.lcol, False, 256, 4)
+    assert S["nblocks"] == 16
+    assert all(S["bch"][b + 1] - S["bch"][b] == 22 for b in range(16))
+
+
+def test_banded_schedule_rejects():
+    """Banded blocks that cannot tile the rows, or whose order would make a
+    block wait on a later one, are refused (EINVAL)."""
+    B = matrices_small()["heat3d_13"]  # plane of 169 rows: no power-of-two run divides it
+    pb = O.Pattern(B)
+    with pytest.raises(lpcg.LpcgError) as e:
+        lpcg.blocked_schedule(pb.lrowptr, pb.lcol, False, 256, 4)
+    assert e.value.code == lpcg.EINVAL
+    # n = 256, every row depends on rows r - 1 and r - 64 (stride 64, runs of
+    # 32): the first row of a run depends on the last row of the run before,
+    # which lies in that run's last band, a later block than band 0
+    rows, cols = [], []
+    for r in range(256):
+        for c in [c for c in (r - 64, r - 1) if c >= 0] + [r]:
+            rows.append(r)
+            cols.append(c)
+    rp = np.zeros(257, np.int32)
+    np.add.at(rp, np.asarray(rows) + 1, 1)
+    rp = np.cumsum(rp).astype(np.int32)
+    with pytest.raises(lpcg.LpcgError) as e:
+        lpcg.blocked_schedule(rp, np.asarray(cols, np.int32), False, 64, 2)
+    assert e.value.code == lpcg.EINVAL

@@ -205,3 +205,60 @@ def test_blocked_pcg_c3_full_size():
         assert res["status"] == 0 and O.true_relres(A, b, host(x)) <= 1e-6
         its[(mode, stride)] = res["iters"]
     assert abs(its[(3, 1)] - its[(0, 1)]) <= 1 and abs(its[(3, 8)] - its[(0, 1)]) <= 1, its
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("transpose", [0, 1])
+@pytest.mark.parametrize("brows,runs", [(2048, 2), (2048, 4), (2048, 8), (1024, 4)])
+def test_banded_c3_full_size(transpose, brows, runs):
+    """Banded blocks (runs of rows one 64^2-row plane apart) at 64^3 natural
+    order: bit-identical to the dependency-driven mode (both accumulate a
+    row's entries in CSR order) and to consecutive-row blocks."""
+    print(f"[banded] heat3d_64 transpose {transpose} rows {brows} runs {runs}", flush=True)
+    A, b = g.heat_system_3d(64, 1e-3, 1000, 2000)
+    S = gpu_system(A)
+    l, ut, _ = lpcg.ic0(S)
+    rhs = cuda_f32(b.astype(np.float32).astype(np.float64))
+    outs = {}
+    for key, (mode, br, k) in {"dep": (0, 0, 1), "blk": (3, brows, 1), "band": (3, brows, runs)}.items():
+        for d in (0, 1):
+            lpcg.set_trsv_cfg(S, d, mode, 0, 1 if mode == 0 else 0, 1, br, k)
+            got = lpcg.get_trsv_cfg(S, d)
+            assert got["block_runs"] == (k if mode == 3 else 0)
+        outs[key] = host(lpcg.sptrsv(S, transpose, l, ut, rhs))
+    assert np.array_equal(outs["band"].view(np.uint32), outs["dep"].view(np.uint32))
+    assert np.array_equal(outs["band"].view(np.uint32), outs["blk"].view(np.uint32))
+
+
+@pytest.mark.gpu
+def test_banded_pcg_c3_full_size():
+    """PCG at 64^3 with banded blocks in both directions (graph captured,
+    fused r.z in the backward solve): FP64 true residual, and iterations
+    within one of the dependency-driven and consecutive-block runs (the r.z
+    partials are summed per block, so the rounding of beta differs)."""
+    A, b = g.heat_system_3d(64, 1e-3, 1000, 2000)
+    S = gpu_system(A)
+    l, ut, _ = lpcg.ic0(S)
+    its = {}
+    for key, (mode, br, k) in {"dep": (0, 0, 1), "blk": (3, 2048, 1), "band": (3, 2048, 4)}.items():
+        for d in (0, 1):
+            lpcg.set_trsv_cfg(S, d, mode, 0, 1 if mode == 0 else 0, 1, br, k)
+        x, res = lpcg.pcg_solve(S, lpcg.PC_LLT, cuda_f64(b), l_val=l, ut_val=ut, tol=1e-6, max_restarts=2,
+                                use_graph=True)
+        assert res["status"] == 0 and O.true_relres(A, b, host(x)) <= 1e-6
+        its[key] = res["iters"]
+    assert abs(its["band"] - its["dep"]) <= 1 and abs(its["band"] - its["blk"]) <= 1, its
+
+
+@pytest.mark.gpu
+def test_banded_rejected_where_rows_do_not_tile():
+    """A 13^3 grid (plane of 169 rows) cannot be cut into banded blocks: the
+    configuration is refused and the previous one stays in force."""
+    A = matrices_small()["heat3d_13"]
+    S = gpu_system(A)
+    lpcg.set_trsv_cfg(S, 0, 3, 0, 0, 1, 256, 1)
+    with pytest.raises(lpcg.LpcgError) as e:
+        lpcg.set_trsv_cfg(S, 0, 3, 0, 0, 1, 256, 4)
+    assert e.value.code == lpcg.EINVAL
+    got = lpcg.get_trsv_cfg(S, 0)
+    assert got["mode"] == 3 and got["block_runs"] == 1
