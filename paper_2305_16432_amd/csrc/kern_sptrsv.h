@@ -315,22 +315,23 @@ static __global__ void k_lo_prep(int noff, int n, const int *__restrict__ src, c
 namespace lpcg {
 
 // ---------------------------------------------------------------------------
-// Blocked substitution (mode 3).  The rows are cut into blocks of B rows,
-// taken in solve order (ascending for L, descending for L^T); one wave owns a
-// block, blocks are handed out through a ticket in that order.  A block is
-// either B consecutive rows or, banded, K runs of B/K consecutive rows that
-// lie a fixed stride apart (the pattern's longest dependency, one grid plane
-// on a natural-order grid), so that several planes of a band share a wave and
-// their plane-to-plane dependencies stay in its LDS.  A host-built schedule lists a block's rows by their level inside
-// the block (longest path over in-block dependencies), in chunks of at most
-// 64 rows of one level.  The wave copies its block's records and right-hand
-// side into LDS once, then walks the chunks: in-block dependencies are read
-// from LDS; dependencies on rows of earlier blocks are polled from global
-// memory (the value is its own ready flag, as in the dependency-driven mode),
-// their loads issued kBlkDist chunks ahead in a register ring.  Every load of
-// the ring is unconditional (slots without such a dependency read entry 0 and
-// ignore it) so that the waits for one chunk leave the later chunks' loads in
-// flight.  Accumulation follows the row's CSR order, as in the other modes.
+// Blocked substitution (mode 3).  The rows are cut into blocks of B rows, taken
+// in solve order (ascending for L, descending for L^T); one wave owns a block,
+// blocks are handed out through a ticket in that order.  A block is either B
+// consecutive rows or, banded, K runs of B/K consecutive rows that lie a fixed
+// stride apart (the pattern's longest dependency, one grid plane on a
+// natural-order grid), so that several planes of a band share a wave and their
+// plane-to-plane dependencies stay in its LDS.  A host-built schedule lists a
+// block's rows by their level inside the block (longest path over in-block
+// dependencies), in chunks of at most 64 rows of one level.  The wave copies
+// its block's records and right-hand side into LDS once, then walks the
+// chunks: in-block dependencies are read from LDS; dependencies on rows of
+// earlier blocks are polled from global memory (the value is its own ready
+// flag, as in the dependency-driven mode), their loads issued kBlkDist chunks
+// ahead in a register ring.  Every load of the ring is unconditional (slots
+// without such a dependency read entry 0 and ignore it) so that the waits for
+// one chunk leave the later chunks' loads in flight.  Accumulation follows the
+// row's CSR order, as in the other modes.
 //
 // Record of a row (2W + 2 words, W = 3 or 7 dependencies at most): words
 // [0, W) dependency codes (>= 0: global row; -1: none; <= -2: in-block row
