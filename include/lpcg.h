@@ -209,8 +209,10 @@ int lpcg_time_spmv(const lpcg_system *sys, const float *x, float *y, int32_t rep
  * polling); mode 2: single workgroup (one block of 1024 threads walks every
  * level with block barriers, on a level-ordered copy of the factor that is
  * prepared once per factor; only for systems whose widest level has at most
- * 3072 rows).  A new system uses mode 1 when the direction has at most 16
- * levels, mode 0 with 4096 waves and backoff 1 otherwise. */
+ * 3072 rows); mode 3: blocked (one wave per block of rows, its in-block
+ * dependencies in LDS; block_rows, block_runs).  A new system uses mode 1
+ * when the direction has at most 16 levels, mode 0 with 4096 waves and
+ * backoff 1 otherwise. */
 typedef struct {
     int32_t direction;     /* 0: forward (L y = r), 1: backward (L^T z = y) */
     int32_t mode;          /* 0 dependency driven, 1 level synchronous, 2 single workgroup,
@@ -282,8 +284,11 @@ int lpcg_blocked_schedule(int32_t n, const int32_t *rowptr, const int32_t *col, 
 
 /* Autotuner: times every candidate configuration of both substitution
  * directions on this system with the given factor (reps timed runs after
- * one warm-up, HIP events on `stream`), keeps the fastest per direction for
- * every later call on the system, and writes up to table_len measured
+ * one warm-up, HIP events on `stream`): levels (few levels only), single
+ * workgroup (narrow levels only), blocked with 512, 1024, 2048 consecutive
+ * rows and banded with 1024, 2048 rows in 2, 4, 8 runs (where the rows
+ * tile), and dependency driven with 64 .. 4096 waves.  It keeps the fastest
+ * per direction for every later call on the system, and writes up to table_len measured
  * candidates to table (HOST, may be NULL) and their number to *n_table
  * (HOST, may be NULL).  Uses the system's work vectors: not concurrent with
  * a solve on the same system.  Synchronous. */
@@ -292,8 +297,9 @@ int lpcg_autotune(lpcg_system *sys, const float *l_val, const float *ut_val, int
 
 /* Read / force the configuration of one direction (HOST struct; `us` is
  * ignored).  Errors: EINVAL for an unknown direction, mode, a backoff outside
- * 0..64, a block_stride other than 0, 1, 2, 4, 8, or mode 2 on a system with
- * a level wider than 3072 rows. */
+ * 0..64, a block_stride other than 0, 1, 2, 4, 8, mode 2 on a system with
+ * a level wider than 3072 rows, or a mode-3 block shape the pattern does not
+ * allow (the previous configuration then stays in force). */
 int lpcg_get_trsv_cfg(const lpcg_system *sys, int32_t direction, lpcg_trsv_cfg *out);
 int lpcg_set_trsv_cfg(lpcg_system *sys, const lpcg_trsv_cfg *cfg);
 
