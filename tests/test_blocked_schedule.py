@@ -181,3 +181,62 @@ def test_banded_schedule_on_a_batch(brows, runs):
         y = _emulate(S, B.n, vals, rhs)
         ref = O.trsv_upper(pat, lval, rhs) if upper else O.trsv_lower(pat, lval, rhs)
         np.testing.assert_array_equal(y, ref)
+
+
+def _tri_solve(rp, ci, vals, rhs, upper):
+    """Row-by-row substitution in CSR order (the definition), FP64."""
+    n = len(rp) - 1
+    y = np.zeros(n)
+    for r in (range(n - 1, -1, -1) if upper else range(n)):
+        acc, dg = rhs[r], None
+        for k in range(rp[r], rp[r + 1]):
+            if ci[k] == r:
+                dg = vals[k]
+            else:
+                acc -= vals[k] * y[ci[k]]
+        y[r] = acc / dg
+    return y
+
+
+def test_banded_schedules_of_random_patterns():
+    """Random lower patterns on 512 rows (each row depends on a random subset
+    of up to three offsets from a grid-like menu, the longest being 64) and
+    their transposes, with random block sizes and run counts: every schedule
+    the builder accepts keeps each cross-block dependency on an earlier
+    block (checked by the emulation) and reproduces the substitution bit for
+    bit; the ones it refuses are refused with EINVAL.  Both outcomes occur."""
+    rng = np.random.default_rng(2024)
+    n, menu = 512, [1, 2, 7, 8, 9, 56, 63, 64]
+    accepted = refused = 0
+    for case in range(24):
+        offs = rng.choice(menu, size=rng.integers(1, 4), replace=False)
+        offs = np.append(offs[offs != 64], 64)[-3:]  # the longest offset is 64
+        rows, cols = [], []
+        for r in range(n):
+            deps = sorted({r - int(o) for o in offs if r - int(o) >= 0 and rng.random() < 0.9})
+            rows += [r] * (len(deps) + 1)
+            cols += deps + [r]
+        rp = np.zeros(n + 1, np.int64)
+        np.add.at(rp, np.asarray(rows) + 1, 1)
+        rp = np.cumsum(rp)
+        ci = np.asarray(cols, np.int64)
+        vals = rng.uniform(-0.3, 0.3, len(ci))
+        vals[ci == np.asarray(rows)] = rng.uniform(1.0, 2.0, n)
+        rhs = rng.standard_normal(n)
+        import scipy.sparse as sp
+        L = sp.csr_matrix((vals, ci, rp), shape=(n, n))
+        U = L.T.tocsr()
+        U.sort_indices()
+        brows = int(rng.choice([64, 128, 256]))
+        runs = int(rng.choice([2, 4, 8]))
+        for upper, M in ((False, L), (True, U)):
+            try:
+                S = lpcg.blocked_schedule(M.indptr.astype(np.int32), M.indices.astype(np.int32), upper, brows, runs)
+            except lpcg.LpcgError as e:
+                assert e.code == lpcg.EINVAL
+                refused += 1
+                continue
+            accepted += 1
+            y = _emulate(S, n, M.data, rhs)
+            np.testing.assert_array_equal(y, _tri_solve(M.indptr, M.indices, M.data, rhs, upper))
+    assert accepted > 0 and refused > 0, (accepted, refused)
