@@ -1,11 +1,13 @@
 """GPU parity: the preconditioner GNN forward (BF16 MFMA, FP32 accumulation)
 against the FP64 oracle.
 
-Tolerance: the GPU rounds every GEMM operand to BF16 (8-bit mantissa,
-relative rounding 2^-9) through n_mp + 2 MLPs; with O(1) random weights the
-relative Frobenius error of the predicted L stays at the 1e-2 level, so the
-bar is 2e-2 relative Frobenius over all entries, and every diagonal entry
-must be positive and finite."""
+Bars (tests/parity_bars.py): the strictly lower entries, which are the
+network's decoded pair averages, and the diagonal are checked separately,
+each by relative Frobenius <= 2e-2 and entry by entry within 3e-2 of
+(|ref| + rms of the part); in diag_mode 1 the diagonal sqrt(A_ii) carries
+no network output and must match to two FP32 ulps.  The bars sit 2.3-5x
+above the error of a BF16 emulation of the same arithmetic
+(tests/bf16_emul.py).  Every diagonal entry must be positive and finite."""
 import numpy as np
 import pytest
 import torch
@@ -14,11 +16,10 @@ import oracle as O
 import pdegen as g
 from oracle import gnn as ognn
 from paper_2305_16432_amd import lpcg
+from tests import parity_bars as PB
 from tests.gpu_util import cuda_f64, gpu_system, host, matrices_small
 
 pytestmark = pytest.mark.gpu
-
-REL_TOL = 2e-2
 
 
 def _gpu_L(S, A, b, P, h, n_mp, diag_mode=0):
@@ -32,22 +33,20 @@ def _gpu_L(S, A, b, P, h, n_mp, diag_mode=0):
     return host(lv).astype(np.float64), host(ut).astype(np.float64)
 
 
-def _check(A, b, h, n_mp, seed, sys_rowptr=None, diag_mode=0):
+def _check(A, b, h, n_mp, seed, sys_rowptr=None, diag_mode=0, P=None):
     pat = O.Pattern(A)
-    P = g.init_gnn_params(h, n_mp, seed=seed)
+    if P is None:
+        P = g.init_gnn_params(h, n_mp, seed=seed)
     S = gpu_system(A, sys_rowptr)
     lg, ut = _gpu_L(S, A, b, P, h, n_mp, diag_mode)
     if sys_rowptr is None:
         ref, _ = ognn.forward(A, b, P, h, n_mp, rev=pat.rev, diag_mode=diag_mode)
     else:  # per-system normalisation: the oracle runs each block separately
         ref = _blockwise_ref(A, b, P, h, n_mp, sys_rowptr, pat, diag_mode)
-    rel = np.linalg.norm(lg - ref) / np.linalg.norm(ref)
-    row = np.repeat(np.arange(A.n), np.diff(pat.lrowptr))
-    diag = pat.lcol == row
-    assert np.all(np.isfinite(lg)) and np.all(lg[diag] > 0)
-    assert rel <= REL_TOL, rel
+    st = PB.check_factor(pat, lg, ref, diag_mode)
+    print("bars:", {k: f"{v:.2e}" for k, v in st.items()}, flush=True)
     np.testing.assert_array_equal(ut, lg[pat.usrc])
-    return rel
+    return st
 
 
 def _blockwise_ref(A, b, P, h, n_mp, srp, pat, diag_mode=0):
@@ -61,7 +60,7 @@ def _blockwise_ref(A, b, P, h, n_mp, srp, pat, diag_mode=0):
 
 
 @pytest.mark.parametrize("diag_mode", [0, 1, 2])
-@pytest.mark.parametrize("h,n_mp", [(32, 3), (64, 2)])
+@pytest.mark.parametrize("h,n_mp", [(32, 3), (64, 2), (64, 5)])
 @pytest.mark.parametrize("name", ["poisson2d_32", "heat3d_13", "fem_40", "random_777", "tridiag_1000",
                                   "one"])
 def test_gnn_forward_parity(name, h, n_mp, diag_mode):
@@ -84,8 +83,31 @@ def test_gnn_forward_batch_per_system_normalisation(diag_mode):
 def test_gnn_forward_c3_full_size(diag_mode):
     print(f"[gnn] heat3d_64 h=32 n_mp=3 diag_mode={diag_mode}", flush=True)
     A, b = g.heat_system_3d(64, 1e-3, 1000, 2000)
-    rel = _check(A, b, 32, 3, seed=11, diag_mode=diag_mode)
-    print(f"rel err {rel:.3e}")
+    _check(A, b, 32, 3, seed=11, diag_mode=diag_mode)
+
+
+@pytest.mark.parametrize("wfile", ["heat3d_h32_mp3_ft64.npz", "heat3d_h32_mp3.npz"])
+def test_gnn_forward_trained_c3_full_size(wfile):
+    """The shipped networks, whose decoded values vary from edge to edge, on
+    the full 64^3 benchmark system."""
+    import os
+    W = np.load(os.path.join(os.path.dirname(lpcg.__file__), "weights", wfile))
+    h, n_mp, dm = int(W["h"]), int(W["n_mp"]), int(W["diag_mode"])
+    P = {k: np.asarray(v, np.float64) for k, v in
+         lpcg.unpack_params(torch.as_tensor(W["params"].astype(np.float32)), h, n_mp).items()}
+    print(f"[gnn] heat3d_64 trained {wfile}", flush=True)
+    A, b = g.heat_system_3d(64, 1e-3, 1000, 2000)
+    _check(A, b, h, n_mp, seed=0, diag_mode=dm, P=P)
+
+
+@pytest.mark.parametrize("diag_mode", [0, 1])
+def test_gnn_forward_c1_full_size(diag_mode):
+    """The 2D FEM configuration: 128 x 128 jittered points (15,876 unknowns),
+    h = 64 with 5 message-passing layers (the appendix's depth for its 2D
+    problems), softplus diagonal (mode 0) and the fixed-diagonal form."""
+    print(f"[gnn] fem_128 h=64 n_mp=5 diag_mode={diag_mode}", flush=True)
+    A, b, _ = g.fem_p1_delaunay(128, 0, 1)
+    _check(A, b, 64, 5, seed=13, diag_mode=diag_mode)
 
 
 def test_gnn_zero_weights_closed_form():
@@ -120,3 +142,28 @@ def test_gnn_deterministic_and_workspace_check():
     with pytest.raises(lpcg.LpcgError) as e:
         lpcg.gnn_predict_L(S, params, 48, 3, cuda_f64(b), lpcg.gnn_workspace(S, 32, 3))
     assert e.value.code == lpcg.EINVAL
+
+
+def test_learned_pcg_c1_full_size():
+    """Learned-L PCG on the 2D FEM configuration (15,876 unknowns, h = 64,
+    five layers, fixed-diagonal form): the GPU's factor in the GPU's PCG and
+    the oracle's factor in the oracle's PCG reach 1e-6 in the same number of
+    iterations, give or take max(2, 10%), and the FP64 residual is met."""
+    print("[gnn] fem_128 learned-L PCG", flush=True)
+    A, b, _ = g.fem_p1_delaunay(128, 0, 1)
+    pat = O.Pattern(A)
+    h, n_mp, dm = 64, 5, 1
+    P = g.init_gnn_params(h, n_mp, seed=13)
+    S = gpu_system(A)
+    params = lpcg.pack_params(P, h, n_mp).cuda()
+    ws = lpcg.gnn_workspace(S, h, n_mp)
+    lv = torch.empty(pat.nnz_l, dtype=torch.float32, device="cuda")
+    ut = torch.empty_like(lv)
+    bd = cuda_f64(b)
+    lpcg.gnn_predict_L(S, params, h, n_mp, bd, ws, lv, ut, diag_mode=dm)
+    x, r = lpcg.pcg_solve(S, lpcg.PC_LLT, bd, l_val=lv, ut_val=ut, tol=1e-6, max_restarts=2)
+    lref, _ = ognn.forward(A, b, P, h, n_mp, rev=pat.rev, diag_mode=dm)
+    ro = O.pcg(A, b, O.PC_LLT, pat, lref, tol=1e-6)
+    print(f"iters gpu {r['iters']} oracle {ro['iters']}", flush=True)
+    assert r["status"] == 0 and O.true_relres(A, b, host(x)) <= 1e-6
+    assert abs(r["iters"] - ro["iters"]) <= max(2, 0.1 * ro["iters"])

@@ -3,13 +3,14 @@ starting guess x^0): the node decoder's forward, its loss and its place in
 the hand-written reverse mode, against the FP64 oracle.
 
 Tolerances: the head is an MLP of the same shape as the edge decoder on
-BF16-rounded latents, so its output carries the forward's 1e-2-level
-relative error and takes the same bar, 2e-2 relative norm over all nodes.
-The loss runs in FP64 on the FP32 head output and matches the oracle's
-formula on that same output to 1e-10 relative.  The reverse mode takes the
-whole-gradient bars of the network's backward (cosine >= 0.999, relative
-norm <= 0.05) and the per-tensor cosine >= 0.99 (0.98 for the two scalar-
-input encoder weights).  Its target is the solution A^-1 b, as in training:
+BF16-rounded latents, so its output takes the forward's bars
+(tests/parity_bars.py): relative norm <= 2e-2 over all nodes and, node by
+node, within 3e-2 of (|ref| + rms).  The loss runs in FP64 on the FP32 head
+output and matches the oracle's formula on that same output to 1e-10
+relative.  The reverse mode takes the network backward's bars: whole
+gradient cosine >= 0.999 and relative norm <= 0.05, and per tensor the
+relative error and 1 - cosine within 6 times those of a BF16 emulation on
+the same inputs (tests/bf16_emul.py).  Its target is the solution A^-1 b, as in training:
 with an independent random target the head's node gradients have random
 signs, so the bias and first-layer gradients (sums over all nodes) cancel
 down to their BF16 rounding noise, which measures nothing about the code.
@@ -22,11 +23,11 @@ import oracle as O
 import pdegen as g
 from oracle import gnn as ognn
 from paper_2305_16432_amd import lpcg
+from tests import bf16_emul as EMU
+from tests import parity_bars as PB
 from tests.gpu_util import cuda_f32, cuda_f64, gpu_system, host, matrices_small
 
 pytestmark = pytest.mark.gpu
-
-REL_TOL = 2e-2
 
 
 def _x0(S, P, h, n_mp, b, diag_mode=1):
@@ -47,9 +48,7 @@ def test_x0_forward_parity(name, h, n_mp):
     S = gpu_system(A)
     lg, x0 = _x0(S, P, h, n_mp, b)
     _, cache = ognn.forward(A, b, P, h, n_mp, diag_mode=1, x_head=True)
-    ref = cache["x0"]
-    rel = np.linalg.norm(x0 - ref) / np.linalg.norm(ref)
-    assert np.all(np.isfinite(x0)) and rel <= REL_TOL, rel
+    print("bars:", PB.check_vector(x0, cache["x0"]), flush=True)
     # L from the same launch equals the plain predictor's, bit for bit
     P_nohead = {k: v for k, v in P.items() if not k.startswith("xdec.")}
     params = lpcg.pack_params(P_nohead, h, n_mp).cuda()
@@ -78,7 +77,7 @@ def test_x0_colour_order_is_original_numbering():
     _, xc = _x0(gpu_system(A, ordering=lpcg.ORDER_COLOR), P, 32, 3, b)
     _, cache = ognn.forward(A, b, P, 32, 3, diag_mode=1, x_head=True)
     for x in (xn, xc):
-        assert np.linalg.norm(x - cache["x0"]) / np.linalg.norm(cache["x0"]) <= REL_TOL
+        PB.check_vector(x, cache["x0"])
 
 
 def test_x0_batch_per_system_scaling():
@@ -91,8 +90,7 @@ def test_x0_batch_per_system_scaling():
     for s, m in enumerate(mats):
         r0, r1 = srp[s], srp[s + 1]
         _, cache = ognn.forward(m, b[r0:r1], P, 32, 2, diag_mode=1, x_head=True)
-        ref = cache["x0"]
-        assert np.linalg.norm(x0[r0:r1] - ref) / np.linalg.norm(ref) <= REL_TOL, s
+        PB.check_vector(x0[r0:r1], cache["x0"], f"x0 of system {s}")
 
 
 def test_x0_loss_parity_and_errors():
@@ -148,22 +146,10 @@ def test_x0_backward_parity(name, h, n_mp, with_l):
     _, gx = ognn.x0_loss(A, b, x, cache["xhat"])
     R = ognn.backward(P, cache, gl.astype(np.float64), w * gx)
     names = [k for k, _ in lpcg.param_layout(h, n_mp, True)]
-    fa = np.concatenate([np.asarray(G[k], np.float64).ravel() for k in names])
-    fr = np.concatenate([R[k].ravel() for k in names])
-    cos_all = fa @ fr / (np.linalg.norm(fa) * np.linalg.norm(fr))
-    rel_all = np.linalg.norm(fa - fr) / np.linalg.norm(fr)
-    cosines = {}
-    for k in names:
-        a, r = np.asarray(G[k], np.float64).ravel(), R[k].ravel()
-        if np.linalg.norm(r) == 0:  # the edge decoder without an L gradient
-            assert np.linalg.norm(a) <= 1e-6, k
-            continue
-        cosines[k] = a @ r / (np.linalg.norm(a) * np.linalg.norm(r) + 1e-300)
-    print(f"whole gradient cos {cos_all:.6f} rel {rel_all:.4f}")
-    print(" ".join(f"{k}:{c:.4f}" for k, c in cosines.items()))
-    assert cos_all >= 0.999 and rel_all <= 0.05, (cos_all, rel_all)
-    for k, c in cosines.items():
-        assert c >= (0.98 if k in ("node_enc.W0", "edge_enc.W0") else 0.99), (k, c)
+    _, ce = EMU.forward(A, b, P, h, n_mp, pat.rev, diag_mode=1, keep=True, x_head=True)
+    Em = EMU.backward(P, ce, gl.astype(np.float64), w * gx)
+    print("bars", PB.check_grads({k: np.asarray(G[k], np.float64) for k in names}, R, Em, names),
+          flush=True)
 
 
 def test_backward_without_head_loss_matches_headless_network():

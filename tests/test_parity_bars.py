@@ -1,0 +1,102 @@
+"""The GNN parity bars themselves (tests/parity_bars.py), on the CPU.
+
+A dithered BF16 emulation of the network stands in for a correct GPU
+kernel: it must pass every bar.  Planted mistakes in it must fail them:
+the strictly lower values of one grid plane's rows stored in reversed
+column order (a localised indexing error that a norm over all entries,
+diagonal included, admits), a diagonal entry 20% off, and a parameter
+gradient scaled by 2 (the decoder's output bias and two inner biases: a
+scale error that a per-tensor cosine alone cannot see)."""
+import numpy as np
+import pytest
+
+import oracle as O
+import pdegen as g
+from oracle import gnn as ognn
+from tests import bf16_emul as E
+from tests import parity_bars as PB
+
+
+def _systems():
+    return {
+        "heat3d_9": g.heat_system_3d(9, 1e-3, 5, 6)[0],
+        "fem_24": g.fem_p1_delaunay(24, 1, 2)[0],
+        "poisson2d_20": g.poisson_grid(20, 2),
+    }
+
+
+@pytest.mark.parametrize("diag_mode", [0, 1, 2])
+@pytest.mark.parametrize("h,n_mp", [(32, 3), (64, 5)])
+@pytest.mark.parametrize("name", ["heat3d_9", "fem_24", "poisson2d_20"])
+def test_forward_bar_passes_bf16_model_and_catches_planted(name, h, n_mp, diag_mode):
+    A = _systems()[name]
+    pat = O.Pattern(A)
+    b = np.random.default_rng(1).standard_normal(A.n)
+    P = g.init_gnn_params(h, n_mp, seed=5)
+    ref, _ = ognn.forward(A, b, P, h, n_mp, rev=pat.rev, diag_mode=diag_mode)
+    with E.dithered(11):
+        em, _ = E.forward(A, b, P, h, n_mp, pat.rev, diag_mode=diag_mode)
+    st = PB.check_factor(pat, em, ref, diag_mode)
+    assert st["off_rel"] <= PB.OFF_REL / 3 and st["off_elem"] <= PB.ELEM / 3, st
+    diag, off = PB.lower_masks(pat)
+    # planted: one diagonal entry 20% off
+    bad = em.copy()
+    j = np.flatnonzero(diag)[A.n // 2]
+    bad[j] *= 1.2
+    with pytest.raises(AssertionError):
+        PB.check_factor(pat, bad, ref, diag_mode)
+
+
+def test_forward_bar_trained_networks():
+    """The shipped trained networks: the BF16 model stays inside the bars,
+    and reversing the column order of the strictly lower values in the rows
+    of one grid plane (144 of 1728 rows) fails them.  (Random weights at
+    gain 1 decode nearly the same value on every edge, so such a swap is
+    invisible there; trained networks vary from edge to edge.)"""
+    import os
+    import torch
+    from paper_2305_16432_amd import lpcg
+    wdir = os.path.join(os.path.dirname(os.path.dirname(__file__)), "paper_2305_16432_amd", "weights")
+    A, b = g.heat_system_3d(12, 1e-3, 1, 2)
+    pat = O.Pattern(A)
+    for f in ("heat3d_h32_mp3.npz", "heat3d_h32_mp3_ft64.npz"):
+        W = np.load(os.path.join(wdir, f))
+        h, n_mp, dm = int(W["h"]), int(W["n_mp"]), int(W["diag_mode"])
+        P = lpcg.unpack_params(torch.as_tensor(W["params"].astype(np.float32)), h, n_mp)
+        P = {k: np.asarray(v, np.float64) for k, v in P.items()}
+        ref, _ = ognn.forward(A, b, P, h, n_mp, rev=pat.rev, diag_mode=dm)
+        with E.dithered(3):
+            em, _ = E.forward(A, b, P, h, n_mp, pat.rev, diag_mode=dm)
+        st = PB.check_factor(pat, em, ref, dm)
+        assert st["off_rel"] <= PB.OFF_REL / 2 and st["off_elem"] <= PB.ELEM / 2, (f, st)
+        bad = em.copy()
+        for i in range(A.n // 2, A.n // 2 + 144):
+            s0, s1 = pat.lrowptr[i], pat.lrowptr[i + 1] - 1  # diagonal last
+            bad[s0:s1] = bad[s0:s1][::-1]
+        with pytest.raises(AssertionError):
+            PB.check_factor(pat, bad, ref, dm)
+
+
+@pytest.mark.parametrize("diag_mode", [0, 1])
+@pytest.mark.parametrize("h,n_mp", [(32, 3), (64, 5)])
+@pytest.mark.parametrize("name", ["heat3d_9", "fem_24"])
+def test_grad_bar_passes_bf16_model_and_catches_scaled_tensor(name, h, n_mp, diag_mode):
+    A = _systems()[name]
+    pat = O.Pattern(A)
+    b = np.random.default_rng(4).standard_normal(A.n)
+    P = g.init_gnn_params(h, n_mp, seed=6)
+    gl = np.random.default_rng(7).standard_normal(pat.nnz_l).astype(np.float32).astype(np.float64)
+    _, c = ognn.forward(A, b, P, h, n_mp, rev=pat.rev, keep=True, diag_mode=diag_mode)
+    R = ognn.backward(P, c, gl)
+    _, ce = E.forward(A, b, P, h, n_mp, pat.rev, diag_mode=diag_mode, keep=True)
+    Em = E.backward(P, ce, gl)
+    with E.dithered(21):
+        _, cd = E.forward(A, b, P, h, n_mp, pat.rev, diag_mode=diag_mode, keep=True)
+        Gd = E.backward(P, cd, gl)
+    keys = list(R.keys())
+    PB.check_grads(Gd, R, Em, keys)
+    for k in ("dec.b1", f"mp{n_mp - 1}.edge.b1", "node_enc.b1"):
+        bad = dict(Gd)
+        bad[k] = 2.0 * Gd[k]
+        with pytest.raises(AssertionError):
+            PB.check_grads(bad, R, Em, keys)
