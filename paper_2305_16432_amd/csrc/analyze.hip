@@ -840,8 +840,7 @@ extern "C" int lpcg_export_perm(const lpcg_system *s, int32_t *perm, hipStream_t
 
 extern "C" void lpcg_destroy(lpcg_system *s) {
     if (!s) return;
-    if (s->graph_exec) hipGraphExecDestroy(s->graph_exec);
-    if (s->bgraph_exec) hipGraphExecDestroy(s->bgraph_exec);
+    drop_graphs(s);
     if (s->cap_stream) hipStreamDestroy(s->cap_stream);
     for (int d = 0; d < 2; ++d) blk_free(s, d);
     for (void *p : s->allocs) hipFree(p);

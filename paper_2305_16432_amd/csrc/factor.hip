@@ -196,7 +196,23 @@ bool wg_mode_fits(const lpcg_system *s, int transpose) {
 // ---------------------------------------------------------------- mode 3
 constexpr size_t kBlkLdsMax = 144 * 1024;  // dynamic LDS of a blocked wave (160 KB per CU)
 
+// Cached PCG graphs hold the kernel arguments of their capture, blocked
+// schedules included: every change of a schedule or configuration drops them.
+void drop_graphs(lpcg_system *s) {
+    if (s->graph_exec) {
+        (void)hipGraphExecDestroy(s->graph_exec);
+        s->graph_exec = nullptr;
+    }
+    s->graph_key.clear();
+    if (s->bgraph_exec) {
+        (void)hipGraphExecDestroy(s->bgraph_exec);
+        s->bgraph_exec = nullptr;
+    }
+    s->bgraph_key.clear();
+}
+
 void blk_free(lpcg_system *s, int d) {
+    drop_graphs(s);
     for (int **p : {&s->blk_brow[d], &s->blk_bch[d], &s->blk_ch[d], &s->blk_rec[d], &s->blk_vsrc[d]}) {
         if (*p) (void)hipFree(*p);
         *p = nullptr;
@@ -796,16 +812,7 @@ extern "C" int lpcg_set_trsv_cfg(lpcg_system *s, const lpcg_trsv_cfg *cfg) {
     c.stride = cfg->block_stride > 0 ? cfg->block_stride : 1;
     c.blk = cfg->mode == 3 ? (cfg->block_rows > 0 ? cfg->block_rows : 1024) : 0;
     c.runs = cfg->mode == 3 && cfg->block_runs > 0 ? cfg->block_runs : 1;
-    if (s->graph_exec) {  // the cached PCG graph launches the old kernels
-        hipGraphExecDestroy(s->graph_exec);
-        s->graph_exec = nullptr;
-        s->graph_key.clear();
-    }
-    if (s->bgraph_exec) {
-        hipGraphExecDestroy(s->bgraph_exec);
-        s->bgraph_exec = nullptr;
-        s->bgraph_key.clear();
-    }
+    drop_graphs(s);  // the cached PCG graphs launch the old kernels
     return LPCG_OK;
 }
 
@@ -888,15 +895,6 @@ extern "C" int lpcg_autotune(lpcg_system *s, const float *l_val, const float *ut
         s->trsv[dir] = best_c;
     }
     if (n_table) *n_table = count;
-    if (s->graph_exec) {
-        hipGraphExecDestroy(s->graph_exec);
-        s->graph_exec = nullptr;
-        s->graph_key.clear();
-    }
-    if (s->bgraph_exec) {
-        hipGraphExecDestroy(s->bgraph_exec);
-        s->bgraph_exec = nullptr;
-        s->bgraph_key.clear();
-    }
+    drop_graphs(s);
     return LPCG_OK;
 }

@@ -176,4 +176,5 @@ int lo_prepare(const lpcg_system *s, int transpose, const float *lval, const flo
 int blk_prepare(lpcg_system *s, int d, int B, int K = 1);
 int blk_pack(const lpcg_system *s, int d, const float *lval, const float *utval, hipStream_t st);
 void blk_free(lpcg_system *s, int d);
+void drop_graphs(lpcg_system *s);
 }  // namespace lpcg

@@ -508,13 +508,16 @@ int run_solve(lpcg_system *s, const Args &a, const lpcg_solve_opts &o, int &iter
     hipGraphExec_t exec = nullptr;
     if (o.use_graph) {
         // key: kernel arguments + preconditioner kind + chunk length
-        std::vector<unsigned char> key(sizeof(Args) + 13 * sizeof(int));
+        std::vector<unsigned char> key(sizeof(Args) + 15 * sizeof(int) + 2 * sizeof(void *));
         memcpy(key.data(), &a, sizeof(Args));
-        const int extra[13] = {KIND, chunk, s->trsv[0].mode, s->trsv[0].waves, s->trsv[0].backoff,
+        const int extra[15] = {KIND, chunk, s->trsv[0].mode, s->trsv[0].waves, s->trsv[0].backoff,
                                s->trsv[1].mode, s->trsv[1].waves, s->trsv[1].backoff, s->trsv_g,
-                               s->trsv[0].blk, s->trsv[1].blk, s->trsv[0].runs, s->trsv[1].runs};
+                               s->trsv[0].blk, s->trsv[1].blk, s->trsv[0].runs, s->trsv[1].runs,
+                               s->blk_nb[0], s->blk_nb[1]};
         // (the block strides travel in Args and are part of the key through it)
         memcpy(key.data() + sizeof(Args), extra, sizeof(extra));
+        const void *sched[2] = {s->blk_rec[0], s->blk_rec[1]};  // blocked schedules in the graph
+        memcpy(key.data() + sizeof(Args) + sizeof(extra), sched, sizeof(sched));
         if (s->graph_exec && s->graph_key == key) {
             exec = s->graph_exec;
         } else {

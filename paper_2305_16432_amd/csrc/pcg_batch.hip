@@ -351,13 +351,16 @@ int run_batch(lpcg_system *s, const BArgs &a, const lpcg_precond *P, const lpcg_
     const int chunk = o.check_every > 0 ? o.check_every : 8;
     hipGraphExec_t exec = nullptr;
     if (o.use_graph) {
-        std::vector<unsigned char> key(sizeof(BArgs) + 14 * sizeof(int) + 2 * sizeof(void *));
+        // key: kernel arguments, configuration, factor and blocked-schedule
+        // arrays (the graph holds the pointers it was captured with)
+        std::vector<unsigned char> key(sizeof(BArgs) + 16 * sizeof(int) + 4 * sizeof(void *));
         memcpy(key.data(), &a, sizeof(BArgs));
-        const int extra[14] = {KIND, chunk, s->trsv[0].mode, s->trsv[0].waves, s->trsv[0].backoff, s->trsv[0].stride,
+        const int extra[16] = {KIND, chunk, s->trsv[0].mode, s->trsv[0].waves, s->trsv[0].backoff, s->trsv[0].stride,
                                s->trsv[1].mode, s->trsv[1].waves, s->trsv[1].backoff, s->trsv[1].stride,
-                               s->trsv[0].blk, s->trsv[1].blk, s->trsv[0].runs, s->trsv[1].runs};
+                               s->trsv[0].blk, s->trsv[1].blk, s->trsv[0].runs, s->trsv[1].runs,
+                               s->blk_nb[0], s->blk_nb[1]};
         memcpy(key.data() + sizeof(BArgs), extra, sizeof(extra));
-        const void *vals[2] = {P->l_val, P->ut_val};
+        const void *vals[4] = {P->l_val, P->ut_val, s->blk_rec[0], s->blk_rec[1]};
         memcpy(key.data() + sizeof(BArgs) + sizeof(extra), vals, sizeof(vals));
         if (s->bgraph_exec && s->bgraph_key == key) {
             exec = s->bgraph_exec;

@@ -187,34 +187,18 @@ def test_uneven_mixed_batch_ir():
         assert np.linalg.norm(xi - ro["x"]) <= 1e-6 * np.linalg.norm(ro["x"])
 
 
-def _gen(args):
-    from threadpoolctl import threadpool_limits
-
-    import pdegen as gg
-    seed, i, n = args
-    with threadpool_limits(1):
-        if i % 2 == 0:
-            side = max(4, int(round(np.sqrt(n))) + 2)
-            A, b, _ = gg.fem_p1_delaunay(side, k_seed=seed * 1000 + i, f_seed=seed * 1000 + i + 500)
-        else:
-            m = max(2, int(np.ceil(n ** (1.0 / 3.0))))
-            A, b = gg.heat_system_3d(m, 1e-3, k_seed=seed * 1000 + i, u0_seed=seed * 1000 + i + 500)
-    return A, b
-
-
 def test_c4_full_size_256_uneven_systems():
     """256 systems with sizes log-uniform in [2k, 200k] (half 2D FEM, half
     3D heat steps; the sizes and seeds of pdegen.mixed_batch(256, 2000,
     200000, seed=9)), one analysis, IC(0), FP64 refinement over the batched
     FP32 PCG to 1e-10: every system's FP64 residual, and four sampled systems
     against the oracle's FP64 IC(0)-PCG."""
-    import multiprocessing as mp
+    from tests.sysgen import mixed_batch
     seed, nsys = 9, 256
     rng = np.random.default_rng(seed)
     sizes = np.exp(rng.uniform(np.log(2000), np.log(200000), nsys))
     print(f"[c4] generating {nsys} systems, sum n ~ {int(sizes.sum())}", flush=True)
-    with mp.get_context("fork").Pool(16) as pool:
-        sysl = pool.map(_gen, [(seed, i, n) for i, n in enumerate(sizes)], chunksize=4)
+    sysl = mixed_batch(seed, sizes)
     mats = [A for A, _ in sysl]
     B, srp = g.block_diag_csr(mats)
     b = np.concatenate([bb for _, bb in sysl])
@@ -262,3 +246,27 @@ def test_batched_banded_substitution():
         assert res[i]["status"] == lpcg.OK and O.true_relres(A, b, xi) <= tol
         assert abs(res[i]["iters"] - res0[i]["iters"]) <= 1
         assert abs(res[i]["iters"] - it_ref) <= max(2, int(0.1 * it_ref)), (i, res[i]["iters"], it_ref)
+
+
+def test_graph_cache_follows_schedule_changes():
+    """A cached iteration graph holds the blocked schedule it was captured
+    with.  Switching the block shape rebuilds the schedule and must drop the
+    graph: solving again after each switch gives, bit for bit, what a fresh
+    system with that configuration gives."""
+    mats = [g.heat_system_3d(16, 1e-3, 50 + i, 60 + i)[0] for i in range(2)]
+    B, srp = g.block_diag_csr(mats)
+    b = np.random.default_rng(8).standard_normal(B.n)
+    cfgs = [(512, 4), (256, 2), (512, 4)]
+
+    def run(S, blk, runs):
+        for d in (0, 1):
+            lpcg.set_trsv_cfg(S, d, 3, 0, 0, 1, blk, runs)
+        x, res = _solve(S, "ic0", b, tol=1e-6, max_restarts=2, use_graph=True)
+        return host(x), [r["iters"] for r in res]
+
+    S = gpu_system(B, srp)
+    seen = [run(S, *c) for c in cfgs]
+    for c, (x, its) in zip(cfgs, seen):
+        xf, itf = run(gpu_system(B, srp), *c)
+        print(f"[graph cache] blocks {c}: iterations {its} (fresh system {itf})", flush=True)
+        assert its == itf and np.array_equal(x, xf)
