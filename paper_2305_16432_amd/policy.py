@@ -46,9 +46,13 @@ class LibraryBackend:
         self.L = lpcg
 
     def predict(self, S, net, b):
+        import torch
         L = self.L
         ws = L.gnn_workspace(S, net["h"], net["n_mp"])
-        return L.gnn_predict_L(S, net["params"], net["h"], net["n_mp"], b, ws,
+        nl = S.info["nnz_l"]
+        l_val = torch.empty(nl, dtype=torch.float32, device="cuda")
+        ut_val = torch.empty(nl, dtype=torch.float32, device="cuda")
+        return L.gnn_predict_L(S, net["params"], net["h"], net["n_mp"], b, ws, l_val, ut_val,
                                diag_mode=net.get("diag_mode", 0))
 
     def check(self, S, l_val):
