@@ -2,18 +2,25 @@
 hand-written backward, data loss and Adam kernels (paper: loss_Ab, Adam at
 lr 1e-3; training-setup appendix).
 
-Data: implicit-Euler heat steps on an m^3 grid (7-point, k = exp(GRF sigma=1,
-ell=0.1), dt = 1e-3, b = u0 a smooth GRF; --rhs white/mix use white-noise
-right-hand sides for all/every other system), k seeds 0..nsys-1 and u0 seeds
-10000+seed; the solution x of each system (the third member of the paper's
-(A, x, b) training tuples) comes from SciPy's CG to a 1e-12 relative
-residual.  Every system shares one sparsity pattern, so a batch of B
-systems is one block-diagonal pattern analysed once; each step swaps in the
-batch's values.  --ordering color trains for the multicolour row ordering
-(the factor then lives on tril(P A P^T)).  Held-out check: PCG iterations to 1e-6 with the predicted
-L on a 64^3 system with unseen seeds, every eval_every steps; the weights
-with the fewest held-out iterations are kept (early stop on held-out;
---head-only keeps the last weights, since L does not change).
+Data: (A, b, x) triples read from a file written by the FP64 oracle's
+triple generator (x from the oracle's PCG to a 1e-12 relative residual, the
+third member of the paper's (A, x, b) training tuples):
+  heat3d  implicit-Euler heat steps on an m^3 grid (7-point, k = exp(GRF
+          sigma=1, ell=0.1), dt = 1e-3, b = u0 a smooth GRF), k seeds
+          0..nsys-1; every system shares one pattern, so a batch of B
+          systems is one block-diagonal pattern analysed once and each step
+          swaps in the batch's values.
+  fem2d   P1 FEM systems on jittered Delaunay meshes (one pattern per
+          system): the systems are split once into fixed batches of B
+          (seeded shuffle), each batch's block-diagonal pattern is analysed
+          once, and each step trains on one batch.
+--ordering color trains for the multicolour row ordering (the factor then
+lives on tril(P A P^T)).  Held-out check: PCG iterations to 1e-6 with the
+predicted L on unseen systems of the family (heat3d: eval_m^3, k seeds
+5000+i, u0 seeds 6000+i; fem2d: the training mesh size, k seeds 5000+i, f
+seeds 6000+i), every eval_every steps; the weights with the fewest held-out
+iterations are kept (early stop on held-out; --head-only keeps the last
+weights, since L does not change).
 
 --x-head adds the initial-guess head (appendix comparing with a predicted
 starting guess x^0): a node decoder regressing x s / rms(b), trained with
@@ -21,20 +28,29 @@ the weighted loss sum_i (x^_i - x_i s / rms(b))^2 next to the data loss (or
 alone with --head-only, which updates only the head so L stays that of the
 --init network); the held-out PCG then starts from the predicted x0.
 
-    python -m paper_2305_16432_amd.train --out paper_2305_16432_amd/weights/heat3d_h32_mp3.npz
+    python -m oracle.triples --family heat3d --m 32 --nsys 1000 --out /tmp/heat3d_32.npz
+    python -m paper_2305_16432_amd.train --triples /tmp/heat3d_32.npz \
+        --out paper_2305_16432_amd/weights/heat3d_h32_mp3.npz
 
 Fine-tuning on the 64^3 size the network is evaluated at (400 systems, k
 seeds 0..399; held-out selection as above) gives the benchmark's network:
 
-    python -m paper_2305_16432_amd.train --m 64 --nsys 400 --batch 4 --lr 1e-4 --steps 3000 \
+    python -m oracle.triples --family heat3d --m 64 --nsys 400 --out /tmp/heat3d_64.npz
+    python -m paper_2305_16432_amd.train --triples /tmp/heat3d_64.npz --batch 4 --lr 1e-4 --steps 3000 \
         --init paper_2305_16432_amd/weights/heat3d_h32_mp3.npz \
         --out paper_2305_16432_amd/weights/heat3d_h32_mp3_ft64.npz
+
+The 2D FEM network (h = 64, five message-passing layers, softplus diagonal;
+1000 systems of a 128 x 128 jittered point grid, batch 32, Adam lr 1e-3):
+
+    python -m oracle.triples --family fem2d --side 128 --nsys 1000 --out /tmp/fem2d_128.npz
+    python -m paper_2305_16432_amd.train --triples /tmp/fem2d_128.npz --batch 32 --h 64 --n-mp 5 \
+        --diag-mode 0 --out paper_2305_16432_amd/weights/fem2d_h64_mp5.npz
 """
 from __future__ import annotations
 
 import argparse
 import json
-import multiprocessing as mp
 import os
 import sys
 import time
@@ -46,43 +62,30 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 
-def _make(args):
-    m, seed, rhs = args
-    import scipy.sparse.linalg as spla
-    from threadpoolctl import threadpool_limits
-
-    import pdegen as g
-    if rhs == "mix":  # alternate smooth and white right-hand sides
-        rhs = "grf" if seed % 2 == 0 else "white"
-    A, b = g.heat_system_3d(m, 1e-3, k_seed=seed, u0_seed=10000 + seed, rhs=rhs)
-    with threadpool_limits(1):  # one BLAS thread per worker process
-        x, info = spla.cg(A.to_scipy(), b, rtol=1e-12, maxiter=20 * A.n)
-    assert info == 0
-    return A.val.astype(np.float64), b, x
+def load_triples(path):
+    """The systems of a triples file: list of (rowptr, colind, val, b, x)
+    (NumPy), the family and its size parameter."""
+    z = np.load(path, allow_pickle=False)
+    srp, snp = z["sys_rowptr"], z["sys_nnzptr"]
+    rows = []
+    for s in range(len(srp) - 1):
+        lo, hi, a, c = int(srp[s]), int(srp[s + 1]), int(snp[s]), int(snp[s + 1])
+        rows.append((z["rowptr"][s + lo:s + 1 + hi], z["colind"][a:c], z["val"][a:c], z["b"][lo:hi],
+                     z["x"][lo:hi]))
+    return rows, str(z["family"]), int(z["size"])
 
 
-def make_dataset(m: int, nsys: int, workers: int, rhs: str = "grf"):
-    import pdegen as g
-    A0, _ = g.heat_system_3d(m, 1e-3, k_seed=0, u0_seed=10000)
-    out = []
-    # fork before any GPU context exists (the workers re-import nothing), with
-    # the BLAS thread pools limited so workers do not oversubscribe the cores
-    from threadpoolctl import threadpool_limits
-    with threadpool_limits(1), mp.get_context("fork").Pool(workers) as pool:
-        for i, o in enumerate(pool.imap(_make, [(m, s, rhs) for s in range(nsys)], chunksize=2)):
-            out.append(o)
-            if (i + 1) % 50 == 0:
-                print(f"[train] generated {i + 1}/{nsys} systems", flush=True)
-    vals = np.stack([o[0] for o in out])
-    bs = np.stack([o[1] for o in out])
-    xs = np.stack([o[2] for o in out])
-    return A0, vals, bs, xs
+def shared_pattern(rows):
+    r0 = rows[0]
+    return all(r[0].shape == r0[0].shape and r[1].shape == r0[1].shape and np.array_equal(r[0], r0[0])
+               and np.array_equal(r[1], r0[1]) for r in rows)
 
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--m", type=int, default=32)
-    ap.add_argument("--nsys", type=int, default=1000)
+    ap.add_argument("--triples", required=True,
+                    help="(A, b, x) training file written by python -m oracle.triples")
+    ap.add_argument("--nsys", type=int, default=0, help="use the first nsys systems of the file (0: all)")
     ap.add_argument("--batch", type=int, default=8)
     ap.add_argument("--steps", type=int, default=3000)
     ap.add_argument("--h", type=int, default=32)
@@ -92,8 +95,6 @@ def main():
     ap.add_argument("--ordering", choices=["natural", "color"], default="natural")
     ap.add_argument("--loss", choices=["data", "frobenius"], default="data",
                     help="data: ||L L^T x - b||^2 (equation loss_Ab); frobenius: ||L L^T - A||_F^2 (loss_A ablation)")
-    ap.add_argument("--rhs", choices=["grf", "white", "mix"], default="grf",
-                    help="training right-hand sides: smooth GRF states, white noise, or both")
     ap.add_argument("--x-head", action="store_true",
                     help="add the initial-guess head (node decoder regressing x); held-out PCG starts from its x0")
     ap.add_argument("--x-weight", type=float, default=1.0, help="weight of the head's loss")
@@ -103,10 +104,10 @@ def main():
                                                  "diag mode and ordering override the options")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--eval-every", type=int, default=100)
-    ap.add_argument("--eval-m", type=int, default=64)
+    ap.add_argument("--eval-m", type=int, default=64, help="heat3d: held-out grid side")
+    ap.add_argument("--eval-maxit", type=int, default=2000)
     ap.add_argument("--eval-systems", type=int, default=1,
                     help="held-out systems (k seeds 5000+i, u0 seeds 6000+i); selection uses their mean iterations")
-    ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--out", required=True)
     args = ap.parse_args()
     init = None
@@ -117,10 +118,14 @@ def main():
         args.ordering = "color" if int(z["ordering"]) == 1 else "natural"
     if args.head_only and not args.x_head:
         ap.error("--head-only needs --x-head")
-    print(f"[train] generating {args.nsys} systems of {args.m}^3 on {args.workers} workers", flush=True)
     t0 = time.time()
-    A0, vals, bs, xs = make_dataset(args.m, args.nsys, args.workers, args.rhs)
-    print(f"[train] dataset {args.nsys} x n={A0.n} in {time.time() - t0:.1f}s", flush=True)
+    rows, family, size = load_triples(args.triples)
+    if args.nsys:
+        rows = rows[:args.nsys]
+    args.nsys = len(rows)
+    shared = shared_pattern(rows)
+    print(f"[train] {args.nsys} {family} triples (size {size}, "
+          f"{'one shared pattern' if shared else 'one pattern per system'}) in {time.time() - t0:.1f}s", flush=True)
 
     import torch
 
@@ -128,19 +133,40 @@ def main():
     from paper_2305_16432_amd import lpcg
     print("[train] torch imported", flush=True)
     order = lpcg.ORDER_COLOR if args.ordering == "color" else lpcg.ORDER_NATURAL
-    B, srp = g.block_diag_csr([A0] * args.batch)
-    S = lpcg.analyze(torch.as_tensor(B.rowptr).cuda(), torch.as_tensor(B.colind).cuda(),
-                     torch.as_tensor(B.val).cuda(), srp, order)
-    dv = torch.as_tensor(vals).cuda()
-    db = torch.as_tensor(bs).cuda()
-    dx = torch.as_tensor(xs).cuda()
+
+    def batch_system(members):
+        mats = [g.CSR(len(rows[i][0]) - 1, rows[i][0], rows[i][1], rows[i][2]) for i in members]
+        B, srp = g.block_diag_csr(mats)
+        return lpcg.analyze(torch.as_tensor(B.rowptr).cuda(), torch.as_tensor(B.colind).cuda(),
+                            torch.as_tensor(B.val).cuda(), srp, order)
+
+    rng = np.random.default_rng(args.seed)
+    if shared:
+        # one analysed pattern; each step gathers the batch's values
+        S = batch_system(list(range(args.batch)))
+        systems = [S]
+        dv = torch.as_tensor(np.stack([r[2] for r in rows])).cuda()
+        db = torch.as_tensor(np.stack([r[3] for r in rows])).cuda()
+        dx = torch.as_tensor(np.stack([r[4] for r in rows])).cuda()
+    else:
+        # fixed batches (seeded shuffle), each analysed once
+        perm = rng.permutation(args.nsys)
+        groups = [perm[k:k + args.batch] for k in range(0, args.nsys - args.batch + 1, args.batch)]
+        systems, bvec, xvec = [], [], []
+        for gi, members in enumerate(groups):
+            systems.append(batch_system(members))
+            bvec.append(torch.as_tensor(np.concatenate([rows[i][3] for i in members])).cuda())
+            xvec.append(torch.as_tensor(np.concatenate([rows[i][4] for i in members])).cuda())
+        print(f"[train] {len(groups)} batches of {args.batch} systems analysed", flush=True)
+        S = max(systems, key=lambda q: q.info["nnz"])
     h, n_mp = args.h, args.n_mp
     dm = args.diag_mode
     xh = args.x_head
     P0 = g.init_gnn_params(h, n_mp, seed=args.seed, gain=1.0, x_head=xh)
-    if dm in (1, 2):  # decoder output layer zero: L' = I, i.e. training starts at Jacobi
-        P0["dec.W1"][:] = 0.0
-        P0["dec.b1"][:] = 0.0
+    # decoder output layer zero: training starts from a diagonal factor (modes
+    # 1 and 2: L' = I, i.e. Jacobi; mode 0: L = sqrt(s) ln(2) I, plain CG)
+    P0["dec.W1"][:] = 0.0
+    P0["dec.b1"][:] = 0.0
     if xh:  # head output zero: the first evaluation starts PCG from x0 = 0
         P0["xdec.W1"][:] = 0.0
         P0["xdec.b1"][:] = 0.0
@@ -152,19 +178,22 @@ def main():
         grad_mask = torch.zeros_like(params)
         grad_mask[lpcg.param_count(h, n_mp, False):] = 1.0
     m1, v1 = torch.zeros_like(params), torch.zeros_like(params)
-    ws = lpcg.gnn_workspace(S, h, n_mp, train=True)
+    ws = lpcg.gnn_workspace(S, h, n_mp, train=True)  # sized for the largest batch
 
     # held-out evaluation systems (unseen seeds, full size)
     held = []
     ric_its, rj_its = [], []
     for i in range(max(1, args.eval_systems)):
-        Ae, be = g.heat_system_3d(args.eval_m, 1e-3, k_seed=5000 + i, u0_seed=6000 + i)
+        if family == "heat3d":
+            Ae, be = g.heat_system_3d(args.eval_m, 1e-3, k_seed=5000 + i, u0_seed=6000 + i)
+        else:
+            Ae, be, _ = g.fem_p1_delaunay(size, k_seed=5000 + i, f_seed=6000 + i)
         Se = lpcg.analyze(torch.as_tensor(Ae.rowptr).cuda(), torch.as_tensor(Ae.colind).cuda(),
                           torch.as_tensor(Ae.val).cuda(), None, order)
         bed = torch.as_tensor(be).cuda()
         lic, uic, _ = lpcg.ic0(Se)
-        _, ric = lpcg.pcg_solve(Se, lpcg.PC_LLT, bed, l_val=lic, ut_val=uic, tol=1e-6, maxit=2000)
-        _, rj = lpcg.pcg_solve(Se, lpcg.PC_JACOBI, bed, tol=1e-6, maxit=2000)
+        _, ric = lpcg.pcg_solve(Se, lpcg.PC_LLT, bed, l_val=lic, ut_val=uic, tol=1e-6, maxit=args.eval_maxit)
+        _, rj = lpcg.pcg_solve(Se, lpcg.PC_JACOBI, bed, tol=1e-6, maxit=args.eval_maxit)
         ric_its.append(ric["iters"])
         rj_its.append(rj["iters"])
         held.append((Se, bed))
@@ -175,7 +204,7 @@ def main():
     ue = torch.empty(nl, dtype=torch.float32, device="cuda")
     ric = {"iters": float(np.mean(ric_its))}
     rj = {"iters": float(np.mean(rj_its))}
-    print(f"[train] held-out {len(held)} x {args.eval_m}^3 ({args.ordering} order, {Se.info['nlev_fwd']} levels): "
+    print(f"[train] held-out {len(held)} x n={Se.n} ({args.ordering} order, {Se.info['nlev_fwd']} levels): "
           f"IC(0) {ric_its} its, Jacobi {rj_its} its", flush=True)
 
     def evaluate(with_x0=xh, report=None):
@@ -188,7 +217,7 @@ def main():
             else:
                 lpcg.gnn_predict_L(Sk, params, h, n_mp, bk, wse, le, ue, diag_mode=dm)
             _, r, hist = lpcg.pcg_solve(Sk, lpcg.PC_LLT, bk, x=x0 if with_x0 else None, l_val=le, ut_val=ue,
-                                        tol=1e-6, maxit=2000, hist=True)
+                                        tol=1e-6, maxit=args.eval_maxit, hist=True)
             if report is not None and k == 0:  # first system: starting relative residual, then per tolerance
                 hh = hist.cpu().numpy()
                 report["start_relres"] = float(hh[0])
@@ -197,18 +226,20 @@ def main():
             its.append(r["iters"] if r["status"] == 0 else 10 ** 6)
         return float(np.mean(its)) if len(its) > 1 else its[0]
 
-    rng = np.random.default_rng(args.seed)
     log = {"loss": [], "eval": [], "ic0_iters": ric["iters"], "jacobi_iters": rj["iters"]}
     best = (evaluate(), 0, params.clone())
     log["eval"].append((0, best[0]))
     print(f"[train] step 0 held-out iters {best[0]}", flush=True)
-    nb = A0.nnz
     t0 = time.time()
     for step in range(1, args.steps + 1):
-        idx = torch.as_tensor(rng.choice(args.nsys, args.batch, replace=False)).cuda()
-        lpcg.update_values(S, dv[idx].reshape(-1).contiguous())
-        bb = db[idx].reshape(-1).contiguous()
-        xb = dx[idx].reshape(-1).contiguous()
+        if shared:
+            idx = torch.as_tensor(rng.choice(args.nsys, args.batch, replace=False)).cuda()
+            lpcg.update_values(S, dv[idx].reshape(-1).contiguous())
+            bb = db[idx].reshape(-1).contiguous()
+            xb = dx[idx].reshape(-1).contiguous()
+        else:
+            k = int(rng.integers(len(systems)))
+            S, bb, xb = systems[k], bvec[k], xvec[k]
         L = lpcg.gnn_forward_train(S, params, h, n_mp, bb, ws, diag_mode=dm)
         if args.loss == "data":
             loss, dl = lpcg.llt_loss(S, L, xb, bb)
@@ -233,7 +264,6 @@ def main():
                 best = (it, step, params.clone())
             print(f"[train] step {step} loss/system {log['loss'][-1][1]:.4g} held-out iters {it} "
                   f"(best {best[0]} @ {best[1]}) {time.time() - t0:.1f}s", flush=True)
-    del nb
     if xh:
         params.copy_(best[2])
         log["from_x0"], log["from_zero"] = {}, {}
