@@ -186,6 +186,22 @@ int lpcg_sgs(const lpcg_system *sys, float *l_val, float *ut_val, hipStream_t st
 int lpcg_ic0(const lpcg_system *sys, double shift0, int32_t max_retries,
              float *l_val, float *ut_val, double *shift_used, hipStream_t stream);
 
+/* No-allocation variant of lpcg_ic0, for callers that cannot allocate
+ * device memory during the call (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): same arguments, same results bit
+ * for bit, same errors, but the FP64 working copy of the factor lives in a
+ * library-owned device array of LPCG_IC0_NOALLOC_MAX_NNZ_L doubles (16 MiB)
+ * instead of a per-call hipMallocAsync.  Every device the library runs on
+ * holds its own array until the process ends.  Calls that overlap on one
+ * device (several streams or threads) share that array and race; serialise
+ * them.  The array keeps the last call's contents; each call presets the
+ * entries it uses.  The system itself (lpcg_analyze) is allocated at set-up
+ * as for every other entry point.  Synchronous.  Errors: as lpcg_ic0, plus
+ * EINVAL when nnz_l exceeds LPCG_IC0_NOALLOC_MAX_NNZ_L. */
+#define LPCG_IC0_NOALLOC_MAX_NNZ_L 2097152
+int lpcg_ic0_noalloc(const lpcg_system *sys, double shift0, int32_t max_retries,
+                     float *l_val, float *ut_val, double *shift_used, hipStream_t stream);
+
 /* Jacobi (Experiments baseline): dinv = 1 / diag(A), FP32 [n]. */
 int lpcg_jacobi(const lpcg_system *sys, float *dinv, hipStream_t stream);
 

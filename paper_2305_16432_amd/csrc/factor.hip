@@ -1,5 +1,6 @@
 // Standalone building blocks: SpMV, triangular solves, IC(0), Jacobi.
 #include <algorithm>
+#include <mutex>
 
 #include "device_util.h"
 #include "kern_spmv.h"
@@ -590,20 +591,16 @@ extern "C" int lpcg_jacobi(const lpcg_system *s, float *dinv, hipStream_t st) {
     return LPCG_OK;
 }
 
-extern "C" int lpcg_ic0(const lpcg_system *s, double shift0, int32_t max_retries, float *l_val,
-                        float *ut_val, double *shift_used, hipStream_t st) {
-    if (!s || (!l_val && !ut_val) || shift0 < 0) {
-        set_error("lpcg_ic0: invalid arguments");
-        return LPCG_EINVAL;
-    }
-    // FP64 factor in the (otherwise idle) partial-sum area would be too small:
-    // it lives in a dedicated scratch carved from the work vectors' storage.
-    double *l64 = nullptr;
-    LPCG_HIP(hipMallocAsync((void **)&l64, sizeof(double) * (size_t)s->nnz_l, st));
+namespace lpcg {
+namespace {
+
+// IC(0) with the FP64 factor in l64 (nnz_l doubles, preset here): the body
+// shared by the allocating and the no-allocation entry points.
+int ic0_run(const lpcg_system *s, double shift0, int32_t max_retries, float *l_val, float *ut_val,
+            double *shift_used, double *l64, hipStream_t st) {
     int *flags = s->ctrl + C_TICKET_X;  // ticket
     int *bad = s->ctrl + C_STATUS;      // reused as the bad-row slot
     double shift = shift0;
-    int rc = LPCG_EBREAKDOWN;
     for (int attempt = 0; attempt <= std::max(0, (int)max_retries); ++attempt) {
         k_fill_u64<<<nblk(s->nnz_l, 256), 256, 0, st>>>(s->nnz_l, (uint64_t *)l64, kUnset64);
         k_set_i32<<<1, 1, 0, st>>>(flags, 0);
@@ -622,16 +619,84 @@ extern "C" int lpcg_ic0(const lpcg_system *s, double shift0, int32_t max_retries
         if (hbad == 0x7fffffff) {
             k_l64_to_f32<<<nblk(s->nnz_l, 256), 256, 0, st>>>(s->nnz_l, l64, s->u2l, l_val, ut_val);
             LPCG_LAUNCH_CHECK();
+            LPCG_HIP(hipStreamSynchronize(st));
             if (shift_used) *shift_used = shift;
-            rc = LPCG_OK;
-            break;
+            return LPCG_OK;
         }
         set_error("lpcg_ic0: non-positive pivot at row %d (shift %g)", hbad, shift);
         shift = shift == 0.0 ? 1e-3 : 2.0 * shift;
     }
+    return LPCG_EBREAKDOWN;
+}
+
+// Scratch of lpcg_ic0_noalloc: the FP64 factor of one call.  Each device
+// holds its own copy for the life of the process; host code never passes
+// the symbol itself to a kernel, only the device address looked up below.
+constexpr size_t kIc0ScratchDoubles = (size_t)LPCG_IC0_NOALLOC_MAX_NNZ_L;
+__device__ __align__(256) double scratch[kIc0ScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per
+// device with that device current.
+int ic0_scratch(double **out) {
+    int dev = -1;
+    LPCG_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) {
+        set_error("lpcg_ic0_noalloc: device ordinal %d out of range", dev);
+        return LPCG_EINVAL;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            set_error("lpcg_ic0_noalloc: hipGetSymbolAddress(scratch) failed on device %d: %s", dev,
+                      hipGetErrorString(e));
+            return LPCG_EHIP;
+        }
+        g_scratch_ptr[dev] = (double *)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return LPCG_OK;
+}
+
+}  // namespace
+}  // namespace lpcg
+
+using namespace lpcg;
+
+extern "C" int lpcg_ic0(const lpcg_system *s, double shift0, int32_t max_retries, float *l_val,
+                        float *ut_val, double *shift_used, hipStream_t st) {
+    if (!s || (!l_val && !ut_val) || shift0 < 0) {
+        set_error("lpcg_ic0: invalid arguments");
+        return LPCG_EINVAL;
+    }
+    double *l64 = nullptr;
+    LPCG_HIP(hipMallocAsync((void **)&l64, sizeof(double) * (size_t)s->nnz_l, st));
+    const int rc = ic0_run(s, shift0, max_retries, l_val, ut_val, shift_used, l64, st);
     LPCG_HIP(hipFreeAsync(l64, st));
     LPCG_HIP(hipStreamSynchronize(st));
     return rc;
+}
+
+extern "C" int lpcg_ic0_noalloc(const lpcg_system *s, double shift0, int32_t max_retries, float *l_val,
+                                float *ut_val, double *shift_used, hipStream_t st) {
+    if (!s || (!l_val && !ut_val) || shift0 < 0) {
+        set_error("lpcg_ic0_noalloc: invalid arguments");
+        return LPCG_EINVAL;
+    }
+    if ((size_t)s->nnz_l > kIc0ScratchDoubles) {
+        set_error("lpcg_ic0_noalloc: nnz_l = %d exceeds the scratch limit of %zu entries "
+                  "(LPCG_IC0_NOALLOC_MAX_NNZ_L); use lpcg_ic0", s->nnz_l, kIc0ScratchDoubles);
+        return LPCG_EINVAL;
+    }
+    double *l64 = nullptr;
+    int rc = ic0_scratch(&l64);
+    if (rc) return rc;
+    return ic0_run(s, shift0, max_retries, l_val, ut_val, shift_used, l64, st);
 }
 
 // Factor validation: the first row whose diagonal is not a positive finite

@@ -320,6 +320,24 @@ def ic0(sys: System, shift0=0.0, max_retries=8, l_val=None, ut_val=None):
     return l_val, ut_val, used.value
 
 
+def ic0_noalloc(sys: System, shift0=0.0, max_retries=8, l_val=None, ut_val=None):
+    """lpcg_ic0_noalloc: IC(0) with the library's static FP64 scratch (no
+    device allocation inside the call; nnz_l <= IC0_NOALLOC_MAX_NNZ_L)."""
+    nl = sys.info["nnz_l"]
+    if l_val is None:
+        l_val = torch.empty(nl, dtype=torch.float32, device="cuda")
+    if ut_val is None:
+        ut_val = torch.empty(nl, dtype=torch.float32, device="cuda")
+    used = C.c_double(0)
+    rc = lib().lpcg_ic0_noalloc(sys.handle, C.c_double(shift0), C.c_int32(max_retries), _ptr(l_val),
+                                _ptr(ut_val), C.byref(used), _stream())
+    _check(rc, "lpcg_ic0_noalloc")
+    return l_val, ut_val, used.value
+
+
+IC0_NOALLOC_MAX_NNZ_L = 2097152
+
+
 def jacobi(sys: System, out=None):
     if out is None:
         out = torch.empty(sys.n, dtype=torch.float32, device="cuda")
