@@ -30,6 +30,12 @@ Readings where the paper is silent (each listed in the design notes):
     L'_ii = max(softplus(d_ii + ln(e - 1)), 1e-6) > 0 (equal to 1 at
     d_ii = 0), so L_ii = sqrt(A_ii) L'_ii and L_ij = sqrt(A_jj) (d_ij + d_ji)/2.
     Zero decoder output gives L' = I, i.e. P = diag(A), in modes 1 and 2.
+  * diag_mode 3 (a reading of the same L' D L'^T form in which the diagonal
+    is not predicted but completed): the strictly-lower entries as in mode 1,
+    L_ij = sqrt(A_jj) (d_ij + d_ji)/2, and
+    L_ii = sqrt(max(A_ii - sum_{j<i} L_ij^2, 1e-3 A_ii)), so that
+    diag(L L^T) = diag(A) wherever the floor is not reached.  On a red-black
+    ordering, decoded values d_ij = A_ij / A_jj reproduce IC(0) exactly.
 
 frobenius_loss: the loss_A ablation of the loss-function section, pinned by
 a dense computation, finite differences, zero at an exact Cholesky factor
@@ -46,6 +52,7 @@ import numpy as np
 
 SOFTPLUS_FLOOR = 1e-6
 DIAG_SHIFT = float(np.log(np.e - 1.0))  # softplus(DIAG_SHIFT) = 1
+COMPLETE_FLOOR = 1e-3  # mode 3: L_ii^2 >= 1e-3 A_ii
 
 
 def _relu(x):
@@ -143,17 +150,27 @@ def forward(A, b, P, h, n_mp, rev=None, keep=False, diag_mode=0, x_head=False):
     else:
         adiag = A.val[diag]                       # A_jj, j = 0..n-1
         colscale = np.sqrt(adiag[np.minimum(row, col)])  # sqrt(A_cc), cc = column of the lower entry
-        if diag_mode == 1:
+        if diag_mode in (1, 3):
             ldiag = np.sqrt(adiag[row])
         else:
             ldiag = colscale * np.maximum(_softplus(d + DIAG_SHIFT), SOFTPLUS_FLOOR)
         lfull = np.where(diag, ldiag, colscale * 0.5 * (d + d[rev]))
+        if diag_mode == 3:  # complete the diagonal: diag(L L^T) = diag(A)
+            strict = lower & ~diag
+            ssq = np.zeros(n)
+            np.add.at(ssq, row[strict], lfull[strict] ** 2)
+            rad = adiag - ssq
+            active = rad > COMPLETE_FLOOR * adiag       # the floor not reached
+            ldg = np.sqrt(np.where(active, rad, COMPLETE_FLOOR * adiag))
+            lfull = np.where(diag, ldg[row], lfull)
         lval = lfull[lower]
     cache = None
     if keep:
         cache = dict(row=row, col=col, rev=rev, s=s, rms=rms, d=d, lower=lower, diag=diag,
                      Vs=Vs, Es=Es, mlp=caches, n=n, h=h, n_mp=n_mp, diag_mode=diag_mode,
-                     colscale=colscale, xhat=xhat, x0=None if xhat is None else xhat * rms / s)
+                     colscale=colscale, xhat=xhat, x0=None if xhat is None else xhat * rms / s,
+                     lfull=lfull if diag_mode != 0 else None,
+                     active=active if diag_mode == 3 else None)
     return lval, cache
 
 
@@ -178,6 +195,17 @@ def backward(P, cache, glval, gxhat=None):
         # (mode 1) or sqrt(A_ii) max(softplus(d_ii + shift), floor) (mode 2)
         glhat = np.zeros(nnz)
         glhat[np.nonzero(lower)[0]] = np.asarray(glval, np.float64)
+        if cache["diag_mode"] == 3:
+            # L_ii = sqrt(A_ii - sum_j L_ij^2): dL_ii / dL_ij = -L_ij / L_ii
+            # for the strictly-lower entries of row i (0 at the floor)
+            lf = cache["lfull"]
+            gdiag = np.zeros(n)
+            gdiag[row[diag]] = glhat[diag]
+            strict = lower & ~diag
+            ldiag = np.zeros(n)
+            ldiag[row[diag]] = lf[diag]
+            act = cache["active"][row]
+            glhat = glhat + np.where(strict & act, -gdiag[row] * lf / ldiag[row], 0.0)
         if cache["diag_mode"] == 2:
             ds = d + DIAG_SHIFT
             gd += np.where(diag & (_softplus(ds) > SOFTPLUS_FLOOR),

@@ -161,6 +161,13 @@ def _torch_model(A, b, P, h, n_mp, diag_mode=0, x_head=False):
         diag = torch.clamp(torch.nn.functional.softplus(torch.diagonal(Dm)), min=1e-6)
         Lfull = torch.tril(Sym, -1) + torch.diag(diag)
         return torch.sqrt(s) * Lfull[row[lower], col[lower]], T
+    if diag_mode == 3:  # strictly lower as mode 1, diagonal completed
+        Ad = torch.as_tensor(A.to_dense()).diagonal()
+        Ls = torch.tril(Sym, -1) * torch.sqrt(Ad)[None, :]
+        rad = Ad - (Ls * Ls).sum(1)
+        ldg = torch.sqrt(torch.where(rad > 1e-3 * Ad, rad, 1e-3 * Ad))
+        Lfull = Ls + torch.diag(ldg)
+        return Lfull[row[lower], col[lower]], T
     if diag_mode == 1:
         dprime = torch.ones(A.n, dtype=torch.float64)
     else:
@@ -171,7 +178,7 @@ def _torch_model(A, b, P, h, n_mp, diag_mode=0, x_head=False):
     return Lfull[row[lower], col[lower]], T
 
 
-@pytest.mark.parametrize("mode", [0, 1, 2])
+@pytest.mark.parametrize("mode", [0, 1, 2, 3])
 def test_backward_matches_torch_autograd(mode):
     A = g.fem_p1_delaunay(8, 3, 4)[0]
     b = np.random.default_rng(11).standard_normal(A.n)
@@ -247,7 +254,7 @@ def test_diag_mode1_zero_weights_closed_form_and_jacobi_start(mode):
     np.testing.assert_allclose(r1["x"], r2["x"], rtol=1e-12, atol=1e-14)
 
 
-@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("mode", [1, 2, 3])
 def test_diag_mode1_backward_finite_differences_and_torch(mode):
     A = g.fem_p1_delaunay(8, 3, 4)[0]
     b = np.random.default_rng(11).standard_normal(A.n)
@@ -318,3 +325,33 @@ def test_x0_loss_zero_at_solution_and_gradient():
     eps = 1e-6
     fd = (gnn.x0_loss(A, b, x, xh + eps * v)[0] - gnn.x0_loss(A, b, x, xh - eps * v)[0]) / (2 * eps)
     assert abs(fd - gr @ v) <= 1e-7 * max(1.0, abs(fd))
+
+
+def test_diag_mode3_completed_diagonal():
+    """Mode 3: every row with its radicand above the floor has
+    (L L^T)_ii = A_ii (dense product, FP64); all-zero weights with decoder
+    bias c give L_ij = sqrt(A_jj) c and L_ii = sqrt(max(A_ii - c^2 sum_j A_jj,
+    1e-3 A_ii)), computed here from the dense matrix."""
+    A, b = g.heat_system_3d(5, 1e-3, k_seed=3, u0_seed=4)
+    pat = O.Pattern(A)
+    Ad = A.to_dense()
+    ad = np.diag(Ad)
+    row = np.repeat(np.arange(A.n), np.diff(pat.lrowptr))
+    P = g.init_gnn_params(8, 2, seed=21, gain=1.5)
+    lval, _ = gnn.forward(A, b, P, 8, 2, diag_mode=3)
+    Ld = np.zeros((A.n, A.n))
+    Ld[row, pat.lcol] = lval
+    strict = np.tril(Ld, -1)
+    rad = ad - (strict ** 2).sum(1)
+    act = rad > 1e-3 * ad
+    assert act.sum() > 0
+    np.testing.assert_allclose(np.diag(Ld @ Ld.T)[act], ad[act], rtol=1e-13)
+    np.testing.assert_allclose(np.diag(Ld)[~act], np.sqrt(1e-3 * ad[~act]), rtol=1e-14)
+    Z = g.init_gnn_params(8, 2, seed=1, zero=True)
+    c = float(Z["dec.b1"][0])
+    lz, _ = gnn.forward(A, b, Z, 8, 2, diag_mode=3)
+    offp = np.where(Ad != 0, 1.0, 0.0) * (np.arange(A.n)[:, None] > np.arange(A.n)[None, :])
+    Lz = offp * np.sqrt(ad)[None, :] * c
+    dz = np.sqrt(np.maximum(ad - (Lz ** 2).sum(1), 1e-3 * ad))
+    Lz += np.diag(dz)
+    np.testing.assert_allclose(lz, Lz[row, pat.lcol], rtol=1e-14, atol=1e-300)
