@@ -230,7 +230,8 @@ int lpcg_time_spmv(const lpcg_system *sys, const float *x, float *y, int32_t rep
  * when the direction has at most 16 levels, mode 0 with 4096 waves and
  * backoff 1 otherwise. */
 typedef struct {
-    int32_t direction;     /* 0: forward (L y = r), 1: backward (L^T z = y) */
+    int32_t direction;     /* 0: forward (L y = r), 1: backward (L^T z = y); 2 (autotune
+                              table only): the SpMV, mode = lanes per row, waves = blocks */
     int32_t mode;          /* 0 dependency driven, 1 level synchronous, 2 single workgroup,
                               3 blocked (one wave per block of block_rows rows, consecutive
                               or banded (block_runs); dependencies inside a block through
@@ -304,7 +305,11 @@ int lpcg_blocked_schedule(int32_t n, const int32_t *rowptr, const int32_t *col, 
  * workgroup (narrow levels only), blocked with 512, 1024, 2048 consecutive
  * rows and banded with 1024, 2048 rows in 2, 4, 8 runs (where the rows
  * tile), and dependency driven with 64 .. 4096 waves.  It keeps the fastest
- * per direction for every later call on the system, and writes up to table_len measured
+ * per direction for every later call on the system.  It then times the
+ * FP32 SpMV w = A p for G = 4, 8, 16, 32, 64 lanes per row (64 / G rows per
+ * wavefront) on grids of up to 512, 1024 and 2048 blocks and keeps the
+ * fastest for the PCG's product and lpcg_spmv; those table entries have
+ * direction 2, mode = G and waves = blocks.  It writes up to table_len measured
  * candidates to table (HOST, may be NULL) and their number to *n_table
  * (HOST, may be NULL).  Uses the system's work vectors: not concurrent with
  * a solve on the same system.  Synchronous. */
@@ -312,7 +317,9 @@ int lpcg_autotune(lpcg_system *sys, const float *l_val, const float *ut_val, int
                   lpcg_trsv_cfg *table, int32_t table_len, int32_t *n_table, hipStream_t stream);
 
 /* Read / force the configuration of one direction (HOST struct; `us` is
- * ignored).  Errors: EINVAL for an unknown direction, mode, a backoff outside
+ * ignored).  Direction 2 is the SpMV: mode = lanes per row (4, 8, 16, 32 or
+ * 64), waves = blocks of 256 threads (1 .. 2048).  Errors: EINVAL for an
+ * unknown direction, mode, a backoff outside
  * 0..64, a block_stride other than 0, 1, 2, 4, 8, mode 2 on a system with
  * a level wider than 3072 rows, or a mode-3 block shape the pattern does not
  * allow (the previous configuration then stays in force). */
@@ -417,7 +424,10 @@ typedef struct {
                               L_ii = sqrt(A_ii), L_ij = sqrt(A_jj) (d_ij + d_ji)/2;
                            2: the same form with a learned positive diagonal of L':
                               L_ii = sqrt(A_ii) max(softplus(d_ii + ln(e-1)), 1e-6),
-                              L_ij = sqrt(A_jj) (d_ij + d_ji)/2 */
+                              L_ij = sqrt(A_jj) (d_ij + d_ji)/2;
+                           3: L_ij as in 1, the diagonal completed so that
+                              diag(L L^T) = diag(A):
+                              L_ii = sqrt(max(A_ii - sum_{j<i} L_ij^2, 1e-3 A_ii)) */
     int32_t x_head;     /* 1: the network also carries the initial-guess head xdec (appendix
                            comparing with a predicted starting guess x^0), an MLP on the
                            final node latents; 0: no head */

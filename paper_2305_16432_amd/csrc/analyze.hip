@@ -588,6 +588,37 @@ int analyze_impl(const lpcg_csr *A, const int32_t *h_sys, int32_t nsys, lpcg_sys
     s->trsv_g = lmean <= 4 ? 4 : lmean <= 8 ? 8 : 16;
     s->trsv[0].mode = s->nlev_f <= kLevelModeMaxLevels ? 1 : 0;
     s->trsv[1].mode = s->nlev_b <= kLevelModeMaxLevels ? 1 : 0;
+    {  // row-aligned tiles of at most 32 entries for the network's fused pass
+        std::vector<int> hrp(n + 1), tiles(1, 0);
+        LPCG_HIP(hipMemcpyAsync(hrp.data(), s->rowptr, sizeof(int) * (n + 1), hipMemcpyDeviceToHost, st));
+        LPCG_HIP(hipStreamSynchronize(st));
+        bool ok = true;
+        for (int r = 0; r < n && ok;) {
+            int r1 = r;
+            while (r1 < n && hrp[r1 + 1] - hrp[r] <= 32) ++r1;
+            ok = r1 > r;
+            tiles.push_back(r1);
+            r = r1;
+        }
+        s->gtiles = 0;
+        if (ok) {
+            ALLOC(s->gtile_row, tiles.size());
+            LPCG_HIP(hipMemcpyAsync(s->gtile_row, tiles.data(), sizeof(int) * tiles.size(), hipMemcpyHostToDevice,
+                                    st));
+            LPCG_HIP(hipStreamSynchronize(st));
+            s->gtiles = (int)tiles.size() - 1;
+        }
+    }
+    s->two_level_p = 0;
+    if (s->nlev_f == 2 && s->h_flev_ptr.size() == 3 && s->h_flev_ptr[1] > 0) {
+        // level 0 lists its rows ascending: it is the prefix [0, p) exactly
+        // when its last row is p - 1
+        const int p = s->h_flev_ptr[1];
+        int last = -1;
+        LPCG_HIP(hipMemcpyAsync(&last, s->flev_rows + (p - 1), sizeof(int), hipMemcpyDeviceToHost, st));
+        LPCG_HIP(hipStreamSynchronize(st));
+        if (last == p - 1) s->two_level_p = p;
+    }
     // SpMV lanes per row from the mean row length
     const double mean = (double)nnz / n;
     s->spmv_group = mean <= 4 ? 4 : mean <= 8 ? 8 : mean <= 16 ? 16 : mean <= 32 ? 32 : 64;

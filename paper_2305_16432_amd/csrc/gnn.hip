@@ -56,13 +56,16 @@ GnnOff gnn_offsets(int h, int n_mp, bool x_head) {
 // buffers come first, at offsets common to both layouts.
 struct GnnWs {
     size_t sys_s, sys_rms, norm_part;
-    size_t V[kMaxMp + 1], Pa[kMaxMp], Pb[kMaxMp], E[kMaxMp + 1];
+    size_t V[kMaxMp + 1], Pa[kMaxMp], Pb[kMaxMp], E[kMaxMp + 1], M;
     size_t d, xhat, gxhat;
     // backward (train only)
     size_t gd, gE[2], gV[2], gVmlp, gm, GH, G1, GVN, GH1, H1, Mt, gPa, gPb, HD, GHD, Henc, GHenc, Xn, Xe;
     size_t wpart;
     size_t total;
 };
+
+// Layers the fused inference pass supports (its edge chain is unrolled).
+constexpr int kFusedMaxMp = 4;
 
 // Blocks of the weight-gradient kernels = number of per-block partial sums.
 constexpr int kWgradBlocks = 256;
@@ -76,8 +79,15 @@ int norm_segments(const lpcg_system *s) {
     return (mx + kNormRows - 1) / kNormRows;
 }
 
+// The fused inference pass (k_fused_edge): latent width 32, at most
+// kFusedMaxMp layers, and row-aligned edge tiles (no row above 32 entries).
+bool gnn_fused(const lpcg_system *s, int h, int n_mp, bool train) {
+    return !train && h == 32 && n_mp <= kFusedMaxMp && s->gtiles > 0;
+}
+
 GnnWs gnn_ws_layout(const lpcg_system *s, int h, int n_mp, bool train) {
     GnnWs w{};
+    const bool fused = gnn_fused(s, h, n_mp, train);
     size_t off = 0;
     auto take = [&](size_t bytes) {
         size_t o = off;
@@ -93,13 +103,15 @@ GnnWs gnn_ws_layout(const lpcg_system *s, int h, int n_mp, bool train) {
     w.xhat = take(4 * n);
     w.gxhat = take(4 * n);
     const int nv = train ? n_mp + 1 : 2;
-    const int np = train ? n_mp : 1;
+    const int np = train || fused ? n_mp : 1;
     for (int i = 0; i < nv; ++i) w.V[i] = take(2 * n * h);
     for (int i = 0; i < np; ++i) {
         w.Pa[i] = take(2 * n * h);
         w.Pb[i] = take(2 * n * h);
     }
-    for (int i = 0; i < nv; ++i) w.E[i] = take(2 * nnz * h);
+    if (fused) w.M = take(2 * n * h);  // aggregated messages, BF16
+    else
+        for (int i = 0; i < nv; ++i) w.E[i] = take(2 * nnz * h);
     w.d = take(4 * nnz);
     if (train) {
         w.gd = take(4 * nnz);
@@ -407,10 +419,278 @@ __global__ void __launch_bounds__(kGnnThreads) k_edge(int nnz, const int *__rest
     }
 }
 
+// ---------------------------------------------------------------------------
+// Fused inference pass (latent width 32).  The edge latents are never stored:
+// E_t[e] is recomputed from the edge input A_e/s through the encoder and the
+// chain of edge MLPs 0..t-1, whose node terms (V_u W_a)[row] and
+// (V_u W_b)[col] come from the per-layer projections the node passes keep.
+// Message-passing pass t computes, per row-aligned tile of at most 32
+// entries, the messages E_t[e] * V_t[col e] and their row sums m_i in CSR
+// order (through LDS); the node pass then needs only V_t and m.  The last
+// pass runs the whole chain and the decoder.  Edge MLP evaluations grow from
+// n_mp to n_mp (n_mp + 1) / 2, but no edge latent crosses HBM.  Rounding
+// points are those of the stored form: E_t enters each product as BF16, the
+// message sum runs in FP32 in CSR order and m enters the node MLP as BF16.
+struct FusedChain {
+    MlpOff edge[kFusedMaxMp];
+    const __bf16 *pa[kFusedMaxMp];
+    const __bf16 *pb[kFusedMaxMp];
+};
+
+template <int CH, bool DEC>
+__global__ void __launch_bounds__(kGnnThreads) k_fused_edge(
+    int nnz, int ntiles, const int *__restrict__ tile_row, const int *__restrict__ rowptr,
+    const int *__restrict__ erow, const int *__restrict__ col, const double *__restrict__ aval,
+    const int *__restrict__ row_sys, const double *__restrict__ sys_s, const float *__restrict__ P, MlpOff enc,
+    FusedChain ch, MlpOff md, const __bf16 *__restrict__ V, __bf16 *__restrict__ M, float *__restrict__ d,
+    int zero) {
+    constexpr int H = 32, S = H / 16;
+    constexpr int NW = CH > 0 ? CH : 1;
+    // FP32 constants: encoder W0, b0, b1; b0, b1 of each chain layer; decoder
+    // b0, W1 (a column), b1
+    constexpr int C_ENC = 0, C_CH = 3 * H, C_DEC = C_CH + 2 * H * CH, NC = C_DEC + 2 * H + 1;
+    __shared__ __bf16 wenc[H * H];
+    __shared__ __bf16 we[NW][H * H], w1[NW][H * H];
+    __shared__ __bf16 wd[DEC ? H * H : 1];
+    __shared__ float cst[NC];
+    __shared__ float msg[DEC ? 1 : kGnnThreads / kWave][DEC ? 1 : 32][H + 1];
+    stage_weights<false>(wenc, P + enc.W1, H, H, H);
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+        stage_weights<true>(we[u], P + ch.edge[u].W0, H, H, H);
+        stage_weights<true>(w1[u], P + ch.edge[u].W1, H, H, H);
+    }
+    if (DEC) stage_weights<true>(wd, P + md.W0, H, H, H);
+    for (int i = threadIdx.x; i < NC; i += blockDim.x) {
+        float v;
+        if (i < C_CH) v = P[(i < H ? enc.W0 : i < 2 * H ? enc.b0 - H : enc.b1 - 2 * H) + i];
+        else if (i < C_DEC) {
+            const int u = (i - C_CH) / (2 * H), k = (i - C_CH) % (2 * H);
+            v = k < H ? P[ch.edge[u].b0 + k] : P[ch.edge[u].b1 + k - H];
+        } else {
+            const int k = i - C_DEC;
+            v = DEC ? (k < H ? P[md.b0 + k] : k < 2 * H ? P[md.W1 + k - H] : P[md.b1]) : 0.f;
+        }
+        cst[i] = v;
+    }
+    __syncthreads();
+    const int lane = lane_id(), wv = threadIdx.x / kWave;
+    const int tiles = DEC ? (nnz + 31) / 32 : ntiles;
+    for (int tile = blockIdx.x * 4 + wv; tile < tiles; tile += gridDim.x * 4) {
+        // `zero` is 0 at run time; the compiler cannot prove it, so the weight
+        // operands and constants below are re-read from LDS in every tile
+        // rather than hoisted into registers for the whole loop (over a
+        // hundred registers for a three-layer chain, one wave per SIMD)
+        const int z = zero * tile;
+        const float *C = cst + z;
+        int e, e_end, e0 = 0, r0 = 0, r1 = 0;
+        if (DEC) {
+            e = tile * 32 + (lane & 31);
+            e_end = nnz;
+        } else {
+            r0 = tile_row[tile];
+            r1 = tile_row[tile + 1];
+            e0 = rowptr[r0];
+            e = e0 + (lane & 31);
+            e_end = rowptr[r1];
+        }
+        const bool valid = e < e_end;
+        const int r = valid ? erow[e] : 0, c = valid ? col[e] : 0;
+        // encoder: E_0 = relu(x W0 + b0) W1 + b1, x = A_e / s
+        const float x = valid ? (float)(aval[e] / sys_s[row_sys[r]]) : 0.f;
+        f32x16 acc[1];
+        acc[0] = zero16();
+#pragma unroll
+        for (int st = 0; st < S; ++st) {
+            bf16x8 b;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int k = k_nat(st, j, lane);
+                b[j] = (__bf16)fmaxf(x * C[C_ENC + k] + C[C_ENC + H + k], 0.f);
+            }
+            acc[0] = mfma(lds_op(wenc + z, S, 0, st, lane), b, acc[0]);
+        }
+        add_bias<1>(acc, C + C_ENC + 2 * H, lane, false);
+        // edge MLPs 0..CH-1 through the factored first layer
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+            f32x16 hid[1];
+            hid[0] = zero16();
+#pragma unroll
+            for (int st = 0; st < S; ++st)
+                hid[0] = mfma(lds_op(we[u] + z, S, 0, st, lane), acc_operand<1>(acc, st), hid[0]);
+            const float *b0 = C + C_CH + 2 * H * u;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int f = acc_feat(0, 4 * q, lane);
+                bf16x4 ga, gb;
+                if (valid) {
+                    ga = *reinterpret_cast<const bf16x4 *>(ch.pa[u] + (size_t)r * H + f);
+                    gb = *reinterpret_cast<const bf16x4 *>(ch.pb[u] + (size_t)c * H + f);
+                }
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const float add = valid ? (float)ga[t] + (float)gb[t] : 0.f;
+                    hid[0][4 * q + t] = fmaxf(hid[0][4 * q + t] + add + b0[f + t], 0.f);
+                }
+            }
+            f32x16 out[1];
+            out[0] = zero16();
+#pragma unroll
+            for (int st = 0; st < S; ++st)
+                out[0] = mfma(lds_op(w1[u] + z, S, 0, st, lane), acc_operand<1>(hid, st), out[0]);
+            add_bias<1>(out, C + C_CH + 2 * H * u + H, lane, false);
+            acc[0] = out[0];
+        }
+        if (DEC) {
+            // decoder d = relu(E W0 + b0) w1 + b1 (one scalar per edge)
+            f32x16 hd[1];
+            hd[0] = zero16();
+#pragma unroll
+            for (int st = 0; st < S; ++st) hd[0] = mfma(lds_op(wd + z, S, 0, st, lane), acc_operand<1>(acc, st), hd[0]);
+            add_bias<1>(hd, C + C_DEC, lane, true);
+            float part = 0.f;
+#pragma unroll
+            for (int i = 0; i < 16; ++i) part += hd[0][i] * C[C_DEC + H + acc_feat(0, i, lane)];
+            part += __shfl_xor(part, 32, kWave);
+            if (valid && lane < 32) d[e] = part + C[C_DEC + 2 * H];
+        } else {
+            // messages E_t[e] * V_t[col e] (E_t rounded to BF16 as when stored)
+            float(*mw)[H + 1] = msg[wv];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int f = acc_feat(0, 4 * q, lane);
+                bf16x4 v4;
+                if (valid) v4 = *reinterpret_cast<const bf16x4 *>(V + (size_t)c * H + f);
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+                    mw[lane & 31][f + t] = valid ? (float)(__bf16)acc[0][4 * q + t] * (float)v4[t] : 0.f;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            // row sums in CSR order: lane l sums 16 features (half l / 32) of
+            // row r0 + l % 32
+            const int rr = lane & 31, fh = (lane >> 5) * 16;
+            if (r0 + rr < r1) {
+                const int ka = rowptr[r0 + rr] - e0, kb = rowptr[r0 + rr + 1] - e0;
+                float sum[16];
+#pragma unroll
+                for (int j = 0; j < 16; ++j) sum[j] = 0.f;
+                for (int k = ka; k < kb; ++k)
+#pragma unroll
+                    for (int j = 0; j < 16; ++j) sum[j] += mw[k][fh + j];
+                bf16x8 lo, hi;
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    lo[j] = (__bf16)sum[j];
+                    hi[j] = (__bf16)sum[8 + j];
+                }
+                __bf16 *dst = M + (size_t)(r0 + rr) * H + fh;
+                *reinterpret_cast<bf16x8 *>(dst) = lo;
+                *reinterpret_cast<bf16x8 *>(dst + 8) = hi;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+    }
+}
+
+// Node layer of the fused pass: V' = f_v([V, m]) with the aggregated
+// messages m read from memory; Pa = V' W_a, Pb = V' W_b as in k_node.
+template <int H>
+__global__ void __launch_bounds__(kGnnThreads) k_node_m(int n, const float *__restrict__ P, MlpOff mv, MlpOff me,
+                                                        const __bf16 *__restrict__ V, const __bf16 *__restrict__ M,
+                                                        __bf16 *__restrict__ Vn, __bf16 *__restrict__ Pa,
+                                                        __bf16 *__restrict__ Pb) {
+    constexpr int S = H / 16, MT = H / 32;
+    __shared__ __bf16 w0[2 * H * H], w1[H * H], wa[H * H], wb[H * H];
+    stage_weights<false>(w0, P + mv.W0, H, 2 * H, H);
+    stage_weights<true>(w1, P + mv.W1, H, H, H);
+    stage_weights<true>(wa, P + me.W0 + H * H, H, H, H);
+    stage_weights<true>(wb, P + me.W0 + 2 * H * H, H, H, H);
+    __syncthreads();
+    const int lane = lane_id();
+    const int ntiles = (n + 31) / 32;
+    for (int tile = blockIdx.x * 4 + threadIdx.x / kWave; tile < ntiles; tile += gridDim.x * 4) {
+        const int i = tile * 32 + (lane & 31);
+        const bool valid = i < n;
+        bf16x8 bx[2 * S];
+#pragma unroll
+        for (int st = 0; st < S; ++st) {
+            if (valid) {
+                bx[st] = load8(V + (size_t)i * H + k_nat(st, 0, lane));
+                bx[S + st] = load8(M + (size_t)i * H + k_nat(st, 0, lane));
+            } else {
+#pragma unroll
+                for (int j = 0; j < 8; ++j) bx[st][j] = bx[S + st][j] = (__bf16)0.f;
+            }
+        }
+        f32x16 hid[MT];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) hid[mt] = zero16();
+#pragma unroll
+        for (int st = 0; st < 2 * S; ++st)
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) hid[mt] = mfma(lds_op(w0, 2 * S, mt, st, lane), bx[st], hid[mt]);
+        add_bias<MT>(hid, P + mv.b0, lane, true);
+        f32x16 vo[MT];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) vo[mt] = zero16();
+#pragma unroll
+        for (int st = 0; st < S; ++st) {
+            const bf16x8 b = acc_operand<MT>(hid, st);
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) vo[mt] = mfma(lds_op(w1, S, mt, st, lane), b, vo[mt]);
+        }
+        add_bias<MT>(vo, P + mv.b1, lane, false);
+        if (valid) store_acc_bf16<MT>(Vn + (size_t)i * H, vo, lane);
+        f32x16 pa[MT], pb[MT];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+            pa[mt] = zero16();
+            pb[mt] = zero16();
+        }
+#pragma unroll
+        for (int st = 0; st < S; ++st) {
+            const bf16x8 b = acc_operand<MT>(vo, st);
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) {
+                pa[mt] = mfma(lds_op(wa, S, mt, st, lane), b, pa[mt]);
+                pb[mt] = mfma(lds_op(wb, S, mt, st, lane), b, pb[mt]);
+            }
+        }
+        if (valid) {
+            store_acc_bf16<MT>(Pa + (size_t)i * H, pa, lane);
+            store_acc_bf16<MT>(Pb + (size_t)i * H, pb, lane);
+        }
+    }
+}
+
 // softplus(kDiagShift) = 1: the learned diagonal of L' starts at 1 (mode 2).
 constexpr float kDiagShift = 0.54132485461291810f;  // ln(e - 1)
 
 __device__ __forceinline__ float softplus_f(float x) { return x > 20.f ? x : log1pf(expf(x)); }
+
+// Mode 3 (diagonal completed): radicand A_ii - sum_{j<i} L_ij^2 of row i, the
+// strictly-lower values in the mode-1 form, FP64 sum in row order.  The
+// strictly-lower entries of row i are its first (lrowptr[i+1] - lrowptr[i] -
+// 1) stored entries of A (columns ascending).
+constexpr double kCompleteFloor = 1e-3;
+__device__ __forceinline__ double complete_radicand(int i, const int *__restrict__ rowptr,
+                                                    const int *__restrict__ lrowptr, const int *__restrict__ col,
+                                                    const int *__restrict__ rev, const double *__restrict__ diag64,
+                                                    const float *__restrict__ d) {
+    const int a = rowptr[i], cnt = lrowptr[i + 1] - lrowptr[i] - 1;
+    double ssq = 0.0;
+    for (int q = 0; q < cnt; ++q) {
+        const int k = a + q;
+        const float l = (float)sqrt(diag64[col[k]]) * (0.5f * (d[k] + d[rev[k]]));
+        ssq += (double)l * (double)l;
+    }
+    return diag64[i] - ssq;
+}
 
 // L value of the lower-pattern entry with A-position k.
 __device__ __forceinline__ float l_entry(int k, int mode, const int *__restrict__ erow,
@@ -425,20 +705,38 @@ __device__ __forceinline__ float l_entry(int k, int mode, const int *__restrict_
     }
     if (j == i) {
         const float sa = (float)sqrt(diag64[i]);
-        return mode == 1 ? sa : sa * fmaxf(softplus_f(d[k] + kDiagShift), 1e-6f);
+        return mode == 1 || mode == 3 ? sa : sa * fmaxf(softplus_f(d[k] + kDiagShift), 1e-6f);
     }
     return (float)sqrt(diag64[j]) * (0.5f * (d[k] + d[rev[k]]));
 }
 
+// Value of L at L-position q (mode 3 completes the diagonal).
+__device__ __forceinline__ float l_value(int q, int mode, const int *__restrict__ lsrc,
+                                         const int *__restrict__ rowptr, const int *__restrict__ lrowptr,
+                                         const int *__restrict__ erow, const int *__restrict__ col,
+                                         const int *__restrict__ rev, const int *__restrict__ row_sys,
+                                         const double *__restrict__ sys_s, const double *__restrict__ diag64,
+                                         const float *__restrict__ d) {
+    const int k = lsrc[q];
+    const int i = erow[k];
+    if (mode == 3 && col[k] == i) {
+        const double rad = complete_radicand(i, rowptr, lrowptr, col, rev, diag64, d);
+        const double fl = kCompleteFloor * diag64[i];
+        return (float)sqrt(rad > fl ? rad : fl);
+    }
+    return l_entry(k, mode, erow, col, rev, row_sys, sys_s, diag64, d);
+}
+
 __global__ void k_assemble(int nnz_l, int mode, const int *__restrict__ lsrc, const int *__restrict__ u2l,
+                           const int *__restrict__ rowptr, const int *__restrict__ lrowptr,
                            const int *__restrict__ erow, const int *__restrict__ col,
                            const int *__restrict__ rev, const int *__restrict__ row_sys,
                            const double *__restrict__ sys_s, const double *__restrict__ diag64,
                            const float *__restrict__ d, float *__restrict__ lval, float *__restrict__ utval) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= nnz_l) return;
-    if (lval) lval[p] = l_entry(lsrc[p], mode, erow, col, rev, row_sys, sys_s, diag64, d);
-    if (utval) utval[p] = l_entry(lsrc[u2l[p]], mode, erow, col, rev, row_sys, sys_s, diag64, d);
+    if (lval) lval[p] = l_value(p, mode, lsrc, rowptr, lrowptr, erow, col, rev, row_sys, sys_s, diag64, d);
+    if (utval) utval[p] = l_value(u2l[p], mode, lsrc, rowptr, lrowptr, erow, col, rev, row_sys, sys_s, diag64, d);
 }
 
 // Initial-guess head: x^_i = relu(V_i W0 + b0) w1 + b1 on the final node
@@ -504,16 +802,47 @@ int forward_impl(const lpcg_system *s, const lpcg_gnn *net, const double *b, uns
     }
     auto V = [&](int t) { return (__bf16 *)(ws + L.V[train ? t : (t & 1)]); };
     auto E = [&](int t) { return (__bf16 *)(ws + L.E[train ? t : (t & 1)]); };
-    auto Pa = [&](int t) { return (__bf16 *)(ws + L.Pa[train ? t : 0]); };
-    auto Pb = [&](int t) { return (__bf16 *)(ws + L.Pb[train ? t : 0]); };
+    const bool fused = gnn_fused(s, H, net->n_mp, train);  // per-layer projections kept
+    auto Pa = [&](int t) { return (__bf16 *)(ws + L.Pa[train || fused ? t : 0]); };
+    auto Pb = [&](int t) { return (__bf16 *)(ws + L.Pb[train || fused ? t : 0]); };
     float *d = (float *)(ws + L.d);
+    const int T = net->n_mp;
+    if (H == 32 && fused) {
+        k_enc<H, true><<<gnn_blocks(s->n), kGnnThreads, 0, st>>>(s->n, P, o.node_enc, b, s->erow, s->row_sys,
+                                                                  sys_rms, V(0), nullptr);
+        __bf16 *M = (__bf16 *)(ws + L.M);
+        FusedChain ch{};
+        for (int t = 0; t <= T; ++t) {
+            const int g = t < T ? gnn_blocks((long)s->gtiles * 32) : gnn_blocks(s->nnz);
+            switch (t + (t == T ? 8 : 0)) {
+#define LPCG_FUSED(CHN, DECN)                                                                                     \
+    k_fused_edge<CHN, DECN><<<g, kGnnThreads, 0, st>>>(s->nnz, s->gtiles, s->gtile_row, s->rowptr, s->erow,   \
+                                                       s->colind, s->val64, s->row_sys, sys_s, P, o.edge_enc, ch, \
+                                                       o.dec, V(t), M, d, 0)
+                case 0: LPCG_FUSED(0, false); break;
+                case 1: LPCG_FUSED(1, false); break;
+                case 2: LPCG_FUSED(2, false); break;
+                case 3: LPCG_FUSED(3, false); break;
+                case 9: LPCG_FUSED(1, true); break;
+                case 10: LPCG_FUSED(2, true); break;
+                case 11: LPCG_FUSED(3, true); break;
+                default: LPCG_FUSED(4, true); break;
+#undef LPCG_FUSED
+            }
+            if (t == T) break;
+            k_node_m<H><<<gnn_blocks(s->n), kGnnThreads, 0, st>>>(s->n, P, o.node[t], o.edge[t], V(t), M, V(t + 1),
+                                                                  Pa(t), Pb(t));
+            ch.edge[t] = o.edge[t];
+            ch.pa[t] = Pa(t);
+            ch.pb[t] = Pb(t);
+        }
+    } else {
     k_enc<H, true><<<gnn_blocks(s->n), kGnnThreads, 0, st>>>(s->n, P, o.node_enc, b, s->erow, s->row_sys,
                                                               sys_rms, V(0),
                                                               train ? (float *)(ws + L.Xn) : nullptr);
     k_enc<H, false><<<gnn_blocks(s->nnz), kGnnThreads, 0, st>>>(s->nnz, P, o.edge_enc, s->val64, s->erow,
                                                                  s->row_sys, sys_s, E(0),
                                                                  train ? (float *)(ws + L.Xe) : nullptr);
-    const int T = net->n_mp;
     for (int t = 0; t < T; ++t) {
         k_node<H><<<gnn_blocks(s->n), kGnnThreads, 0, st>>>(s->n, s->rowptr, s->colind, P, o.node[t],
                                                              o.edge[t], V(t), E(t), V(t + 1), Pa(t), Pb(t));
@@ -525,7 +854,9 @@ int forward_impl(const lpcg_system *s, const lpcg_gnn *net, const double *b, uns
                 s->nnz, s->erow, s->colind, P, o.edge[t], o.dec, E(t), Pa(t), Pb(t),
                 train ? E(t + 1) : nullptr, d);
     }
-    k_assemble<<<nblk(s->nnz_l, 256), 256, 0, st>>>(s->nnz_l, net->diag_mode, s->lsrc, s->u2l, s->erow,
+    }
+    k_assemble<<<nblk(s->nnz_l, 256), 256, 0, st>>>(s->nnz_l, net->diag_mode, s->lsrc, s->u2l, s->rowptr,
+                                                     s->lrowptr, s->erow,
                                                      s->colind, s->rev, s->row_sys, sys_s, s->diag64, d, lval,
                                                      utval);
     if (net->x_head) {
@@ -540,8 +871,8 @@ int forward_impl(const lpcg_system *s, const lpcg_gnn *net, const double *b, uns
 
 int check_net(const lpcg_gnn *net) {
     if (!net || !net->params || (net->h != 32 && net->h != 64) || net->n_mp < 1 || net->n_mp > kMaxMp ||
-        net->diag_mode < 0 || net->diag_mode > 2 || net->x_head < 0 || net->x_head > 1) {
-        set_error("gnn: h must be 32 or 64, 1 <= n_mp <= %d, diag_mode 0, 1 or 2, x_head 0 or 1", kMaxMp);
+        net->diag_mode < 0 || net->diag_mode > 3 || net->x_head < 0 || net->x_head > 1) {
+        set_error("gnn: h must be 32 or 64, 1 <= n_mp <= %d, diag_mode 0 .. 3, x_head 0 or 1", kMaxMp);
         return LPCG_EINVAL;
     }
     return LPCG_OK;
@@ -747,7 +1078,15 @@ __global__ void k_assemble_bwd(int nnz, int mode, const int *__restrict__ rowptr
         const int klo = i > j ? k : rev[k];
         const int p = lrowptr[lo_r] + (klo - rowptr[lo_r]);
         const float scale = mode == 0 ? (float)sqrt(sys_s[row_sys[i]]) : (float)sqrt(diag64[lo_c]);
-        g = 0.5f * scale * gl[p];
+        float gp = gl[p];
+        if (mode == 3) {  // through the completed diagonal: dL_ii / dL_ij = -L_ij / L_ii
+            const double rad = complete_radicand(lo_r, rowptr, lrowptr, col, rev, diag64, d);
+            if (rad > kCompleteFloor * diag64[lo_r]) {
+                const float lij = scale * (0.5f * (d[klo] + d[rev[klo]]));
+                gp -= gl[lrowptr[lo_r + 1] - 1] * lij / (float)sqrt(rad);
+            }
+        }
+        g = 0.5f * scale * gp;
     }
     gd[k] = g;
 }

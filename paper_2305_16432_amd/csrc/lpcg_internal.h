@@ -125,6 +125,15 @@ struct lpcg_system {
     lpcg::TrsvCfg ic0_cfg;       // IC(0): the fastest dependency-driven forward configuration
     bool ic0_tuned = false;
     int trsv_g = 8;              // lanes per row of the level-synchronous kernel
+    // Two-level structure: the forward level 0 is exactly rows [0, two_level_p)
+    // (no strictly-lower entries) and every other row is level 1 (0: not so).
+    // Multicolour orderings of bipartite graphs (red-black grids) have it.
+    int two_level_p = 0;
+    // Row-aligned edge tiles of the network's fused inference pass: tile j
+    // holds the whole rows gtile_row[j] .. gtile_row[j+1]-1, at most 32 stored
+    // entries in all (0 tiles: some row has more than 32 entries).
+    int *gtile_row = nullptr;
+    int gtiles = 0;
     // batched solves: row segments of at most kSegRows rows that never cross
     // a system (one block each), the segment range of every system, and the
     // per-system FP64 scalars / control words

@@ -111,20 +111,32 @@ def forward(A, b, P, h, n_mp, rev, diag_mode=0, keep=False, x_head=False):
     if diag_mode == 0:
         lhat = np.where(diag, np.maximum(ognn._softplus(d), ognn.SOFTPLUS_FLOOR), 0.5 * (d + d[rev]))
         lval = np.sqrt(s) * lhat[lower]
-        colscale = None
+        colscale = lfull = active = None
     else:
         adiag = A.val[diag]
         colscale = np.sqrt(adiag[np.minimum(row, col)])
-        if diag_mode == 1:
+        if diag_mode in (1, 3):
             ldiag = np.sqrt(adiag[row])
         else:
             ldiag = colscale * np.maximum(ognn._softplus(d + ognn.DIAG_SHIFT), ognn.SOFTPLUS_FLOOR)
-        lval = np.where(diag, ldiag, colscale * 0.5 * (d + d[rev]))[lower]
+        lfull = np.where(diag, ldiag, colscale * 0.5 * (d + d[rev]))
+        active = None
+        if diag_mode == 3:  # completed diagonal from the FP32-rounded strictly lower values
+            strict = lower & ~diag
+            l32 = lfull.astype(np.float32).astype(np.float64)
+            ssq = np.zeros(n)
+            np.add.at(ssq, row[strict], l32[strict] ** 2)
+            rad = adiag - ssq
+            active = rad > ognn.COMPLETE_FLOOR * adiag
+            ldg = np.sqrt(np.where(active, rad, ognn.COMPLETE_FLOOR * adiag))
+            lfull = np.where(diag, ldg[row], lfull)
+        lval = lfull[lower]
     lval = lval.astype(np.float32).astype(np.float64)
     cache = None
     if keep:
         cache = dict(row=row, col=col, rev=rev, s=s, d=d, lower=lower, diag=diag, Vs=Vs, Es=Es,
-                     mlp=caches, n=n, h=h, n_mp=n_mp, diag_mode=diag_mode, colscale=colscale, x0=x0)
+                     mlp=caches, n=n, h=h, n_mp=n_mp, diag_mode=diag_mode, colscale=colscale, x0=x0,
+                     lfull=lfull, active=active)
     return lval, cache
 
 
@@ -143,6 +155,12 @@ def backward(P, cache, glval, gxhat=None):
         glhat *= np.sqrt(cache["s"])
         gd += np.where(diag & (ognn._softplus(d) > ognn.SOFTPLUS_FLOOR), glhat * ognn._sigmoid(d), 0.0)
     else:
+        if cache["diag_mode"] == 3:  # dL_ii / dL_ij = -L_ij / L_ii off the floor
+            lf = cache["lfull"]
+            gdiag, ldiag = np.zeros(n), np.zeros(n)
+            gdiag[row[diag]] = glhat[diag]
+            ldiag[row[diag]] = lf[diag]
+            glhat = glhat + np.where(off & cache["active"][row], -gdiag[row] * lf / ldiag[row], 0.0)
         if cache["diag_mode"] == 2:
             ds = d + ognn.DIAG_SHIFT
             gd += np.where(diag & (ognn._softplus(ds) > ognn.SOFTPLUS_FLOOR),

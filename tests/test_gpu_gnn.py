@@ -59,7 +59,7 @@ def _blockwise_ref(A, b, P, h, n_mp, srp, pat, diag_mode=0):
     return out
 
 
-@pytest.mark.parametrize("diag_mode", [0, 1, 2])
+@pytest.mark.parametrize("diag_mode", [0, 1, 2, 3])
 @pytest.mark.parametrize("h,n_mp", [(32, 3), (64, 2), (64, 5)])
 @pytest.mark.parametrize("name", ["poisson2d_32", "heat3d_13", "fem_40", "random_777", "tridiag_1000",
                                   "one"])
@@ -79,7 +79,7 @@ def test_gnn_forward_batch_per_system_normalisation(diag_mode):
     _check(B, b, 32, 3, seed=7, sys_rowptr=srp, diag_mode=diag_mode)
 
 
-@pytest.mark.parametrize("diag_mode", [0, 1, 2])
+@pytest.mark.parametrize("diag_mode", [0, 1, 2, 3])
 def test_gnn_forward_c3_full_size(diag_mode):
     print(f"[gnn] heat3d_64 h=32 n_mp=3 diag_mode={diag_mode}", flush=True)
     A, b = g.heat_system_3d(64, 1e-3, 1000, 2000)
@@ -167,3 +167,40 @@ def test_learned_pcg_c1_full_size():
     print(f"iters gpu {r['iters']} oracle {ro['iters']}", flush=True)
     assert r["status"] == 0 and O.true_relres(A, b, host(x)) <= 1e-6
     assert abs(r["iters"] - ro["iters"]) <= max(2, 0.1 * ro["iters"])
+
+
+@pytest.mark.parametrize("n_mp", [1, 2, 3, 4, 5])
+@pytest.mark.parametrize("name", ["heat3d_13", "fem_40", "poisson2d_32"])
+def test_gnn_fused_inference_parity(name, n_mp):
+    """Inference at width 32 and up to four layers runs the fused pass (edge
+    latents recomputed, never stored); five layers, and training, run the
+    stored form.  Both against the oracle, and the fused factor against the
+    training forward's (stored form) on the same weights, by the same bars."""
+    print(f"[gnn] fused {name} h=32 n_mp={n_mp}", flush=True)
+    A = matrices_small()[name]
+    b = np.random.default_rng(2).standard_normal(A.n)
+    P = g.init_gnn_params(32, n_mp, seed=17)
+    st = _check(A, b, 32, n_mp, seed=17, diag_mode=1, P=P)
+    S = gpu_system(A)
+    params = lpcg.pack_params(P, 32, n_mp).cuda()
+    ws = lpcg.gnn_workspace(S, 32, n_mp, train=True)
+    lt = host(lpcg.gnn_forward_train(S, params, 32, n_mp, cuda_f64(b), ws, diag_mode=1)).astype(np.float64)
+    lf, _ = _gpu_L(S, A, b, P, 32, n_mp, 1)
+    pat = O.Pattern(A)
+    st2 = PB.check_factor(pat, lf, lt, 1)
+    print("fused vs stored:", {k: f"{v:.2e}" for k, v in st2.items()}, "oracle:", st["off_rel"], flush=True)
+
+
+def test_gnn_row_longer_than_a_tile():
+    """A row with more than 32 stored entries (a star graph joined to a grid)
+    has no row-aligned tile: inference falls back to the stored form."""
+    import scipy.sparse as sp
+    base = g.poisson_grid(8, 2).to_scipy().tolil()
+    n = base.shape[0]
+    for j in range(1, 40):
+        base[0, j] = base[j, 0] = -0.01
+    base[0, 0] = base[0, 0] + 1.0
+    A = g.canonical_csr(sp.csr_matrix(base))
+    assert np.max(np.diff(A.rowptr)) > 32
+    b = np.random.default_rng(4).standard_normal(n)
+    _check(A, b, 32, 3, seed=19, diag_mode=0)

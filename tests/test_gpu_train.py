@@ -74,7 +74,7 @@ def _grad_check(A, b, h, n_mp, seed, sys_rowptr=None, diag_mode=0):
     return worst
 
 
-@pytest.mark.parametrize("diag_mode", [0, 1, 2])
+@pytest.mark.parametrize("diag_mode", [0, 1, 2, 3])
 @pytest.mark.parametrize("h,n_mp", [(32, 3), (64, 2), (64, 5)])
 @pytest.mark.parametrize("name", ["poisson2d_32", "heat3d_13", "fem_40"])
 def test_gnn_backward_parity(name, h, n_mp, diag_mode):

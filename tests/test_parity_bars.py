@@ -25,7 +25,7 @@ def _systems():
     }
 
 
-@pytest.mark.parametrize("diag_mode", [0, 1, 2])
+@pytest.mark.parametrize("diag_mode", [0, 1, 2, 3])
 @pytest.mark.parametrize("h,n_mp", [(32, 3), (64, 5)])
 @pytest.mark.parametrize("name", ["heat3d_9", "fem_24", "poisson2d_20"])
 def test_forward_bar_passes_bf16_model_and_catches_planted(name, h, n_mp, diag_mode):
