@@ -1,5 +1,6 @@
 // Standalone building blocks: SpMV, triangular solves, IC(0), Jacobi.
 #include <algorithm>
+#include <cstring>
 #include <mutex>
 
 #include "device_util.h"
@@ -17,12 +18,15 @@ __global__ void k_zero_i32(int *p, int count) {
     if (i < count) p[i] = 0;
 }
 
+// CSR SpMV with G = group lanes per row (64 / G rows per wavefront) on
+// `blocks` blocks (0: the system's tuned grid).
 template <typename VT, typename XT>
-int launch_spmv(const lpcg_system *s, const VT *v, const XT *x, XT *y, hipStream_t st) {
+int launch_spmv(const lpcg_system *s, const VT *v, const XT *x, XT *y, hipStream_t st, int group = 0,
+                int blocks = 0) {
     const int threads = 256;
-    const int rows_per_block = threads / s->spmv_group;
-    const int blocks = std::min(nblk(s->n, rows_per_block), 8192);
-    switch (s->spmv_group) {
+    if (group == 0) group = s->spmv_group;
+    if (blocks == 0) blocks = s->spmv_blocks;
+    switch (group) {
         case 4: k_spmv<4><<<blocks, threads, 0, st>>>(s->n, s->rowptr, s->colind, v, x, y); break;
         case 8: k_spmv<8><<<blocks, threads, 0, st>>>(s->n, s->rowptr, s->colind, v, x, y); break;
         case 16: k_spmv<16><<<blocks, threads, 0, st>>>(s->n, s->rowptr, s->colind, v, x, y); break;
@@ -836,9 +840,16 @@ extern "C" int lpcg_blocked_schedule(int32_t n, const int32_t *rowptr, const int
 }
 
 extern "C" int lpcg_get_trsv_cfg(const lpcg_system *s, int32_t direction, lpcg_trsv_cfg *out) {
-    if (!s || !out || direction < 0 || direction > 1) {
+    if (!s || !out || direction < 0 || direction > 2) {
         set_error("lpcg_get_trsv_cfg: invalid arguments");
         return LPCG_EINVAL;
+    }
+    if (direction == 2) {  // the SpMV: lanes per row and grid
+        std::memset(out, 0, sizeof(*out));
+        out->direction = 2;
+        out->mode = s->spmv_group;
+        out->waves = s->spmv_blocks;
+        return LPCG_OK;
     }
     const TrsvCfg &c = s->trsv[direction];
     out->direction = direction;
@@ -853,6 +864,18 @@ extern "C" int lpcg_get_trsv_cfg(const lpcg_system *s, int32_t direction, lpcg_t
 }
 
 extern "C" int lpcg_set_trsv_cfg(lpcg_system *s, const lpcg_trsv_cfg *cfg) {
+    if (s && cfg && cfg->direction == 2) {  // the SpMV: G lanes per row on `waves` blocks
+        const int G = cfg->mode;
+        if ((G != 4 && G != 8 && G != 16 && G != 32 && G != 64) || cfg->waves < 1 || cfg->waves > kMaxSpmvBlocks) {
+            set_error("lpcg_set_trsv_cfg: SpMV lanes per row must be 4, 8, 16, 32 or 64 and blocks 1..%d",
+                      kMaxSpmvBlocks);
+            return LPCG_EINVAL;
+        }
+        s->spmv_group = G;
+        s->spmv_blocks = cfg->waves;
+        drop_graphs(s);
+        return LPCG_OK;
+    }
     if (!s || !cfg || cfg->direction < 0 || cfg->direction > 1 || cfg->mode < 0 || cfg->mode > 3 ||
         cfg->waves < 0 || cfg->backoff < 0 || cfg->backoff > 64 ||
         (cfg->block_stride != 0 && cfg->block_stride != 1 && cfg->block_stride != 2 &&
@@ -958,6 +981,45 @@ extern "C" int lpcg_autotune(lpcg_system *s, const float *l_val, const float *ut
             if (rc) return rc;
         }
         s->trsv[dir] = best_c;
+    }
+    // SpMV: lanes per row G (64 / G rows per wavefront) and grid size, timed
+    // on w = A p with the FP32 values (the PCG's product)
+    {
+        double best = 1e30;
+        int best_g = s->spmv_group, best_b = s->spmv_blocks;
+        for (int G : {4, 8, 16, 32, 64})
+            for (int cap : {512, 1024, 2048}) {
+                const int blocks = std::max(1, std::min(cap, nblk(s->n, kVecThreads / G)));
+                if (cap > 512 && blocks < cap / 2) continue;  // the same grid as a smaller cap
+                double tot = 0;
+                for (int r = 0; r <= reps; ++r) {
+                    LPCG_HIP(hipEventRecord(ev.a, st));
+                    int rc = launch_spmv(s, s->val32, s->p, s->w, st, G, blocks);
+                    if (rc) return rc;
+                    LPCG_HIP(hipEventRecord(ev.b, st));
+                    LPCG_HIP(hipEventSynchronize(ev.b));
+                    float ms = 0;
+                    LPCG_HIP(hipEventElapsedTime(&ms, ev.a, ev.b));
+                    if (r > 0) tot += ms;
+                }
+                const double us = 1e3 * tot / reps;
+                if (count < table_len) {
+                    lpcg_trsv_cfg &e = table[count];
+                    std::memset(&e, 0, sizeof(e));
+                    e.direction = 2;
+                    e.mode = G;
+                    e.waves = blocks;
+                    e.us = us;
+                }
+                ++count;
+                if (us < best) {
+                    best = us;
+                    best_g = G;
+                    best_b = blocks;
+                }
+            }
+        s->spmv_group = best_g;
+        s->spmv_blocks = best_b;
     }
     if (n_table) *n_table = count;
     drop_graphs(s);

@@ -26,10 +26,12 @@
 //                 it), w = A p computed from z and p_prev on the fly, p.w
 //                 partials; reducer block: alpha, breakdown test, it += 1
 //           xr    x += alpha p, r -= alpha w, ||r||^2 (Jacobi/none: r.z)
-//                 partials, presets of the dependency-driven substitution;
-//                 reducer block: convergence test (Jacobi/none: beta)
-// Jacobi and none form z = dinv r / r on the fly, so an iteration is two
-// launches; LLT adds the substitutions.
+//                 partials, Jacobi's z = dinv r, presets of the
+//                 dependency-driven substitution; reducer block:
+//                 convergence test (Jacobi/none: beta)
+// Jacobi writes z = dinv r where it updates r and no preconditioning reads r
+// as z, so an iteration is two launches; LLT adds the substitutions (two
+// launches in all for the two-level orderings, see k_llt2_*).
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -118,7 +120,10 @@ __global__ void __launch_bounds__(VT) k_setup(Args a) {
         a.r[i] = ri;
         bb += bi * bi;
         rr += (double)ri * ri;
-        if (KIND == LPCG_PC_JACOBI) rz += (double)ri * ri * a.dinv[i];
+        if (KIND == LPCG_PC_JACOBI) {
+            rz += (double)ri * ri * a.dinv[i];
+            a.z[i] = __float_as_uint(a.dinv[i] * ri);
+        }
         if (KIND == LPCG_PC_NONE) rz += (double)ri * ri;
         if (KIND == LPCG_PC_LLT) {
             a.y[i] = kUnset;
@@ -279,6 +284,74 @@ __global__ void __launch_bounds__(256) k_llt_bwd_level(Args a, int lev0, int row
     if (last && is_reducer()) finish_rz(a, lds);
 }
 
+// Two-level form of z = L^-T L^-1 r for systems whose forward level 0 is the
+// row prefix [0, p) (rows without strictly-lower entries; p = two_level_p)
+// and whose other rows all lie on level 1, as multicolour orderings of
+// red-black grids give.  Then no edge joins two rows of the prefix or two rows
+// of the suffix, so
+//   prefix rows have L_jj as their only entry, at position j of l_val:
+//     y_j = r_j / L_jj                                  (elementwise)
+//   suffix rows:  y_i = (r_i - sum_{j<i} L_ij y_j) / L_ii,  z_i = y_i / L_ii
+//     (their column of L holds only the diagonal)
+//   prefix rows:  z_j = (y_j - sum_{i>j} L_ij z_i) / L_jj
+// Two launches instead of one per level and direction: the suffix kernel
+// forms y of its prefix neighbours on the fly; the prefix kernel recomputes
+// y_j.  Each publishes one r.z partial per block; the prefix kernel's
+// reducer block takes beta from all of them.
+template <int G>
+__global__ void __launch_bounds__(256) k_llt2_suffix(Args a, int p) {
+    __shared__ double lds[VT / kWave];
+    if (is_done(a)) return;
+    const int sub = threadIdx.x % G;
+    constexpr int per = 256 / G;
+    float *z = (float *)a.z;
+    double rz = 0;
+    for (int row = p + blockIdx.x * per + threadIdx.x / G; row < a.n; row += gridDim.x * per) {
+        const int k0 = a.lrp[row], k1 = a.lrp[row + 1] - 1;
+        float acc = 0.f;
+        for (int k = k0 + sub; k < k1; k += G) {
+            const int j = a.lci[k];
+            acc += a.lval[k] * (a.r[j] / a.lval[j]);
+        }
+#pragma unroll
+        for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, G);
+        if (sub == 0) {
+            const float d = a.lval[k1], ri = a.r[row];
+            const float zv = ((ri - acc) / d) / d;
+            z[row] = zv;
+            rz += (double)ri * (double)zv;
+        }
+    }
+    rz = block_sum<VT>(rz, lds);
+    if (threadIdx.x == 0) publish_partial(a.sp_rz, blockIdx.x, rz);
+}
+
+template <int G>
+__global__ void __launch_bounds__(256) k_llt2_prefix(Args a, int p, int part0) {
+    __shared__ double lds[VT / kWave];
+    if (is_done(a)) return;
+    const int sub = threadIdx.x % G;
+    constexpr int per = 256 / G;
+    float *z = (float *)a.z;
+    double rz = 0;
+    for (int row = blockIdx.x * per + threadIdx.x / G; row < p; row += gridDim.x * per) {
+        const int k0 = a.urp[row], k1 = a.urp[row + 1];
+        float acc = 0.f;
+        for (int k = k0 + 1 + sub; k < k1; k += G) acc += a.utval[k] * z[a.uci[k]];
+#pragma unroll
+        for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, G);
+        if (sub == 0) {
+            const float d = a.utval[k0], ri = a.r[row];
+            const float zv = (ri / d - acc) / d;
+            z[row] = zv;
+            rz += (double)ri * (double)zv;
+        }
+    }
+    rz = block_sum<VT>(rz, lds);
+    if (threadIdx.x == 0) publish_partial(a.sp_rz, part0 + blockIdx.x, rz);
+    if (is_reducer()) finish_rz(a, lds);
+}
+
 // Single-workgroup substitutions (one block walking all levels): forward,
 // backward, or both in one launch; the backward part also forms r.z with a
 // block reduction and beta, so no partials are published.
@@ -307,8 +380,7 @@ __global__ void __launch_bounds__(kWgThreads) k_llt_wg(Args a, int do_fwd, int d
 template <int KIND>
 __device__ __forceinline__ float pdir(const Args &a, int j, bool first, float beta, const float *__restrict__ pp) {
     float zj;
-    if (KIND == LPCG_PC_LLT) zj = __uint_as_float(a.z[j]);
-    else if (KIND == LPCG_PC_JACOBI) zj = a.dinv[j] * a.r[j];
+    if (KIND == LPCG_PC_LLT || KIND == LPCG_PC_JACOBI) zj = __uint_as_float(a.z[j]);
     else zj = a.r[j];
     return first ? zj : __fmaf_rn(beta, pp[j], zj);
 }
@@ -375,7 +447,10 @@ __global__ void __launch_bounds__(VT) k_xr(Args a) {
         const float ri = a.r[i] - af * a.w[i];
         a.r[i] = ri;
         rr += (double)ri * ri;
-        if (KIND == LPCG_PC_JACOBI) rzn += (double)ri * ri * a.dinv[i];
+        if (KIND == LPCG_PC_JACOBI) {
+            rzn += (double)ri * ri * a.dinv[i];
+            a.z[i] = __float_as_uint(a.dinv[i] * ri);
+        }
         if (KIND == LPCG_PC_NONE) rzn += (double)ri * ri;
         if (KIND == LPCG_PC_LLT) {
             if (a.reset_y) a.y[i] = kUnset;
@@ -436,11 +511,31 @@ int blk_set_lds(const lpcg_system *s, int d) {
     return LPCG_OK;
 }
 
+// The PCG iteration applies L L^T through the two-level pair when the system
+// has the two-level structure and both substitutions run level-synchronous
+// (the tuner's choice for so few levels).
+bool two_level_path(const lpcg_system *s) {
+    return s->two_level_p > 0 && s->two_level_p < s->n && s->trsv[0].mode == 1 && s->trsv[1].mode == 1;
+}
+
 template <int KIND>
 int enqueue_iteration(const lpcg_system *s, const Args &a, hipStream_t st) {
     const int vb = s->vec_blocks;
     const int sb = s->spmv_blocks;
-    if (KIND == LPCG_PC_LLT) {
+    if (KIND == LPCG_PC_LLT && two_level_path(s)) {
+        const int G = s->trsv_g, p = s->two_level_p;
+        const int nbs = level_blocks(s->n - p, G), nbp = level_blocks(p, G);
+        if (G == 4) {
+            k_llt2_suffix<4><<<nbs, 256, 0, st>>>(a, p);
+            k_llt2_prefix<4><<<nbp, 256, 0, st>>>(a, p, nbs);
+        } else if (G == 8) {
+            k_llt2_suffix<8><<<nbs, 256, 0, st>>>(a, p);
+            k_llt2_prefix<8><<<nbp, 256, 0, st>>>(a, p, nbs);
+        } else {
+            k_llt2_suffix<16><<<nbs, 256, 0, st>>>(a, p);
+            k_llt2_prefix<16><<<nbp, 256, 0, st>>>(a, p, nbs);
+        }
+    } else if (KIND == LPCG_PC_LLT) {
         const int G = s->trsv_g;
         const bool wf = s->trsv[0].mode == 2, wb = s->trsv[1].mode == 2;
         if (wf) {
@@ -602,7 +697,9 @@ extern "C" int lpcg_pcg_solve(lpcg_system *s, const lpcg_precond *P, const doubl
     a.stride_b = s->trsv[1].stride;
     a.reset_y = s->trsv[0].mode == 0 || s->trsv[0].mode == 3;
     a.reset_z = s->trsv[1].mode == 0 || s->trsv[1].mode == 3;
-    if (s->trsv[1].mode == 0) {
+    if (two_level_path(s)) {
+        a.np_rz = level_blocks(s->n - s->two_level_p, s->trsv_g) + level_blocks(s->two_level_p, s->trsv_g);
+    } else if (s->trsv[1].mode == 0) {
         a.np_rz = (s->n + kWave - 1) / kWave;
     } else if (s->trsv[1].mode == 3) {
         a.np_rz = s->blk_nb[1];

@@ -178,3 +178,29 @@ def test_color_update_values():
     l, _, _ = lpcg.ic0(S)
     lref, _ = O.ic0(pat, O.permute_sym(A2, perm))
     assert np.all(np.abs(host(l) - lref) <= 1.0001 * U32 * np.abs(lref))
+
+
+@pytest.mark.parametrize("name", ["heat3d_13", "poisson2d_32"])
+def test_two_level_pcg_matches_per_level_launches(name):
+    """On a red-black system the PCG applies L L^T with the two-level pair
+    (k_llt2_*); forcing the backward direction to the dependency-driven mode
+    takes the per-level path.  Both reach the FP64 tolerance with the
+    oracle's iteration count, and their iterates agree to FP32 rounding."""
+    A = matrices_small()[name]
+    b = np.random.default_rng(5).standard_normal(A.n)
+    perm, _, Ap, pat = _ref(A)
+    S = gpu_system(A, None, COLOR)
+    assert S.info["nlev_fwd"] == 2 and S.info["ncolors"] == 2
+    l, ut, _ = lpcg.ic0(S)
+    bd = cuda_f64(b)
+    x2, r2 = lpcg.pcg_solve(S, lpcg.PC_LLT, bd, l_val=l, ut_val=ut, tol=1e-6, max_restarts=2)
+    lpcg.set_trsv_cfg(S, 1, 0)
+    x1, r1 = lpcg.pcg_solve(S, lpcg.PC_LLT, bd, l_val=l, ut_val=ut, tol=1e-6, max_restarts=2)
+    lref, _ = O.ic0(pat, Ap)
+    ro = O.pcg(Ap, b[perm], O.PC_LLT, pat, lref, tol=1e-6)
+    for res in (r1, r2):
+        assert res["status"] == 0 and res["relres_true"] <= 1e-6
+        assert abs(res["iters"] - ro["iters"]) <= max(2, 0.1 * ro["iters"]), (res["iters"], ro["iters"])
+    assert abs(r1["iters"] - r2["iters"]) <= 2, (r1["iters"], r2["iters"])
+    xa, xb = host(x1), host(x2)
+    assert np.linalg.norm(xa - xb) / np.linalg.norm(xa) <= 1e-3

@@ -9,6 +9,7 @@ division); PCG iterations within max(2, 10%) of the FP64 oracle's and the
 FP64 true residual <= tol."""
 import numpy as np
 import pytest
+import torch
 
 import oracle as O
 import pdegen as g
@@ -127,14 +128,40 @@ def test_autotune_c3_full_size(ordering):
         for t in sorted(rows, key=lambda t: t["us"])[:6]:
             print(f"  dir {d} mode {t['mode']} waves {t['waves']} backoff {t['backoff']} "
                   f"stride {t['block_stride']} rows {t['block_rows']}: {t['us']:.1f} us")
+    # the SpMV: every lanes-per-row choice timed, the fastest kept
+    sp = [t for t in table if t["direction"] == 2]
+    assert {t["mode"] for t in sp} == {4, 8, 16, 32, 64}
+    best = min(sp, key=lambda t: t["us"])
+    got = lpcg.get_trsv_cfg(S, 2)
+    assert got["mode"] == best["mode"] and got["waves"] == best["waves"]
+    print(f"  spmv: G {best['mode']} blocks {best['waves']}: {best['us']:.1f} us")
     x, res = lpcg.pcg_solve(S, lpcg.PC_LLT, cuda_f64(b), l_val=l, ut_val=ut, tol=1e-6, max_restarts=2)
     assert res["status"] == 0 and O.true_relres(A, b, host(x)) <= 1e-6
 
 
+@pytest.mark.parametrize("G", [4, 16, 64])
+def test_spmv_lanes_per_row_within_bound(G):
+    """Every SpMV lanes-per-row choice gives an FP32 product within the
+    per-row bound of the FP64 oracle, and the PCG reaches the tolerance."""
+    A = matrices_small()["fem_40"]
+    S = gpu_system(A)
+    x = np.random.default_rng(1).standard_normal(A.n).astype(np.float32)
+    lpcg.set_trsv_cfg(S, 2, G, waves=37)
+    assert lpcg.get_trsv_cfg(S, 2)["mode"] == G
+    y = host(lpcg.spmv(S, torch.as_tensor(x).cuda()))
+    ref = O.spmv(A, x.astype(np.float64))
+    bound = O.spmv(g.CSR(A.n, A.rowptr, A.colind, np.abs(A.val)), np.abs(x.astype(np.float64)))
+    k = np.diff(A.rowptr)
+    assert np.all(np.abs(y - ref) <= 2 * k * U32 * bound + 1e-30)
+    b = np.random.default_rng(2).standard_normal(A.n)
+    xs, res = lpcg.pcg_solve(S, lpcg.PC_JACOBI, cuda_f64(b), tol=1e-6, max_restarts=2)
+    assert res["status"] == 0 and O.true_relres(A, b, host(xs)) <= 1e-6
+
+
 def test_trsv_cfg_rejects_bad_values():
     S = gpu_system(g.poisson_grid(5, 2))
-    for bad in [(2, 0, 0, 1), (0, 4, 0, 1), (0, 0, 0, 65), (0, 0, 0, 1, 3), (0, 3, 0, 1, 1, 32),
-                (0, 3, 0, 1, 1, 1 << 17)]:
+    for bad in [(3, 0, 0, 1), (0, 4, 0, 1), (0, 0, 0, 65), (0, 0, 0, 1, 3), (0, 3, 0, 1, 1, 32),
+                (0, 3, 0, 1, 1, 1 << 17), (2, 12, 8), (2, 8, 0), (2, 8, 4096)]:
         with pytest.raises(lpcg.LpcgError) as e:
             lpcg.set_trsv_cfg(S, *bad)
         assert e.value.code == lpcg.EINVAL
