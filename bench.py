@@ -32,6 +32,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # natural order: the network trained on 32^3 heat steps and fine-tuned on 64^3 ones
+FEM_WEIGHTS = os.path.join(ROOT, "paper_2305_16432_amd", "weights", "fem2d_h64_mp5.npz")
 WEIGHTS = {"natural": os.path.join(ROOT, "paper_2305_16432_amd", "weights", "heat3d_h32_mp3_ft64.npz"),
            "color": os.path.join(ROOT, "paper_2305_16432_amd", "weights", "heat3d_h32_mp3_color.npz")}
 PEAK_HBM = 8000.0  # GB/s, MI355X HBM3E
@@ -217,6 +218,144 @@ def run_seeds(args, S, lval, utval, x, coef, solve_kw, net):
     return summary
 
 
+def run_c1(args, weights):
+    """The 2D FEM workload: P1 FEM on a Delaunay triangulation of a 128 x 128
+    jittered point grid (k = exp(GRF sigma=1, ell=0.1) per triangle, lumped
+    load of f ~ N(0,1); k seed 1000, f seed 2000, n = 15,876 after the
+    boundary), PCG to 1e-6 with the FP64 check: learned L from the 2D network
+    (h = 64, five message-passing layers, softplus diagonal), IC(0) and
+    Jacobi in the natural order, IC(0) in the colour order; the paper's
+    protocol (12 runs, mean of the fastest 5)."""
+    import torch
+
+    import pdegen as g
+    from paper_2305_16432_amd import lpcg
+    A, b, _ = g.fem_p1_delaunay(128, k_seed=1000, f_seed=2000)
+    bd = torch.as_tensor(b).cuda()
+    x = torch.zeros_like(bd)
+    out = {"workload": f"2D P1 FEM on a jittered 128x128 Delaunay grid, n={A.n}, nnz={A.nnz}, "
+                       f"k=exp(GRF sigma=1, ell=0.1), k seed 1000, f seed 2000, tol=1e-06"}
+    for ordering, code in (("natural", lpcg.ORDER_NATURAL), ("color", lpcg.ORDER_COLOR)):
+        S = lpcg.analyze(torch.as_tensor(A.rowptr).cuda(), torch.as_tensor(A.colind).cuda(),
+                         torch.as_tensor(A.val).cuda(), None, code)
+        nl = S.info["nnz_l"]
+        lval = torch.empty(nl, dtype=torch.float32, device="cuda")
+        utval = torch.empty(nl, dtype=torch.float32, device="cuda")
+        dinv = torch.empty(A.n, dtype=torch.float32, device="cuda")
+        lpcg.ic0(S, 0.0, 8, lval, utval)
+        lpcg.autotune(S, lval, utval, reps=3)
+        meth = {"ic0": (lambda: lpcg.ic0(S, 0.0, 8, lval, utval), lpcg.PC_LLT)}
+        if ordering == "natural":
+            meth["jacobi"] = (lambda: lpcg.jacobi(S, dinv), lpcg.PC_JACOBI)
+            if os.path.exists(weights):
+                W = np.load(weights)
+                h, n_mp, dmode = int(W["h"]), int(W["n_mp"]), int(W["diag_mode"])
+                params = torch.as_tensor(W["params"].astype(np.float32)).cuda()
+                ws = lpcg.gnn_workspace(S, h, n_mp, train=False)
+                meth["learned"] = (lambda: lpcg.gnn_predict_L(S, params, h, n_mp, bd, ws, lval, utval,
+                                                              diag_mode=dmode), lpcg.PC_LLT)
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        for name, (pre, kind) in meth.items():
+            tot, prem, its = [], [], []
+            for k in range(args.warmup + args.steps):
+                e0.record()
+                pre()
+                e1.record()
+                x.zero_()
+                _, res = lpcg.pcg_solve(S, kind, bd, x=x, l_val=lval, ut_val=utval, dinv=dinv, tol=1e-6,
+                                        check_every=8, max_restarts=2, use_graph=True)
+                e2.record()
+                torch.cuda.synchronize()
+                if k >= args.warmup:
+                    tot.append(e0.elapsed_time(e2))
+                    prem.append(e0.elapsed_time(e1))
+                    its.append(res["iters"])
+            fast = np.argsort(tot)[:min(5, len(tot))]
+            key = name if ordering == "natural" else f"{name}_{ordering}"
+            out[key] = dict(ms=float(np.mean(np.array(tot)[fast])),
+                            precompute_ms=float(np.mean(np.array(prem)[fast])), iters=int(np.max(its)),
+                            relres_true=res["relres_true"], status=res["status"], levels=S.info["nlev_fwd"])
+            _log(f"c1 {key}: {out[key]}")
+        del S
+    return out
+
+
+def run_c4(args, weights):
+    """The batched workload: 256 independent systems with sizes log-uniform in
+    [2k, 200k] (half 2D P1 FEM, half 3D heat steps; seed 9), one block-diagonal
+    analysis (natural order), FP64 iterative refinement over the batched FP32
+    PCG (inner tolerance 1e-4) until every system reaches ||b - A x|| <=
+    1e-10 ||b||.  A run = precompute (IC(0) of the whole batch, or the network
+    on the whole batch) + the refinement solve, timed with events; one warm-up,
+    then 3 runs (mean of the fastest 2).  Algorithmic bytes: per inner
+    iteration of system i, 8 nnz_i + 12 n_i (SpMV) + 2 (8 nnz_L,i + 12 n_i)
+    (substitutions) + 56 n_i (vector passes); per refinement step, the FP64
+    residual 12 nnz_i + 24 n_i."""
+    import torch
+
+    import pdegen as g
+    from paper_2305_16432_amd import lpcg
+    t0 = time.perf_counter()
+    sysl = g.mixed_batch_parallel(256, 2000, 200000, 9, workers=16)
+    mats = [A for A, _ in sysl]
+    B, srp = g.block_diag_csr(mats)
+    b = np.concatenate([bb for _, bb in sysl])
+    _log(f"c4: {len(mats)} systems, n={B.n}, nnz={B.nnz} generated in {time.perf_counter() - t0:.1f}s")
+    S = lpcg.analyze(torch.as_tensor(B.rowptr).cuda(), torch.as_tensor(B.colind).cuda(),
+                     torch.as_tensor(B.val).cuda(), srp, lpcg.ORDER_NATURAL)
+    nl = S.info["nnz_l"]
+    lval = torch.empty(nl, dtype=torch.float32, device="cuda")
+    utval = torch.empty(nl, dtype=torch.float32, device="cuda")
+    lpcg.ic0(S, 0.0, 8, lval, utval)
+    lpcg.autotune(S, lval, utval, reps=2)
+    bd = torch.as_tensor(b).cuda()
+    x = torch.zeros_like(bd)
+    ns = np.diff(srp)
+    nnzs = np.array([A.nnz for A in mats])
+    nnzl = (nnzs - ns) // 2 + ns
+    per_it = 8 * nnzs + 12 * ns + 2 * (8 * nnzl + 12 * ns) + 56 * ns
+    pres = {"ic0": lambda: lpcg.ic0(S, 0.0, 8, lval, utval)}
+    if os.path.exists(weights):
+        W = np.load(weights)
+        h, n_mp, dmode = int(W["h"]), int(W["n_mp"]), int(W["diag_mode"])
+        params = torch.as_tensor(W["params"].astype(np.float32)).cuda()
+        ws = lpcg.gnn_workspace(S, h, n_mp, train=False)
+        pres["learned"] = lambda: lpcg.gnn_predict_L(S, params, h, n_mp, bd, ws, lval, utval, diag_mode=dmode)
+    out = {"workload": f"256 systems, sizes log-uniform in [2000, 200000] (half 2D P1 FEM, half 3D heat "
+                       f"steps, seed 9), n={B.n}, nnz={B.nnz}; FP64 refinement to 1e-10 over FP32 PCG "
+                       f"(inner tol 1e-4), natural order",
+           "trsv_cfg": [lpcg.get_trsv_cfg(S, d) for d in (0, 1)], "spmv_cfg": lpcg.get_trsv_cfg(S, 2)}
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    for name, pre in pres.items():
+        runs = []
+        for k in range(4):
+            e0.record()
+            pre()
+            e1.record()
+            x.zero_()
+            _, res = lpcg.pcg_solve_ir(S, lpcg.PC_LLT, bd, x=x, l_val=lval, ut_val=utval, tol=1e-10,
+                                       tol_inner=1e-4, max_outer=20, maxit=5000, use_graph=True)
+            e2.record()
+            torch.cuda.synchronize()
+            if k > 0:
+                runs.append((e0.elapsed_time(e2), e0.elapsed_time(e1), res))
+        runs.sort(key=lambda r: r[0])
+        ms = float(np.mean([r[0] for r in runs[:2]]))
+        res = runs[0][2]
+        its = np.array([r["iters"] for r in res])
+        steps = np.array([r["restarts"] for r in res])
+        ok = all(r["status"] == 0 for r in res)
+        byts = float(np.sum(its * per_it) + np.sum((steps + 1) * (12 * nnzs + 24 * ns)))
+        out[name] = dict(ms=ms, precompute_ms=float(np.mean([r[1] for r in runs[:2]])), all_converged=ok,
+                         inner_iters=dict(min=int(its.min()), median=float(np.median(its)), max=int(its.max()),
+                                          sum=int(its.sum())),
+                         refinement_steps_max=int(steps.max()), algorithmic_gb=byts / 1e9,
+                         gbs=byts / (ms * 1e-3) / 1e9)
+        _log(f"c4 {name}: {out[name]}")
+    del S
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -227,6 +366,8 @@ def main():
     ap.add_argument("--u-seed", type=int, default=2000)
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-c4", action="store_true", help="skip the batched 256-system workload")
+    ap.add_argument("--no-c1", action="store_true", help="skip the 2D FEM workload")
     ap.add_argument("--orderings", default="natural,color")
     ap.add_argument("--methods", default="learned,ic0,sgs,jacobi")
     ap.add_argument("--seeds", type=int, default=10,
@@ -382,6 +523,8 @@ def main():
         gnn_info = dict(ms=t * 1e3, gflop=gf / 1e9, tflops=gf / t / 1e12, mfma_frac=gf / t / 1e12 / PEAK_BF16_TFLOPS,
                         hbm_mb=gb / 1e6, gbs=gb / t / 1e9, hbm_frac=gb / t / 1e9 / PEAK_HBM,
                         h=gnn_dims[3], n_mp=gnn_dims[4])
+    c1 = None if args.no_c1 else run_c1(args, FEM_WEIGHTS)
+    c4 = None if args.no_c4 else run_c4(args, WEIGHTS["natural"])
     cpu = None
     if not args.no_cpu:
         os.environ.setdefault("OMP_NUM_THREADS", "1")
@@ -436,6 +579,8 @@ def main():
         "cpu_baseline": cpu,
         "seeds": per_seed if args.seeds > 0 and "natural" in args.orderings.split(",") else None,
         "gnn": gnn_info,
+        "c1": c1,
+        "c4": c4,
     }
     print(json.dumps(out), flush=True)
 

@@ -115,13 +115,13 @@ def load(path):
     from pdegen.csr import CSR
     z = np.load(path, allow_pickle=False)
     srp, snp = z["sys_rowptr"], z["sys_nnzptr"]
+    rpa, ci, va, bb, xx = z["rowptr"], z["colind"], z["val"], z["b"], z["x"]  # each read once
     out = []
     for s in range(len(srp) - 1):
         n = int(srp[s + 1] - srp[s])
-        rp = z["rowptr"][s + srp[s]:s + 1 + srp[s + 1]]
+        rp = rpa[s + srp[s]:s + 1 + srp[s + 1]]
         a, c = int(snp[s]), int(snp[s + 1])
-        out.append((CSR(n, rp, z["colind"][a:c], z["val"][a:c]), z["b"][srp[s]:srp[s + 1]],
-                    z["x"][srp[s]:srp[s + 1]]))
+        out.append((CSR(n, rp, ci[a:c], va[a:c]), bb[srp[s]:srp[s + 1]], xx[srp[s]:srp[s + 1]]))
     return out
 
 

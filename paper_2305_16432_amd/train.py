@@ -66,12 +66,13 @@ def load_triples(path):
     """The systems of a triples file: list of (rowptr, colind, val, b, x)
     (NumPy), the family and its size parameter."""
     z = np.load(path, allow_pickle=False)
+    # every array is read from the file once (each z[key] reads it afresh)
     srp, snp = z["sys_rowptr"], z["sys_nnzptr"]
+    rp, ci, va, bb, xx = z["rowptr"], z["colind"], z["val"], z["b"], z["x"]
     rows = []
     for s in range(len(srp) - 1):
         lo, hi, a, c = int(srp[s]), int(srp[s + 1]), int(snp[s]), int(snp[s + 1])
-        rows.append((z["rowptr"][s + lo:s + 1 + hi], z["colind"][a:c], z["val"][a:c], z["b"][lo:hi],
-                     z["x"][lo:hi]))
+        rows.append((rp[s + lo:s + 1 + hi], ci[a:c], va[a:c], bb[lo:hi], xx[lo:hi]))
     return rows, str(z["family"]), int(z["size"])
 
 

@@ -185,22 +185,46 @@ def random_lower_dag(n: int, p: float, seed: int) -> CSR:
     return canonical_csr(sp.csr_matrix(np.where(pat | np.eye(n, dtype=bool), d, 0.0)))
 
 
-def mixed_batch(nsys: int, n_min: int, n_max: int, seed: int):
-    """Uneven batch of independent systems: sizes log-uniform in
-    [n_min, n_max] (seeded), alternately P1 FEM on a jittered Delaunay grid
-    (side ~ sqrt(n) + 2, boundary eliminated) and the 3D heat step on a cube of
-    side ceil(n^(1/3)); k fields and right-hand sides seeded per system
-    (b = u0 GRF for the 3D systems, the lumped FEM load for the 2D ones).
-    Returns a list of (A, b)."""
+def mixed_batch_member(seed: int, i: int, n: float):
+    """System i of a mixed batch: P1 FEM on a jittered Delaunay grid (side ~
+    sqrt(n) + 2, boundary eliminated) for even i, the 3D heat step on a cube
+    of side ceil(n^(1/3)) for odd i; k fields and right-hand sides seeded per
+    system (b = u0 GRF for the 3D systems, the lumped FEM load for the 2D
+    ones).  Returns (A, b)."""
+    if i % 2 == 0:
+        side = max(4, int(round(np.sqrt(n))) + 2)
+        A, b, _ = fem_p1_delaunay(side, k_seed=seed * 1000 + i, f_seed=seed * 1000 + i + 500)
+    else:
+        m = max(2, int(np.ceil(n ** (1.0 / 3.0))))
+        A, b = heat_system_3d(m, 1e-3, k_seed=seed * 1000 + i, u0_seed=seed * 1000 + i + 500)
+    return A, b
+
+
+def mixed_batch_sizes(nsys: int, n_min: int, n_max: int, seed: int) -> np.ndarray:
+    """Target sizes of a mixed batch: log-uniform in [n_min, n_max], seeded."""
     rng = np.random.default_rng(seed)
-    sizes = np.exp(rng.uniform(np.log(n_min), np.log(n_max), nsys))
-    out = []
-    for i, n in enumerate(sizes):
-        if i % 2 == 0:
-            side = max(4, int(round(np.sqrt(n))) + 2)
-            A, b, _ = fem_p1_delaunay(side, k_seed=seed * 1000 + i, f_seed=seed * 1000 + i + 500)
-        else:
-            m = max(2, int(np.ceil(n ** (1.0 / 3.0))))
-            A, b = heat_system_3d(m, 1e-3, k_seed=seed * 1000 + i, u0_seed=seed * 1000 + i + 500)
-        out.append((A, b))
-    return out
+    return np.exp(rng.uniform(np.log(n_min), np.log(n_max), nsys))
+
+
+def mixed_batch(nsys: int, n_min: int, n_max: int, seed: int):
+    """Uneven batch of independent systems (mixed_batch_member for each of the
+    sizes of mixed_batch_sizes).  Returns a list of (A, b)."""
+    sizes = mixed_batch_sizes(nsys, n_min, n_max, seed)
+    return [mixed_batch_member(seed, i, n) for i, n in enumerate(sizes)]
+
+
+def _member(args):
+    from threadpoolctl import threadpool_limits
+    seed, i, n = args
+    with threadpool_limits(1):
+        return mixed_batch_member(seed, i, n)
+
+
+def mixed_batch_parallel(nsys: int, n_min: int, n_max: int, seed: int, workers: int = 8):
+    """mixed_batch generated by `workers` processes started fresh ("spawn":
+    they import neither torch nor any GPU library, so a caller that has
+    initialised a GPU hands nothing of it to them).  Same systems, same order."""
+    import multiprocessing as mp
+    sizes = mixed_batch_sizes(nsys, n_min, n_max, seed)
+    with mp.get_context("spawn").Pool(workers) as pool:
+        return pool.map(_member, [(seed, i, float(n)) for i, n in enumerate(sizes)], chunksize=4)

@@ -193,12 +193,10 @@ def test_c4_full_size_256_uneven_systems():
     200000, seed=9)), one analysis, IC(0), FP64 refinement over the batched
     FP32 PCG to 1e-10: every system's FP64 residual, and four sampled systems
     against the oracle's FP64 IC(0)-PCG."""
-    from tests.sysgen import mixed_batch
     seed, nsys = 9, 256
-    rng = np.random.default_rng(seed)
-    sizes = np.exp(rng.uniform(np.log(2000), np.log(200000), nsys))
+    sizes = g.mixed_batch_sizes(nsys, 2000, 200000, seed)
     print(f"[c4] generating {nsys} systems, sum n ~ {int(sizes.sum())}", flush=True)
-    sysl = mixed_batch(seed, sizes)
+    sysl = g.mixed_batch_parallel(nsys, 2000, 200000, seed, workers=8)
     mats = [A for A, _ in sysl]
     B, srp = g.block_diag_csr(mats)
     b = np.concatenate([bb for _, bb in sysl])

@@ -127,3 +127,35 @@ def test_fine_tuned_network_64(k_seed, u_seed):
     print(f"[fine-tuned] seeds ({k_seed},{u_seed}): fine-tuned {it_ft}, 32^3-trained {it_32}, IC(0) {ric['iters']}",
           flush=True)
     assert it_ft < ric["iters"] and it_ft <= it_32 + 1
+
+
+FEM_WEIGHTS = os.path.join(WDIR, "fem2d_h64_mp5.npz")
+
+
+@pytest.mark.parametrize("k_seed,f_seed", [(1000, 2000), (1001, 2001), (1002, 2002)])
+def test_fem_network_gain(k_seed, f_seed):
+    """The 2D FEM network (h = 64, five message-passing layers, softplus
+    diagonal; trained on 1000 oracle-solved FEM systems, k seeds 0..999) on
+    held-out 128 x 128 meshes (k seeds 1000+): fewer PCG iterations than the
+    same network at its starting point (decoder output zero: L = sqrt(s)
+    ln(2) I, i.e. plain CG) and than Jacobi; IC(0) is reported beside it."""
+    if not os.path.exists(FEM_WEIGHTS):
+        pytest.skip("the 2D FEM network has not been trained into the tree yet")
+    W = np.load(FEM_WEIGHTS)
+    h, n_mp, dm = int(W["h"]), int(W["n_mp"]), int(W["diag_mode"])
+    params = torch.as_tensor(W["params"].astype(np.float32)).cuda()
+    A, b, _ = g.fem_p1_delaunay(128, k_seed=k_seed, f_seed=f_seed)
+    S = gpu_system(A)
+    bd = cuda_f64(b)
+    it_trained = _iters_learned(S, params, h, n_mp, dm, bd)
+    P0 = g.init_gnn_params(h, n_mp, seed=0)
+    P0["dec.W1"][:] = 0.0
+    P0["dec.b1"][:] = 0.0
+    it_untrained = _iters_learned(S, lpcg.pack_params(P0, h, n_mp).cuda(), h, n_mp, dm, bd)
+    l, ut, _ = lpcg.ic0(S)
+    _, ric = lpcg.pcg_solve(S, lpcg.PC_LLT, bd, l_val=l, ut_val=ut, tol=1e-6, max_restarts=2)
+    _, rj = lpcg.pcg_solve(S, lpcg.PC_JACOBI, bd, tol=1e-6, max_restarts=2)
+    print(f"[learned] fem2d seeds ({k_seed},{f_seed}): trained {it_trained}, untrained {it_untrained}, "
+          f"IC(0) {ric['iters']}, Jacobi {rj['iters']}", flush=True)
+    assert it_trained < 0.8 * it_untrained
+    assert it_trained < rj["iters"]
