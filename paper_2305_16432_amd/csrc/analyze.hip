@@ -602,9 +602,13 @@ int analyze_impl(const lpcg_csr *A, const int32_t *h_sys, int32_t nsys, lpcg_sys
         }
         s->gtiles = 0;
         if (ok) {
+            std::vector<int> te(tiles.size());
+            for (size_t j = 0; j < tiles.size(); ++j) te[j] = hrp[tiles[j]];
             ALLOC(s->gtile_row, tiles.size());
+            ALLOC(s->gtile_e, tiles.size());
             LPCG_HIP(hipMemcpyAsync(s->gtile_row, tiles.data(), sizeof(int) * tiles.size(), hipMemcpyHostToDevice,
                                     st));
+            LPCG_HIP(hipMemcpyAsync(s->gtile_e, te.data(), sizeof(int) * te.size(), hipMemcpyHostToDevice, st));
             LPCG_HIP(hipStreamSynchronize(st));
             s->gtiles = (int)tiles.size() - 1;
         }

@@ -18,6 +18,9 @@
 //                initial-guess head x^_i (in the frame of A/s and b/rms(b))
 #include <algorithm>
 #include <cstring>
+#include <mutex>
+#include <utility>
+#include <vector>
 
 #include "device_util.h"
 #include "kern_gnn.h"
@@ -56,7 +59,7 @@ GnnOff gnn_offsets(int h, int n_mp, bool x_head) {
 // buffers come first, at offsets common to both layouts.
 struct GnnWs {
     size_t sys_s, sys_rms, norm_part;
-    size_t V[kMaxMp + 1], Pa[kMaxMp], Pb[kMaxMp], E[kMaxMp + 1], M;
+    size_t V[kMaxMp + 1], Pa[kMaxMp], Pb[kMaxMp], E[kMaxMp + 1], M, Ahat;
     size_t d, xhat, gxhat;
     // backward (train only)
     size_t gd, gE[2], gV[2], gVmlp, gm, GH, G1, GVN, GH1, H1, Mt, gPa, gPb, HD, GHD, Henc, GHenc, Xn, Xe;
@@ -109,7 +112,10 @@ GnnWs gnn_ws_layout(const lpcg_system *s, int h, int n_mp, bool train) {
         w.Pa[i] = take(2 * n * h);
         w.Pb[i] = take(2 * n * h);
     }
-    if (fused) w.M = take(2 * n * h);  // aggregated messages, BF16
+    if (fused) {
+        w.M = take(2 * n * h);  // aggregated messages, BF16
+        w.Ahat = take(4 * nnz);  // edge inputs A_e / s, FP32
+    }
     else
         for (int i = 0; i < nv; ++i) w.E[i] = take(2 * nnz * h);
     w.d = take(4 * nnz);
@@ -439,11 +445,11 @@ struct FusedChain {
 
 template <int CH, bool DEC>
 __global__ void __launch_bounds__(kGnnThreads) k_fused_edge(
-    int nnz, int ntiles, const int *__restrict__ tile_row, const int *__restrict__ rowptr,
-    const int *__restrict__ erow, const int *__restrict__ col, const double *__restrict__ aval,
-    const int *__restrict__ row_sys, const double *__restrict__ sys_s, const float *__restrict__ P, MlpOff enc,
-    FusedChain ch, MlpOff md, const __bf16 *__restrict__ V, __bf16 *__restrict__ M, float *__restrict__ d,
-    int zero) {
+    int nnz, int ntiles, const int *__restrict__ tile_row, const int *__restrict__ tile_e,
+    const int *__restrict__ rowptr, const int *__restrict__ erow, const int *__restrict__ col,
+    const double *__restrict__ aval, const int *__restrict__ row_sys, const double *__restrict__ sys_s,
+    float *__restrict__ ahat, const float *__restrict__ P, MlpOff enc, FusedChain ch, MlpOff md,
+    const __bf16 *__restrict__ V, __bf16 *__restrict__ M, float *__restrict__ d, int zero) {
     constexpr int H = 32, S = H / 16;
     constexpr int NW = CH > 0 ? CH : 1;
     // FP32 constants: encoder W0, b0, b1; b0, b1 of each chain layer; decoder
@@ -476,28 +482,73 @@ __global__ void __launch_bounds__(kGnnThreads) k_fused_edge(
     __syncthreads();
     const int lane = lane_id(), wv = threadIdx.x / kWave;
     const int tiles = DEC ? (nnz + 31) / 32 : ntiles;
-    for (int tile = blockIdx.x * 4 + wv; tile < tiles; tile += gridDim.x * 4) {
+    const int rr = lane & 31;
+    // A tile's index data: its rows and entries, the lane's edge (row r,
+    // column c, input x = A_e / s) and the entry range of the row the lane
+    // sums.  The next tile's are loaded while the current one computes (one
+    // tile ahead, unconditionally: the last tile is re-read at the end), so
+    // only the gathers that depend on them wait a full memory round trip.
+    struct TileIn {
+        int e0, r0, r1, e, r, c, ka, kb;
+        bool valid, sums;
+        float x;
+    };
+    auto load_in = [&](int t) {
+        TileIn q;
+        int e_end;
+        if (DEC) {
+            q.r0 = q.r1 = q.e0 = 0;
+            q.e = t * 32 + rr;
+            e_end = nnz;
+        } else {
+            q.r0 = tile_row[t];
+            q.r1 = tile_row[t + 1];
+            q.e0 = tile_e[t];
+            q.e = q.e0 + rr;
+            e_end = tile_e[t + 1];
+        }
+        q.valid = q.e < e_end;
+        const int ec = q.valid ? q.e : 0;
+        q.r = erow[ec];
+        q.c = col[ec];
+        q.sums = !DEC && q.r0 + rr < q.r1;
+        const int ra = q.sums ? q.r0 + rr : 0;
+        q.ka = rowptr[ra] - q.e0;
+        q.kb = rowptr[ra + 1] - q.e0;
+        if (CH == 0 && !DEC) q.x = (float)(aval[ec] / sys_s[row_sys[q.r]]);  // first pass: A_e / s
+        else q.x = ahat[ec];                                                  // later: as kept
+        if (!q.valid) q.x = 0.f;
+        return q;
+    };
+    const int stride = gridDim.x * 4;
+    int tile = blockIdx.x * 4 + wv;
+    TileIn nxt = load_in(min(tile, tiles - 1));
+    for (; tile < tiles; tile += stride) {
+        const TileIn ti = nxt;
+        nxt = load_in(min(tile + stride, tiles - 1));
         // `zero` is 0 at run time; the compiler cannot prove it, so the weight
         // operands and constants below are re-read from LDS in every tile
         // rather than hoisted into registers for the whole loop (over a
         // hundred registers for a three-layer chain, one wave per SIMD)
         const int z = zero * tile;
         const float *C = cst + z;
-        int e, e_end, e0 = 0, r0 = 0, r1 = 0;
-        if (DEC) {
-            e = tile * 32 + (lane & 31);
-            e_end = nnz;
-        } else {
-            r0 = tile_row[tile];
-            r1 = tile_row[tile + 1];
-            e0 = rowptr[r0];
-            e = e0 + (lane & 31);
-            e_end = rowptr[r1];
+        const int e = ti.e, r0 = ti.r0, r = ti.r, c = ti.c, ka = ti.ka, kb = ti.kb;
+        const bool valid = ti.valid;
+        const float x = ti.x;
+        if (CH == 0 && !DEC && valid && lane < 32) ahat[e] = x;  // kept for the later passes
+        // every gather of the tile issued up front, so their latencies overlap
+        // instead of following each other layer by layer
+        bf16x4 gpa[NW][4], gpb[NW][4], gv[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int f = acc_feat(0, 4 * q, lane);
+#pragma unroll
+            for (int u = 0; u < CH; ++u) {
+                gpa[u][q] = *reinterpret_cast<const bf16x4 *>(ch.pa[u] + (size_t)r * H + f);
+                gpb[u][q] = *reinterpret_cast<const bf16x4 *>(ch.pb[u] + (size_t)c * H + f);
+            }
+            if (!DEC) gv[q] = *reinterpret_cast<const bf16x4 *>(V + (size_t)c * H + f);
         }
-        const bool valid = e < e_end;
-        const int r = valid ? erow[e] : 0, c = valid ? col[e] : 0;
-        // encoder: E_0 = relu(x W0 + b0) W1 + b1, x = A_e / s
-        const float x = valid ? (float)(aval[e] / sys_s[row_sys[r]]) : 0.f;
         f32x16 acc[1];
         acc[0] = zero16();
 #pragma unroll
@@ -523,14 +574,9 @@ __global__ void __launch_bounds__(kGnnThreads) k_fused_edge(
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int f = acc_feat(0, 4 * q, lane);
-                bf16x4 ga, gb;
-                if (valid) {
-                    ga = *reinterpret_cast<const bf16x4 *>(ch.pa[u] + (size_t)r * H + f);
-                    gb = *reinterpret_cast<const bf16x4 *>(ch.pb[u] + (size_t)c * H + f);
-                }
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
-                    const float add = valid ? (float)ga[t] + (float)gb[t] : 0.f;
+                    const float add = valid ? (float)gpa[u][q][t] + (float)gpb[u][q][t] : 0.f;
                     hid[0][4 * q + t] = fmaxf(hid[0][4 * q + t] + add + b0[f + t], 0.f);
                 }
             }
@@ -560,35 +606,24 @@ __global__ void __launch_bounds__(kGnnThreads) k_fused_edge(
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int f = acc_feat(0, 4 * q, lane);
-                bf16x4 v4;
-                if (valid) v4 = *reinterpret_cast<const bf16x4 *>(V + (size_t)c * H + f);
 #pragma unroll
                 for (int t = 0; t < 4; ++t)
-                    mw[lane & 31][f + t] = valid ? (float)(__bf16)acc[0][4 * q + t] * (float)v4[t] : 0.f;
+                    mw[lane & 31][f + t] = valid ? (float)(__bf16)acc[0][4 * q + t] * (float)gv[q][t] : 0.f;
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            // row sums in CSR order: lane l sums 16 features (half l / 32) of
-            // row r0 + l % 32
-            const int rr = lane & 31, fh = (lane >> 5) * 16;
-            if (r0 + rr < r1) {
-                const int ka = rowptr[r0 + rr] - e0, kb = rowptr[r0 + rr + 1] - e0;
-                float sum[16];
-#pragma unroll
-                for (int j = 0; j < 16; ++j) sum[j] = 0.f;
-                for (int k = ka; k < kb; ++k)
-#pragma unroll
-                    for (int j = 0; j < 16; ++j) sum[j] += mw[k][fh + j];
-                bf16x8 lo, hi;
-#pragma unroll
-                for (int j = 0; j < 8; ++j) {
-                    lo[j] = (__bf16)sum[j];
-                    hi[j] = (__bf16)sum[8 + j];
-                }
-                __bf16 *dst = M + (size_t)(r0 + rr) * H + fh;
-                *reinterpret_cast<bf16x8 *>(dst) = lo;
-                *reinterpret_cast<bf16x8 *>(dst + 8) = hi;
+            // row sums in CSR order, one (row, feature) pair per lane and step:
+            // pair p = row * H + feature for p = lane, lane + 64, ...; lane rr
+            // holds row rr's entry range (ka, kb)
+            const int pairs = (ti.r1 - r0) * H;
+            for (int pb = 0; pb < pairs; pb += kWave) {
+                const int pr = pb + lane;
+                const int row = min(pr, pairs - 1) / H, f = pr % H;
+                const int a0 = __shfl(ka, row), a1 = __shfl(kb, row);
+                float sum = 0.f;
+                for (int k = a0; k < a1; ++k) sum += mw[k][f];
+                if (pr < pairs) M[(size_t)(r0 + row) * H + f] = (__bf16)sum;
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
@@ -787,6 +822,32 @@ __global__ void k_zero_f32(int n, float *__restrict__ p) {
 
 int gnn_blocks(long rows) { return std::max(1, std::min(kMaxGnnBlocks, nblk(rows, 32 * 4))); }
 
+// Grid of a fused-pass kernel: as many 256-thread blocks as the chip holds
+// at once (the kernel's occupancy, queried once per kernel, times the
+// compute units), never more than one per 4 tiles.  Each wave then loops
+// over its tiles, and the whole grid is resident.
+int resident_grid(const void *kfn, long tiles) {
+    static std::mutex mu;
+    static std::vector<std::pair<const void *, int>> cache;
+    int per = 0;
+    {
+        std::lock_guard<std::mutex> lock(mu);
+        for (auto &c : cache)
+            if (c.first == kfn) per = c.second;
+        if (per == 0) {
+            int dev = 0, cus = 0, occ = 0;
+            if (hipGetDevice(&dev) != hipSuccess ||
+                hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+                hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kfn, kGnnThreads, 0) != hipSuccess || occ <= 0)
+                per = kMaxGnnBlocks;
+            else
+                per = occ * cus;
+            cache.emplace_back(kfn, per);
+        }
+    }
+    return (int)std::max(1L, std::min((long)per, (tiles + 3) / 4));
+}
+
 template <int H>
 int forward_impl(const lpcg_system *s, const lpcg_gnn *net, const double *b, unsigned char *ws,
                  const GnnWs &L, bool train, float *lval, float *utval, hipStream_t st) {
@@ -811,14 +872,15 @@ int forward_impl(const lpcg_system *s, const lpcg_gnn *net, const double *b, uns
         k_enc<H, true><<<gnn_blocks(s->n), kGnnThreads, 0, st>>>(s->n, P, o.node_enc, b, s->erow, s->row_sys,
                                                                   sys_rms, V(0), nullptr);
         __bf16 *M = (__bf16 *)(ws + L.M);
+        float *ahat = (float *)(ws + L.Ahat);
         FusedChain ch{};
         for (int t = 0; t <= T; ++t) {
-            const int g = t < T ? gnn_blocks((long)s->gtiles * 32) : gnn_blocks(s->nnz);
+            const long tiles = t < T ? s->gtiles : (s->nnz + 31) / 32;
             switch (t + (t == T ? 8 : 0)) {
-#define LPCG_FUSED(CHN, DECN)                                                                                     \
-    k_fused_edge<CHN, DECN><<<g, kGnnThreads, 0, st>>>(s->nnz, s->gtiles, s->gtile_row, s->rowptr, s->erow,   \
-                                                       s->colind, s->val64, s->row_sys, sys_s, P, o.edge_enc, ch, \
-                                                       o.dec, V(t), M, d, 0)
+#define LPCG_FUSED(CHN, DECN)                                                                                       \
+    k_fused_edge<CHN, DECN><<<resident_grid((const void *)k_fused_edge<CHN, DECN>, tiles), kGnnThreads, 0, st>>>( \
+        s->nnz, s->gtiles, s->gtile_row, s->gtile_e, s->rowptr, s->erow, s->colind, s->val64, s->row_sys, sys_s,    \
+        ahat, P, o.edge_enc, ch, o.dec, V(t), M, d, 0)
                 case 0: LPCG_FUSED(0, false); break;
                 case 1: LPCG_FUSED(1, false); break;
                 case 2: LPCG_FUSED(2, false); break;

@@ -133,6 +133,7 @@ struct lpcg_system {
     // holds the whole rows gtile_row[j] .. gtile_row[j+1]-1, at most 32 stored
     // entries in all (0 tiles: some row has more than 32 entries).
     int *gtile_row = nullptr;
+    int *gtile_e = nullptr;  // first stored entry of each tile's rows: rowptr[gtile_row[j]]
     int gtiles = 0;
     // batched solves: row segments of at most kSegRows rows that never cross
     // a system (one block each), the segment range of every system, and the
