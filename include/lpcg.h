@@ -305,7 +305,9 @@ int lpcg_blocked_schedule(int32_t n, const int32_t *rowptr, const int32_t *col, 
  * workgroup (narrow levels only), blocked with 512, 1024, 2048 consecutive
  * rows and banded with 1024, 2048 rows in 2, 4, 8 runs (where the rows
  * tile), and dependency driven with 64 .. 4096 waves.  It keeps the fastest
- * per direction for every later call on the system.  It then times the
+ * per direction for every later call on the system (on a two-level system,
+ * a red-black grid in colour order, it keeps the level mode in both
+ * directions, which lets the PCG apply L L^T in two fused launches).  It then times the
  * FP32 SpMV w = A p for G = 4, 8, 16, 32, 64 lanes per row (64 / G rows per
  * wavefront) on grids of up to 512, 1024 and 2048 blocks and keeps the
  * fastest for the PCG's product and lpcg_spmv; those table entries have
@@ -368,6 +370,19 @@ typedef struct {
 int lpcg_pcg_solve(lpcg_system *sys, const lpcg_precond *P, const double *b,
                    double *x, const lpcg_solve_opts *opts, lpcg_result *res,
                    double *hist, double *coef, hipStream_t stream);
+
+/* Timing aid for the PCG iteration's own kernels: from x = 0 and right-hand
+ * side b (device FP64 [n], caller's numbering) with preconditioner P, the
+ * iteration runs `reps` times after one warm-up, launched eagerly in its
+ * three parts with HIP events between them on `stream`: out_us (HOST, 3)
+ * receives the mean duration in microseconds of [0] the application
+ * z = (L L^T)^-1 r (LLT only; 0 otherwise), [1] the SpMV w = A p with
+ * p = z + beta p_prev and the p.w reduction, [2] the x, r update with
+ * ||r||^2.  The iteration never converges (tolerance 0).  Synchronous; uses
+ * the system's work vectors (not concurrent with a solve on the system).
+ * Errors: EINVAL. */
+int lpcg_time_pcg_kernels(lpcg_system *sys, const lpcg_precond *P, const double *b, int32_t reps,
+                          double *out_us, hipStream_t stream);
 
 /* Condition-number estimate of the preconditioned operator (appendix
  * "Condition Number Comparison"): extreme eigenvalues of the CG-Lanczos

@@ -976,6 +976,10 @@ extern "C" int lpcg_autotune(lpcg_system *s, const float *l_val, const float *ut
                 s->ic0_tuned = true;
             }
         }
+        // a two-level system applies L L^T in the PCG with the fused pair
+        // (two launches for both directions), which needs the level mode in
+        // both directions: it beats any pair of standalone substitutions
+        if (s->two_level_p > 0) best_c = TrsvCfg{1, 0, 1, 1};
         if (best_c.mode == 3) {  // leave the winner's schedule in place
             const int rc = blk_prepare(s, dir, best_c.blk, best_c.runs);
             if (rc) return rc;

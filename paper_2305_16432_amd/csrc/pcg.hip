@@ -518,10 +518,11 @@ bool two_level_path(const lpcg_system *s) {
     return s->two_level_p > 0 && s->two_level_p < s->n && s->trsv[0].mode == 1 && s->trsv[1].mode == 1;
 }
 
+// One iteration = the application z = P^-1 r (LLT only), the SpMV with the
+// new search direction and p.w, and the x, r update; enqueued in parts so
+// that the timing aid can bracket each.
 template <int KIND>
-int enqueue_iteration(const lpcg_system *s, const Args &a, hipStream_t st) {
-    const int vb = s->vec_blocks;
-    const int sb = s->spmv_blocks;
+int enqueue_apply(const lpcg_system *s, const Args &a, hipStream_t st) {
     if (KIND == LPCG_PC_LLT && two_level_path(s)) {
         const int G = s->trsv_g, p = s->two_level_p;
         const int nbs = level_blocks(s->n - p, G), nbp = level_blocks(p, G);
@@ -580,6 +581,13 @@ int enqueue_iteration(const lpcg_system *s, const Args &a, hipStream_t st) {
             }
         }
     }
+    LPCG_LAUNCH_CHECK();
+    return LPCG_OK;
+}
+
+template <int KIND>
+int enqueue_spmv(const lpcg_system *s, const Args &a, hipStream_t st) {
+    const int sb = s->spmv_blocks;
     switch (s->spmv_group) {
         case 4: k_spmv_pw<4, KIND><<<sb, VT, 0, st>>>(a); break;
         case 8: k_spmv_pw<8, KIND><<<sb, VT, 0, st>>>(a); break;
@@ -587,9 +595,22 @@ int enqueue_iteration(const lpcg_system *s, const Args &a, hipStream_t st) {
         case 32: k_spmv_pw<32, KIND><<<sb, VT, 0, st>>>(a); break;
         default: k_spmv_pw<64, KIND><<<sb, VT, 0, st>>>(a); break;
     }
-    k_xr<KIND><<<vb, VT, 0, st>>>(a);
     LPCG_LAUNCH_CHECK();
     return LPCG_OK;
+}
+
+template <int KIND>
+int enqueue_xr(const lpcg_system *s, const Args &a, hipStream_t st) {
+    k_xr<KIND><<<s->vec_blocks, VT, 0, st>>>(a);
+    LPCG_LAUNCH_CHECK();
+    return LPCG_OK;
+}
+
+template <int KIND>
+int enqueue_iteration(const lpcg_system *s, const Args &a, hipStream_t st) {
+    int rc;
+    if ((rc = enqueue_apply<KIND>(s, a, st)) || (rc = enqueue_spmv<KIND>(s, a, st))) return rc;
+    return enqueue_xr<KIND>(s, a, st);
 }
 
 template <int KIND>
@@ -666,30 +687,15 @@ int run_solve(lpcg_system *s, const Args &a, const lpcg_solve_opts &o, int &iter
     return LPCG_OK;
 }
 
-}  // namespace
-}  // namespace lpcg
-
-using namespace lpcg;
-
-extern "C" int lpcg_pcg_solve(lpcg_system *s, const lpcg_precond *P, const double *b, double *x,
-                              const lpcg_solve_opts *opts, lpcg_result *res, double *hist, double *coef,
-                              hipStream_t st) {
-    if (!s || !P || !b || !x || !opts || !res || !(opts->tol >= 0)) {
-        set_error("lpcg_pcg_solve: invalid arguments");
-        return LPCG_EINVAL;
-    }
-    if (P->kind == LPCG_PC_LLT && (!P->l_val || !P->ut_val)) {
-        set_error("lpcg_pcg_solve: LLT preconditioner needs l_val and ut_val");
-        return LPCG_EINVAL;
-    }
-    if (P->kind != LPCG_PC_LLT && P->kind != LPCG_PC_JACOBI && P->kind != LPCG_PC_NONE) {
-        set_error("lpcg_pcg_solve: unknown preconditioner kind %d", P->kind);
-        return LPCG_EINVAL;
-    }
-    Args a{};
+// Kernel arguments of a solve on system s with preconditioner P from x (both
+// in the caller's numbering; a reordered system works on internal copies),
+// with the factor's values packed for the configured substitution modes.
+int build_args(lpcg_system *s, const lpcg_precond *P, const double *b, double *x, double tol, int maxit,
+               double *hist, double *coef, Args &a, hipStream_t st) {
+    a = Args{};
     a.n = s->n;
     a.np_vec = s->vec_blocks;
-    a.maxit = opts->maxit > 0 ? opts->maxit : s->n;
+    a.maxit = maxit > 0 ? maxit : s->n;
     a.kind = P->kind;
     a.backoff_f = s->trsv[0].backoff;
     a.backoff_b = s->trsv[1].backoff;
@@ -758,7 +764,7 @@ extern "C" int lpcg_pcg_solve(lpcg_system *s, const lpcg_precond *P, const doubl
     a.hist = hist;
     a.coef = coef;
     a.ctrl = s->ctrl;
-    a.tol2 = opts->tol * opts->tol;
+    a.tol2 = tol * tol;
     if (P->kind == LPCG_PC_LLT) {  // the factor's values in the layouts of the single-workgroup and blocked modes
         for (int d = 0; d < 2; ++d) {
             int rc = LPCG_OK;
@@ -780,6 +786,35 @@ extern "C" int lpcg_pcg_solve(lpcg_system *s, const lpcg_precond *P, const doubl
         int rc = lpcg_jacobi(s, s->dinv, st);
         if (rc) return rc;
     }
+    return LPCG_OK;
+}
+
+}  // namespace
+}  // namespace lpcg
+
+using namespace lpcg;
+
+extern "C" int lpcg_pcg_solve(lpcg_system *s, const lpcg_precond *P, const double *b, double *x,
+                              const lpcg_solve_opts *opts, lpcg_result *res, double *hist, double *coef,
+                              hipStream_t st) {
+    if (!s || !P || !b || !x || !opts || !res || !(opts->tol >= 0)) {
+        set_error("lpcg_pcg_solve: invalid arguments");
+        return LPCG_EINVAL;
+    }
+    if (P->kind == LPCG_PC_LLT && (!P->l_val || !P->ut_val)) {
+        set_error("lpcg_pcg_solve: LLT preconditioner needs l_val and ut_val");
+        return LPCG_EINVAL;
+    }
+    if (P->kind != LPCG_PC_LLT && P->kind != LPCG_PC_JACOBI && P->kind != LPCG_PC_NONE) {
+        set_error("lpcg_pcg_solve: unknown preconditioner kind %d", P->kind);
+        return LPCG_EINVAL;
+    }
+    Args a{};
+    {
+        const int rc = build_args(s, P, b, x, opts->tol, opts->maxit, hist, coef, a, st);
+        if (rc) return rc;
+    }
+
     res->iters = 0;
     res->restarts = 0;
     res->status = LPCG_OK;
@@ -826,6 +861,71 @@ extern "C" int lpcg_pcg_solve(lpcg_system *s, const lpcg_precond *P, const doubl
 // beta_{i-1}/alpha_{i-1}, T_i,i+1 = sqrt(beta_i)/alpha_i.  Each extreme is
 // found by bisection on the Sturm count (number of eigenvalues below x) inside
 // the Gershgorin interval.
+namespace lpcg {
+namespace {
+
+struct EvPair {
+    hipEvent_t e[4] = {nullptr, nullptr, nullptr, nullptr};
+    ~EvPair() {
+        for (hipEvent_t &x : e)
+            if (x) hipEventDestroy(x);
+    }
+};
+
+template <int KIND>
+int time_parts(lpcg_system *s, const Args &a, int reps, double *out_us, hipStream_t st) {
+    EvPair ev;
+    for (hipEvent_t &x : ev.e) LPCG_HIP(hipEventCreate(&x));
+    k_setup<KIND><<<s->vec_blocks, VT, 0, st>>>(a);
+    k_setup_scal<KIND><<<1, VT, 0, st>>>(a);
+    LPCG_LAUNCH_CHECK();
+    double tot[3] = {0, 0, 0};
+    for (int r = 0; r <= reps; ++r) {  // the first round warms up
+        int rc;
+        LPCG_HIP(hipEventRecord(ev.e[0], st));
+        if ((rc = enqueue_apply<KIND>(s, a, st))) return rc;
+        LPCG_HIP(hipEventRecord(ev.e[1], st));
+        if ((rc = enqueue_spmv<KIND>(s, a, st))) return rc;
+        LPCG_HIP(hipEventRecord(ev.e[2], st));
+        if ((rc = enqueue_xr<KIND>(s, a, st))) return rc;
+        LPCG_HIP(hipEventRecord(ev.e[3], st));
+        LPCG_HIP(hipEventSynchronize(ev.e[3]));
+        if (r == 0) continue;
+        for (int k = 0; k < 3; ++k) {
+            float ms = 0;
+            LPCG_HIP(hipEventElapsedTime(&ms, ev.e[k], ev.e[k + 1]));
+            tot[k] += ms;
+        }
+    }
+    for (int k = 0; k < 3; ++k) out_us[k] = 1e3 * tot[k] / reps;
+    if (KIND != LPCG_PC_LLT) out_us[0] = 0.0;  // no application kernel
+    return LPCG_OK;
+}
+
+}  // namespace
+}  // namespace lpcg
+
+extern "C" int lpcg_time_pcg_kernels(lpcg_system *s, const lpcg_precond *P, const double *b, int32_t reps,
+                                     double *out_us, hipStream_t st) {
+    if (!s || !P || !b || reps <= 0 || !out_us || (P->kind == LPCG_PC_LLT && (!P->l_val || !P->ut_val)) ||
+        (P->kind != LPCG_PC_LLT && P->kind != LPCG_PC_JACOBI && P->kind != LPCG_PC_NONE)) {
+        set_error("lpcg_time_pcg_kernels: invalid arguments");
+        return LPCG_EINVAL;
+    }
+    // x = 0 in a work vector; tolerance 0 so that the iterations never stop
+    double *x0 = s->t64c;
+    LPCG_HIP(hipMemsetAsync(x0, 0, sizeof(double) * (size_t)s->n, st));
+    Args a{};
+    int rc = build_args(s, P, b, x0, 0.0, 1 << 30, nullptr, nullptr, a, st);
+    if (rc) return rc;
+    if (P->kind == LPCG_PC_LLT) rc = time_parts<LPCG_PC_LLT>(s, a, reps, out_us, st);
+    else if (P->kind == LPCG_PC_JACOBI) rc = time_parts<LPCG_PC_JACOBI>(s, a, reps, out_us, st);
+    else rc = time_parts<LPCG_PC_NONE>(s, a, reps, out_us, st);
+    if (rc) return rc;
+    LPCG_HIP(hipStreamSynchronize(st));
+    return LPCG_OK;
+}
+
 extern "C" int lpcg_lanczos_extremes(const double *coef, int32_t k, double *lmin, double *lmax) {
     if (!coef || k < 1 || !lmin || !lmax) {
         set_error("lpcg_lanczos_extremes: invalid arguments");

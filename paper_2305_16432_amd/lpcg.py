@@ -408,6 +408,18 @@ def pcg_solve_ir(sys: System, kind: int, b, x=None, l_val=None, ut_val=None, din
     return x, [{f: getattr(r, f) for f, _ in _Result._fields_ if f != "reserved"} for r in res]
 
 
+def time_pcg_kernels(sys: System, kind: int, b, l_val=None, ut_val=None, dinv=None, reps: int = 20):
+    """Mean microseconds of one PCG iteration's parts, launched eagerly with
+    events between them: (application of L L^T, SpMV with p and p.w, x/r
+    update)."""
+    b = _dev(b, torch.float64).contiguous()
+    P = _Precond(kind, _ptr(l_val), _ptr(ut_val), _ptr(dinv))
+    out = (C.c_double * 3)()
+    _check(lib().lpcg_time_pcg_kernels(sys.handle, C.byref(P), _ptr(b), C.c_int32(reps), out, _stream()),
+           "lpcg_time_pcg_kernels")
+    return tuple(out[i] for i in range(3))
+
+
 def lanczos_extremes(coef, iters: int):
     """(lambda_min, lambda_max) of the preconditioned operator estimated from
     the PCG coefficients (host computation in the library)."""

@@ -160,3 +160,20 @@ def test_pcg_nonzero_initial_guess_and_restart():
     x, res = lpcg.pcg_solve(S, lpcg.PC_JACOBI, cuda_f64(b), x=cuda_f64(x0), tol=1e-10,
                             max_restarts=3)
     assert res["status"] == lpcg.OK and res["relres_true"] <= 1e-10
+
+
+@pytest.mark.parametrize("ordering", [0, 1])
+def test_time_pcg_kernels_parts(ordering):
+    """The timing aid runs the iteration's three parts and returns positive
+    durations; with Jacobi the application part is empty (0).  A solve
+    afterwards on the same system is unaffected (it resets its own state)."""
+    A, b = g.heat_system_3d(16, 1e-3, 3, 4)
+    S = gpu_system(A, None, ordering)
+    bd = cuda_f64(b)
+    l, ut, _ = lpcg.ic0(S)
+    t = lpcg.time_pcg_kernels(S, lpcg.PC_LLT, bd, l_val=l, ut_val=ut, reps=5)
+    assert all(v > 0 for v in t), t
+    tj = lpcg.time_pcg_kernels(S, lpcg.PC_JACOBI, bd, reps=5)
+    assert tj[0] == 0 and tj[1] > 0 and tj[2] > 0, tj
+    x, res = lpcg.pcg_solve(S, lpcg.PC_LLT, bd, l_val=l, ut_val=ut, tol=1e-6, max_restarts=2)
+    assert res["status"] == 0 and O.true_relres(A, b, host(x)) <= 1e-6
