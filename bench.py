@@ -34,7 +34,7 @@ sys.path.insert(0, ROOT)
 # natural order: the network trained on 32^3 heat steps and fine-tuned on 64^3 ones
 FEM_WEIGHTS = os.path.join(ROOT, "paper_2305_16432_amd", "weights", "fem2d_h64_mp5.npz")
 WEIGHTS = {"natural": os.path.join(ROOT, "paper_2305_16432_amd", "weights", "heat3d_h32_mp3_ft64.npz"),
-           "color": os.path.join(ROOT, "paper_2305_16432_amd", "weights", "heat3d_h32_mp3_color.npz")}
+           "color": os.path.join(ROOT, "paper_2305_16432_amd", "weights", "heat3d_h32_mp3_color3.npz")}
 PEAK_HBM = 8000.0  # GB/s, MI355X HBM3E
 # HBM bytes of the roofline kernel measured with rocprofv3 --pmc FETCH_SIZE /
 # WRITE_SIZE (scaled by the same counters on a copy of known size); valid
@@ -70,6 +70,19 @@ def hbm_bytes_sptrsv(info):
     right-hand side and the result (8 n), the level-order row list (4 n)."""
     n, nl = info["n"], info["nnz_l"]
     return 8 * nl + 4 * (n + 1) + 8 * n + 4 * n
+
+
+def hbm_bytes_pcg_parts(info, two_level):
+    """Algorithmic bytes of the PCG iteration's three parts (FP32 vectors and
+    values, int32 indices, FP64 x): the application z = (L L^T)^-1 r (two
+    fused launches on a two-level system: L's values and indices in each
+    half, r read twice, z written and read once; else the two substitutions),
+    the SpMV w = A p with p = z + beta p_prev (A, z and p_prev read, p and w
+    written), and the x, r update (x read and written in FP64, r read and
+    written, p and w read)."""
+    n, nnz, nl = info["n"], info["nnz"], info["nnz_l"]
+    apply = 2 * (8 * nl + 4 * (n + 1)) + 16 * n if two_level else 2 * hbm_bytes_sptrsv(info)
+    return {"apply": apply, "spmv_p": 8 * nnz + 4 * (n + 1) + 16 * n, "xr": 32 * n}
 
 
 def hbm_bytes_spmv(info):
@@ -504,8 +517,16 @@ def main():
         ms_b = lpcg.time_sptrsv(S, True, lval, utval, rhs, reps=50)
         ms_spmv = lpcg.time_spmv(S, rhs, reps=100)
         bt, bs = hbm_bytes_sptrsv(info), hbm_bytes_spmv(info)
+        # the PCG iteration's own kernels, timed live (HIP events between
+        # its three parts, launched on this stream)
+        parts_us = lpcg.time_pcg_kernels(S, lpcg.PC_LLT, bd, l_val=lval, ut_val=utval, reps=50)
+        two_level = info["nlev_fwd"] == 2 and cfg[0]["mode"] == 1 and cfg[1]["mode"] == 1
+        pb = hbm_bytes_pcg_parts(info, two_level)
+        parts = {k: dict(us=u, bytes=pb[k], gbs=pb[k] / (u * 1e-6) / 1e9)
+                 for k, u in zip(("apply", "spmv_p", "xr"), parts_us)}
         kernels[ordering] = dict(
-            levels=info["nlev_fwd"], trsv_cfg=cfg,
+            levels=info["nlev_fwd"], trsv_cfg=cfg, spmv_cfg=lpcg.get_trsv_cfg(S, 2), pcg_parts=parts,
+            apply_form="two-level pair" if two_level else "two substitutions",
             sptrsv_fwd=dict(us=ms_f * 1e3, bytes=bt, gbs=bt / (ms_f * 1e-3) / 1e9),
             sptrsv_bwd=dict(us=ms_b * 1e3, bytes=bt, gbs=bt / (ms_b * 1e-3) / 1e9),
             spmv=dict(us=ms_spmv * 1e3, bytes=bs, gbs=bs / (ms_spmv * 1e-3) / 1e9))
@@ -545,7 +566,14 @@ def main():
                     iters=r["iters"], ordering=r["ordering"])
     head = best("learned") or best("ic0")
     head_order = results[head]["ordering"]
-    kf = kernels[head_order]["sptrsv_fwd"]
+    # roofline: the iteration part that takes the most time per iteration in
+    # the value's ordering (measured live above)
+    parts = kernels[head_order]["pcg_parts"]
+    dom = max(parts, key=lambda k: parts[k]["us"])
+    kf = parts[dom]
+    dom_name = {"apply": f"L L^T application ({kernels[head_order]['apply_form']}, {head_order} order)",
+                "spmv_p": f"k_spmv_pw: p = z + beta p_prev, w = A p, p.w ({head_order} order)",
+                "xr": f"k_xr: x += alpha p, r -= alpha w, ||r||^2 ({head_order} order)"}[dom]
     ic0_same = "ic0" if head_order == "natural" else f"ic0_{head_order}"
     out = {
         "metric": "time-to-1e-6 rel. residual (ms) + PCG iters: learned-L vs IC(0), 3D 64³",
@@ -572,9 +600,9 @@ def main():
                              "(the paper's protocol); mean_all_ms per method beside it",
                    "k_seed": args.k_seed, "u0_seed": args.u_seed},
         "methods": results,
-        "roofline": {"bound": "hbm", "kernel": f"sptrsv_forward ({head_order} order)",
+        "roofline": {"bound": "hbm", "kernel": dom_name,
                      "achieved": kf["gbs"], "peak": PEAK_HBM, "unit": "GB/s", "frac": kf["gbs"] / PEAK_HBM,
-                     "traffic": measured_traffic(f"sptrsv_forward ({head_order} order)"), "bytes_per_launch": kf["bytes"], "us_per_launch": kf["us"],
+                     "traffic": measured_traffic(dom_name), "bytes_per_launch": kf["bytes"], "us_per_launch": kf["us"],
                      "levels": kernels[head_order]["levels"], "kernels": kernels},
         "cpu_baseline": cpu,
         "seeds": per_seed if args.seeds > 0 and "natural" in args.orderings.split(",") else None,
