@@ -520,12 +520,20 @@ __global__ void __launch_bounds__(kGnnThreads) k_fused_edge(
         if (!q.valid) q.x = 0.f;
         return q;
     };
-    const int stride = gridDim.x * 4;
-    int tile = blockIdx.x * 4 + wv;
-    TileIn nxt = load_in(min(tile, tiles - 1));
-    for (; tile < tiles; tile += stride) {
+    // XCD-aware mapping: blocks are dispatched round-robin over the 8 XCDs,
+    // so block b runs on XCD b % 8; each XCD takes one contiguous eighth of
+    // the tiles (rows), and the node rows its tiles gather (the neighbours of
+    // a contiguous row range) stay in that XCD's L2.
+    const int nx = gridDim.x % 8 == 0 ? 8 : 1;
+    const int xcd = blockIdx.x % nx, nbx = gridDim.x / nx;
+    const int t_lo = (int)((long)tiles * xcd / nx), t_hi = (int)((long)tiles * (xcd + 1) / nx);
+    if (t_lo >= t_hi) return;
+    const int stride = nbx * 4;
+    int tile = t_lo + (blockIdx.x / nx) * 4 + wv;
+    TileIn nxt = load_in(min(tile, t_hi - 1));
+    for (; tile < t_hi; tile += stride) {
         const TileIn ti = nxt;
-        nxt = load_in(min(tile + stride, tiles - 1));
+        nxt = load_in(min(tile + stride, t_hi - 1));
         // `zero` is 0 at run time; the compiler cannot prove it, so the weight
         // operands and constants below are re-read from LDS in every tile
         // rather than hoisted into registers for the whole loop (over a
@@ -845,7 +853,9 @@ int resident_grid(const void *kfn, long tiles) {
             cache.emplace_back(kfn, per);
         }
     }
-    return (int)std::max(1L, std::min((long)per, (tiles + 3) / 4));
+    long g = std::max(1L, std::min((long)per, (tiles + 3) / 4));
+    if (g >= 64) g -= g % 8;  // whole XCD rounds (the kernels map tiles per XCD)
+    return (int)g;
 }
 
 template <int H>

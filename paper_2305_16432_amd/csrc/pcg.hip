@@ -375,16 +375,6 @@ __global__ void __launch_bounds__(kWgThreads) k_llt_wg(Args a, int do_fwd, int d
     }
 }
 
-// Entry j of the new search direction p = z + beta p_prev (p = z in the first
-// iteration), with z formed on the fly for Jacobi / no preconditioning.
-template <int KIND>
-__device__ __forceinline__ float pdir(const Args &a, int j, bool first, float beta, const float *__restrict__ pp) {
-    float zj;
-    if (KIND == LPCG_PC_LLT || KIND == LPCG_PC_JACOBI) zj = __uint_as_float(a.z[j]);
-    else zj = a.r[j];
-    return first ? zj : __fmaf_rn(beta, pp[j], zj);
-}
-
 // p = z + beta p_prev, w = A p and p.w partials; the reducer block computes
 // alpha (breakdown when p.w <= 0 or non-finite) and counts the product.
 template <int G, int KIND>
@@ -398,17 +388,31 @@ __global__ void __launch_bounds__(VT) k_spmv_pw(Args a) {
     const float *pp = (it & 1) ? a.p0 : a.p1;
     const int sub = threadIdx.x % G;
     const int rows_per_pass = gridDim.x * (VT / G);
+    // the arrays this kernel reads never alias the ones it writes (p_new, w):
+    // restrict-qualified copies let the compiler keep the gathers in flight
+    // across the stores
+    const int *__restrict__ rp = a.rp;
+    const int *__restrict__ ci = a.ci;
+    const float *__restrict__ v = a.v32;
+    const float *__restrict__ zs = KIND == LPCG_PC_NONE ? a.r : (const float *)a.z;
+    const float *__restrict__ pq = pp;
+    float *__restrict__ pnw = pn;
+    float *__restrict__ w = a.w;
     double pw = 0;
     for (int row = blockIdx.x * (VT / G) + threadIdx.x / G; row < a.n; row += rows_per_pass) {
         float acc = 0.f;
-        for (int k = a.rp[row] + sub; k < a.rp[row + 1]; k += G)
-            acc += a.v32[k] * pdir<KIND>(a, a.ci[k], first, beta, pp);
+        for (int k = rp[row] + sub; k < rp[row + 1]; k += G) {
+            const int j = ci[k];
+            const float zj = zs[j];
+            acc += v[k] * (first ? zj : __fmaf_rn(beta, pq[j], zj));
+        }
 #pragma unroll
         for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, G);
         if (sub == 0) {
-            const float pi = pdir<KIND>(a, row, first, beta, pp);
-            pn[row] = pi;
-            a.w[row] = acc;
+            const float zi = zs[row];
+            const float pi = first ? zi : __fmaf_rn(beta, pq[row], zi);
+            pnw[row] = pi;
+            w[row] = acc;
             pw += (double)pi * (double)acc;
         }
     }
@@ -441,20 +445,27 @@ __global__ void __launch_bounds__(VT) k_xr(Args a) {
     const float *p = ((it - 1) & 1) ? a.p1 : a.p0;
     const double alpha = a.scal[S_ALPHA];
     const float af = (float)alpha;
+    // element-wise: each index is read and written by one thread only
+    const float *__restrict__ pr = p;
+    const float *__restrict__ wr = a.w;
+    const float *__restrict__ dv = a.dinv;
+    double *__restrict__ xr = a.x;
+    float *__restrict__ rv = a.r;
+    uint32_t *__restrict__ zb = a.z;
     double rr = 0, rzn = 0;
     for (int i = blockIdx.x * VT + threadIdx.x; i < a.n; i += gridDim.x * VT) {
-        a.x[i] += alpha * (double)p[i];
-        const float ri = a.r[i] - af * a.w[i];
-        a.r[i] = ri;
+        xr[i] += alpha * (double)pr[i];
+        const float ri = rv[i] - af * wr[i];
+        rv[i] = ri;
         rr += (double)ri * ri;
         if (KIND == LPCG_PC_JACOBI) {
-            rzn += (double)ri * ri * a.dinv[i];
-            a.z[i] = __float_as_uint(a.dinv[i] * ri);
+            rzn += (double)ri * ri * dv[i];
+            zb[i] = __float_as_uint(dv[i] * ri);
         }
         if (KIND == LPCG_PC_NONE) rzn += (double)ri * ri;
         if (KIND == LPCG_PC_LLT) {
             if (a.reset_y) a.y[i] = kUnset;
-            if (a.reset_z) a.z[i] = kUnset;
+            if (a.reset_z) zb[i] = kUnset;
         }
     }
     rr = block_sum<VT>(rr, lds);
