@@ -39,25 +39,25 @@ PEAK_HBM = 8000.0  # GB/s, MI355X HBM3E
 # HBM bytes of the roofline kernel measured with rocprofv3 --pmc FETCH_SIZE /
 # WRITE_SIZE (scaled by the same counters on a copy of known size); valid
 # only while the kernel source is the one that was profiled.
-TRAFFIC = os.path.join(ROOT, "profiles", "sptrsv_forward_heat3d_64_traffic.json")
-TRAFFIC_SRC = [os.path.join(ROOT, "paper_2305_16432_amd", "csrc", "kern_sptrsv.h")]
+TRAFFIC = os.path.join(ROOT, "profiles", "pcg_parts_heat3d_64_traffic.json")
 
 
 def measured_traffic(kernel):
     """HBM bytes per launch from the committed counter summary, or None when
-    absent, for another kernel, or taken on a different kernel source."""
+    absent, for a kernel it does not list, or taken on different kernel
+    sources (SHA-256 over the files it names)."""
     import hashlib
     if not os.path.exists(TRAFFIC):
         return None
     with open(TRAFFIC) as f:
         t = json.load(f)
     h = hashlib.sha256()
-    for p in TRAFFIC_SRC:
-        with open(p, "rb") as f:
+    for p in t.get("sources", []):
+        with open(os.path.join(ROOT, p), "rb") as f:
             h.update(f.read())
-    if t.get("kernel") != kernel or t.get("source_sha256") != h.hexdigest():
+    if t.get("source_sha256") != h.hexdigest() or kernel not in t.get("kernels", {}):
         return None
-    return t.get("bytes_per_launch")
+    return t["kernels"][kernel]["bytes_per_launch"]
 
 
 def _log(msg):
