@@ -23,9 +23,17 @@ FLAGS = [
 ]
 
 
+# per-file additions: the GNN kernels keep MFMA accumulators in ordinary
+# VGPRs (no copies out of the accumulation registers before the element-wise
+# work between products; every GNN kernel keeps or raises its occupancy)
+FILE_FLAGS = {
+    "gnn.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"],
+}
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(OBJ, os.path.basename(src) + ".o")
-    cmd = ["hipcc", *FLAGS, "-c", src, "-o", obj]
+    cmd = ["hipcc", *FLAGS, *FILE_FLAGS.get(os.path.basename(src), []), "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)

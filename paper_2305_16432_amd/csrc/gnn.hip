@@ -59,7 +59,7 @@ GnnOff gnn_offsets(int h, int n_mp, bool x_head) {
 // buffers come first, at offsets common to both layouts.
 struct GnnWs {
     size_t sys_s, sys_rms, norm_part;
-    size_t V[kMaxMp + 1], Pa[kMaxMp], Pb[kMaxMp], E[kMaxMp + 1], M, Ahat;
+    size_t V[kMaxMp + 1], Pa[kMaxMp], Pb[kMaxMp], E[kMaxMp + 1], M, Ahat, wpack;
     size_t d, xhat, gxhat;
     // backward (train only)
     size_t gd, gE[2], gV[2], gVmlp, gm, GH, G1, GVN, GH1, H1, Mt, gPa, gPb, HD, GHD, Henc, GHenc, Xn, Xe;
@@ -69,6 +69,22 @@ struct GnnWs {
 
 // Layers the fused inference pass supports (its edge chain is unrolled).
 constexpr int kFusedMaxMp = 4;
+
+// Packed weights of the fused inference pass (latent width 32): every
+// weight the pass kernels keep in LDS, converted once per forward to BF16 in
+// MFMA operand order (the LDS image stage_weights writes), 1024 values per
+// 32 x 32 image.  Layer u occupies slots (7u .. 7u + 6): 0-1 the node MLP's
+// first weight (2H x H, natural order), 2 its second (phi), 3 and 4 the
+// node rows W_a, W_b of the edge MLP's first weight (phi), 5 its edge rows
+// W_e (phi), 6 the edge MLP's second weight (phi).  After the layers: the
+// edge encoder's second weight (natural), the decoder's first (phi), the
+// identity (phi) and the node encoder's second weight (natural).
+constexpr int kImg = 1024;
+__host__ __device__ constexpr int pk_layer(int u, int slot) { return (7 * u + slot) * kImg; }
+__host__ __device__ constexpr int pk_glob(int n_mp, int k) { return (7 * n_mp + k) * kImg; }
+constexpr int kPkGlob = 4;  // images after the layers
+constexpr int kPkEncE = 0, kPkDec = 1, kPkId = 2, kPkEncN = 3;
+size_t pack_bytes(int n_mp) { return 2 * (size_t)pk_glob(n_mp, kPkGlob); }
 
 // Blocks of the weight-gradient kernels = number of per-block partial sums.
 constexpr int kWgradBlocks = 256;
@@ -114,6 +130,7 @@ GnnWs gnn_ws_layout(const lpcg_system *s, int h, int n_mp, bool train) {
     }
     if (fused) {
         w.M = take(2 * n * h);  // aggregated messages, BF16
+        w.wpack = take(pack_bytes(n_mp));
         w.Ahat = take(4 * nnz);  // edge inputs A_e / s, FP32
     }
     else
@@ -155,6 +172,77 @@ constexpr int kMaxGnnBlocks = 1024;
 
 int nblk(long n, int t) { return (int)((n + t - 1) / t); }
 
+// Copy N BF16 values (N a multiple of 8) from global memory into LDS, 16
+// bytes per load; every load of the thread is issued before its first store.
+template <int N>
+__device__ __forceinline__ void lds_copy(__bf16 *lds, const __bf16 *__restrict__ src) {
+    constexpr int C = N / 8, PER = (C + kGnnThreads - 1) / kGnnThreads;
+    bf16x8 t[PER];
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+        const int g = p * kGnnThreads + threadIdx.x;
+        if (g < C) t[p] = *reinterpret_cast<const bf16x8 *>(src + 8 * g);
+    }
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+        const int g = p * kGnnThreads + threadIdx.x;
+        if (g < C) *reinterpret_cast<bf16x8 *>(lds + 8 * g) = t[p];
+    }
+}
+
+// One 1024-value unit of the packed weights: values base .. base + 1023 of
+// the operand image of a [K x 32] FP32 weight at P + src (row stride ldw;
+// phi or natural K order), written from wpack + dst; src < 0: the identity.
+struct PackUnit {
+    int dst, src, ldw, K, phi, base;
+};
+struct PackPlan {
+    PackUnit u[7 * kFusedMaxMp + kPkGlob];
+};
+
+// Block b writes unit b of the plan, four values per thread, loads first.
+__global__ void __launch_bounds__(256) k_pack_weights(const float *__restrict__ P, PackPlan plan,
+                                                      __bf16 *__restrict__ wpack) {
+    const PackUnit pu = plan.u[blockIdx.x];
+    const int S = pu.K / 16;
+    float v[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int i = pu.base + r * 256 + threadIdx.x;
+        const int j = i & 7, lane = (i >> 3) & 63, ms = i >> 9;
+        const int st = ms % S, mt = ms / S;
+        if (pu.src < 0) v[r] = k_phi(st, j, lane) == (lane & 31) ? 1.f : 0.f;
+        else {
+            const int k = pu.phi ? k_phi(st, j, lane) : k_nat(st, j, lane);
+            v[r] = P[pu.src + (size_t)k * pu.ldw + mt * 32 + (lane & 31)];
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) wpack[pu.dst + pu.base + r * 256 + threadIdx.x] = (__bf16)v[r];
+}
+
+// Units of the packed weights for n_mp layers (latent width 32).
+int pack_plan(const GnnOff &o, int n_mp, PackPlan &plan) {
+    constexpr int H = 32;
+    int nu = 0;
+    auto img = [&](int dst, int src, int ldw, int K, bool phi) {
+        for (int base = 0; base < K * H; base += kImg) plan.u[nu++] = PackUnit{dst, src, ldw, K, phi ? 1 : 0, base};
+    };
+    for (int u = 0; u < n_mp; ++u) {
+        img(pk_layer(u, 0), o.node[u].W0, H, 2 * H, false);
+        img(pk_layer(u, 2), o.node[u].W1, H, H, true);
+        img(pk_layer(u, 3), o.edge[u].W0 + H * H, H, H, true);
+        img(pk_layer(u, 4), o.edge[u].W0 + 2 * H * H, H, H, true);
+        img(pk_layer(u, 5), o.edge[u].W0, H, H, true);
+        img(pk_layer(u, 6), o.edge[u].W1, H, H, true);
+    }
+    img(pk_glob(n_mp, kPkEncE), o.edge_enc.W1, H, H, false);
+    img(pk_glob(n_mp, kPkDec), o.dec.W0, H, H, true);
+    img(pk_glob(n_mp, kPkId), -1, 0, H, true);
+    img(pk_glob(n_mp, kPkEncN), o.node_enc.W1, H, H, false);
+    return nu;
+}
+
 // Normalisation sums, stage 1: block (x, y) sums diag(A) and b^2 over
 // segment x (kNormRows rows) of system y; empty segments write zeros.
 __global__ void k_gnn_norm_part(int nseg, const int *__restrict__ sys_rowptr, const int *__restrict__ dpos,
@@ -164,10 +252,24 @@ __global__ void k_gnn_norm_part(int nseg, const int *__restrict__ sys_rowptr, co
     const int sy = blockIdx.y, sg = blockIdx.x;
     const int r0 = sys_rowptr[sy] + sg * kNormRows;
     const int r1 = min(sys_rowptr[sy + 1], r0 + kNormRows);
+    // the thread's rows r0 + threadIdx.x + u * kGnnThreads, summed in that
+    // order; all their loads are issued before the first sum
+    constexpr int PER = kNormRows / kGnnThreads;
+    int ip[PER];
+    double bv[PER], dv[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int i = r0 + threadIdx.x + u * kGnnThreads;
+        ip[u] = i < r1 ? dpos[i] : -1;
+        bv[u] = i < r1 ? b[i] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < PER; ++u) dv[u] = ip[u] >= 0 ? val[ip[u]] : 0.0;
     double sd = 0, sb = 0;
-    for (int i = r0 + threadIdx.x; i < r1; i += kGnnThreads) {
-        sd += val[dpos[i]];
-        sb += b[i] * b[i];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        sd += dv[u];
+        sb += bv[u] * bv[u];
     }
     sd = block_sum<kGnnThreads>(sd, lds);
     sb = block_sum<kGnnThreads>(sb, lds);
@@ -202,10 +304,12 @@ __global__ void __launch_bounds__(kGnnThreads) k_enc(int rows, const float *__re
                                                      const int *__restrict__ erow,
                                                      const int *__restrict__ row_sys,
                                                      const double *__restrict__ sys_scale,
-                                                     __bf16 *__restrict__ out, float *__restrict__ xs_out) {
+                                                     __bf16 *__restrict__ out, float *__restrict__ xs_out,
+                                                     const __bf16 *__restrict__ w1p) {
     constexpr int S = H / 16, MT = H / 32;
-    __shared__ __bf16 w1[H * H];
-    stage_weights<false>(w1, P + m.W1, H, H, H);
+    __shared__ __align__(16) __bf16 w1[H * H];
+    if (w1p) lds_copy<H * H>(w1, w1p);  // packed (the fused inference pass)
+    else stage_weights<false>(w1, P + m.W1, H, H, H);
     __syncthreads();
     const int lane = lane_id();
     const float *W0 = P + m.W0, *b0 = P + m.b0, *b1 = P + m.b1;
@@ -441,6 +545,8 @@ struct FusedChain {
     MlpOff edge[kFusedMaxMp];
     const __bf16 *pa[kFusedMaxMp];
     const __bf16 *pb[kFusedMaxMp];
+    const __bf16 *wpack;  // packed weights (pk_layer / pk_glob layout)
+    int n_mp;
 };
 
 template <int CH, bool DEC>
@@ -451,33 +557,63 @@ __global__ void __launch_bounds__(kGnnThreads) k_fused_edge(
     float *__restrict__ ahat, const float *__restrict__ P, MlpOff enc, FusedChain ch, MlpOff md,
     const __bf16 *__restrict__ V, __bf16 *__restrict__ M, float *__restrict__ d, int zero) {
     constexpr int H = 32, S = H / 16;
-    constexpr int NW = CH > 0 ? CH : 1;
     // FP32 constants: encoder W0, b0, b1; b0, b1 of each chain layer; decoder
     // b0, W1 (a column), b1
     constexpr int C_ENC = 0, C_CH = 3 * H, C_DEC = C_CH + 2 * H * CH, NC = C_DEC + 2 * H + 1;
-    __shared__ __bf16 wenc[H * H];
-    __shared__ __bf16 we[NW][H * H], w1[NW][H * H];
-    __shared__ __bf16 wd[DEC ? H * H : 1];
-    __shared__ float cst[NC];
+    // LDS weights, one image each: the encoder's second layer, then W_e and
+    // W_1 of each chain layer, the decoder's first layer, the identity
+    constexpr int NIMG = 1 + 2 * CH + (DEC ? 1 : 0) + (CH > 0 ? 1 : 0);
+    __shared__ __align__(16) __bf16 wl[NIMG][H * H];
+    __bf16 *const wenc = wl[0];
+    __bf16 *const wd = wl[DEC ? 1 + 2 * CH : 0];
+    __bf16 *const wid = wl[CH > 0 ? NIMG - 1 : 0];
+    __shared__ __align__(16) float cst[NC];
     __shared__ float msg[DEC ? 1 : kGnnThreads / kWave][DEC ? 1 : 32][H + 1];
-    stage_weights<false>(wenc, P + enc.W1, H, H, H);
+    {
+        // every 16-byte chunk of the packed images and every constant is
+        // loaded before the first LDS store (one memory round trip)
+        constexpr int CPI = H * H / 8, CHUNKS = NIMG * CPI;
+        constexpr int PER = (CHUNKS + kGnnThreads - 1) / kGnnThreads, PERC = (NC + kGnnThreads - 1) / kGnnThreads;
+        const int T = ch.n_mp;
+        bf16x8 tv[PER];
+        float cv[PERC];
 #pragma unroll
-    for (int u = 0; u < CH; ++u) {
-        stage_weights<true>(we[u], P + ch.edge[u].W0, H, H, H);
-        stage_weights<true>(w1[u], P + ch.edge[u].W1, H, H, H);
-    }
-    if (DEC) stage_weights<true>(wd, P + md.W0, H, H, H);
-    for (int i = threadIdx.x; i < NC; i += blockDim.x) {
-        float v;
-        if (i < C_CH) v = P[(i < H ? enc.W0 : i < 2 * H ? enc.b0 - H : enc.b1 - 2 * H) + i];
-        else if (i < C_DEC) {
-            const int u = (i - C_CH) / (2 * H), k = (i - C_CH) % (2 * H);
-            v = k < H ? P[ch.edge[u].b0 + k] : P[ch.edge[u].b1 + k - H];
-        } else {
-            const int k = i - C_DEC;
-            v = DEC ? (k < H ? P[md.b0 + k] : k < 2 * H ? P[md.W1 + k - H] : P[md.b1]) : 0.f;
+        for (int p = 0; p < PER; ++p) {
+            const int g = p * kGnnThreads + threadIdx.x;
+            if (g < CHUNKS) {
+                const int q = g / CPI;
+                int off;
+                if (q == 0) off = pk_glob(T, kPkEncE);
+                else if (q <= 2 * CH) off = pk_layer((q - 1) >> 1, 5 + ((q - 1) & 1));
+                else if (DEC && q == 2 * CH + 1) off = pk_glob(T, kPkDec);
+                else off = pk_glob(T, kPkId);
+                tv[p] = *reinterpret_cast<const bf16x8 *>(ch.wpack + off + 8 * (g % CPI));
+            }
         }
-        cst[i] = v;
+#pragma unroll
+        for (int p = 0; p < PERC; ++p) {
+            const int i = p * kGnnThreads + threadIdx.x;
+            float v = 0.f;
+            if (i < C_CH) v = P[(i < H ? enc.W0 : i < 2 * H ? enc.b0 - H : enc.b1 - 2 * H) + i];
+            else if (i < C_DEC) {
+                const int u = (i - C_CH) / (2 * H), k = (i - C_CH) % (2 * H);
+                v = k < H ? P[ch.edge[u].b0 + k] : P[ch.edge[u].b1 + k - H];
+            } else if (DEC && i < NC) {
+                const int k = i - C_DEC;
+                v = k < H ? P[md.b0 + k] : k < 2 * H ? P[md.W1 + k - H] : P[md.b1];
+            }
+            cv[p] = v;
+        }
+#pragma unroll
+        for (int p = 0; p < PER; ++p) {
+            const int g = p * kGnnThreads + threadIdx.x;
+            if (g < CHUNKS) *reinterpret_cast<bf16x8 *>(&wl[0][0] + 8 * g) = tv[p];
+        }
+#pragma unroll
+        for (int p = 0; p < PERC; ++p) {
+            const int i = p * kGnnThreads + threadIdx.x;
+            if (i < NC) cst[i] = cv[p];
+        }
     }
     __syncthreads();
     const int lane = lane_id(), wv = threadIdx.x / kWave;
@@ -546,7 +682,7 @@ __global__ void __launch_bounds__(kGnnThreads) k_fused_edge(
         if (CH == 0 && !DEC && valid && lane < 32) ahat[e] = x;  // kept for the later passes
         // every gather of the tile issued up front, so their latencies overlap
         // instead of following each other layer by layer
-        bf16x4 gpa[NW][4], gpb[NW][4], gv[4];
+        bf16x4 gpa[CH > 0 ? CH : 1][4], gpb[CH > 0 ? CH : 1][4], gv[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int f = acc_feat(0, 4 * q, lane);
@@ -557,52 +693,56 @@ __global__ void __launch_bounds__(kGnnThreads) k_fused_edge(
             }
             if (!DEC) gv[q] = *reinterpret_cast<const bf16x4 *>(V + (size_t)c * H + f);
         }
+        // every accumulator starts from its layer's bias (the MFMA adds onto it)
         f32x16 acc[1];
-        acc[0] = zero16();
+        acc[0] = bias16(C + C_ENC + 2 * H, lane);
 #pragma unroll
         for (int st = 0; st < S; ++st) {
+            // first encoder layer at this lane's 8 input features k_nat(st, 0..7)
+            const int k0 = k_nat(st, 0, lane);
             bf16x8 b;
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int k = k_nat(st, j, lane);
-                b[j] = (__bf16)fmaxf(x * C[C_ENC + k] + C[C_ENC + H + k], 0.f);
+            for (int j4 = 0; j4 < 2; ++j4) {
+                const f32x4 w0 = *reinterpret_cast<const f32x4 *>(C + C_ENC + k0 + 4 * j4);
+                const f32x4 b0 = *reinterpret_cast<const f32x4 *>(C + C_ENC + H + k0 + 4 * j4);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) b[4 * j4 + j] = (__bf16)fmaxf(x * w0[j] + b0[j], 0.f);
             }
             acc[0] = mfma(lds_op(wenc + z, S, 0, st, lane), b, acc[0]);
         }
-        add_bias<1>(acc, C + C_ENC + 2 * H, lane, false);
-        // edge MLPs 0..CH-1 through the factored first layer
+        // edge MLPs 0..CH-1 through the factored first layer: the node terms
+        // Pa[row] and Pb[col] enter the accumulator through an identity
+        // product, straight from their BF16 gathers (the lane's gathered
+        // features are exactly its accumulator features, in phi order)
 #pragma unroll
         for (int u = 0; u < CH; ++u) {
             f32x16 hid[1];
-            hid[0] = zero16();
+            hid[0] = bias16(C + C_CH + 2 * H * u, lane);
 #pragma unroll
-            for (int st = 0; st < S; ++st)
-                hid[0] = mfma(lds_op(we[u] + z, S, 0, st, lane), acc_operand<1>(acc, st), hid[0]);
-            const float *b0 = C + C_CH + 2 * H * u;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int f = acc_feat(0, 4 * q, lane);
-#pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    const float add = valid ? (float)gpa[u][q][t] + (float)gpb[u][q][t] : 0.f;
-                    hid[0][4 * q + t] = fmaxf(hid[0][4 * q + t] + add + b0[f + t], 0.f);
-                }
+            for (int st = 0; st < S; ++st) {
+                hid[0] = mfma(lds_op(wid + z, S, 0, st, lane), cat8(gpa[u][2 * st], gpa[u][2 * st + 1]), hid[0]);
+                hid[0] = mfma(lds_op(wid + z, S, 0, st, lane), cat8(gpb[u][2 * st], gpb[u][2 * st + 1]), hid[0]);
             }
-            f32x16 out[1];
-            out[0] = zero16();
 #pragma unroll
             for (int st = 0; st < S; ++st)
-                out[0] = mfma(lds_op(w1[u] + z, S, 0, st, lane), acc_operand<1>(hid, st), out[0]);
-            add_bias<1>(out, C + C_CH + 2 * H * u + H, lane, false);
+                hid[0] = mfma(lds_op(wl[1 + 2 * u] + z, S, 0, st, lane), acc_operand<1>(acc, st), hid[0]);
+#pragma unroll
+            for (int i = 0; i < 16; ++i) hid[0][i] = relu_bits(hid[0][i]);
+            f32x16 out[1];
+            out[0] = bias16(C + C_CH + 2 * H * u + H, lane);
+#pragma unroll
+            for (int st = 0; st < S; ++st)
+                out[0] = mfma(lds_op(wl[2 + 2 * u] + z, S, 0, st, lane), acc_operand<1>(hid, st), out[0]);
             acc[0] = out[0];
         }
         if (DEC) {
             // decoder d = relu(E W0 + b0) w1 + b1 (one scalar per edge)
             f32x16 hd[1];
-            hd[0] = zero16();
+            hd[0] = bias16(C + C_DEC, lane);
 #pragma unroll
             for (int st = 0; st < S; ++st) hd[0] = mfma(lds_op(wd + z, S, 0, st, lane), acc_operand<1>(acc, st), hd[0]);
-            add_bias<1>(hd, C + C_DEC, lane, true);
+#pragma unroll
+            for (int i = 0; i < 16; ++i) hd[0][i] = relu_bits(hd[0][i]);
             float part = 0.f;
 #pragma unroll
             for (int i = 0; i < 16; ++i) part += hd[0][i] * C[C_DEC + H + acc_feat(0, i, lane)];
@@ -616,7 +756,7 @@ __global__ void __launch_bounds__(kGnnThreads) k_fused_edge(
                 const int f = acc_feat(0, 4 * q, lane);
 #pragma unroll
                 for (int t = 0; t < 4; ++t)
-                    mw[lane & 31][f + t] = valid ? (float)(__bf16)acc[0][4 * q + t] * (float)gv[q][t] : 0.f;
+                    mw[lane & 31][f + t] = (float)(__bf16)acc[0][4 * q + t] * (float)gv[q][t];
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
@@ -646,13 +786,13 @@ template <int H>
 __global__ void __launch_bounds__(kGnnThreads) k_node_m(int n, const float *__restrict__ P, MlpOff mv, MlpOff me,
                                                         const __bf16 *__restrict__ V, const __bf16 *__restrict__ M,
                                                         __bf16 *__restrict__ Vn, __bf16 *__restrict__ Pa,
-                                                        __bf16 *__restrict__ Pb) {
+                                                        __bf16 *__restrict__ Pb, const __bf16 *__restrict__ wp) {
     constexpr int S = H / 16, MT = H / 32;
-    __shared__ __bf16 w0[2 * H * H], w1[H * H], wa[H * H], wb[H * H];
-    stage_weights<false>(w0, P + mv.W0, H, 2 * H, H);
-    stage_weights<true>(w1, P + mv.W1, H, H, H);
-    stage_weights<true>(wa, P + me.W0 + H * H, H, H, H);
-    stage_weights<true>(wb, P + me.W0 + 2 * H * H, H, H, H);
+    // the layer's packed images in their packed order: the node MLP's two
+    // weights, then W_a and W_b of the edge MLP (one contiguous copy)
+    __shared__ __align__(16) __bf16 wl[5 * H * H];
+    __bf16 *const w0 = wl, *const w1 = wl + 2 * H * H, *const wa = wl + 3 * H * H, *const wb = wl + 4 * H * H;
+    lds_copy<5 * H * H>(wl, wp);
     __syncthreads();
     const int lane = lane_id();
     const int ntiles = (n + 31) / 32;
@@ -770,6 +910,14 @@ __device__ __forceinline__ float l_value(int q, int mode, const int *__restrict_
     return l_entry(k, mode, erow, col, rev, row_sys, sys_s, diag64, d);
 }
 
+// Transposed copy: ut[p] = l[u2l[p]] (the values k_assemble would compute
+// again at those positions).
+__global__ void k_gather_ut(int nnz_l, const int *__restrict__ u2l, const float *__restrict__ lval,
+                            float *__restrict__ utval) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < nnz_l) utval[p] = lval[u2l[p]];
+}
+
 __global__ void k_assemble(int nnz_l, int mode, const int *__restrict__ lsrc, const int *__restrict__ u2l,
                            const int *__restrict__ rowptr, const int *__restrict__ lrowptr,
                            const int *__restrict__ erow, const int *__restrict__ col,
@@ -879,11 +1027,20 @@ int forward_impl(const lpcg_system *s, const lpcg_gnn *net, const double *b, uns
     float *d = (float *)(ws + L.d);
     const int T = net->n_mp;
     if (H == 32 && fused) {
+        __bf16 *wpack = (__bf16 *)(ws + L.wpack);
+        {
+            PackPlan plan{};
+            const int nu = pack_plan(o, T, plan);
+            k_pack_weights<<<nu, 256, 0, st>>>(P, plan, wpack);
+        }
         k_enc<H, true><<<gnn_blocks(s->n), kGnnThreads, 0, st>>>(s->n, P, o.node_enc, b, s->erow, s->row_sys,
-                                                                  sys_rms, V(0), nullptr);
+                                                                  sys_rms, V(0), nullptr,
+                                                                  wpack + pk_glob(T, kPkEncN));
         __bf16 *M = (__bf16 *)(ws + L.M);
         float *ahat = (float *)(ws + L.Ahat);
         FusedChain ch{};
+        ch.wpack = wpack;
+        ch.n_mp = T;
         for (int t = 0; t <= T; ++t) {
             const long tiles = t < T ? s->gtiles : (s->nnz + 31) / 32;
             switch (t + (t == T ? 8 : 0)) {
@@ -903,7 +1060,7 @@ int forward_impl(const lpcg_system *s, const lpcg_gnn *net, const double *b, uns
             }
             if (t == T) break;
             k_node_m<H><<<gnn_blocks(s->n), kGnnThreads, 0, st>>>(s->n, P, o.node[t], o.edge[t], V(t), M, V(t + 1),
-                                                                  Pa(t), Pb(t));
+                                                                  Pa(t), Pb(t), wpack + pk_layer(t, 0));
             ch.edge[t] = o.edge[t];
             ch.pa[t] = Pa(t);
             ch.pb[t] = Pb(t);
@@ -911,10 +1068,10 @@ int forward_impl(const lpcg_system *s, const lpcg_gnn *net, const double *b, uns
     } else {
     k_enc<H, true><<<gnn_blocks(s->n), kGnnThreads, 0, st>>>(s->n, P, o.node_enc, b, s->erow, s->row_sys,
                                                               sys_rms, V(0),
-                                                              train ? (float *)(ws + L.Xn) : nullptr);
+                                                              train ? (float *)(ws + L.Xn) : nullptr, nullptr);
     k_enc<H, false><<<gnn_blocks(s->nnz), kGnnThreads, 0, st>>>(s->nnz, P, o.edge_enc, s->val64, s->erow,
                                                                  s->row_sys, sys_s, E(0),
-                                                                 train ? (float *)(ws + L.Xe) : nullptr);
+                                                                 train ? (float *)(ws + L.Xe) : nullptr, nullptr);
     for (int t = 0; t < T; ++t) {
         k_node<H><<<gnn_blocks(s->n), kGnnThreads, 0, st>>>(s->n, s->rowptr, s->colind, P, o.node[t],
                                                              o.edge[t], V(t), E(t), V(t + 1), Pa(t), Pb(t));
@@ -927,10 +1084,13 @@ int forward_impl(const lpcg_system *s, const lpcg_gnn *net, const double *b, uns
                 train ? E(t + 1) : nullptr, d);
     }
     }
+    // L in its own order, then L^T gathered from it when both are wanted
+    // (each value computed once); U alone is assembled directly
     k_assemble<<<nblk(s->nnz_l, 256), 256, 0, st>>>(s->nnz_l, net->diag_mode, s->lsrc, s->u2l, s->rowptr,
                                                      s->lrowptr, s->erow,
                                                      s->colind, s->rev, s->row_sys, sys_s, s->diag64, d, lval,
-                                                     utval);
+                                                     lval ? nullptr : utval);
+    if (lval && utval) k_gather_ut<<<nblk(s->nnz_l, 256), 256, 0, st>>>(s->nnz_l, s->u2l, lval, utval);
     if (net->x_head) {
         k_xdec<H><<<gnn_blocks(s->n), kGnnThreads, 0, st>>>(s->n, P, o.xdec, V(T), (float *)(ws + L.xhat));
         // the head's loss gradient starts at zero: a backward without an

@@ -164,6 +164,41 @@ __device__ __forceinline__ void store_acc_bf16(__bf16 *row, const f32x16 (&acc)[
         }
 }
 
+// Accumulator tile holding a bias vector (this lane's features), the
+// starting value of a product that adds onto it.
+// b must be 16-byte aligned: each group of four features is one 16-byte read.
+__device__ __forceinline__ f32x16 bias16(const float *b, int lane) {
+    f32x16 v;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const f32x4 t = *reinterpret_cast<const f32x4 *>(b + acc_feat(0, 4 * q, lane));
+#pragma unroll
+        for (int r = 0; r < 4; ++r) v[4 * q + r] = t[r];
+    }
+    return v;
+}
+
+// max(x, 0) for every non-NaN x as one integer max on the bit pattern
+// (negative values and -0 have the sign bit set); unlike fmaxf it needs no
+// canonicalisation of an MFMA result first.
+__device__ __forceinline__ float relu_bits(float x) {
+    return __builtin_bit_cast(float, max(__builtin_bit_cast(int, x), 0));
+}
+
+// Two 4-wide BF16 slices as one B-operand slot group.
+__device__ __forceinline__ bf16x8 cat8(bf16x4 a, bf16x4 b) {
+    return __builtin_shufflevector(a, b, 0, 1, 2, 3, 4, 5, 6, 7);
+}
+
+// Stage the identity as an A operand in phi order (32 x 32): a product with
+// it copies a B operand given in phi order into the accumulator layout.
+__device__ __forceinline__ void stage_identity(__bf16 *lds) {
+    for (int idx = threadIdx.x; idx < 2 * 64 * 8; idx += blockDim.x) {
+        const int j = idx & 7, lane = (idx >> 3) & 63, s = idx >> 9;
+        lds[idx] = (__bf16)(k_phi(s, j, lane) == (lane & 31) ? 1.f : 0.f);
+    }
+}
+
 // Add bias (FP32 params) to accumulator tiles.
 template <int MT>
 __device__ __forceinline__ void add_bias(f32x16 (&acc)[MT], const float *__restrict__ b, int lane,
