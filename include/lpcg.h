@@ -248,7 +248,14 @@ typedef struct {
                               0 means 1. */
     int32_t block_rows;    /* mode 3: rows per block (64 .. 65536; 0 = 1024); the
                               schedule is built on the host when the configuration is set
-                              (synchronous) */
+                              (synchronous).  Direction 2 (the SpMV): 0 = the gather form;
+                              R >= 64 = the LDS-staged form, one block of 256 threads per
+                              R consecutive rows, each block copying the input over its
+                              rows' off-diagonal column window into LDS (windows computed
+                              on the device when set, synchronous; EINVAL when a window
+                              exceeds 16384 inputs or n / R exceeds 2048 blocks).  Both
+                              forms sum a row's entries in the same order: same result bit
+                              for bit */
     double us;             /* lpcg_autotune: mean duration of one solve */
     int32_t block_runs;    /* mode 3: 1 (or 0): a block is block_rows consecutive rows.
                               K > 1: banded, K runs of block_rows / K consecutive rows
@@ -309,9 +316,11 @@ int lpcg_blocked_schedule(int32_t n, const int32_t *rowptr, const int32_t *col, 
  * a red-black grid in colour order, it keeps the level mode in both
  * directions, which lets the PCG apply L L^T in two fused launches).  It then times the
  * FP32 SpMV w = A p for G = 4, 8, 16, 32, 64 lanes per row (64 / G rows per
- * wavefront) on grids of up to 512, 1024 and 2048 blocks and keeps the
- * fastest for the PCG's product and lpcg_spmv; those table entries have
- * direction 2, mode = G and waves = blocks.  It writes up to table_len measured
+ * wavefront) on grids of up to 512, 1024 and 2048 blocks, and the LDS-staged
+ * form with 256, 512 and 1024 rows per block at G = 4 and 8 (where the
+ * windows fit), and keeps the fastest for the PCG's product and lpcg_spmv;
+ * those table entries have direction 2, mode = G, waves = blocks and
+ * block_rows (0 for the gather form).  It writes up to table_len measured
  * candidates to table (HOST, may be NULL) and their number to *n_table
  * (HOST, may be NULL).  Uses the system's work vectors: not concurrent with
  * a solve on the same system.  Synchronous. */
@@ -320,7 +329,9 @@ int lpcg_autotune(lpcg_system *sys, const float *l_val, const float *ut_val, int
 
 /* Read / force the configuration of one direction (HOST struct; `us` is
  * ignored).  Direction 2 is the SpMV: mode = lanes per row (4, 8, 16, 32 or
- * 64), waves = blocks of 256 threads (1 .. 2048).  Errors: EINVAL for an
+ * 64), waves = blocks of 256 threads (1 .. 2048) of the gather form, or
+ * block_rows = R > 0 for the LDS-staged form (waves then reads back as its
+ * block count; a refused R leaves the previous form in force).  Errors: EINVAL for an
  * unknown direction, mode, a backoff outside
  * 0..64, a block_stride other than 0, 1, 2, 4, 8, mode 2 on a system with
  * a level wider than 3072 rows, or a mode-3 block shape the pattern does not

@@ -2,6 +2,7 @@
 #include <algorithm>
 #include <cstring>
 #include <mutex>
+#include <type_traits>
 
 #include "device_util.h"
 #include "kern_spmv.h"
@@ -19,13 +20,34 @@ __global__ void k_zero_i32(int *p, int count) {
 }
 
 // CSR SpMV with G = group lanes per row (64 / G rows per wavefront) on
-// `blocks` blocks (0: the system's tuned grid).
+// `blocks` blocks (0: the system's tuned grid), or (FP32, rows > 0, windows
+// prepared for that R) the LDS-staged form with `rows` rows per block.
 template <typename VT, typename XT>
 int launch_spmv(const lpcg_system *s, const VT *v, const XT *x, XT *y, hipStream_t st, int group = 0,
-                int blocks = 0) {
+                int blocks = 0, int rows = -1) {
     const int threads = 256;
     if (group == 0) group = s->spmv_group;
     if (blocks == 0) blocks = s->spmv_blocks;
+    if (rows < 0) rows = s->spmv_rows;
+    if constexpr (std::is_same<VT, float>::value && std::is_same<XT, float>::value) {
+        if (rows > 0) {
+            if (rows != s->spmv_win_rows) {
+                set_error("SpMV: windows not prepared for %d rows per block", rows);
+                return LPCG_EINVAL;
+            }
+            const int nb = nblk(s->n, rows);
+            const size_t lds = sizeof(float) * (size_t)std::max(1, s->spmv_wmax);
+            switch (group) {
+                case 4: k_spmv_st<4><<<nb, threads, lds, st>>>(s->n, rows, s->rowptr, s->colind, v, x, y, s->spmv_win); break;
+                case 8: k_spmv_st<8><<<nb, threads, lds, st>>>(s->n, rows, s->rowptr, s->colind, v, x, y, s->spmv_win); break;
+                case 16: k_spmv_st<16><<<nb, threads, lds, st>>>(s->n, rows, s->rowptr, s->colind, v, x, y, s->spmv_win); break;
+                case 32: k_spmv_st<32><<<nb, threads, lds, st>>>(s->n, rows, s->rowptr, s->colind, v, x, y, s->spmv_win); break;
+                default: k_spmv_st<64><<<nb, threads, lds, st>>>(s->n, rows, s->rowptr, s->colind, v, x, y, s->spmv_win); break;
+            }
+            LPCG_LAUNCH_CHECK();
+            return LPCG_OK;
+        }
+    }
     switch (group) {
         case 4: k_spmv<4><<<blocks, threads, 0, st>>>(s->n, s->rowptr, s->colind, v, x, y); break;
         case 8: k_spmv<8><<<blocks, threads, 0, st>>>(s->n, s->rowptr, s->colind, v, x, y); break;
@@ -183,10 +205,82 @@ __global__ void k_jacobi(int n, const double *__restrict__ diag, float *__restri
 
 __global__ void k_set_i32(int *p, int v) { *p = v; }
 
+// Window of block b: the smallest and largest off-diagonal column of its rows
+// (columns are sorted, so each row contributes its first and last
+// off-diagonal entry); *wmax receives the longest window.
+__global__ void __launch_bounds__(256) k_spmv_window(int n, int R, const int *__restrict__ rp,
+                                                     const int *__restrict__ ci, int *__restrict__ win,
+                                                     int *__restrict__ wmax) {
+    __shared__ int slo[256 / kWave], shi[256 / kWave];
+    const int r0 = blockIdx.x * R, r1 = min(n, r0 + R);
+    int lo = 0x7fffffff, hi = -1;
+    for (int row = r0 + (int)threadIdx.x; row < r1; row += blockDim.x) {
+        const int a = rp[row], e = rp[row + 1];
+        const int f = a < e && ci[a] == row ? a + 1 : a;
+        const int l = a < e && ci[e - 1] == row ? e - 2 : e - 1;
+        if (f < e && ci[f] != row) lo = min(lo, ci[f]);
+        if (l >= a && ci[l] != row) hi = max(hi, ci[l]);
+    }
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        lo = min(lo, __shfl_xor(lo, off, kWave));
+        hi = max(hi, __shfl_xor(hi, off, kWave));
+    }
+    const int w = threadIdx.x / kWave;
+    if (lane_id() == 0) {
+        slo[w] = lo;
+        shi[w] = hi;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < (int)blockDim.x / kWave; ++i) {
+            lo = min(lo, slo[i]);
+            hi = max(hi, shi[i]);
+        }
+        if (hi < lo) lo = hi + 1;  // empty window
+        win[2 * blockIdx.x] = lo;
+        win[2 * blockIdx.x + 1] = hi;
+        if (hi >= lo) atomicMax(wmax, hi - lo + 1);
+    }
+}
+
+
 }  // namespace
 
 int spmv32(const lpcg_system *s, const float *x, float *y, hipStream_t st) {
     return launch_spmv<float, float>(s, s->val32, x, y, st);
+}
+
+// Column windows of the LDS-staged SpMV for R rows per block (synchronous).
+// EINVAL when the blocks exceed the published-partial slots or the longest
+// window the LDS budget (kSpmvMaxWindow inputs).
+int spmv_prepare_window(lpcg_system *s, int R, hipStream_t st) {
+    if (R < 64 || nblk(s->n, R) > kMaxSpmvBlocks) {
+        set_error("SpMV: %d rows per block give %d blocks (1 .. %d)", R, nblk(s->n, std::max(R, 1)), kMaxSpmvBlocks);
+        return LPCG_EINVAL;
+    }
+    if (s->spmv_win_rows == R) return s->spmv_wmax <= kSpmvMaxWindow ? LPCG_OK : LPCG_EINVAL;
+    if (!s->spmv_win) {
+        void *q = nullptr;
+        LPCG_HIP(hipMalloc(&q, sizeof(int) * (2 * (size_t)kMaxSpmvBlocks + 1)));
+        s->allocs.push_back(q);
+        s->spmv_win = (int *)q;
+    }
+    int *wmax = s->spmv_win + 2 * kMaxSpmvBlocks;
+    k_set_i32<<<1, 1, 0, st>>>(wmax, 0);
+    k_spmv_window<<<nblk(s->n, R), 256, 0, st>>>(s->n, R, s->rowptr, s->colind, s->spmv_win, wmax);
+    LPCG_LAUNCH_CHECK();
+    int h = 0;
+    LPCG_HIP(hipMemcpyAsync(&h, wmax, sizeof(int), hipMemcpyDeviceToHost, st));
+    LPCG_HIP(hipStreamSynchronize(st));
+    s->spmv_win_rows = R;
+    s->spmv_wmax = h;
+    if (h > kSpmvMaxWindow) {
+        set_error("SpMV: a window of %d inputs exceeds the LDS budget (%d) at %d rows per block", h,
+                  kSpmvMaxWindow, R);
+        return LPCG_EINVAL;
+    }
+    return LPCG_OK;
 }
 int spmv64(const lpcg_system *s, const double *x, double *y, hipStream_t st) {
     return launch_spmv<double, double>(s, s->val64, x, y, st);
@@ -848,7 +942,8 @@ extern "C" int lpcg_get_trsv_cfg(const lpcg_system *s, int32_t direction, lpcg_t
         std::memset(out, 0, sizeof(*out));
         out->direction = 2;
         out->mode = s->spmv_group;
-        out->waves = s->spmv_blocks;
+        out->waves = s->spmv_rows > 0 ? nblk(s->n, s->spmv_rows) : s->spmv_blocks;
+        out->block_rows = s->spmv_rows;
         return LPCG_OK;
     }
     const TrsvCfg &c = s->trsv[direction];
@@ -864,15 +959,25 @@ extern "C" int lpcg_get_trsv_cfg(const lpcg_system *s, int32_t direction, lpcg_t
 }
 
 extern "C" int lpcg_set_trsv_cfg(lpcg_system *s, const lpcg_trsv_cfg *cfg) {
-    if (s && cfg && cfg->direction == 2) {  // the SpMV: G lanes per row on `waves` blocks
-        const int G = cfg->mode;
-        if ((G != 4 && G != 8 && G != 16 && G != 32 && G != 64) || cfg->waves < 1 || cfg->waves > kMaxSpmvBlocks) {
+    if (s && cfg && cfg->direction == 2) {  // the SpMV: G lanes per row on `waves` blocks, or staged
+        const int G = cfg->mode, R = cfg->block_rows;
+        if ((G != 4 && G != 8 && G != 16 && G != 32 && G != 64) || R < 0 ||
+            (R == 0 && (cfg->waves < 1 || cfg->waves > kMaxSpmvBlocks))) {
             set_error("lpcg_set_trsv_cfg: SpMV lanes per row must be 4, 8, 16, 32 or 64 and blocks 1..%d",
                       kMaxSpmvBlocks);
             return LPCG_EINVAL;
         }
+        if (R > 0) {  // LDS-staged: R rows per block
+            int rc = spmv_prepare_window(s, R, 0);
+            if (rc) {
+                // the previous configuration stays in force, with its windows
+                if (s->spmv_rows > 0) (void)spmv_prepare_window(s, s->spmv_rows, 0);
+                return rc;
+            }
+        }
         s->spmv_group = G;
-        s->spmv_blocks = cfg->waves;
+        if (R == 0) s->spmv_blocks = cfg->waves;
+        s->spmv_rows = R;
         drop_graphs(s);
         return LPCG_OK;
     }
@@ -986,44 +1091,66 @@ extern "C" int lpcg_autotune(lpcg_system *s, const float *l_val, const float *ut
         }
         s->trsv[dir] = best_c;
     }
-    // SpMV: lanes per row G (64 / G rows per wavefront) and grid size, timed
+    // SpMV: lanes per row G (64 / G rows per wavefront) and grid size, then
+    // the LDS-staged form with R rows per block where the windows fit; timed
     // on w = A p with the FP32 values (the PCG's product)
     {
         double best = 1e30;
-        int best_g = s->spmv_group, best_b = s->spmv_blocks;
+        int best_g = s->spmv_group, best_b = s->spmv_blocks, best_r = 0;
+        auto time_one = [&](int G, int blocks, int R, double &us) -> int {
+            double tot = 0;
+            for (int r = 0; r <= reps; ++r) {
+                LPCG_HIP(hipEventRecord(ev.a, st));
+                int rc = launch_spmv(s, s->val32, s->p, s->w, st, G, blocks, R);
+                if (rc) return rc;
+                LPCG_HIP(hipEventRecord(ev.b, st));
+                LPCG_HIP(hipEventSynchronize(ev.b));
+                float ms = 0;
+                LPCG_HIP(hipEventElapsedTime(&ms, ev.a, ev.b));
+                if (r > 0) tot += ms;
+            }
+            us = 1e3 * tot / reps;
+            if (count < table_len) {
+                lpcg_trsv_cfg &e = table[count];
+                std::memset(&e, 0, sizeof(e));
+                e.direction = 2;
+                e.mode = G;
+                e.waves = R > 0 ? nblk(s->n, R) : blocks;
+                e.block_rows = R;
+                e.us = us;
+            }
+            ++count;
+            if (us < best) {
+                best = us;
+                best_g = G;
+                best_b = blocks;
+                best_r = R;
+            }
+            return LPCG_OK;
+        };
         for (int G : {4, 8, 16, 32, 64})
             for (int cap : {512, 1024, 2048}) {
                 const int blocks = std::max(1, std::min(cap, nblk(s->n, kVecThreads / G)));
                 if (cap > 512 && blocks < cap / 2) continue;  // the same grid as a smaller cap
-                double tot = 0;
-                for (int r = 0; r <= reps; ++r) {
-                    LPCG_HIP(hipEventRecord(ev.a, st));
-                    int rc = launch_spmv(s, s->val32, s->p, s->w, st, G, blocks);
-                    if (rc) return rc;
-                    LPCG_HIP(hipEventRecord(ev.b, st));
-                    LPCG_HIP(hipEventSynchronize(ev.b));
-                    float ms = 0;
-                    LPCG_HIP(hipEventElapsedTime(&ms, ev.a, ev.b));
-                    if (r > 0) tot += ms;
-                }
-                const double us = 1e3 * tot / reps;
-                if (count < table_len) {
-                    lpcg_trsv_cfg &e = table[count];
-                    std::memset(&e, 0, sizeof(e));
-                    e.direction = 2;
-                    e.mode = G;
-                    e.waves = blocks;
-                    e.us = us;
-                }
-                ++count;
-                if (us < best) {
-                    best = us;
-                    best_g = G;
-                    best_b = blocks;
-                }
+                double us;
+                int rc = time_one(G, blocks, 0, us);
+                if (rc) return rc;
             }
+        for (int R : {256, 512, 1024}) {
+            if (nblk(s->n, R) > kMaxSpmvBlocks || spmv_prepare_window(s, R, st) != LPCG_OK) continue;
+            for (int G : {4, 8}) {
+                double us;
+                int rc = time_one(G, 0, R, us);
+                if (rc) return rc;
+            }
+        }
         s->spmv_group = best_g;
         s->spmv_blocks = best_b;
+        s->spmv_rows = best_r;
+        if (best_r > 0) {
+            int rc = spmv_prepare_window(s, best_r, st);
+            if (rc) return rc;
+        }
     }
     if (n_table) *n_table = count;
     drop_graphs(s);

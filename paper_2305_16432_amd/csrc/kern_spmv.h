@@ -32,4 +32,55 @@ __global__ void __launch_bounds__(256) k_spmv(int n, const int *__restrict__ rp,
     }
 }
 
+// ---------------------------------------------------------------------------
+// LDS-staged input.  Block b owns rows [b R, (b + 1) R) and first copies the
+// input over its window of off-diagonal columns, win[2b] .. win[2b + 1]
+// (lo > hi: none), into LDS with coalesced loads; the rows then read their
+// off-diagonal inputs from LDS and the diagonal's from memory (a row's own
+// input lies outside the window in multicolour orders, where a block's rows
+// and their neighbours sit in different colours).  Per row the entries are
+// summed as in k_spmv (same lanes, order and reduction), so the result is
+// the same bit for bit.  Bytes per row: as k_spmv, with the gathered inputs
+// replaced by the window (its length over R per row).  The windows are
+// computed once per pattern and R (k_spmv_window, factor.hip).
+
+// Copy len (>= 0) inputs g[0 .. len) into LDS, eight loads per thread in
+// flight before their stores (loads clamped to the window, stores guarded).
+template <typename F>
+__device__ __forceinline__ void stage_window(float *sx, int len, F &&load) {
+    for (int base = 0; base < len; base += 8 * 256) {
+        float t[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) t[u] = load(min(base + u * 256 + (int)threadIdx.x, len - 1));
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int i = base + u * 256 + (int)threadIdx.x;
+            if (i < len) sx[i] = t[u];
+        }
+    }
+}
+
+template <int G>
+__global__ void __launch_bounds__(256) k_spmv_st(int n, int R, const int *__restrict__ rp,
+                                                 const int *__restrict__ ci, const float *__restrict__ v,
+                                                 const float *__restrict__ x, float *__restrict__ y,
+                                                 const int *__restrict__ win) {
+    extern __shared__ float sx[];
+    const int r0 = blockIdx.x * R, r1 = min(n, r0 + R);
+    const int lo = win[2 * blockIdx.x], len = win[2 * blockIdx.x + 1] - lo + 1;
+    stage_window(sx, len, [&](int i) { return x[lo + i]; });
+    __syncthreads();
+    const int sub = threadIdx.x % G;
+    for (int row = r0 + (int)threadIdx.x / G; row < r1; row += 256 / G) {
+        float acc = 0;
+        for (int k = rp[row] + sub; k < rp[row + 1]; k += G) {
+            const int c = ci[k];
+            acc += v[k] * (c == row ? x[row] : sx[c - lo]);
+        }
+#pragma unroll
+        for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, G);
+        if (sub == 0) y[row] = acc;
+    }
+}
+
 }  // namespace lpcg

@@ -19,6 +19,7 @@ int hip_fail(hipError_t e, const char *what, const char *file, int line);
 constexpr int kVecThreads = 256;
 constexpr int kMaxVecBlocks = 1024;
 constexpr int kMaxSpmvBlocks = 2048;
+constexpr int kSpmvMaxWindow = 16384;  // inputs one block of the LDS-staged SpMV may stage (64 KB)
 // Default substitution mode: level-synchronous up to this many levels.
 constexpr int kLevelModeMaxLevels = 16;
 // The autotuner tries level-synchronous launches up to this many levels.
@@ -121,6 +122,13 @@ struct lpcg_system {
     int vec_blocks = 1;          // grid of the fixed-grid vector kernels
     int spmv_blocks = 1;         // grid of the fused SpMV + p.w kernel
     int spmv_group = 8;          // lanes per row in SpMV
+    // LDS-staged SpMV (kern_spmv.h): spmv_rows = R > 0 rows per block, each
+    // block staging its input over the window spmv_win[2b], spmv_win[2b + 1]
+    // (device; computed for spmv_win_rows); 0 = the gather form
+    int spmv_rows = 0;
+    int spmv_win_rows = 0;
+    int spmv_wmax = 0;           // longest window (elements) for spmv_win_rows
+    int *spmv_win = nullptr;     // [2 * kMaxSpmvBlocks]
     lpcg::TrsvCfg trsv[2];       // forward (L) and backward (L^T) substitution
     lpcg::TrsvCfg ic0_cfg;       // IC(0): the fastest dependency-driven forward configuration
     bool ic0_tuned = false;

@@ -434,6 +434,70 @@ __global__ void __launch_bounds__(VT) k_spmv_pw(Args a) {
     }
 }
 
+// LDS-staged form of k_spmv_pw (kern_spmv.h): block b forms the new search
+// direction p_j = z_j + beta p_prev_j over its column window into LDS (each
+// input read once per block, in order), writes p and w = A p for its own rows
+// (the diagonal's p from its own inputs) and publishes p.w.  The arithmetic
+// per entry and the reduction are those of k_spmv_pw: p, w and p.w agree
+// bit for bit.
+template <int G, int KIND>
+__global__ void __launch_bounds__(VT) k_spmv_pw_st(Args a, int R, const int *__restrict__ win) {
+    extern __shared__ float sp[];
+    __shared__ double lds[VT / kWave];
+    if (is_done(a)) return;
+    const int it = a.ctrl[C_IT];
+    const bool first = it == 0;
+    const float beta = (float)a.scal[S_BETA];
+    const int *__restrict__ rp = a.rp;
+    const int *__restrict__ ci = a.ci;
+    const float *__restrict__ v = a.v32;
+    const float *__restrict__ zs = KIND == LPCG_PC_NONE ? a.r : (const float *)a.z;
+    const float *__restrict__ pq = (it & 1) ? a.p0 : a.p1;
+    float *__restrict__ pnw = (it & 1) ? a.p1 : a.p0;
+    float *__restrict__ w = a.w;
+    const int r0 = blockIdx.x * R, r1 = min(a.n, r0 + R);
+    const int lo = win[2 * blockIdx.x], len = win[2 * blockIdx.x + 1] - lo + 1;
+    stage_window(sp, len, [&](int i) {
+        const float zj = zs[lo + i];
+        return first ? zj : __fmaf_rn(beta, pq[lo + i], zj);
+    });
+    __syncthreads();
+    const int sub = threadIdx.x % G;
+    double pw = 0;
+    for (int row = r0 + (int)threadIdx.x / G; row < r1; row += VT / G) {
+        const float zi = zs[row];
+        const float pi = first ? zi : __fmaf_rn(beta, pq[row], zi);
+        float acc = 0.f;
+        for (int k = rp[row] + sub; k < rp[row + 1]; k += G) {
+            const int c = ci[k];
+            acc += v[k] * (c == row ? pi : sp[c - lo]);
+        }
+#pragma unroll
+        for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, G);
+        if (sub == 0) {
+            pnw[row] = pi;
+            w[row] = acc;
+            pw += (double)pi * (double)acc;
+        }
+    }
+    pw = block_sum<VT>(pw, lds);
+    if (threadIdx.x == 0) publish_partial(a.sp_pw, blockIdx.x, pw);
+    if (!is_reducer()) return;
+    const double pwt = reduce_published<VT>(a.sp_pw, gridDim.x, lds);
+    if (threadIdx.x == 0) {
+        const double rz = a.scal[S_RZ0];
+        a.ctrl[C_IT] = it + 1;
+        if (!(pwt > 0.0) || !isfinite(pwt) || !isfinite(rz)) {
+            a.ctrl[C_DONE] = 1;
+            a.ctrl[C_STATUS] = LPCG_EBREAKDOWN;
+            a.ctrl[C_ITERS] = it + 1;
+        } else {
+            a.scal[S_ALPHA] = rz / pwt;
+            if (a.coef && it + 1 <= a.maxit) a.coef[2 * (it + 1)] = rz / pwt;
+        }
+    }
+}
+
 // x += alpha p, r -= alpha w, ||r||^2 (Jacobi/none: r.z) partials, presets
 // for the dependency-driven substitutions; the reducer block takes the
 // convergence test (Jacobi/none: and beta) and rearms the tickets.
@@ -598,6 +662,19 @@ int enqueue_apply(const lpcg_system *s, const Args &a, hipStream_t st) {
 
 template <int KIND>
 int enqueue_spmv(const lpcg_system *s, const Args &a, hipStream_t st) {
+    if (s->spmv_rows > 0) {  // LDS-staged (windows prepared when the configuration was set)
+        const int R = s->spmv_rows, nb = (s->n + R - 1) / R;
+        const size_t lds = sizeof(float) * (size_t)std::max(1, s->spmv_wmax);
+        switch (s->spmv_group) {
+            case 4: k_spmv_pw_st<4, KIND><<<nb, VT, lds, st>>>(a, R, s->spmv_win); break;
+            case 8: k_spmv_pw_st<8, KIND><<<nb, VT, lds, st>>>(a, R, s->spmv_win); break;
+            case 16: k_spmv_pw_st<16, KIND><<<nb, VT, lds, st>>>(a, R, s->spmv_win); break;
+            case 32: k_spmv_pw_st<32, KIND><<<nb, VT, lds, st>>>(a, R, s->spmv_win); break;
+            default: k_spmv_pw_st<64, KIND><<<nb, VT, lds, st>>>(a, R, s->spmv_win); break;
+        }
+        LPCG_LAUNCH_CHECK();
+        return LPCG_OK;
+    }
     const int sb = s->spmv_blocks;
     switch (s->spmv_group) {
         case 4: k_spmv_pw<4, KIND><<<sb, VT, 0, st>>>(a); break;

@@ -136,7 +136,10 @@ def test_autotune_c3_full_size(ordering):
     best = min(sp, key=lambda t: t["us"])
     got = lpcg.get_trsv_cfg(S, 2)
     assert got["mode"] == best["mode"] and got["waves"] == best["waves"]
-    print(f"  spmv: G {best['mode']} blocks {best['waves']}: {best['us']:.1f} us")
+    assert got["block_rows"] == best["block_rows"]
+    assert {t["block_rows"] for t in sp} >= {0, 256, 512, 1024}  # the LDS-staged form timed too
+    for t in sorted(sp, key=lambda t: t["us"])[:6]:
+        print(f"  spmv: G {t['mode']} blocks {t['waves']} rows/block {t['block_rows']}: {t['us']:.1f} us")
     x, res = lpcg.pcg_solve(S, lpcg.PC_LLT, cuda_f64(b), l_val=l, ut_val=ut, tol=1e-6, max_restarts=2)
     assert res["status"] == 0 and O.true_relres(A, b, host(x)) <= 1e-6
 
@@ -158,6 +161,79 @@ def test_spmv_lanes_per_row_within_bound(G):
     b = np.random.default_rng(2).standard_normal(A.n)
     xs, res = lpcg.pcg_solve(S, lpcg.PC_JACOBI, cuda_f64(b), tol=1e-6, max_restarts=2)
     assert res["status"] == 0 and O.true_relres(A, b, host(xs)) <= 1e-6
+
+
+def _spmv_cases():
+    m = matrices_small()
+    return [(m["heat3d_13"], 0), (m["heat3d_13"], 1), (m["fem_40"], 0), (m["fem_40"], 1),
+            (m["poisson2d_32"], 1), (m["tridiag_1000"], 0)]
+
+
+@pytest.mark.parametrize("case", range(6))
+def test_spmv_staged_matches_gather_bit_for_bit(case):
+    """The LDS-staged SpMV (block of R rows, inputs staged over the block's
+    column window) sums every row exactly as the gather form with the same
+    lanes per row: equal bit for bit, ragged last blocks included; the PCG
+    with the staged product ends as the gather form's does (the 1D Laplacian,
+    kappa ~ 1e6, does not reach 1e-6 with FP32 Jacobi-PCG in n iterations in
+    either form) and, where that converges, in the same iterations."""
+    A, ordering = _spmv_cases()[case]
+    print(f"[spmv staged] case {case} n={A.n} ordering {ordering}", flush=True)
+    S = gpu_system(A, None, ordering)
+    x = torch.as_tensor(np.random.default_rng(3).standard_normal(A.n).astype(np.float32)).cuda()
+    b = np.random.default_rng(4).standard_normal(A.n)
+    for G in (4, 8):
+        lpcg.set_trsv_cfg(S, 2, G, waves=64)
+        y0 = host(lpcg.spmv(S, x))
+        _, r0 = lpcg.pcg_solve(S, lpcg.PC_JACOBI, cuda_f64(b), tol=1e-6, max_restarts=2)
+        for R in (256, 512, 1024):
+            lpcg.set_trsv_cfg(S, 2, G, block_rows=R)
+            got = lpcg.get_trsv_cfg(S, 2)
+            assert got["mode"] == G and got["block_rows"] == R and got["waves"] == -(-A.n // R)
+            y1 = host(lpcg.spmv(S, x))
+            assert np.array_equal(y0.view(np.uint32), y1.view(np.uint32)), (G, R)
+            xs, r1 = lpcg.pcg_solve(S, lpcg.PC_JACOBI, cuda_f64(b), tol=1e-6, max_restarts=2)
+            assert r1["status"] == r0["status"], (G, R, r0, r1)
+            if r0["status"] == 0:
+                assert O.true_relres(A, b, host(xs)) <= 1e-6
+                assert abs(r1["iters"] - r0["iters"]) <= 1, (G, R, r0["iters"], r1["iters"])
+
+
+def test_spmv_staged_c3_full_size():
+    """64^3 in both orderings: staged and gather products equal bit for bit;
+    IC(0)-PCG with the staged product matches the gather form's iterations."""
+    A, b = g.heat_system_3d(64, 1e-3, 1000, 2000)
+    x = torch.as_tensor(np.random.default_rng(5).standard_normal(A.n).astype(np.float32)).cuda()
+    for ordering in (0, 1):
+        print(f"[spmv staged] heat3d_64 ordering {ordering}", flush=True)
+        S = gpu_system(A, None, ordering)
+        l, ut, _ = lpcg.ic0(S)
+        lpcg.set_trsv_cfg(S, 2, 4, waves=1024)
+        y0 = host(lpcg.spmv(S, x))
+        _, r0 = lpcg.pcg_solve(S, lpcg.PC_LLT, cuda_f64(b), l_val=l, ut_val=ut, tol=1e-6, max_restarts=2)
+        for R in (256, 1024):
+            lpcg.set_trsv_cfg(S, 2, 4, block_rows=R)
+            assert np.array_equal(y0.view(np.uint32), host(lpcg.spmv(S, x)).view(np.uint32)), R
+            xs, r1 = lpcg.pcg_solve(S, lpcg.PC_LLT, cuda_f64(b), l_val=l, ut_val=ut, tol=1e-6, max_restarts=2)
+            assert r1["status"] == 0 and O.true_relres(A, b, host(xs)) <= 1e-6
+            assert abs(r1["iters"] - r0["iters"]) <= 1, (R, r0["iters"], r1["iters"])
+
+
+def test_spmv_staged_rejects_bad_rows():
+    """Rows per block below 64, or more blocks than the partial slots
+    (64^3 at 64 rows per block), are refused and the configuration in force
+    stays (with its windows)."""
+    A, _ = g.heat_system_3d(64, 1e-3, 1, 2)
+    S = gpu_system(A)
+    x = torch.as_tensor(np.random.default_rng(6).standard_normal(A.n).astype(np.float32)).cuda()
+    lpcg.set_trsv_cfg(S, 2, 8, block_rows=512)
+    y0 = host(lpcg.spmv(S, x))
+    for bad in (32, 64, -1):
+        with pytest.raises(lpcg.LpcgError) as e:
+            lpcg.set_trsv_cfg(S, 2, 8, block_rows=bad)
+        assert e.value.code == lpcg.EINVAL
+        assert lpcg.get_trsv_cfg(S, 2)["block_rows"] == 512
+    assert np.array_equal(y0.view(np.uint32), host(lpcg.spmv(S, x)).view(np.uint32))
 
 
 def test_trsv_cfg_rejects_bad_values():
