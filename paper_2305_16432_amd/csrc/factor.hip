@@ -1095,8 +1095,8 @@ extern "C" int lpcg_autotune(lpcg_system *s, const float *l_val, const float *ut
     // the LDS-staged form with R rows per block where the windows fit; timed
     // on w = A p with the FP32 values (the PCG's product)
     {
-        double best = 1e30;
-        int best_g = s->spmv_group, best_b = s->spmv_blocks, best_r = 0;
+        double best = 1e30, best_gather = 1e30;
+        int best_g = s->spmv_group, best_b = s->spmv_blocks, best_r = 0, gather_b = s->spmv_blocks;
         auto time_one = [&](int G, int blocks, int R, double &us) -> int {
             double tot = 0;
             for (int r = 0; r <= reps; ++r) {
@@ -1126,6 +1126,10 @@ extern "C" int lpcg_autotune(lpcg_system *s, const float *l_val, const float *ut
                 best_b = blocks;
                 best_r = R;
             }
+            if (R == 0 && us < best_gather) {
+                best_gather = us;
+                gather_b = blocks;
+            }
             return LPCG_OK;
         };
         for (int G : {4, 8, 16, 32, 64})
@@ -1144,8 +1148,10 @@ extern "C" int lpcg_autotune(lpcg_system *s, const float *l_val, const float *ut
                 if (rc) return rc;
             }
         }
+        // the gather form's grid stays a valid one (the FP64 product and any
+        // later gather-form launch use it) when the staged form wins
         s->spmv_group = best_g;
-        s->spmv_blocks = best_b;
+        s->spmv_blocks = best_r > 0 ? gather_b : best_b;
         s->spmv_rows = best_r;
         if (best_r > 0) {
             int rc = spmv_prepare_window(s, best_r, st);

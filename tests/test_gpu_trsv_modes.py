@@ -219,6 +219,26 @@ def test_spmv_staged_c3_full_size():
             assert abs(r1["iters"] - r0["iters"]) <= 1, (R, r0["iters"], r1["iters"])
 
 
+def test_spmv_fp64_while_staged():
+    """The FP64 product has no staged form: with the LDS-staged FP32 form in
+    force it runs the gather form on the configured grid, within the FP64
+    per-row bound of the oracle (before and after an autotune)."""
+    A = matrices_small()["fem_40"]
+    S = gpu_system(A)
+    x = np.random.default_rng(7).standard_normal(A.n)
+    ref = O.spmv(A, x)
+    bound = O.spmv(g.CSR(A.n, A.rowptr, A.colind, np.abs(A.val)), np.abs(x))
+    k = np.diff(A.rowptr)
+    lpcg.set_trsv_cfg(S, 2, 4, block_rows=256)
+    y = host(lpcg.spmv(S, cuda_f64(x)))
+    assert np.all(np.abs(y - ref) <= 2 * k * 2.0 ** -53 * bound + 1e-300)
+    l, ut, _ = lpcg.ic0(S)
+    lpcg.autotune(S, l, ut, reps=1)
+    assert lpcg.get_trsv_cfg(S, 2)["waves"] >= 1
+    y = host(lpcg.spmv(S, cuda_f64(x)))
+    assert np.all(np.abs(y - ref) <= 2 * k * 2.0 ** -53 * bound + 1e-300)
+
+
 def test_spmv_staged_rejects_bad_rows():
     """Rows per block below 64, or more blocks than the partial slots
     (64^3 at 64 rows per block), are refused and the configuration in force
