@@ -40,6 +40,13 @@ seeds 0..399; held-out selection as above) gives the benchmark's network:
         --init paper_2305_16432_amd/weights/heat3d_h32_mp3.npz \
         --out paper_2305_16432_amd/weights/heat3d_h32_mp3_ft64.npz
 
+The red-black network (one message-passing layer, completed diagonal; a
+single 32^3 batch of 8 systems is the most the colour analysis takes):
+
+    python -m paper_2305_16432_amd.train --triples /tmp/heat3d_32.npz --batch 8 --h 32 --n-mp 1 \
+        --diag-mode 3 --ordering color --steps 10000 --eval-systems 4 \
+        --out paper_2305_16432_amd/weights/heat3d_h32_mp1_color3.npz
+
 The 2D FEM network (h = 64, five message-passing layers, softplus diagonal;
 1000 systems of a 128 x 128 jittered point grid, batch 32, Adam lr 1e-3):
 

@@ -15,7 +15,8 @@ WDIR = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
 @pytest.mark.parametrize("fname,ordering,h,n_mp,dm", [
     ("heat3d_h32_mp3.npz", 0, 32, 3, 1), ("heat3d_h32_mp3_color.npz", 1, 32, 3, 1),
     ("heat3d_h32_mp3_frobenius.npz", 0, 32, 3, 1), ("heat3d_h32_mp3_ft64.npz", 0, 32, 3, 1),
-    ("heat3d_h32_mp3_color3.npz", 1, 32, 3, 3), ("fem2d_h64_mp5.npz", 0, 64, 5, 1)])
+    ("heat3d_h32_mp3_color3.npz", 1, 32, 3, 3), ("heat3d_h32_mp1_color3.npz", 1, 32, 1, 3),
+    ("fem2d_h64_mp5.npz", 0, 64, 5, 1)])
 def test_weights_file_layout(fname, ordering, h, n_mp, dm):
     W = np.load(os.path.join(WDIR, fname))  # allow_pickle stays False
     assert (int(W["h"]), int(W["n_mp"]), int(W["diag_mode"]), int(W["ordering"])) == (h, n_mp, dm, ordering)
@@ -35,6 +36,6 @@ def test_fine_tuned_network_provenance():
 def test_oracle_triples_provenance():
     """The networks trained since the triple generator came in name a triples
     file (written by the oracle's PCG) as their training data."""
-    for fname in ("heat3d_h32_mp3_color3.npz", "fem2d_h64_mp5.npz"):
+    for fname in ("heat3d_h32_mp3_color3.npz", "heat3d_h32_mp1_color3.npz", "fem2d_h64_mp5.npz"):
         cfg = json.loads(str(np.load(os.path.join(WDIR, fname))["config"]))
         assert cfg["triples"].endswith(".npz") and "m" not in cfg
