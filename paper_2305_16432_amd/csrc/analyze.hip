@@ -330,6 +330,16 @@ __global__ void k_values(int nnz, int n, const double *__restrict__ v64, const i
 
 int nblk(long n, int t) { return (int)((n + t - 1) / t); }
 
+// dst[i] = src[pos[i]] (pos < 0: padding, 0)
+__global__ void k_ell_pack(long count, const int *__restrict__ pos, const float *__restrict__ src,
+                           float *__restrict__ dst) {
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) {
+        const int k = pos[i];
+        dst[i] = k >= 0 ? src[k] : 0.f;
+    }
+}
+
 __global__ void k_fill_part(long n, uint64_t *p) {
     long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = kPartUnset;
@@ -623,6 +633,89 @@ int analyze_impl(const lpcg_csr *A, const int32_t *h_sys, int32_t nsys, lpcg_sys
         LPCG_HIP(hipStreamSynchronize(st));
         if (last == p - 1) s->two_level_p = p;
     }
+    // ELL forms of single systems (the batched solver does not use them): A,
+    // and the two-level pair's suffix rows of L and prefix rows of U = L^T
+    if (nsys == 1) {
+        std::vector<int> hrp(n + 1), hci(nnz);
+        LPCG_HIP(hipMemcpyAsync(hrp.data(), s->rowptr, sizeof(int) * (n + 1), hipMemcpyDeviceToHost, st));
+        LPCG_HIP(hipMemcpyAsync(hci.data(), s->colind, sizeof(int) * (size_t)nnz, hipMemcpyDeviceToHost, st));
+        LPCG_HIP(hipStreamSynchronize(st));
+        int wa = 0;
+        for (int i = 0; i < n; ++i) wa = std::max(wa, hrp[i + 1] - hrp[i]);
+        if (wa >= 1 && wa <= kEllMaxW) {
+            const size_t m = (size_t)wa * n;
+            std::vector<int> col(m), pos(m);
+            for (int t = 0; t < wa; ++t)
+                for (int i = 0; i < n; ++i) {
+                    const int k = hrp[i] + t;
+                    const bool real = k < hrp[i + 1];
+                    col[(size_t)t * n + i] = real ? hci[k] : i;
+                    pos[(size_t)t * n + i] = real ? k : -1;
+                }
+            ALLOC(s->ea_col, m);
+            ALLOC(s->ea_pos, m);
+            ALLOC(s->ea_val, m);
+            LPCG_HIP(hipMemcpyAsync(s->ea_col, col.data(), sizeof(int) * m, hipMemcpyHostToDevice, st));
+            LPCG_HIP(hipMemcpyAsync(s->ea_pos, pos.data(), sizeof(int) * m, hipMemcpyHostToDevice, st));
+            LPCG_HIP(hipStreamSynchronize(st));
+            s->ea_w = wa;
+        }
+        const int p = s->two_level_p;
+        if (p > 0 && p < n) {
+            const int nb = n - p;
+            std::vector<int> lrp(n + 1), lc(nnzl), urp(n + 1), uc(nnzl);
+            LPCG_HIP(hipMemcpyAsync(lrp.data(), s->lrowptr, sizeof(int) * (n + 1), hipMemcpyDeviceToHost, st));
+            LPCG_HIP(hipMemcpyAsync(lc.data(), s->lcol, sizeof(int) * (size_t)nnzl, hipMemcpyDeviceToHost, st));
+            LPCG_HIP(hipMemcpyAsync(urp.data(), s->urowptr, sizeof(int) * (n + 1), hipMemcpyDeviceToHost, st));
+            LPCG_HIP(hipMemcpyAsync(uc.data(), s->ucol, sizeof(int) * (size_t)nnzl, hipMemcpyDeviceToHost, st));
+            LPCG_HIP(hipStreamSynchronize(st));
+            int ws = 0, wp = 0;
+            for (int i = p; i < n; ++i) ws = std::max(ws, lrp[i + 1] - lrp[i] - 1);  // L rows: diagonal last
+            for (int j = 0; j < p; ++j) wp = std::max(wp, urp[j + 1] - urp[j] - 1);  // U rows: diagonal first
+            if (ws >= 1 && ws <= kEllMaxW && wp <= kEllMaxW) {
+                std::vector<int> scol((size_t)ws * nb), spos((size_t)ws * nb), sdpos(nb);
+                std::vector<int> pcol((size_t)std::max(wp, 1) * p), ppos((size_t)std::max(wp, 1) * p), pdpos(p);
+                for (int i = 0; i < nb; ++i) {
+                    const int k0 = lrp[p + i], k1 = lrp[p + i + 1] - 1;
+                    sdpos[i] = k1;
+                    for (int t = 0; t < ws; ++t) {
+                        const bool real = k0 + t < k1;
+                        scol[(size_t)t * nb + i] = real ? lc[k0 + t] : 0;
+                        spos[(size_t)t * nb + i] = real ? k0 + t : -1;
+                    }
+                }
+                for (int j = 0; j < p; ++j) {
+                    const int k0 = urp[j] + 1, k1 = urp[j + 1];
+                    pdpos[j] = urp[j];
+                    for (int t = 0; t < wp; ++t) {
+                        const bool real = k0 + t < k1;
+                        pcol[(size_t)t * p + j] = real ? uc[k0 + t] : p;
+                        ppos[(size_t)t * p + j] = real ? k0 + t : -1;
+                    }
+                }
+                const size_t ms = (size_t)ws * nb, mp = (size_t)std::max(wp, 1) * p;
+                ALLOC(s->e2_scol, ms);
+                ALLOC(s->e2_spos, ms);
+                ALLOC(s->e2_sdpos, nb);
+                ALLOC(s->e2_pcol, mp);
+                ALLOC(s->e2_ppos, mp);
+                ALLOC(s->e2_pdpos, p);
+                ALLOC(s->e2_sval, ms);
+                ALLOC(s->e2_sdiag, nb);
+                ALLOC(s->e2_pval, mp);
+                ALLOC(s->e2_pdiag, p);
+                LPCG_HIP(hipMemcpyAsync(s->e2_scol, scol.data(), sizeof(int) * ms, hipMemcpyHostToDevice, st));
+                LPCG_HIP(hipMemcpyAsync(s->e2_spos, spos.data(), sizeof(int) * ms, hipMemcpyHostToDevice, st));
+                LPCG_HIP(hipMemcpyAsync(s->e2_sdpos, sdpos.data(), sizeof(int) * nb, hipMemcpyHostToDevice, st));
+                LPCG_HIP(hipMemcpyAsync(s->e2_pcol, pcol.data(), sizeof(int) * mp, hipMemcpyHostToDevice, st));
+                LPCG_HIP(hipMemcpyAsync(s->e2_ppos, ppos.data(), sizeof(int) * mp, hipMemcpyHostToDevice, st));
+                LPCG_HIP(hipMemcpyAsync(s->e2_pdpos, pdpos.data(), sizeof(int) * p, hipMemcpyHostToDevice, st));
+                LPCG_HIP(hipStreamSynchronize(st));
+                s->e2_ws = ws;
+                s->e2_wp = wp;
+            }
+        }
+    }
     // SpMV lanes per row from the mean row length
     const double mean = (double)nnz / n;
     s->spmv_group = mean <= 4 ? 4 : mean <= 8 ? 8 : mean <= 16 ? 16 : mean <= 32 ? 32 : 64;
@@ -630,6 +723,7 @@ int analyze_impl(const lpcg_csr *A, const int32_t *h_sys, int32_t nsys, lpcg_sys
     k_values<<<nblk(std::max(n, nnz), 256), 256, 0, st>>>(nnz, n, A->val, nullptr, s->dpos, s->val64,
                                                            s->val32, s->diag64);
     LPCG_LAUNCH_CHECK();
+    if ((rc = ell_pack_a(s, st))) return rc;
     LPCG_HIP(hipStreamSynchronize(st));
 #undef ALLOC
     return LPCG_OK;
@@ -754,6 +848,14 @@ int to_internal_f32(const lpcg_system *s, const float *src, float *dst, hipStrea
 int from_internal_f32(const lpcg_system *s, const float *src, float *dst, hipStream_t st) {
     return permute_vec(s, src, dst, false, st);
 }
+
+int ell_pack_a(const lpcg_system *s, hipStream_t st) {
+    if (s->ea_w == 0) return LPCG_OK;
+    const long m = (long)s->ea_w * s->n;
+    k_ell_pack<<<nblk(m, 256), 256, 0, st>>>(m, s->ea_pos, s->val32, s->ea_val);
+    LPCG_LAUNCH_CHECK();
+    return LPCG_OK;
+}
 }  // namespace lpcg
 
 extern "C" int lpcg_analyze(const lpcg_csr *A, const int32_t *sys_rowptr, int32_t nsys, int32_t ordering,
@@ -808,7 +910,7 @@ extern "C" int lpcg_update_values(lpcg_system *s, const double *val, hipStream_t
     k_values<<<nblk(std::max(s->n, s->nnz), 256), 256, 0, stream>>>(s->nnz, s->n, val, s->psrc, s->dpos,
                                                                        s->val64, s->val32, s->diag64);
     LPCG_LAUNCH_CHECK();
-    return LPCG_OK;
+    return ell_pack_a(s, stream);
 }
 
 extern "C" int lpcg_get_info(const lpcg_system *s, lpcg_info *info) {

@@ -93,8 +93,11 @@ __device__ __forceinline__ T block_sum(T v, T *lds) {
 // waits for each slot to be published and rearms it with kPartUnset.  Each
 // thread issues the loads of up to kPubBatch of its slots at once and
 // re-polls only the ones still unset, so the wait costs about one memory
-// round trip rather than one per slot.
-constexpr int kPubBatch = 16;
+// round trip rather than one per slot.  Eight slots per thread cover 2048
+// partials of a 256-thread block in one batch and keep the kernels that
+// contain the reducer at or under 64 VGPRs (eight waves per SIMD; sixteen
+// slots needed about 75, which capped them at six).
+constexpr int kPubBatch = 8;
 template <int BS>
 __device__ __forceinline__ double reduce_published(double *part, int np, double *lds) {
     uint64_t *q = reinterpret_cast<uint64_t *>(part);

@@ -21,15 +21,32 @@ __global__ void k_zero_i32(int *p, int count) {
 
 // CSR SpMV with G = group lanes per row (64 / G rows per wavefront) on
 // `blocks` blocks (0: the system's tuned grid), or (FP32, rows > 0, windows
-// prepared for that R) the LDS-staged form with `rows` rows per block.
+// prepared for that R) the LDS-staged form with `rows` rows per block, or
+// (group 1, or group 0 when the tuned form is ELL; A's FP32 values) the ELL
+// form.
 template <typename VT, typename XT>
 int launch_spmv(const lpcg_system *s, const VT *v, const XT *x, XT *y, hipStream_t st, int group = 0,
                 int blocks = 0, int rows = -1) {
     const int threads = 256;
+    if constexpr (std::is_same<VT, float>::value && std::is_same<XT, float>::value) {
+        if (group == 0 && s->spmv_ell && v == s->val32) group = 1;
+    }
     if (group == 0) group = s->spmv_group;
     if (blocks == 0) blocks = s->spmv_blocks;
     if (rows < 0) rows = s->spmv_rows;
     if constexpr (std::is_same<VT, float>::value && std::is_same<XT, float>::value) {
+        if (group == 1) {  // ELL form (A's FP32 values only)
+            if (s->ea_w == 0 || v != s->val32) {
+                set_error("SpMV: the ELL form serves A's FP32 values of a pattern with rows of at most %d entries",
+                          kEllMaxW);
+                return LPCG_EINVAL;
+            }
+            const int eb = std::max(1, std::min(kMaxSpmvBlocks, nblk(s->n, threads)));
+            if (s->ea_w <= 4) k_spmv_e<4><<<eb, threads, 0, st>>>(s->n, s->ea_w, s->ea_col, s->ea_val, x, y);
+            else k_spmv_e<8><<<eb, threads, 0, st>>>(s->n, s->ea_w, s->ea_col, s->ea_val, x, y);
+            LPCG_LAUNCH_CHECK();
+            return LPCG_OK;
+        }
         if (rows > 0) {
             if (rows != s->spmv_win_rows) {
                 set_error("SpMV: windows not prepared for %d rows per block", rows);
@@ -941,9 +958,11 @@ extern "C" int lpcg_get_trsv_cfg(const lpcg_system *s, int32_t direction, lpcg_t
     if (direction == 2) {  // the SpMV: lanes per row and grid
         std::memset(out, 0, sizeof(*out));
         out->direction = 2;
-        out->mode = s->spmv_group;
-        out->waves = s->spmv_rows > 0 ? nblk(s->n, s->spmv_rows) : s->spmv_blocks;
-        out->block_rows = s->spmv_rows;
+        out->mode = s->spmv_ell ? 1 : s->spmv_group;
+        out->waves = s->spmv_ell ? std::max(1, std::min(kMaxSpmvBlocks, nblk(s->n, kVecThreads)))
+                     : s->spmv_rows > 0 ? nblk(s->n, s->spmv_rows)
+                                        : s->spmv_blocks;
+        out->block_rows = s->spmv_ell ? 0 : s->spmv_rows;
         return LPCG_OK;
     }
     const TrsvCfg &c = s->trsv[direction];
@@ -959,8 +978,19 @@ extern "C" int lpcg_get_trsv_cfg(const lpcg_system *s, int32_t direction, lpcg_t
 }
 
 extern "C" int lpcg_set_trsv_cfg(lpcg_system *s, const lpcg_trsv_cfg *cfg) {
-    if (s && cfg && cfg->direction == 2) {  // the SpMV: G lanes per row on `waves` blocks, or staged
+    if (s && cfg && cfg->direction == 2) {  // the SpMV: G lanes per row on `waves` blocks, or staged, or ELL
         const int G = cfg->mode, R = cfg->block_rows;
+        if (G == 1) {  // the ELL form: rows of at most kEllMaxW entries (the gather form's settings stay)
+            if (s->ea_w == 0 || s->nsys != 1) {
+                set_error("lpcg_set_trsv_cfg: no ELL form (a row has more than %d entries, or a batched system)",
+                          kEllMaxW);
+                return LPCG_EINVAL;
+            }
+            s->spmv_ell = true;
+            s->spmv_rows = 0;
+            drop_graphs(s);
+            return LPCG_OK;
+        }
         if ((G != 4 && G != 8 && G != 16 && G != 32 && G != 64) || R < 0 ||
             (R == 0 && (cfg->waves < 1 || cfg->waves > kMaxSpmvBlocks))) {
             set_error("lpcg_set_trsv_cfg: SpMV lanes per row must be 4, 8, 16, 32 or 64 and blocks 1..%d",
@@ -978,6 +1008,7 @@ extern "C" int lpcg_set_trsv_cfg(lpcg_system *s, const lpcg_trsv_cfg *cfg) {
         s->spmv_group = G;
         if (R == 0) s->spmv_blocks = cfg->waves;
         s->spmv_rows = R;
+        s->spmv_ell = false;
         drop_graphs(s);
         return LPCG_OK;
     }
@@ -1092,24 +1123,18 @@ extern "C" int lpcg_autotune(lpcg_system *s, const float *l_val, const float *ut
         s->trsv[dir] = best_c;
     }
     // SpMV: lanes per row G (64 / G rows per wavefront) and grid size, then
-    // the LDS-staged form with R rows per block where the windows fit; timed
-    // on w = A p with the FP32 values (the PCG's product)
+    // the LDS-staged form with R rows per block where the windows fit.  Each
+    // candidate is timed as the PCG's product kernel (p = z + beta p_prev,
+    // w = A p and p.w, median of reps launches), which is where the choice
+    // counts: the plain product ranks G = 4 and 8 within a few percent, the
+    // PCG's form (two gathered vectors per entry) does not
     {
         double best = 1e30, best_gather = 1e30;
         int best_g = s->spmv_group, best_b = s->spmv_blocks, best_r = 0, gather_b = s->spmv_blocks;
+        int gather_g = s->spmv_group;
         auto time_one = [&](int G, int blocks, int R, double &us) -> int {
-            double tot = 0;
-            for (int r = 0; r <= reps; ++r) {
-                LPCG_HIP(hipEventRecord(ev.a, st));
-                int rc = launch_spmv(s, s->val32, s->p, s->w, st, G, blocks, R);
-                if (rc) return rc;
-                LPCG_HIP(hipEventRecord(ev.b, st));
-                LPCG_HIP(hipEventSynchronize(ev.b));
-                float ms = 0;
-                LPCG_HIP(hipEventElapsedTime(&ms, ev.a, ev.b));
-                if (r > 0) tot += ms;
-            }
-            us = 1e3 * tot / reps;
+            const int rc = time_pcg_product(s, G, blocks, R, reps, us, st);
+            if (rc) return rc;
             if (count < table_len) {
                 lpcg_trsv_cfg &e = table[count];
                 std::memset(&e, 0, sizeof(e));
@@ -1126,8 +1151,9 @@ extern "C" int lpcg_autotune(lpcg_system *s, const float *l_val, const float *ut
                 best_b = blocks;
                 best_r = R;
             }
-            if (R == 0 && us < best_gather) {
+            if (G > 1 && R == 0 && us < best_gather) {
                 best_gather = us;
+                gather_g = G;
                 gather_b = blocks;
             }
             return LPCG_OK;
@@ -1148,10 +1174,17 @@ extern "C" int lpcg_autotune(lpcg_system *s, const float *l_val, const float *ut
                 if (rc) return rc;
             }
         }
-        // the gather form's grid stays a valid one (the FP64 product and any
-        // later gather-form launch use it) when the staged form wins
-        s->spmv_group = best_g;
-        s->spmv_blocks = best_r > 0 ? gather_b : best_b;
+        if (s->ea_w > 0) {  // the ELL form (one row per lane)
+            double us;
+            int rc = time_one(1, std::max(1, std::min(kMaxSpmvBlocks, nblk(s->n, kVecThreads))), 0, us);
+            if (rc) return rc;
+        }
+        // the gather form's lanes and grid stay valid ones (the FP64 product
+        // and any later gather-form launch use them) when the staged or the
+        // ELL form wins
+        s->spmv_ell = best_g == 1;
+        s->spmv_group = best_g == 1 ? gather_g : best_g;
+        s->spmv_blocks = best_r > 0 || best_g == 1 ? gather_b : best_b;
         s->spmv_rows = best_r;
         if (best_r > 0) {
             int rc = spmv_prepare_window(s, best_r, st);

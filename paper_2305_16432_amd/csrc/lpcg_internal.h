@@ -19,6 +19,7 @@ int hip_fail(hipError_t e, const char *what, const char *file, int line);
 constexpr int kVecThreads = 256;
 constexpr int kMaxVecBlocks = 1024;
 constexpr int kMaxSpmvBlocks = 2048;
+constexpr int kEllMaxW = 8;  // longest row (stored entries) of the ELL forms
 constexpr int kSpmvMaxWindow = 16384;  // inputs one block of the LDS-staged SpMV may stage (64 KB)
 // Default substitution mode: level-synchronous up to this many levels.
 constexpr int kLevelModeMaxLevels = 16;
@@ -137,6 +138,26 @@ struct lpcg_system {
     // (no strictly-lower entries) and every other row is level 1 (0: not so).
     // Multicolour orderings of bipartite graphs (red-black grids) have it.
     int two_level_p = 0;
+    // ELL forms (one row per lane; slot t of row i at t * rows + i, so a
+    // wave's loads of one slot are contiguous; padding: value 0 at a valid
+    // column) for patterns whose rows have at most kEllMaxW entries.  The
+    // two-level pair: suffix rows [p, n) of L without the diagonal (e2_ws
+    // slots, columns in the prefix) and prefix rows [0, p) of U = L^T without
+    // the diagonal (e2_wp slots, columns in the suffix); *_pos = source
+    // position in l_val / ut_val (-1: padding), *_dpos = the diagonal's.  The
+    // values of one factor are packed per solve.  e2_ws = 0: not built.
+    int e2_ws = 0, e2_wp = 0;
+    int *e2_scol = nullptr, *e2_spos = nullptr, *e2_sdpos = nullptr;
+    int *e2_pcol = nullptr, *e2_ppos = nullptr, *e2_pdpos = nullptr;
+    float *e2_sval = nullptr, *e2_sdiag = nullptr, *e2_pval = nullptr, *e2_pdiag = nullptr;
+    // A in ELL form (ea_w slots per row, the diagonal included; padding
+    // column = the row itself), FP32 values packed with every value update.
+    // ea_w = 0: not built.  spmv_ell: the PCG's product and the FP32 SpMV use
+    // it (an autotuner candidate beside the gather and staged forms).
+    int ea_w = 0;
+    int *ea_col = nullptr, *ea_pos = nullptr;
+    float *ea_val = nullptr;
+    bool spmv_ell = false;
     // Row-aligned edge tiles of the network's fused inference pass: tile j
     // holds the whole rows gtile_row[j] .. gtile_row[j+1]-1, at most 32 stored
     // entries in all (0 tiles: some row has more than 32 entries).
@@ -195,4 +216,9 @@ int blk_prepare(lpcg_system *s, int d, int B, int K = 1);
 int blk_pack(const lpcg_system *s, int d, const float *lval, const float *utval, hipStream_t st);
 void blk_free(lpcg_system *s, int d);
 void drop_graphs(lpcg_system *s);
+// Pack A's FP32 values into the ELL form (no-op when not built).
+int ell_pack_a(const lpcg_system *s, hipStream_t st);
+// Median duration (us) of the PCG's product kernel for an SpMV candidate
+// (pcg.hip; overwrites the solver's work vectors and control words).
+int time_pcg_product(lpcg_system *s, int G, int blocks, int R, int reps, double &us, hipStream_t st);
 }  // namespace lpcg

@@ -35,6 +35,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <vector>
 
 #include "device_util.h"
 #include "kern_spmv.h"
@@ -83,6 +84,32 @@ __device__ __forceinline__ bool is_done(const Args &a) {
     if (threadIdx.x == 0) flag = a.ctrl[C_DONE];
     __syncthreads();
     return flag != 0;
+}
+
+// The same flag read by every wave, with no block barrier, so that a kernel
+// can issue it together with its first data loads (which are in bounds and
+// harmless when the flag is set).  Every wave of a launch reads the same
+// value: the flag is raised only by an earlier launch or by a reducer block
+// after every other block has published its partial (each block reads the
+// flag before it publishes) and after the reducer's own block barriers.
+// readfirstlane keeps the branch on it scalar.
+__device__ __forceinline__ bool done_now(int flag) { return __builtin_amdgcn_readfirstlane(flag) != 0; }
+
+// Control words and FP64 scalars read at a kernel's start through the vector
+// memory path: a scalar load would share its wait counter with the kernel's
+// argument loads, so the first data loads (which need the arguments) would
+// wait for it too.
+__device__ __forceinline__ int ld_ctrl(const int *p) { return ld_agent_i(p); }
+
+// Marks a loaded word as a per-lane value.  The compiler otherwise reads a
+// load from a uniform address into a scalar register at once, which waits for
+// that load before the kernel's other loads are issued; called after those.
+__device__ __forceinline__ int lane_value(int v) {
+    asm volatile("" : "+v"(v));
+    return v;
+}
+__device__ __forceinline__ double ld_scal(const double *p) {
+    return __longlong_as_double((long long)ld_agent_u64(reinterpret_cast<const uint64_t *>(p)));
 }
 
 // The block of highest index reduces: after publishing its own partial it
@@ -301,25 +328,58 @@ __global__ void __launch_bounds__(256) k_llt_bwd_level(Args a, int lev0, int row
 template <int G>
 __global__ void __launch_bounds__(256) k_llt2_suffix(Args a, int p) {
     __shared__ double lds[VT / kWave];
-    if (is_done(a)) return;
+    const int n = a.n;
     const int sub = threadIdx.x % G;
     constexpr int per = 256 / G;
-    float *z = (float *)a.z;
+    const int *__restrict__ lrp = a.lrp;
+    const int *__restrict__ lci = a.lci;
+    const float *__restrict__ lv = a.lval;
+    const float *__restrict__ rv = a.r;
+    float *__restrict__ z = (float *)a.z;
+    // memory round trips per row: the done flag with the row's bounds and
+    // r_i; its entries and L_ii; the gathers (two entries per lane at once)
+    int row = p + blockIdx.x * per + threadIdx.x / G;
+    int k0 = 0, k1 = 0;
+    float ri = 0.f;
+    const int flag = ld_ctrl(a.ctrl + C_DONE);
+    if (row < n) {
+        k0 = lrp[row];
+        k1 = lrp[row + 1] - 1;
+        ri = rv[row];
+    }
+    if (done_now(flag)) return;
     double rz = 0;
-    for (int row = p + blockIdx.x * per + threadIdx.x / G; row < a.n; row += gridDim.x * per) {
-        const int k0 = a.lrp[row], k1 = a.lrp[row + 1] - 1;
+    while (row < n) {
+        const float d = lv[k1];
         float acc = 0.f;
-        for (int k = k0 + sub; k < k1; k += G) {
-            const int j = a.lci[k];
-            acc += a.lval[k] * (a.r[j] / a.lval[j]);
+        for (int k = k0 + sub; k < k1; k += 2 * G) {
+            const bool h2 = k + G < k1;
+            const int j1 = lci[k];
+            const float l1 = lv[k];
+            int j2 = 0;
+            float l2 = 0.f;
+            if (h2) {
+                j2 = lci[k + G];
+                l2 = lv[k + G];
+            }
+            const float g1 = rv[j1] / lv[j1];
+            float g2 = 0.f;
+            if (h2) g2 = rv[j2] / lv[j2];
+            acc += l1 * g1;
+            if (h2) acc += l2 * g2;
         }
 #pragma unroll
         for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, G);
         if (sub == 0) {
-            const float d = a.lval[k1], ri = a.r[row];
             const float zv = ((ri - acc) / d) / d;
             z[row] = zv;
             rz += (double)ri * (double)zv;
+        }
+        row += gridDim.x * per;
+        if (row < n) {
+            k0 = lrp[row];
+            k1 = lrp[row + 1] - 1;
+            ri = rv[row];
         }
     }
     rz = block_sum<VT>(rz, lds);
@@ -329,27 +389,178 @@ __global__ void __launch_bounds__(256) k_llt2_suffix(Args a, int p) {
 template <int G>
 __global__ void __launch_bounds__(256) k_llt2_prefix(Args a, int p, int part0) {
     __shared__ double lds[VT / kWave];
-    if (is_done(a)) return;
     const int sub = threadIdx.x % G;
     constexpr int per = 256 / G;
+    const int *__restrict__ urp = a.urp;
+    const int *__restrict__ uci = a.uci;
+    const float *__restrict__ uv = a.utval;
+    const float *__restrict__ rv = a.r;
     float *z = (float *)a.z;
+    // round trips as in k_llt2_suffix (the z gathered here is the suffix
+    // rows', which this kernel does not write)
+    int row = blockIdx.x * per + threadIdx.x / G;
+    int k0 = 0, k1 = 0;
+    float ri = 0.f;
+    const int flag = ld_ctrl(a.ctrl + C_DONE);
+    if (row < p) {
+        k0 = urp[row];
+        k1 = urp[row + 1];
+        ri = rv[row];
+    }
+    if (done_now(flag)) return;
     double rz = 0;
-    for (int row = blockIdx.x * per + threadIdx.x / G; row < p; row += gridDim.x * per) {
-        const int k0 = a.urp[row], k1 = a.urp[row + 1];
+    while (row < p) {
+        const float d = uv[k0];
         float acc = 0.f;
-        for (int k = k0 + 1 + sub; k < k1; k += G) acc += a.utval[k] * z[a.uci[k]];
+        for (int k = k0 + 1 + sub; k < k1; k += 2 * G) {
+            const bool h2 = k + G < k1;
+            const int j1 = uci[k];
+            const float u1 = uv[k];
+            int j2 = 0;
+            float u2 = 0.f;
+            if (h2) {
+                j2 = uci[k + G];
+                u2 = uv[k + G];
+            }
+            const float g1 = z[j1];
+            float g2 = 0.f;
+            if (h2) g2 = z[j2];
+            acc += u1 * g1;
+            if (h2) acc += u2 * g2;
+        }
 #pragma unroll
         for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, G);
         if (sub == 0) {
-            const float d = a.utval[k0], ri = a.r[row];
             const float zv = (ri / d - acc) / d;
             z[row] = zv;
             rz += (double)ri * (double)zv;
+        }
+        row += gridDim.x * per;
+        if (row < p) {
+            k0 = urp[row];
+            k1 = urp[row + 1];
+            ri = rv[row];
         }
     }
     rz = block_sum<VT>(rz, lds);
     if (threadIdx.x == 0) publish_partial(a.sp_rz, part0 + blockIdx.x, rz);
     if (is_reducer()) finish_rz(a, lds);
+}
+
+// ELL form of the two-level pair (slots built with the pattern, this
+// factor's values packed per solve by k_e2_pack): one row per lane, so a
+// row's loads take two memory round trips (its slots, diagonal and r with
+// the done flag; then the gathers) instead of three (bounds, entries,
+// gathers).  A row's entries are summed in its CSR order.  WM: the slot
+// count rounded up (4 or 8); w <= WM slots are used.
+struct E2 {
+    int p, ws, wp;
+    const int *scol, *pcol;
+    const float *sval, *sdiag, *pval, *pdiag;
+};
+
+template <int WM>
+__global__ void __launch_bounds__(VT) k_llt2e_suffix(Args a, E2 e) {
+    __shared__ double lds[VT / kWave];
+    const int p = e.p, nb = a.n - p, w = e.ws;
+    const int i = blockIdx.x * VT + threadIdx.x;  // suffix row p + i
+    const float *__restrict__ rv = a.r;
+    const float *__restrict__ lv = a.lval;
+    int col[WM];
+    float val[WM];
+    float d = 1.f, ri = 0.f;
+    const int flag = ld_ctrl(a.ctrl + C_DONE);
+    if (i < nb) {
+#pragma unroll
+        for (int t = 0; t < WM; ++t)
+            if (t < w) {
+                col[t] = e.scol[(size_t)t * nb + i];
+                val[t] = e.sval[(size_t)t * nb + i];
+            }
+        d = e.sdiag[i];
+        ri = rv[p + i];
+    }
+    if (done_now(flag)) return;
+    double rz = 0;
+    if (i < nb) {
+        float g[WM];
+#pragma unroll
+        for (int t = 0; t < WM; ++t)
+            if (t < w) g[t] = rv[col[t]] / lv[col[t]];  // y_j = r_j / L_jj of prefix row j
+        float acc = 0.f;
+#pragma unroll
+        for (int t = 0; t < WM; ++t)
+            if (t < w) acc += val[t] * g[t];
+        const float zv = ((ri - acc) / d) / d;
+        ((float *)a.z)[p + i] = zv;
+        rz = (double)ri * (double)zv;
+    }
+    rz = block_sum<VT>(rz, lds);
+    if (threadIdx.x == 0) publish_partial(a.sp_rz, blockIdx.x, rz);
+}
+
+template <int WM>
+__global__ void __launch_bounds__(VT) k_llt2e_prefix(Args a, E2 e, int part0) {
+    __shared__ double lds[VT / kWave];
+    const int p = e.p, w = e.wp;
+    const int j = blockIdx.x * VT + threadIdx.x;  // prefix row j
+    float *z = (float *)a.z;  // reads the suffix rows' z, writes the prefix rows'
+    int col[WM];
+    float val[WM];
+    float d = 1.f, rj = 0.f;
+    const int flag = ld_ctrl(a.ctrl + C_DONE);
+    if (j < p) {
+#pragma unroll
+        for (int t = 0; t < WM; ++t)
+            if (t < w) {
+                col[t] = e.pcol[(size_t)t * p + j];
+                val[t] = e.pval[(size_t)t * p + j];
+            }
+        d = e.pdiag[j];
+        rj = a.r[j];
+    }
+    if (done_now(flag)) return;
+    double rz = 0;
+    if (j < p) {
+        float g[WM];
+#pragma unroll
+        for (int t = 0; t < WM; ++t)
+            if (t < w) g[t] = z[col[t]];
+        float acc = 0.f;
+#pragma unroll
+        for (int t = 0; t < WM; ++t)
+            if (t < w) acc += val[t] * g[t];
+        const float zv = (rj / d - acc) / d;
+        z[j] = zv;
+        rz = (double)rj * (double)zv;
+    }
+    rz = block_sum<VT>(rz, lds);
+    if (threadIdx.x == 0) publish_partial(a.sp_rz, part0 + blockIdx.x, rz);
+    if (is_reducer()) finish_rz(a, lds);
+}
+
+// One factor's values into the pair's ELL slots (padding: 0) and diagonals.
+__global__ void k_e2_pack(int n, int p, int ws, int wp, const int *__restrict__ spos,
+                          const int *__restrict__ sdpos, const int *__restrict__ ppos,
+                          const int *__restrict__ pdpos, const float *__restrict__ lval,
+                          const float *__restrict__ utval, float *__restrict__ sval, float *__restrict__ sdiag,
+                          float *__restrict__ pval, float *__restrict__ pdiag) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nb = n - p;
+    if (i < nb) {
+        for (int t = 0; t < ws; ++t) {
+            const int k = spos[(size_t)t * nb + i];
+            sval[(size_t)t * nb + i] = k >= 0 ? lval[k] : 0.f;
+        }
+        sdiag[i] = lval[sdpos[i]];
+    }
+    if (i < p) {
+        for (int t = 0; t < wp; ++t) {
+            const int k = ppos[(size_t)t * p + i];
+            pval[(size_t)t * p + i] = k >= 0 ? utval[k] : 0.f;
+        }
+        pdiag[i] = utval[pdpos[i]];
+    }
 }
 
 // Single-workgroup substitutions (one block walking all levels): forward,
@@ -377,17 +588,18 @@ __global__ void __launch_bounds__(kWgThreads) k_llt_wg(Args a, int do_fwd, int d
 
 // p = z + beta p_prev, w = A p and p.w partials; the reducer block computes
 // alpha (breakdown when p.w <= 0 or non-finite) and counts the product.
+// Each thread takes two rows at a time (row and row + one grid's rows) and
+// up to two entries of each per lane at once, so that its loads take three
+// memory round trips per pair: the done flag, the iteration state, both
+// rows' bounds and diagonal z; their entries and diagonal p_prev; the
+// gathers.  Per lane the entries are summed in the order k0 + sub,
+// k0 + sub + G, ..., as in k_spmv_pw_st.
 template <int G, int KIND>
 __global__ void __launch_bounds__(VT) k_spmv_pw(Args a) {
     __shared__ double lds[VT / kWave];
-    if (is_done(a)) return;
-    const int it = a.ctrl[C_IT];
-    const bool first = it == 0;
-    const float beta = (float)a.scal[S_BETA];
-    float *pn = (it & 1) ? a.p1 : a.p0;
-    const float *pp = (it & 1) ? a.p0 : a.p1;
+    const int n = a.n;
     const int sub = threadIdx.x % G;
-    const int rows_per_pass = gridDim.x * (VT / G);
+    const int rpp = gridDim.x * (VT / G);  // rows per grid pass
     // the arrays this kernel reads never alias the ones it writes (p_new, w):
     // restrict-qualified copies let the compiler keep the gathers in flight
     // across the stores
@@ -395,25 +607,162 @@ __global__ void __launch_bounds__(VT) k_spmv_pw(Args a) {
     const int *__restrict__ ci = a.ci;
     const float *__restrict__ v = a.v32;
     const float *__restrict__ zs = KIND == LPCG_PC_NONE ? a.r : (const float *)a.z;
-    const float *__restrict__ pq = pp;
-    float *__restrict__ pnw = pn;
     float *__restrict__ w = a.w;
+    int ra = blockIdx.x * (VT / G) + threadIdx.x / G;
+    int a0 = 0, a1 = 0, b0 = 0, b1 = 0;
+    float za = 0.f, zb = 0.f;
+    const int flag = ld_ctrl(a.ctrl + C_DONE);
+    int it = ld_ctrl(a.ctrl + C_IT);
+    const float beta = (float)ld_scal(a.scal + S_BETA);
+    if (ra < n) {
+        a0 = rp[ra];
+        a1 = rp[ra + 1];
+        za = zs[ra];
+    }
+    if (ra + rpp < n) {
+        b0 = rp[ra + rpp];
+        b1 = rp[ra + rpp + 1];
+        zb = zs[ra + rpp];
+    }
+    if (done_now(flag)) return;
+    it = lane_value(it);
+    const bool first = it == 0;
+    const float *__restrict__ pq = (it & 1) ? a.p0 : a.p1;
+    float *__restrict__ pnw = (it & 1) ? a.p1 : a.p0;
     double pw = 0;
-    for (int row = blockIdx.x * (VT / G) + threadIdx.x / G; row < a.n; row += rows_per_pass) {
-        float acc = 0.f;
-        for (int k = rp[row] + sub; k < rp[row + 1]; k += G) {
-            const int j = ci[k];
-            const float zj = zs[j];
-            acc += v[k] * (first ? zj : __fmaf_rn(beta, pq[j], zj));
+    while (ra < n) {
+        const int rb = ra + rpp;
+        const bool hb = rb < n;
+        const float pa = first ? za : __fmaf_rn(beta, pq[ra], za);
+        const float pb = !hb ? 0.f : first ? zb : __fmaf_rn(beta, pq[rb], zb);
+        const int la = a1 - a0, lb = b1 - b0;  // lb = 0 without a second row
+        float acca = 0.f, accb = 0.f;
+        for (int t = sub; t < max(la, lb); t += 2 * G) {
+            const bool ia1 = t < la, ia2 = t + G < la, ib1 = t < lb, ib2 = t + G < lb;
+            int ja1 = 0, ja2 = 0, jb1 = 0, jb2 = 0;
+            float va1 = 0.f, va2 = 0.f, vb1 = 0.f, vb2 = 0.f;
+            if (ia1) { ja1 = ci[a0 + t]; va1 = v[a0 + t]; }
+            if (ia2) { ja2 = ci[a0 + t + G]; va2 = v[a0 + t + G]; }
+            if (ib1) { jb1 = ci[b0 + t]; vb1 = v[b0 + t]; }
+            if (ib2) { jb2 = ci[b0 + t + G]; vb2 = v[b0 + t + G]; }
+            float ga1 = 0.f, ga2 = 0.f, gb1 = 0.f, gb2 = 0.f;
+            if (ia1) ga1 = first ? zs[ja1] : __fmaf_rn(beta, pq[ja1], zs[ja1]);
+            if (ia2) ga2 = first ? zs[ja2] : __fmaf_rn(beta, pq[ja2], zs[ja2]);
+            if (ib1) gb1 = first ? zs[jb1] : __fmaf_rn(beta, pq[jb1], zs[jb1]);
+            if (ib2) gb2 = first ? zs[jb2] : __fmaf_rn(beta, pq[jb2], zs[jb2]);
+            if (ia1) acca += va1 * ga1;
+            if (ia2) acca += va2 * ga2;
+            if (ib1) accb += vb1 * gb1;
+            if (ib2) accb += vb2 * gb2;
         }
 #pragma unroll
-        for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, G);
+        for (int off = G / 2; off > 0; off >>= 1) {
+            acca += __shfl_xor(acca, off, G);
+            accb += __shfl_xor(accb, off, G);
+        }
         if (sub == 0) {
-            const float zi = zs[row];
-            const float pi = first ? zi : __fmaf_rn(beta, pq[row], zi);
-            pnw[row] = pi;
-            w[row] = acc;
-            pw += (double)pi * (double)acc;
+            pnw[ra] = pa;
+            w[ra] = acca;
+            pw += (double)pa * (double)acca;
+            if (hb) {
+                pnw[rb] = pb;
+                w[rb] = accb;
+                pw += (double)pb * (double)accb;
+            }
+        }
+        ra += 2 * rpp;
+        if (ra < n) {
+            a0 = rp[ra];
+            a1 = rp[ra + 1];
+            za = zs[ra];
+        }
+        if (ra + rpp < n) {
+            b0 = rp[ra + rpp];
+            b1 = rp[ra + rpp + 1];
+            zb = zs[ra + rpp];
+        }
+    }
+    pw = block_sum<VT>(pw, lds);
+    if (threadIdx.x == 0) publish_partial(a.sp_pw, blockIdx.x, pw);
+    if (!is_reducer()) return;
+    const double pwt = reduce_published<VT>(a.sp_pw, gridDim.x, lds);
+    if (threadIdx.x == 0) {
+        const double rz = a.scal[S_RZ0];
+        a.ctrl[C_IT] = it + 1;
+        if (!(pwt > 0.0) || !isfinite(pwt) || !isfinite(rz)) {
+            a.ctrl[C_DONE] = 1;
+            a.ctrl[C_STATUS] = LPCG_EBREAKDOWN;
+            a.ctrl[C_ITERS] = it + 1;
+        } else {
+            a.scal[S_ALPHA] = rz / pwt;
+            if (a.coef && it + 1 <= a.maxit) a.coef[2 * (it + 1)] = rz / pwt;
+        }
+    }
+}
+
+// ELL form of k_spmv_pw (A's slots and FP32 values, analysis-built): one
+// row per lane; the first row's loads take two memory round trips (its slots
+// and z with the done flag and the iteration state; then the gathers and its
+// p_prev).  A row's entries are summed in its CSR order (padding slots add
+// 0 * p_i).
+struct EA {
+    int w;
+    const int *col;
+    const float *val;
+};
+
+template <int WM, int KIND>
+__global__ void __launch_bounds__(VT) k_spmv_pw_e(Args a, EA e) {
+    __shared__ double lds[VT / kWave];
+    const int n = a.n, w = e.w;
+    const float *__restrict__ zs = KIND == LPCG_PC_NONE ? a.r : (const float *)a.z;
+    const int *__restrict__ ec = e.col;
+    const float *__restrict__ ev = e.val;
+    float *__restrict__ wv = a.w;
+    int row = blockIdx.x * VT + threadIdx.x;
+    int col[WM];
+    float val[WM];
+    float zr = 0.f;
+    const int flag = ld_ctrl(a.ctrl + C_DONE);
+    int it = ld_ctrl(a.ctrl + C_IT);
+    const float beta = (float)ld_scal(a.scal + S_BETA);
+    if (row < n) {
+#pragma unroll
+        for (int t = 0; t < WM; ++t)
+            if (t < w) {
+                col[t] = ec[(size_t)t * n + row];
+                val[t] = ev[(size_t)t * n + row];
+            }
+        zr = zs[row];
+    }
+    if (done_now(flag)) return;
+    it = lane_value(it);
+    const bool first = it == 0;
+    const float *__restrict__ pq = (it & 1) ? a.p0 : a.p1;
+    float *__restrict__ pnw = (it & 1) ? a.p1 : a.p0;
+    double pw = 0;
+    while (row < n) {
+        float g[WM];
+#pragma unroll
+        for (int t = 0; t < WM; ++t)
+            if (t < w) g[t] = first ? zs[col[t]] : __fmaf_rn(beta, pq[col[t]], zs[col[t]]);
+        const float pr = first ? zr : __fmaf_rn(beta, pq[row], zr);
+        float acc = 0.f;
+#pragma unroll
+        for (int t = 0; t < WM; ++t)
+            if (t < w) acc += val[t] * g[t];
+        pnw[row] = pr;
+        wv[row] = acc;
+        pw += (double)pr * (double)acc;
+        row += gridDim.x * VT;
+        if (row < n) {
+#pragma unroll
+            for (int t = 0; t < WM; ++t)
+                if (t < w) {
+                    col[t] = ec[(size_t)t * n + row];
+                    val[t] = ev[(size_t)t * n + row];
+                }
+            zr = zs[row];
         }
     }
     pw = block_sum<VT>(pw, lds);
@@ -504,32 +853,60 @@ __global__ void __launch_bounds__(VT) k_spmv_pw_st(Args a, int R, const int *__r
 template <int KIND>
 __global__ void __launch_bounds__(VT) k_xr(Args a) {
     __shared__ double lds[VT / kWave];
-    if (is_done(a)) return;
-    const int it = a.ctrl[C_IT];
-    const float *p = ((it - 1) & 1) ? a.p1 : a.p0;
-    const double alpha = a.scal[S_ALPHA];
-    const float af = (float)alpha;
+    const int n = a.n;
     // element-wise: each index is read and written by one thread only
-    const float *__restrict__ pr = p;
     const float *__restrict__ wr = a.w;
     const float *__restrict__ dv = a.dinv;
     double *__restrict__ xr = a.x;
     float *__restrict__ rv = a.r;
     uint32_t *__restrict__ zb = a.z;
+    // the first element's w, r, x (and 1/diag) are loaded with the done flag
+    // and the iteration state, and so is p from both buffers (which one holds
+    // the current direction depends on the iteration): one memory round trip
+    int i = blockIdx.x * VT + threadIdx.x;
+    float wi = 0.f, ri0 = 0.f, di = 0.f, pa = 0.f, pb = 0.f;
+    double xi = 0.0;
+    const int flag = ld_ctrl(a.ctrl + C_DONE);
+    int it = ld_ctrl(a.ctrl + C_IT);
+    const double alpha = ld_scal(a.scal + S_ALPHA);
+    const float *__restrict__ p0 = a.p0;
+    const float *__restrict__ p1 = a.p1;
+    if (i < n) {
+        wi = wr[i];
+        ri0 = rv[i];
+        xi = xr[i];
+        pa = p0[i];
+        pb = p1[i];
+        if (KIND == LPCG_PC_JACOBI) di = dv[i];
+    }
+    if (done_now(flag)) return;
+    it = lane_value(it);
+    const float af = (float)alpha;
+    const bool odd = ((it - 1) & 1) != 0;
+    const float *__restrict__ pr = odd ? p1 : p0;
+    float pi = odd ? pb : pa;
     double rr = 0, rzn = 0;
-    for (int i = blockIdx.x * VT + threadIdx.x; i < a.n; i += gridDim.x * VT) {
-        xr[i] += alpha * (double)pr[i];
-        const float ri = rv[i] - af * wr[i];
+    while (i < n) {
+        xr[i] = xi + alpha * (double)pi;
+        const float ri = ri0 - af * wi;
         rv[i] = ri;
         rr += (double)ri * ri;
         if (KIND == LPCG_PC_JACOBI) {
-            rzn += (double)ri * ri * dv[i];
-            zb[i] = __float_as_uint(dv[i] * ri);
+            rzn += (double)ri * ri * di;
+            zb[i] = __float_as_uint(di * ri);
         }
         if (KIND == LPCG_PC_NONE) rzn += (double)ri * ri;
         if (KIND == LPCG_PC_LLT) {
             if (a.reset_y) a.y[i] = kUnset;
             if (a.reset_z) zb[i] = kUnset;
+        }
+        i += gridDim.x * VT;
+        if (i < n) {
+            wi = wr[i];
+            ri0 = rv[i];
+            xi = xr[i];
+            pi = pr[i];
+            if (KIND == LPCG_PC_JACOBI) di = dv[i];
         }
     }
     rr = block_sum<VT>(rr, lds);
@@ -593,12 +970,36 @@ bool two_level_path(const lpcg_system *s) {
     return s->two_level_p > 0 && s->two_level_p < s->n && s->trsv[0].mode == 1 && s->trsv[1].mode == 1;
 }
 
+// The pair runs in its ELL form whenever the analysis built it (rows of at
+// most kEllMaxW entries).
+bool e2_path(const lpcg_system *s) { return two_level_path(s) && s->e2_ws > 0; }
+
+E2 e2_args(const lpcg_system *s) {
+    return E2{s->two_level_p, s->e2_ws, s->e2_wp, s->e2_scol, s->e2_pcol,
+              s->e2_sval, s->e2_sdiag, s->e2_pval, s->e2_pdiag};
+}
+
+EA ea_args(const lpcg_system *s) { return EA{s->ea_w, s->ea_col, s->ea_val}; }
+
+int ell_blocks(const lpcg_system *s) { return std::max(1, std::min(kMaxSpmvBlocks, (s->n + VT - 1) / VT)); }
+
 // One iteration = the application z = P^-1 r (LLT only), the SpMV with the
 // new search direction and p.w, and the x, r update; enqueued in parts so
 // that the timing aid can bracket each.
 template <int KIND>
 int enqueue_apply(const lpcg_system *s, const Args &a, hipStream_t st) {
-    if (KIND == LPCG_PC_LLT && two_level_path(s)) {
+    if (KIND == LPCG_PC_LLT && e2_path(s)) {
+        const int p = s->two_level_p;
+        const int nbs = (s->n - p + VT - 1) / VT, nbp = (p + VT - 1) / VT;
+        const E2 e = e2_args(s);
+        if (s->e2_ws <= 4 && s->e2_wp <= 4) {
+            k_llt2e_suffix<4><<<nbs, VT, 0, st>>>(a, e);
+            k_llt2e_prefix<4><<<nbp, VT, 0, st>>>(a, e, nbs);
+        } else {
+            k_llt2e_suffix<8><<<nbs, VT, 0, st>>>(a, e);
+            k_llt2e_prefix<8><<<nbp, VT, 0, st>>>(a, e, nbs);
+        }
+    } else if (KIND == LPCG_PC_LLT && two_level_path(s)) {
         const int G = s->trsv_g, p = s->two_level_p;
         const int nbs = level_blocks(s->n - p, G), nbp = level_blocks(p, G);
         if (G == 4) {
@@ -662,6 +1063,13 @@ int enqueue_apply(const lpcg_system *s, const Args &a, hipStream_t st) {
 
 template <int KIND>
 int enqueue_spmv(const lpcg_system *s, const Args &a, hipStream_t st) {
+    if (s->spmv_ell && s->ea_w > 0) {
+        const int eb = ell_blocks(s);
+        if (s->ea_w <= 4) k_spmv_pw_e<4, KIND><<<eb, VT, 0, st>>>(a, ea_args(s));
+        else k_spmv_pw_e<8, KIND><<<eb, VT, 0, st>>>(a, ea_args(s));
+        LPCG_LAUNCH_CHECK();
+        return LPCG_OK;
+    }
     if (s->spmv_rows > 0) {  // LDS-staged (windows prepared when the configuration was set)
         const int R = s->spmv_rows, nb = (s->n + R - 1) / R;
         const size_t lds = sizeof(float) * (size_t)std::max(1, s->spmv_wmax);
@@ -726,7 +1134,7 @@ int run_solve(lpcg_system *s, const Args &a, const lpcg_solve_opts &o, int &iter
             exec = s->graph_exec;
         } else {
             if (s->graph_exec) {
-                hipGraphExecDestroy(s->graph_exec);
+                (void)hipGraphExecDestroy(s->graph_exec);
                 s->graph_exec = nullptr;
             }
             if (!s->cap_stream) LPCG_HIP(hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));
@@ -736,12 +1144,12 @@ int run_solve(lpcg_system *s, const Args &a, const lpcg_solve_opts &o, int &iter
             for (int c = 0; c < chunk && rc == LPCG_OK; ++c) rc = enqueue_iteration<KIND>(s, a, s->cap_stream);
             hipError_t e = hipStreamEndCapture(s->cap_stream, &graph);
             if (rc != LPCG_OK) {
-                if (graph) hipGraphDestroy(graph);
+                if (graph) (void)hipGraphDestroy(graph);
                 return rc;
             }
             LPCG_HIP(e);
             hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-            hipGraphDestroy(graph);
+            (void)hipGraphDestroy(graph);
             LPCG_HIP(ie);
             s->graph_exec = exec;
             s->graph_key = key;
@@ -791,7 +1199,9 @@ int build_args(lpcg_system *s, const lpcg_precond *P, const double *b, double *x
     a.stride_b = s->trsv[1].stride;
     a.reset_y = s->trsv[0].mode == 0 || s->trsv[0].mode == 3;
     a.reset_z = s->trsv[1].mode == 0 || s->trsv[1].mode == 3;
-    if (two_level_path(s)) {
+    if (e2_path(s)) {
+        a.np_rz = (s->n - s->two_level_p + VT - 1) / VT + (s->two_level_p + VT - 1) / VT;
+    } else if (two_level_path(s)) {
         a.np_rz = level_blocks(s->n - s->two_level_p, s->trsv_g) + level_blocks(s->two_level_p, s->trsv_g);
     } else if (s->trsv[1].mode == 0) {
         a.np_rz = (s->n + kWave - 1) / kWave;
@@ -853,6 +1263,13 @@ int build_args(lpcg_system *s, const lpcg_precond *P, const double *b, double *x
     a.coef = coef;
     a.ctrl = s->ctrl;
     a.tol2 = tol * tol;
+    if (P->kind == LPCG_PC_LLT && e2_path(s)) {  // the factor's values in the pair's ELL slots
+        const int nmax = std::max(s->n - s->two_level_p, s->two_level_p);
+        k_e2_pack<<<(nmax + 255) / 256, 256, 0, st>>>(s->n, s->two_level_p, s->e2_ws, s->e2_wp, s->e2_spos,
+                                                      s->e2_sdpos, s->e2_ppos, s->e2_pdpos, P->l_val, P->ut_val,
+                                                      s->e2_sval, s->e2_sdiag, s->e2_pval, s->e2_pdiag);
+        LPCG_LAUNCH_CHECK();
+    }
     if (P->kind == LPCG_PC_LLT) {  // the factor's values in the layouts of the single-workgroup and blocked modes
         for (int d = 0; d < 2; ++d) {
             int rc = LPCG_OK;
@@ -877,7 +1294,99 @@ int build_args(lpcg_system *s, const lpcg_precond *P, const double *b, double *x
     return LPCG_OK;
 }
 
+// State of one timed product launch: not done, iteration 1 (so the kernel
+// takes p = z + beta p_prev with the gathers of both), beta = 1/2.
+__global__ void k_product_state(Args a) {
+    if (threadIdx.x == 0) {
+        a.ctrl[C_DONE] = 0;
+        a.ctrl[C_IT] = 1;
+        a.scal[S_BETA] = 0.5;
+        a.scal[S_RZ0] = 1.0;
+    }
+}
+
 }  // namespace
+
+// Median duration of the PCG's product kernel (p = z + beta p_prev, w = A p,
+// p.w; the reducer's alpha) with G lanes per row on `blocks` blocks, or
+// LDS-staged with R > 0 rows per block (windows prepared for R), or in the
+// ELL form for G = 1 (built with the pattern), over reps
+// launches after one warm-up.  Runs on the system's work vectors with
+// z = p_prev = 1 and A's FP32 values; overwrites z, both search directions,
+// w and the control words.  The autotuner ranks its SpMV candidates with it.
+int time_pcg_product(lpcg_system *s, int G, int blocks, int R, int reps, double &us, hipStream_t st) {
+    if (G == 1 && s->ea_w == 0) {
+        set_error("SpMV: no ELL form for this pattern");
+        return LPCG_EINVAL;
+    }
+    Args a{};
+    a.n = s->n;
+    a.maxit = 1 << 30;
+    a.kind = LPCG_PC_LLT;
+    a.rp = s->rowptr;
+    a.ci = s->colind;
+    a.v32 = s->val32;
+    a.z = (uint32_t *)s->z;
+    a.p0 = s->p;
+    a.p1 = s->p2;
+    a.w = s->w;
+    a.sp_pw = s->sync_part + s->npart;
+    a.scal = s->scal;
+    a.ctrl = s->ctrl;
+    const int fb = (s->n + 255) / 256;
+    k_fill_u32<<<fb, 256, 0, st>>>(s->n, a.z, 0x3f800000u);
+    k_fill_u32<<<fb, 256, 0, st>>>(s->n, (uint32_t *)s->p, 0x3f800000u);
+    k_fill_u32<<<fb, 256, 0, st>>>(s->n, (uint32_t *)s->p2, 0x3f800000u);
+    LPCG_LAUNCH_CHECK();
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    LPCG_HIP(hipEventCreate(&e0));
+    hipError_t he = hipEventCreate(&e1);
+    if (he != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        LPCG_HIP(he);
+    }
+    const size_t lds = sizeof(float) * (size_t)std::max(1, s->spmv_wmax);
+    const int nb = R > 0 ? (s->n + R - 1) / R : blocks;
+    std::vector<float> t;
+    hipError_t e = hipSuccess;
+    for (int r = 0; r <= reps && e == hipSuccess; ++r) {
+        k_product_state<<<1, 64, 0, st>>>(a);
+        e = hipEventRecord(e0, st);
+        if (e != hipSuccess) break;
+        if (G == 1) {
+            if (s->ea_w <= 4) k_spmv_pw_e<4, LPCG_PC_LLT><<<ell_blocks(s), VT, 0, st>>>(a, ea_args(s));
+            else k_spmv_pw_e<8, LPCG_PC_LLT><<<ell_blocks(s), VT, 0, st>>>(a, ea_args(s));
+        } else if (R > 0) {
+            switch (G) {
+                case 4: k_spmv_pw_st<4, LPCG_PC_LLT><<<nb, VT, lds, st>>>(a, R, s->spmv_win); break;
+                case 8: k_spmv_pw_st<8, LPCG_PC_LLT><<<nb, VT, lds, st>>>(a, R, s->spmv_win); break;
+                case 16: k_spmv_pw_st<16, LPCG_PC_LLT><<<nb, VT, lds, st>>>(a, R, s->spmv_win); break;
+                case 32: k_spmv_pw_st<32, LPCG_PC_LLT><<<nb, VT, lds, st>>>(a, R, s->spmv_win); break;
+                default: k_spmv_pw_st<64, LPCG_PC_LLT><<<nb, VT, lds, st>>>(a, R, s->spmv_win); break;
+            }
+        } else {
+            switch (G) {
+                case 4: k_spmv_pw<4, LPCG_PC_LLT><<<nb, VT, 0, st>>>(a); break;
+                case 8: k_spmv_pw<8, LPCG_PC_LLT><<<nb, VT, 0, st>>>(a); break;
+                case 16: k_spmv_pw<16, LPCG_PC_LLT><<<nb, VT, 0, st>>>(a); break;
+                case 32: k_spmv_pw<32, LPCG_PC_LLT><<<nb, VT, 0, st>>>(a); break;
+                default: k_spmv_pw<64, LPCG_PC_LLT><<<nb, VT, 0, st>>>(a); break;
+            }
+        }
+        if ((e = hipGetLastError()) != hipSuccess) break;
+        if ((e = hipEventRecord(e1, st)) != hipSuccess || (e = hipEventSynchronize(e1)) != hipSuccess) break;
+        float ms = 0;
+        if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
+        if (r > 0) t.push_back(ms);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    LPCG_HIP(e);
+    std::sort(t.begin(), t.end());
+    us = 1e3 * (double)t[t.size() / 2];
+    return LPCG_OK;
+}
+
 }  // namespace lpcg
 
 using namespace lpcg;
@@ -956,7 +1465,7 @@ struct EvPair {
     hipEvent_t e[4] = {nullptr, nullptr, nullptr, nullptr};
     ~EvPair() {
         for (hipEvent_t &x : e)
-            if (x) hipEventDestroy(x);
+            if (x) (void)hipEventDestroy(x);
     }
 };
 

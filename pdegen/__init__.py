@@ -15,14 +15,14 @@ diagonal always stored, float64 values.
 """
 from .csr import CSR, canonical_csr, csr_from_dense, block_diag_csr, permute_csr
 from .grf import grf
-from .systems import (tridiag_1d, poisson_grid, heat_step_3d, heat_system_3d, fem_p1_delaunay,
+from .systems import (tridiag_1d, poisson_grid, bipartite_grid, heat_step_3d, heat_system_3d, fem_p1_delaunay,
                       random_spd, random_lower_dag, mixed_batch, mixed_batch_member, mixed_batch_sizes,
                       mixed_batch_parallel)
 from .weights import gnn_param_shapes, init_gnn_params
 
 __all__ = [
     "CSR", "canonical_csr", "csr_from_dense", "block_diag_csr", "permute_csr",
-    "grf", "tridiag_1d", "poisson_grid", "heat_step_3d", "heat_system_3d", "fem_p1_delaunay",
+    "grf", "tridiag_1d", "poisson_grid", "bipartite_grid", "heat_step_3d", "heat_system_3d", "fem_p1_delaunay",
     "random_spd", "random_lower_dag", "mixed_batch", "mixed_batch_member", "mixed_batch_sizes",
     "mixed_batch_parallel", "gnn_param_shapes", "init_gnn_params",
 ]

@@ -8,6 +8,8 @@
                     K the 7-point finite-volume operator of -div(k grad u) with
                     nodal k, harmonic-mean face coefficients and homogeneous
                     Dirichlet walls whose face coefficient is the nodal k.
+* bipartite_grid  : a 2D grid stencil with odd-sum offsets only (bipartite,
+                    rows of up to 13 entries), diagonally dominant.
 * fem_p1_delaunay : P1 Galerkin stiffness of -div(k grad u) = f on a Delaunay
                     mesh of a jittered point grid in the unit square, k
                     constant per triangle, boundary nodes eliminated
@@ -50,6 +52,28 @@ def poisson_grid(m: int, d: int) -> CSR:
     coo = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
                         shape=(n, n))
     return canonical_csr(coo)
+
+
+def bipartite_grid(m: int) -> CSR:
+    """2D m x m grid whose stencil couples each node to the nodes at offsets
+    (+-1, 0), (0, +-1), (+-1, +-2) and (+-2, +-1): every offset has an odd
+    coordinate sum, so the graph is bipartite (a red-black colouring has two
+    colours) while interior rows hold 13 entries.  Off-diagonal -1, diagonal
+    1 + the row's neighbour count: a strictly diagonally dominant M-matrix."""
+    offs = [(1, 0), (-1, 0), (0, 1), (0, -1), (1, 2), (1, -2), (-1, 2), (-1, -2), (2, 1), (2, -1), (-2, 1), (-2, -1)]
+    idx = _grid_index((m, m))
+    rows, cols = [], []
+    deg = np.zeros(m * m)
+    for di, dj in offs:
+        a = idx[max(0, -di):m - max(0, di), max(0, -dj):m - max(0, dj)].ravel()
+        b = idx[max(0, di):m - max(0, -di), max(0, dj):m - max(0, -dj)].ravel()
+        rows.append(a)
+        cols.append(b)
+        np.add.at(deg, a, 1.0)
+    r = np.concatenate(rows + [np.arange(m * m)])
+    c = np.concatenate(cols + [np.arange(m * m)])
+    v = np.concatenate([np.full(sum(len(x) for x in rows), -1.0), 1.0 + deg])
+    return canonical_csr(sp.coo_matrix((v, (r, c)), shape=(m * m, m * m)))
 
 
 def heat_step_3d(m: int, dt: float, k: np.ndarray) -> CSR:

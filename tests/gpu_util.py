@@ -42,5 +42,6 @@ def matrices_small():
         "fem_40": g.fem_p1_delaunay(40, 1, 2)[0],
         "random_777": g.random_spd(777, 0.01, 3),
         "dag_60": g.random_lower_dag(60, 0.2, 4),
+        "bipartite_24": g.bipartite_grid(24),
     }
     return out

@@ -180,12 +180,14 @@ def test_color_update_values():
     assert np.all(np.abs(host(l) - lref) <= 1.0001 * U32 * np.abs(lref))
 
 
-@pytest.mark.parametrize("name", ["heat3d_13", "poisson2d_32"])
+@pytest.mark.parametrize("name", ["heat3d_13", "poisson2d_32", "bipartite_24"])
 def test_two_level_pcg_matches_per_level_launches(name):
-    """On a red-black system the PCG applies L L^T with the two-level pair
-    (k_llt2_*); forcing the backward direction to the dependency-driven mode
-    takes the per-level path.  Both reach the FP64 tolerance with the
-    oracle's iteration count, and their iterates agree to FP32 rounding."""
+    """On a red-black system the PCG applies L L^T with the two-level pair:
+    its ELL form (rows of at most 8 entries: the 7- and 5-point grids) or its
+    CSR form (the bipartite 13-entry stencil); forcing the backward direction
+    to the dependency-driven mode takes the per-level path.  Both reach the
+    FP64 tolerance with the oracle's iteration count, and their iterates
+    agree to FP32 rounding."""
     A = matrices_small()[name]
     b = np.random.default_rng(5).standard_normal(A.n)
     perm, _, Ap, pat = _ref(A)

@@ -132,7 +132,7 @@ def test_autotune_c3_full_size(ordering):
                   f"stride {t['block_stride']} rows {t['block_rows']}: {t['us']:.1f} us")
     # the SpMV: every lanes-per-row choice timed, the fastest kept
     sp = [t for t in table if t["direction"] == 2]
-    assert {t["mode"] for t in sp} == {4, 8, 16, 32, 64}
+    assert {t["mode"] for t in sp} == {1, 4, 8, 16, 32, 64}  # 1: the ELL form (7-entry rows)
     best = min(sp, key=lambda t: t["us"])
     got = lpcg.get_trsv_cfg(S, 2)
     assert got["mode"] == best["mode"] and got["waves"] == best["waves"]
@@ -197,6 +197,70 @@ def test_spmv_staged_matches_gather_bit_for_bit(case):
             if r0["status"] == 0:
                 assert O.true_relres(A, b, host(xs)) <= 1e-6
                 assert abs(r1["iters"] - r0["iters"]) <= 1, (G, R, r0["iters"], r1["iters"])
+
+
+@pytest.mark.parametrize("case", range(7))
+def test_spmv_ell_within_bound(case):
+    """The ELL SpMV (one row per lane, slots column-major, padding of value
+    0): within the per-row FP32 bound of the FP64 oracle; Jacobi-PCG with it
+    reaches the tolerance as the gather form does (iterations within
+    max(2, 5%) when neither restarts); the FP64 product keeps the gather
+    form.  A pattern with a
+    row of more than 8 entries refuses it and keeps its configuration."""
+    cases = _spmv_cases() + [(matrices_small()["bipartite_24"], 1)]
+    A, ordering = cases[case]
+    print(f"[spmv ell] case {case} n={A.n} ordering {ordering}", flush=True)
+    S = gpu_system(A, None, ordering)
+    xh = np.random.default_rng(8).standard_normal(A.n).astype(np.float32)
+    x = torch.as_tensor(xh).cuda()
+    b = np.random.default_rng(9).standard_normal(A.n)
+    lpcg.set_trsv_cfg(S, 2, 4, waves=64)
+    # an iteration budget of 4 n leaves the FP64 restarts room on the 1D
+    # Laplacian (kappa ~ 4e5), whose FP32 iteration needs about n products
+    _, r0 = lpcg.pcg_solve(S, lpcg.PC_JACOBI, cuda_f64(b), tol=1e-6, maxit=4 * A.n, max_restarts=4)
+    k = np.diff(A.rowptr)
+    if k.max() > 8:
+        with pytest.raises(lpcg.LpcgError) as e:
+            lpcg.set_trsv_cfg(S, 2, 1)
+        assert e.value.code == lpcg.EINVAL
+        assert lpcg.get_trsv_cfg(S, 2)["mode"] == 4
+        return
+    lpcg.set_trsv_cfg(S, 2, 1)
+    got = lpcg.get_trsv_cfg(S, 2)
+    assert got["mode"] == 1 and got["block_rows"] == 0 and got["waves"] == min(2048, -(-A.n // 256))
+    y = host(lpcg.spmv(S, x))
+    ref = O.spmv(A, xh.astype(np.float64))
+    bound = O.spmv(g.CSR(A.n, A.rowptr, A.colind, np.abs(A.val)), np.abs(xh.astype(np.float64)))
+    assert np.all(np.abs(y - ref) <= 2 * k * U32 * bound + 1e-30)
+    x64 = np.random.default_rng(10).standard_normal(A.n)
+    y64 = host(lpcg.spmv(S, cuda_f64(x64)))
+    b64 = O.spmv(g.CSR(A.n, A.rowptr, A.colind, np.abs(A.val)), np.abs(x64))
+    assert np.all(np.abs(y64 - O.spmv(A, x64)) <= 2 * k * 2.0 ** -53 * b64 + 1e-300)
+    xs, r1 = lpcg.pcg_solve(S, lpcg.PC_JACOBI, cuda_f64(b), tol=1e-6, maxit=4 * A.n, max_restarts=4)
+    assert r0["status"] == 0 and r1["status"] == 0, (r0, r1)
+    assert O.true_relres(A, b, host(xs)) <= 1e-6
+    if r0["restarts"] == 0 and r1["restarts"] == 0:
+        # rounding differs from the gather form's (one lane sums a row), so
+        # the iteration counts of an ill-conditioned system may part by a few
+        # percent
+        assert abs(r1["iters"] - r0["iters"]) <= max(2, 0.05 * r0["iters"]), (r0["iters"], r1["iters"])
+
+
+def test_spmv_ell_c3_full_size():
+    """64^3 in both orderings with the ELL product in force: IC(0)-PCG (the
+    red-black order also through the pair's ELL form) reaches the tolerance
+    with the gather form's iterations (within one)."""
+    A, b = g.heat_system_3d(64, 1e-3, 1000, 2000)
+    for ordering in (0, 1):
+        print(f"[spmv ell] heat3d_64 ordering {ordering}", flush=True)
+        S = gpu_system(A, None, ordering)
+        l, ut, _ = lpcg.ic0(S)
+        lpcg.set_trsv_cfg(S, 2, 4, waves=1024)
+        _, r0 = lpcg.pcg_solve(S, lpcg.PC_LLT, cuda_f64(b), l_val=l, ut_val=ut, tol=1e-6, max_restarts=2)
+        lpcg.set_trsv_cfg(S, 2, 1)
+        xs, r1 = lpcg.pcg_solve(S, lpcg.PC_LLT, cuda_f64(b), l_val=l, ut_val=ut, tol=1e-6, max_restarts=2)
+        assert r1["status"] == 0 and O.true_relres(A, b, host(xs)) <= 1e-6
+        assert abs(r1["iters"] - r0["iters"]) <= 1, (r0["iters"], r1["iters"])
 
 
 def test_spmv_staged_c3_full_size():
