@@ -72,16 +72,19 @@ def hbm_bytes_sptrsv(info):
     return 8 * nl + 4 * (n + 1) + 8 * n + 4 * n
 
 
-def hbm_bytes_pcg_parts(info, two_level):
+def hbm_bytes_pcg_parts(info, two_level, fused_xr=False):
     """Algorithmic bytes of the PCG iteration's three parts (FP32 vectors and
     values, int32 indices, FP64 x): the application z = (L L^T)^-1 r (two
     fused launches on a two-level system: L's values and indices in each
     half, r read twice, z written and read once; else the two substitutions),
     the SpMV w = A p with p = z + beta p_prev (A, z and p_prev read, p and w
     written), and the x, r update (x read and written in FP64, r read and
-    written, p and w read)."""
+    written, p and w read).  fused_xr: the two-level pair performs the update
+    (its bytes move to the application; no separate part)."""
     n, nnz, nl = info["n"], info["nnz"], info["nnz_l"]
     apply = 2 * (8 * nl + 4 * (n + 1)) + 16 * n if two_level else 2 * hbm_bytes_sptrsv(info)
+    if fused_xr:
+        return {"apply": apply + 32 * n, "spmv_p": 8 * nnz + 4 * (n + 1) + 16 * n}
     return {"apply": apply, "spmv_p": 8 * nnz + 4 * (n + 1) + 16 * n, "xr": 32 * n}
 
 
@@ -560,12 +563,14 @@ def main():
         # its three parts, launched on this stream)
         parts_us = lpcg.time_pcg_kernels(S, lpcg.PC_LLT, bd, l_val=lval, ut_val=utval, reps=50)
         two_level = info["nlev_fwd"] == 2 and cfg[0]["mode"] == 1 and cfg[1]["mode"] == 1
-        pb = hbm_bytes_pcg_parts(info, two_level)
+        fused_xr = two_level and parts_us[2] == 0.0  # the pair's ELL form takes the x, r update
+        pb = hbm_bytes_pcg_parts(info, two_level, fused_xr)
         parts = {k: dict(us=u, bytes=pb[k], gbs=pb[k] / (u * 1e-6) / 1e9)
-                 for k, u in zip(("apply", "spmv_p", "xr"), parts_us)}
+                 for k, u in zip(("apply", "spmv_p", "xr"), parts_us) if k in pb}
         kernels[ordering] = dict(
             levels=info["nlev_fwd"], trsv_cfg=cfg, spmv_cfg=lpcg.get_trsv_cfg(S, 2), pcg_parts=parts,
-            apply_form="two-level pair" if two_level else "two substitutions",
+            apply_form=("two-level pair with the x, r update" if fused_xr else "two-level pair") if two_level
+            else "two substitutions",
             sptrsv_fwd=dict(us=ms_f * 1e3, bytes=bt, gbs=bt / (ms_f * 1e-3) / 1e9),
             sptrsv_bwd=dict(us=ms_b * 1e3, bytes=bt, gbs=bt / (ms_b * 1e-3) / 1e9),
             spmv=dict(us=ms_spmv * 1e3, bytes=bs, gbs=bs / (ms_spmv * 1e-3) / 1e9))

@@ -230,8 +230,8 @@ int lpcg_time_spmv(const lpcg_system *sys, const float *x, float *y, int32_t rep
  * when the direction has at most 16 levels, mode 0 with 4096 waves and
  * backoff 1 otherwise. */
 typedef struct {
-    int32_t direction;     /* 0: forward (L y = r), 1: backward (L^T z = y); 2 (autotune
-                              table only): the SpMV, mode = lanes per row, waves = blocks */
+    int32_t direction;     /* 0: forward (L y = r), 1: backward (L^T z = y); 2: the SpMV,
+                              mode = lanes per row (1: ELL form), waves = blocks */
     int32_t mode;          /* 0 dependency driven, 1 level synchronous, 2 single workgroup,
                               3 blocked (one wave per block of block_rows rows, consecutive
                               or banded (block_runs); dependencies inside a block through
@@ -314,13 +314,18 @@ int lpcg_blocked_schedule(int32_t n, const int32_t *rowptr, const int32_t *col, 
  * tile), and dependency driven with 64 .. 4096 waves.  It keeps the fastest
  * per direction for every later call on the system (on a two-level system,
  * a red-black grid in colour order, it keeps the level mode in both
- * directions, which lets the PCG apply L L^T in two fused launches).  It then times the
- * FP32 SpMV w = A p for G = 4, 8, 16, 32, 64 lanes per row (64 / G rows per
- * wavefront) on grids of up to 512, 1024 and 2048 blocks, and the LDS-staged
- * form with 256, 512 and 1024 rows per block at G = 4 and 8 (where the
- * windows fit), and keeps the fastest for the PCG's product and lpcg_spmv;
- * those table entries have direction 2, mode = G, waves = blocks and
- * block_rows (0 for the gather form).  It writes up to table_len measured
+ * directions, which lets the PCG apply L L^T in two fused launches; where
+ * the rows of both halves hold at most 8 entries that pair runs in an ELL
+ * form that also performs the iteration's x, r update).  It then times the
+ * PCG's product kernel (p = z + beta p_prev, w = A p, p.w; median of reps)
+ * for G = 4, 8, 16, 32, 64 lanes per row (64 / G rows per wavefront) on
+ * grids of up to 512, 1024 and 2048 blocks, the LDS-staged form with 256,
+ * 512 and 1024 rows per block at G = 4 and 8 (where the windows fit), and
+ * the ELL form (G = 1: one row per lane, for single systems whose rows hold
+ * at most 8 entries), and keeps the fastest for the PCG's product and the
+ * FP32 lpcg_spmv (the FP64 product keeps the fastest gather form); those
+ * table entries have direction 2, mode = G, waves = blocks and block_rows
+ * (0 for the gather and ELL forms).  It writes up to table_len measured
  * candidates to table (HOST, may be NULL) and their number to *n_table
  * (HOST, may be NULL).  Uses the system's work vectors: not concurrent with
  * a solve on the same system.  Synchronous. */
@@ -331,7 +336,10 @@ int lpcg_autotune(lpcg_system *sys, const float *l_val, const float *ut_val, int
  * ignored).  Direction 2 is the SpMV: mode = lanes per row (4, 8, 16, 32 or
  * 64), waves = blocks of 256 threads (1 .. 2048) of the gather form, or
  * block_rows = R > 0 for the LDS-staged form (waves then reads back as its
- * block count; a refused R leaves the previous form in force).  Errors: EINVAL for an
+ * block count; a refused R leaves the previous form in force), or mode 1 for
+ * the ELL form (single systems whose rows hold at most 8 entries, else
+ * EINVAL; waves and block_rows ignored, the gather form's settings kept for
+ * the FP64 product).  Errors: EINVAL for an
  * unknown direction, mode, a backoff outside
  * 0..64, a block_stride other than 0, 1, 2, 4, 8, mode 2 on a system with
  * a level wider than 3072 rows, or a mode-3 block shape the pattern does not
@@ -389,7 +397,9 @@ int lpcg_pcg_solve(lpcg_system *sys, const lpcg_precond *P, const double *b,
  * receives the mean duration in microseconds of [0] the application
  * z = (L L^T)^-1 r (LLT only; 0 otherwise), [1] the SpMV w = A p with
  * p = z + beta p_prev and the p.w reduction, [2] the x, r update with
- * ||r||^2.  The iteration never converges (tolerance 0).  Synchronous; uses
+ * ||r||^2 (0 where the application performs it: the ELL form of the
+ * two-level pair, whose launches then also carry that update from the second
+ * round on).  The iteration never converges (tolerance 0).  Synchronous; uses
  * the system's work vectors (not concurrent with a solve on the system).
  * Errors: EINVAL. */
 int lpcg_time_pcg_kernels(lpcg_system *sys, const lpcg_precond *P, const double *b, int32_t reps,

@@ -459,17 +459,29 @@ struct E2 {
     const float *sval, *sdiag, *pval, *pdiag;
 };
 
-template <int WM>
+// XR: the iteration's x, r update rides along (three launches per
+// iteration instead of four).  After the product of iteration it >= 1 (alpha
+// and p in place) each kernel forms r_i - alpha w_i for its own rows, writes
+// it with x_i + alpha p_i, and the suffix kernel forms its prefix neighbours'
+// new r on the fly (the same expression, so the same value the prefix kernel
+// writes); both publish ||r||^2 partials and the prefix kernel's reducer
+// takes the convergence test.  The first application (it = 0) updates
+// nothing.
+template <int WM, bool XR>
 __global__ void __launch_bounds__(VT) k_llt2e_suffix(Args a, E2 e) {
     __shared__ double lds[VT / kWave];
     const int p = e.p, nb = a.n - p, w = e.ws;
     const int i = blockIdx.x * VT + threadIdx.x;  // suffix row p + i
     const float *__restrict__ rv = a.r;
     const float *__restrict__ lv = a.lval;
+    const float *__restrict__ wv = a.w;
     int col[WM];
     float val[WM];
-    float d = 1.f, ri = 0.f;
+    float d = 1.f, ri = 0.f, wi = 0.f, pa = 0.f, pb = 0.f;
+    double xi = 0.0;
     const int flag = ld_ctrl(a.ctrl + C_DONE);
+    int it = XR ? ld_ctrl(a.ctrl + C_IT) : 0;
+    const double alpha = XR ? ld_scal(a.scal + S_ALPHA) : 0.0;
     if (i < nb) {
 #pragma unroll
         for (int t = 0; t < WM; ++t)
@@ -479,14 +491,37 @@ __global__ void __launch_bounds__(VT) k_llt2e_suffix(Args a, E2 e) {
             }
         d = e.sdiag[i];
         ri = rv[p + i];
+        if (XR) {
+            wi = wv[p + i];
+            xi = a.x[p + i];
+            pa = a.p0[p + i];
+            pb = a.p1[p + i];
+        }
     }
     if (done_now(flag)) return;
-    double rz = 0;
+    bool upd = false;
+    float af = 0.f;
+    if (XR) {
+        it = lane_value(it);
+        upd = it > 0;
+        af = (float)alpha;
+    }
+    double rz = 0, rr = 0;
     if (i < nb) {
         float g[WM];
 #pragma unroll
         for (int t = 0; t < WM; ++t)
-            if (t < w) g[t] = rv[col[t]] / lv[col[t]];  // y_j = r_j / L_jj of prefix row j
+            if (t < w) {
+                float rj = rv[col[t]];
+                if (XR && upd) rj = __fmaf_rn(-af, wv[col[t]], rj);
+                g[t] = rj / lv[col[t]];  // y_j = r_j / L_jj of prefix row j
+            }
+        if (XR && upd) {
+            ri = __fmaf_rn(-af, wi, ri);
+            a.r[p + i] = ri;
+            a.x[p + i] = __fma_rn(alpha, (double)(((it - 1) & 1) ? pb : pa), xi);
+            rr = (double)ri * ri;
+        }
         float acc = 0.f;
 #pragma unroll
         for (int t = 0; t < WM; ++t)
@@ -496,10 +531,14 @@ __global__ void __launch_bounds__(VT) k_llt2e_suffix(Args a, E2 e) {
         rz = (double)ri * (double)zv;
     }
     rz = block_sum<VT>(rz, lds);
-    if (threadIdx.x == 0) publish_partial(a.sp_rz, blockIdx.x, rz);
+    if (XR && upd) rr = block_sum<VT>(rr, lds);
+    if (threadIdx.x == 0) {
+        publish_partial(a.sp_rz, blockIdx.x, rz);
+        if (XR && upd) publish_partial(a.sp_rr, blockIdx.x, rr);
+    }
 }
 
-template <int WM>
+template <int WM, bool XR>
 __global__ void __launch_bounds__(VT) k_llt2e_prefix(Args a, E2 e, int part0) {
     __shared__ double lds[VT / kWave];
     const int p = e.p, w = e.wp;
@@ -507,8 +546,11 @@ __global__ void __launch_bounds__(VT) k_llt2e_prefix(Args a, E2 e, int part0) {
     float *z = (float *)a.z;  // reads the suffix rows' z, writes the prefix rows'
     int col[WM];
     float val[WM];
-    float d = 1.f, rj = 0.f;
+    float d = 1.f, rj = 0.f, wj = 0.f, pa = 0.f, pb = 0.f;
+    double xj = 0.0;
     const int flag = ld_ctrl(a.ctrl + C_DONE);
+    int it = XR ? ld_ctrl(a.ctrl + C_IT) : 0;
+    const double alpha = XR ? ld_scal(a.scal + S_ALPHA) : 0.0;
     if (j < p) {
 #pragma unroll
         for (int t = 0; t < WM; ++t)
@@ -518,14 +560,31 @@ __global__ void __launch_bounds__(VT) k_llt2e_prefix(Args a, E2 e, int part0) {
             }
         d = e.pdiag[j];
         rj = a.r[j];
+        if (XR) {
+            wj = a.w[j];
+            xj = a.x[j];
+            pa = a.p0[j];
+            pb = a.p1[j];
+        }
     }
     if (done_now(flag)) return;
-    double rz = 0;
+    bool upd = false;
+    if (XR) {
+        it = lane_value(it);
+        upd = it > 0;
+    }
+    double rz = 0, rr = 0;
     if (j < p) {
         float g[WM];
 #pragma unroll
         for (int t = 0; t < WM; ++t)
             if (t < w) g[t] = z[col[t]];
+        if (XR && upd) {
+            rj = __fmaf_rn(-(float)alpha, wj, rj);
+            a.r[j] = rj;
+            a.x[j] = __fma_rn(alpha, (double)(((it - 1) & 1) ? pb : pa), xj);
+            rr = (double)rj * rj;
+        }
         float acc = 0.f;
 #pragma unroll
         for (int t = 0; t < WM; ++t)
@@ -535,8 +594,17 @@ __global__ void __launch_bounds__(VT) k_llt2e_prefix(Args a, E2 e, int part0) {
         rz = (double)rj * (double)zv;
     }
     rz = block_sum<VT>(rz, lds);
-    if (threadIdx.x == 0) publish_partial(a.sp_rz, part0 + blockIdx.x, rz);
-    if (is_reducer()) finish_rz(a, lds);
+    if (XR && upd) rr = block_sum<VT>(rr, lds);
+    if (threadIdx.x == 0) {
+        publish_partial(a.sp_rz, part0 + blockIdx.x, rz);
+        if (XR && upd) publish_partial(a.sp_rr, part0 + blockIdx.x, rr);
+    }
+    if (!is_reducer()) return;
+    if (XR && upd) {  // the convergence test of r_it (the update of iteration it)
+        const double rrt = reduce_published<VT>(a.sp_rr, a.np_rz, lds);
+        if (threadIdx.x == 0) record_residual(a, rrt, it);
+    }
+    finish_rz(a, lds);
 }
 
 // One factor's values into the pair's ELL slots (padding: 0) and diagonals.
@@ -887,8 +955,8 @@ __global__ void __launch_bounds__(VT) k_xr(Args a) {
     float pi = odd ? pb : pa;
     double rr = 0, rzn = 0;
     while (i < n) {
-        xr[i] = xi + alpha * (double)pi;
-        const float ri = ri0 - af * wi;
+        xr[i] = __fma_rn(alpha, (double)pi, xi);
+        const float ri = __fmaf_rn(-af, wi, ri0);
         rv[i] = ri;
         rr += (double)ri * ri;
         if (KIND == LPCG_PC_JACOBI) {
@@ -988,16 +1056,16 @@ int ell_blocks(const lpcg_system *s) { return std::max(1, std::min(kMaxSpmvBlock
 // that the timing aid can bracket each.
 template <int KIND>
 int enqueue_apply(const lpcg_system *s, const Args &a, hipStream_t st) {
-    if (KIND == LPCG_PC_LLT && e2_path(s)) {
+    if (KIND == LPCG_PC_LLT && e2_path(s)) {  // the x, r update rides along (k_xr is not launched)
         const int p = s->two_level_p;
         const int nbs = (s->n - p + VT - 1) / VT, nbp = (p + VT - 1) / VT;
         const E2 e = e2_args(s);
         if (s->e2_ws <= 4 && s->e2_wp <= 4) {
-            k_llt2e_suffix<4><<<nbs, VT, 0, st>>>(a, e);
-            k_llt2e_prefix<4><<<nbp, VT, 0, st>>>(a, e, nbs);
+            k_llt2e_suffix<4, true><<<nbs, VT, 0, st>>>(a, e);
+            k_llt2e_prefix<4, true><<<nbp, VT, 0, st>>>(a, e, nbs);
         } else {
-            k_llt2e_suffix<8><<<nbs, VT, 0, st>>>(a, e);
-            k_llt2e_prefix<8><<<nbp, VT, 0, st>>>(a, e, nbs);
+            k_llt2e_suffix<8, true><<<nbs, VT, 0, st>>>(a, e);
+            k_llt2e_prefix<8, true><<<nbp, VT, 0, st>>>(a, e, nbs);
         }
     } else if (KIND == LPCG_PC_LLT && two_level_path(s)) {
         const int G = s->trsv_g, p = s->two_level_p;
@@ -1097,6 +1165,7 @@ int enqueue_spmv(const lpcg_system *s, const Args &a, hipStream_t st) {
 
 template <int KIND>
 int enqueue_xr(const lpcg_system *s, const Args &a, hipStream_t st) {
+    if (KIND == LPCG_PC_LLT && e2_path(s)) return LPCG_OK;  // done by the next application
     k_xr<KIND><<<s->vec_blocks, VT, 0, st>>>(a);
     LPCG_LAUNCH_CHECK();
     return LPCG_OK;
@@ -1496,6 +1565,7 @@ int time_parts(lpcg_system *s, const Args &a, int reps, double *out_us, hipStrea
     }
     for (int k = 0; k < 3; ++k) out_us[k] = 1e3 * tot[k] / reps;
     if (KIND != LPCG_PC_LLT) out_us[0] = 0.0;  // no application kernel
+    if (KIND == LPCG_PC_LLT && e2_path(s)) out_us[2] = 0.0;  // the update runs in the application
     return LPCG_OK;
 }
 

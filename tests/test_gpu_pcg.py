@@ -165,15 +165,63 @@ def test_pcg_nonzero_initial_guess_and_restart():
 @pytest.mark.parametrize("ordering", [0, 1])
 def test_time_pcg_kernels_parts(ordering):
     """The timing aid runs the iteration's three parts and returns positive
-    durations; with Jacobi the application part is empty (0).  A solve
-    afterwards on the same system is unaffected (it resets its own state)."""
+    durations; with Jacobi the application part is empty (0), and so is the
+    update part in the red-black order, whose two-level pair (ELL form)
+    performs the update.  A solve afterwards on the same system is
+    unaffected (it resets its own state)."""
     A, b = g.heat_system_3d(16, 1e-3, 3, 4)
     S = gpu_system(A, None, ordering)
     bd = cuda_f64(b)
     l, ut, _ = lpcg.ic0(S)
     t = lpcg.time_pcg_kernels(S, lpcg.PC_LLT, bd, l_val=l, ut_val=ut, reps=5)
-    assert all(v > 0 for v in t), t
+    if ordering == 1:
+        assert t[0] > 0 and t[1] > 0 and t[2] == 0, t
+    else:
+        assert all(v > 0 for v in t), t
     tj = lpcg.time_pcg_kernels(S, lpcg.PC_JACOBI, bd, reps=5)
     assert tj[0] == 0 and tj[1] > 0 and tj[2] > 0, tj
     x, res = lpcg.pcg_solve(S, lpcg.PC_LLT, bd, l_val=l, ut_val=ut, tol=1e-6, max_restarts=2)
     assert res["status"] == 0 and O.true_relres(A, b, host(x)) <= 1e-6
+
+
+def test_pcg_color_fused_update():
+    """Red-black order: the two-level pair's ELL form performs the x, r
+    update (three launches per iteration).  Graph replay equals eager bit for
+    bit and repeats bit for bit; an iteration cap ends with ENOTCONV after
+    exactly maxit products at the oracle's iterate (same IC(0) in FP64); the
+    residual history follows the per-level path's (separate update kernel)
+    to FP32 rounding, with the same iteration count."""
+    A = matrices_small()["heat3d_13"]
+    b = np.random.default_rng(11).standard_normal(A.n)
+    S = gpu_system(A, None, 1)
+    assert S.info["nlev_fwd"] == 2
+    l, ut, _ = lpcg.ic0(S)
+    outs = []
+    for use_graph in (False, True, True, False):
+        x, res = lpcg.pcg_solve(S, lpcg.PC_LLT, cuda_f64(b), l_val=l, ut_val=ut, tol=1e-8,
+                                use_graph=use_graph, check_every=3)
+        torch.cuda.synchronize()
+        outs.append((host(x), res["iters"]))
+    for x, it in outs[1:]:
+        assert it == outs[0][1]
+        assert np.array_equal(x, outs[0][0])
+    # the cap: 5 products, x after the 5th update
+    x, res = lpcg.pcg_solve(S, lpcg.PC_LLT, cuda_f64(b), l_val=l, ut_val=ut, tol=1e-12, maxit=5)
+    assert res["status"] == lpcg.ENOTCONV and res["iters"] == 5
+    perm, _, _ = O.color_order(A)
+    Ap = O.permute_sym(A, perm)
+    pat = O.Pattern(Ap)
+    lref, _ = O.ic0(pat, Ap)
+    ref = O.pcg(Ap, b[perm], O.PC_LLT, pat, lref, tol=1e-12, maxit=5)
+    assert ref["status"] == O.NOTCONV
+    xr = np.empty(A.n)
+    xr[perm] = ref["x"]
+    np.testing.assert_allclose(host(x), xr, rtol=1e-4, atol=1e-5 * np.abs(xr).max())
+    # history against the per-level path (k_xr)
+    _, r1, h1 = lpcg.pcg_solve(S, lpcg.PC_LLT, cuda_f64(b), l_val=l, ut_val=ut, tol=1e-8, hist=True)
+    lpcg.set_trsv_cfg(S, 1, 0)
+    _, r2, h2 = lpcg.pcg_solve(S, lpcg.PC_LLT, cuda_f64(b), l_val=l, ut_val=ut, tol=1e-8, hist=True)
+    assert r1["status"] == 0 and r2["status"] == 0 and r1["iters"] == r2["iters"], (r1, r2)
+    k = r1["iters"] + 1
+    h1, h2 = host(h1)[:k], host(h2)[:k]
+    assert np.all(np.abs(h1 - h2) <= 1e-3 * h2), np.max(np.abs(h1 - h2) / h2)
