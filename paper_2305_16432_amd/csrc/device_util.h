@@ -134,6 +134,56 @@ __device__ __forceinline__ double reduce_published(double *part, int np, double 
     return block_sum<BS>(s, lds);
 }
 
+// Two published arrays of np slots each, summed as reduce_published sums
+// each (every thread takes its slots in the same order, so the sums are the
+// same bit for bit), with their loads issued together and one wait for both.
+template <int BS>
+__device__ __forceinline__ void reduce_published2(double *pa, double *pb, int np, double *lds, double &sa,
+                                                  double &sb) {
+    constexpr int H = kPubBatch / 2;
+    uint64_t *qa = reinterpret_cast<uint64_t *>(pa);
+    uint64_t *qb = reinterpret_cast<uint64_t *>(pb);
+    double s0 = 0.0, s1 = 0.0;
+    for (int base = 0; base < np; base += BS * H) {
+        uint64_t va[H], vb[H];
+#pragma unroll
+        for (int t = 0; t < H; ++t) {
+            const int i = base + t * BS + (int)threadIdx.x;
+            va[t] = i < np ? ld_agent_u64(qa + i) : 0ull;
+            vb[t] = i < np ? ld_agent_u64(qb + i) : 0ull;
+        }
+        for (;;) {
+            bool pending = false;
+#pragma unroll
+            for (int t = 0; t < H; ++t) {
+                const int i = base + t * BS + (int)threadIdx.x;
+                if (i < np && va[t] == kPartUnset) {
+                    va[t] = ld_agent_u64(qa + i);
+                    pending = pending || va[t] == kPartUnset;
+                }
+                if (i < np && vb[t] == kPartUnset) {
+                    vb[t] = ld_agent_u64(qb + i);
+                    pending = pending || vb[t] == kPartUnset;
+                }
+            }
+            if (!pending) break;
+            __builtin_amdgcn_s_sleep(1);
+        }
+#pragma unroll
+        for (int t = 0; t < H; ++t) {
+            const int i = base + t * BS + (int)threadIdx.x;
+            if (i < np) {
+                s0 += __longlong_as_double((long long)va[t]);
+                s1 += __longlong_as_double((long long)vb[t]);
+                st_agent_u64(qa + i, kPartUnset);
+                st_agent_u64(qb + i, kPartUnset);
+            }
+        }
+    }
+    sa = block_sum<BS>(s0, lds);
+    sb = block_sum<BS>(s1, lds);
+}
+
 // Deterministic reduction of np partial sums (fixed order), result in all
 // threads of the block.
 template <int BS>

@@ -194,16 +194,18 @@ __global__ void __launch_bounds__(VT) k_setup_scal(Args a) {
 
 // beta from the r.z partials (reducer block of the backward substitution;
 // BS threads).
+__device__ __forceinline__ void set_beta(const Args &a, double rz) {
+    const int it = a.ctrl[C_IT];
+    const double old = a.scal[S_RZ0];
+    a.scal[S_BETA] = it == 0 ? 0.0 : rz / old;
+    a.scal[S_RZ0] = rz;
+    if (a.coef && it >= 1 && it <= a.maxit) a.coef[2 * it + 1] = rz / old;
+}
+
 template <int BS = VT>
 __device__ __forceinline__ void finish_rz(const Args &a, double *lds) {
     const double rz = reduce_published<BS>(a.sp_rz, a.np_rz, lds);
-    if (threadIdx.x == 0) {
-        const int it = a.ctrl[C_IT];
-        const double old = a.scal[S_RZ0];
-        a.scal[S_BETA] = it == 0 ? 0.0 : rz / old;
-        a.scal[S_RZ0] = rz;
-        if (a.coef && it >= 1 && it <= a.maxit) a.coef[2 * it + 1] = rz / old;
-    }
+    if (threadIdx.x == 0) set_beta(a, rz);
 }
 
 __global__ void __launch_bounds__(256) k_llt_fwd(Args a) {
@@ -600,11 +602,16 @@ __global__ void __launch_bounds__(VT) k_llt2e_prefix(Args a, E2 e, int part0) {
         if (XR && upd) publish_partial(a.sp_rr, part0 + blockIdx.x, rr);
     }
     if (!is_reducer()) return;
-    if (XR && upd) {  // the convergence test of r_it (the update of iteration it)
-        const double rrt = reduce_published<VT>(a.sp_rr, a.np_rz, lds);
-        if (threadIdx.x == 0) record_residual(a, rrt, it);
+    if (XR && upd) {  // beta and the convergence test of r_it (the update of iteration it)
+        double rzt, rrt;
+        reduce_published2<VT>(a.sp_rz, a.sp_rr, a.np_rz, lds, rzt, rrt);
+        if (threadIdx.x == 0) {
+            record_residual(a, rrt, it);
+            set_beta(a, rzt);
+        }
+    } else {
+        finish_rz(a, lds);
     }
-    finish_rz(a, lds);
 }
 
 // One factor's values into the pair's ELL slots (padding: 0) and diagonals.
