@@ -323,7 +323,8 @@ int lpcg_blocked_schedule(int32_t n, const int32_t *rowptr, const int32_t *col, 
  * 512 and 1024 rows per block at G = 4 and 8 (where the windows fit), and
  * the ELL form (G = 1: one row per lane, for single systems whose rows hold
  * at most 8 entries), and keeps the fastest for the PCG's product and the
- * FP32 lpcg_spmv (the FP64 product keeps the fastest gather form); those
+ * FP32 lpcg_spmv (the ELL form unless another is at least 10% faster; the
+ * FP64 product keeps the fastest gather form); those
  * table entries have direction 2, mode = G, waves = blocks and block_rows
  * (0 for the gather and ELL forms).  It writes up to table_len measured
  * candidates to table (HOST, may be NULL) and their number to *n_table

@@ -134,6 +134,9 @@ def test_autotune_c3_full_size(ordering):
     sp = [t for t in table if t["direction"] == 2]
     assert {t["mode"] for t in sp} == {1, 4, 8, 16, 32, 64}  # 1: the ELL form (7-entry rows)
     best = min(sp, key=lambda t: t["us"])
+    ell = next(t for t in sp if t["mode"] == 1)
+    if ell["us"] <= 1.1 * best["us"]:  # the ELL form stays unless another is 10% faster
+        best = ell
     got = lpcg.get_trsv_cfg(S, 2)
     assert got["mode"] == best["mode"] and got["waves"] == best["waves"]
     assert got["block_rows"] == best["block_rows"]
