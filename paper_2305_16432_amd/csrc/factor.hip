@@ -42,8 +42,16 @@ int launch_spmv(const lpcg_system *s, const VT *v, const XT *x, XT *y, hipStream
                 return LPCG_EINVAL;
             }
             const int eb = std::max(1, std::min(kMaxSpmvBlocks, nblk(s->n, threads)));
-            if (s->ea_w <= 4) k_spmv_e<4><<<eb, threads, 0, st>>>(s->n, s->ea_w, s->ea_col, s->ea_val, x, y);
-            else k_spmv_e<8><<<eb, threads, 0, st>>>(s->n, s->ea_w, s->ea_col, s->ea_val, x, y);
+            switch (s->ea_w) {
+                case 1: k_spmv_e<1><<<eb, threads, 0, st>>>(s->n, s->ea_col, s->ea_val, x, y); break;
+                case 2: k_spmv_e<2><<<eb, threads, 0, st>>>(s->n, s->ea_col, s->ea_val, x, y); break;
+                case 3: k_spmv_e<3><<<eb, threads, 0, st>>>(s->n, s->ea_col, s->ea_val, x, y); break;
+                case 4: k_spmv_e<4><<<eb, threads, 0, st>>>(s->n, s->ea_col, s->ea_val, x, y); break;
+                case 5: k_spmv_e<5><<<eb, threads, 0, st>>>(s->n, s->ea_col, s->ea_val, x, y); break;
+                case 6: k_spmv_e<6><<<eb, threads, 0, st>>>(s->n, s->ea_col, s->ea_val, x, y); break;
+                case 7: k_spmv_e<7><<<eb, threads, 0, st>>>(s->n, s->ea_col, s->ea_val, x, y); break;
+                default: k_spmv_e<8><<<eb, threads, 0, st>>>(s->n, s->ea_col, s->ea_val, x, y); break;
+            }
             LPCG_LAUNCH_CHECK();
             return LPCG_OK;
         }

@@ -32,30 +32,28 @@ __global__ void __launch_bounds__(256) k_spmv(int n, const int *__restrict__ rp,
     }
 }
 
-// ELL form (slot t of row i at t * n + i, w <= WM slots, padding adds
-// 0 * x_i): one row per lane, entries summed in the row's CSR order.
-template <int WM>
-__global__ void __launch_bounds__(256) k_spmv_e(int n, int w, const int *__restrict__ col,
+// ELL form (slot t of row i at t * n + i, W slots, padding adds 0 * x_i):
+// one row per lane, entries summed in the row's CSR order; W is a template
+// argument so that every slot load is unconditional.
+template <int W>
+__global__ void __launch_bounds__(256) k_spmv_e(int n, const int *__restrict__ col,
                                                 const float *__restrict__ val, const float *__restrict__ x,
                                                 float *__restrict__ y) {
     for (int row = blockIdx.x * 256 + threadIdx.x; row < n; row += gridDim.x * 256) {
         // every slot's loads, then every gather, then the sum: two memory
         // round trips per row
-        int c[WM];
-        float v[WM], g[WM];
+        int c[W];
+        float v[W], g[W];
 #pragma unroll
-        for (int t = 0; t < WM; ++t)
-            if (t < w) {
-                c[t] = col[(size_t)t * n + row];
-                v[t] = val[(size_t)t * n + row];
-            }
+        for (int t = 0; t < W; ++t) {
+            c[t] = col[(size_t)t * n + row];
+            v[t] = val[(size_t)t * n + row];
+        }
 #pragma unroll
-        for (int t = 0; t < WM; ++t)
-            if (t < w) g[t] = x[c[t]];
+        for (int t = 0; t < W; ++t) g[t] = x[c[t]];
         float acc = 0.f;
 #pragma unroll
-        for (int t = 0; t < WM; ++t)
-            if (t < w) acc += v[t] * g[t];
+        for (int t = 0; t < W; ++t) acc += v[t] * g[t];
         y[row] = acc;
     }
 }

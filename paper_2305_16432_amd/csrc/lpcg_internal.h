@@ -39,6 +39,7 @@ enum Ctrl : int {
     C_TICKET_X = 6,  // spare work counter (standalone solves)
     C_MAXIT = 7,
     C_NDONE = 8,     // batched solve: systems finished
+    C_PHASE = 9,     // fused red-black path: 0 before the solve's first application, 1 after
     C_NCTRL = 16
 };
 enum Scal : int {

@@ -53,6 +53,10 @@ constexpr int VT = kVecThreads;
 
 struct Args {
     int n, np_vec, np_rz, maxit, kind;
+    // defer: the product kernel publishes its p.w partials to part_pw (plain
+    // stores, np_pw slots) and computes no alpha; the fused red-black pair
+    // reduces them itself (see k_llt2e_*)
+    int defer, np_pw;
     int backoff_f, backoff_b, stride_f, stride_b, reset_y, reset_z;
     const int *rp, *ci;
     const float *v32;
@@ -182,6 +186,7 @@ __global__ void __launch_bounds__(VT) k_setup_scal(Args a) {
         a.scal[S_BETA] = 0;
         a.scal[S_RR] = rr;
         a.ctrl[C_IT] = 0;
+        a.ctrl[C_PHASE] = 0;
         a.ctrl[C_ITERS] = 0;
         a.ctrl[C_TICKET_F] = 0;
         a.ctrl[C_TICKET_B] = 0;
@@ -194,8 +199,7 @@ __global__ void __launch_bounds__(VT) k_setup_scal(Args a) {
 
 // beta from the r.z partials (reducer block of the backward substitution;
 // BS threads).
-__device__ __forceinline__ void set_beta(const Args &a, double rz) {
-    const int it = a.ctrl[C_IT];
+__device__ __forceinline__ void set_beta(const Args &a, double rz, int it) {
     const double old = a.scal[S_RZ0];
     a.scal[S_BETA] = it == 0 ? 0.0 : rz / old;
     a.scal[S_RZ0] = rz;
@@ -205,7 +209,7 @@ __device__ __forceinline__ void set_beta(const Args &a, double rz) {
 template <int BS = VT>
 __device__ __forceinline__ void finish_rz(const Args &a, double *lds) {
     const double rz = reduce_published<BS>(a.sp_rz, a.np_rz, lds);
-    if (threadIdx.x == 0) set_beta(a, rz);
+    if (threadIdx.x == 0) set_beta(a, rz, a.ctrl[C_IT]);
 }
 
 __global__ void __launch_bounds__(256) k_llt_fwd(Args a) {
@@ -453,164 +457,211 @@ __global__ void __launch_bounds__(256) k_llt2_prefix(Args a, int p, int part0) {
 // factor's values packed per solve by k_e2_pack): one row per lane, so a
 // row's loads take two memory round trips (its slots, diagonal and r with
 // the done flag; then the gathers) instead of three (bounds, entries,
-// gathers).  A row's entries are summed in its CSR order.  WM: the slot
-// count rounded up (4 or 8); w <= WM slots are used.
+// gathers).  A row's entries are summed in its CSR order.  W: the slot
+// count (1..kEllMaxW), a template argument so that every slot load is
+// unconditional and all are issued before the first wait.
 struct E2 {
     int p, ws, wp;
     const int *scol, *pcol;
     const float *sval, *sdiag, *pval, *pdiag;
 };
 
-// XR: the iteration's x, r update rides along (three launches per
-// iteration instead of four).  After the product of iteration it >= 1 (alpha
-// and p in place) each kernel forms r_i - alpha w_i for its own rows, writes
-// it with x_i + alpha p_i, and the suffix kernel forms its prefix neighbours'
-// new r on the fly (the same expression, so the same value the prefix kernel
-// writes); both publish ||r||^2 partials and the prefix kernel's reducer
-// takes the convergence test.  The first application (it = 0) updates
-// nothing.
-template <int WM, bool XR>
+// The iteration's x, r update rides along (three launches per iteration
+// instead of four).  The product before the application k >= 1 published
+// its p.w partials without reducing them (defer); every block of both
+// kernels sums them in the same fixed order, so all take the same
+// alpha_k = r.z_(k-1) / p.w (a breakdown is seen by all alike and the
+// prefix kernel's reducer records it).  Each kernel then forms
+// r_i - alpha w_i for its own rows and writes it with x_i + alpha p_i; the
+// suffix kernel forms its prefix neighbours' new r on the fly (the same
+// fused multiply-add, so the same value the prefix kernel writes).  Both
+// publish ||r||^2 partials; the prefix kernel's reducer counts the product,
+// takes the convergence test and beta from one wait on both sets of
+// partials.  The solve's first application (C_PHASE = 0) updates nothing.
+
+// The deferred p.w partials: this thread's slots tid, tid + VT, ... (at most
+// kMaxSpmvBlocks in all), loaded with the kernel's first data and summed
+// only after its done test (a sum placed among the loads makes the compiler
+// wait for them there), in the order reduce_published takes.
+constexpr int kPwShare = kMaxSpmvBlocks / VT;
+
+// (The partial arrays hold kMaxSpmvBlocks slots, so every load is in
+// bounds; the slots past np_pw are read and left out of the sum.)
+__device__ __forceinline__ void pw_load(const Args &a, double (&v)[kPwShare]) {
+#pragma unroll
+    for (int u = 0; u < kPwShare; ++u) v[u] = a.part_pw[(int)threadIdx.x + u * VT];
+}
+
+// alpha of the pending update (every block alike); false on a breakdown
+// (p.w <= 0 or not finite, or r.z not finite).
+__device__ __forceinline__ bool deferred_alpha(const Args &a, const double (&v)[kPwShare], double rz_old,
+                                               double *lds, double &alpha) {
+    double s = 0.0;
+#pragma unroll
+    for (int u = 0; u < kPwShare; ++u)
+        if ((int)threadIdx.x + u * VT < a.np_pw) s += v[u];
+    const double pwt = block_sum<VT>(s, lds);
+    alpha = rz_old / pwt;
+    return pwt > 0.0 && isfinite(pwt) && isfinite(rz_old);
+}
+
+template <int W>
 __global__ void __launch_bounds__(VT) k_llt2e_suffix(Args a, E2 e) {
     __shared__ double lds[VT / kWave];
-    const int p = e.p, nb = a.n - p, w = e.ws;
+    const int p = e.p, nb = a.n - p;
     const int i = blockIdx.x * VT + threadIdx.x;  // suffix row p + i
     const float *__restrict__ rv = a.r;
     const float *__restrict__ lv = a.lval;
     const float *__restrict__ wv = a.w;
-    int col[WM];
-    float val[WM];
+    int col[W];
+    float val[W];
     float d = 1.f, ri = 0.f, wi = 0.f, pa = 0.f, pb = 0.f;
     double xi = 0.0;
     const int flag = ld_ctrl(a.ctrl + C_DONE);
-    int it = XR ? ld_ctrl(a.ctrl + C_IT) : 0;
-    const double alpha = XR ? ld_scal(a.scal + S_ALPHA) : 0.0;
+    int it = ld_ctrl(a.ctrl + C_IT);
+    int phase = ld_ctrl(a.ctrl + C_PHASE);
+    const double rz_old = ld_scal(a.scal + S_RZ0);
+    double share[kPwShare];
+    pw_load(a, share);
     if (i < nb) {
 #pragma unroll
-        for (int t = 0; t < WM; ++t)
-            if (t < w) {
+        for (int t = 0; t < W; ++t)
+            {
                 col[t] = e.scol[(size_t)t * nb + i];
                 val[t] = e.sval[(size_t)t * nb + i];
             }
         d = e.sdiag[i];
         ri = rv[p + i];
-        if (XR) {
-            wi = wv[p + i];
-            xi = a.x[p + i];
-            pa = a.p0[p + i];
-            pb = a.p1[p + i];
-        }
+        wi = wv[p + i];
+        xi = a.x[p + i];
+        pa = a.p0[p + i];
+        pb = a.p1[p + i];
     }
     if (done_now(flag)) return;
-    bool upd = false;
-    float af = 0.f;
-    if (XR) {
-        it = lane_value(it);
-        upd = it > 0;
-        af = (float)alpha;
-    }
+    it = lane_value(it);
+    const bool upd = done_now(phase);  // wave-uniform read of the phase word
+    double alpha = 0.0;
+    if (upd && !deferred_alpha(a, share, rz_old, lds, alpha)) return;  // breakdown: the prefix kernel records it
+    const float af = (float)alpha;
     double rz = 0, rr = 0;
     if (i < nb) {
-        float g[WM];
+        float g[W];
 #pragma unroll
-        for (int t = 0; t < WM; ++t)
-            if (t < w) {
+        for (int t = 0; t < W; ++t)
+            {
                 float rj = rv[col[t]];
-                if (XR && upd) rj = __fmaf_rn(-af, wv[col[t]], rj);
+                if (upd) rj = __fmaf_rn(-af, wv[col[t]], rj);
                 g[t] = rj / lv[col[t]];  // y_j = r_j / L_jj of prefix row j
             }
-        if (XR && upd) {
+        if (upd) {  // p_k was written to the buffer of parity k - 1 = it
             ri = __fmaf_rn(-af, wi, ri);
             a.r[p + i] = ri;
-            a.x[p + i] = __fma_rn(alpha, (double)(((it - 1) & 1) ? pb : pa), xi);
+            a.x[p + i] = __fma_rn(alpha, (double)((it & 1) ? pb : pa), xi);
             rr = (double)ri * ri;
         }
         float acc = 0.f;
 #pragma unroll
-        for (int t = 0; t < WM; ++t)
-            if (t < w) acc += val[t] * g[t];
+        for (int t = 0; t < W; ++t)
+            acc += val[t] * g[t];
         const float zv = ((ri - acc) / d) / d;
         ((float *)a.z)[p + i] = zv;
         rz = (double)ri * (double)zv;
     }
     rz = block_sum<VT>(rz, lds);
-    if (XR && upd) rr = block_sum<VT>(rr, lds);
+    if (upd) rr = block_sum<VT>(rr, lds);
     if (threadIdx.x == 0) {
         publish_partial(a.sp_rz, blockIdx.x, rz);
-        if (XR && upd) publish_partial(a.sp_rr, blockIdx.x, rr);
+        if (upd) publish_partial(a.sp_rr, blockIdx.x, rr);
     }
 }
 
-template <int WM, bool XR>
+template <int W>
 __global__ void __launch_bounds__(VT) k_llt2e_prefix(Args a, E2 e, int part0) {
     __shared__ double lds[VT / kWave];
-    const int p = e.p, w = e.wp;
+    const int p = e.p;
     const int j = blockIdx.x * VT + threadIdx.x;  // prefix row j
     float *z = (float *)a.z;  // reads the suffix rows' z, writes the prefix rows'
-    int col[WM];
-    float val[WM];
+    int col[W > 0 ? W : 1];
+    float val[W > 0 ? W : 1];
     float d = 1.f, rj = 0.f, wj = 0.f, pa = 0.f, pb = 0.f;
     double xj = 0.0;
     const int flag = ld_ctrl(a.ctrl + C_DONE);
-    int it = XR ? ld_ctrl(a.ctrl + C_IT) : 0;
-    const double alpha = XR ? ld_scal(a.scal + S_ALPHA) : 0.0;
+    int it = ld_ctrl(a.ctrl + C_IT);
+    int phase = ld_ctrl(a.ctrl + C_PHASE);
+    const double rz_old = ld_scal(a.scal + S_RZ0);
+    double share[kPwShare];
+    pw_load(a, share);
     if (j < p) {
 #pragma unroll
-        for (int t = 0; t < WM; ++t)
-            if (t < w) {
+        for (int t = 0; t < W; ++t)
+            {
                 col[t] = e.pcol[(size_t)t * p + j];
                 val[t] = e.pval[(size_t)t * p + j];
             }
         d = e.pdiag[j];
         rj = a.r[j];
-        if (XR) {
-            wj = a.w[j];
-            xj = a.x[j];
-            pa = a.p0[j];
-            pb = a.p1[j];
-        }
+        wj = a.w[j];
+        xj = a.x[j];
+        pa = a.p0[j];
+        pb = a.p1[j];
     }
     if (done_now(flag)) return;
-    bool upd = false;
-    if (XR) {
-        it = lane_value(it);
-        upd = it > 0;
+    it = lane_value(it);
+    const bool upd = done_now(phase);
+    double alpha = 0.0;
+    if (upd && !deferred_alpha(a, share, rz_old, lds, alpha)) {
+        if (is_reducer() && threadIdx.x == 0) {  // the breakdown of product it + 1
+            a.ctrl[C_DONE] = 1;
+            a.ctrl[C_STATUS] = LPCG_EBREAKDOWN;
+            a.ctrl[C_ITERS] = it + 1;
+            a.ctrl[C_IT] = it + 1;
+        }
+        return;
     }
     double rz = 0, rr = 0;
     if (j < p) {
-        float g[WM];
+        float g[W > 0 ? W : 1];
 #pragma unroll
-        for (int t = 0; t < WM; ++t)
-            if (t < w) g[t] = z[col[t]];
-        if (XR && upd) {
+        for (int t = 0; t < W; ++t)
+            g[t] = z[col[t]];
+        if (upd) {
             rj = __fmaf_rn(-(float)alpha, wj, rj);
             a.r[j] = rj;
-            a.x[j] = __fma_rn(alpha, (double)(((it - 1) & 1) ? pb : pa), xj);
+            a.x[j] = __fma_rn(alpha, (double)((it & 1) ? pb : pa), xj);
             rr = (double)rj * rj;
         }
         float acc = 0.f;
 #pragma unroll
-        for (int t = 0; t < WM; ++t)
-            if (t < w) acc += val[t] * g[t];
+        for (int t = 0; t < W; ++t)
+            acc += val[t] * g[t];
         const float zv = (rj / d - acc) / d;
         z[j] = zv;
         rz = (double)rj * (double)zv;
     }
     rz = block_sum<VT>(rz, lds);
-    if (XR && upd) rr = block_sum<VT>(rr, lds);
+    if (upd) rr = block_sum<VT>(rr, lds);
     if (threadIdx.x == 0) {
         publish_partial(a.sp_rz, part0 + blockIdx.x, rz);
-        if (XR && upd) publish_partial(a.sp_rr, part0 + blockIdx.x, rr);
+        if (upd) publish_partial(a.sp_rr, part0 + blockIdx.x, rr);
     }
     if (!is_reducer()) return;
-    if (XR && upd) {  // beta and the convergence test of r_it (the update of iteration it)
+    if (upd) {  // product k = it + 1 done: alpha_k, the test of r_k, beta_k
         double rzt, rrt;
         reduce_published2<VT>(a.sp_rz, a.sp_rr, a.np_rz, lds, rzt, rrt);
         if (threadIdx.x == 0) {
-            record_residual(a, rrt, it);
-            set_beta(a, rzt);
+            const int k = it + 1;
+            a.ctrl[C_IT] = k;
+            a.scal[S_ALPHA] = alpha;
+            if (a.coef && k <= a.maxit) a.coef[2 * k] = alpha;
+            record_residual(a, rrt, k);
+            set_beta(a, rzt, k);
         }
-    } else {
-        finish_rz(a, lds);
+    } else {  // the first application: r.z of r_0
+        const double rzt = reduce_published<VT>(a.sp_rz, a.np_rz, lds);
+        if (threadIdx.x == 0) {
+            set_beta(a, rzt, 0);
+            a.ctrl[C_PHASE] = 1;
+        }
     }
 }
 
@@ -758,6 +809,10 @@ __global__ void __launch_bounds__(VT) k_spmv_pw(Args a) {
         }
     }
     pw = block_sum<VT>(pw, lds);
+    if (a.defer) {  // the fused red-black pair reduces the partials (next launch)
+        if (threadIdx.x == 0) a.part_pw[blockIdx.x] = pw;
+        return;
+    }
     if (threadIdx.x == 0) publish_partial(a.sp_pw, blockIdx.x, pw);
     if (!is_reducer()) return;
     const double pwt = reduce_published<VT>(a.sp_pw, gridDim.x, lds);
@@ -786,25 +841,25 @@ struct EA {
     const float *val;
 };
 
-template <int WM, int KIND>
+template <int W, int KIND>
 __global__ void __launch_bounds__(VT) k_spmv_pw_e(Args a, EA e) {
     __shared__ double lds[VT / kWave];
-    const int n = a.n, w = e.w;
+    const int n = a.n;
     const float *__restrict__ zs = KIND == LPCG_PC_NONE ? a.r : (const float *)a.z;
     const int *__restrict__ ec = e.col;
     const float *__restrict__ ev = e.val;
     float *__restrict__ wv = a.w;
     int row = blockIdx.x * VT + threadIdx.x;
-    int col[WM];
-    float val[WM];
+    int col[W];
+    float val[W];
     float zr = 0.f;
     const int flag = ld_ctrl(a.ctrl + C_DONE);
     int it = ld_ctrl(a.ctrl + C_IT);
     const float beta = (float)ld_scal(a.scal + S_BETA);
     if (row < n) {
 #pragma unroll
-        for (int t = 0; t < WM; ++t)
-            if (t < w) {
+        for (int t = 0; t < W; ++t)
+            {
                 col[t] = ec[(size_t)t * n + row];
                 val[t] = ev[(size_t)t * n + row];
             }
@@ -817,23 +872,23 @@ __global__ void __launch_bounds__(VT) k_spmv_pw_e(Args a, EA e) {
     float *__restrict__ pnw = (it & 1) ? a.p1 : a.p0;
     double pw = 0;
     while (row < n) {
-        float g[WM];
+        float g[W];
 #pragma unroll
-        for (int t = 0; t < WM; ++t)
-            if (t < w) g[t] = first ? zs[col[t]] : __fmaf_rn(beta, pq[col[t]], zs[col[t]]);
+        for (int t = 0; t < W; ++t)
+            g[t] = first ? zs[col[t]] : __fmaf_rn(beta, pq[col[t]], zs[col[t]]);
         const float pr = first ? zr : __fmaf_rn(beta, pq[row], zr);
         float acc = 0.f;
 #pragma unroll
-        for (int t = 0; t < WM; ++t)
-            if (t < w) acc += val[t] * g[t];
+        for (int t = 0; t < W; ++t)
+            acc += val[t] * g[t];
         pnw[row] = pr;
         wv[row] = acc;
         pw += (double)pr * (double)acc;
         row += gridDim.x * VT;
         if (row < n) {
 #pragma unroll
-            for (int t = 0; t < WM; ++t)
-                if (t < w) {
+            for (int t = 0; t < W; ++t)
+                {
                     col[t] = ec[(size_t)t * n + row];
                     val[t] = ev[(size_t)t * n + row];
                 }
@@ -841,6 +896,10 @@ __global__ void __launch_bounds__(VT) k_spmv_pw_e(Args a, EA e) {
         }
     }
     pw = block_sum<VT>(pw, lds);
+    if (a.defer) {  // the fused red-black pair reduces the partials (next launch)
+        if (threadIdx.x == 0) a.part_pw[blockIdx.x] = pw;
+        return;
+    }
     if (threadIdx.x == 0) publish_partial(a.sp_pw, blockIdx.x, pw);
     if (!is_reducer()) return;
     const double pwt = reduce_published<VT>(a.sp_pw, gridDim.x, lds);
@@ -905,6 +964,10 @@ __global__ void __launch_bounds__(VT) k_spmv_pw_st(Args a, int R, const int *__r
         }
     }
     pw = block_sum<VT>(pw, lds);
+    if (a.defer) {  // the fused red-black pair reduces the partials (next launch)
+        if (threadIdx.x == 0) a.part_pw[blockIdx.x] = pw;
+        return;
+    }
     if (threadIdx.x == 0) publish_partial(a.sp_pw, blockIdx.x, pw);
     if (!is_reducer()) return;
     const double pwt = reduce_published<VT>(a.sp_pw, gridDim.x, lds);
@@ -1058,22 +1121,64 @@ EA ea_args(const lpcg_system *s) { return EA{s->ea_w, s->ea_col, s->ea_val}; }
 
 int ell_blocks(const lpcg_system *s) { return std::max(1, std::min(kMaxSpmvBlocks, (s->n + VT - 1) / VT)); }
 
+// ELL launches with the slot count as a template argument (1..kEllMaxW).
+template <int KIND>
+void launch_spmv_pw_e(const lpcg_system *s, const Args &a, hipStream_t st) {
+    const int eb = ell_blocks(s);
+    const EA e = ea_args(s);
+    switch (s->ea_w) {
+        case 1: k_spmv_pw_e<1, KIND><<<eb, VT, 0, st>>>(a, e); break;
+        case 2: k_spmv_pw_e<2, KIND><<<eb, VT, 0, st>>>(a, e); break;
+        case 3: k_spmv_pw_e<3, KIND><<<eb, VT, 0, st>>>(a, e); break;
+        case 4: k_spmv_pw_e<4, KIND><<<eb, VT, 0, st>>>(a, e); break;
+        case 5: k_spmv_pw_e<5, KIND><<<eb, VT, 0, st>>>(a, e); break;
+        case 6: k_spmv_pw_e<6, KIND><<<eb, VT, 0, st>>>(a, e); break;
+        case 7: k_spmv_pw_e<7, KIND><<<eb, VT, 0, st>>>(a, e); break;
+        default: k_spmv_pw_e<8, KIND><<<eb, VT, 0, st>>>(a, e); break;
+    }
+}
+
+void launch_pair_e(const lpcg_system *s, const Args &a, hipStream_t st) {
+    const int p = s->two_level_p;
+    const int nbs = (s->n - p + VT - 1) / VT, nbp = (p + VT - 1) / VT;
+    const E2 e = e2_args(s);
+    switch (s->e2_ws) {
+        case 1: k_llt2e_suffix<1><<<nbs, VT, 0, st>>>(a, e); break;
+        case 2: k_llt2e_suffix<2><<<nbs, VT, 0, st>>>(a, e); break;
+        case 3: k_llt2e_suffix<3><<<nbs, VT, 0, st>>>(a, e); break;
+        case 4: k_llt2e_suffix<4><<<nbs, VT, 0, st>>>(a, e); break;
+        case 5: k_llt2e_suffix<5><<<nbs, VT, 0, st>>>(a, e); break;
+        case 6: k_llt2e_suffix<6><<<nbs, VT, 0, st>>>(a, e); break;
+        case 7: k_llt2e_suffix<7><<<nbs, VT, 0, st>>>(a, e); break;
+        default: k_llt2e_suffix<8><<<nbs, VT, 0, st>>>(a, e); break;
+    }
+    switch (s->e2_wp) {
+        case 0: k_llt2e_prefix<0><<<nbp, VT, 0, st>>>(a, e, nbs); break;
+        case 1: k_llt2e_prefix<1><<<nbp, VT, 0, st>>>(a, e, nbs); break;
+        case 2: k_llt2e_prefix<2><<<nbp, VT, 0, st>>>(a, e, nbs); break;
+        case 3: k_llt2e_prefix<3><<<nbp, VT, 0, st>>>(a, e, nbs); break;
+        case 4: k_llt2e_prefix<4><<<nbp, VT, 0, st>>>(a, e, nbs); break;
+        case 5: k_llt2e_prefix<5><<<nbp, VT, 0, st>>>(a, e, nbs); break;
+        case 6: k_llt2e_prefix<6><<<nbp, VT, 0, st>>>(a, e, nbs); break;
+        case 7: k_llt2e_prefix<7><<<nbp, VT, 0, st>>>(a, e, nbs); break;
+        default: k_llt2e_prefix<8><<<nbp, VT, 0, st>>>(a, e, nbs); break;
+    }
+}
+
+// Blocks of the PCG's product kernel in the form in force (enqueue_spmv).
+int product_grid(const lpcg_system *s) {
+    if (s->spmv_ell && s->ea_w > 0) return ell_blocks(s);
+    if (s->spmv_rows > 0) return (s->n + s->spmv_rows - 1) / s->spmv_rows;
+    return s->spmv_blocks;
+}
+
 // One iteration = the application z = P^-1 r (LLT only), the SpMV with the
 // new search direction and p.w, and the x, r update; enqueued in parts so
 // that the timing aid can bracket each.
 template <int KIND>
 int enqueue_apply(const lpcg_system *s, const Args &a, hipStream_t st) {
     if (KIND == LPCG_PC_LLT && e2_path(s)) {  // the x, r update rides along (k_xr is not launched)
-        const int p = s->two_level_p;
-        const int nbs = (s->n - p + VT - 1) / VT, nbp = (p + VT - 1) / VT;
-        const E2 e = e2_args(s);
-        if (s->e2_ws <= 4 && s->e2_wp <= 4) {
-            k_llt2e_suffix<4, true><<<nbs, VT, 0, st>>>(a, e);
-            k_llt2e_prefix<4, true><<<nbp, VT, 0, st>>>(a, e, nbs);
-        } else {
-            k_llt2e_suffix<8, true><<<nbs, VT, 0, st>>>(a, e);
-            k_llt2e_prefix<8, true><<<nbp, VT, 0, st>>>(a, e, nbs);
-        }
+        launch_pair_e(s, a, st);
     } else if (KIND == LPCG_PC_LLT && two_level_path(s)) {
         const int G = s->trsv_g, p = s->two_level_p;
         const int nbs = level_blocks(s->n - p, G), nbp = level_blocks(p, G);
@@ -1139,9 +1244,7 @@ int enqueue_apply(const lpcg_system *s, const Args &a, hipStream_t st) {
 template <int KIND>
 int enqueue_spmv(const lpcg_system *s, const Args &a, hipStream_t st) {
     if (s->spmv_ell && s->ea_w > 0) {
-        const int eb = ell_blocks(s);
-        if (s->ea_w <= 4) k_spmv_pw_e<4, KIND><<<eb, VT, 0, st>>>(a, ea_args(s));
-        else k_spmv_pw_e<8, KIND><<<eb, VT, 0, st>>>(a, ea_args(s));
+        launch_spmv_pw_e<KIND>(s, a, st);
         LPCG_LAUNCH_CHECK();
         return LPCG_OK;
     }
@@ -1277,6 +1380,10 @@ int build_args(lpcg_system *s, const lpcg_precond *P, const double *b, double *x
     a.reset_z = s->trsv[1].mode == 0 || s->trsv[1].mode == 3;
     if (e2_path(s)) {
         a.np_rz = (s->n - s->two_level_p + VT - 1) / VT + (s->two_level_p + VT - 1) / VT;
+        if (P->kind == LPCG_PC_LLT) {  // the pair reduces the product's p.w partials
+            a.defer = 1;
+            a.np_pw = product_grid(s);
+        }
     } else if (two_level_path(s)) {
         a.np_rz = level_blocks(s->n - s->two_level_p, s->trsv_g) + level_blocks(s->two_level_p, s->trsv_g);
     } else if (s->trsv[1].mode == 0) {
@@ -1430,8 +1537,7 @@ int time_pcg_product(lpcg_system *s, int G, int blocks, int R, int reps, double 
         e = hipEventRecord(e0, st);
         if (e != hipSuccess) break;
         if (G == 1) {
-            if (s->ea_w <= 4) k_spmv_pw_e<4, LPCG_PC_LLT><<<ell_blocks(s), VT, 0, st>>>(a, ea_args(s));
-            else k_spmv_pw_e<8, LPCG_PC_LLT><<<ell_blocks(s), VT, 0, st>>>(a, ea_args(s));
+            launch_spmv_pw_e<LPCG_PC_LLT>(s, a, st);
         } else if (R > 0) {
             switch (G) {
                 case 4: k_spmv_pw_st<4, LPCG_PC_LLT><<<nb, VT, lds, st>>>(a, R, s->spmv_win); break;

@@ -225,3 +225,25 @@ def test_pcg_color_fused_update():
     k = r1["iters"] + 1
     h1, h2 = host(h1)[:k], host(h2)[:k]
     assert np.all(np.abs(h1 - h2) <= 1e-3 * h2), np.max(np.abs(h1 - h2) / h2)
+
+
+def test_pcg_color_fused_breakdown():
+    """Red-black order, where the product's p.w is reduced by the next
+    application: a negative definite A (the factor of the SPD -A) breaks down
+    at the first product, as the oracle does, with the iteration counted and
+    x left at x0."""
+    A = matrices_small()["heat3d_13"]
+    b = np.random.default_rng(12).standard_normal(A.n)
+    S = gpu_system(A, None, 1)
+    l, ut, _ = lpcg.ic0(S)
+    neg = g.CSR(A.n, A.rowptr, A.colind, -A.val)
+    lpcg.update_values(S, cuda_f64(neg.val))
+    x, res = lpcg.pcg_solve(S, lpcg.PC_LLT, cuda_f64(b), l_val=l, ut_val=ut, tol=1e-8)
+    perm, _, _ = O.color_order(A)
+    Ap = O.permute_sym(A, perm)
+    pat = O.Pattern(Ap)
+    lref, _ = O.ic0(pat, Ap)
+    ref = O.pcg(O.permute_sym(neg, perm), b[perm], O.PC_LLT, pat, lref, tol=1e-8)
+    assert ref["status"] == O.BREAKDOWN
+    assert res["status"] == lpcg.EBREAKDOWN and res["iters"] == ref["iters"] == 1, (res, ref["iters"])
+    assert not np.any(host(x))
