@@ -18,20 +18,25 @@
 // computes the scalar the next kernel needs: runs are bit-reproducible, no
 // launch is spent on a reduction, and neither an arrival counter (device-scope
 // atomics on one address serialise) nor a cache-flushing fence is needed.
+// The product's p.w partials are plain stores instead, summed in the same
+// order by every block of the next launch (which needs alpha first), so the
+// product ends without a reducer.
 //
 // Kernels of one iteration (it = products A p so far):
 //   LLT:    fwd   y = L^-1 r                       (kern_sptrsv.h, either mode)
 //           bwd   z = L^-T y, r.z partials; reducer block: beta
 //   all:    spmv  p = z + beta p_prev (p double-buffered by the parity of
 //                 it), w = A p computed from z and p_prev on the fly, p.w
-//                 partials; reducer block: alpha, breakdown test, it += 1
-//           xr    x += alpha p, r -= alpha w, ||r||^2 (Jacobi/none: r.z)
-//                 partials, Jacobi's z = dinv r, presets of the
-//                 dependency-driven substitution; reducer block:
+//                 partials
+//           xr    alpha and the breakdown test from the p.w partials (every
+//                 block), x += alpha p, r -= alpha w, ||r||^2 (Jacobi/none:
+//                 r.z) partials, Jacobi's z = dinv r, presets of the
+//                 dependency-driven substitution; reducer block: it += 1,
 //                 convergence test (Jacobi/none: beta)
 // Jacobi writes z = dinv r where it updates r and no preconditioning reads r
 // as z, so an iteration is two launches; LLT adds the substitutions (two
-// launches in all for the two-level orderings, see k_llt2_*).
+// launches in all for the two-level orderings, see k_llt2_*; the ELL form of
+// that pair also performs the update: three launches, see k_llt2e_*).
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -53,10 +58,10 @@ constexpr int VT = kVecThreads;
 
 struct Args {
     int n, np_vec, np_rz, maxit, kind;
-    // defer: the product kernel publishes its p.w partials to part_pw (plain
-    // stores, np_pw slots) and computes no alpha; the fused red-black pair
-    // reduces them itself (see k_llt2e_*)
-    int defer, np_pw;
+    // the product kernel stores its p.w partials to part_pw (plain stores,
+    // np_pw slots); the next launch (k_xr, or the red-black pair) reduces
+    // them in every block and takes alpha
+    int np_pw;
     int backoff_f, backoff_b, stride_f, stride_b, reset_y, reset_z;
     const int *rp, *ci;
     const float *v32;
@@ -712,8 +717,8 @@ __global__ void __launch_bounds__(kWgThreads) k_llt_wg(Args a, int do_fwd, int d
     }
 }
 
-// p = z + beta p_prev, w = A p and p.w partials; the reducer block computes
-// alpha (breakdown when p.w <= 0 or non-finite) and counts the product.
+// p = z + beta p_prev, w = A p and p.w partials (reduced by the next launch,
+// which takes alpha and the breakdown test).
 // Each thread takes two rows at a time (row and row + one grid's rows) and
 // up to two entries of each per lane at once, so that its loads take three
 // memory round trips per pair: the done flag, the iteration state, both
@@ -809,25 +814,7 @@ __global__ void __launch_bounds__(VT) k_spmv_pw(Args a) {
         }
     }
     pw = block_sum<VT>(pw, lds);
-    if (a.defer) {  // the fused red-black pair reduces the partials (next launch)
-        if (threadIdx.x == 0) a.part_pw[blockIdx.x] = pw;
-        return;
-    }
-    if (threadIdx.x == 0) publish_partial(a.sp_pw, blockIdx.x, pw);
-    if (!is_reducer()) return;
-    const double pwt = reduce_published<VT>(a.sp_pw, gridDim.x, lds);
-    if (threadIdx.x == 0) {
-        const double rz = a.scal[S_RZ0];
-        a.ctrl[C_IT] = it + 1;
-        if (!(pwt > 0.0) || !isfinite(pwt) || !isfinite(rz)) {
-            a.ctrl[C_DONE] = 1;
-            a.ctrl[C_STATUS] = LPCG_EBREAKDOWN;
-            a.ctrl[C_ITERS] = it + 1;
-        } else {
-            a.scal[S_ALPHA] = rz / pwt;
-            if (a.coef && it + 1 <= a.maxit) a.coef[2 * (it + 1)] = rz / pwt;
-        }
-    }
+    if (threadIdx.x == 0) a.part_pw[blockIdx.x] = pw;  // reduced by the next launch (k_xr or the pair)
 }
 
 // ELL form of k_spmv_pw (A's slots and FP32 values, analysis-built): one
@@ -896,33 +883,15 @@ __global__ void __launch_bounds__(VT) k_spmv_pw_e(Args a, EA e) {
         }
     }
     pw = block_sum<VT>(pw, lds);
-    if (a.defer) {  // the fused red-black pair reduces the partials (next launch)
-        if (threadIdx.x == 0) a.part_pw[blockIdx.x] = pw;
-        return;
-    }
-    if (threadIdx.x == 0) publish_partial(a.sp_pw, blockIdx.x, pw);
-    if (!is_reducer()) return;
-    const double pwt = reduce_published<VT>(a.sp_pw, gridDim.x, lds);
-    if (threadIdx.x == 0) {
-        const double rz = a.scal[S_RZ0];
-        a.ctrl[C_IT] = it + 1;
-        if (!(pwt > 0.0) || !isfinite(pwt) || !isfinite(rz)) {
-            a.ctrl[C_DONE] = 1;
-            a.ctrl[C_STATUS] = LPCG_EBREAKDOWN;
-            a.ctrl[C_ITERS] = it + 1;
-        } else {
-            a.scal[S_ALPHA] = rz / pwt;
-            if (a.coef && it + 1 <= a.maxit) a.coef[2 * (it + 1)] = rz / pwt;
-        }
-    }
+    if (threadIdx.x == 0) a.part_pw[blockIdx.x] = pw;  // reduced by the next launch (k_xr or the pair)
 }
 
 // LDS-staged form of k_spmv_pw (kern_spmv.h): block b forms the new search
 // direction p_j = z_j + beta p_prev_j over its column window into LDS (each
 // input read once per block, in order), writes p and w = A p for its own rows
-// (the diagonal's p from its own inputs) and publishes p.w.  The arithmetic
-// per entry and the reduction are those of k_spmv_pw: p, w and p.w agree
-// bit for bit.
+// (the diagonal's p from its own inputs) and stores its p.w partial.  The
+// arithmetic per entry and the reduction are those of k_spmv_pw: p, w and
+// p.w agree bit for bit.
 template <int G, int KIND>
 __global__ void __launch_bounds__(VT) k_spmv_pw_st(Args a, int R, const int *__restrict__ win) {
     extern __shared__ float sp[];
@@ -964,25 +933,7 @@ __global__ void __launch_bounds__(VT) k_spmv_pw_st(Args a, int R, const int *__r
         }
     }
     pw = block_sum<VT>(pw, lds);
-    if (a.defer) {  // the fused red-black pair reduces the partials (next launch)
-        if (threadIdx.x == 0) a.part_pw[blockIdx.x] = pw;
-        return;
-    }
-    if (threadIdx.x == 0) publish_partial(a.sp_pw, blockIdx.x, pw);
-    if (!is_reducer()) return;
-    const double pwt = reduce_published<VT>(a.sp_pw, gridDim.x, lds);
-    if (threadIdx.x == 0) {
-        const double rz = a.scal[S_RZ0];
-        a.ctrl[C_IT] = it + 1;
-        if (!(pwt > 0.0) || !isfinite(pwt) || !isfinite(rz)) {
-            a.ctrl[C_DONE] = 1;
-            a.ctrl[C_STATUS] = LPCG_EBREAKDOWN;
-            a.ctrl[C_ITERS] = it + 1;
-        } else {
-            a.scal[S_ALPHA] = rz / pwt;
-            if (a.coef && it + 1 <= a.maxit) a.coef[2 * (it + 1)] = rz / pwt;
-        }
-    }
+    if (threadIdx.x == 0) a.part_pw[blockIdx.x] = pw;  // reduced by the next launch (k_xr or the pair)
 }
 
 // x += alpha p, r -= alpha w, ||r||^2 (Jacobi/none: r.z) partials, presets
@@ -998,15 +949,18 @@ __global__ void __launch_bounds__(VT) k_xr(Args a) {
     double *__restrict__ xr = a.x;
     float *__restrict__ rv = a.r;
     uint32_t *__restrict__ zb = a.z;
-    // the first element's w, r, x (and 1/diag) are loaded with the done flag
-    // and the iteration state, and so is p from both buffers (which one holds
-    // the current direction depends on the iteration): one memory round trip
+    // the first element's w, r, x (and 1/diag) are loaded with the done flag,
+    // the iteration state and the product's p.w partials, and so is p from
+    // both buffers (which one holds the current direction depends on the
+    // iteration): one memory round trip
     int i = blockIdx.x * VT + threadIdx.x;
     float wi = 0.f, ri0 = 0.f, di = 0.f, pa = 0.f, pb = 0.f;
     double xi = 0.0;
     const int flag = ld_ctrl(a.ctrl + C_DONE);
     int it = ld_ctrl(a.ctrl + C_IT);
-    const double alpha = ld_scal(a.scal + S_ALPHA);
+    const double rz_old = ld_scal(a.scal + S_RZ0);
+    double share[kPwShare];
+    pw_load(a, share);
     const float *__restrict__ p0 = a.p0;
     const float *__restrict__ p1 = a.p1;
     if (i < n) {
@@ -1019,8 +973,19 @@ __global__ void __launch_bounds__(VT) k_xr(Args a) {
     }
     if (done_now(flag)) return;
     it = lane_value(it);
+    const int k = it + 1;  // the product this update completes
+    double alpha;
+    if (!deferred_alpha(a, share, rz_old, lds, alpha)) {
+        if (is_reducer() && threadIdx.x == 0) {
+            a.ctrl[C_DONE] = 1;
+            a.ctrl[C_STATUS] = LPCG_EBREAKDOWN;
+            a.ctrl[C_ITERS] = k;
+            a.ctrl[C_IT] = k;
+        }
+        return;
+    }
     const float af = (float)alpha;
-    const bool odd = ((it - 1) & 1) != 0;
+    const bool odd = (it & 1) != 0;  // p_k is in the buffer of parity k - 1
     const float *__restrict__ pr = odd ? p1 : p0;
     float pi = odd ? pb : pa;
     double rr = 0, rzn = 0;
@@ -1054,15 +1019,16 @@ __global__ void __launch_bounds__(VT) k_xr(Args a) {
         if (KIND != LPCG_PC_LLT) publish_partial(a.sp_rz2, blockIdx.x, rzn);
     }
     if (!is_reducer()) return;
-    const double rrt = reduce_published<VT>(a.sp_rr, gridDim.x, lds);
-    const double rzt = KIND != LPCG_PC_LLT ? reduce_published<VT>(a.sp_rz2, gridDim.x, lds) : 0.0;
+    double rrt, rzt = 0.0;
+    if (KIND != LPCG_PC_LLT) reduce_published2<VT>(a.sp_rr, a.sp_rz2, gridDim.x, lds, rrt, rzt);
+    else rrt = reduce_published<VT>(a.sp_rr, gridDim.x, lds);
     if (threadIdx.x == 0) {
-        record_residual(a, rrt, it);
+        a.ctrl[C_IT] = k;
+        a.scal[S_ALPHA] = alpha;
+        if (a.coef && k <= a.maxit) a.coef[2 * k] = alpha;
+        record_residual(a, rrt, k);
         if (KIND != LPCG_PC_LLT) {
-            const double old = a.scal[S_RZ0];
-            a.scal[S_BETA] = rzt / old;
-            a.scal[S_RZ0] = rzt;
-            if (a.coef && it >= 1 && it <= a.maxit) a.coef[2 * it + 1] = rzt / old;
+            set_beta(a, rzt, k);
         } else {
             a.ctrl[C_TICKET_F] = 0;
             a.ctrl[C_TICKET_B] = 0;
@@ -1372,6 +1338,7 @@ int build_args(lpcg_system *s, const lpcg_precond *P, const double *b, double *x
     a.np_vec = s->vec_blocks;
     a.maxit = maxit > 0 ? maxit : s->n;
     a.kind = P->kind;
+    a.np_pw = product_grid(s);
     a.backoff_f = s->trsv[0].backoff;
     a.backoff_b = s->trsv[1].backoff;
     a.stride_f = s->trsv[0].stride;
@@ -1380,10 +1347,6 @@ int build_args(lpcg_system *s, const lpcg_precond *P, const double *b, double *x
     a.reset_z = s->trsv[1].mode == 0 || s->trsv[1].mode == 3;
     if (e2_path(s)) {
         a.np_rz = (s->n - s->two_level_p + VT - 1) / VT + (s->two_level_p + VT - 1) / VT;
-        if (P->kind == LPCG_PC_LLT) {  // the pair reduces the product's p.w partials
-            a.defer = 1;
-            a.np_pw = product_grid(s);
-        }
     } else if (two_level_path(s)) {
         a.np_rz = level_blocks(s->n - s->two_level_p, s->trsv_g) + level_blocks(s->two_level_p, s->trsv_g);
     } else if (s->trsv[1].mode == 0) {
@@ -1513,7 +1476,8 @@ int time_pcg_product(lpcg_system *s, int G, int blocks, int R, int reps, double 
     a.p0 = s->p;
     a.p1 = s->p2;
     a.w = s->w;
-    a.sp_pw = s->sync_part + s->npart;
+    a.part_pw = s->part + 2 * (size_t)s->npart;  // the kernel stores its p.w partials there
+    a.np_pw = product_grid(s);
     a.scal = s->scal;
     a.ctrl = s->ctrl;
     const int fb = (s->n + 255) / 256;
