@@ -317,7 +317,8 @@ int lpcg_blocked_schedule(int32_t n, const int32_t *rowptr, const int32_t *col, 
  * directions, which lets the PCG apply L L^T in two fused launches; where
  * the rows of both halves hold at most 8 entries that pair runs in an ELL
  * form that also performs the iteration's x, r update).  It then times the
- * PCG's product kernel (p = z + beta p_prev, w = A p, p.w; median of reps)
+ * PCG's product kernel (p = z + beta p_prev, w = A p, p.w; median of three
+ * batches of reps back-to-back launches)
  * for G = 4, 8, 16, 32, 64 lanes per row (64 / G rows per wavefront) on
  * grids of up to 512, 1024 and 2048 blocks, the LDS-staged form with 256,
  * 512 and 1024 rows per block at G = 4 and 8 (where the windows fit), and

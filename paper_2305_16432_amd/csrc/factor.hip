@@ -1133,7 +1133,7 @@ extern "C" int lpcg_autotune(lpcg_system *s, const float *l_val, const float *ut
     // SpMV: lanes per row G (64 / G rows per wavefront) and grid size, then
     // the LDS-staged form with R rows per block where the windows fit.  Each
     // candidate is timed as the PCG's product kernel (p = z + beta p_prev,
-    // w = A p and p.w, median of reps launches), which is where the choice
+    // w = A p and p.w; batches of reps back-to-back launches), which is where the choice
     // counts: the plain product ranks G = 4 and 8 within a few percent, the
     // PCG's form (two gathered vectors per entry) does not
     {

@@ -219,7 +219,8 @@ void blk_free(lpcg_system *s, int d);
 void drop_graphs(lpcg_system *s);
 // Pack A's FP32 values into the ELL form (no-op when not built).
 int ell_pack_a(const lpcg_system *s, hipStream_t st);
-// Median duration (us) of the PCG's product kernel for an SpMV candidate
+// Duration (us, median of batches of back-to-back launches) of the PCG's
+// product kernel for an SpMV candidate
 // (pcg.hip; overwrites the solver's work vectors and control words).
 int time_pcg_product(lpcg_system *s, int G, int blocks, int R, int reps, double &us, hipStream_t st);
 }  // namespace lpcg

@@ -1440,7 +1440,7 @@ int build_args(lpcg_system *s, const lpcg_precond *P, const double *b, double *x
     return LPCG_OK;
 }
 
-// State of one timed product launch: not done, iteration 1 (so the kernel
+// State of the timed product launches: not done, iteration 1 (so the kernel
 // takes p = z + beta p_prev with the gathers of both), beta = 1/2.
 __global__ void k_product_state(Args a) {
     if (threadIdx.x == 0) {
@@ -1453,13 +1453,14 @@ __global__ void k_product_state(Args a) {
 
 }  // namespace
 
-// Median duration of the PCG's product kernel (p = z + beta p_prev, w = A p,
-// p.w; the reducer's alpha) with G lanes per row on `blocks` blocks, or
-// LDS-staged with R > 0 rows per block (windows prepared for R), or in the
-// ELL form for G = 1 (built with the pattern), over reps
-// launches after one warm-up.  Runs on the system's work vectors with
-// z = p_prev = 1 and A's FP32 values; overwrites z, both search directions,
-// w and the control words.  The autotuner ranks its SpMV candidates with it.
+// Duration of the PCG's product kernel (p = z + beta p_prev, w = A p and the
+// p.w partials) with G lanes per row on `blocks` blocks, or LDS-staged with
+// R > 0 rows per block (windows prepared for R), or in the ELL form for
+// G = 1 (built with the pattern): the median over three batches of reps
+// back-to-back launches, after a warm-up batch.  Runs on the system's work
+// vectors with z = p_prev = 1 and A's FP32 values; overwrites z, both search
+// directions, w and the control words.  The autotuner ranks its SpMV
+// candidates with it.
 int time_pcg_product(lpcg_system *s, int G, int blocks, int R, int reps, double &us, hipStream_t st) {
     if (G == 1 && s->ea_w == 0) {
         set_error("SpMV: no ELL form for this pattern");
@@ -1494,12 +1495,14 @@ int time_pcg_product(lpcg_system *s, int G, int blocks, int R, int reps, double 
     }
     const size_t lds = sizeof(float) * (size_t)std::max(1, s->spmv_wmax);
     const int nb = R > 0 ? (s->n + R - 1) / R : blocks;
-    std::vector<float> t;
-    hipError_t e = hipSuccess;
-    for (int r = 0; r <= reps && e == hipSuccess; ++r) {
-        k_product_state<<<1, 64, 0, st>>>(a);
-        e = hipEventRecord(e0, st);
-        if (e != hipSuccess) break;
+    // The product no longer changes its own control state (its p.w partials
+    // are reduced by the next launch), so after one state preset the
+    // candidate is launched back to back: `reps` launches between two events
+    // per batch, and the median over three batches after a warm-up one.  A
+    // profiler's per-launch cost then adds alike to every candidate instead
+    // of swamping one launch's time.
+    k_product_state<<<1, 64, 0, st>>>(a);
+    auto launch = [&]() {
         if (G == 1) {
             launch_spmv_pw_e<LPCG_PC_LLT>(s, a, st);
         } else if (R > 0) {
@@ -1519,11 +1522,17 @@ int time_pcg_product(lpcg_system *s, int G, int blocks, int R, int reps, double 
                 default: k_spmv_pw<64, LPCG_PC_LLT><<<nb, VT, 0, st>>>(a); break;
             }
         }
+    };
+    std::vector<float> t;
+    hipError_t e = hipGetLastError();
+    for (int batch = 0; batch <= 3 && e == hipSuccess; ++batch) {
+        if ((e = hipEventRecord(e0, st)) != hipSuccess) break;
+        for (int r = 0; r < reps; ++r) launch();
         if ((e = hipGetLastError()) != hipSuccess) break;
         if ((e = hipEventRecord(e1, st)) != hipSuccess || (e = hipEventSynchronize(e1)) != hipSuccess) break;
         float ms = 0;
         if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
-        if (r > 0) t.push_back(ms);
+        if (batch > 0) t.push_back(ms / reps);
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
