@@ -200,10 +200,10 @@ struct PackPlan {
     PackUnit u[7 * kFusedMaxMp + kPkGlob];
 };
 
-// Block b writes unit b of the plan, four values per thread, loads first.
-__global__ void __launch_bounds__(256) k_pack_weights(const float *__restrict__ P, PackPlan plan,
-                                                      __bf16 *__restrict__ wpack) {
-    const PackUnit pu = plan.u[blockIdx.x];
+// Unit `unit` of the plan, four values per thread (of 256), loads first.
+__device__ __forceinline__ void pack_unit(const float *__restrict__ P, const PackPlan &plan, int unit,
+                                          __bf16 *__restrict__ wpack) {
+    const PackUnit pu = plan.u[unit];
     const int S = pu.K / 16;
     float v[4];
 #pragma unroll
@@ -219,6 +219,12 @@ __global__ void __launch_bounds__(256) k_pack_weights(const float *__restrict__ 
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) wpack[pu.dst + pu.base + r * 256 + threadIdx.x] = (__bf16)v[r];
+}
+
+// Block b writes unit b of the plan.
+__global__ void __launch_bounds__(256) k_pack_weights(const float *__restrict__ P, PackPlan plan,
+                                                      __bf16 *__restrict__ wpack) {
+    pack_unit(P, plan, blockIdx.x, wpack);
 }
 
 // Units of the packed weights for n_mp layers (latent width 32).
@@ -243,13 +249,12 @@ int pack_plan(const GnnOff &o, int n_mp, PackPlan &plan) {
     return nu;
 }
 
-// Normalisation sums, stage 1: block (x, y) sums diag(A) and b^2 over
-// segment x (kNormRows rows) of system y; empty segments write zeros.
-__global__ void k_gnn_norm_part(int nseg, const int *__restrict__ sys_rowptr, const int *__restrict__ dpos,
-                                const double *__restrict__ val, const double *__restrict__ b,
-                                double *__restrict__ part) {
+// Normalisation sums, stage 1: segment sg (kNormRows rows) of system sy sums
+// diag(A) and b^2; empty segments write zeros.
+__device__ __forceinline__ void norm_part(int nseg, int sy, int sg, const int *__restrict__ sys_rowptr,
+                                          const int *__restrict__ dpos, const double *__restrict__ val,
+                                          const double *__restrict__ b, double *__restrict__ part) {
     __shared__ double lds[kGnnThreads / kWave];
-    const int sy = blockIdx.y, sg = blockIdx.x;
     const int r0 = sys_rowptr[sy] + sg * kNormRows;
     const int r1 = min(sys_rowptr[sy + 1], r0 + kNormRows);
     // the thread's rows r0 + threadIdx.x + u * kGnnThreads, summed in that
@@ -279,6 +284,29 @@ __global__ void k_gnn_norm_part(int nseg, const int *__restrict__ sys_rowptr, co
     }
 }
 
+// Block (x, y): segment x of system y.
+__global__ void k_gnn_norm_part(int nseg, const int *__restrict__ sys_rowptr, const int *__restrict__ dpos,
+                                const double *__restrict__ val, const double *__restrict__ b,
+                                double *__restrict__ part) {
+    norm_part(nseg, blockIdx.y, blockIdx.x, sys_rowptr, dpos, val, b, part);
+}
+
+// The fused inference pass's first launch: blocks (x, y < nsys) the
+// normalisation sums, blocks (x < nu, nsys) the weight packing (the two are
+// independent, and one launch saves one launch latency).
+__global__ void __launch_bounds__(kGnnThreads) k_norm_pack(int nsys, int nseg, const int *__restrict__ sys_rowptr,
+                                                           const int *__restrict__ dpos,
+                                                           const double *__restrict__ val,
+                                                           const double *__restrict__ b, double *__restrict__ part,
+                                                           const float *__restrict__ P, PackPlan plan, int nu,
+                                                           __bf16 *__restrict__ wpack) {
+    if ((int)blockIdx.y < nsys) {
+        if ((int)blockIdx.x < nseg) norm_part(nseg, blockIdx.y, blockIdx.x, sys_rowptr, dpos, val, b, part);
+    } else if ((int)blockIdx.x < nu) {
+        pack_unit(P, plan, blockIdx.x, wpack);
+    }
+}
+
 // Stage 2: per system, s = mean(diag A) and rms(b) (1 if b = 0), summing the
 // segments in order (deterministic).
 __global__ void k_gnn_norm_fin(int nsys, int nseg, const int *__restrict__ sys_rowptr,
@@ -297,6 +325,15 @@ __global__ void k_gnn_norm_fin(int nsys, int nseg, const int *__restrict__ sys_r
     sys_rms[sy] = rms > 0 ? rms : 1.0;
 }
 
+// Normalisation finished inside the node encoder (a single system): the
+// stage-1 partials of its nseg segments over cnt rows; block 0 stores s and
+// rms for the later launches.  part = nullptr: the scale comes from sys_scale.
+struct NormIn {
+    const double *part;
+    int nseg, cnt;
+    double *s_out, *rms_out;
+};
+
 // Encoder: out[row] = relu(x W0 + b0) W1 + b1 with scalar input x.
 template <int H, bool NODE>
 __global__ void __launch_bounds__(kGnnThreads) k_enc(int rows, const float *__restrict__ P, MlpOff m,
@@ -305,11 +342,28 @@ __global__ void __launch_bounds__(kGnnThreads) k_enc(int rows, const float *__re
                                                      const int *__restrict__ row_sys,
                                                      const double *__restrict__ sys_scale,
                                                      __bf16 *__restrict__ out, float *__restrict__ xs_out,
-                                                     const __bf16 *__restrict__ w1p) {
+                                                     const __bf16 *__restrict__ w1p, NormIn nin = NormIn{}) {
     constexpr int S = H / 16, MT = H / 32;
     __shared__ __align__(16) __bf16 w1[H * H];
+    __shared__ double nlds[kGnnThreads / kWave];
     if (w1p) lds_copy<H * H>(w1, w1p);  // packed (the fused inference pass)
     else stage_weights<false>(w1, P + m.W1, H, H, H);
+    double own_scale = 1.0;
+    if (nin.part) {  // every block alike: s = mean(diag A), rms(b) (1 if b = 0)
+        double sd = 0.0, sb = 0.0;
+        for (int g = threadIdx.x; g < nin.nseg; g += kGnnThreads) {
+            sd += nin.part[2 * g];
+            sb += nin.part[2 * g + 1];
+        }
+        sd = block_sum<kGnnThreads>(sd, nlds);
+        sb = block_sum<kGnnThreads>(sb, nlds);
+        const double rms = sqrt(sb / nin.cnt);
+        own_scale = rms > 0 ? rms : 1.0;
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            nin.s_out[0] = sd / nin.cnt;
+            nin.rms_out[0] = own_scale;
+        }
+    }
     __syncthreads();
     const int lane = lane_id();
     const float *W0 = P + m.W0, *b0 = P + m.b0, *b1 = P + m.b1;
@@ -320,7 +374,7 @@ __global__ void __launch_bounds__(kGnnThreads) k_enc(int rows, const float *__re
         float x = 0.f;
         if (valid) {
             const int node = NODE ? r : erow[r];
-            x = (float)(xin[r] / sys_scale[row_sys[node]]);
+            x = (float)(xin[r] / (nin.part ? own_scale : sys_scale[row_sys[node]]));
         }
         f32x16 acc[MT];
 #pragma unroll
@@ -867,10 +921,31 @@ __device__ __forceinline__ double complete_radicand(int i, const int *__restrict
                                                     const float *__restrict__ d) {
     const int a = rowptr[i], cnt = lrowptr[i + 1] - lrowptr[i] - 1;
     double ssq = 0.0;
-    for (int q = 0; q < cnt; ++q) {
-        const int k = a + q;
-        const float l = (float)sqrt(diag64[col[k]]) * (0.5f * (d[k] + d[rev[k]]));
-        ssq += (double)l * (double)l;
+    // four entries at a time, all their loads issued before the first use
+    // (past the row's strict entries the loads repeat entry a and the terms
+    // are left out); the terms are summed in entry order
+    for (int q0 = 0; q0 < cnt; q0 += 4) {
+        int c[4], rv[4];
+        float dk[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int k = a + (q0 + u < cnt ? q0 + u : 0);
+            c[u] = col[k];
+            rv[u] = rev[k];
+            dk[u] = d[k];
+        }
+        double dg[4];
+        float dr[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            dg[u] = diag64[c[u]];
+            dr[u] = d[rv[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const float l = (float)sqrt(dg[u]) * (0.5f * (dk[u] + dr[u]));
+            if (q0 + u < cnt) ssq += (double)l * (double)l;
+        }
     }
     return diag64[i] - ssq;
 }
@@ -1012,16 +1087,20 @@ int forward_impl(const lpcg_system *s, const lpcg_gnn *net, const double *b, uns
     const GnnOff o = gnn_offsets(H, net->n_mp, net->x_head != 0);
     const float *P = net->params;
     double *sys_s = (double *)(ws + L.sys_s), *sys_rms = (double *)(ws + L.sys_rms);
-    {
-        const int nseg = norm_segments(s);
-        double *part = (double *)(ws + L.norm_part);
+    const bool fused = gnn_fused(s, H, net->n_mp, train);  // per-layer projections kept
+    const int nseg = norm_segments(s);
+    double *npart = (double *)(ws + L.norm_part);
+    // the fused pass (width 32) launches the normalisation sums with the
+    // weight packing, and a single system's node encoder finishes them
+    const bool fused32 = H == 32 && fused;
+    const bool enc_norm = fused32 && s->nsys == 1;
+    if (!enc_norm) {
         k_gnn_norm_part<<<dim3(nseg, s->nsys), kGnnThreads, 0, st>>>(nseg, s->sys_rowptr, s->dpos, s->val64, b,
-                                                                     part);
-        k_gnn_norm_fin<<<nblk(s->nsys, 64), 64, 0, st>>>(s->nsys, nseg, s->sys_rowptr, part, sys_s, sys_rms);
+                                                                     npart);
+        k_gnn_norm_fin<<<nblk(s->nsys, 64), 64, 0, st>>>(s->nsys, nseg, s->sys_rowptr, npart, sys_s, sys_rms);
     }
     auto V = [&](int t) { return (__bf16 *)(ws + L.V[train ? t : (t & 1)]); };
     auto E = [&](int t) { return (__bf16 *)(ws + L.E[train ? t : (t & 1)]); };
-    const bool fused = gnn_fused(s, H, net->n_mp, train);  // per-layer projections kept
     auto Pa = [&](int t) { return (__bf16 *)(ws + L.Pa[train || fused ? t : 0]); };
     auto Pb = [&](int t) { return (__bf16 *)(ws + L.Pb[train || fused ? t : 0]); };
     float *d = (float *)(ws + L.d);
@@ -1031,11 +1110,17 @@ int forward_impl(const lpcg_system *s, const lpcg_gnn *net, const double *b, uns
         {
             PackPlan plan{};
             const int nu = pack_plan(o, T, plan);
-            k_pack_weights<<<nu, 256, 0, st>>>(P, plan, wpack);
+            if (enc_norm) {
+                k_norm_pack<<<dim3(std::max(nseg, nu), 2), kGnnThreads, 0, st>>>(
+                    1, nseg, s->sys_rowptr, s->dpos, s->val64, b, npart, P, plan, nu, wpack);
+            } else {
+                k_pack_weights<<<nu, 256, 0, st>>>(P, plan, wpack);
+            }
         }
+        const NormIn nin = enc_norm ? NormIn{npart, nseg, s->n, sys_s, sys_rms} : NormIn{};
         k_enc<H, true><<<gnn_blocks(s->n), kGnnThreads, 0, st>>>(s->n, P, o.node_enc, b, s->erow, s->row_sys,
                                                                   sys_rms, V(0), nullptr,
-                                                                  wpack + pk_glob(T, kPkEncN));
+                                                                  wpack + pk_glob(T, kPkEncN), nin);
         __bf16 *M = (__bf16 *)(ws + L.M);
         float *ahat = (float *)(ws + L.Ahat);
         FusedChain ch{};
