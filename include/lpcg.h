@@ -364,7 +364,11 @@ typedef struct {
 typedef struct {
     double tol;            /* stop when ||r_k||_2 <= tol * ||b||_2 */
     int32_t maxit;         /* iteration cap (<= 0: n) */
-    int32_t check_every;   /* iterations per host check of the done flag (<= 0: 8) */
+    int32_t check_every;   /* iterations per host check of the done flag; <= 0:
+                              lpcg_pcg_solve without a graph sizes each chunk
+                              from the recorded residual's decay, extrapolated
+                              to tol (8 for the first chunk, for graphs and for
+                              the batched solver) */
     int32_t max_restarts;  /* restarts from the FP64 true residual when the
                               recursive residual converged but the true one
                               did not (<= 0: none) */

@@ -40,6 +40,9 @@ enum Ctrl : int {
     C_MAXIT = 7,
     C_NDONE = 8,     // batched solve: systems finished
     C_PHASE = 9,     // fused red-black path: 0 before the solve's first application, 1 after
+    C_RES = 10,      // ||r||^2 / ||b||^2 of the last recorded iteration (FP32 bits), for the host
+    C_RES_IT = 11,   // the iteration C_RES belongs to
+    C_RES0 = 12,     // ||r0||^2 / ||b||^2 (FP32 bits)
     C_NCTRL = 16
 };
 enum Scal : int {

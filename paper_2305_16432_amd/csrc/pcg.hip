@@ -135,6 +135,8 @@ __device__ __forceinline__ void record_residual(const Args &a, double rr, int it
     const bool bad = !isfinite(rr);
     if (a.hist && it <= a.maxit) a.hist[it] = sqrt(rr / bb);
     a.scal[S_RR] = rr;
+    a.ctrl[C_RES] = __float_as_int((float)(rr / bb));
+    a.ctrl[C_RES_IT] = it;
     if (conv || cap || bad) {
         a.ctrl[C_DONE] = 1;
         a.ctrl[C_STATUS] = conv ? LPCG_OK : bad ? LPCG_EBREAKDOWN : LPCG_ENOTCONV;
@@ -196,6 +198,9 @@ __global__ void __launch_bounds__(VT) k_setup_scal(Args a) {
         a.ctrl[C_TICKET_F] = 0;
         a.ctrl[C_TICKET_B] = 0;
         a.ctrl[C_STATUS] = LPCG_OK;
+        a.ctrl[C_RES0] = __float_as_int((float)(rr / bb));
+        a.ctrl[C_RES] = a.ctrl[C_RES0];
+        a.ctrl[C_RES_IT] = 0;
         const bool conv = !(rr > a.tol2 * bb);
         a.ctrl[C_DONE] = conv ? 1 : 0;
         if (a.hist) a.hist[0] = sqrt(rr / bb);
@@ -1254,14 +1259,60 @@ int enqueue_iteration(const lpcg_system *s, const Args &a, hipStream_t st) {
     return enqueue_xr<KIND>(s, a, st);
 }
 
+// Iterations to launch before the next look at the done flag, when the
+// caller fixed no interval.  The recorded relative residual (squared) decays
+// about geometrically in PCG, so its decay rate over the iterations since the
+// previous look is extrapolated to the tolerance.  The extrapolation spans at
+// most four times the iterations it was measured over and stops past the
+// iteration cap; without a decay to measure it is kChunk0.  Every look costs
+// a host round trip and every iteration launched after convergence the
+// launches of an iteration, so both errors cost about the same.
+constexpr int kChunk0 = 8;
+
+struct ChunkPlan {
+    int prev_it = 0;
+    float prev_res = -1.0f;  // read from C_RES0 at the first look
+    double rate = 0;         // last measured d log(res) / d iteration (< 0: decaying)
+};
+
+int next_chunk(const int *ctrl, double tol2, int maxit, ChunkPlan &c) {
+    if (c.prev_res < 0.0f) memcpy(&c.prev_res, &ctrl[C_RES0], sizeof(float));
+    const int it = ctrl[C_RES_IT];
+    float res;
+    memcpy(&res, &ctrl[C_RES], sizeof(float));
+    const int span = it - c.prev_it;
+    const float res_prev = c.prev_res;
+    c.prev_it = it;
+    c.prev_res = res;
+    if (span <= 0 || !(res > 0.0f) || !(res_prev > 0.0f) || !std::isfinite(res)) return kChunk0;
+    const double rate = (std::log((double)res) - std::log((double)res_prev)) / span;
+    if (!(rate < -1e-6)) return kChunk0;
+    c.rate = rate;
+    const double cap = std::min(4.0 * span, (double)std::max(1, maxit - it + 1));
+    const double need = tol2 > 0 ? std::ceil((std::log(tol2) - std::log((double)res)) / rate) : cap;
+    return (int)std::max(1.0, std::min(need, cap));
+}
+
+// First chunk of a restart from the FP64 true residual (relative, squared:
+// res0): the previous attempt's decay rate extrapolated from res0, at most
+// kChunk0.
+int restart_chunk(double res0, double tol2, double rate) {
+    if (!(rate < 0) || !(res0 > 0) || !(tol2 > 0) || !std::isfinite(res0)) return kChunk0;
+    const double need = std::ceil((std::log(tol2) - std::log(res0)) / rate);
+    return (int)std::max(1.0, std::min(need, (double)kChunk0));
+}
+
 template <int KIND>
-int run_solve(lpcg_system *s, const Args &a, const lpcg_solve_opts &o, int &iters_total,
-              int &status, double &rr_out, hipStream_t st) {
+int run_solve(lpcg_system *s, const Args &a, const lpcg_solve_opts &o, int first_chunk, int &iters_total,
+              int &status, double &rate, hipStream_t st) {
     const int vb = s->vec_blocks;
     k_setup<KIND><<<vb, VT, 0, st>>>(a);
     k_setup_scal<KIND><<<1, VT, 0, st>>>(a);
     LPCG_LAUNCH_CHECK();
-    const int chunk = o.check_every > 0 ? o.check_every : 8;
+    const bool adaptive = o.check_every <= 0 && !o.use_graph;
+    // the fused red-black path records iteration k in the launches of k + 1
+    const int lag = KIND == LPCG_PC_LLT && e2_path(s) ? 1 : 0;
+    int chunk = o.check_every > 0 ? o.check_every : adaptive ? first_chunk + lag : kChunk0;
     hipGraphExec_t exec = nullptr;
     if (o.use_graph) {
         // key: kernel arguments + preconditioner kind + chunk length
@@ -1301,7 +1352,9 @@ int run_solve(lpcg_system *s, const Args &a, const lpcg_solve_opts &o, int &iter
         }
     }
     int rc = LPCG_OK;
-    for (int guard = 0;; ++guard) {
+    long launched = 0;
+    ChunkPlan plan;
+    for (;;) {
         if (exec) {
             hipError_t e = hipGraphLaunch(exec, st);
             if (e != hipSuccess) { rc = hip_fail(e, "hipGraphLaunch", __FILE__, __LINE__); break; }
@@ -1309,22 +1362,24 @@ int run_solve(lpcg_system *s, const Args &a, const lpcg_solve_opts &o, int &iter
             for (int c = 0; c < chunk && rc == LPCG_OK; ++c) rc = enqueue_iteration<KIND>(s, a, st);
             if (rc != LPCG_OK) break;
         }
+        launched += chunk;
         hipError_t e = hipMemcpyAsync(s->h_ctrl, s->ctrl, sizeof(int) * C_NCTRL, hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
         if (e != hipSuccess) { rc = hip_fail(e, "pcg control readback", __FILE__, __LINE__); break; }
         if (s->h_ctrl[C_DONE]) break;
-        if (guard > a.maxit / std::max(1, chunk) + 4) {
+        // the device stops at maxit (plus the one-iteration lag of the fused
+        // red-black update), so this only trips on a kernel that never set the flag
+        if (launched > (long)a.maxit + 4L * std::max(chunk, kChunk0) + 8) {
             set_error("pcg: done flag never set");
             rc = LPCG_EHIP;
             break;
         }
+        if (adaptive) chunk = next_chunk(s->h_ctrl, a.tol2, a.maxit, plan);
     }
     if (rc != LPCG_OK) return rc;
-    LPCG_HIP(hipMemcpyAsync(s->h_scal, s->scal, sizeof(double) * S_NSCAL, hipMemcpyDeviceToHost, st));
-    LPCG_HIP(hipStreamSynchronize(st));
+    if (plan.rate < 0) rate = plan.rate;
     iters_total += s->h_ctrl[C_ITERS];
     status = s->h_ctrl[C_STATUS];
-    rr_out = s->h_scal[S_RR] / s->h_scal[S_BB];
     return LPCG_OK;
 }
 
@@ -1572,26 +1627,29 @@ extern "C" int lpcg_pcg_solve(lpcg_system *s, const lpcg_precond *P, const doubl
     res->status = LPCG_OK;
     int iters = 0, status = LPCG_OK;
     const int maxit0 = a.maxit;
-    double rr = 0;
+    int first = kChunk0;
+    double rate = 0;
     for (int attempt = 0;; ++attempt) {
         int rc;
-        if (P->kind == LPCG_PC_LLT) rc = run_solve<LPCG_PC_LLT>(s, a, *opts, iters, status, rr, st);
-        else if (P->kind == LPCG_PC_JACOBI) rc = run_solve<LPCG_PC_JACOBI>(s, a, *opts, iters, status, rr, st);
-        else rc = run_solve<LPCG_PC_NONE>(s, a, *opts, iters, status, rr, st);
+        if (P->kind == LPCG_PC_LLT) rc = run_solve<LPCG_PC_LLT>(s, a, *opts, first, iters, status, rate, st);
+        else if (P->kind == LPCG_PC_JACOBI)
+            rc = run_solve<LPCG_PC_JACOBI>(s, a, *opts, first, iters, status, rate, st);
+        else rc = run_solve<LPCG_PC_NONE>(s, a, *opts, first, iters, status, rate, st);
         if (rc != LPCG_OK) return rc;
-        // FP64 true residual
+        // FP64 true residual; the same readback brings the recursive ||r||^2
         k_true_res<<<s->vec_blocks, VT, 0, st>>>(a);
         k_true_fin<<<1, VT, 0, st>>>(a);
         LPCG_LAUNCH_CHECK();
         LPCG_HIP(hipMemcpyAsync(s->h_scal, s->scal, sizeof(double) * S_NSCAL, hipMemcpyDeviceToHost, st));
         LPCG_HIP(hipStreamSynchronize(st));
         const double truerel = sqrt(s->h_scal[S_TRUE] / s->h_scal[S_BB]);
-        res->relres_rec = sqrt(rr);
+        res->relres_rec = sqrt(s->h_scal[S_RR] / s->h_scal[S_BB]);
         res->relres_true = truerel;
         if (status == LPCG_OK && truerel > opts->tol && attempt < opts->max_restarts &&
             iters < maxit0) {
             res->restarts = attempt + 1;
             a.maxit = std::max(1, maxit0 - iters);
+            first = restart_chunk(truerel * truerel, a.tol2, rate);
             continue;
         }
         break;

@@ -347,7 +347,7 @@ def jacobi(sys: System, out=None):
 
 # ---------------------------------------------------------------------- PCG
 def pcg_solve(sys: System, kind: int, b, x=None, l_val=None, ut_val=None, dinv=None,
-              tol=1e-6, maxit=0, check_every=8, max_restarts=0, use_graph=False,
+              tol=1e-6, maxit=0, check_every=0, max_restarts=0, use_graph=False,
               hist=False, raise_on_status=False, coef=None):
     """Returns (x, result dict[, hist tensor]).  coef: optional device FP64
     tensor of 2 (maxit + 1) entries that receives alpha_k / beta_k."""

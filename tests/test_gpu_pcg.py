@@ -247,3 +247,35 @@ def test_pcg_color_fused_breakdown():
     assert ref["status"] == O.BREAKDOWN
     assert res["status"] == lpcg.EBREAKDOWN and res["iters"] == ref["iters"] == 1, (res, ref["iters"])
     assert not np.any(host(x))
+
+
+@pytest.mark.parametrize("case", ["natural_ic0", "color_ic0", "jacobi"])
+def test_pcg_adaptive_chunks_equal_fixed(case):
+    """When the host looks at the done flag changes nothing on the device:
+    chunks sized from the residual's decay (check_every = 0), fixed chunks of
+    8 and of 1, and graph replay give the same iterate bit for bit, the same
+    iteration count, status and residual history; also when the cap ends the
+    solve (tol = 0) and with a cap below the first chunk."""
+    print(f"[pcg] adaptive chunks {case}", flush=True)
+    A = matrices_small()["heat3d_13"]
+    b = np.random.default_rng(21).standard_normal(A.n)
+    S = gpu_system(A, None, 1 if case == "color_ic0" else 0)
+    if case == "jacobi":
+        kind, kw = lpcg.PC_JACOBI, {}
+    else:
+        l, ut, _ = lpcg.ic0(S)
+        kind, kw = lpcg.PC_LLT, dict(l_val=l, ut_val=ut)
+    for tol, maxit, status in ((1e-8, 0, lpcg.OK), (0.0, 23, lpcg.ENOTCONV), (1e-12, 3, lpcg.ENOTCONV)):
+        outs = []
+        for check_every, use_graph in ((0, False), (8, False), (1, False), (5, True)):
+            x, res, h = lpcg.pcg_solve(S, kind, cuda_f64(b), tol=tol, maxit=maxit, check_every=check_every,
+                                       use_graph=use_graph, hist=True, **kw)
+            torch.cuda.synchronize()
+            outs.append((host(x), res["iters"], res["status"], host(h)))
+        assert outs[0][2] == status, (tol, maxit, outs[0][1:3])
+        if maxit:
+            assert outs[0][1] == maxit
+        for x, it, st, h in outs[1:]:
+            assert (it, st) == outs[0][1:3], (tol, maxit, it, st, outs[0][1:3])
+            assert np.array_equal(x, outs[0][0])
+            assert np.array_equal(h, outs[0][3], equal_nan=True)
