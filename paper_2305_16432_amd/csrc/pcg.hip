@@ -1041,7 +1041,9 @@ __global__ void __launch_bounds__(VT) k_xr(Args a) {
     }
 }
 
-// FP64 true residual partials ||b - A x||^2 (FP64 values).
+// FP64 true residual partials ||b - A x||^2 (FP64 values), in the setup's
+// ||b||^2 slots, which nothing reads during the iteration: the host may append
+// these two kernels to a chunk that is still running.
 __global__ void __launch_bounds__(VT) k_true_res(Args a) {
     __shared__ double lds[VT / kWave];
     double rr = 0;
@@ -1052,12 +1054,12 @@ __global__ void __launch_bounds__(VT) k_true_res(Args a) {
         rr += ri * ri;
     }
     rr = block_sum<VT>(rr, lds);
-    if (threadIdx.x == 0) a.part_pw[blockIdx.x] = rr;
+    if (threadIdx.x == 0) a.part_bb[blockIdx.x] = rr;
 }
 
 __global__ void __launch_bounds__(VT) k_true_fin(Args a) {
     __shared__ double lds[VT / kWave];
-    const double rr = reduce_partials<VT>(a.part_pw, a.np_vec, lds);
+    const double rr = reduce_partials<VT>(a.part_bb, a.np_vec, lds);
     if (threadIdx.x == 0) a.scal[S_TRUE] = rr;
 }
 
@@ -1266,8 +1268,14 @@ int enqueue_iteration(const lpcg_system *s, const Args &a, hipStream_t st) {
 // most four times the iterations it was measured over and stops past the
 // iteration cap; without a decay to measure it is kChunk0.  Every look costs
 // a host round trip and every iteration launched after convergence the
-// launches of an iteration, so both errors cost about the same.
+// launches of an iteration, so both errors cost about the same.  The decay
+// quickens late in a solve (CG's superlinear phase), which a rate measured
+// earlier misses, so the extrapolation is shortened by kLate: on recorded
+// histories of red-black IC(0) and Jacobi solves at 64^3 (tolerances 1e-2,
+// 1e-6, 1e-10) 0.85 gave 3-4 looks and at most 6 iterations past convergence,
+// 1.0 up to 18.
 constexpr int kChunk0 = 8;
+constexpr double kLate = 0.85;
 
 struct ChunkPlan {
     int prev_it = 0;
@@ -1275,7 +1283,8 @@ struct ChunkPlan {
     double rate = 0;         // last measured d log(res) / d iteration (< 0: decaying)
 };
 
-int next_chunk(const int *ctrl, double tol2, int maxit, ChunkPlan &c) {
+int next_chunk(const int *ctrl, double tol2, int maxit, ChunkPlan &c, bool &fin) {
+    fin = false;
     if (c.prev_res < 0.0f) memcpy(&c.prev_res, &ctrl[C_RES0], sizeof(float));
     const int it = ctrl[C_RES_IT];
     float res;
@@ -1289,22 +1298,27 @@ int next_chunk(const int *ctrl, double tol2, int maxit, ChunkPlan &c) {
     if (!(rate < -1e-6)) return kChunk0;
     c.rate = rate;
     const double cap = std::min(4.0 * span, (double)std::max(1, maxit - it + 1));
-    const double need = tol2 > 0 ? std::ceil((std::log(tol2) - std::log((double)res)) / rate) : cap;
+    const double need = tol2 > 0 ? std::ceil(kLate * (std::log(tol2) - std::log((double)res)) / rate) : cap;
+    fin = tol2 > 0 && need <= cap;
     return (int)std::max(1.0, std::min(need, cap));
 }
 
 // First chunk of a restart from the FP64 true residual (relative, squared:
 // res0): the previous attempt's decay rate extrapolated from res0, at most
-// kChunk0.
+// kChunk0; 0 without a rate to extrapolate.
 int restart_chunk(double res0, double tol2, double rate) {
-    if (!(rate < 0) || !(res0 > 0) || !(tol2 > 0) || !std::isfinite(res0)) return kChunk0;
+    if (!(rate < 0) || !(res0 > 0) || !(tol2 > 0) || !std::isfinite(res0)) return 0;
     const double need = std::ceil((std::log(tol2) - std::log(res0)) / rate);
-    return (int)std::max(1.0, std::min(need, (double)kChunk0));
+    return need <= kChunk0 ? (int)std::max(1.0, need) : 0;
 }
 
 template <int KIND>
+// first_chunk: iterations of the first chunk (0: kChunk0), predicted to reach
+// the tolerance when nonzero.  A chunk predicted to reach it is followed by
+// the FP64 true residual, which then comes back with the done flag
+// (true_ready) instead of after one more round trip.
 int run_solve(lpcg_system *s, const Args &a, const lpcg_solve_opts &o, int first_chunk, int &iters_total,
-              int &status, double &rate, hipStream_t st) {
+              int &status, double &rate, bool &true_ready, hipStream_t st) {
     const int vb = s->vec_blocks;
     k_setup<KIND><<<vb, VT, 0, st>>>(a);
     k_setup_scal<KIND><<<1, VT, 0, st>>>(a);
@@ -1312,7 +1326,9 @@ int run_solve(lpcg_system *s, const Args &a, const lpcg_solve_opts &o, int first
     const bool adaptive = o.check_every <= 0 && !o.use_graph;
     // the fused red-black path records iteration k in the launches of k + 1
     const int lag = KIND == LPCG_PC_LLT && e2_path(s) ? 1 : 0;
-    int chunk = o.check_every > 0 ? o.check_every : adaptive ? first_chunk + lag : kChunk0;
+    bool fin = adaptive && first_chunk > 0;
+    int chunk = o.check_every > 0 ? o.check_every : fin ? first_chunk + lag : kChunk0;
+    true_ready = false;
     hipGraphExec_t exec = nullptr;
     if (o.use_graph) {
         // key: kernel arguments + preconditioner kind + chunk length
@@ -1363,10 +1379,20 @@ int run_solve(lpcg_system *s, const Args &a, const lpcg_solve_opts &o, int first
             if (rc != LPCG_OK) break;
         }
         launched += chunk;
+        if (fin) {
+            k_true_res<<<vb, VT, 0, st>>>(a);
+            k_true_fin<<<1, VT, 0, st>>>(a);
+            LPCG_LAUNCH_CHECK();
+        }
         hipError_t e = hipMemcpyAsync(s->h_ctrl, s->ctrl, sizeof(int) * C_NCTRL, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess && fin)
+            e = hipMemcpyAsync(s->h_scal, s->scal, sizeof(double) * S_NSCAL, hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
         if (e != hipSuccess) { rc = hip_fail(e, "pcg control readback", __FILE__, __LINE__); break; }
-        if (s->h_ctrl[C_DONE]) break;
+        if (s->h_ctrl[C_DONE]) {
+            true_ready = fin;
+            break;
+        }
         // the device stops at maxit (plus the one-iteration lag of the fused
         // red-black update), so this only trips on a kernel that never set the flag
         if (launched > (long)a.maxit + 4L * std::max(chunk, kChunk0) + 8) {
@@ -1374,7 +1400,7 @@ int run_solve(lpcg_system *s, const Args &a, const lpcg_solve_opts &o, int first
             rc = LPCG_EHIP;
             break;
         }
-        if (adaptive) chunk = next_chunk(s->h_ctrl, a.tol2, a.maxit, plan);
+        if (adaptive) chunk = next_chunk(s->h_ctrl, a.tol2, a.maxit, plan, fin);
     }
     if (rc != LPCG_OK) return rc;
     if (plan.rate < 0) rate = plan.rate;
@@ -1627,21 +1653,24 @@ extern "C" int lpcg_pcg_solve(lpcg_system *s, const lpcg_precond *P, const doubl
     res->status = LPCG_OK;
     int iters = 0, status = LPCG_OK;
     const int maxit0 = a.maxit;
-    int first = kChunk0;
+    int first = 0;
     double rate = 0;
+    bool true_ready = false;
     for (int attempt = 0;; ++attempt) {
         int rc;
-        if (P->kind == LPCG_PC_LLT) rc = run_solve<LPCG_PC_LLT>(s, a, *opts, first, iters, status, rate, st);
+        if (P->kind == LPCG_PC_LLT)
+            rc = run_solve<LPCG_PC_LLT>(s, a, *opts, first, iters, status, rate, true_ready, st);
         else if (P->kind == LPCG_PC_JACOBI)
-            rc = run_solve<LPCG_PC_JACOBI>(s, a, *opts, first, iters, status, rate, st);
-        else rc = run_solve<LPCG_PC_NONE>(s, a, *opts, first, iters, status, rate, st);
+            rc = run_solve<LPCG_PC_JACOBI>(s, a, *opts, first, iters, status, rate, true_ready, st);
+        else rc = run_solve<LPCG_PC_NONE>(s, a, *opts, first, iters, status, rate, true_ready, st);
         if (rc != LPCG_OK) return rc;
-        // FP64 true residual; the same readback brings the recursive ||r||^2
-        k_true_res<<<s->vec_blocks, VT, 0, st>>>(a);
-        k_true_fin<<<1, VT, 0, st>>>(a);
-        LPCG_LAUNCH_CHECK();
-        LPCG_HIP(hipMemcpyAsync(s->h_scal, s->scal, sizeof(double) * S_NSCAL, hipMemcpyDeviceToHost, st));
-        LPCG_HIP(hipStreamSynchronize(st));
+        if (!true_ready) {  // FP64 true residual; the same readback brings the recursive ||r||^2
+            k_true_res<<<s->vec_blocks, VT, 0, st>>>(a);
+            k_true_fin<<<1, VT, 0, st>>>(a);
+            LPCG_LAUNCH_CHECK();
+            LPCG_HIP(hipMemcpyAsync(s->h_scal, s->scal, sizeof(double) * S_NSCAL, hipMemcpyDeviceToHost, st));
+            LPCG_HIP(hipStreamSynchronize(st));
+        }
         const double truerel = sqrt(s->h_scal[S_TRUE] / s->h_scal[S_BB]);
         res->relres_rec = sqrt(s->h_scal[S_RR] / s->h_scal[S_BB]);
         res->relres_true = truerel;
