@@ -144,6 +144,31 @@ __device__ __forceinline__ void record_residual(const Args &a, double rr, int it
     }
 }
 
+// (A x)_i in FP64 from the FP64 values, summed in entry order.  The row's
+// entries are loaded eight at a time (indices clamped into the row) and their
+// inputs gathered together, so a row of up to eight entries costs three
+// dependent round trips instead of two per entry.
+__device__ __forceinline__ double row_ax64(const Args &a, int i) {
+    const int beg = a.rp[i], end = a.rp[i + 1];
+    double s = 0;
+    for (int k0 = beg; k0 < end; k0 += 8) {
+        int c[8];
+        double v[8], xv[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const int k = min(k0 + t, end - 1);
+            c[t] = a.ci[k];
+            v[t] = a.v64[k];
+        }
+#pragma unroll
+        for (int t = 0; t < 8; ++t) xv[t] = a.x[c[t]];
+#pragma unroll
+        for (int t = 0; t < 8; ++t)
+            if (k0 + t < end) s += v[t] * xv[t];
+    }
+    return s;
+}
+
 // r = b - A x (FP64 product, FP32 r), ||b||^2, ||r||^2 and (Jacobi/none) r.z
 // partials; presets y, z for dependency-driven substitutions.
 template <int KIND>
@@ -151,8 +176,7 @@ __global__ void __launch_bounds__(VT) k_setup(Args a) {
     __shared__ double lds[VT / kWave];
     double bb = 0, rr = 0, rz = 0;
     for (int i = blockIdx.x * VT + threadIdx.x; i < a.n; i += gridDim.x * VT) {
-        double s = 0;
-        for (int k = a.rp[i]; k < a.rp[i + 1]; ++k) s += a.v64[k] * a.x[a.ci[k]];
+        const double s = row_ax64(a, i);
         const double bi = a.b[i];
         const float ri = (float)(bi - s);
         a.r[i] = ri;
@@ -1048,8 +1072,7 @@ __global__ void __launch_bounds__(VT) k_true_res(Args a) {
     __shared__ double lds[VT / kWave];
     double rr = 0;
     for (int i = blockIdx.x * VT + threadIdx.x; i < a.n; i += gridDim.x * VT) {
-        double s = 0;
-        for (int k = a.rp[i]; k < a.rp[i + 1]; ++k) s += a.v64[k] * a.x[a.ci[k]];
+        const double s = row_ax64(a, i);
         const double ri = a.b[i] - s;
         rr += ri * ri;
     }
