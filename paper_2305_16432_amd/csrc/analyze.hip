@@ -258,6 +258,18 @@ __global__ void k_vec_gather(int n, const int *__restrict__ perm, const T *__res
     if (r < n) dst[r] = src[perm[r]];
 }
 
+// Two vectors into the internal order in one launch (a solve's b and x).
+__global__ void k_vec_gather2(int n, const int *__restrict__ perm, const double *__restrict__ s0,
+                              double *__restrict__ d0, const double *__restrict__ s1, double *__restrict__ d1) {
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < n) {
+        const int q = perm[r];
+        const double v0 = s0[q], v1 = s1[q];
+        d0[r] = v0;
+        d1[r] = v1;
+    }
+}
+
 template <typename T>
 __global__ void k_vec_scatter(int n, const int *__restrict__ perm, const T *__restrict__ src, T *__restrict__ dst) {
     int r = blockIdx.x * blockDim.x + threadIdx.x;
@@ -838,6 +850,16 @@ static int permute_vec(const lpcg_system *s, const T *src, T *dst, bool to_int, 
 }
 int to_internal_f64(const lpcg_system *s, const double *src, double *dst, hipStream_t st) {
     return permute_vec(s, src, dst, true, st);
+}
+int to_internal_f64_2(const lpcg_system *s, const double *s0, double *d0, const double *s1, double *d1,
+                      hipStream_t st) {
+    if (!s->perm) {
+        int rc = permute_vec(s, s0, d0, true, st);
+        return rc ? rc : permute_vec(s, s1, d1, true, st);
+    }
+    k_vec_gather2<<<nblk(s->n, 256), 256, 0, st>>>(s->n, s->perm, s0, d0, s1, d1);
+    LPCG_LAUNCH_CHECK();
+    return LPCG_OK;
 }
 int from_internal_f64(const lpcg_system *s, const double *src, double *dst, hipStream_t st) {
     return permute_vec(s, src, dst, false, st);

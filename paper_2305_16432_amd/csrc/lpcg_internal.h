@@ -205,6 +205,8 @@ namespace lpcg {
 // from_internal: dst[perm[r]] = src[r].  No-ops (plain copies are not made)
 // when the system has the natural ordering; callers test s->perm first.
 int to_internal_f64(const lpcg_system *s, const double *src, double *dst, hipStream_t st);
+int to_internal_f64_2(const lpcg_system *s, const double *s0, double *d0, const double *s1, double *d1,
+                      hipStream_t st);
 int from_internal_f64(const lpcg_system *s, const double *src, double *dst, hipStream_t st);
 int to_internal_f32(const lpcg_system *s, const float *src, float *dst, hipStream_t st);
 int from_internal_f32(const lpcg_system *s, const float *src, float *dst, hipStream_t st);

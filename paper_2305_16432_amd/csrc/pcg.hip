@@ -700,6 +700,10 @@ __global__ void __launch_bounds__(VT) k_llt2e_prefix(Args a, E2 e, int part0) {
 }
 
 // One factor's values into the pair's ELL slots (padding: 0) and diagonals.
+// Slot indices past the row's width are clamped to its last slot and padding
+// positions to entry 0, so that every load is unconditional and a thread's
+// loads take two round trips (positions, then values); only the stores and
+// the padding's zero depend on them.
 __global__ void k_e2_pack(int n, int p, int ws, int wp, const int *__restrict__ spos,
                           const int *__restrict__ sdpos, const int *__restrict__ ppos,
                           const int *__restrict__ pdpos, const float *__restrict__ lval,
@@ -707,20 +711,29 @@ __global__ void k_e2_pack(int n, int p, int ws, int wp, const int *__restrict__ 
                           float *__restrict__ pval, float *__restrict__ pdiag) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int nb = n - p;
-    if (i < nb) {
-        for (int t = 0; t < ws; ++t) {
-            const int k = spos[(size_t)t * nb + i];
-            sval[(size_t)t * nb + i] = k >= 0 ? lval[k] : 0.f;
-        }
-        sdiag[i] = lval[sdpos[i]];
+    const bool fs = i < nb && ws > 0, fp = i < p && wp > 0;
+    const int is = fs ? i : 0, ip = fp ? i : 0;
+    int ks[kEllMaxW], kp[kEllMaxW];
+#pragma unroll
+    for (int t = 0; t < kEllMaxW; ++t) {
+        ks[t] = fs ? spos[(size_t)min(t, ws - 1) * nb + is] : -1;
+        kp[t] = fp ? ppos[(size_t)min(t, wp - 1) * p + ip] : -1;
     }
-    if (i < p) {
-        for (int t = 0; t < wp; ++t) {
-            const int k = ppos[(size_t)t * p + i];
-            pval[(size_t)t * p + i] = k >= 0 ? utval[k] : 0.f;
-        }
-        pdiag[i] = utval[pdpos[i]];
+    const int ds = i < nb ? sdpos[i] : 0, dp = i < p ? pdpos[i] : 0;
+    float vs[kEllMaxW], vp[kEllMaxW];
+#pragma unroll
+    for (int t = 0; t < kEllMaxW; ++t) {
+        vs[t] = lval[max(ks[t], 0)];
+        vp[t] = utval[max(kp[t], 0)];
     }
+    const float dvs = lval[ds], dvp = utval[dp];
+#pragma unroll
+    for (int t = 0; t < kEllMaxW; ++t) {
+        if (fs && t < ws) sval[(size_t)t * nb + i] = ks[t] >= 0 ? vs[t] : 0.f;
+        if (fp && t < wp) pval[(size_t)t * p + i] = kp[t] >= 0 ? vp[t] : 0.f;
+    }
+    if (i < nb) sdiag[i] = dvs;
+    if (i < p) pdiag[i] = dvp;
 }
 
 // Single-workgroup substitutions (one block walking all levels): forward,
@@ -1490,7 +1503,7 @@ int build_args(lpcg_system *s, const lpcg_precond *P, const double *b, double *x
     // a reordered system solves (P A P^T)(P x) = P b in its internal order
     if (s->perm) {
         int rc;
-        if ((rc = to_internal_f64(s, b, s->bperm, st)) || (rc = to_internal_f64(s, x, s->xperm, st))) return rc;
+        if ((rc = to_internal_f64_2(s, b, s->bperm, x, s->xperm, st))) return rc;
     }
     a.b = s->perm ? s->bperm : b;
     a.x = s->perm ? s->xperm : x;
