@@ -985,6 +985,54 @@ __device__ __forceinline__ float l_value(int q, int mode, const int *__restrict_
     return l_entry(k, mode, erow, col, rev, row_sys, sys_s, diag64, d);
 }
 
+// Mode 3 with one thread per row: the row's strictly-lower values and its
+// completed diagonal from one set of loads (per entry, each strictly-lower
+// value is computed once for its own position and again in its row's
+// radicand).  The expressions and the FP64 order of the radicand are those of
+// l_value; the row's last L position holds the diagonal.  Entries are taken
+// eight at a time, indices clamped into the row, all loads issued before the
+// first use.
+__global__ void k_assemble_rows3(int n, const int *__restrict__ lsrc, const int *__restrict__ lrowptr,
+                                 const int *__restrict__ col, const int *__restrict__ rev,
+                                 const double *__restrict__ diag64, const float *__restrict__ d,
+                                 float *__restrict__ lval) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int q0 = lrowptr[i], cnt = lrowptr[i + 1] - q0 - 1;
+    const double di = diag64[i];
+    double ssq = 0.0;
+    for (int u0 = 0; u0 < cnt; u0 += 8) {
+        int k[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) k[u] = lsrc[q0 + min(u0 + u, cnt - 1)];
+        int c[8], rv[8];
+        float dk[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            c[u] = col[k[u]];
+            rv[u] = rev[k[u]];
+            dk[u] = d[k[u]];
+        }
+        double dg[8];
+        float dr[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            dg[u] = diag64[c[u]];
+            dr[u] = d[rv[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            if (u0 + u < cnt) {
+                const float l = (float)sqrt(dg[u]) * (0.5f * (dk[u] + dr[u]));
+                lval[q0 + u0 + u] = l;
+                ssq += (double)l * (double)l;
+            }
+        }
+    }
+    const double rad = di - ssq, fl = kCompleteFloor * di;
+    lval[q0 + cnt] = (float)sqrt(rad > fl ? rad : fl);
+}
+
 // Transposed copy: ut[p] = l[u2l[p]] (the values k_assemble would compute
 // again at those positions).
 __global__ void k_gather_ut(int nnz_l, const int *__restrict__ u2l, const float *__restrict__ lval,
@@ -1171,10 +1219,13 @@ int forward_impl(const lpcg_system *s, const lpcg_gnn *net, const double *b, uns
     }
     // L in its own order, then L^T gathered from it when both are wanted
     // (each value computed once); U alone is assembled directly
-    k_assemble<<<nblk(s->nnz_l, 256), 256, 0, st>>>(s->nnz_l, net->diag_mode, s->lsrc, s->u2l, s->rowptr,
-                                                     s->lrowptr, s->erow,
-                                                     s->colind, s->rev, s->row_sys, sys_s, s->diag64, d, lval,
-                                                     lval ? nullptr : utval);
+    if (net->diag_mode == 3 && lval)
+        k_assemble_rows3<<<nblk(s->n, 256), 256, 0, st>>>(s->n, s->lsrc, s->lrowptr, s->colind, s->rev,
+                                                          s->diag64, d, lval);
+    else
+        k_assemble<<<nblk(s->nnz_l, 256), 256, 0, st>>>(s->nnz_l, net->diag_mode, s->lsrc, s->u2l, s->rowptr,
+                                                         s->lrowptr, s->erow, s->colind, s->rev, s->row_sys,
+                                                         sys_s, s->diag64, d, lval, lval ? nullptr : utval);
     if (lval && utval) k_gather_ut<<<nblk(s->nnz_l, 256), 256, 0, st>>>(s->nnz_l, s->u2l, lval, utval);
     if (net->x_head) {
         k_xdec<H><<<gnn_blocks(s->n), kGnnThreads, 0, st>>>(s->n, P, o.xdec, V(T), (float *)(ws + L.xhat));

@@ -70,7 +70,7 @@ def test_gnn_forward_parity(name, h, n_mp, diag_mode):
     _check(A, b, h, n_mp, seed=5, diag_mode=diag_mode)
 
 
-@pytest.mark.parametrize("diag_mode", [0, 1, 2])
+@pytest.mark.parametrize("diag_mode", [0, 1, 2, 3])
 def test_gnn_forward_batch_per_system_normalisation(diag_mode):
     mats = [g.poisson_grid(9, 2), g.heat_system_3d(6, 1e-3, 1, 2)[0], g.fem_p1_delaunay(13, 0, 1)[0]]
     B, srp = g.block_diag_csr(mats)
