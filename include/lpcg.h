@@ -396,6 +396,20 @@ int lpcg_pcg_solve(lpcg_system *sys, const lpcg_precond *P, const double *b,
                    double *x, const lpcg_solve_opts *opts, lpcg_result *res,
                    double *hist, double *coef, hipStream_t stream);
 
+/* The rule lpcg_pcg_solve (check_every <= 0, no graph) uses to size its next
+ * chunk of iterations, for callers that drive their own loop and for tests.
+ * it, res: the last recorded iteration and its ||r||^2 / ||b||^2; prev_it,
+ * prev_res: the same at the previous look (0 and ||r0||^2 / ||b||^2 at the
+ * first).  The decay rate of log(res) between the two looks is extrapolated
+ * to tol^2, shortened by 15%, capped at four times (it - prev_it) and at
+ * maxit - it + 1, at least 1; without a decay (it <= prev_it, res or
+ * prev_res not positive and finite, no decrease) the answer is 8; tol = 0
+ * gives the cap.
+ * *predicted_final (may be NULL): 1 when the chunk is expected to reach tol
+ * (the solver then appends the FP64 true residual).  Host-only, no GPU. */
+int32_t lpcg_next_chunk(int32_t it, float res, int32_t prev_it, float prev_res, double tol, int32_t maxit,
+                        int32_t *predicted_final);
+
 /* Timing aid for the PCG iteration's own kernels: from x = 0 and right-hand
  * side b (device FP64 [n], caller's numbering) with preconditioner P, the
  * iteration runs `reps` times after one warm-up, launched eagerly in its

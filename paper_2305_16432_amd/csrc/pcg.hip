@@ -1319,12 +1319,9 @@ struct ChunkPlan {
     double rate = 0;         // last measured d log(res) / d iteration (< 0: decaying)
 };
 
-int next_chunk(const int *ctrl, double tol2, int maxit, ChunkPlan &c, bool &fin) {
+// it, res: the last recorded iteration and its ||r||^2 / ||b||^2.
+int next_chunk(int it, float res, double tol2, int maxit, ChunkPlan &c, bool &fin) {
     fin = false;
-    if (c.prev_res < 0.0f) memcpy(&c.prev_res, &ctrl[C_RES0], sizeof(float));
-    const int it = ctrl[C_RES_IT];
-    float res;
-    memcpy(&res, &ctrl[C_RES], sizeof(float));
     const int span = it - c.prev_it;
     const float res_prev = c.prev_res;
     c.prev_it = it;
@@ -1337,6 +1334,13 @@ int next_chunk(const int *ctrl, double tol2, int maxit, ChunkPlan &c, bool &fin)
     const double need = tol2 > 0 ? std::ceil(kLate * (std::log(tol2) - std::log((double)res)) / rate) : cap;
     fin = tol2 > 0 && need <= cap;
     return (int)std::max(1.0, std::min(need, cap));
+}
+
+int next_chunk(const int *ctrl, double tol2, int maxit, ChunkPlan &c, bool &fin) {
+    if (c.prev_res < 0.0f) memcpy(&c.prev_res, &ctrl[C_RES0], sizeof(float));
+    float res;
+    memcpy(&res, &ctrl[C_RES], sizeof(float));
+    return next_chunk(ctrl[C_RES_IT], res, tol2, maxit, c, fin);
 }
 
 // First chunk of a restart from the FP64 true residual (relative, squared:
@@ -1729,6 +1733,17 @@ extern "C" int lpcg_pcg_solve(lpcg_system *s, const lpcg_precond *P, const doubl
     if (status == LPCG_ENOTCONV) set_error("pcg: no convergence within maxit");
     if (status == LPCG_EBREAKDOWN) set_error("pcg: breakdown (p.Ap <= 0 or non-finite)");
     return status;
+}
+
+extern "C" int32_t lpcg_next_chunk(int32_t it, float res, int32_t prev_it, float prev_res, double tol,
+                                   int32_t maxit, int32_t *predicted_final) {
+    ChunkPlan c;
+    c.prev_it = prev_it;
+    c.prev_res = prev_res;
+    bool fin = false;
+    const int n = next_chunk(it, res, tol * tol, maxit, c, fin);
+    if (predicted_final) *predicted_final = fin ? 1 : 0;
+    return n;
 }
 
 // Extreme eigenvalues of the CG-Lanczos tridiagonal T_k of the preconditioned

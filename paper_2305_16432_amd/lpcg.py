@@ -420,6 +420,17 @@ def time_pcg_kernels(sys: System, kind: int, b, l_val=None, ut_val=None, dinv=No
     return tuple(out[i] for i in range(3))
 
 
+def next_chunk(it: int, res: float, prev_it: int, prev_res: float, tol: float, maxit: int):
+    """(iterations, predicted_final): the solver's rule for its next chunk
+    of iterations (host computation in the library, no GPU)."""
+    fin = C.c_int32(0)
+    fn = lib().lpcg_next_chunk
+    fn.restype = C.c_int32
+    fn.argtypes = [C.c_int32, C.c_float, C.c_int32, C.c_float, C.c_double, C.c_int32, C.POINTER(C.c_int32)]
+    n = fn(int(it), float(res), int(prev_it), float(prev_res), float(tol), int(maxit), C.byref(fin))
+    return int(n), bool(fin.value)
+
+
 def lanczos_extremes(coef, iters: int):
     """(lambda_min, lambda_max) of the preconditioned operator estimated from
     the PCG coefficients (host computation in the library)."""
