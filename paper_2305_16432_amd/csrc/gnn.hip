@@ -991,14 +991,18 @@ __device__ __forceinline__ float l_value(int q, int mode, const int *__restrict_
 // radicand).  The expressions and the FP64 order of the radicand are those of
 // l_value; the row's last L position holds the diagonal.  Entries are taken
 // eight at a time, indices clamped into the row, all loads issued before the
-// first use.
+// first use.  utval (may be null): each value also goes to its L^T position,
+// entry (j, i) of U row j at urowptr[j] + (rev - dpos[j]) (the diagonal first
+// in its row), found with the same round of loads as the value's inputs.
 __global__ void k_assemble_rows3(int n, const int *__restrict__ lsrc, const int *__restrict__ lrowptr,
                                  const int *__restrict__ col, const int *__restrict__ rev,
+                                 const int *__restrict__ urowptr, const int *__restrict__ dpos,
                                  const double *__restrict__ diag64, const float *__restrict__ d,
-                                 float *__restrict__ lval) {
+                                 float *__restrict__ lval, float *__restrict__ utval) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int q0 = lrowptr[i], cnt = lrowptr[i + 1] - q0 - 1;
+    const int u0i = urowptr[i];
     const double di = diag64[i];
     double ssq = 0.0;
     for (int u0 = 0; u0 < cnt; u0 += 8) {
@@ -1015,22 +1019,28 @@ __global__ void k_assemble_rows3(int n, const int *__restrict__ lsrc, const int 
         }
         double dg[8];
         float dr[8];
+        int ur[8], dp[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             dg[u] = diag64[c[u]];
             dr[u] = d[rv[u]];
+            ur[u] = utval ? urowptr[c[u]] : 0;
+            dp[u] = utval ? dpos[c[u]] : 0;
         }
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             if (u0 + u < cnt) {
                 const float l = (float)sqrt(dg[u]) * (0.5f * (dk[u] + dr[u]));
                 lval[q0 + u0 + u] = l;
+                if (utval) utval[ur[u] + (rv[u] - dp[u])] = l;
                 ssq += (double)l * (double)l;
             }
         }
     }
     const double rad = di - ssq, fl = kCompleteFloor * di;
-    lval[q0 + cnt] = (float)sqrt(rad > fl ? rad : fl);
+    const float dv = (float)sqrt(rad > fl ? rad : fl);
+    lval[q0 + cnt] = dv;
+    if (utval) utval[u0i] = dv;
 }
 
 // Transposed copy: ut[p] = l[u2l[p]] (the values k_assemble would compute
@@ -1219,14 +1229,15 @@ int forward_impl(const lpcg_system *s, const lpcg_gnn *net, const double *b, uns
     }
     // L in its own order, then L^T gathered from it when both are wanted
     // (each value computed once); U alone is assembled directly
-    if (net->diag_mode == 3 && lval)
+    const bool rows3 = net->diag_mode == 3 && lval;
+    if (rows3)
         k_assemble_rows3<<<nblk(s->n, 256), 256, 0, st>>>(s->n, s->lsrc, s->lrowptr, s->colind, s->rev,
-                                                          s->diag64, d, lval);
+                                                          s->urowptr, s->dpos, s->diag64, d, lval, utval);
     else
         k_assemble<<<nblk(s->nnz_l, 256), 256, 0, st>>>(s->nnz_l, net->diag_mode, s->lsrc, s->u2l, s->rowptr,
                                                          s->lrowptr, s->erow, s->colind, s->rev, s->row_sys,
                                                          sys_s, s->diag64, d, lval, lval ? nullptr : utval);
-    if (lval && utval) k_gather_ut<<<nblk(s->nnz_l, 256), 256, 0, st>>>(s->nnz_l, s->u2l, lval, utval);
+    if (lval && utval && !rows3) k_gather_ut<<<nblk(s->nnz_l, 256), 256, 0, st>>>(s->nnz_l, s->u2l, lval, utval);
     if (net->x_head) {
         k_xdec<H><<<gnn_blocks(s->n), kGnnThreads, 0, st>>>(s->n, P, o.xdec, V(T), (float *)(ws + L.xhat));
         // the head's loss gradient starts at zero: a backward without an
